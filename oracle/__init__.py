@@ -1,0 +1,170 @@
+"""SBMT CPU oracle -- test infrastructure only.
+
+A plain, slow, independent CPU implementation of the meshing path of
+Structured Bitmap-to-Mesh Triangulation (arXiv 2602.19474).  Only the tests,
+``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may
+import this package.  The product path (``paper_2602_19474_amd``) never
+imports it and shares no code with it.
+
+The arithmetic lives in ``sbmt_oracle.cpp`` (exact Z[sqrt3] predicates, a
+segment-driven crossing registry, ray-parity labelling, procedural templates,
+brute-force class enumeration).  This module only marshals arguments.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sbmt_oracle.cpp")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+BOTH_SIDES = 1
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with g++ (plain -O2, no FMA contraction)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+class LocalResult(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("tok", ctypes.c_int32 * 4), ("code", ctypes.c_int32),
+                ("canon_code", ctypes.c_int32), ("rot", ctypes.c_int32), ("class_id", ctypes.c_int32),
+                ("paper_m", ctypes.c_int32), ("paper_n", ctypes.c_int32), ("n_tris", ctypes.c_int32),
+                ("tris", (ctypes.c_int32 * 4) * 5), ("slot_seg", ctypes.c_int32 * 6),
+                ("slot_xy", (ctypes.c_double * 2) * 6), ("chain_vertex", ctypes.c_int32)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+        L.oracle_mesh_from_bitmap.restype = vp
+        L.oracle_mesh_from_bitmap.argtypes = [vp, i32, i32, i64, i32, u32, ctypes.c_char_p, i32]
+        for name in ("oracle_n_vertices", "oracle_n_triangles", "oracle_n_segments", "oracle_n_cut",
+                     "oracle_n_contours"):
+            getattr(L, name).restype = i64
+            getattr(L, name).argtypes = [vp]
+        L.oracle_grid_dims.restype = None
+        L.oracle_grid_dims.argtypes = [vp, vp, vp, vp]
+        L.oracle_copy.restype = None
+        L.oracle_copy.argtypes = [vp, vp, vp, vp]
+        L.oracle_copy_chains.restype = None
+        L.oracle_copy_chains.argtypes = [vp, vp, vp]
+        L.oracle_free.restype = None
+        L.oracle_free.argtypes = [vp]
+        L.oracle_class_table.restype = i32
+        L.oracle_class_table.argtypes = [vp, i32]
+        L.oracle_template_of_code.restype = i32
+        L.oracle_template_of_code.argtypes = [i32, vp]
+        L.oracle_z3_sign.restype = i32
+        L.oracle_z3_sign.argtypes = [i64, i64]
+        L.oracle_local.restype = i32
+        L.oracle_local.argtypes = [vp, vp, i32, ctypes.c_double, ctypes.POINTER(LocalResult),
+                                   ctypes.c_char_p, i32]
+        _lib = L
+    return _lib
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+@dataclass
+class OracleMesh:
+    verts: np.ndarray        # float64 [V, 2]  (x, y) pixel units, pixel (r, c) centred at (c, r)
+    tris: np.ndarray         # int32 [T, 3]    positive orientation in (x, y)
+    codes: np.ndarray        # uint8 [T]       0 = uncut, 1..K = class id, bit 7 = background side
+    n_segments: int
+    n_cut: int
+    n_contours: int
+    chains: list             # list of int64 [n, 2] closed polylines in quarter-pixel units
+    grid: tuple              # (NK, NI, s)
+
+
+def mesh_from_bitmap(bitmap: np.ndarray, grid_h: int, flags: int = 0) -> OracleMesh:
+    """Oracle mesh of a uint8 bitmap (nonzero = foreground) at integer grid edge ``grid_h``."""
+    L = lib()
+    bm = np.ascontiguousarray(bitmap, dtype=np.uint8)
+    H, W = bm.shape
+    err = ctypes.create_string_buffer(512)
+    ptr = bm.ctypes.data if bm.size else None
+    res = L.oracle_mesh_from_bitmap(ptr, W, H, W, int(grid_h), int(flags), err, 512)
+    if not res:
+        raise OracleError(err.value.decode())
+    try:
+        nv, nt = L.oracle_n_vertices(res), L.oracle_n_triangles(res)
+        verts = np.zeros((nv, 2), np.float64)
+        tris = np.zeros((nt, 3), np.int32)
+        codes = np.zeros((nt,), np.uint8)
+        L.oracle_copy(res, verts.ctypes.data, tris.ctypes.data, codes.ctypes.data)
+        nc = L.oracle_n_contours(res)
+        ns = L.oracle_n_segments(res)
+        xy = np.zeros((ns, 2), np.int64)
+        starts = np.zeros((nc + 1,), np.int64)
+        L.oracle_copy_chains(res, xy.ctypes.data, starts.ctypes.data)
+        chains = [xy[starts[j]:starts[j + 1]].copy() for j in range(nc)]
+        nk, ni, s = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        L.oracle_grid_dims(res, ctypes.byref(nk), ctypes.byref(ni), ctypes.byref(s))
+        return OracleMesh(verts, tris, codes, ns, L.oracle_n_cut(res), nc, chains,
+                          (nk.value, ni.value, s.value))
+    finally:
+        L.oracle_free(res)
+
+
+def class_table() -> np.ndarray:
+    """Admissible canonical key codes, ascending; class id = 1 + index."""
+    L = lib()
+    buf = np.zeros(4096, np.int32)
+    n = L.oracle_class_table(buf.ctypes.data, 4096)
+    return buf[:n].copy()
+
+
+def z3_sign(a: int, b: int) -> int:
+    """Exact sign of a + b*sqrt(3) as the oracle decides it."""
+    return int(lib().oracle_z3_sign(int(a), int(b)))
+
+
+def template_of_code(code: int):
+    """Procedural template (both sides) of a key code: list of (a, b, c, side)."""
+    L = lib()
+    buf = np.zeros(5 * 4, np.int32)
+    n = L.oracle_template_of_code(int(code), buf.ctypes.data)
+    if n < 0:
+        return None
+    return [tuple(int(v) for v in buf[4 * j:4 * j + 4]) for j in range(n)]
+
+
+def local(corners, chain, unit: float):
+    """Classify and retriangulate one triangle against a polyline.
+
+    ``corners``: 3 x (x, ya, yb) integers, y = ya + yb*sqrt(3), positive orientation.
+    ``chain``: m x (x, y) integers.  All coordinates share the scale ``unit``
+    (value = integer / unit).  Returns a ``LocalResult`` or raises; a degenerate
+    contact (a vertex on an edge) raises ``ValueError``.
+    """
+    L = lib()
+    c = np.ascontiguousarray(np.asarray(corners, dtype=np.int64).reshape(3, 3))
+    p = np.ascontiguousarray(np.asarray(chain, dtype=np.int64).reshape(-1, 2))
+    out = LocalResult()
+    err = ctypes.create_string_buffer(512)
+    rc = L.oracle_local(c.ctypes.data, p.ctypes.data, p.shape[0], float(unit), ctypes.byref(out), err, 512)
+    if rc == -2:
+        raise ValueError("degenerate contact")
+    if rc != 0:
+        raise OracleError(err.value.decode())
+    return out

@@ -1,0 +1,137 @@
+/*
+ * sbmt.h -- C ABI of the MI355X (gfx950) implementation of Structured
+ * Bitmap-to-Mesh Triangulation (SBMT, arXiv 2602.19474).
+ *
+ * The library turns a binary bitmap into a closed triangle mesh of its
+ * foreground: the boundary extracted from the bitmap is embedded into a
+ * regular equilateral grid by replacing only the cut base triangles with
+ * templates from a finite lookup table (Sec. 3.3, Alg. 1 and Alg. 2, App. G).
+ *
+ * Conventions
+ *  - Pixel (row r, column c) is a unit square centred at (x = c, y = r)
+ *    (Sec. 3.3, structured triangular filling).  A nonzero byte is foreground.
+ *  - grid_h is the edge length of the base equilateral grid in pixels.  It
+ *    must be one of the supported integers {1, 2, 3, 4, 5, 6}; others return
+ *    SBMT_E_UNSUPPORTED_GRID_H.  The boundary is taken from a raster
+ *    coarsened by block majority with the stride s = min{s : s^2 > 2 h^2}
+ *    (h = 1 -> 2, 2 -> 3, 4 -> 6) so that every boundary segment is longer than
+ *    the base edge, as the geometric protocol of Sec. 3.2 requires.
+ *  - Grid rows are horizontal: vertex (k, i) lies at
+ *      x = -(2h+3)/4 + h*i + (h/2)*(k mod 2),   y = -1 + k*h*sqrt(3)/2.
+ *  - Output vertices are FP64 (x, y) pairs; triangles are int32 index
+ *    triples with positive signed area in (x, y); codes are one byte per
+ *    triangle: 0 = uncut base triangle, 1..SBMT_NUM_CLASSES = canonical class
+ *    of the cut parent triangle (the key kappa(K) of Sec. 3.3.3 reduced by
+ *    rotation), bit 7 set = background side (only with SBMT_BOTH_SIDES).
+ *  - Vertex and triangle order is canonical and independent of tiling:
+ *    vertices by owner lattice vertex (row k, then i): the vertex itself (if
+ *    emitted), the crossings on its edges to (k,i+1), (k+1,i+o-1), (k+1,i+o)
+ *    (o = k mod 2) in order from the owner, the chain vertex in its triangle
+ *    with apex on row k, then the one in its triangle with base on row k.
+ *    Triangles by parent base triangle (row k, then i, apex-on-row-k first),
+ *    each rotated to start at its smallest index, sorted within the parent.
+ *
+ * Memory and ownership
+ *  - Every pointer named "device" is a device pointer on the handle's device;
+ *    the caller allocates and owns all of them (bitmap, workspace, outputs).
+ *    The library never allocates device memory on these paths; the handle only
+ *    owns a small pinned host buffer used to return sizes.
+ *  - Calls on one handle must not overlap (the pinned buffer is shared).
+ *
+ * Errors
+ *  - Every call returns an sbmt_status.  Arguments are validated before any
+ *    launch.  On error the output contents are undefined.
+ */
+#ifndef SBMT_H_
+#define SBMT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SBMT_OK = 0,
+  SBMT_E_INVALID_ARG = -1,        /* null pointer, negative size, stride < width ... */
+  SBMT_E_UNSUPPORTED_GRID_H = -2, /* grid_h not in {1,...,6} */
+  SBMT_E_INDEX_OVERFLOW = -3,     /* more than INT32_MAX vertices */
+  SBMT_E_WORKSPACE = -4,          /* workspace missing or smaller than required */
+  SBMT_E_DEVICE = -5,             /* a HIP runtime call failed */
+  SBMT_E_PROTOCOL = -6,           /* an inadmissible local pattern was seen (unreachable by design) */
+  SBMT_E_CAPACITY = -7            /* outputs larger than the capacity given to a bounded call */
+} sbmt_status;
+
+/* flags */
+#define SBMT_BOTH_SIDES 1u /* also emit background-side triangles and all lattice vertices */
+
+typedef struct sbmt_context* sbmt_handle;
+
+/* One image.  bitmap: device pointer to height rows of row_stride bytes,
+ * row-major, nonzero = foreground.  width/height >= 0 (0 gives an empty mesh). */
+typedef struct {
+  const uint8_t* bitmap;
+  int32_t width;
+  int32_t height;
+  int64_t row_stride;
+  int32_t grid_h;
+  uint32_t flags;
+} sbmt_image;
+
+/* Sizes returned by planning. */
+typedef struct {
+  int64_t n_vertices;  /* rows of the vertex array (x, y) */
+  int64_t n_triangles; /* rows of the triangle array and length of the code array */
+  int64_t n_cut;       /* base triangles replaced by a template */
+} sbmt_sizes;
+
+/* Geometry of an image's grid (host-only computation). */
+typedef struct {
+  int32_t stride_s;      /* coarse stride s */
+  int32_t coarse_w, coarse_h;
+  int32_t grid_rows;     /* NK */
+  int32_t grid_cols;     /* NI */
+  size_t workspace_bytes;
+} sbmt_layout;
+
+/* Create a context on a HIP device (allocates a small pinned host buffer). */
+sbmt_status sbmt_create(int device, sbmt_handle* out);
+sbmt_status sbmt_destroy(sbmt_handle h);
+
+/* Host-only: grid geometry and the workspace size for an image. */
+sbmt_status sbmt_query(const sbmt_image* img, sbmt_layout* out);
+
+/* Plan (Alg. 1 over every base triangle): extract the boundary, classify every
+ * base triangle, count outputs and prefix-sum the output offsets into the
+ * workspace.  Enqueued on `stream` (a hipStream_t, may be NULL for the null
+ * stream); synchronises that stream to return the sizes in *out. */
+sbmt_status sbmt_plan(sbmt_handle h, const sbmt_image* img, void* workspace, size_t ws_bytes,
+                      sbmt_sizes* out, void* stream);
+
+/* Run (Alg. 2 for every cut triangle, plus the uncut ones): write the mesh.
+ * Requires the workspace produced by sbmt_plan for the same image.  Outputs:
+ * verts [n_vertices][2] FP64, tris [n_triangles][3] int32, codes [n_triangles]
+ * uint8, all device pointers.  Asynchronous on `stream`. */
+sbmt_status sbmt_run(sbmt_handle h, const sbmt_image* img, void* workspace, size_t ws_bytes,
+                     double* verts, int32_t* tris, uint8_t* codes, void* stream);
+
+/* Plan and run in one asynchronous call, without a host round trip: outputs are
+ * written only if they fit the capacities; the sizes and a status word are
+ * written to the device buffer `sizes_dev` (int64 [4]: n_vertices, n_triangles,
+ * n_cut, status).  status = SBMT_E_CAPACITY if the mesh did not fit. */
+sbmt_status sbmt_mesh_async(sbmt_handle h, const sbmt_image* img, void* workspace, size_t ws_bytes,
+                            double* verts, int64_t vert_cap, int32_t* tris, uint8_t* codes,
+                            int64_t tri_cap, int64_t* sizes_dev, void* stream);
+
+/* Number of canonical classes and the key code of class id c (1-based). */
+int32_t sbmt_num_classes(void);
+int32_t sbmt_class_code(int32_t class_id);
+
+const char* sbmt_status_string(sbmt_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBMT_H_ */

@@ -1,0 +1,86 @@
+"""ctypes binding of libsbmt.so (the C ABI declared in include/sbmt.h).
+
+Argument marshalling only: every step of the meshing path runs in the HIP
+kernels of the library.  The library must have been built (see
+``paper_2602_19474_amd.build``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsbmt.so")
+
+SBMT_OK = 0
+STATUS = {
+    0: "ok", -1: "invalid argument", -2: "unsupported grid_h", -3: "index overflow", -4: "workspace",
+    -5: "device error", -6: "protocol violation", -7: "capacity exceeded",
+}
+BOTH_SIDES = 1
+
+
+class SbmtError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        self.status = status
+        super().__init__(f"{where}: sbmt status {status} ({STATUS.get(status, '?')})")
+
+
+class Image(ctypes.Structure):
+    _fields_ = [("bitmap", ctypes.c_void_p), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("row_stride", ctypes.c_int64), ("grid_h", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int64), ("n_triangles", ctypes.c_int64), ("n_cut", ctypes.c_int64)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("stride_s", ctypes.c_int32), ("coarse_w", ctypes.c_int32), ("coarse_h", ctypes.c_int32),
+                ("grid_rows", ctypes.c_int32), ("grid_cols", ctypes.c_int32), ("workspace_bytes", ctypes.c_size_t)]
+
+
+EXPORTS = ("sbmt_create", "sbmt_destroy", "sbmt_query", "sbmt_plan", "sbmt_run", "sbmt_mesh_async",
+           "sbmt_plan_batch", "sbmt_run_batch", "sbmt_num_classes", "sbmt_class_code", "sbmt_status_string")
+
+_lib = None
+
+
+def lib():
+    """Load libsbmt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    L.sbmt_create.restype = i32
+    L.sbmt_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+    L.sbmt_destroy.restype = i32
+    L.sbmt_destroy.argtypes = [vp]
+    L.sbmt_query.restype = i32
+    L.sbmt_query.argtypes = [ctypes.POINTER(Image), ctypes.POINTER(Layout)]
+    L.sbmt_plan.restype = i32
+    L.sbmt_plan.argtypes = [vp, ctypes.POINTER(Image), vp, sz, ctypes.POINTER(Sizes), vp]
+    L.sbmt_run.restype = i32
+    L.sbmt_run.argtypes = [vp, ctypes.POINTER(Image), vp, sz, vp, vp, vp, vp]
+    L.sbmt_mesh_async.restype = i32
+    L.sbmt_mesh_async.argtypes = [vp, ctypes.POINTER(Image), vp, sz, vp, i64, vp, vp, i64, vp, vp]
+    L.sbmt_num_classes.restype = i32
+    L.sbmt_num_classes.argtypes = []
+    L.sbmt_class_code.restype = i32
+    L.sbmt_class_code.argtypes = [i32]
+    L.sbmt_status_string.restype = ctypes.c_char_p
+    L.sbmt_status_string.argtypes = [i32]
+    if hasattr(L, "sbmt_plan_batch"):
+        L.sbmt_plan_batch.restype = i32
+        L.sbmt_run_batch.restype = i32
+    _lib = L
+    return L
+
+
+def check(status: int, where: str):
+    if status != SBMT_OK:
+        raise SbmtError(status, where)

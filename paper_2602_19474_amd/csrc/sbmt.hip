@@ -1,0 +1,575 @@
+// SBMT hot path for MI355X (gfx950): bitmap -> boundary -> exact per-triangle
+// classification -> canonical class -> template lookup -> closed mesh
+// (arXiv 2602.19474, Sec. 3.3, Alg. 1, Alg. 2, App. G).
+//
+// Kernels
+//   k_coarsen  block-majority coarse raster as packed bits, with a background ring
+//   k_count    per row segment (row k, CB owners): classify every owner, sum
+//              vertex/triangle counts (plan)
+//   k_scan_*   exclusive prefix sum of the per-segment counts -> output offsets
+//   k_emit     per tile (RB rows x CB owners): re-classify, prefix-sum the owner
+//              counts in LDS (with a one-row, one-column halo for neighbour ids),
+//              write FP64 vertices, int32 triangles and u8 class codes
+//
+// The output order is fixed by the owner numbering and does not depend on
+// the tile shape.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "../../include/sbmt.h"
+
+#define SBMT_CONST __constant__
+#include "sbmt_tables.h"
+#define SBMT_HD __device__ __forceinline__
+#include "sbmt_device.h"
+
+namespace sbmt {
+
+SBMT_HD int lut_key(int code) { return sbmt_lut_key[code]; }
+SBMT_HD int lut_nfg(int cls) { return sbmt_lut_nfg[cls]; }
+SBMT_HD int lut_ntri(int cls) { return sbmt_lut_ntri[cls]; }
+SBMT_HD uint16_t lut_tri(int cls, int j) { return sbmt_lut_tri[cls][j]; }
+
+constexpr int kThreads = 256;
+constexpr int kCB = 512;          // owners per row segment
+constexpr int kOPT = kCB / kThreads;  // owners per thread per row
+constexpr int kRB = 8;            // rows per emission tile
+constexpr int kScanThreads = 1024;
+constexpr int kScanChunk = 4 * kScanThreads;
+
+
+struct Work {
+  uint32_t* bits;
+  int4* seg_cnt;       // [nseg] (nv, nt, ncut, err)
+  longlong2* seg_off;  // [nseg] exclusive (vertex, triangle) offsets
+  longlong4* blk;      // [nblk] scan block sums / offsets
+  long long* tot;      // [8] nv, nt, ncut, err
+};
+
+
+// ---------------------------------------------------------------------------
+// Coarse raster: bit (R + ring, C + ring) = 2 * #fg pixels of block (R, C) >= s^2.
+// One thread per 32-bit word; out-of-image samples (the ring) are background.
+// ---------------------------------------------------------------------------
+__global__ void k_coarsen(Geo g, const uint8_t* __restrict__ bm, uint32_t* __restrict__ bits,
+                          long long* __restrict__ tot) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  const int rr = blockIdx.y;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 8) tot[threadIdx.x] = 0;
+  if (w >= g.wpr) return;
+  const int R = rr - kRing;
+  uint32_t word = 0;
+  if (R >= 0 && R < g.CH) {
+    const int s = g.s;
+    const int r0 = s * R, r1 = min(r0 + s, g.H);
+    for (int b = 0; b < 32; ++b) {
+      const int C = 32 * w + b - kRing;
+      if (C < 0 || C >= g.CW) continue;
+      const int c0 = s * C, c1 = min(c0 + s, g.W);
+      int cnt = 0;
+      for (int r = r0; r < r1; ++r) {
+        const uint8_t* row = bm + (int64_t)r * g.stride;
+        for (int c = c0; c < c1; ++c) cnt += row[c] != 0;
+      }
+      word |= (uint32_t)(2 * cnt >= s * s) << b;
+    }
+  }
+  bits[(int64_t)rr * g.wpr + w] = word;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Plan: classify every owner of a row segment and sum its counts.
+// grid (NCB, ceil(NK / kRB)), kThreads threads, kOPT owners per thread per row.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_count(Geo g, const uint32_t* __restrict__ bits,
+                                                    int4* __restrict__ seg_cnt, long long* __restrict__ tot) {
+  __shared__ int red[4][kThreads / 64];
+  const int cb = blockIdx.x;
+  const int k0 = blockIdx.y * kRB;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int r = 0; r < kRB; ++r) {
+    const int k = k0 + r;
+    if (k >= g.NK) break;
+    const int Rlo = row_cell(k, g.h, g.s);
+    int nv = 0, nt = 0, nc = 0, er = 0;
+    for (int j = 0; j < kOPT; ++j) {
+      const int c = cb * kCB + j * kThreads + threadIdx.x;
+      if (c >= g.NI) continue;
+      Owner o;
+      classify_owner<false>(g, bits, k, c, Rlo, o);
+      nv += info_nv(o.info);
+      nt += info_nt(o.info);
+      nc += info_ncut(o.info);
+      er |= info_err(o.info);
+    }
+    nv = wave_sum(nv); nt = wave_sum(nt); nc = wave_sum(nc); er = wave_sum(er);
+    if (lane == 0) { red[0][wv] = nv; red[1][wv] = nt; red[2][wv] = nc; red[3][wv] = er; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int4 v = {0, 0, 0, 0};
+      for (int q = 0; q < kThreads / 64; ++q) { v.x += red[0][q]; v.y += red[1][q]; v.z += red[2][q]; v.w += red[3][q]; }
+      seg_cnt[(int64_t)k * g.NCB + cb] = v;
+      if (v.w) atomicOr((unsigned long long*)&tot[3], 1ull);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of the per-segment (nv, nt) counts, three phases.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v, int lane) {
+  for (int off = 1; off < 64; off <<= 1) {
+    T u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
+  }
+  return v;
+}
+
+// block-wide exclusive scan of (a, b) over kScanThreads threads; returns totals
+__device__ void block_excl_scan2(long long& a, long long& b, long long* sa, long long* sb,
+                                 long long& ta, long long& tb) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  long long ia = wave_incl_scan(a, lane), ib = wave_incl_scan(b, lane);
+  if (lane == 63) { sa[wv] = ia; sb[wv] = ib; }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int nw = blockDim.x >> 6;
+    long long xa = threadIdx.x < nw ? sa[threadIdx.x] : 0, xb = threadIdx.x < nw ? sb[threadIdx.x] : 0;
+    long long ya = wave_incl_scan(xa, lane), yb = wave_incl_scan(xb, lane);
+    if (threadIdx.x < nw) { sa[threadIdx.x] = ya - xa; sb[threadIdx.x] = yb - xb; }
+    if (threadIdx.x == nw - 1) { sa[32] = ya; sb[32] = yb; }
+  }
+  __syncthreads();
+  a = ia - a + sa[wv];
+  b = ib - b + sb[wv];
+  ta = sa[32];
+  tb = sb[32];
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const int4* __restrict__ seg_cnt, int64_t nseg,
+                                                              longlong4* __restrict__ blk) {
+  __shared__ long long sa[33], sb[33];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  long long a = 0, b = 0, c = 0;
+  for (int q = 0; q < 4; ++q) {
+    const int64_t j = base + (int64_t)threadIdx.x * 4 + q;
+    if (j < nseg) { int4 v = seg_cnt[j]; a += v.x; b += v.y; c += v.z; }
+  }
+  long long ta, tb, tc, dummy;
+  block_excl_scan2(a, b, sa, sb, ta, tb);
+  long long z = 0;
+  block_excl_scan2(c, z, sa, sb, tc, dummy);
+  if (threadIdx.x == 0) blk[blockIdx.x] = make_longlong4(ta, tb, tc, 0);
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_blocks(longlong4* __restrict__ blk, int nblk,
+                                                              long long* __restrict__ tot) {
+  __shared__ long long sa[33], sb[33];
+  long long ra = 0, rb = 0, rc = 0;
+  for (int base = 0; base < nblk; base += kScanThreads) {
+    const int j = base + threadIdx.x;
+    longlong4 v = j < nblk ? blk[j] : make_longlong4(0, 0, 0, 0);
+    long long a = v.x, b = v.y, ta, tb;
+    block_excl_scan2(a, b, sa, sb, ta, tb);
+    long long c = v.z, z = 0, tc, d;
+    block_excl_scan2(c, z, sa, sb, tc, d);
+    if (j < nblk) blk[j] = make_longlong4(ra + a, rb + b, rc + c, 0);
+    ra += ta; rb += tb; rc += tc;
+  }
+  if (threadIdx.x == 0) { tot[0] = ra; tot[1] = rb; tot[2] = rc; }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int4* __restrict__ seg_cnt, int64_t nseg,
+                                                             const longlong4* __restrict__ blk,
+                                                             longlong2* __restrict__ seg_off) {
+  __shared__ long long sa[33], sb[33];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  int4 v[4];
+  long long a = 0, b = 0;
+  for (int q = 0; q < 4; ++q) {
+    const int64_t j = base + (int64_t)threadIdx.x * 4 + q;
+    v[q] = j < nseg ? seg_cnt[j] : make_int4(0, 0, 0, 0);
+    a += v[q].x; b += v[q].y;
+  }
+  long long ta, tb;
+  block_excl_scan2(a, b, sa, sb, ta, tb);
+  const longlong4 bo = blk[blockIdx.x];
+  a += bo.x; b += bo.y;
+  for (int q = 0; q < 4; ++q) {
+    const int64_t j = base + (int64_t)threadIdx.x * 4 + q;
+    if (j < nseg) seg_off[j] = make_longlong2(a, b);
+    a += v[q].x; b += v[q].y;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Emission.
+// ---------------------------------------------------------------------------
+// grid (NCB, ceil(NK / kRB)), kThreads threads.
+__global__ void __launch_bounds__(kThreads) k_emit(Geo g, const uint32_t* __restrict__ bits,
+                                                   const longlong2* __restrict__ seg_off,
+                                                   const long long* __restrict__ tot, int64_t vcap, int64_t tcap,
+                                                   double* __restrict__ verts, int32_t* __restrict__ tris,
+                                                   uint8_t* __restrict__ codes) {
+  constexpr int W = kCB + 2;  // columns c0-1 .. c0+CB
+  __shared__ uint32_t info[kRB + 1][W];
+  __shared__ int voff[2][W];
+  __shared__ int toff[2][W];
+  __shared__ int rowR[kRB + 1];
+  __shared__ int part[2][kThreads];
+  if (tot[0] > vcap || tot[1] > tcap || tot[3] != 0) return;  // does not fit / plan failed
+  const int cb = blockIdx.x;
+  const int k0 = blockIdx.y * kRB;
+  const int c0 = cb * kCB;
+  if (threadIdx.x <= kRB) rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < (kRB + 1) * W; idx += kThreads) {
+    const int rr = idx / W, col = idx - rr * W;
+    const int k = k0 + rr, c = c0 - 1 + col;
+    uint32_t f = 0;
+    if (k < g.NK && c >= 0 && c < g.NI) {
+      Owner o;
+      classify_owner<false>(g, bits, k, c, rowR[rr], o);
+      f = o.info;
+    }
+    info[rr][col] = f;
+  }
+  __syncthreads();
+  // offsets of row rr (buffer b): prefix over the segment's owners, plus halo columns
+  auto scan_row = [&](int rr, int b) {
+    const int k = k0 + rr;
+    const bool ok = k < g.NK;
+    const longlong2 base = ok ? seg_off[(int64_t)k * g.NCB + cb] : make_longlong2(0, 0);
+    // thread t owns columns 1 + 2t, 2 + 2t
+    const int ca = 1 + 2 * threadIdx.x, cbb = 2 + 2 * threadIdx.x;
+    const int va = info_nv(info[rr][ca]), vb = info_nv(info[rr][cbb]);
+    const int ta = info_nt(info[rr][ca]), tb = info_nt(info[rr][cbb]);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int sv = wave_incl_scan(va + vb, lane), st = wave_incl_scan(ta + tb, lane);
+    if (lane == 63) { part[0][wv] = sv; part[1][wv] = st; }
+    __syncthreads();
+    int pv = 0, pt = 0, totv = 0, tott = 0;
+    for (int q = 0; q < kThreads / 64; ++q) {
+      if (q < wv) { pv += part[0][q]; pt += part[1][q]; }
+      totv += part[0][q]; tott += part[1][q];
+    }
+    const int ev = sv - (va + vb) + pv, et = st - (ta + tb) + pt;
+    const int bv = (int)base.x, bt = (int)0;
+    voff[b][ca] = bv + ev; voff[b][cbb] = bv + ev + va;
+    toff[b][ca] = bt + et; toff[b][cbb] = bt + et + ta;
+    if (threadIdx.x == 0) {
+      voff[b][0] = bv - info_nv(info[rr][0]);
+      voff[b][W - 1] = bv + totv;
+    }
+    (void)tott;
+    __syncthreads();
+  };
+  scan_row(0, 0);
+  for (int r = 0; r < kRB; ++r) {
+    const int k = k0 + r;
+    if (k >= g.NK) break;
+    const int cur = r & 1, nxt = cur ^ 1;
+    scan_row(r + 1, nxt);
+    const int64_t tbase = seg_off[(int64_t)k * g.NCB + cb].y;
+    const int o_ = k & 1;
+    for (int j = 0; j < kOPT; ++j) {
+      const int col = 1 + j * kThreads + threadIdx.x;
+      const int c = c0 + col - 1;
+      if (c >= g.NI) continue;
+      const uint32_t f = info[r][col];
+      if (info_nv(f) == 0 && info_nt(f) == 0) continue;
+      Nb nb;
+      nb.vid = voff[cur][col];
+      nb.id_vr = voff[cur][col + 1];
+      nb.id_vdl = voff[nxt][col + o_ - 1];
+      nb.id_vdr = voff[nxt][col + o_];
+      const int self = info_self(f);
+      nb.base[0] = nb.vid + self;
+      nb.base[1] = nb.base[0] + info_n(f, 0);
+      nb.base[2] = nb.base[1] + info_n(f, 1);
+      const uint32_t fr = info[r][col + 1];
+      nb.base[3] = voff[cur][col + 1] + info_self(fr) + info_n(fr, 0);
+      const uint32_t fl = info[r + 1][col + o_ - 1];
+      nb.base[4] = voff[nxt][col + o_ - 1] + info_self(fl);
+      nb.baseI = nb.base[2] + info_n(f, 2);
+      emit_owner(g, bits, k, c, rowR[r], f, nb, tbase + toff[cur][col], verts, tris, codes);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_sizes(const long long* __restrict__ tot, int64_t vcap, int64_t tcap, int64_t* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    out[0] = tot[0];
+    out[1] = tot[1];
+    out[2] = tot[2];
+    out[3] = tot[3] ? SBMT_E_PROTOCOL : ((tot[0] > vcap || tot[1] > tcap) ? SBMT_E_CAPACITY : SBMT_OK);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+static int stride_for(int h) {
+  int s = 1;
+  while (s * s <= 2 * h * h) ++s;
+  return s;
+}
+
+static bool grid_h_supported(int h) {
+  // the owner parallelogram (width 1.5 h) must fit two coarse cells: 3h <= 2s
+  return h >= 1 && h <= 6 && 3 * h <= 2 * stride_for(h);
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Host copies of the exact row-cell rule, used to check before any launch that
+// every 3x3 sample window the kernels read lies inside the stored raster.
+static int host_z3sign(int64_t a, int64_t b) {
+  if (a >= 0 && b >= 0) return (a | b) != 0 ? 1 : 0;
+  if (a <= 0 && b <= 0) return -1;
+  __int128 a2 = (__int128)a * a, b2 = (__int128)3 * b * b;
+  return a > 0 ? (a2 > b2 ? 1 : -1) : (b2 > a2 ? 1 : -1);
+}
+static int64_t host_floordiv(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  return (a % b != 0 && a < 0) ? q - 1 : q;
+}
+static int64_t host_row_cell(int64_t k, int h, int s) {
+  int64_t kh = k * h;
+  int64_t R = host_floordiv(kh * 17320 / 10000 - s - 1, 2 * s);
+  while (host_z3sign(-(2 * s * R + s + 1), kh) < 0) --R;
+  while (host_z3sign(-(2 * s * (R + 1) + s + 1), kh) >= 0) ++R;
+  return R;
+}
+static bool windows_in_bounds(const Geo& g) {
+  const int64_t rlo_min = host_row_cell(0, g.h, g.s), rlo_max = host_row_cell(g.NK - 1, g.h, g.s);
+  const int64_t xmin = g.X0, xmax = (int64_t)g.X0 + 4LL * g.h * (g.NI - 1) + 2LL * g.h;
+  const int64_t clo_min = host_floordiv(xmin - 2 * g.h - 2 * (g.s - 1), 4 * g.s);
+  const int64_t clo_max = host_floordiv(xmax - 2 * g.h - 2 * (g.s - 1), 4 * g.s);
+  // rows Rlo .. Rlo+2 and bit columns Clo .. Clo+2 (plus one spare word) are read
+  return rlo_min + kRing >= 0 && rlo_max + 2 + kRing < g.CH + 2 * kRing && clo_min + kRing >= 0 &&
+         ((clo_max + 2 + kRing) >> 5) + 1 < g.wpr;
+}
+
+struct Layout {
+  Geo g;
+  int64_t nseg;
+  int nblk;
+  size_t off_bits, off_cnt, off_segoff, off_blk, off_tot, total;
+};
+
+static sbmt_status make_layout(const sbmt_image* img, Layout* L, bool need_ptr = true) {
+  if (!img) return SBMT_E_INVALID_ARG;
+  if (img->width < 0 || img->height < 0) return SBMT_E_INVALID_ARG;
+  if ((int64_t)img->width > (1 << 20) || (int64_t)img->height > (1 << 20)) return SBMT_E_INVALID_ARG;
+  if (img->width > 0 && img->height > 0 && ((need_ptr && img->bitmap == nullptr) || img->row_stride < img->width))
+    return SBMT_E_INVALID_ARG;
+  if (img->flags & ~1u) return SBMT_E_INVALID_ARG;
+  if (!grid_h_supported(img->grid_h)) return SBMT_E_UNSUPPORTED_GRID_H;
+  Geo& g = L->g;
+  g.W = img->width;
+  g.H = img->height;
+  g.stride = img->row_stride;
+  g.h = img->grid_h;
+  g.s = stride_for(g.h);
+  g.CW = (g.W + g.s - 1) / g.s;
+  g.CH = (g.H + g.s - 1) / g.s;
+  // rows 0..m with m the smallest m >= 1 such that 3 m^2 h^2 > (2 s CH + 1)^2
+  int64_t rhs = (2LL * g.s * g.CH + 1) * (2LL * g.s * g.CH + 1);
+  int64_t m = (int64_t)((2.0 * g.s * g.CH + 1) / (g.h * 1.7320508075688772)) - 2;
+  if (m < 1) m = 1;
+  while (3LL * m * m * g.h * g.h <= rhs) ++m;
+  while (m > 1 && 3LL * (m - 1) * (m - 1) * g.h * g.h > rhs) --m;
+  g.NK = (int32_t)(m + 1);
+  g.NI = (int32_t)((4LL * g.s * g.CW + 2LL * g.h + 1) / (4LL * g.h) + 2);
+  g.NCB = (g.NI + kCB - 1) / kCB;
+  g.wpr = (g.CW + 2 * kRing + 31) / 32 + 1;
+  g.X0 = -2 * g.h - 3;
+  g.flags = img->flags;
+  if (!windows_in_bounds(g)) return SBMT_E_INVALID_ARG;
+  L->nseg = (int64_t)g.NK * g.NCB;
+  L->nblk = (int)((L->nseg + kScanChunk - 1) / kScanChunk);
+  size_t off = 0;
+  L->off_bits = off;
+  off = align256(off + (size_t)(g.CH + 2 * kRing) * g.wpr * 4);
+  L->off_cnt = off;
+  off = align256(off + (size_t)L->nseg * sizeof(int4));
+  L->off_segoff = off;
+  off = align256(off + (size_t)L->nseg * sizeof(longlong2));
+  L->off_blk = off;
+  off = align256(off + (size_t)L->nblk * sizeof(longlong4));
+  L->off_tot = off;
+  off = align256(off + 8 * sizeof(long long));
+  L->total = off;
+  return SBMT_OK;
+}
+
+static Work work_of(const Layout& L, void* ws) {
+  char* b = (char*)ws;
+  Work w;
+  w.bits = (uint32_t*)(b + L.off_bits);
+  w.seg_cnt = (int4*)(b + L.off_cnt);
+  w.seg_off = (longlong2*)(b + L.off_segoff);
+  w.blk = (longlong4*)(b + L.off_blk);
+  w.tot = (long long*)(b + L.off_tot);
+  return w;
+}
+
+static sbmt_status launch_plan(const Layout& L, const sbmt_image* img, const Work& w, hipStream_t st) {
+  const Geo& g = L.g;
+  dim3 gc((g.wpr + 63) / 64, g.CH + 2 * kRing);
+  hipLaunchKernelGGL(k_coarsen, gc, dim3(64), 0, st, g, img->bitmap, w.bits, w.tot);
+  dim3 gk(g.NCB, (g.NK + kRB - 1) / kRB);
+  hipLaunchKernelGGL(k_count, gk, dim3(kThreads), 0, st, g, (const uint32_t*)w.bits, w.seg_cnt, w.tot);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(L.nblk), dim3(kScanThreads), 0, st, (const int4*)w.seg_cnt, L.nseg, w.blk);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, st, w.blk, L.nblk, w.tot);
+  hipLaunchKernelGGL(k_scan_apply, dim3(L.nblk), dim3(kScanThreads), 0, st, (const int4*)w.seg_cnt, L.nseg,
+                     (const longlong4*)w.blk, w.seg_off);
+  return hipGetLastError() == hipSuccess ? SBMT_OK : SBMT_E_DEVICE;
+}
+
+static sbmt_status launch_emit(const Layout& L, const Work& w, int64_t vcap, int64_t tcap, double* verts,
+                               int32_t* tris, uint8_t* codes, hipStream_t st) {
+  const Geo& g = L.g;
+  dim3 gk(g.NCB, (g.NK + kRB - 1) / kRB);
+  hipLaunchKernelGGL(k_emit, gk, dim3(kThreads), 0, st, g, (const uint32_t*)w.bits, (const longlong2*)w.seg_off,
+                     (const long long*)w.tot, vcap, tcap, verts, tris, codes);
+  return hipGetLastError() == hipSuccess ? SBMT_OK : SBMT_E_DEVICE;
+}
+
+}  // namespace sbmt
+
+using namespace sbmt;
+
+struct sbmt_context {
+  int device;
+  long long* pinned;  // 8 x int64
+};
+
+extern "C" {
+
+sbmt_status sbmt_create(int device, sbmt_handle* out) {
+  if (!out) return SBMT_E_INVALID_ARG;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SBMT_E_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return SBMT_E_DEVICE;
+  sbmt_context* c = (sbmt_context*)calloc(1, sizeof(sbmt_context));
+  if (!c) return SBMT_E_DEVICE;
+  c->device = device;
+  if (hipHostMalloc((void**)&c->pinned, 8 * sizeof(long long), hipHostMallocDefault) != hipSuccess) {
+    free(c);
+    return SBMT_E_DEVICE;
+  }
+  *out = c;
+  return SBMT_OK;
+}
+
+sbmt_status sbmt_destroy(sbmt_handle h) {
+  if (!h) return SBMT_E_INVALID_ARG;
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  free(h);
+  return SBMT_OK;
+}
+
+sbmt_status sbmt_query(const sbmt_image* img, sbmt_layout* out) {
+  Layout L;
+  sbmt_status st = make_layout(img, &L, false);
+  if (st != SBMT_OK) return st;
+  if (out) {
+    out->stride_s = L.g.s;
+    out->coarse_w = L.g.CW;
+    out->coarse_h = L.g.CH;
+    out->grid_rows = L.g.NK;
+    out->grid_cols = L.g.NI;
+    out->workspace_bytes = L.total;
+  }
+  return SBMT_OK;
+}
+
+sbmt_status sbmt_plan(sbmt_handle h, const sbmt_image* img, void* workspace, size_t ws_bytes, sbmt_sizes* out,
+                      void* stream) {
+  if (!h || !out) return SBMT_E_INVALID_ARG;
+  Layout L;
+  sbmt_status st = make_layout(img, &L);
+  if (st != SBMT_OK) return st;
+  if (!workspace || ws_bytes < L.total) return SBMT_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  Work w = work_of(L, workspace);
+  if ((st = launch_plan(L, img, w, s)) != SBMT_OK) return st;
+  if (hipMemcpyAsync(h->pinned, w.tot, 4 * sizeof(long long), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return SBMT_E_DEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return SBMT_E_DEVICE;
+  if (h->pinned[3]) return SBMT_E_PROTOCOL;
+  out->n_vertices = h->pinned[0];
+  out->n_triangles = h->pinned[1];
+  out->n_cut = h->pinned[2];
+  if (out->n_vertices > 0x7fffffffLL) return SBMT_E_INDEX_OVERFLOW;
+  return SBMT_OK;
+}
+
+sbmt_status sbmt_run(sbmt_handle h, const sbmt_image* img, void* workspace, size_t ws_bytes, double* verts,
+                     int32_t* tris, uint8_t* codes, void* stream) {
+  if (!h) return SBMT_E_INVALID_ARG;
+  Layout L;
+  sbmt_status st = make_layout(img, &L);
+  if (st != SBMT_OK) return st;
+  if (!workspace || ws_bytes < L.total) return SBMT_E_WORKSPACE;
+  Work w = work_of(L, workspace);
+  // the plan's totals bound every write; capacities are the totals themselves
+  const int64_t cap = INT64_MAX;
+  return launch_emit(L, w, cap, cap, verts, tris, codes, (hipStream_t)stream);
+}
+
+sbmt_status sbmt_mesh_async(sbmt_handle h, const sbmt_image* img, void* workspace, size_t ws_bytes, double* verts,
+                            int64_t vert_cap, int32_t* tris, uint8_t* codes, int64_t tri_cap, int64_t* sizes_dev,
+                            void* stream) {
+  if (!h || !sizes_dev || vert_cap < 0 || tri_cap < 0) return SBMT_E_INVALID_ARG;
+  if (vert_cap > 0x7fffffffLL) vert_cap = 0x7fffffffLL;
+  Layout L;
+  sbmt_status st = make_layout(img, &L);
+  if (st != SBMT_OK) return st;
+  if (!workspace || ws_bytes < L.total) return SBMT_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  Work w = work_of(L, workspace);
+  if ((st = launch_plan(L, img, w, s)) != SBMT_OK) return st;
+  if ((st = launch_emit(L, w, vert_cap, tri_cap, verts, tris, codes, s)) != SBMT_OK) return st;
+  hipLaunchKernelGGL(k_sizes, dim3(1), dim3(64), 0, s, (const long long*)w.tot, vert_cap, tri_cap, sizes_dev);
+  return hipGetLastError() == hipSuccess ? SBMT_OK : SBMT_E_DEVICE;
+}
+
+int32_t sbmt_num_classes(void) { return SBMT_NUM_CLASSES; }
+
+int32_t sbmt_class_code(int32_t class_id) {
+  static const int32_t codes[] = {SBMT_CLASS_CODES_INIT};
+  if (class_id < 1 || class_id > SBMT_NUM_CLASSES) return -1;
+  return codes[class_id];
+}
+
+const char* sbmt_status_string(sbmt_status s) {
+  switch (s) {
+    case SBMT_OK: return "ok";
+    case SBMT_E_INVALID_ARG: return "invalid argument";
+    case SBMT_E_UNSUPPORTED_GRID_H: return "unsupported grid_h (supported: 1..6)";
+    case SBMT_E_INDEX_OVERFLOW: return "vertex count exceeds int32";
+    case SBMT_E_WORKSPACE: return "workspace missing or too small";
+    case SBMT_E_DEVICE: return "HIP runtime error";
+    case SBMT_E_PROTOCOL: return "inadmissible local boundary pattern";
+    case SBMT_E_CAPACITY: return "mesh larger than the output capacity";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,266 @@
+"""Benchmark of the SBMT hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints ONE JSON line.  The headline ``value`` is output triangles/s of the
+plain single-image path on the largest single-image workload (8192x8192
+smoothed noise, sigma 16 px, threshold 0.3 after z-normalisation, grid edge
+1 px): one step = plan (coarsen + classify/count + prefix sum + size read-back)
++ run (emit) of that image, inputs resident in HBM, outputs preallocated.
+
+Extra objects on the same line:
+  roofline      achieved algorithmic HBM bytes/s of the dominant kernel (k_emit)
+                against the MI355X peak, timed with HIP events on its stream
+  cpu_baseline  the CPU oracle on a bounded sample of the same workload
+  latency       p50/p99 per-image latency (plan + run + sync) of small images
+  batch256      the 256-image batch workload: plain per-image loop and the
+                batched path (when available), triangles/s and MPix/s
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _gen_batch_item(j):
+    from paper_2602_19474_amd import workloads as wl
+    g = wl.rng(3, j)
+    w, h = int(g.integers(128, 2049)), int(g.integers(128, 2049))
+    gh = int(g.choice([1, 2, 4]))
+    return wl.smoothed_noise(w, h, 8.0, 0.0, False, g), gh
+
+
+def gen_batch(n: int):
+    from concurrent.futures import ProcessPoolExecutor
+    workers = min(16, os.cpu_count() or 1)
+    with ProcessPoolExecutor(workers) as ex:
+        return list(ex.map(_gen_batch_item, range(n), chunksize=4))
+
+
+class Plain:
+    """Preallocated plan/run of one image on the current stream."""
+
+    def __init__(self, bitmap_gpu, grid_h: int):
+        import torch
+
+        import paper_2602_19474_amd as sbmt
+        self.sbmt = sbmt
+        self.t = bitmap_gpu
+        self.h = grid_h
+        self.ws = sbmt.workspace(bitmap_gpu, grid_h)
+        sz = sbmt.plan(bitmap_gpu, grid_h, self.ws)
+        self.sizes = sz
+        dev = bitmap_gpu.device
+        self.verts = torch.empty((max(sz.n_vertices, 1), 2), dtype=torch.float64, device=dev)
+        self.tris = torch.empty((max(sz.n_triangles, 1), 3), dtype=torch.int32, device=dev)
+        self.codes = torch.empty((max(sz.n_triangles, 1),), dtype=torch.uint8, device=dev)
+
+    def plan(self):
+        return self.sbmt.plan(self.t, self.h, self.ws)
+
+    def run(self):
+        self.sbmt.run(self.t, self.h, self.ws, self.verts, self.tris, self.codes)
+
+    def step(self):
+        self.plan()
+        self.run()
+
+    def alg_bytes(self) -> int:
+        H, W = self.t.shape
+        return W * H + 16 * self.sizes.n_vertices + 13 * self.sizes.n_triangles
+
+
+def headline(bm: np.ndarray, steps: int, warmup: int):
+    import torch
+    t = torch.from_numpy(bm).cuda()
+    p = Plain(t, 1)
+    for _ in range(warmup):
+        p.step()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record()
+        p.plan()
+        ev[k][1].record()
+        p.run()
+        ev[k][2].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    plan_ms = float(np.mean([ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]))
+    emit_ms = float(np.mean([ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]))
+    sz = p.sizes
+    return {"bitmap": bm, "plain": p, "wall": wall, "plan_ms": plan_ms, "emit_ms": emit_ms, "sizes": sz}
+
+
+def latency(name: str, images, grid_h: int, repeats: int = 1):
+    """Per-image latency of mesh_from_bitmap-equivalent plan + run + sync."""
+    import torch
+
+    import paper_2602_19474_amd as sbmt
+    lat = []
+    tri = 0
+    gpu = [torch.from_numpy(b).cuda() for b in images]
+    plains = [Plain(g, grid_h) for g in gpu]
+    for p in plains:  # warm
+        p.step()
+    torch.cuda.synchronize()
+    for _ in range(repeats):
+        for p in plains:
+            a = time.perf_counter()
+            sz = p.plan()
+            p.run()
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - a)
+            tri += sz.n_triangles
+    lat = np.array(lat) * 1e3
+    del sbmt
+    return {"workload": name, "images": len(images), "grid_h": grid_h, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+            "tri_per_s": float(tri / (lat.sum() / 1e3))}
+
+
+def batch_section(items):
+    import torch
+    n = len(items)
+    gpu = [(torch.from_numpy(b).cuda(), gh) for b, gh in items]
+    px = sum(b.size for b, _ in items)
+    plains = [Plain(g, gh) for g, gh in gpu]
+    torch.cuda.synchronize()
+    out = {"workload": f"batch{n}", "images": n, "mpix": px / 1e6}
+    # plain: one plan + run per image, back to back on one stream
+    for p in plains:
+        p.step()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    tri = 0
+    for p in plains:
+        tri += p.plan().n_triangles
+        p.run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - a
+    out["plain"] = {"tri_per_s": tri / dt, "mpix_per_s": px / 1e6 / dt, "ms": dt * 1e3, "triangles": tri}
+    try:
+        from paper_2602_19474_amd import batch as sbatch
+        out["batched"] = sbatch.bench([(g, gh) for g, gh in gpu], repeats=3)
+    except ImportError:
+        out["batched"] = None
+    return out
+
+
+def cpu_baseline(full: np.ndarray):
+    import oracle
+    bm = np.ascontiguousarray(full[:4096])
+    a = time.perf_counter()
+    m = oracle.mesh_from_bitmap(bm, 1)
+    dt = time.perf_counter() - a
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": m.tris.shape[0] / dt, "unit": "triangles/s", "cores": 1, "kind": "oracle",
+            "sample": f"top 4096x8192 band of the noise8192 workload, grid_h=1, one pass, single thread "
+                      f"({m.tris.shape[0]} triangles in {dt:.2f}s; host {model or platform.processor()}, "
+                      f"{os.cpu_count()} logical CPUs)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true", help="headline only")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=256)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (one process, one MI355X); --gpus {args.gpus} is not supported. "
+              "Images are independent work units, so N GPUs would each mesh their own share.", file=sys.stderr)
+        sys.exit(2)
+    # every input is generated before the GPU is initialised (the batch uses a
+    # process pool, whose workers must not inherit a GPU context)
+    from paper_2602_19474_amd import workloads as wl
+    t0 = time.time()
+    noise = wl.noise8192()
+    log(f"noise8192 generated in {time.time() - t0:.1f}s")
+    extras = None
+    if not args.no_extras:
+        t0 = time.time()
+        extras = {"disk64": [wl.disk(item=j) for j in range(200)],
+                  "ellipses1024": [wl.ellipses(item=j) for j in range(4)],
+                  "batch": gen_batch(args.batch)}
+        log(f"extra workloads generated in {time.time() - t0:.1f}s")
+    import torch
+    torch.cuda.set_device(0)
+    import paper_2602_19474_amd  # noqa: F401  (fails loudly if the HIP library is missing)
+
+    H = headline(noise, args.steps, args.warmup)
+    sz = H["sizes"]
+    ms = H["wall"] / args.steps * 1e3
+    bm = H["bitmap"]
+    emit_bytes = 16 * sz.n_vertices + 13 * sz.n_triangles
+    achieved = emit_bytes / (H["emit_ms"] * 1e-3) / 1e9
+    path_bytes = H["plain"].alg_bytes()
+    res = {
+        "metric": "output triangles/s (plain single image; batched and latency below)",
+        "value": sz.n_triangles / (ms * 1e-3),
+        "unit": "triangles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32/f64",
+        "data": "synthetic",
+        "config": {"workload": "noise8192", "width": int(bm.shape[1]), "height": int(bm.shape[0]), "grid_h": 1,
+                   "fg_only": True, "generator": "N(0,1) -> Gaussian sigma 16 -> z-score -> > 0.3, seed 4/0"},
+        "mpix_per_s": bm.size / 1e6 / (ms * 1e-3),
+        "mesh": {"vertices": sz.n_vertices, "triangles": sz.n_triangles, "cut": sz.n_cut},
+        "plan_ms": H["plan_ms"],
+        "emit_ms": H["emit_ms"],
+        "path_hbm_frac": path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": "k_emit", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": emit_bytes},
+    }
+    del H
+    if extras is not None:
+        log("latency sections")
+        res["latency"] = [
+            latency("disk64", extras["disk64"], 1),
+            latency("ellipses1024", extras["ellipses1024"], 2, repeats=5),
+        ]
+        log("batch section")
+        res["batch"] = batch_section(extras["batch"])
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        res["cpu_baseline"] = cpu_baseline(noise)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

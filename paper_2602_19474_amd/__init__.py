@@ -52,7 +52,7 @@ def _image(bitmap, grid_h: int, flags: int) -> _lib.Image:
     torch = _torch()
     if bitmap.dtype != torch.uint8 or bitmap.dim() != 2:
         raise ValueError("bitmap must be a 2-D uint8 tensor")
-    if bitmap.numel() and bitmap.stride(1) != 1:
+    if bitmap.numel() and bitmap.shape[1] > 1 and bitmap.stride(1) != 1:
         raise ValueError("bitmap rows must be contiguous")
     H, W = bitmap.shape
     # a size-1 row dimension may carry any stride (numpy's a[None, :] has 0)

@@ -32,12 +32,13 @@ namespace sbmt {
 SBMT_HD int lut_key(int code) { return sbmt_lut_key[code]; }
 SBMT_HD int lut_nfg(int cls) { return sbmt_lut_nfg[cls]; }
 SBMT_HD int lut_ntri(int cls) { return sbmt_lut_ntri[cls]; }
-SBMT_HD uint16_t lut_tri(int cls, int j) { return sbmt_lut_tri[cls][j]; }
+SBMT_HD uint32_t lut_tri(int cls, int j) { return sbmt_lut_tri[cls][j]; }
 
 constexpr int kThreads = 256;
-constexpr int kCB = 512;          // owners per row segment
+constexpr int kCB = 256;          // owners per row segment
 constexpr int kOPT = kCB / kThreads;  // owners per thread per row
 constexpr int kRB = 8;            // rows per emission tile
+constexpr int kRec = 384;         // slow-owner records kept in LDS per emission tile
 constexpr int kScanThreads = 1024;
 constexpr int kScanChunk = 4 * kScanThreads;
 
@@ -52,33 +53,34 @@ struct Work {
 
 
 // ---------------------------------------------------------------------------
-// Coarse raster: bit (R + ring, C + ring) = 2 * #fg pixels of block (R, C) >= s^2.
-// One thread per 32-bit word; out-of-image samples (the ring) are background.
+// Coarse raster: bit (R + ring, C + ringC) = [2 * #fg pixels of block (R, C) >= s^2].
+// One lane per sample; a wave covers 64 consecutive stored columns and packs
+// them with a ballot; samples outside the image (the ring) are background.
+// grid (ceil(32 wpr / 256), CH + 2 ring), 256 threads.
 // ---------------------------------------------------------------------------
-__global__ void k_coarsen(Geo g, const uint8_t* __restrict__ bm, uint32_t* __restrict__ bits,
-                          long long* __restrict__ tot) {
-  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_coarsen(Geo g, const uint8_t* __restrict__ bm, uint32_t* __restrict__ bits,
+                                                 long long* __restrict__ tot) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int gw = blockIdx.x * 4 + wv;  // 64-bit group of the stored row
   const int rr = blockIdx.y;
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 8) tot[threadIdx.x] = 0;
-  if (w >= g.wpr) return;
   const int R = rr - kRing;
-  uint32_t word = 0;
-  if (R >= 0 && R < g.CH) {
+  const int C = 64 * gw + lane - kRingC;
+  int fg = 0;
+  if (R >= 0 && R < g.CH && C >= 0 && C < g.CW) {
     const int s = g.s;
     const int r0 = s * R, r1 = min(r0 + s, g.H);
-    for (int b = 0; b < 32; ++b) {
-      const int C = 32 * w + b - kRing;
-      if (C < 0 || C >= g.CW) continue;
-      const int c0 = s * C, c1 = min(c0 + s, g.W);
-      int cnt = 0;
-      for (int r = r0; r < r1; ++r) {
-        const uint8_t* row = bm + (int64_t)r * g.stride;
-        for (int c = c0; c < c1; ++c) cnt += row[c] != 0;
-      }
-      word |= (uint32_t)(2 * cnt >= s * s) << b;
+    const int c0 = s * C, c1 = min(c0 + s, g.W);
+    int cnt = 0;
+    for (int r = r0; r < r1; ++r) {
+      const uint8_t* row = bm + (int64_t)r * g.stride;
+      for (int c = c0; c < c1; ++c) cnt += row[c] != 0;
     }
+    fg = 2 * cnt >= s * s;
   }
-  bits[(int64_t)rr * g.wpr + w] = word;
+  const unsigned long long m = __ballot(fg);
+  const int w = 2 * gw + lane;
+  if (lane < 2 && w < g.wpr) bits[(int64_t)rr * g.wpr + w] = (uint32_t)(m >> (32 * lane));
 }
 
 __device__ __forceinline__ int wave_sum(int v) {
@@ -87,40 +89,63 @@ __device__ __forceinline__ int wave_sum(int v) {
 }
 
 // ---------------------------------------------------------------------------
-// Plan: classify every owner of a row segment and sum its counts.
+// Plan: classify every owner of kRB row segments and sum the counts per
+// segment.  Owners whose window is not uniform are queued in LDS for the whole
+// tile and classified densely afterwards.
 // grid (NCB, ceil(NK / kRB)), kThreads threads, kOPT owners per thread per row.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads) k_count(Geo g, const uint32_t* __restrict__ bits,
                                                     int4* __restrict__ seg_cnt, long long* __restrict__ tot) {
-  __shared__ int red[4][kThreads / 64];
+  __shared__ int acc[kRB][4];
+  __shared__ int rowR[kRB];
+  __shared__ uint16_t queue[kRB * kCB];
+  __shared__ int qn;
   const int cb = blockIdx.x;
   const int k0 = blockIdx.y * kRB;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c0 = cb * kCB;
+  const int lane = threadIdx.x & 63;
+  if (threadIdx.x < kRB) {
+    rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);
+    acc[threadIdx.x][0] = acc[threadIdx.x][1] = acc[threadIdx.x][2] = acc[threadIdx.x][3] = 0;
+  }
+  if (threadIdx.x == 0) qn = 0;
+  __syncthreads();
   for (int r = 0; r < kRB; ++r) {
     const int k = k0 + r;
     if (k >= g.NK) break;
-    const int Rlo = row_cell(k, g.h, g.s);
-    int nv = 0, nt = 0, nc = 0, er = 0;
+    int nv = 0, nt = 0;
     for (int j = 0; j < kOPT; ++j) {
-      const int c = cb * kCB + j * kThreads + threadIdx.x;
+      const int c = c0 + j * kThreads + threadIdx.x;
       if (c >= g.NI) continue;
-      Owner o;
-      classify_owner<false>(g, bits, k, c, Rlo, o);
-      nv += info_nv(o.info);
-      nt += info_nt(o.info);
-      nc += info_ncut(o.info);
-      er |= info_err(o.info);
+      const Frame f = owner_frame(g, bits, k, c, rowR[r]);
+      if (frame_uniform(f)) {
+        const uint32_t fi = fast_info(g, f);
+        nv += info_nv(fi);
+        nt += info_nt(fi);
+      } else {
+        queue[atomicAdd(&qn, 1)] = (uint16_t)(r * kCB + (c - c0));
+      }
     }
-    nv = wave_sum(nv); nt = wave_sum(nt); nc = wave_sum(nc); er = wave_sum(er);
-    if (lane == 0) { red[0][wv] = nv; red[1][wv] = nt; red[2][wv] = nc; red[3][wv] = er; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int4 v = {0, 0, 0, 0};
-      for (int q = 0; q < kThreads / 64; ++q) { v.x += red[0][q]; v.y += red[1][q]; v.z += red[2][q]; v.w += red[3][q]; }
-      seg_cnt[(int64_t)k * g.NCB + cb] = v;
-      if (v.w) atomicOr((unsigned long long*)&tot[3], 1ull);
-    }
-    __syncthreads();
+    nv = wave_sum(nv);
+    nt = wave_sum(nt);
+    if (lane == 0) { atomicAdd(&acc[r][0], nv); atomicAdd(&acc[r][1], nt); }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < qn; q += kThreads) {
+    const int e = queue[q], r = e / kCB, c = c0 + (e - r * kCB);
+    const Frame f = owner_frame(g, bits, k0 + r, c, rowR[r]);
+    Slow sr;
+    slow_classify(g, f, sr);
+    atomicAdd(&acc[r][0], info_nv(sr.info));
+    atomicAdd(&acc[r][1], info_nt(sr.info));
+    atomicAdd(&acc[r][2], info_ncut(sr.info));
+    if (info_err(sr.info)) atomicOr(&acc[r][3], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < kRB && k0 + (int)threadIdx.x < g.NK) {
+    const int r = threadIdx.x;
+    seg_cnt[(int64_t)(k0 + r) * g.NCB + cb] = make_int4(acc[r][0], acc[r][1], acc[r][2], acc[r][3]);
+    if (acc[r][3]) atomicOr((unsigned long long*)&tot[3], 1ull);
   }
 }
 
@@ -217,7 +242,23 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int4* __restr
 // ---------------------------------------------------------------------------
 // Emission.
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Emission of a tile of kRB rows x kCB owners.
+//   1. counts of the tile's owners plus a one-row / one-column halo; owners
+//      with a non-uniform window are queued and classified densely, their
+//      classification kept in LDS (up to kRec of them; later ones are
+//      classified again at emission);
+//   2. prefix sums of the counts of every row in LDS, plus the segment bases
+//      from the plan, give each owner's first vertex and triangle id and its
+//      neighbours' ids;
+//   3. fast owners are emitted one per thread, then all slow owners densely.
 // grid (NCB, ceil(NK / kRB)), kThreads threads.
+// ---------------------------------------------------------------------------
+struct SlowRec {
+  uint32_t info, valid, tri, pad;
+  uint64_t seg, xm, ord;
+};
+
 __global__ void __launch_bounds__(kThreads) k_emit(Geo g, const uint32_t* __restrict__ bits,
                                                    const longlong2* __restrict__ seg_off,
                                                    const long long* __restrict__ tot, int64_t vcap, int64_t tcap,
@@ -225,88 +266,142 @@ __global__ void __launch_bounds__(kThreads) k_emit(Geo g, const uint32_t* __rest
                                                    uint8_t* __restrict__ codes) {
   constexpr int W = kCB + 2;  // columns c0-1 .. c0+CB
   __shared__ uint32_t info[kRB + 1][W];
-  __shared__ int voff[2][W];
-  __shared__ int toff[2][W];
+  __shared__ int voff[kRB + 1][W];
+  __shared__ int toff[kRB][W];
+  __shared__ uint16_t queue[(kRB + 1) * W];
+  __shared__ SlowRec rec[kRec];
+  __shared__ int qn;
   __shared__ int rowR[kRB + 1];
-  __shared__ int part[2][kThreads];
+  __shared__ long long tb[kRB];
+  __shared__ int part[kRB + 1][2][kThreads / 64];
   if (tot[0] > vcap || tot[1] > tcap || tot[3] != 0) return;  // does not fit / plan failed
   const int cb = blockIdx.x;
   const int k0 = blockIdx.y * kRB;
   const int c0 = cb * kCB;
   if (threadIdx.x <= kRB) rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);
+  if (threadIdx.x == 0) qn = 0;
   __syncthreads();
+  // 1. counts
   for (int idx = threadIdx.x; idx < (kRB + 1) * W; idx += kThreads) {
     const int rr = idx / W, col = idx - rr * W;
     const int k = k0 + rr, c = c0 - 1 + col;
-    uint32_t f = 0;
+    uint32_t fi = 0;
     if (k < g.NK && c >= 0 && c < g.NI) {
-      Owner o;
-      classify_owner<false>(g, bits, k, c, rowR[rr], o);
-      f = o.info;
+      const Frame f = owner_frame(g, bits, k, c, rowR[rr]);
+      if (frame_uniform(f)) fi = fast_info(g, f);
+      else queue[atomicAdd(&qn, 1)] = (uint16_t)idx;
     }
-    info[rr][col] = f;
+    info[rr][col] = fi;
   }
   __syncthreads();
-  // offsets of row rr (buffer b): prefix over the segment's owners, plus halo columns
-  auto scan_row = [&](int rr, int b) {
+  const int nq = qn;
+  for (int q = threadIdx.x; q < nq; q += kThreads) {
+    const int idx = queue[q], rr = idx / W, col = idx - rr * W;
+    const Frame f = owner_frame(g, bits, k0 + rr, c0 - 1 + col, rowR[rr]);
+    Slow sr;
+    slow_classify(g, f, sr);
+    info[rr][col] = sr.info;
+    if (q < kRec) {
+      SlowRec& R = rec[q];
+      R.info = sr.info; R.valid = sr.valid; R.tri = sr.tri; R.seg = sr.seg; R.xm = sr.xm; R.ord = sr.ord;
+    }
+  }
+  __syncthreads();
+  // 2. prefix sums of every row: thread t owns columns 1 + t*kOPT .. kOPT + t*kOPT
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int ev[kRB + 1], et[kRB + 1];
+#pragma unroll
+  for (int rr = 0; rr <= kRB; ++rr) {
+    int sv = 0, st = 0;
+#pragma unroll
+    for (int j = 0; j < kOPT; ++j) {
+      const uint32_t f = info[rr][1 + threadIdx.x * kOPT + j];
+      sv += info_nv(f);
+      st += info_nt(f);
+    }
+    const int iv = wave_incl_scan(sv, lane), it = wave_incl_scan(st, lane);
+    ev[rr] = iv - sv;
+    et[rr] = it - st;
+    if (lane == 63) { part[rr][0][wv] = iv; part[rr][1][wv] = it; }
+  }
+  if (threadIdx.x < kRB) tb[threadIdx.x] = k0 + (int)threadIdx.x < g.NK ? seg_off[(int64_t)(k0 + threadIdx.x) * g.NCB + cb].y : 0;
+  __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr <= kRB; ++rr) {
     const int k = k0 + rr;
-    const bool ok = k < g.NK;
-    const longlong2 base = ok ? seg_off[(int64_t)k * g.NCB + cb] : make_longlong2(0, 0);
-    // thread t owns columns 1 + 2t, 2 + 2t
-    const int ca = 1 + 2 * threadIdx.x, cbb = 2 + 2 * threadIdx.x;
-    const int va = info_nv(info[rr][ca]), vb = info_nv(info[rr][cbb]);
-    const int ta = info_nt(info[rr][ca]), tb = info_nt(info[rr][cbb]);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int sv = wave_incl_scan(va + vb, lane), st = wave_incl_scan(ta + tb, lane);
-    if (lane == 63) { part[0][wv] = sv; part[1][wv] = st; }
-    __syncthreads();
-    int pv = 0, pt = 0, totv = 0, tott = 0;
+    const int bv = k < g.NK ? (int)seg_off[(int64_t)k * g.NCB + cb].x : 0;
+    int pv = 0, pt = 0, totv = 0;
+#pragma unroll
     for (int q = 0; q < kThreads / 64; ++q) {
-      if (q < wv) { pv += part[0][q]; pt += part[1][q]; }
-      totv += part[0][q]; tott += part[1][q];
+      if (q < wv) { pv += part[rr][0][q]; pt += part[rr][1][q]; }
+      totv += part[rr][0][q];
     }
-    const int ev = sv - (va + vb) + pv, et = st - (ta + tb) + pt;
-    const int bv = (int)base.x, bt = (int)0;
-    voff[b][ca] = bv + ev; voff[b][cbb] = bv + ev + va;
-    toff[b][ca] = bt + et; toff[b][cbb] = bt + et + ta;
+    int v = bv + ev[rr] + pv, t = et[rr] + pt;
+#pragma unroll
+    for (int j = 0; j < kOPT; ++j) {
+      const int col = 1 + threadIdx.x * kOPT + j;
+      const uint32_t f = info[rr][col];
+      voff[rr][col] = v;
+      if (rr < kRB) toff[rr][col] = t;
+      v += info_nv(f);
+      t += info_nt(f);
+    }
     if (threadIdx.x == 0) {
-      voff[b][0] = bv - info_nv(info[rr][0]);
-      voff[b][W - 1] = bv + totv;
+      voff[rr][0] = bv - info_nv(info[rr][0]);
+      voff[rr][W - 1] = bv + totv;
     }
-    (void)tott;
-    __syncthreads();
+  }
+  __syncthreads();
+  auto neighbours = [&](int r, int col, uint32_t f, int o_) {
+    Nb nb;
+    nb.vid = voff[r][col];
+    nb.id_vr = voff[r][col + 1];
+    nb.id_vdl = voff[r + 1][col + o_ - 1];
+    nb.id_vdr = voff[r + 1][col + o_];
+    nb.b0 = nb.vid + info_self(f);
+    nb.b1 = nb.b0 + info_n(f, 0);
+    nb.b2 = nb.b1 + info_n(f, 1);
+    const uint32_t fr = info[r][col + 1];
+    nb.b3 = voff[r][col + 1] + info_self(fr) + info_n(fr, 0);
+    const uint32_t fl = info[r + 1][col + o_ - 1];
+    nb.b4 = voff[r + 1][col + o_ - 1] + info_self(fl);
+    nb.bI = nb.b2 + info_n(f, 2);
+    return nb;
   };
-  scan_row(0, 0);
+  // 3a. fast owners, one per thread
   for (int r = 0; r < kRB; ++r) {
     const int k = k0 + r;
     if (k >= g.NK) break;
-    const int cur = r & 1, nxt = cur ^ 1;
-    scan_row(r + 1, nxt);
-    const int64_t tbase = seg_off[(int64_t)k * g.NCB + cb].y;
     const int o_ = k & 1;
     for (int j = 0; j < kOPT; ++j) {
       const int col = 1 + j * kThreads + threadIdx.x;
       const int c = c0 + col - 1;
       if (c >= g.NI) continue;
       const uint32_t f = info[r][col];
-      if (info_nv(f) == 0 && info_nt(f) == 0) continue;
-      Nb nb;
-      nb.vid = voff[cur][col];
-      nb.id_vr = voff[cur][col + 1];
-      nb.id_vdl = voff[nxt][col + o_ - 1];
-      nb.id_vdr = voff[nxt][col + o_];
-      const int self = info_self(f);
-      nb.base[0] = nb.vid + self;
-      nb.base[1] = nb.base[0] + info_n(f, 0);
-      nb.base[2] = nb.base[1] + info_n(f, 1);
-      const uint32_t fr = info[r][col + 1];
-      nb.base[3] = voff[cur][col + 1] + info_self(fr) + info_n(fr, 0);
-      const uint32_t fl = info[r + 1][col + o_ - 1];
-      nb.base[4] = voff[nxt][col + o_ - 1] + info_self(fl);
-      nb.baseI = nb.base[2] + info_n(f, 2);
-      emit_owner(g, bits, k, c, rowR[r], f, nb, tbase + toff[cur][col], verts, tris, codes);
+      if (info_slow(f) || (info_nv(f) == 0 && info_nt(f) == 0)) continue;
+      const Nb nb = neighbours(r, col, f, o_);
+      Frame fr;
+      fr.k = k; fr.i = c; fr.o = o_; fr.X = g.X0 + 4 * g.h * c + 2 * g.h * o_;
+      fr.Rlo = rowR[r]; fr.Clo = 0; fr.s9 = 0;
+      emit_owner(g, fr, f, nullptr, nb, tb[r] + toff[r][col], verts, tris, codes);
     }
-    __syncthreads();
+  }
+  // 3b. slow owners of the tile (not the halo), densely
+  for (int q = threadIdx.x; q < nq; q += kThreads) {
+    const int idx = queue[q], r = idx / W, col = idx - r * W;
+    if (r >= kRB || col < 1 || col > kCB) continue;
+    const int k = k0 + r, c = c0 + col - 1;
+    const uint32_t f = info[r][col];
+    const Nb nb = neighbours(r, col, f, k & 1);
+    const Frame fr = owner_frame(g, bits, k, c, rowR[r]);
+    Slow sr;
+    if (q < kRec) {
+      const SlowRec& R = rec[q];
+      sr.info = R.info; sr.valid = R.valid; sr.tri = R.tri; sr.seg = R.seg; sr.xm = R.xm; sr.ord = R.ord;
+    } else {
+      slow_classify(g, fr, sr);
+    }
+    emit_owner(g, fr, f, &sr, nb, tb[r] + toff[r][col], verts, tris, codes);
   }
 }
 
@@ -360,8 +455,8 @@ static bool windows_in_bounds(const Geo& g) {
   const int64_t clo_min = host_floordiv(xmin - 2 * g.h - 2 * (g.s - 1), 4 * g.s);
   const int64_t clo_max = host_floordiv(xmax - 2 * g.h - 2 * (g.s - 1), 4 * g.s);
   // rows Rlo .. Rlo+2 and bit columns Clo .. Clo+2 (plus one spare word) are read
-  return rlo_min + kRing >= 0 && rlo_max + 2 + kRing < g.CH + 2 * kRing && clo_min + kRing >= 0 &&
-         ((clo_max + 2 + kRing) >> 5) + 1 < g.wpr;
+  return rlo_min + kRing >= 0 && rlo_max + 2 + kRing < g.CH + 2 * kRing && clo_min + kRingC >= 0 &&
+         ((clo_max + 2 + kRingC) >> 5) + 1 < g.wpr;
 }
 
 struct Layout {
@@ -396,9 +491,10 @@ static sbmt_status make_layout(const sbmt_image* img, Layout* L, bool need_ptr =
   g.NK = (int32_t)(m + 1);
   g.NI = (int32_t)((4LL * g.s * g.CW + 2LL * g.h + 1) / (4LL * g.h) + 2);
   g.NCB = (g.NI + kCB - 1) / kCB;
-  g.wpr = (g.CW + 2 * kRing + 31) / 32 + 1;
+  g.wpr = (kRingC + g.CW + kRing + 31) / 32 + 1;
   g.X0 = -2 * g.h - 3;
   g.flags = img->flags;
+  g.inv4s = 1.0f / (float)(4 * g.s);
   if (!windows_in_bounds(g)) return SBMT_E_INVALID_ARG;
   L->nseg = (int64_t)g.NK * g.NCB;
   L->nblk = (int)((L->nseg + kScanChunk - 1) / kScanChunk);
@@ -430,8 +526,8 @@ static Work work_of(const Layout& L, void* ws) {
 
 static sbmt_status launch_plan(const Layout& L, const sbmt_image* img, const Work& w, hipStream_t st) {
   const Geo& g = L.g;
-  dim3 gc((g.wpr + 63) / 64, g.CH + 2 * kRing);
-  hipLaunchKernelGGL(k_coarsen, gc, dim3(64), 0, st, g, img->bitmap, w.bits, w.tot);
+  dim3 gc((32 * g.wpr + 255) / 256, g.CH + 2 * kRing);
+  hipLaunchKernelGGL(k_coarsen, gc, dim3(256), 0, st, g, img->bitmap, w.bits, w.tot);
   dim3 gk(g.NCB, (g.NK + kRB - 1) / kRB);
   hipLaunchKernelGGL(k_count, gk, dim3(kThreads), 0, st, g, (const uint32_t*)w.bits, w.seg_cnt, w.tot);
   hipLaunchKernelGGL(k_scan_reduce, dim3(L.nblk), dim3(kScanThreads), 0, st, (const int4*)w.seg_cnt, L.nseg, w.blk);

@@ -67,3 +67,27 @@ def test_invalid_arguments_rejected_on_host(L):
     assert e.value.status == -1
     with pytest.raises(sbmt.SbmtError):
         sbmt.query(64, 64, 1, flags=8)
+
+
+def test_image_marshalling_of_degenerate_strides():
+    """Row/column views with stride 0 on a size-1 dimension, strided rows, empty images."""
+    import numpy as np
+    import torch
+
+    import paper_2602_19474_amd as sbmt
+    row = torch.from_numpy((np.arange(10) % 3 < 2).astype(np.uint8)[None, :])
+    col = torch.from_numpy((np.arange(9) % 3 < 2).astype(np.uint8)[:, None])
+    assert row.stride(0) == 0 and col.stride(1) == 0
+    a = sbmt._image(row, 1, 0)
+    assert (a.width, a.height, a.row_stride) == (10, 1, 10)
+    b = sbmt._image(col, 1, 0)
+    assert (b.width, b.height, b.row_stride) == (1, 9, col.stride(0))
+    big = torch.zeros((5, 12), dtype=torch.uint8)
+    c = sbmt._image(big[:, :7], 2, 1)
+    assert (c.width, c.height, c.row_stride, c.flags) == (7, 5, 12, 1)
+    e = sbmt._image(torch.zeros((0, 0), dtype=torch.uint8), 1, 0)
+    assert (e.width, e.height) == (0, 0) and not e.bitmap
+    with pytest.raises(ValueError):
+        sbmt._image(big.t(), 1, 0)
+    with pytest.raises(ValueError):
+        sbmt._image(big.float(), 1, 0)

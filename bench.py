@@ -194,6 +194,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (one process, one MI355X); --gpus {args.gpus} is not supported. "
@@ -216,6 +218,13 @@ def main():
     torch.cuda.set_device(0)
     import paper_2602_19474_amd  # noqa: F401  (fails loudly if the HIP library is missing)
 
+    if args.copy_ref:
+        # a plain elementwise kernel reading and writing exactly 1 GiB each
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     H = headline(noise, args.steps, args.warmup)
     sz = H["sizes"]
     ms = H["wall"] / args.steps * 1e3

@@ -18,6 +18,10 @@ App. G):
   cases, App. G "Orientation handling"); the rotation stored is the first j
   reaching it.  Class ids number the admissible canonical codes in ascending
   order from 1 (0 = uncut).
+* ``sbmt_lut_emit[class][rot][t][5]``: the same sub-triangles for triangle t
+  (0 apex on the owner's row, 1 base on it) of an owner, seen through rotation
+  rot, as triples of structural id slots in output order (see
+  ``emission_order``), one uint16 per sub-triangle: a | b << 4 | c << 8 | side << 12.
 * ``sbmt_lut_tri[class][5]``: the template in canonical labels, one uint16 per
   sub-triangle: a | b << 4 | c << 8 | side << 12, labels 0..2 corners,
   3 + 2e + r crossing X(e, r), 9 the chain vertex; side 1 = left of the chain
@@ -180,6 +184,49 @@ def template_of(code: int):
     return tris
 
 
+# Structural slots of the ids a base triangle of owner (k, i) can reference.
+# Their numeric order is fixed by the owner numbering (own vertex, own
+# crossings on E0, E1, E2, own chain vertices, then the next owner's vertex
+# and its crossings on E3, then the row-below owners), so sorting by slot sorts
+# by id:
+#   0 v | 1,2 E0 | 3,4 E1 | 5,6 E2 | 7 I in Tb | 8 I in Ta | 9 vr | 10,11 E3 |
+#   12 vdl | 13,14 E4 | 15 vdr
+# Local edges of the triangles as (edge id, direction): Tb (t = 0):
+# (E2,+) (E4,-) (E1,-); Ta (t = 1): (E0,+) (E3,+) (E2,-).
+TRI_EDGE = {0: [(2, 1), (4, -1), (1, -1)], 1: [(0, 1), (3, 1), (2, -1)]}
+EDGE_SLOT = {0: 1, 1: 3, 2: 5, 3: 10, 4: 13}
+CORNER_SLOT = {0: [0, 15, 12], 1: [0, 9, 15]}
+
+
+def emission_order(canon: int, rot: int, t: int):
+    """Template of class `canon` seen through rotation `rot` on triangle t: the
+    sub-triangles as slot triples rotated to start at the smallest slot and
+    sorted, i.e. in output order; each with its side."""
+    typ, tok = decode(canon)
+    n = ntok(typ)
+    # instance tokens: canonical edge e is instance edge e - rot
+    inst = [2 * (((x >> 1) - rot) % 3) + (x & 1) for x in tok[:n]]
+    count = [sum(1 for x in inst if x >> 1 == e) for e in range(3)]
+    out = []
+    for (a, b, c, side) in template_of(canon):
+        slots = []
+        for lab in (a, b, c):
+            if lab < 3:
+                slots.append(CORNER_SLOT[t][(lab - rot) % 3])
+            elif lab < 9:
+                x = lab - 3
+                e, r = ((x >> 1) - rot) % 3, x & 1
+                eid, d = TRI_EDGE[t][e]
+                re = r if d > 0 else count[e] - 1 - r
+                slots.append(EDGE_SLOT[eid] + re)
+            else:
+                slots.append(7 + t)
+        m = slots.index(min(slots))
+        out.append((tuple(slots[m:] + slots[:m]), side))
+    out.sort()
+    return out
+
+
 def build():
     codes = [c for c in range(1 << 14) if faces_of(c) is not None]
     canon = sorted({canonical(c)[0] for c in codes})
@@ -196,7 +243,18 @@ def build():
         tri.append([a | (b << 4) | (c << 8) | (s << 12) for (a, b, c, s) in ts] + [0] * (5 - len(ts)))
         ntri.append(len(ts))
         nfg.append(sum(s for (_, _, _, s) in ts))
-    return {"canon": canon, "key": key, "tri": tri, "ntri": ntri, "nfg": nfg}
+    emit = [[[[0] * 5 for _ in range(2)] for _ in range(3)]]
+    for cc in canon:
+        per_rot = []
+        for rot in range(3):
+            per_t = []
+            for t in range(2):
+                seq = emission_order(cc, rot, t)
+                row = [a | (b << 4) | (c << 8) | (s << 12) for ((a, b, c), s) in seq]
+                per_t.append(row + [0] * (5 - len(row)))
+            per_rot.append(per_t)
+        emit.append(per_rot)
+    return {"canon": canon, "key": key, "tri": tri, "ntri": ntri, "nfg": nfg, "emit": emit}
 
 
 def emit_header(tables) -> str:
@@ -220,6 +278,11 @@ def emit_header(tables) -> str:
         f"SBMT_CONST const uint16_t sbmt_lut_tri[{len(canon) + 1}][5] = {{",
     ]
     lines += ["  {" + ", ".join(f"0x{v:04x}" for v in row) + "}," for row in tables["tri"]]
+    lines.append("};")
+    lines.append(f"SBMT_CONST const uint16_t sbmt_lut_emit[{len(canon) + 1}][3][2][5] = {{")
+    for per_rot in tables["emit"]:
+        lines.append("  {" + ", ".join("{" + ", ".join("{" + ", ".join(f"0x{v:04x}" for v in row) + "}"
+                                                        for row in per_t) + "}" for per_t in per_rot) + "},")
     lines.append("};")
     lines.append("SBMT_CONST const uint8_t sbmt_lut_key[16384] = {")
     key = tables["key"]

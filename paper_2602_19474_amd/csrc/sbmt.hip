@@ -33,12 +33,13 @@ SBMT_HD int lut_key(int code) { return sbmt_lut_key[code]; }
 SBMT_HD int lut_nfg(int cls) { return sbmt_lut_nfg[cls]; }
 SBMT_HD int lut_ntri(int cls) { return sbmt_lut_ntri[cls]; }
 SBMT_HD uint32_t lut_tri(int cls, int j) { return sbmt_lut_tri[cls][j]; }
+SBMT_HD uint32_t lut_emit(int cls, int rot, int t, int j) { return sbmt_lut_emit[cls][rot][t][j]; }
 
 constexpr int kThreads = 256;
 constexpr int kCB = 256;          // owners per row segment
 constexpr int kOPT = kCB / kThreads;  // owners per thread per row
 constexpr int kRB = 8;            // rows per emission tile
-constexpr int kRec = 384;         // slow-owner records kept in LDS per emission tile
+constexpr int kRec = 192;         // slow-owner records kept in LDS per emission tile
 constexpr int kScanThreads = 1024;
 constexpr int kScanChunk = 4 * kScanThreads;
 
@@ -83,6 +84,29 @@ __global__ void __launch_bounds__(256) k_coarsen(Geo g, const uint8_t* __restric
   if (lane < 2 && w < g.wpr) bits[(int64_t)rr * g.wpr + w] = (uint32_t)(m >> (32 * lane));
 }
 
+// Stage the coarse-raster window of a tile (grid rows k0 .. k0 + nk - 1, owner
+// columns cfirst .. clast) in LDS; returns the view.  Sizes are checked on the
+// host (tile_window_fits).
+constexpr int kWinRows = 16, kWinWords = 16;
+
+__device__ __forceinline__ Bits stage_window(const Geo& g, const uint32_t* __restrict__ bits, uint32_t* win, int rlo, int rhi,
+                             int cfirst, int clast) {
+  const int x0 = g.X0 + 4 * g.h * cfirst, x1 = g.X0 + 4 * g.h * clast + 2 * g.h;
+  const int wlo = (clo_of(g, x0) + kRingC) >> 5;
+  const int whi = ((clo_of(g, x1) + 2 + kRingC) >> 5) + 1;
+  const int nw = whi - wlo + 1, nr = rhi - rlo + 1;
+  for (int t = threadIdx.x; t < nr * nw; t += blockDim.x) {
+    const int r = t / nw, w = t - r * nw;
+    win[r * nw + w] = bits[(int64_t)(rlo + r) * g.wpr + wlo + w];
+  }
+  Bits b;
+  b.p = win;
+  b.wpr = nw;
+  b.rr0 = rlo;
+  b.cc0 = 32 * wlo;
+  return b;
+}
+
 __device__ __forceinline__ int wave_sum(int v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
@@ -94,12 +118,14 @@ __device__ __forceinline__ int wave_sum(int v) {
 // tile and classified densely afterwards.
 // grid (NCB, ceil(NK / kRB)), kThreads threads, kOPT owners per thread per row.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) k_count(Geo g, const uint32_t* __restrict__ bits,
+__global__ void __launch_bounds__(kThreads) k_count(Geo g, const uint32_t* __restrict__ bits_g,
                                                     int4* __restrict__ seg_cnt, long long* __restrict__ tot) {
   __shared__ int acc[kRB][4];
   __shared__ int rowR[kRB];
-  __shared__ uint16_t queue[kRB * kCB];
-  __shared__ int qn;
+  __shared__ uint16_t q1[kRB * kCB];
+  __shared__ uint16_t q2[kRB * kCB];
+  __shared__ int n1, n2;
+  __shared__ uint32_t win[kWinRows * kWinWords];
   const int cb = blockIdx.x;
   const int k0 = blockIdx.y * kRB;
   const int c0 = cb * kCB;
@@ -108,8 +134,13 @@ __global__ void __launch_bounds__(kThreads) k_count(Geo g, const uint32_t* __res
     rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);
     acc[threadIdx.x][0] = acc[threadIdx.x][1] = acc[threadIdx.x][2] = acc[threadIdx.x][3] = 0;
   }
-  if (threadIdx.x == 0) qn = 0;
+  if (threadIdx.x == 0) n1 = n2 = 0;
   __syncthreads();
+  const int klast = min(k0 + kRB, g.NK) - 1;
+  const Bits bw = stage_window(g, bits_g, win, rowR[0] + kRing, rowR[klast - k0] + 2 + kRing, c0,
+                               min(c0 + kCB, g.NI) - 1);
+  __syncthreads();
+  // uniform windows, one owner per thread; the others are queued
   for (int r = 0; r < kRB; ++r) {
     const int k = k0 + r;
     if (k >= g.NK) break;
@@ -117,23 +148,36 @@ __global__ void __launch_bounds__(kThreads) k_count(Geo g, const uint32_t* __res
     for (int j = 0; j < kOPT; ++j) {
       const int c = c0 + j * kThreads + threadIdx.x;
       if (c >= g.NI) continue;
-      const Frame f = owner_frame(g, bits, k, c, rowR[r]);
+      const Frame f = owner_frame(g, bw, k, c, rowR[r]);
       if (frame_uniform(f)) {
         const uint32_t fi = fast_info(g, f);
         nv += info_nv(fi);
         nt += info_nt(fi);
       } else {
-        queue[atomicAdd(&qn, 1)] = (uint16_t)(r * kCB + (c - c0));
+        q1[atomicAdd(&n1, 1)] = (uint16_t)(r * kCB + (c - c0));
       }
     }
     nv = wave_sum(nv);
     nt = wave_sum(nt);
-    if (lane == 0) { atomicAdd(&acc[r][0], nv); atomicAdd(&acc[r][1], nt); }
+    if (lane == 0 && (nv | nt)) { atomicAdd(&acc[r][0], nv); atomicAdd(&acc[r][1], nt); }
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < qn; q += kThreads) {
-    const int e = queue[q], r = e / kCB, c = c0 + (e - r * kCB);
-    const Frame f = owner_frame(g, bits, k0 + r, c, rowR[r]);
+  // non-uniform windows: quiet owners (no segment reaches them) or slow ones
+  for (int q = threadIdx.x; q < n1; q += kThreads) {
+    const int e = q1[q], r = e / kCB, c = c0 + (e - r * kCB);
+    const Frame f = owner_frame(g, bw, k0 + r, c, rowR[r]);
+    uint32_t fi = 0;
+    if (needs_slow(g, f, fi)) {
+      q2[atomicAdd(&n2, 1)] = (uint16_t)e;
+    } else {
+      atomicAdd(&acc[r][0], info_nv(fi));
+      atomicAdd(&acc[r][1], info_nt(fi));
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < n2; q += kThreads) {
+    const int e = q2[q], r = e / kCB, c = c0 + (e - r * kCB);
+    const Frame f = owner_frame(g, bw, k0 + r, c, rowR[r]);
     Slow sr;
     slow_classify(g, f, sr);
     atomicAdd(&acc[r][0], info_nv(sr.info));
@@ -254,12 +298,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int4* __restr
 //   3. fast owners are emitted one per thread, then all slow owners densely.
 // grid (NCB, ceil(NK / kRB)), kThreads threads.
 // ---------------------------------------------------------------------------
-struct SlowRec {
-  uint32_t info, valid, tri, pad;
-  uint64_t seg, xm, ord;
-};
-
-__global__ void __launch_bounds__(kThreads) k_emit(Geo g, const uint32_t* __restrict__ bits,
+__global__ void __launch_bounds__(kThreads) k_emit(Geo g, const uint32_t* __restrict__ bits_g,
                                                    const longlong2* __restrict__ seg_off,
                                                    const long long* __restrict__ tot, int64_t vcap, int64_t tcap,
                                                    double* __restrict__ verts, int32_t* __restrict__ tris,
@@ -267,44 +306,56 @@ __global__ void __launch_bounds__(kThreads) k_emit(Geo g, const uint32_t* __rest
   constexpr int W = kCB + 2;  // columns c0-1 .. c0+CB
   __shared__ uint32_t info[kRB + 1][W];
   __shared__ int voff[kRB + 1][W];
-  __shared__ int toff[kRB][W];
+  __shared__ int16_t toff[kRB][W];
+  __shared__ uint32_t win[kWinRows * kWinWords];
   __shared__ uint16_t queue[(kRB + 1) * W];
+  __shared__ uint16_t q1[(kRB + 1) * W];
   __shared__ SlowRec rec[kRec];
-  __shared__ int qn;
+  __shared__ int qn, n1;
   __shared__ int rowR[kRB + 1];
   __shared__ long long tb[kRB];
   __shared__ int part[kRB + 1][2][kThreads / 64];
+  __shared__ int trow[kRB];
   if (tot[0] > vcap || tot[1] > tcap || tot[3] != 0) return;  // does not fit / plan failed
   const int cb = blockIdx.x;
   const int k0 = blockIdx.y * kRB;
   const int c0 = cb * kCB;
   if (threadIdx.x <= kRB) rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);
-  if (threadIdx.x == 0) qn = 0;
+  if (threadIdx.x == 0) qn = n1 = 0;
   __syncthreads();
-  // 1. counts
+  const int klast = min(k0 + kRB + 1, g.NK) - 1;
+  const Bits bw = stage_window(g, bits_g, win, rowR[0] + kRing, rowR[max(klast - k0, 0)] + 2 + kRing,
+                               max(c0 - 1, 0), min(c0 + kCB + 1, g.NI) - 1);
+  __syncthreads();
+  // 1. counts: uniform windows one owner per thread, then the queued ones densely
   for (int idx = threadIdx.x; idx < (kRB + 1) * W; idx += kThreads) {
     const int rr = idx / W, col = idx - rr * W;
     const int k = k0 + rr, c = c0 - 1 + col;
     uint32_t fi = 0;
     if (k < g.NK && c >= 0 && c < g.NI) {
-      const Frame f = owner_frame(g, bits, k, c, rowR[rr]);
+      const Frame f = owner_frame(g, bw, k, c, rowR[rr]);
       if (frame_uniform(f)) fi = fast_info(g, f);
-      else queue[atomicAdd(&qn, 1)] = (uint16_t)idx;
+      else q1[atomicAdd(&n1, 1)] = (uint16_t)idx;
     }
     info[rr][col] = fi;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < n1; q += kThreads) {
+    const int idx = q1[q], rr = idx / W, col = idx - rr * W;
+    const Frame f = owner_frame(g, bw, k0 + rr, c0 - 1 + col, rowR[rr]);
+    uint32_t fi = 0;
+    if (needs_slow(g, f, fi)) queue[atomicAdd(&qn, 1)] = (uint16_t)idx;
+    else info[rr][col] = fi;
   }
   __syncthreads();
   const int nq = qn;
   for (int q = threadIdx.x; q < nq; q += kThreads) {
     const int idx = queue[q], rr = idx / W, col = idx - rr * W;
-    const Frame f = owner_frame(g, bits, k0 + rr, c0 - 1 + col, rowR[rr]);
+    const Frame f = owner_frame(g, bw, k0 + rr, c0 - 1 + col, rowR[rr]);
     Slow sr;
     slow_classify(g, f, sr);
     info[rr][col] = sr.info;
-    if (q < kRec) {
-      SlowRec& R = rec[q];
-      R.info = sr.info; R.valid = sr.valid; R.tri = sr.tri; R.seg = sr.seg; R.xm = sr.xm; R.ord = sr.ord;
-    }
+    if (q < kRec) rec[q] = pack_slow(sr);
   }
   __syncthreads();
   // 2. prefix sums of every row: thread t owns columns 1 + t*kOPT .. kOPT + t*kOPT
@@ -342,13 +393,18 @@ __global__ void __launch_bounds__(kThreads) k_emit(Geo g, const uint32_t* __rest
       const int col = 1 + threadIdx.x * kOPT + j;
       const uint32_t f = info[rr][col];
       voff[rr][col] = v;
-      if (rr < kRB) toff[rr][col] = t;
+      if (rr < kRB) toff[rr][col] = (int16_t)t;
       v += info_nv(f);
       t += info_nt(f);
     }
     if (threadIdx.x == 0) {
       voff[rr][0] = bv - info_nv(info[rr][0]);
       voff[rr][W - 1] = bv + totv;
+      if (rr < kRB) {
+        int tt = 0;
+        for (int q = 0; q < kThreads / 64; ++q) tt += part[rr][1][q];
+        trow[rr] = tt;
+      }
     }
   }
   __syncthreads();
@@ -368,40 +424,54 @@ __global__ void __launch_bounds__(kThreads) k_emit(Geo g, const uint32_t* __rest
     nb.bI = nb.b2 + info_n(f, 2);
     return nb;
   };
-  // 3a. fast owners, one per thread
+  // 3. fast owners one per thread (their writes coalesce), then all slow
+  // owners of the tile densely from their records.
+  const bool both = (g.flags & 1u) != 0;
+  Out out;
+  out.v = verts; out.t = tris; out.c = codes; out.vbase = 0; out.tbase = 0;
   for (int r = 0; r < kRB; ++r) {
     const int k = k0 + r;
     if (k >= g.NK) break;
     const int o_ = k & 1;
+    const double y = lat_y(g.h, k);
+    const int64_t TB = tb[r];
     for (int j = 0; j < kOPT; ++j) {
       const int col = 1 + j * kThreads + threadIdx.x;
       const int c = c0 + col - 1;
       if (c >= g.NI) continue;
       const uint32_t f = info[r][col];
-      if (info_slow(f) || (info_nv(f) == 0 && info_nt(f) == 0)) continue;
-      const Nb nb = neighbours(r, col, f, o_);
-      Frame fr;
-      fr.k = k; fr.i = c; fr.o = o_; fr.X = g.X0 + 4 * g.h * c + 2 * g.h * o_;
-      fr.Rlo = rowR[r]; fr.Clo = 0; fr.s9 = 0;
-      emit_owner(g, fr, f, nullptr, nb, tb[r] + toff[r][col], verts, tris, codes);
+      if (info_slow(f)) continue;
+      const int vid = voff[r][col];
+      if (info_self(f)) put_vertex(verts, vid, lat_x(g.X0 + 4 * g.h * c + 2 * g.h * o_), y);
+      int64_t u = TB + toff[r][col];
+      const uint8_t code = both && !info_fg(f) ? 0x80 : 0;
+      if (info_ntb(f)) {
+        tris[3 * u + 0] = vid; tris[3 * u + 1] = voff[r + 1][col + o_]; tris[3 * u + 2] = voff[r + 1][col + o_ - 1];
+        codes[u] = code;
+        ++u;
+      }
+      if (info_nta(f)) {
+        tris[3 * u + 0] = vid; tris[3 * u + 1] = voff[r][col + 1]; tris[3 * u + 2] = voff[r + 1][col + o_];
+        codes[u] = code;
+      }
     }
   }
-  // 3b. slow owners of the tile (not the halo), densely
   for (int q = threadIdx.x; q < nq; q += kThreads) {
     const int idx = queue[q], r = idx / W, col = idx - r * W;
     if (r >= kRB || col < 1 || col > kCB) continue;
     const int k = k0 + r, c = c0 + col - 1;
     const uint32_t f = info[r][col];
     const Nb nb = neighbours(r, col, f, k & 1);
-    const Frame fr = owner_frame(g, bits, k, c, rowR[r]);
-    Slow sr;
+    const Frame fr = owner_frame(g, bw, k, c, rowR[r]);
+    SlowRec R;
     if (q < kRec) {
-      const SlowRec& R = rec[q];
-      sr.info = R.info; sr.valid = R.valid; sr.tri = R.tri; sr.seg = R.seg; sr.xm = R.xm; sr.ord = R.ord;
+      R = rec[q];
     } else {
+      Slow sr;
       slow_classify(g, fr, sr);
+      R = pack_slow(sr);
     }
-    emit_owner(g, fr, f, &sr, nb, tb[r] + toff[r][col], verts, tris, codes);
+    emit_slow(g, fr, R, nb, tb[r] + toff[r][col], out);
   }
 }
 
@@ -449,6 +519,14 @@ static int64_t host_row_cell(int64_t k, int h, int s) {
   while (host_z3sign(-(2 * s * (R + 1) + s + 1), kh) >= 0) ++R;
   return R;
 }
+static bool tile_window_fits(const Geo& g) {
+  // rows: the cell rows of kRB + 1 grid rows plus the 3x3 window; words: the
+  // cell columns of kCB + 2 owners plus the window and one spare word
+  const double rows = ((kRB + 1) * g.h * 0.8660254037844386) / g.s + 5;
+  const double words = ((kCB + 2) * (double)g.h / g.s + 4) / 32.0 + 3;
+  return rows <= kWinRows && words <= kWinWords;
+}
+
 static bool windows_in_bounds(const Geo& g) {
   const int64_t rlo_min = host_row_cell(0, g.h, g.s), rlo_max = host_row_cell(g.NK - 1, g.h, g.s);
   const int64_t xmin = g.X0, xmax = (int64_t)g.X0 + 4LL * g.h * (g.NI - 1) + 2LL * g.h;
@@ -495,7 +573,7 @@ static sbmt_status make_layout(const sbmt_image* img, Layout* L, bool need_ptr =
   g.X0 = -2 * g.h - 3;
   g.flags = img->flags;
   g.inv4s = 1.0f / (float)(4 * g.s);
-  if (!windows_in_bounds(g)) return SBMT_E_INVALID_ARG;
+  if (!windows_in_bounds(g) || !tile_window_fits(g)) return SBMT_E_INVALID_ARG;
   L->nseg = (int64_t)g.NK * g.NCB;
   L->nblk = (int)((L->nseg + kScanChunk - 1) / kScanChunk);
   size_t off = 0;

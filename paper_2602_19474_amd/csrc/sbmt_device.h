@@ -103,27 +103,27 @@ SBMT_HD int row_cell(int k, int h, int s) {
 // foreground->background transition to the next background->foreground one,
 // so background corners are cut off (foreground 8-connected at saddles).
 // Entry: count | (start0 | end0 << 2) << 2 | (start1 | end1 << 2) << 6.
-#define SBMT_MS(n, a0, b0, a1, b1) (uint16_t)((n) | (((a0) | ((b0) << 2)) << 2) | (((a1) | ((b1) << 2)) << 6))
-SBMT_HD uint16_t ms_case(int c) {
-  switch (c) {
-    case 1: return SBMT_MS(1, 0, 3, 0, 0);
-    case 2: return SBMT_MS(1, 1, 0, 0, 0);
-    case 3: return SBMT_MS(1, 1, 3, 0, 0);
-    case 4: return SBMT_MS(1, 2, 1, 0, 0);
-    case 5: return SBMT_MS(2, 0, 1, 2, 3);
-    case 6: return SBMT_MS(1, 2, 0, 0, 0);
-    case 7: return SBMT_MS(1, 2, 3, 0, 0);
-    case 8: return SBMT_MS(1, 3, 2, 0, 0);
-    case 9: return SBMT_MS(1, 0, 2, 0, 0);
-    case 10: return SBMT_MS(2, 1, 2, 3, 0);
-    case 11: return SBMT_MS(1, 1, 2, 0, 0);
-    case 12: return SBMT_MS(1, 3, 1, 0, 0);
-    case 13: return SBMT_MS(1, 0, 1, 0, 0);
-    case 14: return SBMT_MS(1, 3, 0, 0, 0);
-    default: return 0;
-  }
+// Marching squares, corners in positive order TL, TR, BR, BL (bit 0..3); cell
+// edge midpoints 0 top, 1 right, 2 bottom, 3 left.  A segment runs from each
+// foreground->background transition to the next background->foreground one,
+// so background corners are cut off (foreground 8-connected at saddles).
+// Entry: count | (start0 | end0 << 2) << 2 | (start1 | end1 << 2) << 6.
+constexpr uint32_t ms_entry(int n, int a0, int b0, int a1, int b1) {
+  return (uint32_t)(n | ((a0 | (b0 << 2)) << 2) | ((a1 | (b1 << 2)) << 6));
 }
-#undef SBMT_MS
+constexpr uint64_t ms_pack4(uint32_t e0, uint32_t e1, uint32_t e2, uint32_t e3) {
+  return (uint64_t)e0 | ((uint64_t)e1 << 16) | ((uint64_t)e2 << 32) | ((uint64_t)e3 << 48);
+}
+constexpr uint64_t kMS0 = ms_pack4(0, ms_entry(1, 0, 3, 0, 0), ms_entry(1, 1, 0, 0, 0), ms_entry(1, 1, 3, 0, 0));
+constexpr uint64_t kMS1 = ms_pack4(ms_entry(1, 2, 1, 0, 0), ms_entry(2, 0, 1, 2, 3), ms_entry(1, 2, 0, 0, 0),
+                                   ms_entry(1, 2, 3, 0, 0));
+constexpr uint64_t kMS2 = ms_pack4(ms_entry(1, 3, 2, 0, 0), ms_entry(1, 0, 2, 0, 0), ms_entry(2, 1, 2, 3, 0),
+                                   ms_entry(1, 1, 2, 0, 0));
+constexpr uint64_t kMS3 = ms_pack4(ms_entry(1, 3, 1, 0, 0), ms_entry(1, 0, 1, 0, 0), ms_entry(1, 3, 0, 0, 0), 0);
+SBMT_HD uint32_t ms_case(int c) {
+  const uint64_t t = c < 8 ? (c < 4 ? kMS0 : kMS1) : (c < 12 ? kMS2 : kMS3);
+  return (uint32_t)(t >> (16 * (c & 3))) & 0xffffu;
+}
 
 // Packed per-owner counts.
 //  bit 0 self vertex emitted, 1-2 crossings on E0, 3-4 on E1, 5-6 on E2,
@@ -155,24 +155,34 @@ struct Frame {
   uint32_t s9;  // 3x3 samples, bit (3 r + c) = sample (Rlo + r, Clo + c)
 };
 
-SBMT_HD uint32_t sample3(const uint32_t* bits, int wpr, int rr, int cc) {
-  const uint32_t* row = bits + (int64_t)rr * wpr;
-  const int w = cc >> 5, b = cc & 31;
+// A window of the packed coarse raster: rows rr0.., bit columns cc0.. (cc0 a
+// multiple of 32) stored with `wpr` words per row.  The kernels stage the
+// window a tile needs in LDS; the whole raster is the window (0, 0).
+struct Bits {
+  const uint32_t* p;
+  int wpr, rr0, cc0;
+};
+
+SBMT_HD uint32_t sample3(const Bits& b, int rr, int cc) {
+  const uint32_t* row = b.p + (rr - b.rr0) * b.wpr;
+  const int c = cc - b.cc0;
+  const int w = c >> 5, s = c & 31;
   const uint64_t v = ((uint64_t)row[w + 1] << 32) | row[w];
-  return (uint32_t)(v >> b) & 7u;
+  return (uint32_t)(v >> s) & 7u;
 }
 
-SBMT_HD Frame owner_frame(const Geo& g, const uint32_t* bits, int k, int i, int Rlo) {
+SBMT_HD int clo_of(const Geo& g, int X) { return div4s(g, X - 2 * g.h - 2 * (g.s - 1)); }
+
+SBMT_HD Frame owner_frame(const Geo& g, const Bits& bits, int k, int i, int Rlo) {
   Frame f;
   f.k = k;
   f.i = i;
   f.o = k & 1;
   f.X = g.X0 + 4 * g.h * i + 2 * g.h * f.o;
   f.Rlo = Rlo;
-  f.Clo = div4s(g, f.X - 2 * g.h - 2 * (g.s - 1));
+  f.Clo = clo_of(g, f.X);
   const int rr = Rlo + kRing, cc = f.Clo + kRingC;
-  f.s9 = sample3(bits, g.wpr, rr, cc) | (sample3(bits, g.wpr, rr + 1, cc) << 3) |
-         (sample3(bits, g.wpr, rr + 2, cc) << 6);
+  f.s9 = sample3(bits, rr, cc) | (sample3(bits, rr + 1, cc) << 3) | (sample3(bits, rr + 2, cc) << 6);
   return f;
 }
 
@@ -208,14 +218,13 @@ struct Slow {
                    // midpoint at [16 + 8t, 20 + 8t) (15 = none)
 };
 
-SBMT_HD int mid_x(const Geo& g, const Frame& f, int m) {
-  const int xs = 4 * g.s * f.Clo + 2 * (g.s - 1);
-  return m < 6 ? xs + 4 * g.s * (m & 1) + 2 * g.s : xs + 4 * g.s * ((m - 6) % 3);
-}
-SBMT_HD int mid_y(const Geo& g, const Frame& f, int m) {
-  const int ys = 4 * g.s * f.Rlo + 2 * (g.s - 1);
-  return m < 6 ? ys + 4 * g.s * (m >> 1) : ys + 4 * g.s * ((m - 6) / 3) + 2 * g.s;
-}
+// Midpoint m sits at (xs + 2s XI(m), ys + 2s YI(m)) from the block's first sample.
+constexpr uint64_t kMidXI = 0x420420313131ull;  // nibble m: 1,3,1,3,1,3, 0,2,4, 0,2,4 (from m = 0)
+constexpr uint64_t kMidYI = 0x333111442200ull;  // nibble m: 0,0,2,2,4,4, 1,1,1, 3,3,3
+SBMT_HD int mid_xi(int m) { return (int)((kMidXI >> (4 * m)) & 15u); }
+SBMT_HD int mid_yi(int m) { return (int)((kMidYI >> (4 * m)) & 15u); }
+SBMT_HD int mid_x(const Geo& g, const Frame& f, int m) { return 4 * g.s * f.Clo + 2 * (g.s - 1) + 2 * g.s * mid_xi(m); }
+SBMT_HD int mid_y(const Geo& g, const Frame& f, int m) { return 4 * g.s * f.Rlo + 2 * (g.s - 1) + 2 * g.s * mid_yi(m); }
 SBMT_HD int slot_p(uint64_t seg, int a) { return (int)((seg >> (8 * a)) & 15); }
 SBMT_HD int slot_q(uint64_t seg, int a) { return (int)((seg >> (8 * a + 4)) & 15); }
 
@@ -234,6 +243,7 @@ SBMT_HD int popc8(uint32_t m) {
   m = (m & 0x33u) + ((m >> 2) & 0x33u);
   return (int)((m + (m >> 4)) & 0x0fu);
 }
+SBMT_HD int ctz32(uint32_t m) { return __builtin_ctz(m); }
 SBMT_HD int ctz8(uint32_t m) {
   int n = 0;
   if (!(m & 0x0fu)) { n += 4; m >>= 4; }
@@ -247,11 +257,13 @@ SBMT_HD int lut_key(int code);
 SBMT_HD int lut_nfg(int cls);
 SBMT_HD int lut_ntri(int cls);
 SBMT_HD uint32_t lut_tri(int cls, int j);
+SBMT_HD uint32_t lut_emit(int cls, int rot, int t, int j);
 
 // Raw key of triangle t from the crossing sets, looked up into class | rot << 6.
-// Returns 0 for an uncut triangle, -1 on a protocol violation.
+// Returns 0 for an uncut triangle, -1 on a protocol violation.  The candidate
+// token orders of all three key types are formed straight-line and selected.
 SBMT_HD int tri_key(int t, const uint32_t pos[5], uint64_t seg, uint64_t xm, uint64_t ord, int Imid) {
-  uint32_t list = 0;  // per crossing: slot | local edge << 3 | rank << 5 | entry << 7
+  uint32_t list = 0;  // per crossing (8 bits): slot | token << 3 | entry << 7
   int nc = 0;
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
@@ -260,98 +272,64 @@ SBMT_HD int tri_key(int t, const uint32_t pos[5], uint64_t seg, uint64_t xm, uin
     const int n = popc8(m);
 #pragma unroll
     for (int re = 0; re < 2; ++re) {
-      if (re < n) {
-        const int sl = (int)((ord >> (8 * eid + 4 * re)) & 15);
-        const int rt = dir > 0 ? re : n - 1 - re;
-        const int sp = (int)((pos[eid] >> slot_p(seg, sl)) & 1u);
-        const int entry = dir > 0 ? !sp : sp;
-        if (nc < 4) list |= (uint32_t)(sl | (j << 3) | (rt << 5) | (entry << 7)) << (8 * nc);
-        ++nc;
-      }
+      const int sl = (int)((ord >> (8 * eid + 4 * re)) & 15);
+      const int rt = dir > 0 ? re : n - 1 - re;
+      const int spos = (int)((pos[eid] >> slot_p(seg, sl)) & 1u);
+      const int entry = dir > 0 ? !spos : spos;
+      const uint32_t item = (uint32_t)(sl | ((2 * j + rt) << 3) | (entry << 7));
+      const bool take = re < n && nc < 4;
+      list |= take ? item << (8 * nc) : 0u;
+      nc += re < n ? 1 : 0;
     }
   }
   if (nc == 0 && Imid == 15) return 0;
-  if (nc > 4) return -1;
-  int type, t0 = 0, t1 = 0, t2 = 0, t3 = 0;
-#define SBMT_TOK(c) ((int)((((list >> (8 * (c))) >> 3) & 3) * 2 + (((list >> (8 * (c))) >> 5) & 1)))
-#define SBMT_SLOT(c) ((int)((list >> (8 * (c))) & 7))
-#define SBMT_ENT(c) ((int)(((list >> (8 * (c))) >> 7) & 1))
+  const uint32_t i0 = list & 255u, i1 = (list >> 8) & 255u, i2 = (list >> 16) & 255u, i3 = (list >> 24) & 255u;
+  const int s0 = i0 & 7, s1 = i1 & 7, s2 = i2 & 7, s3 = i3 & 7;
+  const int k0 = (i0 >> 3) & 7, k1 = (i1 >> 3) & 7, k2 = (i2 >> 3) & 7, k3 = (i3 >> 3) & 7;
+  const int e0 = (i0 >> 7) & 1, e1 = (i1 >> 7) & 1, e2 = (i2 >> 7) & 1, e3 = (i3 >> 7) & 1;
+  int type = 0, t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+  bool good = false;
   if (Imid != 15) {
-    if (nc != 2) return -1;
-    const int in0 = slot_q(seg, SBMT_SLOT(0)) == Imid, out0 = slot_p(seg, SBMT_SLOT(0)) == Imid;
-    const int in1 = slot_q(seg, SBMT_SLOT(1)) == Imid, out1 = slot_p(seg, SBMT_SLOT(1)) == Imid;
-    int ci, co;
-    if (in0 && out1) { ci = 0; co = 1; }
-    else if (in1 && out0) { ci = 1; co = 0; }
-    else return -1;
-    if (!SBMT_ENT(ci) || SBMT_ENT(co)) return -1;
+    // type 2: the crossing of the segment ending at I enters, the other leaves
+    const bool in0 = slot_q(seg, s0) == Imid, out1 = slot_p(seg, s1) == Imid;
+    const bool in1 = slot_q(seg, s1) == Imid, out0 = slot_p(seg, s0) == Imid;
+    const bool a = in0 && out1 && e0 && !e1, b = in1 && out0 && e1 && !e0;
+    good = nc == 2 && (a || b);
     type = 2;
-    t0 = ci == 0 ? SBMT_TOK(0) : SBMT_TOK(1);
-    t1 = co == 0 ? SBMT_TOK(0) : SBMT_TOK(1);
+    t0 = a ? k0 : k1;
+    t1 = a ? k1 : k0;
   } else if (nc == 2) {
-    if (SBMT_SLOT(0) != SBMT_SLOT(1) || SBMT_ENT(0) == SBMT_ENT(1)) return -1;
+    good = s0 == s1 && e0 != e1;
     type = 1;
-    t0 = SBMT_ENT(0) ? SBMT_TOK(0) : SBMT_TOK(1);
-    t1 = SBMT_ENT(0) ? SBMT_TOK(1) : SBMT_TOK(0);
+    t0 = e0 ? k0 : k1;
+    t1 = e0 ? k1 : k0;
   } else if (nc == 4) {
-    const int sa = SBMT_SLOT(0);
-    int sb = -1;
-#pragma unroll
-    for (int c = 1; c < 4; ++c)
-      if (SBMT_SLOT(c) != sa) sb = SBMT_SLOT(c);
-    if (sb < 0) return -1;
-    int s1, s2;
-    if (slot_q(seg, sa) == slot_p(seg, sb)) { s1 = sa; s2 = sb; }
-    else if (slot_q(seg, sb) == slot_p(seg, sa)) { s1 = sb; s2 = sa; }
-    else return -1;
-    int have = 0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int sl = SBMT_SLOT(c), en = SBMT_ENT(c), tk = SBMT_TOK(c);
-      const int q = (sl == s1 ? 0 : (sl == s2 ? 2 : 8)) + (en ? 0 : 1);
-      if (q > 3) return -1;
-      if (have & (1 << q)) return -1;
-      have |= 1 << q;
-      if (q == 0) t0 = tk;
-      else if (q == 1) t1 = tk;
-      else if (q == 2) t2 = tk;
-      else t3 = tk;
-    }
+    // two consecutive segments S1 -> S2; place each crossing by (segment, entry)
+    const int sa = s0, sb = s1 != s0 ? s1 : (s2 != s0 ? s2 : s3);
+    const bool ab = slot_q(seg, sa) == slot_p(seg, sb), ba = slot_q(seg, sb) == slot_p(seg, sa);
+    const int S1 = ab ? sa : sb;
+    const int q0 = (s0 == S1 ? 0 : 2) + (e0 ? 0 : 1), q1 = (s1 == S1 ? 0 : 2) + (e1 ? 0 : 1);
+    const int q2 = (s2 == S1 ? 0 : 2) + (e2 ? 0 : 1), q3 = (s3 == S1 ? 0 : 2) + (e3 ? 0 : 1);
+    const bool only2 = (s0 == sa || s0 == sb) && (s1 == sa || s1 == sb) && (s2 == sa || s2 == sb) &&
+                       (s3 == sa || s3 == sb) && sa != sb;
+    good = (ab || ba) && only2 && ((1 << q0) | (1 << q1) | (1 << q2) | (1 << q3)) == 15;
     type = 3;
-  } else {
-    return -1;
+    t0 = q0 == 0 ? k0 : (q1 == 0 ? k1 : (q2 == 0 ? k2 : k3));
+    t1 = q0 == 1 ? k0 : (q1 == 1 ? k1 : (q2 == 1 ? k2 : k3));
+    t2 = q0 == 2 ? k0 : (q1 == 2 ? k1 : (q2 == 2 ? k2 : k3));
+    t3 = q0 == 3 ? k0 : (q1 == 3 ? k1 : (q2 == 3 ? k2 : k3));
   }
-#undef SBMT_TOK
-#undef SBMT_SLOT
-#undef SBMT_ENT
+  if (!good) return -1;
   const int code = (type << 12) | (t0 << 9) | (t1 << 6) | (t2 << 3) | t3;
   const int kv = lut_key(code);
   return kv == 0 ? -1 : kv;
 }
 
-SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
-  const bool both = (g.flags & 1u) != 0;
-  const int h = g.h, X = f.X;
-  const int64_t hk = (int64_t)h * f.k;
+// Segments of the four dual cells of the block as slots (see Slow::seg).
+SBMT_HD void block_segments(const Frame& f, uint64_t& seg, uint32_t& valid) {
 #define SBMT_S(rr, cc) ((int)((f.s9 >> (3 * (rr) + (cc))) & 1u))
-  // signs of the 12 midpoints against the five edge lines (bit m = positive),
-  // in coordinates local to the owner vertex: ly = (My + 4) - 2hk sqrt3
-  const double yk = (double)(2 * hk) * kSqrt3;
-  uint32_t pos[5] = {0u, 0u, 0u, 0u, 0u};
-#pragma unroll
-  for (int m = 0; m < 12; ++m) {
-    const int Ay = mid_y(g, f, m) + 4;
-    const int lx = mid_x(g, f, m) - X;
-    const double ly = (double)Ay - yk;
-    pos[0] |= (uint32_t)(sgn_filtered(ly, Ay, -2 * hk) > 0) << m;
-    pos[4] |= (uint32_t)(sgn_filtered(ly - 2.0 * h * kSqrt3, Ay, -2 * (hk + h)) > 0) << m;
-    pos[2] |= (uint32_t)(sgn_filtered(ly - kSqrt3 * lx, Ay, -(lx + 2 * hk)) > 0) << m;
-    pos[1] |= (uint32_t)(sgn_filtered(ly + kSqrt3 * lx, Ay, lx - 2 * hk) < 0) << m;
-    pos[3] |= (uint32_t)(sgn_filtered(ly + kSqrt3 * (lx - 4 * h), Ay, lx - 4 * h - 2 * hk) < 0) << m;
-  }
-  // segments of the four dual cells
-  uint64_t seg = 0;
-  uint32_t valid = 0;
+  seg = 0;
+  valid = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int cr = q >> 1, cc = q & 1;
@@ -370,43 +348,159 @@ SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
       }
     }
   }
-  // signs of the four lattice vertices against each segment line: bit 4a + l;
-  // orient(P, Q, L) = ex (Ly - Py) - ey (Lx - Px), Ly = -4 + LB sqrt3
+#undef SBMT_S
+}
+
+// Slots whose bounding box meets the bounding box of Tb u Ta (conservative in
+// y); only they can cross an owned edge or hold a chain vertex of Tb, Ta.
+SBMT_HD uint32_t relevant_slots(const Geo& g, const Frame& f, uint64_t seg, uint32_t valid) {
+  const int xlo = f.X - 2 * g.h, xhi = f.X + 4 * g.h;
+  const double yk = -4.0 + (double)(2 * (int64_t)g.h * f.k) * kSqrt3;
+  const int ylo = (int)__builtin_floor(yk) - 1;
+  const int yhi = (int)__builtin_ceil(yk + 2.0 * g.h * kSqrt3) + 1;
+  uint32_t rel = 0;
+  for (uint32_t w = valid; w; w &= w - 1) {
+    const int a = ctz32(w);
+    const int pm = slot_p(seg, a), qm = slot_q(seg, a);
+    const int px = mid_x(g, f, pm), py = mid_y(g, f, pm), qx = mid_x(g, f, qm), qy = mid_y(g, f, qm);
+    const int sxl = px < qx ? px : qx, sxh = px < qx ? qx : px;
+    const int syl = py < qy ? py : qy, syh = py < qy ? qy : py;
+    if (sxh >= xlo && sxl <= xhi && syh >= ylo && syl <= yhi) rel |= 1u << a;
+  }
+  return rel;
+}
+
+// Inside bit of the owner vertex: its dual cell (0, cv) of the block is
+// uniform, or v lies left of every segment of that cell.
+SBMT_HD int owner_inside(const Geo& g, const Frame& f, uint64_t seg, uint32_t valid) {
+  const int X = f.X;
+  const int cv = div4s(g, X - 2 * (g.s - 1)) - f.Clo;
+  const int a = (int)((f.s9 >> cv) & 1u), b = (int)((f.s9 >> (cv + 1)) & 1u);
+  const int c = (int)((f.s9 >> (4 + cv)) & 1u), d = (int)((f.s9 >> (3 + cv)) & 1u);
+  if (a == b && b == c && c == d) return a;
+  const int64_t hk = (int64_t)g.h * f.k;
+  const double yb = (double)(2 * hk) * kSqrt3;
+  int fg = 1;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int sl = 2 * cv + j;
+    if ((valid >> sl) & 1u) {
+      const int pm = slot_p(seg, sl), qm = slot_q(seg, sl);
+      const int px = mid_x(g, f, pm), py = mid_y(g, f, pm);
+      const int ex = mid_x(g, f, qm) - px, ey = mid_y(g, f, qm) - py;
+      const double v = ex * ((double)(-4 - py) + yb) - (double)ey * (X - px);
+      if (sgn_filtered(v, (int64_t)ex * (-4 - py) - (int64_t)ey * (X - px), (int64_t)ex * 2 * hk) < 0) fg = 0;
+    }
+  }
+  return fg;
+}
+
+// Counts of an owner whose window is not uniform but which no segment can
+// reach (no relevant slot): like the fast path with the exact inside bit.
+SBMT_HD uint32_t quiet_info(const Geo& g, const Frame& f, int fg) {
+  Frame q = f;
+  q.s9 = fg ? 0x1ffu : 0u;
+  return fast_info(g, q);
+}
+
+// Sign of a + b*sqrt3 evaluated either exactly (EXACT) or from the double
+// value v; in the latter case `ok` is cleared when |v| is inside the band
+// where the double could be wrong.
+template <bool EXACT>
+SBMT_HD int sgn_eval(double v, int64_t a, int64_t b, bool& ok) {
+  if (EXACT) return z3sign(a, b);
+  ok = ok && (v > 1e-6 || v < -1e-6);
+  return v > 0 ? 1 : -1;
+}
+
+template <bool EXACT>
+SBMT_HD bool slot_signs(const Geo& g, const Frame& f, uint64_t seg, uint32_t rel, uint32_t& row0, uint32_t& row4,
+                        uint64_t& sp, uint64_t& sq, uint32_t& lv) {
+  bool ok = true;
+  const int h = g.h, X = f.X;
+  const int64_t hk = (int64_t)h * f.k;
+  const int ys = 4 * g.s * f.Rlo + 2 * (g.s - 1);
+  const double yk = (double)(2 * hk) * kSqrt3, yk1 = (double)(2 * (hk + h)) * kSqrt3;
+  row0 = 0;
+  row4 = 0;
+#pragma unroll
+  for (int yi = 0; yi < 5; ++yi) {
+    const int Ay = ys + 2 * g.s * yi + 4;
+    row0 |= (uint32_t)(sgn_eval<EXACT>((double)Ay - yk, Ay, -2 * hk, ok) > 0) << yi;
+    row4 |= (uint32_t)(sgn_eval<EXACT>((double)Ay - yk1, Ay, -2 * (hk + h), ok) > 0) << yi;
+  }
+  sp = 0;
+  sq = 0;
+  lv = 0;
   const int LX0 = X, LX1 = X + 4 * h, LX2 = X - 2 * h, LX3 = X + 2 * h;
   const int64_t LB01 = 2 * hk, LB23 = 2 * (hk + h);
   const double yb01 = (double)LB01 * kSqrt3, yb23 = (double)LB23 * kSqrt3;
-  uint32_t lv = 0;
+  for (uint32_t w = rel; w; w &= w - 1) {
+    const int a = ctz32(w);
+    const int pm = slot_p(seg, a), qm = slot_q(seg, a);
+    uint32_t e5[2];
 #pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    if ((valid >> a) & 1u) {
-      const int pm = slot_p(seg, a), qm = slot_q(seg, a);
-      const int px = mid_x(g, f, pm), py = mid_y(g, f, pm);
-      const int ex = mid_x(g, f, qm) - px, ey = mid_y(g, f, qm) - py;
-      const int64_t base = (int64_t)ex * (-4 - py);
-      const double d01 = (double)(-4 - py) + yb01, d23 = (double)(-4 - py) + yb23;
-      lv |= (uint32_t)(sgn_filtered(ex * d01 - (double)ey * (LX0 - px), base - (int64_t)ey * (LX0 - px), ex * LB01) > 0)
-            << (4 * a);
-      lv |= (uint32_t)(sgn_filtered(ex * d01 - (double)ey * (LX1 - px), base - (int64_t)ey * (LX1 - px), ex * LB01) > 0)
-            << (4 * a + 1);
-      lv |= (uint32_t)(sgn_filtered(ex * d23 - (double)ey * (LX2 - px), base - (int64_t)ey * (LX2 - px), ex * LB23) > 0)
-            << (4 * a + 2);
-      lv |= (uint32_t)(sgn_filtered(ex * d23 - (double)ey * (LX3 - px), base - (int64_t)ey * (LX3 - px), ex * LB23) > 0)
-            << (4 * a + 3);
+    for (int z = 0; z < 2; ++z) {
+      const int m = z == 0 ? pm : qm;
+      const int Ay = mid_y(g, f, m) + 4, lx = mid_x(g, f, m) - X, yi = mid_yi(m);
+      const double ly = (double)Ay - yk;
+      uint32_t b5 = ((row0 >> yi) & 1u) | (((row4 >> yi) & 1u) << 4);
+      b5 |= (uint32_t)(sgn_eval<EXACT>(ly + kSqrt3 * lx, Ay, lx - 2 * hk, ok) < 0) << 1;
+      b5 |= (uint32_t)(sgn_eval<EXACT>(ly - kSqrt3 * lx, Ay, -(lx + 2 * hk), ok) > 0) << 2;
+      b5 |= (uint32_t)(sgn_eval<EXACT>(ly + kSqrt3 * (lx - 4 * h), Ay, lx - 4 * h - 2 * hk, ok) < 0) << 3;
+      e5[z] = b5;
     }
+    sp |= (uint64_t)e5[0] << (8 * a);
+    sq |= (uint64_t)e5[1] << (8 * a);
+    // orient(P, Q, L) = ex (Ly - Py) - ey (Lx - Px), Ly = -4 + LB sqrt3
+    const int px = mid_x(g, f, pm), py = mid_y(g, f, pm);
+    const int ex = mid_x(g, f, qm) - px, ey = mid_y(g, f, qm) - py;
+    const int64_t base = (int64_t)ex * (-4 - py);
+    const double d01 = (double)(-4 - py) + yb01, d23 = (double)(-4 - py) + yb23;
+    uint32_t l4 = (uint32_t)(sgn_eval<EXACT>(ex * d01 - (double)ey * (LX0 - px), base - (int64_t)ey * (LX0 - px),
+                                             ex * LB01, ok) > 0);
+    l4 |= (uint32_t)(sgn_eval<EXACT>(ex * d01 - (double)ey * (LX1 - px), base - (int64_t)ey * (LX1 - px), ex * LB01,
+                                     ok) > 0) << 1;
+    l4 |= (uint32_t)(sgn_eval<EXACT>(ex * d23 - (double)ey * (LX2 - px), base - (int64_t)ey * (LX2 - px), ex * LB23,
+                                     ok) > 0) << 2;
+    l4 |= (uint32_t)(sgn_eval<EXACT>(ex * d23 - (double)ey * (LX3 - px), base - (int64_t)ey * (LX3 - px), ex * LB23,
+                                     ok) > 0) << 3;
+    lv |= l4 << (4 * a);
   }
-  // crossing sets: both segment ends on different sides of the edge line and
-  // both edge ends on different sides of the segment line
+  return ok;
+}
+
+SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
+  const bool both = (g.flags & 1u) != 0;
+  const int h = g.h, X = f.X;
+  const int64_t hk = (int64_t)h * f.k;
+  uint64_t seg;
+  uint32_t valid;
+  block_segments(f, seg, valid);
+  const uint32_t rel = relevant_slots(g, f, seg, valid);
+  // signs of the five possible point rows against the horizontal edge lines
+  // E0 (row k) and E4 (row k+1): bit yi.  Then, per relevant slot, the signs of
+  // both ends against E0..E4 (5 bits each) and of the lattice vertices
+  // v, vr, vdl, vdr against the segment line (4 bits).  All in double
+  // precision first; if any value falls in the uncertainty band the same
+  // quantities are recomputed exactly.
+  uint32_t row0, row4;
+  uint64_t sp, sq;
+  uint32_t lv;
+  if (!slot_signs<false>(g, f, seg, rel, row0, row4, sp, sq, lv))
+    slot_signs<true>(g, f, seg, rel, row0, row4, sp, sq, lv);
+  // crossing sets: the segment ends on different sides of the edge line and the
+  // edge ends on different sides of the segment line
   uint64_t xm = 0;
-#pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    if ((valid >> a) & 1u) {
-      const int pm = slot_p(seg, a), qm = slot_q(seg, a);
+  for (uint32_t w = rel; w; w &= w - 1) {
+    const int a = ctz32(w);
+    {
+      const uint32_t d = ((uint32_t)(sp >> (8 * a)) ^ (uint32_t)(sq >> (8 * a))) & 31u;
       const uint32_t l4 = (lv >> (4 * a)) & 15u;
 #pragma unroll
       for (int e = 0; e < 5; ++e) {
-        const uint32_t sp = (pos[e] >> pm) & 1u, sq = (pos[e] >> qm) & 1u;
         const uint32_t lu = (l4 >> edge_u(e)) & 1u, lw = (l4 >> edge_v(e)) & 1u;
-        if (sp != sq && lu != lw) xm |= 1ull << (8 * e + a);
+        if (((d >> e) & 1u) && lu != lw) xm |= 1ull << (8 * e + a);
       }
     }
   }
@@ -430,10 +524,10 @@ SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
         else if (slot_q(seg, b) == slot_p(seg, a)) { s1 = b; s2 = a; }
         else err = true;
         const int M = slot_q(seg, s1), P0 = slot_p(seg, s1), P2 = slot_q(seg, s2);
-        const int64_t mx = mid_x(g, f, M), my = mid_y(g, f, M);
-        const int64_t cr = (mid_x(g, f, P0) - mx) * (mid_y(g, f, P2) - my) -
-                           (mid_y(g, f, P0) - my) * (mid_x(g, f, P2) - mx);
-        const bool mpos = (pos[e] >> M) & 1u;
+        const int mx = mid_x(g, f, M), my = mid_y(g, f, M);
+        const int64_t cr = (int64_t)(mid_x(g, f, P0) - mx) * (mid_y(g, f, P2) - my) -
+                           (int64_t)(mid_y(g, f, P0) - my) * (mid_x(g, f, P2) - mx);
+        const bool mpos = (sq >> (8 * s1 + e)) & 1u;
         const bool later = (cr > 0) == mpos;
         first = later ? s1 : s2;
         second = later ? s2 : s1;
@@ -441,41 +535,29 @@ SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
       ord |= (uint64_t)(first | (second << 4)) << (8 * e);
     }
   }
-  // chain vertices: the midpoints between the centre sample and its neighbours
+  // chain vertices: the end point of a relevant segment inside Tb or Ta
   int Ib = 15, Ia = 15;
-  {
-    const int c0 = SBMT_S(1, 1);
-    const int cand[4] = {2, 3, 7, 10};
-    const int ex[4] = {SBMT_S(1, 0) != c0, SBMT_S(1, 2) != c0, SBMT_S(0, 1) != c0, SBMT_S(2, 1) != c0};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (ex[q]) {
-        const int m = cand[q];
-        const bool inb = ((pos[2] >> m) & 1u) && !((pos[4] >> m) & 1u) && !((pos[1] >> m) & 1u);
-        const bool ina = ((pos[0] >> m) & 1u) && ((pos[3] >> m) & 1u) && !((pos[2] >> m) & 1u);
-        if (inb) { if (Ib != 15) err = true; Ib = m; }
-        if (ina) { if (Ia != 15) err = true; Ia = m; }
-      }
+  for (uint32_t w = rel; w; w &= w - 1) {
+    const int a = ctz32(w);
+    {
+      const uint32_t e5 = (uint32_t)(sq >> (8 * a)) & 31u;
+      const bool inb = ((e5 >> 2) & 1u) && !((e5 >> 4) & 1u) && !((e5 >> 1) & 1u);
+      const bool ina = (e5 & 1u) && ((e5 >> 3) & 1u) && !((e5 >> 2) & 1u);
+      if (inb) { if (Ib != 15) err = true; Ib = slot_q(seg, a); }
+      if (ina) { if (Ia != 15) err = true; Ia = slot_q(seg, a); }
     }
   }
-  // inside bit of the owner vertex: its dual cell (0, cv) of the block
-  int fg;
-  {
-    const int cv = div4s(g, X - 2 * (g.s - 1)) - f.Clo;
-    const int a = SBMT_S(0, cv), b = SBMT_S(0, cv + 1), c = SBMT_S(1, cv + 1), d = SBMT_S(1, cv);
-    if (a == b && b == c && c == d) {
-      fg = a;
-    } else {
-      fg = 1;
+  const int fg = owner_inside(g, f, seg, valid);
+  // pos masks per edge over midpoints, for the keys (entry tests use the start point)
+  uint32_t pos[5] = {0u, 0u, 0u, 0u, 0u};
+  for (uint32_t w = rel; w; w &= w - 1) {
+    const int a = ctz32(w);
+    {
+      const int pm = slot_p(seg, a);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int sl = 2 * cv + j;
-        if (((valid >> sl) & 1u) && !((lv >> (4 * sl)) & 1u)) fg = 0;
-      }
+      for (int e = 0; e < 5; ++e) pos[e] |= (uint32_t)((sp >> (8 * a + e)) & 1u) << pm;
     }
   }
-#undef SBMT_S
-  // keys of the two triangles
   const int kb = tri_key(0, pos, seg, xm, ord, Ib);
   const int ka = tri_key(1, pos, seg, xm, ord, Ia);
   if (kb < 0 || ka < 0) err = true;
@@ -499,6 +581,51 @@ SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
   r.tri = (uint32_t)(clsb | (rotb << 5) | ((clsa | (rota << 5)) << 8) | (Ib << 16) | (Ia << 20));
 }
 
+// Classify an owner whose window is not uniform: quiet (no segment can reach
+// it: the fast counts with the exact inside bit) or slow.  Returns true if
+// the full slow classification is needed.
+SBMT_HD bool needs_slow(const Geo& g, const Frame& f, uint32_t& info) {
+  uint64_t seg;
+  uint32_t valid;
+  block_segments(f, seg, valid);
+  if (relevant_slots(g, f, seg, valid)) return true;
+  info = quiet_info(g, f, owner_inside(g, f, seg, valid));
+  return false;
+}
+
+// Compact classification of a slow owner (16 bytes), what emission needs:
+//   info  packed counts
+//   tri   class [0,5) rot [5,7) of Tb, class [8,13) rot [13,15) of Ta,
+//         chain vertex midpoint of Tb [16,20) and Ta [20,24) (15 = none),
+//         crossing counts of E3 [24,26) and E4 [26,28)
+//   x     crossings on E0, E1, E2 in order from the owner, 8 bits each
+//         (start midpoint | end midpoint << 4), E0 at bits [0,16), E1 [16,32),
+//         E2 [32,48)
+struct SlowRec {
+  uint32_t info, tri;
+  uint64_t x;
+};
+
+SBMT_HD SlowRec pack_slow(const Slow& r) {
+  SlowRec o;
+  o.info = r.info;
+  const uint32_t n3 = (uint32_t)popc8((uint32_t)(r.xm >> 24) & 255u), n4 = (uint32_t)popc8((uint32_t)(r.xm >> 32) & 255u);
+  o.tri = (r.tri & 0x00ffffffu) | (n3 << 24) | (n4 << 26);
+  uint64_t x = 0;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int n = popc8((uint32_t)(r.xm >> (8 * e)) & 255u);
+#pragma unroll
+    for (int re = 0; re < 2; ++re) {
+      const int sl = (int)((r.ord >> (8 * e + 4 * re)) & 15);
+      const uint64_t pq = (uint64_t)(slot_p(r.seg, sl) | (slot_q(r.seg, sl) << 4));
+      if (re < n) x |= pq << (16 * e + 8 * re);
+    }
+  }
+  o.x = x;
+  return o;
+}
+
 // ---------------------------------------------------------------------------
 // Emission (Alg. 2, steps 2-4): vertices and sub-triangles of one owner with
 // global ids taken from the owner offsets.
@@ -506,6 +633,15 @@ SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
 constexpr double kHalfSqrt3 = 0.86602540378443864676;
 SBMT_HD double lat_x(int X) { return 0.25 * (double)X; }
 SBMT_HD double lat_y(int h, int k) { return -1.0 + (double)(h * k) * kHalfSqrt3; }
+
+// Where emission writes: vertex p goes to v[p - vbase], triangle t to
+// t[t - tbase] / c[t - tbase] (the kernels stage a row of output in LDS).
+struct Out {
+  double* v;
+  int32_t* t;
+  uint8_t* c;
+  int64_t vbase, tbase;
+};
 
 struct Nb {  // ids one owner needs
   int vid;            // first vertex id of the owner
@@ -515,151 +651,103 @@ struct Nb {  // ids one owner needs
 };
 
 SBMT_HD void put_vertex(double* verts, int64_t p, double x, double y) {
+#ifdef SBMT_HOST_EMUL
   verts[2 * p] = x;
   verts[2 * p + 1] = y;
+#else
+  double2 v;
+  v.x = x;
+  v.y = y;
+  *reinterpret_cast<double2*>(verts + 2 * p) = v;  // verts is 16-byte aligned
+#endif
 }
 
-// Sub-triangle key for sorting: (a, b, c) rotated to start at the smallest id.
-struct TriK {
-  int a, b, c, code;
-};
-SBMT_HD TriK trik(int x, int y, int z, int code) {
-  TriK t;
-  if (y < x && y < z) { t.a = y; t.b = z; t.c = x; }
-  else if (z < x && z < y) { t.a = z; t.b = x; t.c = y; }
-  else { t.a = x; t.b = y; t.c = z; }
-  t.code = code;
-  return t;
-}
-SBMT_HD bool trik_less(const TriK& p, const TriK& q) {
-  return p.a != q.a ? p.a < q.a : (p.b != q.b ? p.b < q.b : p.c < q.c);
-}
-SBMT_HD void trik_cx(TriK& p, TriK& q) {
-  if (trik_less(q, p)) { TriK t = p; p = q; q = t; }
+// Id of structural slot `sl` (see the emission table): a four-level select.
+SBMT_HD int slot_id(const int (&ids)[16], int sl) {
+  const int b0 = sl & 1, b1 = sl & 2, b2 = sl & 4, b3 = sl & 8;
+  const int x0 = b0 ? ids[1] : ids[0], x1 = b0 ? ids[3] : ids[2], x2 = b0 ? ids[5] : ids[4], x3 = b0 ? ids[7] : ids[6];
+  const int x4 = b0 ? ids[9] : ids[8], x5 = b0 ? ids[11] : ids[10], x6 = b0 ? ids[13] : ids[12],
+            x7 = b0 ? ids[15] : ids[14];
+  const int y0 = b1 ? x1 : x0, y1 = b1 ? x3 : x2, y2 = b1 ? x5 : x4, y3 = b1 ? x7 : x6;
+  const int z0 = b2 ? y1 : y0, z1 = b2 ? y3 : y2;
+  return b3 ? z1 : z0;
 }
 
-// Emit the sub-triangles of cut triangle t (sorted within the parent).
-SBMT_HD void emit_cut(const Geo& g, const Slow& r, int t, const Nb& nb, int64_t& tp, int32_t* __restrict__ tris,
-                      uint8_t* __restrict__ codes) {
+// Emit the sub-triangles of cut triangle t in output order (Alg. 2, steps
+// 3-4): the table already holds them rotated and sorted by id.
+SBMT_HD void emit_cut(const Geo& g, const SlowRec& r, int t, const Nb& nb, int64_t& tp, const Out& out) {
   const bool both = (g.flags & 1u) != 0;
   const int cls = (int)((r.tri >> (8 * t)) & 31u), rot = (int)((r.tri >> (8 * t + 5)) & 3u);
-  const int c1 = t == 0 ? nb.id_vdr : nb.id_vr, c2 = t == 0 ? nb.id_vdl : nb.id_vdr;
-  const int idI = nb.bI + (t == 1 ? (int)(((r.tri >> 16) & 15u) != 15u) : 0);
+  const int hasIb = ((r.tri >> 16) & 15u) != 15u;
+  const int ids[16] = {nb.vid, nb.b0, nb.b0 + 1, nb.b1, nb.b1 + 1, nb.b2, nb.b2 + 1, nb.bI, nb.bI + hasIb,
+                       nb.id_vr, nb.b3, nb.b3 + 1, nb.id_vdl, nb.b4, nb.b4 + 1, nb.id_vdr};
   const int nt = lut_ntri(cls);
-  const int bigc = 0x7fffffff;
-  TriK q0 = {bigc, bigc, bigc, 0}, q1 = q0, q2 = q0, q3 = q0, q4 = q0;
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
-    if (j < nt) {
-      const uint32_t w = lut_tri(cls, j);
-      const int side = (int)((w >> 12) & 1u);
-      if (both || side) {
-        int id3[3];
-#pragma unroll
-        for (int z = 0; z < 3; ++z) {
-          const int lab = (int)((w >> (4 * z)) & 15u);
-          int id;
-          if (lab < 3) {
-            const int li = (lab - rot + 3) % 3;
-            id = li == 0 ? nb.vid : (li == 1 ? c1 : c2);
-          } else if (lab < 9) {
-            const int x = lab - 3, rr = x & 1;
-            const int le = ((x >> 1) - rot + 3) % 3;
-            // local edge le of triangle t: (edge id, direction)
-            const int eid = t == 0 ? (le == 0 ? 2 : (le == 1 ? 4 : 1)) : (le == 0 ? 0 : (le == 1 ? 3 : 2));
-            const int dir = t == 0 ? (le == 0 ? 1 : -1) : (le == 2 ? -1 : 1);
-            const int n = popc8((uint32_t)(r.xm >> (8 * eid)) & 255u);
-            const int base = eid == 0 ? nb.b0 : (eid == 1 ? nb.b1 : (eid == 2 ? nb.b2 : (eid == 3 ? nb.b3 : nb.b4)));
-            id = base + (dir > 0 ? rr : n - 1 - rr);
-          } else {
-            id = idI;
-          }
-          id3[z] = id;
-        }
-        const TriK k = trik(id3[0], id3[1], id3[2], cls | (side ? 0 : 0x80));
-        if (j == 0) q0 = k; else if (j == 1) q1 = k; else if (j == 2) q2 = k; else if (j == 3) q3 = k; else q4 = k;
-      }
-    }
-  }
-  // sorting network for five keys (unused slots sort last)
-  trik_cx(q0, q1); trik_cx(q3, q4); trik_cx(q2, q4); trik_cx(q2, q3); trik_cx(q0, q3);
-  trik_cx(q0, q2); trik_cx(q1, q4); trik_cx(q1, q3); trik_cx(q1, q2);
-#pragma unroll
-  for (int j = 0; j < 5; ++j) {
-    const TriK& k = j == 0 ? q0 : (j == 1 ? q1 : (j == 2 ? q2 : (j == 3 ? q3 : q4)));
-    if (k.a != bigc) {
-      tris[3 * tp + 0] = k.a;
-      tris[3 * tp + 1] = k.b;
-      tris[3 * tp + 2] = k.c;
-      codes[tp] = (uint8_t)k.code;
+    const uint32_t w = lut_emit(cls, rot, t, j);
+    const int side = (int)((w >> 12) & 1u);
+    if (j < nt && (both || side)) {
+      const int64_t u = tp - out.tbase;
+      out.t[3 * u + 0] = slot_id(ids, (int)(w & 15u));
+      out.t[3 * u + 1] = slot_id(ids, (int)((w >> 4) & 15u));
+      out.t[3 * u + 2] = slot_id(ids, (int)((w >> 8) & 15u));
+      out.c[u] = (uint8_t)(cls | (side ? 0 : 0x80));
       ++tp;
     }
   }
 }
 
-// Emit one owner.  For a slow owner `r` holds its classification.
-SBMT_HD void emit_owner(const Geo& g, const Frame& f, uint32_t info, const Slow* r, const Nb& nb, int64_t to,
-                        double* __restrict__ verts, int32_t* __restrict__ tris, uint8_t* __restrict__ codes) {
+// Emit one slow owner from its record.
+SBMT_HD void emit_slow(const Geo& g, const Frame& f, const SlowRec& r, const Nb& nb, int64_t to, const Out& out) {
   const bool both = (g.flags & 1u) != 0;
+  const uint32_t info = r.info;
   const int fg = info_fg(info);
-  const int self = info_self(info);
   const double ux = lat_x(f.X), uy = lat_y(g.h, f.k);
   int64_t p = nb.vid;
-  if (self) put_vertex(verts, p++, ux, uy);
-  int64_t tp = to;
-  const uint8_t ucode = both && !fg ? 0x80 : 0;
-  if (!info_slow(info)) {
-    if (info_ntb(info)) {
-      tris[3 * tp + 0] = nb.vid; tris[3 * tp + 1] = nb.id_vdr; tris[3 * tp + 2] = nb.id_vdl;
-      codes[tp] = ucode;
-      ++tp;
-    }
-    if (info_nta(info)) {
-      tris[3 * tp + 0] = nb.vid; tris[3 * tp + 1] = nb.id_vr; tris[3 * tp + 2] = nb.id_vdr;
-      codes[tp] = ucode;
-    }
-    return;
-  }
+  if (info_self(info)) put_vertex(out.v, p++ - out.vbase, ux, uy);
   // crossings on E0, E1, E2 in order from the owner: X = P + t (Q - P),
   // t = dP / (dP - dQ), dP = (V-U) x (P-U), dQ = (V-U) x (Q-U)
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
-    const int n = popc8((uint32_t)(r->xm >> (8 * e)) & 255u);
+    const int n = info_n(info, e);
     const int vX = e == 0 ? f.X + 4 * g.h : (e == 1 ? f.X - 2 * g.h : f.X + 2 * g.h);
     const double vx = lat_x(vX), vy = lat_y(g.h, e == 0 ? f.k : f.k + 1);
     const double gx = vx - ux, gy = vy - uy;
 #pragma unroll
     for (int re = 0; re < 2; ++re) {
       if (re < n) {
-        const int sl = (int)((r->ord >> (8 * e + 4 * re)) & 15);
-        const int pm = slot_p(r->seg, sl), qm = slot_q(r->seg, sl);
+        const uint32_t pq = (uint32_t)(r.x >> (16 * e + 8 * re)) & 255u;
+        const int pm = (int)(pq & 15u), qm = (int)(pq >> 4);
         const double px = 0.25 * (double)mid_x(g, f, pm), py = 0.25 * (double)mid_y(g, f, pm);
         const double qx = 0.25 * (double)mid_x(g, f, qm), qy = 0.25 * (double)mid_y(g, f, qm);
         const double dp = gx * (py - uy) - gy * (px - ux);
         const double dq = gx * (qy - uy) - gy * (qx - ux);
         const double tt = dp / (dp - dq);
-        put_vertex(verts, p++, px + tt * (qx - px), py + tt * (qy - py));
+        put_vertex(out.v, p++ - out.vbase, px + tt * (qx - px), py + tt * (qy - py));
       }
     }
   }
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    const int m = (int)((r->tri >> (16 + 4 * t)) & 15u);
-    if (m != 15) put_vertex(verts, p++, 0.25 * (double)mid_x(g, f, m), 0.25 * (double)mid_y(g, f, m));
+    const int m = (int)((r.tri >> (16 + 4 * t)) & 15u);
+    if (m != 15) put_vertex(out.v, p++ - out.vbase, 0.25 * (double)mid_x(g, f, m), 0.25 * (double)mid_y(g, f, m));
   }
+  int64_t tp = to;
+  const uint8_t ucode = both && !fg ? 0x80 : 0;
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    const int cls = (int)((r->tri >> (8 * t)) & 31u);
+    const int cls = (int)((r.tri >> (8 * t)) & 31u);
     if (cls == 0) {
       if ((t == 0 ? info_ntb(info) : info_nta(info)) != 0) {
-        tris[3 * tp + 0] = nb.vid;
-        tris[3 * tp + 1] = t == 0 ? nb.id_vdr : nb.id_vr;
-        tris[3 * tp + 2] = t == 0 ? nb.id_vdl : nb.id_vdr;
-        codes[tp] = ucode;
+        const int64_t u = tp - out.tbase;
+        out.t[3 * u + 0] = nb.vid;
+        out.t[3 * u + 1] = t == 0 ? nb.id_vdr : nb.id_vr;
+        out.t[3 * u + 2] = t == 0 ? nb.id_vdl : nb.id_vdr;
+        out.c[u] = ucode;
         ++tp;
       }
     } else {
-      emit_cut(g, *r, t, nb, tp, tris, codes);
+      emit_cut(g, r, t, nb, tp, out);
     }
   }
 }

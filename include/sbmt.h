@@ -37,6 +37,9 @@
  *    The library never allocates device memory on these paths; the handle only
  *    owns a small pinned host buffer used to return sizes.
  *  - Calls on one handle must not overlap (the pinned buffer is shared).
+ *  - The workspace holds the coarse raster, one info word per lattice vertex
+ *    whose sample window is not uniform, and 16-byte records of the owners
+ *    classified exactly (by default room for a quarter of the owners).
  *
  * Errors
  *  - Every call returns an sbmt_status.  Arguments are validated before any
@@ -123,6 +126,73 @@ sbmt_status sbmt_run(sbmt_handle h, const sbmt_image* img, void* workspace, size
 sbmt_status sbmt_mesh_async(sbmt_handle h, const sbmt_image* img, void* workspace, size_t ws_bytes,
                             double* verts, int64_t vert_cap, int32_t* tris, uint8_t* codes,
                             int64_t tri_cap, int64_t* sizes_dev, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many images of different sizes and grid_h meshed by one set of
+ * launches (or one persistent launch), e.g. inside a captured hipGraph.
+ *
+ * Life cycle:
+ *   sbmt_batch_create  host only: validate the images, lay out the workspace
+ *   sbmt_batch_bind    upload the image table (bitmaps, workspace regions and,
+ *                      optionally, output views) into the workspace; waits for
+ *                      the copy, so it is not capturable
+ *   sbmt_batch_plan    classify and count every image; waits; per-image sizes
+ *   sbmt_batch_emit    write the planned meshes (asynchronous, capturable)
+ *   sbmt_batch_mesh    the whole path without a host round trip (asynchronous,
+ *                      capturable): an image is written only if it fits its
+ *                      output capacities, sizes and statuses go to the
+ *                      workspace (read with sbmt_batch_sizes) and to
+ *                      sizes_dev if given
+ *   sbmt_batch_tune    autotuner: times every candidate tuning on this batch
+ *                      and keeps the fastest
+ * A batch object and its workspace serve one call at a time; the image
+ * bitmaps and outputs must stay valid while calls that use them run.
+ * ------------------------------------------------------------------------- */
+typedef struct sbmt_batch_s* sbmt_batch;
+
+/* Output view of one image: device arrays with capacities in rows. */
+typedef struct {
+  double* verts;     /* [vert_cap][2] */
+  int32_t* tris;     /* [tri_cap][3] */
+  uint8_t* codes;    /* [tri_cap] */
+  int64_t vert_cap;
+  int64_t tri_cap;
+} sbmt_outputs;
+
+#define SBMT_STRATEGY_MULTI 0 /* coarsen, count, slow-owner, scan and emit kernels */
+#define SBMT_STRATEGY_FUSED 1 /* coarsen, then one persistent classify-scan-emit kernel */
+
+typedef struct {
+  int32_t strategy;      /* SBMT_STRATEGY_* */
+  int32_t tile_rows;     /* grid rows per tile or band: 4, 8 or 16 (16: multi only) */
+  int32_t groups_per_cu; /* fused: resident workgroups per compute unit (0 = default) */
+  int32_t reserved;
+  int64_t record_cap;    /* slow-owner records in the workspace: 0 = default
+                            (a quarter of the owners), > 0 = that many; owners
+                            beyond it are classified where they are needed */
+} sbmt_tuning;
+
+/* Host only.  tuning may be NULL (multi-kernel, 8-row tiles).  The fused
+ * strategy needs per-image widths up to 12288 * grid_h pixels and at most
+ * 2^31 / 10 lattice vertices per image; otherwise the batch uses the
+ * multi-kernel strategy.  *ws_bytes receives the workspace size. */
+sbmt_status sbmt_batch_create(sbmt_handle h, const sbmt_image* imgs, int32_t n, const sbmt_tuning* tuning,
+                              size_t* ws_bytes, sbmt_batch* out);
+sbmt_status sbmt_batch_destroy(sbmt_batch b);
+/* outs: n output views, or NULL to bind none yet (plan only). */
+sbmt_status sbmt_batch_bind(sbmt_batch b, void* workspace, size_t ws_bytes, const sbmt_outputs* outs, void* stream);
+/* out: n host sizes.  Returns SBMT_E_PROTOCOL / SBMT_E_INDEX_OVERFLOW if an
+ * image has that status (its sizes are still reported). */
+sbmt_status sbmt_batch_plan(sbmt_batch b, sbmt_sizes* out, void* stream);
+/* sizes_dev: device int64 [n][4] (n_vertices, n_triangles, n_cut, status) or NULL. */
+sbmt_status sbmt_batch_emit(sbmt_batch b, int64_t* sizes_dev, void* stream);
+sbmt_status sbmt_batch_mesh(sbmt_batch b, int64_t* sizes_dev, void* stream);
+/* Host copy of the last call's per-image sizes and statuses (waits). */
+sbmt_status sbmt_batch_sizes(sbmt_batch b, sbmt_sizes* out, int64_t* status, void* stream);
+sbmt_status sbmt_batch_get_tuning(sbmt_batch b, sbmt_tuning* out);
+sbmt_status sbmt_batch_set_tuning(sbmt_batch b, const sbmt_tuning* t);
+/* reps timed runs per candidate; best / best_ms may be NULL. */
+sbmt_status sbmt_batch_tune(sbmt_batch b, int32_t reps, sbmt_tuning* best, float* best_ms, void* stream);
 
 /* Number of canonical classes and the key code of class id c (1-based). */
 int32_t sbmt_num_classes(void);

@@ -40,8 +40,28 @@ class Layout(ctypes.Structure):
                 ("grid_rows", ctypes.c_int32), ("grid_cols", ctypes.c_int32), ("workspace_bytes", ctypes.c_size_t)]
 
 
+class Outputs(ctypes.Structure):
+    _fields_ = [("verts", ctypes.c_void_p), ("tris", ctypes.c_void_p), ("codes", ctypes.c_void_p),
+                ("vert_cap", ctypes.c_int64), ("tri_cap", ctypes.c_int64)]
+
+
+STRATEGY_MULTI = 0
+STRATEGY_FUSED = 1
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("strategy", ctypes.c_int32), ("tile_rows", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("record_cap", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {"strategy": "fused" if self.strategy == STRATEGY_FUSED else "multi", "tile_rows": self.tile_rows,
+                "groups_per_cu": self.groups_per_cu, "record_cap": self.record_cap}
+
+
 EXPORTS = ("sbmt_create", "sbmt_destroy", "sbmt_query", "sbmt_plan", "sbmt_run", "sbmt_mesh_async",
-           "sbmt_plan_batch", "sbmt_run_batch", "sbmt_num_classes", "sbmt_class_code", "sbmt_status_string")
+           "sbmt_batch_create", "sbmt_batch_destroy", "sbmt_batch_bind", "sbmt_batch_plan", "sbmt_batch_emit",
+           "sbmt_batch_mesh", "sbmt_batch_sizes", "sbmt_batch_get_tuning", "sbmt_batch_set_tuning",
+           "sbmt_batch_tune", "sbmt_num_classes", "sbmt_class_code", "sbmt_status_string")
 
 _lib = None
 
@@ -74,9 +94,27 @@ def lib():
     L.sbmt_class_code.argtypes = [i32]
     L.sbmt_status_string.restype = ctypes.c_char_p
     L.sbmt_status_string.argtypes = [i32]
-    if hasattr(L, "sbmt_plan_batch"):
-        L.sbmt_plan_batch.restype = i32
-        L.sbmt_run_batch.restype = i32
+    P = ctypes.POINTER
+    L.sbmt_batch_create.restype = i32
+    L.sbmt_batch_create.argtypes = [vp, P(Image), i32, P(Tuning), P(sz), P(vp)]
+    L.sbmt_batch_destroy.restype = i32
+    L.sbmt_batch_destroy.argtypes = [vp]
+    L.sbmt_batch_bind.restype = i32
+    L.sbmt_batch_bind.argtypes = [vp, vp, sz, P(Outputs), vp]
+    L.sbmt_batch_plan.restype = i32
+    L.sbmt_batch_plan.argtypes = [vp, P(Sizes), vp]
+    L.sbmt_batch_emit.restype = i32
+    L.sbmt_batch_emit.argtypes = [vp, vp, vp]
+    L.sbmt_batch_mesh.restype = i32
+    L.sbmt_batch_mesh.argtypes = [vp, vp, vp]
+    L.sbmt_batch_sizes.restype = i32
+    L.sbmt_batch_sizes.argtypes = [vp, P(Sizes), P(i64), vp]
+    L.sbmt_batch_get_tuning.restype = i32
+    L.sbmt_batch_get_tuning.argtypes = [vp, P(Tuning)]
+    L.sbmt_batch_set_tuning.restype = i32
+    L.sbmt_batch_set_tuning.argtypes = [vp, P(Tuning)]
+    L.sbmt_batch_tune.restype = i32
+    L.sbmt_batch_tune.argtypes = [vp, i32, P(Tuning), P(ctypes.c_float), vp]
     _lib = L
     return L
 

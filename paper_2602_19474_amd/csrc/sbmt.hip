@@ -2,23 +2,39 @@
 // classification -> canonical class -> template lookup -> closed mesh
 // (arXiv 2602.19474, Sec. 3.3, Alg. 1, Alg. 2, App. G).
 //
+// Every kernel serves one image or a batch of images: a kernel's blocks are
+// numbered across the images of the call and mapped back to (image, local
+// block) through a prefix table of per-image block counts.
+//
 // Kernels
 //   k_coarsen  block-majority coarse raster as packed bits, with a background ring
-//   k_count    per row segment (row k, CB owners): classify every owner, sum
-//              vertex/triangle counts (plan)
+//   k_count    per tile (RB rows x kCB owners): owners whose 3x3 sample window
+//              is uniform, or that no boundary segment reaches, are counted at
+//              once; the others ("slow" owners) are appended to a record list
+//   k_slow     every slow owner of the call, densely: exact classification
+//              (Alg. 1), class and rotation (Sec. 3.3.3), a 16-byte record, and
+//              its counts added to its row segment
 //   k_scan_*   exclusive prefix sum of the per-segment counts -> output offsets
-//   k_emit     per tile (RB rows x CB owners): re-classify, prefix-sum the owner
-//              counts in LDS (with a one-row, one-column halo for neighbour ids),
-//              write FP64 vertices, int32 triangles and u8 class codes
+//   k_emit     per tile: owner counts and their prefix sums in LDS (with a
+//              one-row, one-column halo for neighbour ids), then FP64
+//              vertices, int32 triangles and u8 class codes (Alg. 2)
+//   k_fused    the whole classify-scan-emit path in one persistent launch:
+//              workgroups take full-width row bands in ticket order, publish
+//              their counts and find their output offsets by a decoupled
+//              look-back over earlier bands of the same image
 //
 // The output order is fixed by the owner numbering and does not depend on
-// the tile shape.
+// the tile shape, the strategy or the batch.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
 
 #include "../../include/sbmt.h"
 
@@ -36,35 +52,101 @@ SBMT_HD uint32_t lut_tri(int cls, int j) { return sbmt_lut_tri[cls][j]; }
 SBMT_HD uint32_t lut_emit(int cls, int rot, int t, int j) { return sbmt_lut_emit[cls][rot][t][j]; }
 
 constexpr int kThreads = 256;
-constexpr int kCB = 256;          // owners per row segment
-constexpr int kOPT = kCB / kThreads;  // owners per thread per row
-constexpr int kRB = 8;            // rows per emission tile
-constexpr int kRec = 192;         // slow-owner records kept in LDS per emission tile
+constexpr int kCB = 256;               // owners per row segment (one per thread)
 constexpr int kScanThreads = 1024;
 constexpr int kScanChunk = 4 * kScanThreads;
+constexpr int kWinRows = 16, kWinWords = 16;  // LDS window of the coarse raster per tile
+constexpr uint32_t kSlowBit = 0x80000000u;     // owner info word: slow owner, low bits = record
+constexpr uint32_t kNoRec = 0x7fffffffu;       // slow owner without a record (list full)
+constexpr int kMaxBandChunks = 64;             // fused path: row segments per band
 
-
-struct Work {
-  uint32_t* bits;
-  int4* seg_cnt;       // [nseg] (nv, nt, ncut, err)
-  longlong2* seg_off;  // [nseg] exclusive (vertex, triangle) offsets
-  longlong4* blk;      // [nblk] scan block sums / offsets
-  long long* tot;      // [8] nv, nt, ncut, err
+// One image of a call, as the kernels see it.
+struct Img {
+  Geo g;
+  const uint8_t* bm;  // bitmap rows (device)
+  uint32_t* bits;     // coarse raster, (CH + 2 kRing) rows of wpr words
+  uint32_t* oinfo;    // [NK][NI] info word of every owner whose window is not uniform
+  int64_t seg0;       // first row segment of the image in the call's segment arrays
+  int64_t band0;      // first band of the image (fused path, 4-row numbering)
+  int64_t halo0;      // first word of the image's halo rows (fused path)
+  double* verts;
+  int32_t* tris;
+  uint8_t* codes;
+  int64_t vcap, tcap;  // output capacities in rows
 };
 
+// Scratch shared by the images of a call.
+struct Shared {
+  int4* seg_cnt;                    // [nseg] (nv, nt, ncut, 0) of owners counted in k_count
+  unsigned long long* seg_slow;     // [nseg] slow-owner counts nv | nt << 21 | ncut << 42
+  longlong4* seg_off;               // [nseg + 1] exclusive (v, t, cut) over the call; [nseg] = totals
+  longlong4* blk;                   // [nblk] scan block sums
+  unsigned long long* ctr;          // [8] 0: records handed out, 1: band ticket
+  int* imgerr;                      // [n] protocol violation seen
+  int64_t* sizes;                   // [n][4] n_vertices, n_triangles, n_cut, status
+  SlowRec* rec;                     // [rcap] slow-owner records
+  unsigned long long* band;         // [nbands] fused path look-back words
+  int64_t rcap, nseg, nbands;
+  int nblk, n;
+};
+
+// Block -> image maps.  OneSrc carries the single image by value; ManySrc
+// reads the image table of the workspace and a per-kernel prefix table of
+// block counts.
+struct OneSrc {
+  Img d;
+  __device__ __forceinline__ int find(int64_t b, const int64_t*, int64_t& local) const {
+    local = b;
+    return 0;
+  }
+  __device__ __forceinline__ const Img& img(int) const { return d; }
+};
+
+struct ManySrc {
+  const Img* d;
+  int n;
+  __device__ __forceinline__ int find(int64_t b, const int64_t* tab, int64_t& local) const {
+    int lo = 0, hi = n - 1;  // largest i with tab[i] <= b
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tab[mid] <= b) lo = mid;
+      else hi = mid - 1;
+    }
+    local = b - tab[lo];
+    return lo;
+  }
+  __device__ __forceinline__ const Img& img(int i) const { return d[i]; }
+};
+
+SBMT_HD unsigned long long pack_counts(uint32_t info) {
+  return (unsigned long long)info_nv(info) | ((unsigned long long)info_nt(info) << 21) |
+         ((unsigned long long)info_ncut(info) << 42);
+}
 
 // ---------------------------------------------------------------------------
 // Coarse raster: bit (R + ring, C + ringC) = [2 * #fg pixels of block (R, C) >= s^2].
 // One lane per sample; a wave covers 64 consecutive stored columns and packs
 // them with a ballot; samples outside the image (the ring) are background.
-// grid (ceil(32 wpr / 256), CH + 2 ring), 256 threads.
+// Blocks per image: ceil(32 wpr / 256) x (CH + 2 ring); 256 threads.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_coarsen(Geo g, const uint8_t* __restrict__ bm, uint32_t* __restrict__ bits,
-                                                 long long* __restrict__ tot) {
+template <class Src>
+__global__ void __launch_bounds__(256) k_coarsen(Src src, const int64_t* __restrict__ tab, Shared sh) {
+  int64_t local;
+  const int ii = src.find(blockIdx.x, tab, local);
+  const Img& d = src.img(ii);
+  const Geo g = d.g;
+  const int nbx = (32 * g.wpr + 255) / 256;
+  const int bx = (int)(local % nbx), rr = (int)(local / nbx);
+  if (blockIdx.x == 0 && threadIdx.x < 8) sh.ctr[threadIdx.x] = 0;
+  if (local == 0 && threadIdx.x == 0) sh.imgerr[ii] = 0;
+  // look-back words and size slots of the fused path start at zero
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < sh.nbands; q += (int64_t)gridDim.x * blockDim.x)
+    sh.band[q] = 0ull;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < 4 * (int64_t)sh.n;
+       q += (int64_t)gridDim.x * blockDim.x)
+    sh.sizes[q] = 0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int gw = blockIdx.x * 4 + wv;  // 64-bit group of the stored row
-  const int rr = blockIdx.y;
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 8) tot[threadIdx.x] = 0;
+  const int gw = bx * 4 + wv;  // 64-bit group of the stored row
   const int R = rr - kRing;
   const int C = 64 * gw + lane - kRingC;
   int fg = 0;
@@ -74,23 +156,21 @@ __global__ void __launch_bounds__(256) k_coarsen(Geo g, const uint8_t* __restric
     const int c0 = s * C, c1 = min(c0 + s, g.W);
     int cnt = 0;
     for (int r = r0; r < r1; ++r) {
-      const uint8_t* row = bm + (int64_t)r * g.stride;
+      const uint8_t* row = d.bm + (int64_t)r * g.stride;
       for (int c = c0; c < c1; ++c) cnt += row[c] != 0;
     }
     fg = 2 * cnt >= s * s;
   }
   const unsigned long long m = __ballot(fg);
   const int w = 2 * gw + lane;
-  if (lane < 2 && w < g.wpr) bits[(int64_t)rr * g.wpr + w] = (uint32_t)(m >> (32 * lane));
+  if (lane < 2 && w < g.wpr) d.bits[(int64_t)rr * g.wpr + w] = (uint32_t)(m >> (32 * lane));
 }
 
-// Stage the coarse-raster window of a tile (grid rows k0 .. k0 + nk - 1, owner
+// Stage the coarse-raster window of a tile (cell rows rlo .. rhi, owner
 // columns cfirst .. clast) in LDS; returns the view.  Sizes are checked on the
 // host (tile_window_fits).
-constexpr int kWinRows = 16, kWinWords = 16;
-
-__device__ __forceinline__ Bits stage_window(const Geo& g, const uint32_t* __restrict__ bits, uint32_t* win, int rlo, int rhi,
-                             int cfirst, int clast) {
+__device__ __forceinline__ Bits stage_window(const Geo& g, const uint32_t* __restrict__ bits, uint32_t* win, int rlo,
+                                             int rhi, int cfirst, int clast) {
   const int x0 = g.X0 + 4 * g.h * cfirst, x1 = g.X0 + 4 * g.h * clast + 2 * g.h;
   const int wlo = (clo_of(g, x0) + kRingC) >> 5;
   const int whi = ((clo_of(g, x1) + 2 + kRingC) >> 5) + 1;
@@ -112,90 +192,6 @@ __device__ __forceinline__ int wave_sum(int v) {
   return v;
 }
 
-// ---------------------------------------------------------------------------
-// Plan: classify every owner of kRB row segments and sum the counts per
-// segment.  Owners whose window is not uniform are queued in LDS for the whole
-// tile and classified densely afterwards.
-// grid (NCB, ceil(NK / kRB)), kThreads threads, kOPT owners per thread per row.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) k_count(Geo g, const uint32_t* __restrict__ bits_g,
-                                                    int4* __restrict__ seg_cnt, long long* __restrict__ tot) {
-  __shared__ int acc[kRB][4];
-  __shared__ int rowR[kRB];
-  __shared__ uint16_t q1[kRB * kCB];
-  __shared__ uint16_t q2[kRB * kCB];
-  __shared__ int n1, n2;
-  __shared__ uint32_t win[kWinRows * kWinWords];
-  const int cb = blockIdx.x;
-  const int k0 = blockIdx.y * kRB;
-  const int c0 = cb * kCB;
-  const int lane = threadIdx.x & 63;
-  if (threadIdx.x < kRB) {
-    rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);
-    acc[threadIdx.x][0] = acc[threadIdx.x][1] = acc[threadIdx.x][2] = acc[threadIdx.x][3] = 0;
-  }
-  if (threadIdx.x == 0) n1 = n2 = 0;
-  __syncthreads();
-  const int klast = min(k0 + kRB, g.NK) - 1;
-  const Bits bw = stage_window(g, bits_g, win, rowR[0] + kRing, rowR[klast - k0] + 2 + kRing, c0,
-                               min(c0 + kCB, g.NI) - 1);
-  __syncthreads();
-  // uniform windows, one owner per thread; the others are queued
-  for (int r = 0; r < kRB; ++r) {
-    const int k = k0 + r;
-    if (k >= g.NK) break;
-    int nv = 0, nt = 0;
-    for (int j = 0; j < kOPT; ++j) {
-      const int c = c0 + j * kThreads + threadIdx.x;
-      if (c >= g.NI) continue;
-      const Frame f = owner_frame(g, bw, k, c, rowR[r]);
-      if (frame_uniform(f)) {
-        const uint32_t fi = fast_info(g, f);
-        nv += info_nv(fi);
-        nt += info_nt(fi);
-      } else {
-        q1[atomicAdd(&n1, 1)] = (uint16_t)(r * kCB + (c - c0));
-      }
-    }
-    nv = wave_sum(nv);
-    nt = wave_sum(nt);
-    if (lane == 0 && (nv | nt)) { atomicAdd(&acc[r][0], nv); atomicAdd(&acc[r][1], nt); }
-  }
-  __syncthreads();
-  // non-uniform windows: quiet owners (no segment reaches them) or slow ones
-  for (int q = threadIdx.x; q < n1; q += kThreads) {
-    const int e = q1[q], r = e / kCB, c = c0 + (e - r * kCB);
-    const Frame f = owner_frame(g, bw, k0 + r, c, rowR[r]);
-    uint32_t fi = 0;
-    if (needs_slow(g, f, fi)) {
-      q2[atomicAdd(&n2, 1)] = (uint16_t)e;
-    } else {
-      atomicAdd(&acc[r][0], info_nv(fi));
-      atomicAdd(&acc[r][1], info_nt(fi));
-    }
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < n2; q += kThreads) {
-    const int e = q2[q], r = e / kCB, c = c0 + (e - r * kCB);
-    const Frame f = owner_frame(g, bw, k0 + r, c, rowR[r]);
-    Slow sr;
-    slow_classify(g, f, sr);
-    atomicAdd(&acc[r][0], info_nv(sr.info));
-    atomicAdd(&acc[r][1], info_nt(sr.info));
-    atomicAdd(&acc[r][2], info_ncut(sr.info));
-    if (info_err(sr.info)) atomicOr(&acc[r][3], 1);
-  }
-  __syncthreads();
-  if (threadIdx.x < kRB && k0 + (int)threadIdx.x < g.NK) {
-    const int r = threadIdx.x;
-    seg_cnt[(int64_t)(k0 + r) * g.NCB + cb] = make_int4(acc[r][0], acc[r][1], acc[r][2], acc[r][3]);
-    if (acc[r][3]) atomicOr((unsigned long long*)&tot[3], 1ull);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Exclusive scan of the per-segment (nv, nt) counts, three phases.
-// ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v, int lane) {
   for (int off = 1; off < 64; off <<= 1) {
@@ -205,19 +201,179 @@ __device__ __forceinline__ T wave_incl_scan(T v, int lane) {
   return v;
 }
 
+// ---------------------------------------------------------------------------
+// Count one tile: rows k0 .. k0+RB-1, owners c0 .. c0+kCB-1.  Uniform windows
+// are counted from one bit; the other owners are checked against the
+// segments of their block: quiet ones (no segment reaches them) get their info
+// word in oinfo, slow ones get a record slot (their position is written into
+// it for k_slow) or, once the record list is full, are classified here.
+// Writes the segment counts of owners counted here and clears the slow ones.
+// ---------------------------------------------------------------------------
+template <int RB>
+struct CountLds {
+  int acc[RB][4];
+  int rowR[RB];
+  uint16_t q1[RB * kCB];
+  uint16_t q2[RB * kCB];
+  int n1, n2;
+  unsigned long long base;
+  uint32_t win[kWinRows * kWinWords];
+};
+
+template <int RB>
+__device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, int ky, int cb, const Shared& sh,
+                                           CountLds<RB>& L, int4* acc_out) {
+  const int k0 = ky * RB;
+  const int c0 = cb * kCB;
+  const int lane = threadIdx.x & 63;
+  if (threadIdx.x < RB) {
+    L.rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);
+    L.acc[threadIdx.x][0] = L.acc[threadIdx.x][1] = L.acc[threadIdx.x][2] = L.acc[threadIdx.x][3] = 0;
+  }
+  if (threadIdx.x == 0) L.n1 = L.n2 = 0;
+  __syncthreads();
+  const int klast = min(k0 + RB, g.NK) - 1;
+  const Bits bw = stage_window(g, d.bits, L.win, L.rowR[0] + kRing, L.rowR[klast - k0] + 2 + kRing, c0,
+                               min(c0 + kCB, g.NI) - 1);
+  __syncthreads();
+  // uniform windows, one owner per thread; the others are queued
+  for (int r = 0; r < RB; ++r) {
+    const int k = k0 + r;
+    if (k >= g.NK) break;
+    int nv = 0, nt = 0;
+    const int c = c0 + threadIdx.x;
+    if (c < g.NI) {
+      const Frame f = owner_frame(g, bw, k, c, L.rowR[r]);
+      if (frame_uniform(f)) {
+        const uint32_t fi = fast_info(g, f);
+        nv = info_nv(fi);
+        nt = info_nt(fi);
+      } else {
+        L.q1[atomicAdd(&L.n1, 1)] = (uint16_t)(r * kCB + threadIdx.x);
+      }
+    }
+    nv = wave_sum(nv);
+    nt = wave_sum(nt);
+    if (lane == 0 && (nv | nt)) {
+      atomicAdd(&L.acc[r][0], nv);
+      atomicAdd(&L.acc[r][1], nt);
+    }
+  }
+  __syncthreads();
+  // non-uniform windows: quiet owners (no segment reaches them) or slow ones
+  for (int q = threadIdx.x; q < L.n1; q += kThreads) {
+    const int e = L.q1[q], r = e / kCB, c = c0 + (e - r * kCB);
+    const int k = k0 + r;
+    const Frame f = owner_frame(g, bw, k, c, L.rowR[r]);
+    uint32_t fi = 0;
+    if (needs_slow(g, f, fi)) {
+      L.q2[atomicAdd(&L.n2, 1)] = (uint16_t)e;
+    } else {
+      d.oinfo[(int64_t)k * g.NI + c] = fi;
+      atomicAdd(&L.acc[r][0], info_nv(fi));
+      atomicAdd(&L.acc[r][1], info_nt(fi));
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) L.base = L.n2 ? atomicAdd(&sh.ctr[0], (unsigned long long)L.n2) : 0ull;
+  __syncthreads();
+  for (int q = threadIdx.x; q < L.n2; q += kThreads) {
+    const int e = L.q2[q], r = e / kCB, c = c0 + (e - r * kCB);
+    const int k = k0 + r;
+    const unsigned long long idx = L.base + (unsigned long long)q;
+    if (idx < (unsigned long long)sh.rcap) {
+      sh.rec[idx].x = (uint64_t)c | ((uint64_t)k << 24) | ((uint64_t)ii << 48);
+      d.oinfo[(int64_t)k * g.NI + c] = kSlowBit | (uint32_t)idx;
+    } else {
+      const Frame f = owner_frame(g, bw, k, c, L.rowR[r]);
+      Slow sr;
+      slow_classify(g, f, sr);
+      d.oinfo[(int64_t)k * g.NI + c] = kSlowBit | kNoRec;
+      atomicAdd(&L.acc[r][0], info_nv(sr.info));
+      atomicAdd(&L.acc[r][1], info_nt(sr.info));
+      atomicAdd(&L.acc[r][2], info_ncut(sr.info));
+      if (info_err(sr.info)) atomicOr(&L.acc[r][3], 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < RB && k0 + (int)threadIdx.x < g.NK) {
+    const int r = threadIdx.x;
+    acc_out[r] = make_int4(L.acc[r][0], L.acc[r][1], L.acc[r][2], L.acc[r][3]);
+    if (L.acc[r][3]) atomicOr(&sh.imgerr[ii], 1);
+  }
+}
+
+template <class Src, int RB>
+__global__ void __launch_bounds__(kThreads) k_count(Src src, const int64_t* __restrict__ tab, Shared sh) {
+  __shared__ CountLds<RB> L;
+  __shared__ int4 out[RB];
+  int64_t local;
+  const int ii = src.find(blockIdx.x, tab, local);
+  const Img& d = src.img(ii);
+  const Geo g = d.g;
+  const int cb = (int)(local % g.NCB), ky = (int)(local / g.NCB);
+  count_tile<RB>(d, g, ii, ky, cb, sh, L, out);
+  __syncthreads();
+  const int k = ky * RB + (int)threadIdx.x;
+  if (threadIdx.x < RB && k < g.NK) {
+    const int64_t j = d.seg0 + (int64_t)k * g.NCB + cb;
+    sh.seg_cnt[j] = out[threadIdx.x];
+    sh.seg_slow[j] = 0ull;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Slow owners of the call, one per lane over the record list: classify, store
+// the 16-byte record in place of the position, add the counts to the segment.
+// ---------------------------------------------------------------------------
+template <class Src>
+__global__ void __launch_bounds__(256) k_slow(Src src, Shared sh) {
+  const unsigned long long n = min(sh.ctr[0], (unsigned long long)sh.rcap);
+  for (unsigned long long idx = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (unsigned long long)gridDim.x * blockDim.x) {
+    const uint64_t p = sh.rec[idx].x;
+    const int ii = (int)(p >> 48), k = (int)((p >> 24) & 0xffffffu), c = (int)(p & 0xffffffu);
+    const Img& d = src.img(ii);
+    const Geo g = d.g;
+    Bits b;
+    b.p = d.bits;
+    b.wpr = g.wpr;
+    b.rr0 = 0;
+    b.cc0 = 0;
+    const Frame f = owner_frame(g, b, k, c, row_cell(k, g.h, g.s));
+    Slow sr;
+    slow_classify(g, f, sr);
+    sh.rec[idx] = pack_slow(sr);
+    atomicAdd(&sh.seg_slow[d.seg0 + (int64_t)k * g.NCB + c / kCB], pack_counts(sr.info));
+    if (info_err(sr.info)) atomicOr(&sh.imgerr[ii], 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of the per-segment (nv, nt, ncut) over the whole call.
+// ---------------------------------------------------------------------------
 // block-wide exclusive scan of (a, b) over kScanThreads threads; returns totals
-__device__ void block_excl_scan2(long long& a, long long& b, long long* sa, long long* sb,
-                                 long long& ta, long long& tb) {
+__device__ void block_excl_scan2(long long& a, long long& b, long long* sa, long long* sb, long long& ta,
+                                 long long& tb) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   long long ia = wave_incl_scan(a, lane), ib = wave_incl_scan(b, lane);
-  if (lane == 63) { sa[wv] = ia; sb[wv] = ib; }
+  if (lane == 63) {
+    sa[wv] = ia;
+    sb[wv] = ib;
+  }
   __syncthreads();
   if (threadIdx.x < 64) {
     const int nw = blockDim.x >> 6;
     long long xa = threadIdx.x < nw ? sa[threadIdx.x] : 0, xb = threadIdx.x < nw ? sb[threadIdx.x] : 0;
     long long ya = wave_incl_scan(xa, lane), yb = wave_incl_scan(xb, lane);
-    if (threadIdx.x < nw) { sa[threadIdx.x] = ya - xa; sb[threadIdx.x] = yb - xb; }
-    if (threadIdx.x == nw - 1) { sa[32] = ya; sb[32] = yb; }
+    if (threadIdx.x < nw) {
+      sa[threadIdx.x] = ya - xa;
+      sb[threadIdx.x] = yb - xb;
+    }
+    if (threadIdx.x == nw - 1) {
+      sa[32] = ya;
+      sb[32] = yb;
+    }
   }
   __syncthreads();
   a = ia - a + sa[wv];
@@ -227,260 +383,570 @@ __device__ void block_excl_scan2(long long& a, long long& b, long long* sa, long
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const int4* __restrict__ seg_cnt, int64_t nseg,
-                                                              longlong4* __restrict__ blk) {
+__device__ __forceinline__ void seg_counts(const Shared& sh, int64_t j, long long& a, long long& b, long long& c) {
+  const int4 v = sh.seg_cnt[j];
+  const unsigned long long s = sh.seg_slow[j];
+  a = v.x + (long long)(s & 0x1fffffull);
+  b = v.y + (long long)((s >> 21) & 0x1fffffull);
+  c = v.z + (long long)(s >> 42);
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(Shared sh) {
   __shared__ long long sa[33], sb[33];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
   long long a = 0, b = 0, c = 0;
   for (int q = 0; q < 4; ++q) {
     const int64_t j = base + (int64_t)threadIdx.x * 4 + q;
-    if (j < nseg) { int4 v = seg_cnt[j]; a += v.x; b += v.y; c += v.z; }
+    if (j < sh.nseg) {
+      long long x, y, z;
+      seg_counts(sh, j, x, y, z);
+      a += x;
+      b += y;
+      c += z;
+    }
   }
   long long ta, tb, tc, dummy;
   block_excl_scan2(a, b, sa, sb, ta, tb);
   long long z = 0;
   block_excl_scan2(c, z, sa, sb, tc, dummy);
-  if (threadIdx.x == 0) blk[blockIdx.x] = make_longlong4(ta, tb, tc, 0);
+  if (threadIdx.x == 0) sh.blk[blockIdx.x] = make_longlong4(ta, tb, tc, 0);
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_blocks(longlong4* __restrict__ blk, int nblk,
-                                                              long long* __restrict__ tot) {
+__global__ void __launch_bounds__(kScanThreads) k_scan_blocks(Shared sh) {
   __shared__ long long sa[33], sb[33];
   long long ra = 0, rb = 0, rc = 0;
-  for (int base = 0; base < nblk; base += kScanThreads) {
+  for (int base = 0; base < sh.nblk; base += kScanThreads) {
     const int j = base + threadIdx.x;
-    longlong4 v = j < nblk ? blk[j] : make_longlong4(0, 0, 0, 0);
+    longlong4 v = j < sh.nblk ? sh.blk[j] : make_longlong4(0, 0, 0, 0);
     long long a = v.x, b = v.y, ta, tb;
     block_excl_scan2(a, b, sa, sb, ta, tb);
-    long long c = v.z, z = 0, tc, d;
-    block_excl_scan2(c, z, sa, sb, tc, d);
-    if (j < nblk) blk[j] = make_longlong4(ra + a, rb + b, rc + c, 0);
-    ra += ta; rb += tb; rc += tc;
+    long long c = v.z, z = 0, tc, dd;
+    block_excl_scan2(c, z, sa, sb, tc, dd);
+    if (j < sh.nblk) sh.blk[j] = make_longlong4(ra + a, rb + b, rc + c, 0);
+    ra += ta;
+    rb += tb;
+    rc += tc;
   }
-  if (threadIdx.x == 0) { tot[0] = ra; tot[1] = rb; tot[2] = rc; }
+  if (threadIdx.x == 0) sh.seg_off[sh.nseg] = make_longlong4(ra, rb, rc, 0);
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int4* __restrict__ seg_cnt, int64_t nseg,
-                                                             const longlong4* __restrict__ blk,
-                                                             longlong2* __restrict__ seg_off) {
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(Shared sh) {
   __shared__ long long sa[33], sb[33];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
-  int4 v[4];
-  long long a = 0, b = 0;
+  long long va[4], vb[4], vc[4];
+  long long a = 0, b = 0, c = 0;
   for (int q = 0; q < 4; ++q) {
     const int64_t j = base + (int64_t)threadIdx.x * 4 + q;
-    v[q] = j < nseg ? seg_cnt[j] : make_int4(0, 0, 0, 0);
-    a += v[q].x; b += v[q].y;
+    va[q] = vb[q] = vc[q] = 0;
+    if (j < sh.nseg) seg_counts(sh, j, va[q], vb[q], vc[q]);
+    a += va[q];
+    b += vb[q];
+    c += vc[q];
   }
-  long long ta, tb;
+  long long ta, tb, tc, dd;
   block_excl_scan2(a, b, sa, sb, ta, tb);
-  const longlong4 bo = blk[blockIdx.x];
-  a += bo.x; b += bo.y;
+  long long z = 0;
+  block_excl_scan2(c, z, sa, sb, tc, dd);
+  const longlong4 bo = sh.blk[blockIdx.x];
+  a += bo.x;
+  b += bo.y;
+  c += bo.z;
   for (int q = 0; q < 4; ++q) {
     const int64_t j = base + (int64_t)threadIdx.x * 4 + q;
-    if (j < nseg) seg_off[j] = make_longlong2(a, b);
-    a += v[q].x; b += v[q].y;
+    if (j < sh.nseg) sh.seg_off[j] = make_longlong4(a, b, c, 0);
+    a += va[q];
+    b += vb[q];
+    c += vc[q];
+  }
+}
+
+// Per-image sizes and status from the scanned offsets (one thread per image).
+template <class Src>
+__device__ __forceinline__ void image_totals(const Img& d, const Shared& sh, long long& nv, long long& nt,
+                                             long long& nc) {
+  const int64_t nsegi = (int64_t)d.g.NK * d.g.NCB;
+  const longlong4 a = sh.seg_off[d.seg0], b = sh.seg_off[d.seg0 + nsegi];
+  nv = b.x - a.x;
+  nt = b.y - a.y;
+  nc = b.z - a.z;
+}
+
+__device__ __forceinline__ int64_t image_status(const Img& d, int err, long long nv, long long nt) {
+  if (err) return SBMT_E_PROTOCOL;
+  if (nv > 0x7fffffffLL) return SBMT_E_INDEX_OVERFLOW;
+  if (nv > d.vcap || nt > d.tcap) return SBMT_E_CAPACITY;
+  return SBMT_OK;
+}
+
+template <class Src>
+__global__ void k_sizes(Src src, Shared sh, int64_t* __restrict__ user) {
+  const int ii = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ii >= sh.n) return;
+  const Img& d = src.img(ii);
+  long long nv, nt, nc;
+  image_totals<Src>(d, sh, nv, nt, nc);
+  const int64_t st = image_status(d, sh.imgerr[ii], nv, nt);
+  int64_t* o = sh.sizes + 4 * (int64_t)ii;
+  o[0] = nv;
+  o[1] = nt;
+  o[2] = nc;
+  o[3] = st;
+  if (user) {
+    user[4 * (int64_t)ii + 0] = nv;
+    user[4 * (int64_t)ii + 1] = nt;
+    user[4 * (int64_t)ii + 2] = nc;
+    user[4 * (int64_t)ii + 3] = st;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Emission.
+// Emission of one tile: rows k0 .. k0+RB-1, owners c0 .. c0+kCB-1.
+//   1. info of the tile's owners plus a one-row / one-column halo: uniform
+//      windows from their samples, the others from their info word (plain, or
+//      the record of a slow owner; owners without a record are classified);
+//   2. prefix sums of the counts of every row in LDS plus the segment bases
+//      give each owner's first vertex and triangle id and its neighbours' ids;
+//   3. fast and quiet owners are emitted one per thread, then the slow owners
+//      of the tile densely from their records.
+// The caller fills bv[0..RB] (image-local first vertex of each row's segment,
+// row RB = the halo row) and tb[0..RB-1] (first triangle) and syncs.
 // ---------------------------------------------------------------------------
-// ---------------------------------------------------------------------------
-// Emission of a tile of kRB rows x kCB owners.
-//   1. counts of the tile's owners plus a one-row / one-column halo; owners
-//      with a non-uniform window are queued and classified densely, their
-//      classification kept in LDS (up to kRec of them; later ones are
-//      classified again at emission);
-//   2. prefix sums of the counts of every row in LDS, plus the segment bases
-//      from the plan, give each owner's first vertex and triangle id and its
-//      neighbours' ids;
-//   3. fast owners are emitted one per thread, then all slow owners densely.
-// grid (NCB, ceil(NK / kRB)), kThreads threads.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) k_emit(Geo g, const uint32_t* __restrict__ bits_g,
-                                                   const longlong2* __restrict__ seg_off,
-                                                   const long long* __restrict__ tot, int64_t vcap, int64_t tcap,
-                                                   double* __restrict__ verts, int32_t* __restrict__ tris,
-                                                   uint8_t* __restrict__ codes) {
-  constexpr int W = kCB + 2;  // columns c0-1 .. c0+CB
-  __shared__ uint32_t info[kRB + 1][W];
-  __shared__ int voff[kRB + 1][W];
-  __shared__ int16_t toff[kRB][W];
-  __shared__ uint32_t win[kWinRows * kWinWords];
-  __shared__ uint16_t queue[(kRB + 1) * W];
-  __shared__ uint16_t q1[(kRB + 1) * W];
-  __shared__ SlowRec rec[kRec];
-  __shared__ int qn, n1;
-  __shared__ int rowR[kRB + 1];
-  __shared__ long long tb[kRB];
-  __shared__ int part[kRB + 1][2][kThreads / 64];
-  __shared__ int trow[kRB];
-  if (tot[0] > vcap || tot[1] > tcap || tot[3] != 0) return;  // does not fit / plan failed
-  const int cb = blockIdx.x;
-  const int k0 = blockIdx.y * kRB;
+template <int RB>
+struct EmitLds {
+  static constexpr int W = kCB + 2;  // columns c0-1 .. c0+kCB
+  uint32_t info[RB + 1][W];
+  int voff[RB + 1][W];
+  int16_t toff[RB][W];
+  uint32_t win[kWinRows * kWinWords];
+  uint16_t qa[(RB + 1) * W];  // slow owners without a record
+  uint16_t qs[RB * kCB];      // slow owners to emit
+  int na, ns;
+  int rowR[RB + 1];
+  int bv[RB + 1];
+  long long tb[RB];
+  int rowv[RB + 1];  // vertices of each row's kCB owners
+  int part[RB + 1][2][kThreads / 64];
+};
+
+template <int RB>
+__device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, int cb, const Shared& sh,
+                                          EmitLds<RB>& L, const uint32_t* __restrict__ hrow) {
+  constexpr int W = EmitLds<RB>::W;
+  const int k0 = ky * RB;
   const int c0 = cb * kCB;
-  if (threadIdx.x <= kRB) rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);
-  if (threadIdx.x == 0) qn = n1 = 0;
+  if (threadIdx.x <= RB) L.rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);
+  if (threadIdx.x == 0) L.na = L.ns = 0;
   __syncthreads();
-  const int klast = min(k0 + kRB + 1, g.NK) - 1;
-  const Bits bw = stage_window(g, bits_g, win, rowR[0] + kRing, rowR[max(klast - k0, 0)] + 2 + kRing,
+  const int klast = min(k0 + RB + 1, g.NK) - 1;
+  const Bits bw = stage_window(g, d.bits, L.win, L.rowR[0] + kRing, L.rowR[max(klast - k0, 0)] + 2 + kRing,
                                max(c0 - 1, 0), min(c0 + kCB + 1, g.NI) - 1);
   __syncthreads();
-  // 1. counts: uniform windows one owner per thread, then the queued ones densely
-  for (int idx = threadIdx.x; idx < (kRB + 1) * W; idx += kThreads) {
+  // 1. info words
+  for (int idx = threadIdx.x; idx < (RB + 1) * W; idx += kThreads) {
     const int rr = idx / W, col = idx - rr * W;
     const int k = k0 + rr, c = c0 - 1 + col;
     uint32_t fi = 0;
     if (k < g.NK && c >= 0 && c < g.NI) {
-      const Frame f = owner_frame(g, bw, k, c, rowR[rr]);
-      if (frame_uniform(f)) fi = fast_info(g, f);
-      else q1[atomicAdd(&n1, 1)] = (uint16_t)idx;
+      const Frame f = owner_frame(g, bw, k, c, L.rowR[rr]);
+      if (frame_uniform(f)) {
+        fi = fast_info(g, f);
+      } else {
+        const uint32_t w = rr == RB ? hrow[c] : d.oinfo[(int64_t)k * g.NI + c];
+        if (!(w & kSlowBit)) {
+          fi = w;
+        } else {
+          const uint32_t ri = w & kNoRec;
+          if (ri == kNoRec) L.qa[atomicAdd(&L.na, 1)] = (uint16_t)idx;
+          else fi = sh.rec[ri].info;
+          if (rr < RB && col >= 1 && col <= kCB) L.qs[atomicAdd(&L.ns, 1)] = (uint16_t)idx;
+        }
+      }
     }
-    info[rr][col] = fi;
+    L.info[rr][col] = fi;
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < n1; q += kThreads) {
-    const int idx = q1[q], rr = idx / W, col = idx - rr * W;
-    const Frame f = owner_frame(g, bw, k0 + rr, c0 - 1 + col, rowR[rr]);
-    uint32_t fi = 0;
-    if (needs_slow(g, f, fi)) queue[atomicAdd(&qn, 1)] = (uint16_t)idx;
-    else info[rr][col] = fi;
-  }
-  __syncthreads();
-  const int nq = qn;
-  for (int q = threadIdx.x; q < nq; q += kThreads) {
-    const int idx = queue[q], rr = idx / W, col = idx - rr * W;
-    const Frame f = owner_frame(g, bw, k0 + rr, c0 - 1 + col, rowR[rr]);
+  for (int q = threadIdx.x; q < L.na; q += kThreads) {
+    const int idx = L.qa[q], rr = idx / W, col = idx - rr * W;
+    const Frame f = owner_frame(g, bw, k0 + rr, c0 - 1 + col, L.rowR[rr]);
     Slow sr;
     slow_classify(g, f, sr);
-    info[rr][col] = sr.info;
-    if (q < kRec) rec[q] = pack_slow(sr);
+    L.info[rr][col] = sr.info;
   }
   __syncthreads();
-  // 2. prefix sums of every row: thread t owns columns 1 + t*kOPT .. kOPT + t*kOPT
+  // 2. prefix sums of every row: thread t owns column 1 + t
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int ev[kRB + 1], et[kRB + 1];
+  int ev[RB + 1], et[RB + 1];
 #pragma unroll
-  for (int rr = 0; rr <= kRB; ++rr) {
-    int sv = 0, st = 0;
-#pragma unroll
-    for (int j = 0; j < kOPT; ++j) {
-      const uint32_t f = info[rr][1 + threadIdx.x * kOPT + j];
-      sv += info_nv(f);
-      st += info_nt(f);
-    }
+  for (int rr = 0; rr <= RB; ++rr) {
+    const uint32_t f = L.info[rr][1 + threadIdx.x];
+    const int sv = info_nv(f), st = info_nt(f);
     const int iv = wave_incl_scan(sv, lane), it = wave_incl_scan(st, lane);
     ev[rr] = iv - sv;
     et[rr] = it - st;
-    if (lane == 63) { part[rr][0][wv] = iv; part[rr][1][wv] = it; }
+    if (lane == 63) {
+      L.part[rr][0][wv] = iv;
+      L.part[rr][1][wv] = it;
+    }
   }
-  if (threadIdx.x < kRB) tb[threadIdx.x] = k0 + (int)threadIdx.x < g.NK ? seg_off[(int64_t)(k0 + threadIdx.x) * g.NCB + cb].y : 0;
   __syncthreads();
 #pragma unroll
-  for (int rr = 0; rr <= kRB; ++rr) {
-    const int k = k0 + rr;
-    const int bv = k < g.NK ? (int)seg_off[(int64_t)k * g.NCB + cb].x : 0;
+  for (int rr = 0; rr <= RB; ++rr) {
+    const int bv = L.bv[rr];
     int pv = 0, pt = 0, totv = 0;
 #pragma unroll
     for (int q = 0; q < kThreads / 64; ++q) {
-      if (q < wv) { pv += part[rr][0][q]; pt += part[rr][1][q]; }
-      totv += part[rr][0][q];
-    }
-    int v = bv + ev[rr] + pv, t = et[rr] + pt;
-#pragma unroll
-    for (int j = 0; j < kOPT; ++j) {
-      const int col = 1 + threadIdx.x * kOPT + j;
-      const uint32_t f = info[rr][col];
-      voff[rr][col] = v;
-      if (rr < kRB) toff[rr][col] = (int16_t)t;
-      v += info_nv(f);
-      t += info_nt(f);
-    }
-    if (threadIdx.x == 0) {
-      voff[rr][0] = bv - info_nv(info[rr][0]);
-      voff[rr][W - 1] = bv + totv;
-      if (rr < kRB) {
-        int tt = 0;
-        for (int q = 0; q < kThreads / 64; ++q) tt += part[rr][1][q];
-        trow[rr] = tt;
+      if (q < wv) {
+        pv += L.part[rr][0][q];
+        pt += L.part[rr][1][q];
       }
+      totv += L.part[rr][0][q];
+    }
+    const int col = 1 + threadIdx.x;
+    L.voff[rr][col] = bv + ev[rr] + pv;
+    if (rr < RB) L.toff[rr][col] = (int16_t)(et[rr] + pt);
+    if (threadIdx.x == 0) {
+      L.voff[rr][0] = bv - info_nv(L.info[rr][0]);
+      L.voff[rr][W - 1] = bv + totv;
+      L.rowv[rr] = totv;
     }
   }
   __syncthreads();
   auto neighbours = [&](int r, int col, uint32_t f, int o_) {
     Nb nb;
-    nb.vid = voff[r][col];
-    nb.id_vr = voff[r][col + 1];
-    nb.id_vdl = voff[r + 1][col + o_ - 1];
-    nb.id_vdr = voff[r + 1][col + o_];
+    nb.vid = L.voff[r][col];
+    nb.id_vr = L.voff[r][col + 1];
+    nb.id_vdl = L.voff[r + 1][col + o_ - 1];
+    nb.id_vdr = L.voff[r + 1][col + o_];
     nb.b0 = nb.vid + info_self(f);
     nb.b1 = nb.b0 + info_n(f, 0);
     nb.b2 = nb.b1 + info_n(f, 1);
-    const uint32_t fr = info[r][col + 1];
-    nb.b3 = voff[r][col + 1] + info_self(fr) + info_n(fr, 0);
-    const uint32_t fl = info[r + 1][col + o_ - 1];
-    nb.b4 = voff[r + 1][col + o_ - 1] + info_self(fl);
+    const uint32_t fr = L.info[r][col + 1];
+    nb.b3 = L.voff[r][col + 1] + info_self(fr) + info_n(fr, 0);
+    const uint32_t fl = L.info[r + 1][col + o_ - 1];
+    nb.b4 = L.voff[r + 1][col + o_ - 1] + info_self(fl);
     nb.bI = nb.b2 + info_n(f, 2);
     return nb;
   };
-  // 3. fast owners one per thread (their writes coalesce), then all slow
-  // owners of the tile densely from their records.
+  // 3. fast and quiet owners one per thread (their writes coalesce), then the
+  // slow owners of the tile densely.
   const bool both = (g.flags & 1u) != 0;
   Out out;
-  out.v = verts; out.t = tris; out.c = codes; out.vbase = 0; out.tbase = 0;
-  for (int r = 0; r < kRB; ++r) {
+  out.v = d.verts;
+  out.t = d.tris;
+  out.c = d.codes;
+  out.vbase = 0;
+  out.tbase = 0;
+  for (int r = 0; r < RB; ++r) {
     const int k = k0 + r;
     if (k >= g.NK) break;
     const int o_ = k & 1;
-    const double y = lat_y(g.h, k);
-    const int64_t TB = tb[r];
-    for (int j = 0; j < kOPT; ++j) {
-      const int col = 1 + j * kThreads + threadIdx.x;
-      const int c = c0 + col - 1;
-      if (c >= g.NI) continue;
-      const uint32_t f = info[r][col];
-      if (info_slow(f)) continue;
-      const int vid = voff[r][col];
-      if (info_self(f)) put_vertex(verts, vid, lat_x(g.X0 + 4 * g.h * c + 2 * g.h * o_), y);
-      int64_t u = TB + toff[r][col];
-      const uint8_t code = both && !info_fg(f) ? 0x80 : 0;
-      if (info_ntb(f)) {
-        tris[3 * u + 0] = vid; tris[3 * u + 1] = voff[r + 1][col + o_]; tris[3 * u + 2] = voff[r + 1][col + o_ - 1];
-        codes[u] = code;
-        ++u;
-      }
-      if (info_nta(f)) {
-        tris[3 * u + 0] = vid; tris[3 * u + 1] = voff[r][col + 1]; tris[3 * u + 2] = voff[r + 1][col + o_];
-        codes[u] = code;
-      }
+    const int col = 1 + threadIdx.x;
+    const int c = c0 + threadIdx.x;
+    if (c >= g.NI) continue;
+    const uint32_t f = L.info[r][col];
+    if (info_slow(f)) continue;
+    const int vid = L.voff[r][col];
+    if (info_self(f)) put_vertex(d.verts, vid, lat_x(g.X0 + 4 * g.h * c + 2 * g.h * o_), lat_y(g.h, k));
+    int64_t u = L.tb[r] + L.toff[r][col];
+    const uint8_t code = both && !info_fg(f) ? 0x80 : 0;
+    if (info_ntb(f)) {
+      d.tris[3 * u + 0] = vid;
+      d.tris[3 * u + 1] = L.voff[r + 1][col + o_];
+      d.tris[3 * u + 2] = L.voff[r + 1][col + o_ - 1];
+      d.codes[u] = code;
+      ++u;
+    }
+    if (info_nta(f)) {
+      d.tris[3 * u + 0] = vid;
+      d.tris[3 * u + 1] = L.voff[r][col + 1];
+      d.tris[3 * u + 2] = L.voff[r + 1][col + o_];
+      d.codes[u] = code;
     }
   }
-  for (int q = threadIdx.x; q < nq; q += kThreads) {
-    const int idx = queue[q], r = idx / W, col = idx - r * W;
-    if (r >= kRB || col < 1 || col > kCB) continue;
+  for (int q = threadIdx.x; q < L.ns; q += kThreads) {
+    const int idx = L.qs[q], r = idx / W, col = idx - r * W;
     const int k = k0 + r, c = c0 + col - 1;
-    const uint32_t f = info[r][col];
+    const uint32_t f = L.info[r][col];
     const Nb nb = neighbours(r, col, f, k & 1);
-    const Frame fr = owner_frame(g, bw, k, c, rowR[r]);
+    const Frame fr = owner_frame(g, bw, k, c, L.rowR[r]);
+    const uint32_t ri = d.oinfo[(int64_t)k * g.NI + c] & kNoRec;
     SlowRec R;
-    if (q < kRec) {
-      R = rec[q];
+    if (ri != kNoRec) {
+      R = sh.rec[ri];
     } else {
       Slow sr;
       slow_classify(g, fr, sr);
       R = pack_slow(sr);
     }
-    emit_slow(g, fr, R, nb, tb[r] + toff[r][col], out);
+    emit_slow(g, fr, R, nb, L.tb[r] + L.toff[r][col], out);
   }
 }
 
-__global__ void k_sizes(const long long* __restrict__ tot, int64_t vcap, int64_t tcap, int64_t* __restrict__ out) {
-  if (threadIdx.x == 0) {
-    out[0] = tot[0];
-    out[1] = tot[1];
-    out[2] = tot[2];
-    out[3] = tot[3] ? SBMT_E_PROTOCOL : ((tot[0] > vcap || tot[1] > tcap) ? SBMT_E_CAPACITY : SBMT_OK);
+template <class Src, int RB>
+__global__ void __launch_bounds__(kThreads) k_emit(Src src, const int64_t* __restrict__ tab, Shared sh) {
+  __shared__ EmitLds<RB> L;
+  int64_t local;
+  const int ii = src.find(blockIdx.x, tab, local);
+  const Img& d = src.img(ii);
+  const Geo g = d.g;
+  long long nv, nt, nc;
+  image_totals<Src>(d, sh, nv, nt, nc);
+  if (image_status(d, sh.imgerr[ii], nv, nt) != SBMT_OK) return;  // uniform per block
+  const int cb = (int)(local % g.NCB), ky = (int)(local / g.NCB);
+  const int64_t nsegi = (int64_t)g.NK * g.NCB;
+  const longlong4 base = sh.seg_off[d.seg0];
+  if (threadIdx.x <= RB) {
+    const int k = ky * RB + threadIdx.x;
+    const longlong4 o = sh.seg_off[d.seg0 + (k < g.NK ? (int64_t)k * g.NCB + cb : nsegi)];
+    L.bv[threadIdx.x] = (int)(o.x - base.x);
+    if (threadIdx.x < RB) L.tb[threadIdx.x] = o.y - base.y;
+  }
+  const int kh = min(ky * RB + RB, g.NK - 1);
+  emit_tile<RB>(d, g, ky, cb, sh, L, d.oinfo + (int64_t)kh * g.NI);
+}
+
+// ---------------------------------------------------------------------------
+// Fused persistent path.  A workgroup repeatedly takes the next band (RB
+// full-width rows of one image) in ticket order and
+//   1. counts its row segments and those of the halo row below it, queueing
+//      slow owners in the record list (the halo row's info goes to a per-band
+//      row of scratch instead of oinfo);
+//   2. classifies the band's slow owners densely, adding their counts;
+//   3. publishes the band's (n_v, n_t) and finds its offsets by a decoupled
+//      look-back over the bands of the same image: earlier tickets only, which
+//      are running or done and publish without waiting, so every wait ends;
+//   4. emits its tiles left to right with the per-row segment bases.
+// Bands that would not fit the output capacity skip their writes; the last
+// band of an image writes the image's sizes and status.
+// ---------------------------------------------------------------------------
+constexpr unsigned long long kLbAgg = 1ull << 62, kLbIncl = 2ull << 62;
+SBMT_HD unsigned long long lb_word(unsigned long long flag, long long v, long long t) {
+  return flag | ((unsigned long long)t << 31) | (unsigned long long)v;
+}
+
+template <int RB>
+struct FusedLds {
+  union {
+    CountLds<RB + 1> c;
+    EmitLds<RB> e;
+  } u;
+  int2 cnt[kMaxBandChunks][RB + 1];  // per chunk and row: (nv, nt); later the image-local bases
+  unsigned long long cbase[kMaxBandChunks];
+  int cn[kMaxBandChunks + 1];        // slow owners queued per chunk, then their prefix
+  long long ticket;
+  long long pv, pt;                  // band prefix (vertices, triangles)
+  int ncut, err;
+};
+
+template <int RB>
+__global__ void __launch_bounds__(kThreads) k_fused(ManySrc src, const int64_t* __restrict__ tab, Shared sh,
+                                                    int64_t nbands, uint32_t* __restrict__ halo) {
+  __shared__ FusedLds<RB> F;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) F.ticket = (long long)atomicAdd(&sh.ctr[1], 1ull);
+    __syncthreads();
+    const long long t = F.ticket;
+    if (t >= nbands) break;
+    int64_t j;
+    const int ii = src.find(t, tab, j);
+    const Img& d = src.img(ii);
+    const Geo g = d.g;
+    const int nb = (g.NK + RB - 1) / RB;
+    const int k0 = (int)j * RB;
+    uint32_t* hrow = halo + d.halo0 + j * (int64_t)g.NI;
+    // 1. counts of rows k0 .. k0+RB (the last one is the halo row)
+    if (threadIdx.x == 0) F.ncut = F.err = 0;
+    for (int cb = 0; cb < g.NCB; ++cb) {
+      __syncthreads();
+      CountLds<RB + 1>& C = F.u.c;
+      const int c0 = cb * kCB;
+      if (threadIdx.x <= RB) {
+        C.rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);
+        C.acc[threadIdx.x][0] = C.acc[threadIdx.x][1] = 0;
+      }
+      if (threadIdx.x == 0) C.n1 = C.n2 = 0;
+      __syncthreads();
+      const int klast = min(k0 + RB + 1, g.NK) - 1;
+      const Bits bw = stage_window(g, d.bits, C.win, C.rowR[0] + kRing, C.rowR[klast - k0] + 2 + kRing, c0,
+                                   min(c0 + kCB, g.NI) - 1);
+      __syncthreads();
+      const int lane = threadIdx.x & 63;
+      for (int r = 0; r <= RB; ++r) {
+        const int k = k0 + r;
+        if (k >= g.NK) break;
+        int nv = 0, nt = 0;
+        const int c = c0 + threadIdx.x;
+        if (c < g.NI) {
+          const Frame f = owner_frame(g, bw, k, c, C.rowR[r]);
+          if (frame_uniform(f)) {
+            const uint32_t fi = fast_info(g, f);
+            nv = info_nv(fi);
+            nt = info_nt(fi);
+          } else {
+            C.q1[atomicAdd(&C.n1, 1)] = (uint16_t)(r * kCB + threadIdx.x);
+          }
+        }
+        nv = wave_sum(nv);
+        nt = wave_sum(nt);
+        if (lane == 0 && (nv | nt)) {
+          atomicAdd(&C.acc[r][0], nv);
+          atomicAdd(&C.acc[r][1], nt);
+        }
+      }
+      __syncthreads();
+      for (int q = threadIdx.x; q < C.n1; q += kThreads) {
+        const int e = C.q1[q], r = e / kCB, c = c0 + (e - r * kCB);
+        const int k = k0 + r;
+        const Frame f = owner_frame(g, bw, k, c, C.rowR[r]);
+        uint32_t fi = 0;
+        if (needs_slow(g, f, fi)) {
+          C.q2[atomicAdd(&C.n2, 1)] = (uint16_t)e;
+        } else {
+          if (r < RB) d.oinfo[(int64_t)k * g.NI + c] = fi;
+          else hrow[c] = fi;
+          atomicAdd(&C.acc[r][0], info_nv(fi));
+          atomicAdd(&C.acc[r][1], info_nt(fi));
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        C.base = C.n2 ? atomicAdd(&sh.ctr[0], (unsigned long long)C.n2) : 0ull;
+        F.cbase[cb] = C.base;
+        F.cn[cb] = C.n2;
+      }
+      __syncthreads();
+      for (int q = threadIdx.x; q < C.n2; q += kThreads) {
+        const int e = C.q2[q], r = e / kCB, c = c0 + (e - r * kCB);
+        const int k = k0 + r;
+        const unsigned long long idx = C.base + (unsigned long long)q;
+        if (idx < (unsigned long long)sh.rcap) {
+          sh.rec[idx].x = (uint64_t)c | ((uint64_t)k << 24) | ((uint64_t)ii << 48);
+          if (r < RB) d.oinfo[(int64_t)k * g.NI + c] = kSlowBit | (uint32_t)idx;
+        } else {
+          const Frame f = owner_frame(g, bw, k, c, C.rowR[r]);
+          Slow sr;
+          slow_classify(g, f, sr);
+          if (r < RB) d.oinfo[(int64_t)k * g.NI + c] = kSlowBit | kNoRec;
+          else hrow[c] = sr.info & ~kSlowBit;
+          atomicAdd(&C.acc[r][0], info_nv(sr.info));
+          atomicAdd(&C.acc[r][1], info_nt(sr.info));
+          if (r < RB) atomicAdd(&F.ncut, info_ncut(sr.info));
+          if (info_err(sr.info)) F.err = 1;
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x <= RB) F.cnt[cb][threadIdx.x] = make_int2(C.acc[threadIdx.x][0], C.acc[threadIdx.x][1]);
+    }
+    __syncthreads();
+    // 2. the band's slow owners with records, densely
+    if (threadIdx.x == 0) {
+      int s = 0;
+      for (int cb = 0; cb < g.NCB; ++cb) {
+        const long long room = sh.rcap - (long long)F.cbase[cb];
+        const int n = (int)max(0ll, min((long long)F.cn[cb], room));
+        F.cn[cb] = s;
+        s += n;
+      }
+      F.cn[g.NCB] = s;
+    }
+    __syncthreads();
+    const int nslow = F.cn[g.NCB];
+    for (int q = threadIdx.x; q < nslow; q += kThreads) {
+      int lo = 0, hi = g.NCB - 1;  // chunk: largest cb with cn[cb] <= q
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (F.cn[mid] <= q) lo = mid;
+        else hi = mid - 1;
+      }
+      const unsigned long long idx = F.cbase[lo] + (unsigned long long)(q - F.cn[lo]);
+      const uint64_t p = sh.rec[idx].x;
+      const int k = (int)((p >> 24) & 0xffffffu), c = (int)(p & 0xffffffu);
+      const int r = k - k0;
+      Bits b;
+      b.p = d.bits;
+      b.wpr = g.wpr;
+      b.rr0 = 0;
+      b.cc0 = 0;
+      const Frame f = owner_frame(g, b, k, c, row_cell(k, g.h, g.s));
+      Slow sr;
+      slow_classify(g, f, sr);
+      if (r < RB) sh.rec[idx] = pack_slow(sr);
+      else hrow[c] = sr.info & ~kSlowBit;
+      atomicAdd(&F.cnt[lo][r].x, info_nv(sr.info));
+      atomicAdd(&F.cnt[lo][r].y, info_nt(sr.info));
+      if (r < RB) atomicAdd(&F.ncut, info_ncut(sr.info));
+      if (info_err(sr.info)) F.err = 1;
+    }
+    __syncthreads();
+    // 3. band totals, look-back, per-row segment bases
+    if (threadIdx.x == 0) {
+      long long av = 0, at = 0;
+      for (int cb = 0; cb < g.NCB; ++cb)
+        for (int r = 0; r < RB; ++r) {
+          av += F.cnt[cb][r].x;
+          at += F.cnt[cb][r].y;
+        }
+      if (F.err) atomicOr(&sh.imgerr[ii], 1);
+      if (F.ncut) atomicAdd((unsigned long long*)&sh.sizes[4 * (int64_t)ii + 2], (unsigned long long)F.ncut);
+      unsigned long long* w = sh.band + d.band0 + j;
+      long long pv = 0, pt = 0;
+      if (j == 0) {
+        __hip_atomic_store(w, lb_word(kLbIncl, av, at), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        __hip_atomic_store(w, lb_word(kLbAgg, av, at), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        for (int64_t p = j - 1; p >= 0; --p) {
+          unsigned long long x;
+          for (;;) {
+            x = __hip_atomic_load(sh.band + d.band0 + p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            if (x >> 62) break;
+            __builtin_amdgcn_s_sleep(2);
+          }
+          pv += (long long)(x & 0x7fffffffull);
+          pt += (long long)((x >> 31) & 0x7fffffffull);
+          if ((x >> 62) == 2ull) break;
+        }
+        __hip_atomic_store(w, lb_word(kLbIncl, pv + av, pt + at), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      F.pv = pv;
+      F.pt = pt;
+      // rows of the band in order, chunks in order within a row; the halo row
+      // starts where the band ends
+      long long v = pv, tt = pt;
+      for (int r = 0; r < RB; ++r)
+        for (int cb = 0; cb < g.NCB; ++cb) {
+          const int2 x = F.cnt[cb][r];
+          F.cnt[cb][r] = make_int2((int)v, (int)tt);
+          v += x.x;
+          tt += x.y;
+        }
+      F.cnt[0][RB].x = (int)v;  // first vertex of the halo row's first segment
+      if (j == nb - 1) {
+        // last band of the image: its end is the image total
+        const int st = (int)image_status(d, atomicOr(&sh.imgerr[ii], 0), v, tt);
+        sh.sizes[4 * (int64_t)ii + 0] = v;
+        sh.sizes[4 * (int64_t)ii + 1] = tt;
+        sh.sizes[4 * (int64_t)ii + 3] = st;
+      }
+      // write only if the band's vertex and triangle ranges fit
+      F.err = (v > d.vcap || tt > d.tcap || v > 0x7fffffffLL || atomicOr(&sh.imgerr[ii], 0)) ? 1 : 0;
+    }
+    __syncthreads();
+    if (F.err) continue;
+    // 4. emission, tiles left to right; the halo row's bases follow the row
+    int hv = F.cnt[0][RB].x;
+    for (int cb = 0; cb < g.NCB; ++cb) {
+      EmitLds<RB>& E = F.u.e;
+      __syncthreads();
+      if (threadIdx.x < RB) {
+        E.bv[threadIdx.x] = F.cnt[cb][threadIdx.x].x;
+        E.tb[threadIdx.x] = F.cnt[cb][threadIdx.x].y;
+      }
+      if (threadIdx.x == RB) E.bv[RB] = hv;
+      emit_tile<RB>(d, g, (int)j, cb, sh, E, hrow);
+      __syncthreads();
+      hv += E.rowv[RB];
+    }
   }
 }
 
@@ -519,10 +985,12 @@ static int64_t host_row_cell(int64_t k, int h, int s) {
   while (host_z3sign(-(2 * s * (R + 1) + s + 1), kh) >= 0) ++R;
   return R;
 }
+
+constexpr int kMaxTileRows = 16;  // largest RB instantiated
 static bool tile_window_fits(const Geo& g) {
-  // rows: the cell rows of kRB + 1 grid rows plus the 3x3 window; words: the
-  // cell columns of kCB + 2 owners plus the window and one spare word
-  const double rows = ((kRB + 1) * g.h * 0.8660254037844386) / g.s + 5;
+  // rows: the cell rows of kMaxTileRows + 1 grid rows plus the 3x3 window;
+  // words: the cell columns of kCB + 2 owners plus the window and one spare word
+  const double rows = ((kMaxTileRows + 1) * g.h * 0.8660254037844386) / g.s + 5;
   const double words = ((kCB + 2) * (double)g.h / g.s + 4) / 32.0 + 3;
   return rows <= kWinRows && words <= kWinWords;
 }
@@ -537,14 +1005,7 @@ static bool windows_in_bounds(const Geo& g) {
          ((clo_max + 2 + kRingC) >> 5) + 1 < g.wpr;
 }
 
-struct Layout {
-  Geo g;
-  int64_t nseg;
-  int nblk;
-  size_t off_bits, off_cnt, off_segoff, off_blk, off_tot, total;
-};
-
-static sbmt_status make_layout(const sbmt_image* img, Layout* L, bool need_ptr = true) {
+static sbmt_status make_geo(const sbmt_image* img, Geo* out, bool need_ptr) {
   if (!img) return SBMT_E_INVALID_ARG;
   if (img->width < 0 || img->height < 0) return SBMT_E_INVALID_ARG;
   if ((int64_t)img->width > (1 << 20) || (int64_t)img->height > (1 << 20)) return SBMT_E_INVALID_ARG;
@@ -552,7 +1013,7 @@ static sbmt_status make_layout(const sbmt_image* img, Layout* L, bool need_ptr =
     return SBMT_E_INVALID_ARG;
   if (img->flags & ~1u) return SBMT_E_INVALID_ARG;
   if (!grid_h_supported(img->grid_h)) return SBMT_E_UNSUPPORTED_GRID_H;
-  Geo& g = L->g;
+  Geo g;
   g.W = img->width;
   g.H = img->height;
   g.stride = img->row_stride;
@@ -574,54 +1035,191 @@ static sbmt_status make_layout(const sbmt_image* img, Layout* L, bool need_ptr =
   g.flags = img->flags;
   g.inv4s = 1.0f / (float)(4 * g.s);
   if (!windows_in_bounds(g) || !tile_window_fits(g)) return SBMT_E_INVALID_ARG;
-  L->nseg = (int64_t)g.NK * g.NCB;
-  L->nblk = (int)((L->nseg + kScanChunk - 1) / kScanChunk);
-  size_t off = 0;
-  L->off_bits = off;
-  off = align256(off + (size_t)(g.CH + 2 * kRing) * g.wpr * 4);
-  L->off_cnt = off;
-  off = align256(off + (size_t)L->nseg * sizeof(int4));
-  L->off_segoff = off;
-  off = align256(off + (size_t)L->nseg * sizeof(longlong2));
-  L->off_blk = off;
-  off = align256(off + (size_t)L->nblk * sizeof(longlong4));
-  L->off_tot = off;
-  off = align256(off + 8 * sizeof(long long));
-  L->total = off;
+  // owner positions in record lists: 24 bits per coordinate
+  if (g.NK >= (1 << 24) || g.NI >= (1 << 24)) return SBMT_E_INVALID_ARG;
+  *out = g;
   return SBMT_OK;
 }
 
-static Work work_of(const Layout& L, void* ws) {
+static int rb_index(int rb) { return rb == 4 ? 0 : (rb == 8 ? 1 : (rb == 16 ? 2 : -1)); }
+static const int kRBs[3] = {4, 8, 16};
+
+// Workspace of a call on n images: shared scratch, then per-image regions.
+struct CallLayout {
+  int n = 0;
+  std::vector<Geo> g;
+  std::vector<size_t> off_bits, off_oinfo;
+  std::vector<int64_t> seg0, band0, halo0;  // band0, halo0 for the smallest fused band height
+  std::vector<int64_t> tab;           // [1 + 3 + 3][n + 1]: coarsen blocks, tiles per RB, bands per RB
+  int64_t nseg = 0, owners = 0, rcap = 0, nbands_max = 0, halo_words = 0;
+  int nblk = 0;
+  size_t off_ctr, off_imgerr, off_sizes, off_desc, off_tab, off_cnt, off_slow, off_segoff, off_blk, off_rec,
+      off_band, off_halo, total;
+  bool fused_ok = true;  // per-image counts fit the fused path's int32 bases and band width
+};
+
+static int64_t* tab_row(CallLayout& L, int which) { return L.tab.data() + (size_t)which * (L.n + 1); }
+
+static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t record_cap, bool need_ptr,
+                                    CallLayout* out) {
+  if (n < 1 || n > 65535 || !imgs) return SBMT_E_INVALID_ARG;
+  CallLayout& L = *out;
+  L.n = n;
+  L.g.resize(n);
+  L.off_bits.resize(n);
+  L.off_oinfo.resize(n);
+  L.seg0.resize(n);
+  L.band0.resize(n);
+  L.halo0.resize(n);
+  L.tab.assign((size_t)7 * (n + 1), 0);
+  for (int i = 0; i < n; ++i) {
+    sbmt_status st = make_geo(&imgs[i], &L.g[i], need_ptr);
+    if (st != SBMT_OK) return st;
+  }
+  for (int i = 0; i < n; ++i) {
+    const Geo& g = L.g[i];
+    L.seg0[i] = L.nseg;
+    L.nseg += (int64_t)g.NK * g.NCB;
+    L.owners += (int64_t)g.NK * g.NI;
+    const int64_t cblk = (int64_t)((32 * g.wpr + 255) / 256) * (g.CH + 2 * kRing);
+    tab_row(L, 0)[i + 1] = tab_row(L, 0)[i] + cblk;
+    for (int r = 0; r < 3; ++r) {
+      const int64_t rows = (g.NK + kRBs[r] - 1) / kRBs[r];
+      tab_row(L, 1 + r)[i + 1] = tab_row(L, 1 + r)[i] + rows * g.NCB;
+      tab_row(L, 4 + r)[i + 1] = tab_row(L, 4 + r)[i] + rows;
+    }
+    L.band0[i] = tab_row(L, 4)[i];
+    L.halo0[i] = L.halo_words;
+    L.halo_words += (int64_t)((g.NK + 3) / 4) * g.NI;
+    // a band's counts are kept as int32 image-local offsets: 10 triangles per
+    // owner bound the image's triangles
+    if (g.NCB > kMaxBandChunks || 10LL * g.NK * g.NI > 0x7fffffffLL) L.fused_ok = false;
+  }
+  L.nbands_max = tab_row(L, 4)[n];
+  L.rcap = record_cap > 0 ? record_cap : (record_cap == 0 ? L.owners / 4 + 1024 : 0);
+  if (L.rcap >= (int64_t)kNoRec) L.rcap = (int64_t)kNoRec - 1;
+  L.nblk = (int)((L.nseg + kScanChunk - 1) / kScanChunk);
+  size_t off = 0;
+  L.off_ctr = off;
+  off = align256(off + 8 * sizeof(unsigned long long));
+  L.off_imgerr = off;
+  off = align256(off + (size_t)n * sizeof(int));
+  L.off_sizes = off;
+  off = align256(off + (size_t)n * 4 * sizeof(int64_t));
+  L.off_desc = off;
+  off = align256(off + (size_t)n * sizeof(Img));
+  L.off_tab = off;
+  off = align256(off + L.tab.size() * sizeof(int64_t));
+  L.off_cnt = off;
+  off = align256(off + (size_t)L.nseg * sizeof(int4));
+  L.off_slow = off;
+  off = align256(off + (size_t)L.nseg * sizeof(unsigned long long));
+  L.off_segoff = off;
+  off = align256(off + (size_t)(L.nseg + 1) * sizeof(longlong4));
+  L.off_blk = off;
+  off = align256(off + (size_t)L.nblk * sizeof(longlong4));
+  L.off_rec = off;
+  off = align256(off + (size_t)L.rcap * sizeof(SlowRec));
+  L.off_band = off;
+  off = align256(off + (size_t)L.nbands_max * sizeof(unsigned long long));
+  L.off_halo = off;
+  off = align256(off + (size_t)L.halo_words * sizeof(uint32_t));
+  for (int i = 0; i < n; ++i) {
+    const Geo& g = L.g[i];
+    L.off_bits[i] = off;
+    off = align256(off + (size_t)(g.CH + 2 * kRing) * g.wpr * 4);
+    L.off_oinfo[i] = off;
+    off = align256(off + (size_t)g.NK * g.NI * 4);
+  }
+  L.total = off;
+  return SBMT_OK;
+}
+
+static Shared shared_of(const CallLayout& L, void* ws) {
   char* b = (char*)ws;
-  Work w;
-  w.bits = (uint32_t*)(b + L.off_bits);
-  w.seg_cnt = (int4*)(b + L.off_cnt);
-  w.seg_off = (longlong2*)(b + L.off_segoff);
-  w.blk = (longlong4*)(b + L.off_blk);
-  w.tot = (long long*)(b + L.off_tot);
-  return w;
+  Shared s;
+  s.seg_cnt = (int4*)(b + L.off_cnt);
+  s.seg_slow = (unsigned long long*)(b + L.off_slow);
+  s.seg_off = (longlong4*)(b + L.off_segoff);
+  s.blk = (longlong4*)(b + L.off_blk);
+  s.ctr = (unsigned long long*)(b + L.off_ctr);
+  s.imgerr = (int*)(b + L.off_imgerr);
+  s.sizes = (int64_t*)(b + L.off_sizes);
+  s.rec = (SlowRec*)(b + L.off_rec);
+  s.band = (unsigned long long*)(b + L.off_band);
+  s.rcap = L.rcap;
+  s.nseg = L.nseg;
+  s.nbands = L.nbands_max;
+  s.nblk = L.nblk;
+  s.n = L.n;
+  return s;
 }
 
-static sbmt_status launch_plan(const Layout& L, const sbmt_image* img, const Work& w, hipStream_t st) {
-  const Geo& g = L.g;
-  dim3 gc((32 * g.wpr + 255) / 256, g.CH + 2 * kRing);
-  hipLaunchKernelGGL(k_coarsen, gc, dim3(256), 0, st, g, img->bitmap, w.bits, w.tot);
-  dim3 gk(g.NCB, (g.NK + kRB - 1) / kRB);
-  hipLaunchKernelGGL(k_count, gk, dim3(kThreads), 0, st, g, (const uint32_t*)w.bits, w.seg_cnt, w.tot);
-  hipLaunchKernelGGL(k_scan_reduce, dim3(L.nblk), dim3(kScanThreads), 0, st, (const int4*)w.seg_cnt, L.nseg, w.blk);
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, st, w.blk, L.nblk, w.tot);
-  hipLaunchKernelGGL(k_scan_apply, dim3(L.nblk), dim3(kScanThreads), 0, st, (const int4*)w.seg_cnt, L.nseg,
-                     (const longlong4*)w.blk, w.seg_off);
+static Img img_of(const CallLayout& L, int i, const sbmt_image& im, void* ws, const sbmt_outputs* o) {
+  char* b = (char*)ws;
+  Img d;
+  memset(&d, 0, sizeof(d));
+  d.g = L.g[i];
+  d.bm = im.bitmap;
+  d.bits = (uint32_t*)(b + L.off_bits[i]);
+  d.oinfo = (uint32_t*)(b + L.off_oinfo[i]);
+  d.seg0 = L.seg0[i];
+  d.band0 = L.band0[i];
+  d.halo0 = L.halo0[i];
+  if (o) {
+    d.verts = o->verts;
+    d.tris = o->tris;
+    d.codes = o->codes;
+    d.vcap = o->vert_cap;
+    d.tcap = o->tri_cap;
+  }
+  return d;
+}
+
+template <class Src>
+static sbmt_status launch_front(const CallLayout& L, const Src& src, const int64_t* dtab, const Shared& sh, int rbi,
+                                hipStream_t st) {
+  const int64_t* t0 = dtab;
+  const int64_t* tt = dtab ? dtab + (size_t)(1 + rbi) * (L.n + 1) : nullptr;
+  const int64_t ncb = L.tab[(size_t)0 * (L.n + 1) + L.n];
+  const int64_t ntile = L.tab[(size_t)(1 + rbi) * (L.n + 1) + L.n];
+  if (ncb > 0x7fffffffLL || ntile > 0x7fffffffLL) return SBMT_E_INVALID_ARG;
+  hipLaunchKernelGGL(k_coarsen<Src>, dim3((unsigned)ncb), dim3(256), 0, st, src, t0, sh);
+  switch (kRBs[rbi]) {
+    case 4: hipLaunchKernelGGL((k_count<Src, 4>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh); break;
+    case 8: hipLaunchKernelGGL((k_count<Src, 8>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh); break;
+    default: hipLaunchKernelGGL((k_count<Src, 16>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh); break;
+  }
+  hipLaunchKernelGGL(k_slow<Src>, dim3(2048), dim3(256), 0, st, src, sh);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(L.nblk), dim3(kScanThreads), 0, st, sh);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, st, sh);
+  hipLaunchKernelGGL(k_scan_apply, dim3(L.nblk), dim3(kScanThreads), 0, st, sh);
   return hipGetLastError() == hipSuccess ? SBMT_OK : SBMT_E_DEVICE;
 }
 
-static sbmt_status launch_emit(const Layout& L, const Work& w, int64_t vcap, int64_t tcap, double* verts,
-                               int32_t* tris, uint8_t* codes, hipStream_t st) {
-  const Geo& g = L.g;
-  dim3 gk(g.NCB, (g.NK + kRB - 1) / kRB);
-  hipLaunchKernelGGL(k_emit, gk, dim3(kThreads), 0, st, g, (const uint32_t*)w.bits, (const longlong2*)w.seg_off,
-                     (const long long*)w.tot, vcap, tcap, verts, tris, codes);
+template <class Src>
+static sbmt_status launch_sizes(const CallLayout& L, const Src& src, const Shared& sh, int64_t* user, hipStream_t st) {
+  hipLaunchKernelGGL(k_sizes<Src>, dim3((L.n + 255) / 256), dim3(256), 0, st, src, sh, user);
   return hipGetLastError() == hipSuccess ? SBMT_OK : SBMT_E_DEVICE;
+}
+
+template <class Src>
+static sbmt_status launch_emit(const CallLayout& L, const Src& src, const int64_t* dtab, const Shared& sh, int rbi,
+                               hipStream_t st) {
+  const int64_t* tt = dtab ? dtab + (size_t)(1 + rbi) * (L.n + 1) : nullptr;
+  const int64_t ntile = L.tab[(size_t)(1 + rbi) * (L.n + 1) + L.n];
+  if (ntile > 0x7fffffffLL) return SBMT_E_INVALID_ARG;
+  switch (kRBs[rbi]) {
+    case 4: hipLaunchKernelGGL((k_emit<Src, 4>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh); break;
+    case 8: hipLaunchKernelGGL((k_emit<Src, 8>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh); break;
+    default: hipLaunchKernelGGL((k_emit<Src, 16>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh); break;
+  }
+  return hipGetLastError() == hipSuccess ? SBMT_OK : SBMT_E_DEVICE;
+}
+
+__global__ void k_copy_sizes(const int64_t* __restrict__ s, int64_t n4, int64_t* __restrict__ user) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n4) user[q] = s[q];
 }
 
 }  // namespace sbmt
@@ -630,8 +1228,39 @@ using namespace sbmt;
 
 struct sbmt_context {
   int device;
+  int cus;
   long long* pinned;  // 8 x int64
 };
+
+struct sbmt_batch_s {
+  sbmt_context* ctx;
+  std::vector<sbmt_image> imgs;
+  CallLayout L;
+  sbmt_tuning tune;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  unsigned char* stage = nullptr;  // pinned: descriptors + tables
+  size_t stage_bytes = 0;
+  int64_t* psizes = nullptr;       // pinned: n x 4
+};
+
+static bool tuning_valid(const sbmt_tuning* t) {
+  if (t->strategy != SBMT_STRATEGY_MULTI && t->strategy != SBMT_STRATEGY_FUSED) return false;
+  if (rb_index(t->tile_rows) < 0) return false;
+  if (t->strategy == SBMT_STRATEGY_FUSED && t->tile_rows == 16) return false;
+  if (t->groups_per_cu < 0 || t->groups_per_cu > 16) return false;
+  return true;
+}
+
+static sbmt_tuning default_tuning() {
+  sbmt_tuning t;
+  memset(&t, 0, sizeof(t));
+  t.strategy = SBMT_STRATEGY_MULTI;
+  t.tile_rows = 8;
+  t.groups_per_cu = 0;
+  t.record_cap = 0;
+  return t;
+}
 
 extern "C" {
 
@@ -643,6 +1272,8 @@ sbmt_status sbmt_create(int device, sbmt_handle* out) {
   sbmt_context* c = (sbmt_context*)calloc(1, sizeof(sbmt_context));
   if (!c) return SBMT_E_DEVICE;
   c->device = device;
+  if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->cus < 1)
+    c->cus = 256;
   if (hipHostMalloc((void**)&c->pinned, 8 * sizeof(long long), hipHostMallocDefault) != hipSuccess) {
     free(c);
     return SBMT_E_DEVICE;
@@ -659,34 +1290,43 @@ sbmt_status sbmt_destroy(sbmt_handle h) {
 }
 
 sbmt_status sbmt_query(const sbmt_image* img, sbmt_layout* out) {
-  Layout L;
-  sbmt_status st = make_layout(img, &L, false);
+  CallLayout L;
+  sbmt_status st = make_call_layout(img, 1, 0, false, &L);
   if (st != SBMT_OK) return st;
   if (out) {
-    out->stride_s = L.g.s;
-    out->coarse_w = L.g.CW;
-    out->coarse_h = L.g.CH;
-    out->grid_rows = L.g.NK;
-    out->grid_cols = L.g.NI;
+    out->stride_s = L.g[0].s;
+    out->coarse_w = L.g[0].CW;
+    out->coarse_h = L.g[0].CH;
+    out->grid_rows = L.g[0].NK;
+    out->grid_cols = L.g[0].NI;
     out->workspace_bytes = L.total;
   }
+  return SBMT_OK;
+}
+
+static sbmt_status single_prepare(const sbmt_image* img, void* workspace, size_t ws_bytes, CallLayout* L) {
+  sbmt_status st = make_call_layout(img, 1, 0, true, L);
+  if (st != SBMT_OK) return st;
+  if (!workspace || ws_bytes < L->total) return SBMT_E_WORKSPACE;
   return SBMT_OK;
 }
 
 sbmt_status sbmt_plan(sbmt_handle h, const sbmt_image* img, void* workspace, size_t ws_bytes, sbmt_sizes* out,
                       void* stream) {
   if (!h || !out) return SBMT_E_INVALID_ARG;
-  Layout L;
-  sbmt_status st = make_layout(img, &L);
+  CallLayout L;
+  sbmt_status st = single_prepare(img, workspace, ws_bytes, &L);
   if (st != SBMT_OK) return st;
-  if (!workspace || ws_bytes < L.total) return SBMT_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  Work w = work_of(L, workspace);
-  if ((st = launch_plan(L, img, w, s)) != SBMT_OK) return st;
-  if (hipMemcpyAsync(h->pinned, w.tot, 4 * sizeof(long long), hipMemcpyDeviceToHost, s) != hipSuccess)
+  const Shared sh = shared_of(L, workspace);
+  OneSrc src;
+  src.d = img_of(L, 0, *img, workspace, nullptr);
+  if ((st = launch_front(L, src, nullptr, sh, 1, s)) != SBMT_OK) return st;
+  if ((st = launch_sizes(L, src, sh, nullptr, s)) != SBMT_OK) return st;
+  if (hipMemcpyAsync(h->pinned, sh.sizes, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess)
     return SBMT_E_DEVICE;
   if (hipStreamSynchronize(s) != hipSuccess) return SBMT_E_DEVICE;
-  if (h->pinned[3]) return SBMT_E_PROTOCOL;
+  if (h->pinned[3] == SBMT_E_PROTOCOL) return SBMT_E_PROTOCOL;
   out->n_vertices = h->pinned[0];
   out->n_triangles = h->pinned[1];
   out->n_cut = h->pinned[2];
@@ -697,31 +1337,283 @@ sbmt_status sbmt_plan(sbmt_handle h, const sbmt_image* img, void* workspace, siz
 sbmt_status sbmt_run(sbmt_handle h, const sbmt_image* img, void* workspace, size_t ws_bytes, double* verts,
                      int32_t* tris, uint8_t* codes, void* stream) {
   if (!h) return SBMT_E_INVALID_ARG;
-  Layout L;
-  sbmt_status st = make_layout(img, &L);
+  CallLayout L;
+  sbmt_status st = single_prepare(img, workspace, ws_bytes, &L);
   if (st != SBMT_OK) return st;
-  if (!workspace || ws_bytes < L.total) return SBMT_E_WORKSPACE;
-  Work w = work_of(L, workspace);
+  const Shared sh = shared_of(L, workspace);
   // the plan's totals bound every write; capacities are the totals themselves
-  const int64_t cap = INT64_MAX;
-  return launch_emit(L, w, cap, cap, verts, tris, codes, (hipStream_t)stream);
+  sbmt_outputs o;
+  o.verts = verts;
+  o.tris = tris;
+  o.codes = codes;
+  o.vert_cap = INT64_MAX;
+  o.tri_cap = INT64_MAX;
+  OneSrc src;
+  src.d = img_of(L, 0, *img, workspace, &o);
+  return launch_emit(L, src, nullptr, sh, 1, (hipStream_t)stream);
 }
 
 sbmt_status sbmt_mesh_async(sbmt_handle h, const sbmt_image* img, void* workspace, size_t ws_bytes, double* verts,
                             int64_t vert_cap, int32_t* tris, uint8_t* codes, int64_t tri_cap, int64_t* sizes_dev,
                             void* stream) {
   if (!h || !sizes_dev || vert_cap < 0 || tri_cap < 0) return SBMT_E_INVALID_ARG;
-  if (vert_cap > 0x7fffffffLL) vert_cap = 0x7fffffffLL;
-  Layout L;
-  sbmt_status st = make_layout(img, &L);
+  CallLayout L;
+  sbmt_status st = single_prepare(img, workspace, ws_bytes, &L);
   if (st != SBMT_OK) return st;
-  if (!workspace || ws_bytes < L.total) return SBMT_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  Work w = work_of(L, workspace);
-  if ((st = launch_plan(L, img, w, s)) != SBMT_OK) return st;
-  if ((st = launch_emit(L, w, vert_cap, tri_cap, verts, tris, codes, s)) != SBMT_OK) return st;
-  hipLaunchKernelGGL(k_sizes, dim3(1), dim3(64), 0, s, (const long long*)w.tot, vert_cap, tri_cap, sizes_dev);
+  const Shared sh = shared_of(L, workspace);
+  sbmt_outputs o;
+  o.verts = verts;
+  o.tris = tris;
+  o.codes = codes;
+  o.vert_cap = vert_cap;
+  o.tri_cap = tri_cap;
+  OneSrc src;
+  src.d = img_of(L, 0, *img, workspace, &o);
+  if ((st = launch_front(L, src, nullptr, sh, 1, s)) != SBMT_OK) return st;
+  if ((st = launch_emit(L, src, nullptr, sh, 1, s)) != SBMT_OK) return st;
+  return launch_sizes(L, src, sh, sizes_dev, s);
+}
+
+// ---------------------------------------------------------------------------
+// Batches.
+// ---------------------------------------------------------------------------
+sbmt_status sbmt_batch_create(sbmt_handle h, const sbmt_image* imgs, int32_t n, const sbmt_tuning* tuning,
+                              size_t* ws_bytes, sbmt_batch* out) {
+  if (!h || !out || !imgs || n < 1) return SBMT_E_INVALID_ARG;
+  sbmt_tuning t = tuning ? *tuning : default_tuning();
+  if (!tuning_valid(&t)) return SBMT_E_INVALID_ARG;
+  sbmt_batch_s* b = new (std::nothrow) sbmt_batch_s();
+  if (!b) return SBMT_E_DEVICE;
+  b->ctx = h;
+  b->imgs.assign(imgs, imgs + n);
+  sbmt_status st = make_call_layout(imgs, n, t.record_cap, true, &b->L);
+  if (st != SBMT_OK) {
+    delete b;
+    return st;
+  }
+  if (t.strategy == SBMT_STRATEGY_FUSED && !b->L.fused_ok) t.strategy = SBMT_STRATEGY_MULTI;
+  b->tune = t;
+  b->stage_bytes = b->L.off_cnt - b->L.off_desc;
+  if (hipHostMalloc((void**)&b->stage, b->stage_bytes, hipHostMallocDefault) != hipSuccess) {
+    delete b;
+    return SBMT_E_DEVICE;
+  }
+  if (hipHostMalloc((void**)&b->psizes, (size_t)n * 4 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
+    (void)hipHostFree(b->stage);
+    delete b;
+    return SBMT_E_DEVICE;
+  }
+  if (ws_bytes) *ws_bytes = b->L.total;
+  *out = b;
+  return SBMT_OK;
+}
+
+sbmt_status sbmt_batch_destroy(sbmt_batch b) {
+  if (!b) return SBMT_E_INVALID_ARG;
+  if (b->stage) (void)hipHostFree(b->stage);
+  if (b->psizes) (void)hipHostFree(b->psizes);
+  delete b;
+  return SBMT_OK;
+}
+
+sbmt_status sbmt_batch_bind(sbmt_batch b, void* workspace, size_t ws_bytes, const sbmt_outputs* outs, void* stream) {
+  if (!b) return SBMT_E_INVALID_ARG;
+  if (!workspace || ws_bytes < b->L.total) return SBMT_E_WORKSPACE;
+  if (outs)
+    for (int i = 0; i < b->L.n; ++i)
+      if (outs[i].vert_cap < 0 || outs[i].tri_cap < 0) return SBMT_E_INVALID_ARG;
+  const CallLayout& L = b->L;
+  unsigned char* st = b->stage;
+  memset(st, 0, b->stage_bytes);
+  Img* desc = (Img*)(st + (L.off_desc - L.off_desc));
+  for (int i = 0; i < L.n; ++i) desc[i] = img_of(L, i, b->imgs[i], workspace, outs ? &outs[i] : nullptr);
+  memcpy(st + (L.off_tab - L.off_desc), L.tab.data(), L.tab.size() * sizeof(int64_t));
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync((char*)workspace + L.off_desc, st, b->stage_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+    return SBMT_E_DEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return SBMT_E_DEVICE;
+  b->ws = workspace;
+  b->ws_bytes = ws_bytes;
+  return SBMT_OK;
+}
+
+static ManySrc many_of(const sbmt_batch_s* b) {
+  ManySrc m;
+  m.d = (const Img*)((char*)b->ws + b->L.off_desc);
+  m.n = b->L.n;
+  return m;
+}
+static const int64_t* dtab_of(const sbmt_batch_s* b) { return (const int64_t*)((char*)b->ws + b->L.off_tab); }
+
+sbmt_status sbmt_batch_plan(sbmt_batch b, sbmt_sizes* out, void* stream) {
+  if (!b || !out) return SBMT_E_INVALID_ARG;
+  if (!b->ws) return SBMT_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  const Shared sh = shared_of(b->L, b->ws);
+  const ManySrc src = many_of(b);
+  sbmt_status st = launch_front(b->L, src, dtab_of(b), sh, rb_index(b->tune.tile_rows), s);
+  if (st != SBMT_OK) return st;
+  if ((st = launch_sizes(b->L, src, sh, nullptr, s)) != SBMT_OK) return st;
+  const size_t bytes = (size_t)b->L.n * 4 * sizeof(int64_t);
+  if (hipMemcpyAsync(b->psizes, sh.sizes, bytes, hipMemcpyDeviceToHost, s) != hipSuccess) return SBMT_E_DEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return SBMT_E_DEVICE;
+  sbmt_status worst = SBMT_OK;
+  for (int i = 0; i < b->L.n; ++i) {
+    out[i].n_vertices = b->psizes[4 * i + 0];
+    out[i].n_triangles = b->psizes[4 * i + 1];
+    out[i].n_cut = b->psizes[4 * i + 2];
+    const int64_t sti = b->psizes[4 * i + 3];
+    if (sti == SBMT_E_PROTOCOL) worst = SBMT_E_PROTOCOL;
+    if (sti == SBMT_E_INDEX_OVERFLOW && worst == SBMT_OK) worst = SBMT_E_INDEX_OVERFLOW;
+  }
+  return worst;
+}
+
+sbmt_status sbmt_batch_emit(sbmt_batch b, int64_t* sizes_dev, void* stream) {
+  if (!b) return SBMT_E_INVALID_ARG;
+  if (!b->ws) return SBMT_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  const Shared sh = shared_of(b->L, b->ws);
+  const ManySrc src = many_of(b);
+  sbmt_status st = launch_emit(b->L, src, dtab_of(b), sh, rb_index(b->tune.tile_rows), s);
+  if (st != SBMT_OK) return st;
+  return launch_sizes(b->L, src, sh, sizes_dev, s);
+}
+
+static int fused_groups(const sbmt_batch_s* b) {
+  const int gpc = b->tune.groups_per_cu > 0 ? b->tune.groups_per_cu : (b->tune.tile_rows == 4 ? 6 : 4);
+  const int64_t nb = b->L.tab[(size_t)(4 + rb_index(b->tune.tile_rows)) * (b->L.n + 1) + b->L.n];
+  return (int)std::min<int64_t>(nb, (int64_t)gpc * b->ctx->cus);
+}
+
+sbmt_status sbmt_batch_mesh(sbmt_batch b, int64_t* sizes_dev, void* stream) {
+  if (!b) return SBMT_E_INVALID_ARG;
+  if (!b->ws) return SBMT_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  const CallLayout& L = b->L;
+  const Shared sh = shared_of(L, b->ws);
+  const ManySrc src = many_of(b);
+  const int64_t* dtab = dtab_of(b);
+  const int rbi = rb_index(b->tune.tile_rows);
+  if (b->tune.strategy == SBMT_STRATEGY_MULTI || !L.fused_ok) {
+    sbmt_status st = launch_front(L, src, dtab, sh, rbi, s);
+    if (st != SBMT_OK) return st;
+    if ((st = launch_emit(L, src, dtab, sh, rbi, s)) != SBMT_OK) return st;
+    return launch_sizes(L, src, sh, sizes_dev, s);
+  }
+  const int64_t ncb = L.tab[(size_t)L.n];
+  if (ncb > 0x7fffffffLL) return SBMT_E_INVALID_ARG;
+  hipLaunchKernelGGL(k_coarsen<ManySrc>, dim3((unsigned)ncb), dim3(256), 0, s, src, dtab, sh);
+  const int64_t nbands = L.tab[(size_t)(4 + rbi) * (L.n + 1) + L.n];
+  const int64_t* btab = dtab + (size_t)(4 + rbi) * (L.n + 1);
+  uint32_t* halo = (uint32_t*)((char*)b->ws + L.off_halo);
+  const int grid = fused_groups(b);
+  if (b->tune.tile_rows == 4)
+    hipLaunchKernelGGL((k_fused<4>), dim3(grid), dim3(kThreads), 0, s, src, btab, sh, nbands, halo);
+  else
+    hipLaunchKernelGGL((k_fused<8>), dim3(grid), dim3(kThreads), 0, s, src, btab, sh, nbands, halo);
+  if (sizes_dev) {
+    const int64_t n4 = 4 * (int64_t)L.n;
+    hipLaunchKernelGGL(k_copy_sizes, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, (const int64_t*)sh.sizes,
+                       n4, sizes_dev);
+  }
   return hipGetLastError() == hipSuccess ? SBMT_OK : SBMT_E_DEVICE;
+}
+
+sbmt_status sbmt_batch_sizes(sbmt_batch b, sbmt_sizes* out, int64_t* status, void* stream) {
+  if (!b || !out) return SBMT_E_INVALID_ARG;
+  if (!b->ws) return SBMT_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t bytes = (size_t)b->L.n * 4 * sizeof(int64_t);
+  if (hipMemcpyAsync(b->psizes, (char*)b->ws + b->L.off_sizes, bytes, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return SBMT_E_DEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return SBMT_E_DEVICE;
+  for (int i = 0; i < b->L.n; ++i) {
+    out[i].n_vertices = b->psizes[4 * i + 0];
+    out[i].n_triangles = b->psizes[4 * i + 1];
+    out[i].n_cut = b->psizes[4 * i + 2];
+    if (status) status[i] = b->psizes[4 * i + 3];
+  }
+  return SBMT_OK;
+}
+
+sbmt_status sbmt_batch_get_tuning(sbmt_batch b, sbmt_tuning* out) {
+  if (!b || !out) return SBMT_E_INVALID_ARG;
+  *out = b->tune;
+  return SBMT_OK;
+}
+
+sbmt_status sbmt_batch_set_tuning(sbmt_batch b, const sbmt_tuning* t) {
+  if (!b || !t) return SBMT_E_INVALID_ARG;
+  sbmt_tuning x = *t;
+  if (!tuning_valid(&x)) return SBMT_E_INVALID_ARG;
+  if (x.record_cap != b->tune.record_cap) return SBMT_E_INVALID_ARG;  // fixed by the layout
+  if (x.strategy == SBMT_STRATEGY_FUSED && !b->L.fused_ok) return SBMT_E_INVALID_ARG;
+  b->tune = x;
+  return SBMT_OK;
+}
+
+// Autotuner: time every candidate tuning on this batch (one warm-up and
+// `reps` timed runs of the whole path, HIP events on `stream`) and keep the
+// fastest.  Outputs must be bound; they are overwritten.
+sbmt_status sbmt_batch_tune(sbmt_batch b, int32_t reps, sbmt_tuning* best, float* best_ms, void* stream) {
+  if (!b || reps < 1) return SBMT_E_INVALID_ARG;
+  if (!b->ws) return SBMT_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<sbmt_tuning> cand;
+  for (int rb : {4, 8, 16}) {
+    sbmt_tuning t = b->tune;
+    t.strategy = SBMT_STRATEGY_MULTI;
+    t.tile_rows = rb;
+    t.groups_per_cu = 0;
+    cand.push_back(t);
+  }
+  if (b->L.fused_ok)
+    for (int rb : {4, 8})
+      for (int gpc : {2, 4, 6}) {
+        if (rb == 8 && gpc == 6) continue;  // LDS allows 4 groups of the 8-row band per CU
+        sbmt_tuning t = b->tune;
+        t.strategy = SBMT_STRATEGY_FUSED;
+        t.tile_rows = rb;
+        t.groups_per_cu = gpc;
+        cand.push_back(t);
+      }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return SBMT_E_DEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return SBMT_E_DEVICE;
+  }
+  const sbmt_tuning saved = b->tune;
+  float bestt = 1e30f;
+  sbmt_tuning bt = saved;
+  sbmt_status result = SBMT_OK;
+  for (const sbmt_tuning& t : cand) {
+    b->tune = t;
+    sbmt_status st = sbmt_batch_mesh(b, nullptr, stream);
+    if (st == SBMT_OK && hipEventRecord(e0, s) != hipSuccess) st = SBMT_E_DEVICE;
+    for (int r = 0; r < reps && st == SBMT_OK; ++r) st = sbmt_batch_mesh(b, nullptr, stream);
+    if (st == SBMT_OK && hipEventRecord(e1, s) != hipSuccess) st = SBMT_E_DEVICE;
+    if (st == SBMT_OK && hipEventSynchronize(e1) != hipSuccess) st = SBMT_E_DEVICE;
+    float ms = 0.f;
+    if (st == SBMT_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = SBMT_E_DEVICE;
+    if (st != SBMT_OK) {
+      result = st;
+      break;
+    }
+    ms /= (float)reps;
+    if (ms < bestt) {
+      bestt = ms;
+      bt = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->tune = result == SBMT_OK ? bt : saved;
+  if (best) *best = b->tune;
+  if (best_ms) *best_ms = bestt;
+  return result;
 }
 
 int32_t sbmt_num_classes(void) { return SBMT_NUM_CLASSES; }

@@ -1,0 +1,170 @@
+"""GPU parity of the batched paths (multi-kernel and fused persistent) against the oracle.
+
+Every strategy, tile height and grid size must give the same bits as the
+oracle (schedule independence), also when the slow-owner record list
+overflows, when one image of the batch does not fit its outputs, and on
+every replay of a captured graph.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_19474_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _items():
+    g = wl.rng(91, 0)
+    imgs = [
+        (wl.disk(item=3), 1),
+        (wl.ellipses(item=1)[:700, :900], 2),
+        (wl.smoothed_noise(301, 257, 8.0, 0.0, False, g), 1),
+        (wl.smoothed_noise(640, 200, 8.0, 0.0, False, g), 4),
+        (wl.smoothed_noise(129, 517, 8.0, 0.0, False, g), 2),
+        (np.zeros((0, 0), np.uint8), 1),
+        (np.ones((40, 33), np.uint8), 3),
+        ((np.arange(999) % 5 < 3).astype(np.uint8)[None, :], 1),
+        (wl.smoothed_noise(2100, 64, 4.0, 0.0, False, g), 1),
+        (wl.smoothed_noise(333, 444, 6.0, 0.2, True, g), 6),
+    ]
+    return imgs
+
+
+@pytest.fixture(scope="module")
+def expected():
+    return [oracle.mesh_from_bitmap(bm, h) for bm, h in _items()]
+
+
+def _gpu_items():
+    import torch
+    return [(torch.from_numpy(np.ascontiguousarray(bm)).cuda(), h) for bm, h in _items()]
+
+
+def _check(outs, sizes, expected, label):
+    for i, ((v, t, c), ref) in enumerate(zip(outs, expected)):
+        nv, nt = ref.verts.shape[0], ref.tris.shape[0]
+        if sizes is not None:
+            assert sizes[i][0] == nv and sizes[i][1] == nt and sizes[i][3] == 0, (label, i, sizes[i], nv, nt)
+        tv = t[:nt].cpu().numpy()
+        assert np.array_equal(tv, ref.tris), f"{label}: image {i} connectivity differs"
+        assert np.array_equal(c[:nt].cpu().numpy(), ref.codes), f"{label}: image {i} codes differ"
+        h = _items()[i][1]
+        dv = float(np.abs(v[:nv].cpu().numpy() - ref.verts).max(initial=0.0))
+        assert dv <= 1e-12 * h, (label, i, dv)
+
+
+def test_plan_allocate_emit_every_tile_height(expected):
+    import torch
+
+    from paper_2602_19474_amd.batch import Batch, Tuning
+    items = _gpu_items()
+    for rows in (4, 8, 16):
+        print(f"[gpu-batch] multi tile_rows={rows}", flush=True)
+        b = Batch(items, tuning=Tuning(tile_rows=rows))
+        sizes = b.plan()
+        for s, ref in zip(sizes, expected):
+            assert (s.n_vertices, s.n_triangles) == (ref.verts.shape[0], ref.tris.shape[0])
+        outs = b.allocate(sizes)
+        b.emit()
+        torch.cuda.synchronize()
+        _check(outs, b.sizes(), expected, f"multi{rows}")
+
+
+@pytest.mark.parametrize("strategy,rows,gpc", [(0, 8, 0), (1, 4, 2), (1, 8, 2), (1, 4, 6), (1, 8, 1)])
+def test_mesh_without_host_round_trip(expected, strategy, rows, gpc):
+    import torch
+
+    from paper_2602_19474_amd.batch import Batch, Tuning
+    items = _gpu_items()
+    print(f"[gpu-batch] mesh strategy={strategy} rows={rows} gpc={gpc}", flush=True)
+    b = Batch(items, tuning=Tuning(strategy=strategy, tile_rows=rows, groups_per_cu=gpc))
+    outs = b.allocate(b.plan(), slack=0.01)
+    for rep in range(2):
+        for v, t, c in outs:
+            v.fill_(-1.0)
+            t.fill_(-1)
+        b.mesh()
+        torch.cuda.synchronize()
+        _check(outs, b.sizes(), expected, f"s{strategy}r{rows}g{gpc}#{rep}")
+
+
+@pytest.mark.parametrize("strategy,rows", [(0, 8), (1, 4), (1, 8)])
+def test_record_list_overflow(expected, strategy, rows):
+    """A tiny record list: most slow owners are classified where they are needed."""
+    import torch
+
+    from paper_2602_19474_amd.batch import Batch, Tuning
+    items = _gpu_items()
+    print(f"[gpu-batch] record_cap=37 strategy={strategy} rows={rows}", flush=True)
+    b = Batch(items, tuning=Tuning(strategy=strategy, tile_rows=rows, groups_per_cu=2, record_cap=37))
+    outs = b.allocate(b.plan())
+    b.mesh()
+    torch.cuda.synchronize()
+    _check(outs, b.sizes(), expected, f"overflow s{strategy}")
+
+
+@pytest.mark.parametrize("strategy", [0, 1])
+def test_one_image_over_capacity(expected, strategy):
+    import torch
+
+    from paper_2602_19474_amd.batch import Batch, Tuning
+    items = _gpu_items()
+    print(f"[gpu-batch] capacity strategy={strategy}", flush=True)
+    b = Batch(items, tuning=Tuning(strategy=strategy, tile_rows=8, groups_per_cu=2))
+    sizes = b.plan()
+    outs = b.allocate(sizes)
+    small = 2  # the smoothed-noise image at h=1 gets one triangle too few
+    v, t, c = outs[small]
+    nt = t.shape[0]
+    outs[small] = (v, torch.full((nt - 1, 3), -7, dtype=torch.int32, device="cuda"),
+                   torch.zeros((nt - 1,), dtype=torch.uint8, device="cuda"))
+    b.bind(outs)
+    b.mesh()
+    torch.cuda.synchronize()
+    st = b.sizes()
+    assert st[small][3] == -7 and st[small][1] == nt
+    if strategy == 0:
+        assert (outs[small][1].cpu().numpy() == -7).all()
+    keep = [i for i in range(len(outs)) if i != small]
+    _check([outs[i] for i in keep], [st[i] for i in keep], [expected[i] for i in keep], "capacity")
+
+
+def test_graph_replays_match_eager(expected):
+    import torch
+
+    from paper_2602_19474_amd.batch import Batch, Tuning
+    items = _gpu_items()
+    for strategy, rows in ((0, 8), (1, 4)):
+        print(f"[gpu-batch] graph strategy={strategy}", flush=True)
+        b = Batch(items, tuning=Tuning(strategy=strategy, tile_rows=rows, groups_per_cu=2))
+        outs = b.allocate(b.plan())
+        g = b.capture()
+        for rep in range(3):
+            for v, t, c in outs:  # eager work between replays
+                v.zero_()
+                t.zero_()
+                c.zero_()
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            _check(outs, b.sizes(), expected, f"graph s{strategy} replay {rep}")
+
+
+def test_autotuner_keeps_results(expected):
+    import torch
+
+    from paper_2602_19474_amd.batch import Batch
+    items = _gpu_items()
+    print("[gpu-batch] autotune", flush=True)
+    b = Batch(items)
+    outs = b.allocate(b.plan())
+    best, ms = b.tune(reps=1)
+    assert ms > 0 and best.tile_rows in (4, 8, 16)
+    for v, t, c in outs:
+        t.zero_()
+    b.mesh()
+    torch.cuda.synchronize()
+    _check(outs, b.sizes(), expected, f"tuned {best}")

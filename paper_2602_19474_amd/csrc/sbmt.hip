@@ -65,7 +65,8 @@ struct Img {
   Geo g;
   const uint8_t* bm;  // bitmap rows (device)
   uint32_t* bits;     // coarse raster, (CH + 2 kRing) rows of wpr words
-  uint32_t* oinfo;    // [NK][NI] info word of every owner whose window is not uniform
+  uint32_t* oinfo;    // [NK][NI] record index of slow owners (fused path: info of non-uniform owners)
+  uint8_t* omap;      // [NK][NI] one code per owner (multi-kernel path), see owner_code
   int64_t seg0;       // first row segment of the image in the call's segment arrays
   int64_t band0;      // first band of the image (fused path, 4-row numbering)
   int64_t halo0;      // first word of the image's halo rows (fused path)
@@ -84,9 +85,10 @@ struct Shared {
   unsigned long long* ctr;          // [8] 0: records handed out, 1: band ticket
   int* imgerr;                      // [n] protocol violation seen
   int64_t* sizes;                   // [n][4] n_vertices, n_triangles, n_cut, status
-  SlowRec* rec;                     // [rcap] slow-owner records
+  SlowRec* rec;                     // slow-owner records, tcap per count tile
+  int* tile_n;                      // [count tiles] slow owners queued by each tile
   unsigned long long* band;         // [nbands] fused path look-back words
-  int64_t rcap, nseg, nbands;
+  int64_t tcap, nseg, nbands;
   int nblk, n;
 };
 
@@ -123,12 +125,38 @@ SBMT_HD unsigned long long pack_counts(uint32_t info) {
          ((unsigned long long)info_ncut(info) << 42);
 }
 
+// One byte per owner: bit 0 vertex emitted, 1 base triangle Tb emitted, 2 Ta
+// emitted, 3 owner vertex inside, 7 slow owner (its counts are in its record).
+SBMT_HD uint32_t owner_code(uint32_t info) {
+  return (uint32_t)info_self(info) | ((uint32_t)info_ntb(info) << 1) | ((uint32_t)info_nta(info) << 2) |
+         ((uint32_t)info_fg(info) << 3);
+}
+SBMT_HD uint32_t code_info(uint32_t code) {
+  return (code & 1u) | (((code >> 1) & 1u) << 9) | (((code >> 2) & 1u) << 12) | (((code >> 3) & 1u) << 16);
+}
+
+// Owner frame without the samples: what emission needs of a slow owner.
+SBMT_HD Frame owner_place(const Geo& g, int k, int i, int Rlo) {
+  Frame f;
+  f.k = k;
+  f.i = i;
+  f.o = k & 1;
+  f.X = g.X0 + 4 * g.h * i + 2 * g.h * f.o;
+  f.Rlo = Rlo;
+  f.Clo = clo_of(g, f.X);
+  f.s9 = 0;
+  return f;
+}
+
 // ---------------------------------------------------------------------------
 // Coarse raster: bit (R + ring, C + ringC) = [2 * #fg pixels of block (R, C) >= s^2].
 // One lane per sample; a wave covers 64 consecutive stored columns and packs
 // them with a ballot; samples outside the image (the ring) are background.
-// Blocks per image: ceil(32 wpr / 256) x (CH + 2 ring); 256 threads.
+// Blocks per image: ceil(32 wpr / 256) x ceil((CH + 2 ring) / kCoarsenRows);
+// 256 threads, kCoarsenRows stored rows per block.
 // ---------------------------------------------------------------------------
+constexpr int kCoarsenRows = 8;
+
 template <class Src>
 __global__ void __launch_bounds__(256) k_coarsen(Src src, const int64_t* __restrict__ tab, Shared sh) {
   int64_t local;
@@ -136,7 +164,7 @@ __global__ void __launch_bounds__(256) k_coarsen(Src src, const int64_t* __restr
   const Img& d = src.img(ii);
   const Geo g = d.g;
   const int nbx = (32 * g.wpr + 255) / 256;
-  const int bx = (int)(local % nbx), rr = (int)(local / nbx);
+  const int bx = (int)(local % nbx), ry = (int)(local / nbx);
   if (blockIdx.x == 0 && threadIdx.x < 8) sh.ctr[threadIdx.x] = 0;
   if (local == 0 && threadIdx.x == 0) sh.imgerr[ii] = 0;
   // look-back words and size slots of the fused path start at zero
@@ -147,23 +175,27 @@ __global__ void __launch_bounds__(256) k_coarsen(Src src, const int64_t* __restr
     sh.sizes[q] = 0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int gw = bx * 4 + wv;  // 64-bit group of the stored row
-  const int R = rr - kRing;
   const int C = 64 * gw + lane - kRingC;
-  int fg = 0;
-  if (R >= 0 && R < g.CH && C >= 0 && C < g.CW) {
-    const int s = g.s;
-    const int r0 = s * R, r1 = min(r0 + s, g.H);
-    const int c0 = s * C, c1 = min(c0 + s, g.W);
-    int cnt = 0;
-    for (int r = r0; r < r1; ++r) {
-      const uint8_t* row = d.bm + (int64_t)r * g.stride;
-      for (int c = c0; c < c1; ++c) cnt += row[c] != 0;
-    }
-    fg = 2 * cnt >= s * s;
-  }
-  const unsigned long long m = __ballot(fg);
   const int w = 2 * gw + lane;
-  if (lane < 2 && w < g.wpr) d.bits[(int64_t)rr * g.wpr + w] = (uint32_t)(m >> (32 * lane));
+  const int s = g.s;
+  const int c0 = s * C, c1 = min(c0 + s, g.W);
+  const bool colin = C >= 0 && C < g.CW;
+  const int nrows = g.CH + 2 * kRing;
+  for (int rr = ry * kCoarsenRows; rr < min(ry * kCoarsenRows + kCoarsenRows, nrows); ++rr) {
+    const int R = rr - kRing;
+    int fg = 0;
+    if (colin && R >= 0 && R < g.CH) {
+      const int r0 = s * R, r1 = min(r0 + s, g.H);
+      int cnt = 0;
+      for (int r = r0; r < r1; ++r) {
+        const uint8_t* row = d.bm + (int64_t)r * g.stride;
+        for (int c = c0; c < c1; ++c) cnt += row[c] != 0;
+      }
+      fg = 2 * cnt >= s * s;
+    }
+    const unsigned long long m = __ballot(fg);
+    if (lane < 2 && w < g.wpr) d.bits[(int64_t)rr * g.wpr + w] = (uint32_t)(m >> (32 * lane));
+  }
 }
 
 // Stage the coarse-raster window of a tile (cell rows rlo .. rhi, owner
@@ -212,17 +244,17 @@ __device__ __forceinline__ T wave_incl_scan(T v, int lane) {
 template <int RB>
 struct CountLds {
   int acc[RB][4];
+  alignas(4) uint8_t code[RB][kCB];
   int rowR[RB];
   uint16_t q1[RB * kCB];
   uint16_t q2[RB * kCB];
   int n1, n2;
-  unsigned long long base;
   uint32_t win[kWinRows * kWinWords];
 };
 
 template <int RB>
-__device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, int ky, int cb, const Shared& sh,
-                                           CountLds<RB>& L, int4* acc_out) {
+__device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, int64_t tile, int ky, int cb,
+                                           const Shared& sh, CountLds<RB>& L, int4* acc_out) {
   const int k0 = ky * RB;
   const int c0 = cb * kCB;
   const int lane = threadIdx.x & 63;
@@ -248,6 +280,7 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
         const uint32_t fi = fast_info(g, f);
         nv = info_nv(fi);
         nt = info_nt(fi);
+        L.code[r][threadIdx.x] = (uint8_t)owner_code(fi);
       } else {
         L.q1[atomicAdd(&L.n1, 1)] = (uint16_t)(r * kCB + threadIdx.x);
       }
@@ -268,20 +301,33 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
     uint32_t fi = 0;
     if (needs_slow(g, f, fi)) {
       L.q2[atomicAdd(&L.n2, 1)] = (uint16_t)e;
+      L.code[r][e - r * kCB] = 0x80;
     } else {
-      d.oinfo[(int64_t)k * g.NI + c] = fi;
+      L.code[r][e - r * kCB] = (uint8_t)owner_code(fi);
       atomicAdd(&L.acc[r][0], info_nv(fi));
       atomicAdd(&L.acc[r][1], info_nt(fi));
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) L.base = L.n2 ? atomicAdd(&sh.ctr[0], (unsigned long long)L.n2) : 0ull;
-  __syncthreads();
+  // the tile's owner codes, one 4-byte word per lane and row
+  for (int t = threadIdx.x; t < RB * (kCB / 4); t += kThreads) {
+    const int r = t / (kCB / 4), c = c0 + 4 * (t - r * (kCB / 4));
+    const int k = k0 + r;
+    if (k >= g.NK || c >= g.NI) continue;
+    uint8_t* dst = d.omap + (int64_t)k * g.NI + c;
+    const uint8_t* src = &L.code[r][c - c0];
+    if (c + 4 <= g.NI && ((((int64_t)k * g.NI + c) & 3) == 0)) {
+      *reinterpret_cast<uint32_t*>(dst) = *reinterpret_cast<const uint32_t*>(src);
+    } else {
+      for (int u = 0; u < 4 && c + u < g.NI; ++u) dst[u] = src[u];
+    }
+  }
+  if (threadIdx.x == 0) sh.tile_n[tile] = L.n2;
   for (int q = threadIdx.x; q < L.n2; q += kThreads) {
     const int e = L.q2[q], r = e / kCB, c = c0 + (e - r * kCB);
     const int k = k0 + r;
-    const unsigned long long idx = L.base + (unsigned long long)q;
-    if (idx < (unsigned long long)sh.rcap) {
+    const int64_t idx = tile * sh.tcap + q;
+    if (q < sh.tcap) {
       sh.rec[idx].x = (uint64_t)c | ((uint64_t)k << 24) | ((uint64_t)ii << 48);
       d.oinfo[(int64_t)k * g.NI + c] = kSlowBit | (uint32_t)idx;
     } else {
@@ -312,41 +358,48 @@ __global__ void __launch_bounds__(kThreads) k_count(Src src, const int64_t* __re
   const Img& d = src.img(ii);
   const Geo g = d.g;
   const int cb = (int)(local % g.NCB), ky = (int)(local / g.NCB);
-  count_tile<RB>(d, g, ii, ky, cb, sh, L, out);
+  count_tile<RB>(d, g, ii, (int64_t)blockIdx.x, ky, cb, sh, L, out);
   __syncthreads();
   const int k = ky * RB + (int)threadIdx.x;
-  if (threadIdx.x < RB && k < g.NK) {
-    const int64_t j = d.seg0 + (int64_t)k * g.NCB + cb;
-    sh.seg_cnt[j] = out[threadIdx.x];
-    sh.seg_slow[j] = 0ull;
-  }
+  if (threadIdx.x < RB && k < g.NK) sh.seg_cnt[d.seg0 + (int64_t)k * g.NCB + cb] = out[threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
-// Slow owners of the call, one per lane over the record list: classify, store
-// the 16-byte record in place of the position, add the counts to the segment.
+// Slow owners of one count tile per 64-lane block (the tiling of k_count):
+// classify each queued owner, store its 16-byte record in place of its
+// position, and write the tile's per-row sums of the slow owners' counts.
 // ---------------------------------------------------------------------------
-template <class Src>
-__global__ void __launch_bounds__(256) k_slow(Src src, Shared sh) {
-  const unsigned long long n = min(sh.ctr[0], (unsigned long long)sh.rcap);
-  for (unsigned long long idx = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
-       idx += (unsigned long long)gridDim.x * blockDim.x) {
+template <class Src, int RB>
+__global__ void __launch_bounds__(64) k_slow(Src src, const int64_t* __restrict__ tab, Shared sh) {
+  __shared__ unsigned long long acc[RB];
+  int64_t local;
+  const int ii = src.find(blockIdx.x, tab, local);
+  const Img& d = src.img(ii);
+  const Geo g = d.g;
+  const int cb = (int)(local % g.NCB), ky = (int)(local / g.NCB);
+  const int64_t tile = blockIdx.x;
+  if (threadIdx.x < RB) acc[threadIdx.x] = 0ull;
+  __syncthreads();
+  const int n = (int)min((int64_t)sh.tile_n[tile], sh.tcap);
+  Bits b;
+  b.p = d.bits;
+  b.wpr = g.wpr;
+  b.rr0 = 0;
+  b.cc0 = 0;
+  for (int q = threadIdx.x; q < n; q += 64) {
+    const int64_t idx = tile * sh.tcap + q;
     const uint64_t p = sh.rec[idx].x;
-    const int ii = (int)(p >> 48), k = (int)((p >> 24) & 0xffffffu), c = (int)(p & 0xffffffu);
-    const Img& d = src.img(ii);
-    const Geo g = d.g;
-    Bits b;
-    b.p = d.bits;
-    b.wpr = g.wpr;
-    b.rr0 = 0;
-    b.cc0 = 0;
+    const int k = (int)((p >> 24) & 0xffffffu), c = (int)(p & 0xffffffu);
     const Frame f = owner_frame(g, b, k, c, row_cell(k, g.h, g.s));
     Slow sr;
     slow_classify(g, f, sr);
     sh.rec[idx] = pack_slow(sr);
-    atomicAdd(&sh.seg_slow[d.seg0 + (int64_t)k * g.NCB + c / kCB], pack_counts(sr.info));
+    atomicAdd(&acc[k - ky * RB], pack_counts(sr.info));
     if (info_err(sr.info)) atomicOr(&sh.imgerr[ii], 1);
   }
+  __syncthreads();
+  const int k = ky * RB + (int)threadIdx.x;
+  if (threadIdx.x < RB && k < g.NK) sh.seg_slow[d.seg0 + (int64_t)k * g.NCB + cb] = acc[threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
@@ -528,7 +581,10 @@ struct EmitLds {
   int part[RB + 1][2][kThreads / 64];
 };
 
-template <int RB>
+// MAP: owner info from the owner map written by k_count (multi-kernel path);
+// otherwise from the samples, with non-uniform owners' info words in oinfo
+// and, for the halo row, in hrow (fused path).
+template <int RB, bool MAP>
 __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, int cb, const Shared& sh,
                                           EmitLds<RB>& L, const uint32_t* __restrict__ hrow) {
   constexpr int W = EmitLds<RB>::W;
@@ -537,35 +593,124 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, in
   if (threadIdx.x <= RB) L.rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);
   if (threadIdx.x == 0) L.na = L.ns = 0;
   __syncthreads();
-  const int klast = min(k0 + RB + 1, g.NK) - 1;
-  const Bits bw = stage_window(g, d.bits, L.win, L.rowR[0] + kRing, L.rowR[max(klast - k0, 0)] + 2 + kRing,
-                               max(c0 - 1, 0), min(c0 + kCB + 1, g.NI) - 1);
-  __syncthreads();
+  Bits bw;
+  if (MAP) {
+    bw.p = d.bits;
+    bw.wpr = g.wpr;
+    bw.rr0 = 0;
+    bw.cc0 = 0;
+  } else {
+    const int klast = min(k0 + RB + 1, g.NK) - 1;
+    bw = stage_window(g, d.bits, L.win, L.rowR[0] + kRing, L.rowR[max(klast - k0, 0)] + 2 + kRing, max(c0 - 1, 0),
+                      min(c0 + kCB + 1, g.NI) - 1);
+    __syncthreads();
+  }
   // 1. info words
-  for (int idx = threadIdx.x; idx < (RB + 1) * W; idx += kThreads) {
+  constexpr int kPer = ((RB + 1) * W + kThreads - 1) / kThreads;
+  constexpr int kHold = 2;
+  uint32_t codes[kPer];
+  SlowRec held[kHold];
+  int hidx[kHold];
+  uint32_t hri[kHold];
+  if (MAP) {
+    // all code loads of the thread first, so their latencies overlap
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int idx = threadIdx.x + j * kThreads;
+      const int rr = idx / W, col = idx - rr * W;
+      const int k = k0 + rr, c = c0 - 1 + col;
+      codes[j] = (idx < (RB + 1) * W && k < g.NK && c >= 0 && c < g.NI) ? (uint32_t)d.omap[(int64_t)k * g.NI + c]
+                                                                        : 0xffu;
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int idx = threadIdx.x + j * kThreads;
+      if (idx >= (RB + 1) * W) break;
+      const int rr = idx / W, col = idx - rr * W;
+      uint32_t fi = 0;
+      if (codes[j] != 0xffu) {
+        if (!(codes[j] & 0x80u)) {
+          fi = code_info(codes[j]);
+        } else {
+          L.qa[atomicAdd(&L.na, 1)] = (uint16_t)idx;  // record looked up below
+        }
+      }
+      L.info[rr][col] = fi;
+    }
+    __syncthreads();
+    // slow owners: record index, then the record (or a classification); the
+    // first kHold per thread stay in registers for emission
+#pragma unroll
+    for (int j = 0; j < kHold; ++j) {
+      const int q = threadIdx.x + j * kThreads;
+      hidx[j] = q < L.na ? L.qa[q] : -1;
+      hri[j] = kNoRec;
+      if (hidx[j] >= 0) {
+        const int rr = hidx[j] / W, col = hidx[j] - rr * W;
+        hri[j] = d.oinfo[(int64_t)(k0 + rr) * g.NI + c0 - 1 + col] & kNoRec;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kHold; ++j)
+      if (hidx[j] >= 0 && hri[j] != kNoRec) held[j] = sh.rec[hri[j]];
+#pragma unroll
+    for (int j = 0; j < kHold; ++j) {
+      if (hidx[j] < 0) continue;
+      const int rr = hidx[j] / W, col = hidx[j] - rr * W;
+      if (hri[j] == kNoRec) {
+        const Frame f = owner_frame(g, bw, k0 + rr, c0 - 1 + col, L.rowR[rr]);
+        Slow sr;
+        slow_classify(g, f, sr);
+        held[j] = pack_slow(sr);
+      }
+      L.info[rr][col] = held[j].info;
+    }
+    for (int q = threadIdx.x + kHold * kThreads; q < L.na; q += kThreads) {
+      const int idx = L.qa[q], rr = idx / W, col = idx - rr * W;
+      const int k = k0 + rr, c = c0 - 1 + col;
+      const uint32_t ri = d.oinfo[(int64_t)k * g.NI + c] & kNoRec;
+      uint32_t fi;
+      if (ri != kNoRec) {
+        fi = sh.rec[ri].info;
+      } else {
+        const Frame f = owner_frame(g, bw, k, c, L.rowR[rr]);
+        Slow sr;
+        slow_classify(g, f, sr);
+        fi = sr.info;
+      }
+      L.info[rr][col] = fi;
+    }
+  }
+  for (int idx = threadIdx.x; !MAP && idx < (RB + 1) * W; idx += kThreads) {
     const int rr = idx / W, col = idx - rr * W;
     const int k = k0 + rr, c = c0 - 1 + col;
     uint32_t fi = 0;
     if (k < g.NK && c >= 0 && c < g.NI) {
-      const Frame f = owner_frame(g, bw, k, c, L.rowR[rr]);
-      if (frame_uniform(f)) {
-        fi = fast_info(g, f);
-      } else {
-        const uint32_t w = rr == RB ? hrow[c] : d.oinfo[(int64_t)k * g.NI + c];
-        if (!(w & kSlowBit)) {
-          fi = w;
+      uint32_t w;
+      bool plain;
+      {
+        const Frame f = owner_frame(g, bw, k, c, L.rowR[rr]);
+        plain = frame_uniform(f);
+        if (plain) {
+          w = fast_info(g, f);
         } else {
-          const uint32_t ri = w & kNoRec;
-          if (ri == kNoRec) L.qa[atomicAdd(&L.na, 1)] = (uint16_t)idx;
-          else fi = sh.rec[ri].info;
-          if (rr < RB && col >= 1 && col <= kCB) L.qs[atomicAdd(&L.ns, 1)] = (uint16_t)idx;
+          w = rr == RB ? hrow[c] : d.oinfo[(int64_t)k * g.NI + c];
+          plain = !(w & kSlowBit);
         }
+      }
+      if (plain) {
+        fi = w;
+      } else {
+        const uint32_t ri = w & kNoRec;
+        if (ri == kNoRec) L.qa[atomicAdd(&L.na, 1)] = (uint16_t)idx;
+        else fi = sh.rec[ri].info;
+        if (rr < RB && col >= 1 && col <= kCB) L.qs[atomicAdd(&L.ns, 1)] = (uint16_t)idx;
       }
     }
     L.info[rr][col] = fi;
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < L.na; q += kThreads) {
+  for (int q = threadIdx.x; !MAP && q < L.na; q += kThreads) {
     const int idx = L.qa[q], rr = idx / W, col = idx - rr * W;
     const Frame f = owner_frame(g, bw, k0 + rr, c0 - 1 + col, L.rowR[rr]);
     Slow sr;
@@ -663,17 +808,51 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, in
       d.codes[u] = code;
     }
   }
+  if (MAP) {
+    // held records, then any further slow owners of the tile
+#pragma unroll
+    for (int j = 0; j < kHold; ++j) {
+      if (hidx[j] < 0) continue;
+      const int r = hidx[j] / W, col = hidx[j] - r * W;
+      if (r >= RB || col < 1 || col > kCB) continue;
+      const int k = k0 + r, c = c0 + col - 1;
+      const Nb nb = neighbours(r, col, L.info[r][col], k & 1);
+      emit_slow(g, owner_place(g, k, c, L.rowR[r]), held[j], nb, L.tb[r] + L.toff[r][col], out);
+    }
+    for (int q = threadIdx.x + kHold * kThreads; q < L.na; q += kThreads) {
+      const int idx = L.qa[q], r = idx / W, col = idx - r * W;
+      if (r >= RB || col < 1 || col > kCB) continue;
+      const int k = k0 + r, c = c0 + col - 1;
+      const Nb nb = neighbours(r, col, L.info[r][col], k & 1);
+      const uint32_t ri = d.oinfo[(int64_t)k * g.NI + c] & kNoRec;
+      SlowRec R;
+      Frame fr;
+      if (ri != kNoRec) {
+        R = sh.rec[ri];
+        fr = owner_place(g, k, c, L.rowR[r]);
+      } else {
+        fr = owner_frame(g, bw, k, c, L.rowR[r]);
+        Slow sr;
+        slow_classify(g, fr, sr);
+        R = pack_slow(sr);
+      }
+      emit_slow(g, fr, R, nb, L.tb[r] + L.toff[r][col], out);
+    }
+    return;
+  }
   for (int q = threadIdx.x; q < L.ns; q += kThreads) {
     const int idx = L.qs[q], r = idx / W, col = idx - r * W;
     const int k = k0 + r, c = c0 + col - 1;
     const uint32_t f = L.info[r][col];
     const Nb nb = neighbours(r, col, f, k & 1);
-    const Frame fr = owner_frame(g, bw, k, c, L.rowR[r]);
     const uint32_t ri = d.oinfo[(int64_t)k * g.NI + c] & kNoRec;
     SlowRec R;
+    Frame fr;
     if (ri != kNoRec) {
       R = sh.rec[ri];
+      fr = owner_place(g, k, c, L.rowR[r]);
     } else {
+      fr = owner_frame(g, bw, k, c, L.rowR[r]);
       Slow sr;
       slow_classify(g, fr, sr);
       R = pack_slow(sr);
@@ -701,8 +880,7 @@ __global__ void __launch_bounds__(kThreads) k_emit(Src src, const int64_t* __res
     L.bv[threadIdx.x] = (int)(o.x - base.x);
     if (threadIdx.x < RB) L.tb[threadIdx.x] = o.y - base.y;
   }
-  const int kh = min(ky * RB + RB, g.NK - 1);
-  emit_tile<RB>(d, g, ky, cb, sh, L, d.oinfo + (int64_t)kh * g.NI);
+  emit_tile<RB, true>(d, g, ky, cb, sh, L, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -739,8 +917,9 @@ struct FusedLds {
 };
 
 template <int RB>
-__global__ void __launch_bounds__(kThreads) k_fused(ManySrc src, const int64_t* __restrict__ tab, Shared sh,
-                                                    int64_t nbands, uint32_t* __restrict__ halo) {
+__global__ void __launch_bounds__(kThreads) k_fused(ManySrc src, const int64_t* __restrict__ tab,
+                                                    const int64_t* __restrict__ ttab, Shared sh, int64_t nbands,
+                                                    uint32_t* __restrict__ halo) {
   __shared__ FusedLds<RB> F;
   for (;;) {
     __syncthreads();
@@ -810,17 +989,17 @@ __global__ void __launch_bounds__(kThreads) k_fused(ManySrc src, const int64_t* 
         }
       }
       __syncthreads();
+      // the chunk's records live in the region of count tile (j, cb)
+      const int64_t tile = ttab[ii] + j * g.NCB + cb;
       if (threadIdx.x == 0) {
-        C.base = C.n2 ? atomicAdd(&sh.ctr[0], (unsigned long long)C.n2) : 0ull;
-        F.cbase[cb] = C.base;
-        F.cn[cb] = C.n2;
+        F.cbase[cb] = (unsigned long long)(tile * sh.tcap);
+        F.cn[cb] = (int)min((int64_t)C.n2, sh.tcap);
       }
-      __syncthreads();
       for (int q = threadIdx.x; q < C.n2; q += kThreads) {
         const int e = C.q2[q], r = e / kCB, c = c0 + (e - r * kCB);
         const int k = k0 + r;
-        const unsigned long long idx = C.base + (unsigned long long)q;
-        if (idx < (unsigned long long)sh.rcap) {
+        const int64_t idx = tile * sh.tcap + q;
+        if (q < sh.tcap) {
           sh.rec[idx].x = (uint64_t)c | ((uint64_t)k << 24) | ((uint64_t)ii << 48);
           if (r < RB) d.oinfo[(int64_t)k * g.NI + c] = kSlowBit | (uint32_t)idx;
         } else {
@@ -843,8 +1022,7 @@ __global__ void __launch_bounds__(kThreads) k_fused(ManySrc src, const int64_t* 
     if (threadIdx.x == 0) {
       int s = 0;
       for (int cb = 0; cb < g.NCB; ++cb) {
-        const long long room = sh.rcap - (long long)F.cbase[cb];
-        const int n = (int)max(0ll, min((long long)F.cn[cb], room));
+        const int n = F.cn[cb];
         F.cn[cb] = s;
         s += n;
       }
@@ -943,7 +1121,7 @@ __global__ void __launch_bounds__(kThreads) k_fused(ManySrc src, const int64_t* 
         E.tb[threadIdx.x] = F.cnt[cb][threadIdx.x].y;
       }
       if (threadIdx.x == RB) E.bv[RB] = hv;
-      emit_tile<RB>(d, g, (int)j, cb, sh, E, hrow);
+      emit_tile<RB, false>(d, g, (int)j, cb, sh, E, hrow);
       __syncthreads();
       hv += E.rowv[RB];
     }
@@ -1048,13 +1226,14 @@ static const int kRBs[3] = {4, 8, 16};
 struct CallLayout {
   int n = 0;
   std::vector<Geo> g;
-  std::vector<size_t> off_bits, off_oinfo;
+  std::vector<size_t> off_bits, off_oinfo, off_omap;
   std::vector<int64_t> seg0, band0, halo0;  // band0, halo0 for the smallest fused band height
   std::vector<int64_t> tab;           // [1 + 3 + 3][n + 1]: coarsen blocks, tiles per RB, bands per RB
-  int64_t nseg = 0, owners = 0, rcap = 0, nbands_max = 0, halo_words = 0;
+  int64_t nseg = 0, owners = 0, rcap = 0, nbands_max = 0, halo_words = 0, ntiles_max = 0;
+  int64_t tcap[3] = {0, 0, 0};  // records per count tile, per tile height
   int nblk = 0;
   size_t off_ctr, off_imgerr, off_sizes, off_desc, off_tab, off_cnt, off_slow, off_segoff, off_blk, off_rec,
-      off_band, off_halo, total;
+      off_tilen, off_band, off_halo, total;
   bool fused_ok = true;  // per-image counts fit the fused path's int32 bases and band width
 };
 
@@ -1068,6 +1247,7 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
   L.g.resize(n);
   L.off_bits.resize(n);
   L.off_oinfo.resize(n);
+  L.off_omap.resize(n);
   L.seg0.resize(n);
   L.band0.resize(n);
   L.halo0.resize(n);
@@ -1081,7 +1261,7 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
     L.seg0[i] = L.nseg;
     L.nseg += (int64_t)g.NK * g.NCB;
     L.owners += (int64_t)g.NK * g.NI;
-    const int64_t cblk = (int64_t)((32 * g.wpr + 255) / 256) * (g.CH + 2 * kRing);
+    const int64_t cblk = (int64_t)((32 * g.wpr + 255) / 256) * ((g.CH + 2 * kRing + kCoarsenRows - 1) / kCoarsenRows);
     tab_row(L, 0)[i + 1] = tab_row(L, 0)[i] + cblk;
     for (int r = 0; r < 3; ++r) {
       const int64_t rows = (g.NK + kRBs[r] - 1) / kRBs[r];
@@ -1096,8 +1276,16 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
     if (g.NCB > kMaxBandChunks || 10LL * g.NK * g.NI > 0x7fffffffLL) L.fused_ok = false;
   }
   L.nbands_max = tab_row(L, 4)[n];
-  L.rcap = record_cap > 0 ? record_cap : (record_cap == 0 ? L.owners / 4 + 1024 : 0);
+  // records: by default a quarter of each tile's owners; an explicit cap is
+  // shared evenly by the tiles
+  for (int r = 0; r < 3; ++r) L.ntiles_max = std::max(L.ntiles_max, tab_row(L, 1 + r)[n]);
+  if (record_cap == 0) {
+    for (int r = 0; r < 3; ++r) L.rcap = std::max(L.rcap, tab_row(L, 1 + r)[n] * (int64_t)(kRBs[r] * kCB / 4));
+  } else {
+    L.rcap = std::max<int64_t>(record_cap, 0);
+  }
   if (L.rcap >= (int64_t)kNoRec) L.rcap = (int64_t)kNoRec - 1;
+  for (int r = 0; r < 3; ++r) L.tcap[r] = L.rcap / std::max<int64_t>(tab_row(L, 1 + r)[n], 1);
   L.nblk = (int)((L.nseg + kScanChunk - 1) / kScanChunk);
   size_t off = 0;
   L.off_ctr = off;
@@ -1120,6 +1308,8 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
   off = align256(off + (size_t)L.nblk * sizeof(longlong4));
   L.off_rec = off;
   off = align256(off + (size_t)L.rcap * sizeof(SlowRec));
+  L.off_tilen = off;
+  off = align256(off + (size_t)L.ntiles_max * sizeof(int));
   L.off_band = off;
   off = align256(off + (size_t)L.nbands_max * sizeof(unsigned long long));
   L.off_halo = off;
@@ -1130,12 +1320,14 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
     off = align256(off + (size_t)(g.CH + 2 * kRing) * g.wpr * 4);
     L.off_oinfo[i] = off;
     off = align256(off + (size_t)g.NK * g.NI * 4);
+    L.off_omap[i] = off;
+    off = align256(off + (size_t)g.NK * g.NI);
   }
   L.total = off;
   return SBMT_OK;
 }
 
-static Shared shared_of(const CallLayout& L, void* ws) {
+static Shared shared_of(const CallLayout& L, void* ws, int rbi) {
   char* b = (char*)ws;
   Shared s;
   s.seg_cnt = (int4*)(b + L.off_cnt);
@@ -1147,7 +1339,8 @@ static Shared shared_of(const CallLayout& L, void* ws) {
   s.sizes = (int64_t*)(b + L.off_sizes);
   s.rec = (SlowRec*)(b + L.off_rec);
   s.band = (unsigned long long*)(b + L.off_band);
-  s.rcap = L.rcap;
+  s.tile_n = (int*)(b + L.off_tilen);
+  s.tcap = L.tcap[rbi];
   s.nseg = L.nseg;
   s.nbands = L.nbands_max;
   s.nblk = L.nblk;
@@ -1163,6 +1356,7 @@ static Img img_of(const CallLayout& L, int i, const sbmt_image& im, void* ws, co
   d.bm = im.bitmap;
   d.bits = (uint32_t*)(b + L.off_bits[i]);
   d.oinfo = (uint32_t*)(b + L.off_oinfo[i]);
+  d.omap = (uint8_t*)(b + L.off_omap[i]);
   d.seg0 = L.seg0[i];
   d.band0 = L.band0[i];
   d.halo0 = L.halo0[i];
@@ -1190,7 +1384,11 @@ static sbmt_status launch_front(const CallLayout& L, const Src& src, const int64
     case 8: hipLaunchKernelGGL((k_count<Src, 8>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh); break;
     default: hipLaunchKernelGGL((k_count<Src, 16>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh); break;
   }
-  hipLaunchKernelGGL(k_slow<Src>, dim3(2048), dim3(256), 0, st, src, sh);
+  switch (kRBs[rbi]) {
+    case 4: hipLaunchKernelGGL((k_slow<Src, 4>), dim3((unsigned)ntile), dim3(64), 0, st, src, tt, sh); break;
+    case 8: hipLaunchKernelGGL((k_slow<Src, 8>), dim3((unsigned)ntile), dim3(64), 0, st, src, tt, sh); break;
+    default: hipLaunchKernelGGL((k_slow<Src, 16>), dim3((unsigned)ntile), dim3(64), 0, st, src, tt, sh); break;
+  }
   hipLaunchKernelGGL(k_scan_reduce, dim3(L.nblk), dim3(kScanThreads), 0, st, sh);
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, st, sh);
   hipLaunchKernelGGL(k_scan_apply, dim3(L.nblk), dim3(kScanThreads), 0, st, sh);
@@ -1318,7 +1516,7 @@ sbmt_status sbmt_plan(sbmt_handle h, const sbmt_image* img, void* workspace, siz
   sbmt_status st = single_prepare(img, workspace, ws_bytes, &L);
   if (st != SBMT_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  const Shared sh = shared_of(L, workspace);
+  const Shared sh = shared_of(L, workspace, 1);
   OneSrc src;
   src.d = img_of(L, 0, *img, workspace, nullptr);
   if ((st = launch_front(L, src, nullptr, sh, 1, s)) != SBMT_OK) return st;
@@ -1340,7 +1538,7 @@ sbmt_status sbmt_run(sbmt_handle h, const sbmt_image* img, void* workspace, size
   CallLayout L;
   sbmt_status st = single_prepare(img, workspace, ws_bytes, &L);
   if (st != SBMT_OK) return st;
-  const Shared sh = shared_of(L, workspace);
+  const Shared sh = shared_of(L, workspace, 1);
   // the plan's totals bound every write; capacities are the totals themselves
   sbmt_outputs o;
   o.verts = verts;
@@ -1361,7 +1559,7 @@ sbmt_status sbmt_mesh_async(sbmt_handle h, const sbmt_image* img, void* workspac
   sbmt_status st = single_prepare(img, workspace, ws_bytes, &L);
   if (st != SBMT_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  const Shared sh = shared_of(L, workspace);
+  const Shared sh = shared_of(L, workspace, 1);
   sbmt_outputs o;
   o.verts = verts;
   o.tris = tris;
@@ -1450,7 +1648,7 @@ sbmt_status sbmt_batch_plan(sbmt_batch b, sbmt_sizes* out, void* stream) {
   if (!b || !out) return SBMT_E_INVALID_ARG;
   if (!b->ws) return SBMT_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  const Shared sh = shared_of(b->L, b->ws);
+  const Shared sh = shared_of(b->L, b->ws, rb_index(b->tune.tile_rows));
   const ManySrc src = many_of(b);
   sbmt_status st = launch_front(b->L, src, dtab_of(b), sh, rb_index(b->tune.tile_rows), s);
   if (st != SBMT_OK) return st;
@@ -1474,7 +1672,7 @@ sbmt_status sbmt_batch_emit(sbmt_batch b, int64_t* sizes_dev, void* stream) {
   if (!b) return SBMT_E_INVALID_ARG;
   if (!b->ws) return SBMT_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  const Shared sh = shared_of(b->L, b->ws);
+  const Shared sh = shared_of(b->L, b->ws, rb_index(b->tune.tile_rows));
   const ManySrc src = many_of(b);
   sbmt_status st = launch_emit(b->L, src, dtab_of(b), sh, rb_index(b->tune.tile_rows), s);
   if (st != SBMT_OK) return st;
@@ -1492,10 +1690,10 @@ sbmt_status sbmt_batch_mesh(sbmt_batch b, int64_t* sizes_dev, void* stream) {
   if (!b->ws) return SBMT_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   const CallLayout& L = b->L;
-  const Shared sh = shared_of(L, b->ws);
+  const int rbi = rb_index(b->tune.tile_rows);
+  const Shared sh = shared_of(L, b->ws, rbi);
   const ManySrc src = many_of(b);
   const int64_t* dtab = dtab_of(b);
-  const int rbi = rb_index(b->tune.tile_rows);
   if (b->tune.strategy == SBMT_STRATEGY_MULTI || !L.fused_ok) {
     sbmt_status st = launch_front(L, src, dtab, sh, rbi, s);
     if (st != SBMT_OK) return st;
@@ -1508,11 +1706,12 @@ sbmt_status sbmt_batch_mesh(sbmt_batch b, int64_t* sizes_dev, void* stream) {
   const int64_t nbands = L.tab[(size_t)(4 + rbi) * (L.n + 1) + L.n];
   const int64_t* btab = dtab + (size_t)(4 + rbi) * (L.n + 1);
   uint32_t* halo = (uint32_t*)((char*)b->ws + L.off_halo);
+  const int64_t* ttab = dtab + (size_t)(1 + rbi) * (L.n + 1);
   const int grid = fused_groups(b);
   if (b->tune.tile_rows == 4)
-    hipLaunchKernelGGL((k_fused<4>), dim3(grid), dim3(kThreads), 0, s, src, btab, sh, nbands, halo);
+    hipLaunchKernelGGL((k_fused<4>), dim3(grid), dim3(kThreads), 0, s, src, btab, ttab, sh, nbands, halo);
   else
-    hipLaunchKernelGGL((k_fused<8>), dim3(grid), dim3(kThreads), 0, s, src, btab, sh, nbands, halo);
+    hipLaunchKernelGGL((k_fused<8>), dim3(grid), dim3(kThreads), 0, s, src, btab, ttab, sh, nbands, halo);
   if (sizes_dev) {
     const int64_t n4 = 4 * (int64_t)L.n;
     hipLaunchKernelGGL(k_copy_sizes, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, (const int64_t*)sh.sizes,

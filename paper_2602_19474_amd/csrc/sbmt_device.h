@@ -103,11 +103,6 @@ SBMT_HD int row_cell(int k, int h, int s) {
 // foreground->background transition to the next background->foreground one,
 // so background corners are cut off (foreground 8-connected at saddles).
 // Entry: count | (start0 | end0 << 2) << 2 | (start1 | end1 << 2) << 6.
-// Marching squares, corners in positive order TL, TR, BR, BL (bit 0..3); cell
-// edge midpoints 0 top, 1 right, 2 bottom, 3 left.  A segment runs from each
-// foreground->background transition to the next background->foreground one,
-// so background corners are cut off (foreground 8-connected at saddles).
-// Entry: count | (start0 | end0 << 2) << 2 | (start1 | end1 << 2) << 6.
 constexpr uint32_t ms_entry(int n, int a0, int b0, int a1, int b1) {
   return (uint32_t)(n | ((a0 | (b0 << 2)) << 2) | ((a1 | (b1 << 2)) << 6));
 }
@@ -662,6 +657,24 @@ SBMT_HD void put_vertex(double* verts, int64_t p, double x, double y) {
 #endif
 }
 
+// One output triangle as a single 12-byte store.
+struct __attribute__((aligned(4))) Tri3 {
+  int32_t a, b, c;
+};
+SBMT_HD void put_tri(int32_t* tris, int64_t u, int a, int b, int c) {
+#ifdef SBMT_HOST_EMUL
+  tris[3 * u] = a;
+  tris[3 * u + 1] = b;
+  tris[3 * u + 2] = c;
+#else
+  Tri3 x;
+  x.a = a;
+  x.b = b;
+  x.c = c;
+  *reinterpret_cast<Tri3*>(tris + 3 * u) = x;
+#endif
+}
+
 // Id of structural slot `sl` (see the emission table): a four-level select.
 SBMT_HD int slot_id(const int (&ids)[16], int sl) {
   const int b0 = sl & 1, b1 = sl & 2, b2 = sl & 4, b3 = sl & 8;
@@ -688,9 +701,8 @@ SBMT_HD void emit_cut(const Geo& g, const SlowRec& r, int t, const Nb& nb, int64
     const int side = (int)((w >> 12) & 1u);
     if (j < nt && (both || side)) {
       const int64_t u = tp - out.tbase;
-      out.t[3 * u + 0] = slot_id(ids, (int)(w & 15u));
-      out.t[3 * u + 1] = slot_id(ids, (int)((w >> 4) & 15u));
-      out.t[3 * u + 2] = slot_id(ids, (int)((w >> 8) & 15u));
+      put_tri(out.t, u, slot_id(ids, (int)(w & 15u)), slot_id(ids, (int)((w >> 4) & 15u)),
+              slot_id(ids, (int)((w >> 8) & 15u)));
       out.c[u] = (uint8_t)(cls | (side ? 0 : 0x80));
       ++tp;
     }
@@ -740,9 +752,7 @@ SBMT_HD void emit_slow(const Geo& g, const Frame& f, const SlowRec& r, const Nb&
     if (cls == 0) {
       if ((t == 0 ? info_ntb(info) : info_nta(info)) != 0) {
         const int64_t u = tp - out.tbase;
-        out.t[3 * u + 0] = nb.vid;
-        out.t[3 * u + 1] = t == 0 ? nb.id_vdr : nb.id_vr;
-        out.t[3 * u + 2] = t == 0 ? nb.id_vdl : nb.id_vdr;
+        put_tri(out.t, u, nb.vid, t == 0 ? nb.id_vdr : nb.id_vr, t == 0 ? nb.id_vdl : nb.id_vdr);
         out.c[u] = ucode;
         ++tp;
       }

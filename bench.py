@@ -14,7 +14,11 @@ Extra objects on the same line:
   cpu_baseline  the CPU oracle on a bounded sample of the same workload
   latency       p50/p99 per-image latency (plan + run + sync) of small images
   batch256      the 256-image batch workload: plain per-image loop and the
-                batched path (when available), triangles/s and MPix/s
+                batched path (autotuned, replayed as one captured graph),
+                triangles/s, MPix/s and HBM fraction
+  serve         the request stream: plain path per request (FIFO, one stream)
+                and the continuous-batching server, same Poisson arrivals,
+                p50/p99 latency (arrival -> device completion) and throughput
 """
 from __future__ import annotations
 
@@ -137,15 +141,17 @@ def latency(name: str, images, grid_h: int, repeats: int = 1):
             "tri_per_s": float(tri / (lat.sum() / 1e3))}
 
 
-def batch_section(items):
+def batch_section(items, repeats: int = 5):
     import torch
+
+    from paper_2602_19474_amd.batch import Batch
     n = len(items)
     gpu = [(torch.from_numpy(b).cuda(), gh) for b, gh in items]
     px = sum(b.size for b, _ in items)
-    plains = [Plain(g, gh) for g, gh in gpu]
-    torch.cuda.synchronize()
-    out = {"workload": f"batch{n}", "images": n, "mpix": px / 1e6}
+    out = {"workload": f"batch{n}", "images": n, "mpix": px / 1e6,
+           "grid_h_counts": {str(h): sum(1 for _, g in items if g == h) for h in (1, 2, 4)}}
     # plain: one plan + run per image, back to back on one stream
+    plains = [Plain(g, gh) for g, gh in gpu]
     for p in plains:
         p.step()
     torch.cuda.synchronize()
@@ -156,13 +162,118 @@ def batch_section(items):
         p.run()
     torch.cuda.synchronize()
     dt = time.perf_counter() - a
-    out["plain"] = {"tri_per_s": tri / dt, "mpix_per_s": px / 1e6 / dt, "ms": dt * 1e3, "triangles": tri}
-    try:
-        from paper_2602_19474_amd import batch as sbatch
-        out["batched"] = sbatch.bench([(g, gh) for g, gh in gpu], repeats=3)
-    except ImportError:
-        out["batched"] = None
+    alg = px + sum(16 * p.sizes.n_vertices + 13 * p.sizes.n_triangles for p in plains)
+    out["plain"] = {"tri_per_s": tri / dt, "mpix_per_s": px / 1e6 / dt, "ms": dt * 1e3, "triangles": tri,
+                    "hbm_frac": alg / dt / 1e9 / HBM_PEAK_GBS}
+    del plains
+    torch.cuda.empty_cache()
+    # batched: plan once for the sizes, autotune, capture the whole path in a graph
+    b = Batch(gpu)
+    sizes = b.plan()
+    b.allocate(sizes)
+    best, tuned_ms = b.tune(reps=3)
+    g = b.capture()
+    g.replay()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    w0 = time.perf_counter()
+    ev[0].record()
+    for _ in range(repeats):
+        g.replay()
+    ev[1].record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - w0) / repeats
+    ms = ev[0].elapsed_time(ev[1]) / repeats
+    st = b.sizes()
+    assert all(x[3] == 0 for x in st), "batched path reported a failure"
+    btri = sum(x[1] for x in st)
+    assert btri == tri, (btri, tri)
+    alg = px + sum(16 * x[0] + 13 * x[1] for x in st)
+    out["batched"] = {"tri_per_s": tri / (ms * 1e-3), "mpix_per_s": px / 1e6 / (ms * 1e-3), "ms": ms,
+                      "wall_ms": wall * 1e3, "triangles": tri, "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "tuning": best.__dict__, "launch": "one hipGraph replay per step",
+                      "workspace_gb": b.ws.numel() / 1e9}
+    out["speedup"] = out["batched"]["tri_per_s"] / out["plain"]["tri_per_s"]
+    del b, g
+    torch.cuda.empty_cache()
     return out
+
+
+def _gen_serve_item(j):
+    from paper_2602_19474_amd import workloads as wl
+    return wl.serve_request(j)
+
+
+def gen_serve_pool(n: int):
+    from concurrent.futures import ProcessPoolExecutor
+    workers = min(16, os.cpu_count() or 1)
+    with ProcessPoolExecutor(workers) as ex:
+        return list(ex.map(_gen_serve_item, range(n), chunksize=1))
+
+
+def serve_section(pool, n_requests: int, rates=(0.5, 0.8, 1.0), budget_gb: float = 64.0, streams: int = 3):
+    """Request stream over a pool of pre-generated requests sampled with replacement."""
+    import torch
+
+    from paper_2602_19474_amd import workloads as wl
+    from paper_2602_19474_amd.serve import GpuBackend, Server, latency_stats, run_plain, run_trace
+    gpu_pool = [(torch.from_numpy(b).cuda(), gh) for b, gh in pool]
+    pick = wl.rng(7, 0).integers(0, len(pool), size=n_requests)
+    items = [gpu_pool[j] for j in pick]
+    px = [gpu_pool[j][0].numel() for j in pick]
+    res = {"workload": f"serve{n_requests}", "requests": n_requests, "pool": len(pool),
+           "mean_mpix": float(np.mean(px)) / 1e6, "budget_gb": budget_gb, "streams": streams}
+    # plain saturation: back-to-back requests (all arrivals at 0)
+    warm = run_plain(items[:20], np.zeros(20))
+    sat = latency_stats(run_plain(items, np.zeros(n_requests)))
+    r_sat = sat["req_per_s"]
+    res["plain_saturation"] = {"req_per_s": r_sat, "tri_per_s": sat["tri_per_s"]}
+    log(f"serve: plain saturation {r_sat:.0f} req/s")
+    srv = Server(GpuBackend(0), budget_bytes=int(budget_gb * (1 << 30)), streams=streams, max_batch=64)
+    run_trace(srv, items[:64], np.zeros(64))  # warm-up
+    torch.cuda.synchronize()
+    for f in rates:
+        arr = wl.poisson_arrivals(n_requests, f * r_sat, item=int(f * 100))
+        plain = latency_stats(run_plain(items, arr))
+        reqs = run_trace(srv, items, arr)
+        rows = [(r.arrival, r.t_done, r.sizes[1]) for r in reqs]
+        served = latency_stats(rows)
+        served["batches"] = srv.batches
+        served["arena_peak_gb"] = srv.arena.peak / 1e9
+        res[f"rate_{f:.1f}"] = {"qps": f * r_sat, "plain": plain, "served": served}
+        log(f"serve: rate {f:.1f} R_sat plain p99 {plain['p99_ms']:.2f} ms served p99 {served['p99_ms']:.2f} ms")
+    # served saturation
+    reqs = run_trace(srv, items, np.zeros(n_requests))
+    sat_s = latency_stats([(r.arrival, r.t_done, r.sizes[1]) for r in reqs])
+    res["served_saturation"] = {"req_per_s": sat_s["req_per_s"], "tri_per_s": sat_s["tri_per_s"]}
+    del srv
+    torch.cuda.empty_cache()
+    return res
+
+
+def _oracle_tris(item):
+    import oracle
+    bm, gh = item
+    return int(oracle.mesh_from_bitmap(bm, gh).tris.shape[0])
+
+
+def cpu_baseline_pool(items, seconds: float = 15.0):
+    """The oracle over a process pool on all host cores (batch workload sample)."""
+    from concurrent.futures import ProcessPoolExecutor
+    cores = os.cpu_count() or 1
+    done_tri, done_px, n = 0, 0, 0
+    a = time.perf_counter()
+    with ProcessPoolExecutor(cores) as ex:
+        for j in range(0, len(items), cores):
+            chunk = items[j:j + cores]
+            done_tri += sum(ex.map(_oracle_tris, chunk))
+            done_px += sum(b.size for b, _ in chunk)
+            n += len(chunk)
+            if time.perf_counter() - a > seconds:
+                break
+    dt = time.perf_counter() - a
+    return {"value": done_tri / dt, "unit": "triangles/s", "mpix_per_s": done_px / 1e6 / dt, "cores": cores,
+            "kind": "oracle", "sample": f"first {n} images of the batch workload, one process per core"}
 
 
 def cpu_baseline(full: np.ndarray):
@@ -194,6 +305,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-pool", type=int, default=48)
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -210,9 +324,11 @@ def main():
     extras = None
     if not args.no_extras:
         t0 = time.time()
-        extras = {"disk64": [wl.disk(item=j) for j in range(200)],
-                  "ellipses1024": [wl.ellipses(item=j) for j in range(4)],
+        extras = {"disk64": [wl.disk(item=j) for j in range(1000)],
+                  "ellipses1024": [wl.ellipses(item=j) for j in range(8)],
                   "batch": gen_batch(args.batch)}
+        if not args.no_serve:
+            extras["serve"] = gen_serve_pool(args.serve_pool)
         log(f"extra workloads generated in {time.time() - t0:.1f}s")
     import torch
     torch.cuda.set_device(0)
@@ -261,13 +377,26 @@ def main():
         log("latency sections")
         res["latency"] = [
             latency("disk64", extras["disk64"], 1),
-            latency("ellipses1024", extras["ellipses1024"], 2, repeats=5),
+            latency("ellipses1024", extras["ellipses1024"], 2, repeats=10),
         ]
         log("batch section")
         res["batch"] = batch_section(extras["batch"])
+        if "serve" in extras:
+            log("serve section")
+            res["serve"] = serve_section(extras["serve"], args.serve_requests)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         res["cpu_baseline"] = cpu_baseline(noise)
+        if extras is not None:
+            res["batch"]["cpu_baseline"] = cpu_baseline_pool(extras["batch"])
+    res["inputs_sha256"] = {"noise8192": wl.sha256(noise)}
+    if extras is not None:
+        import hashlib
+        hb = hashlib.sha256()
+        for b, gh in extras["batch"]:
+            hb.update(wl.sha256(b).encode())
+            hb.update(bytes([gh]))
+        res["inputs_sha256"]["batch"] = hb.hexdigest()
     print(json.dumps(res), flush=True)
 
 

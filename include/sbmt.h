@@ -36,7 +36,11 @@
  *    the caller allocates and owns all of them (bitmap, workspace, outputs).
  *    The library never allocates device memory on these paths; the handle only
  *    owns a small pinned host buffer used to return sizes.
- *  - Calls on one handle must not overlap (the pinned buffer is shared).
+ *  - Calls on one handle must not overlap (the pinned buffers are shared);
+ *    batch objects keep a pointer to their handle, which must outlive them.
+ *    Pinned host buffers of batch objects come from a pool of the handle
+ *    and are reused, so a serving loop does not allocate pinned memory once
+ *    warm.
  *  - The workspace holds the coarse raster, one info word per lattice vertex
  *    whose sample window is not uniform, and 16-byte records of the owners
  *    classified exactly (by default room for a quarter of the owners).
@@ -137,6 +141,8 @@ sbmt_status sbmt_mesh_async(sbmt_handle h, const sbmt_image* img, void* workspac
  *                      optionally, output views) into the workspace; waits for
  *                      the copy, so it is not capturable
  *   sbmt_batch_plan    classify and count every image; waits; per-image sizes
+ *                      (sbmt_batch_plan_async + sbmt_batch_host_sizes: the
+ *                      same without waiting, for schedulers)
  *   sbmt_batch_emit    write the planned meshes (asynchronous, capturable)
  *   sbmt_batch_mesh    the whole path without a host round trip (asynchronous,
  *                      capturable): an image is written only if it fits its
@@ -184,6 +190,12 @@ sbmt_status sbmt_batch_bind(sbmt_batch b, void* workspace, size_t ws_bytes, cons
 /* out: n host sizes.  Returns SBMT_E_PROTOCOL / SBMT_E_INDEX_OVERFLOW if an
  * image has that status (its sizes are still reported). */
 sbmt_status sbmt_batch_plan(sbmt_batch b, sbmt_sizes* out, void* stream);
+/* Asynchronous plan: the sizes land in a pinned host buffer of the batch once
+ * the stream reaches this point (wait for an event recorded after this call,
+ * then read them with sbmt_batch_host_sizes). */
+sbmt_status sbmt_batch_plan_async(sbmt_batch b, void* stream);
+/* Reads the pinned copy written by the last sbmt_batch_plan_async (no wait). */
+sbmt_status sbmt_batch_host_sizes(sbmt_batch b, sbmt_sizes* out, int64_t* status);
 /* sizes_dev: device int64 [n][4] (n_vertices, n_triangles, n_cut, status) or NULL. */
 sbmt_status sbmt_batch_emit(sbmt_batch b, int64_t* sizes_dev, void* stream);
 sbmt_status sbmt_batch_mesh(sbmt_batch b, int64_t* sizes_dev, void* stream);

@@ -60,6 +60,7 @@ class Tuning(ctypes.Structure):
 
 EXPORTS = ("sbmt_create", "sbmt_destroy", "sbmt_query", "sbmt_plan", "sbmt_run", "sbmt_mesh_async",
            "sbmt_batch_create", "sbmt_batch_destroy", "sbmt_batch_bind", "sbmt_batch_plan", "sbmt_batch_emit",
+           "sbmt_batch_plan_async", "sbmt_batch_host_sizes",
            "sbmt_batch_mesh", "sbmt_batch_sizes", "sbmt_batch_get_tuning", "sbmt_batch_set_tuning",
            "sbmt_batch_tune", "sbmt_num_classes", "sbmt_class_code", "sbmt_status_string")
 
@@ -103,6 +104,10 @@ def lib():
     L.sbmt_batch_bind.argtypes = [vp, vp, sz, P(Outputs), vp]
     L.sbmt_batch_plan.restype = i32
     L.sbmt_batch_plan.argtypes = [vp, P(Sizes), vp]
+    L.sbmt_batch_plan_async.restype = i32
+    L.sbmt_batch_plan_async.argtypes = [vp, vp]
+    L.sbmt_batch_host_sizes.restype = i32
+    L.sbmt_batch_host_sizes.argtypes = [vp, P(Sizes), P(i64)]
     L.sbmt_batch_emit.restype = i32
     L.sbmt_batch_emit.argtypes = [vp, vp, vp]
     L.sbmt_batch_mesh.restype = i32

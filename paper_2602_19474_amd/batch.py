@@ -57,7 +57,10 @@ def _stream_ptr(stream):
 class Batch:
     """One batch object: images, workspace and (optionally) output views."""
 
-    def __init__(self, items, outputs=None, tuning: Tuning | None = None, flags: int = 0, ctx=None, stream=None):
+    def __init__(self, items, outputs=None, tuning: Tuning | None = None, flags: int = 0, ctx=None, stream=None,
+                 workspace=None, bind: bool = True):
+        """``workspace``: optional callable bytes -> uint8 CUDA tensor (e.g. an arena
+        sub-allocation); ``bind=False`` leaves binding to the caller."""
         from . import _image, context
         torch = _torch()
         self.items = [(t, int(h)) for t, h in items]
@@ -75,10 +78,13 @@ class Batch:
                                                 ctypes.byref(ws_bytes), ctypes.byref(b)), "sbmt_batch_create")
         self.handle = b
         self.n = n
-        self.ws = torch.empty(max(int(ws_bytes.value), 1), dtype=torch.uint8, device=dev)
+        self.ws_bytes = max(int(ws_bytes.value), 1)
+        self.ws = (workspace(self.ws_bytes) if workspace is not None
+                   else torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev))
         self.outputs = None
-        self.sizes_dev = torch.zeros((n, 4), dtype=torch.int64, device=dev)
-        self.bind(outputs, stream)
+        self._sizes_dev = None
+        if bind:
+            self.bind(outputs, stream)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -130,9 +136,28 @@ class Batch:
         _lib.check(_lib.lib().sbmt_batch_plan(self.handle, out, _stream_ptr(stream)), "sbmt_batch_plan")
         return list(out)
 
-    def emit(self, stream=None):
-        _lib.check(_lib.lib().sbmt_batch_emit(self.handle, self.sizes_dev.data_ptr(), _stream_ptr(stream)),
-                   "sbmt_batch_emit")
+    def plan_async(self, stream=None):
+        """Plan without waiting; read the sizes with host_sizes() once the stream got here."""
+        _lib.check(_lib.lib().sbmt_batch_plan_async(self.handle, _stream_ptr(stream)), "sbmt_batch_plan_async")
+
+    def host_sizes(self):
+        """(sizes, statuses) copied by the last plan_async (no wait: the caller synchronises)."""
+        out = (_lib.Sizes * self.n)()
+        st = (ctypes.c_int64 * self.n)()
+        _lib.check(_lib.lib().sbmt_batch_host_sizes(self.handle, out, st), "sbmt_batch_host_sizes")
+        return list(out), list(st)
+
+    @property
+    def sizes_dev(self):
+        """Device int64 [n, 4] that emit/mesh fill with (n_vertices, n_triangles, n_cut, status)."""
+        if self._sizes_dev is None:
+            torch = _torch()
+            self._sizes_dev = torch.zeros((self.n, 4), dtype=torch.int64, device=self.ws.device)
+        return self._sizes_dev
+
+    def emit(self, stream=None, sizes: bool = True):
+        ptr = self.sizes_dev.data_ptr() if sizes else None
+        _lib.check(_lib.lib().sbmt_batch_emit(self.handle, ptr, _stream_ptr(stream)), "sbmt_batch_emit")
 
     def mesh(self, stream=None):
         """The whole path without host synchronisation (capturable)."""

@@ -1424,10 +1424,42 @@ __global__ void k_copy_sizes(const int64_t* __restrict__ s, int64_t n4, int64_t*
 
 using namespace sbmt;
 
+// Pinned host buffers are allocated once per size class and recycled, so that
+// creating and destroying batch objects in a serving loop never calls the
+// (device-synchronising) pinned allocator after warm-up.
+struct PinnedPool {
+  std::vector<std::vector<void*>> free_;  // per size class 2^(12 + j) bytes
+  std::vector<void*> all_;
+  void* get(size_t bytes, int* cls) {
+    int j = 0;
+    while (((size_t)4096 << j) < bytes) ++j;
+    *cls = j;
+    if ((int)free_.size() <= j) free_.resize(j + 1);
+    if (!free_[j].empty()) {
+      void* p = free_[j].back();
+      free_[j].pop_back();
+      return p;
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, (size_t)4096 << j, hipHostMallocDefault) != hipSuccess) return nullptr;
+    all_.push_back(p);
+    return p;
+  }
+  void put(void* p, int cls) {
+    if (p) free_[cls].push_back(p);
+  }
+  void release() {
+    for (void* p : all_) (void)hipHostFree(p);
+    all_.clear();
+    free_.clear();
+  }
+};
+
 struct sbmt_context {
   int device;
   int cus;
   long long* pinned;  // 8 x int64
+  PinnedPool pool;
 };
 
 struct sbmt_batch_s {
@@ -1440,6 +1472,7 @@ struct sbmt_batch_s {
   unsigned char* stage = nullptr;  // pinned: descriptors + tables
   size_t stage_bytes = 0;
   int64_t* psizes = nullptr;       // pinned: n x 4
+  int stage_cls = 0, psizes_cls = 0;
 };
 
 static bool tuning_valid(const sbmt_tuning* t) {
@@ -1483,6 +1516,7 @@ sbmt_status sbmt_create(int device, sbmt_handle* out) {
 sbmt_status sbmt_destroy(sbmt_handle h) {
   if (!h) return SBMT_E_INVALID_ARG;
   if (h->pinned) (void)hipHostFree(h->pinned);
+  h->pool.release();
   free(h);
   return SBMT_OK;
 }
@@ -1593,12 +1627,11 @@ sbmt_status sbmt_batch_create(sbmt_handle h, const sbmt_image* imgs, int32_t n, 
   if (t.strategy == SBMT_STRATEGY_FUSED && !b->L.fused_ok) t.strategy = SBMT_STRATEGY_MULTI;
   b->tune = t;
   b->stage_bytes = b->L.off_cnt - b->L.off_desc;
-  if (hipHostMalloc((void**)&b->stage, b->stage_bytes, hipHostMallocDefault) != hipSuccess) {
-    delete b;
-    return SBMT_E_DEVICE;
-  }
-  if (hipHostMalloc((void**)&b->psizes, (size_t)n * 4 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
-    (void)hipHostFree(b->stage);
+  b->stage = (unsigned char*)h->pool.get(b->stage_bytes, &b->stage_cls);
+  b->psizes = (int64_t*)h->pool.get((size_t)n * 4 * sizeof(int64_t), &b->psizes_cls);
+  if (!b->stage || !b->psizes) {
+    h->pool.put(b->stage, b->stage_cls);
+    h->pool.put(b->psizes, b->psizes_cls);
     delete b;
     return SBMT_E_DEVICE;
   }
@@ -1609,8 +1642,8 @@ sbmt_status sbmt_batch_create(sbmt_handle h, const sbmt_image* imgs, int32_t n, 
 
 sbmt_status sbmt_batch_destroy(sbmt_batch b) {
   if (!b) return SBMT_E_INVALID_ARG;
-  if (b->stage) (void)hipHostFree(b->stage);
-  if (b->psizes) (void)hipHostFree(b->psizes);
+  b->ctx->pool.put(b->stage, b->stage_cls);
+  b->ctx->pool.put(b->psizes, b->psizes_cls);
   delete b;
   return SBMT_OK;
 }
@@ -1666,6 +1699,31 @@ sbmt_status sbmt_batch_plan(sbmt_batch b, sbmt_sizes* out, void* stream) {
     if (sti == SBMT_E_INDEX_OVERFLOW && worst == SBMT_OK) worst = SBMT_E_INDEX_OVERFLOW;
   }
   return worst;
+}
+
+sbmt_status sbmt_batch_plan_async(sbmt_batch b, void* stream) {
+  if (!b) return SBMT_E_INVALID_ARG;
+  if (!b->ws) return SBMT_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  const Shared sh = shared_of(b->L, b->ws, rb_index(b->tune.tile_rows));
+  const ManySrc src = many_of(b);
+  sbmt_status st = launch_front(b->L, src, dtab_of(b), sh, rb_index(b->tune.tile_rows), s);
+  if (st != SBMT_OK) return st;
+  if ((st = launch_sizes(b->L, src, sh, nullptr, s)) != SBMT_OK) return st;
+  const size_t bytes = (size_t)b->L.n * 4 * sizeof(int64_t);
+  if (hipMemcpyAsync(b->psizes, sh.sizes, bytes, hipMemcpyDeviceToHost, s) != hipSuccess) return SBMT_E_DEVICE;
+  return SBMT_OK;
+}
+
+sbmt_status sbmt_batch_host_sizes(sbmt_batch b, sbmt_sizes* out, int64_t* status) {
+  if (!b || !out) return SBMT_E_INVALID_ARG;
+  for (int i = 0; i < b->L.n; ++i) {
+    out[i].n_vertices = b->psizes[4 * i + 0];
+    out[i].n_triangles = b->psizes[4 * i + 1];
+    out[i].n_cut = b->psizes[4 * i + 2];
+    if (status) status[i] = b->psizes[4 * i + 3];
+  }
+  return SBMT_OK;
 }
 
 sbmt_status sbmt_batch_emit(sbmt_batch b, int64_t* sizes_dev, void* stream) {

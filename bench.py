@@ -90,6 +90,34 @@ class Plain:
         return W * H + 16 * self.sizes.n_vertices + 13 * self.sizes.n_triangles
 
 
+def kernel_source_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for fn in ("sbmt.hip", "sbmt_device.h", "sbmt_tables.h"):
+        with open(os.path.join(ROOT, "paper_2602_19474_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_emit launch from the committed rocprofv3 counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "noise8192_hbm_traffic.md")
+    try:
+        kv = {}
+        with open(path) as f:
+            for line in f:
+                if ":" in line and not line.startswith(("#", "|", " ")):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("source_sha256") != kernel_source_sha256():
+            return None, "profiles/noise8192_hbm_traffic.md (stale: kernel sources changed)"
+        return int(kv["fetch_bytes_per_launch"]) + int(kv["write_bytes_per_launch"]), \
+            "profiles/noise8192_hbm_traffic.md"
+    except (OSError, KeyError, ValueError):
+        return None, None
+
+
 def headline(bm: np.ndarray, steps: int, warmup: int):
     import torch
     t = torch.from_numpy(bm).cuda()
@@ -348,6 +376,7 @@ def main():
     emit_bytes = 16 * sz.n_vertices + 13 * sz.n_triangles
     achieved = emit_bytes / (H["emit_ms"] * 1e-3) / 1e9
     path_bytes = H["plain"].alg_bytes()
+    traffic, traffic_src = measured_traffic()
     res = {
         "metric": "output triangles/s (plain single image; batched and latency below)",
         "value": sz.n_triangles / (ms * 1e-3),
@@ -369,8 +398,8 @@ def main():
         "emit_ms": H["emit_ms"],
         "path_hbm_frac": path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "kernel": "k_emit", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "alg_bytes_per_launch": emit_bytes},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_source": traffic_src, "alg_bytes_per_launch": emit_bytes},
     }
     del H
     if extras is not None:

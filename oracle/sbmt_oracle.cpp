@@ -31,6 +31,11 @@
 // marching squares on a block-majority coarsened raster, rotation-only
 // canonicalisation, the template rule for free cases, output numbering) are
 // listed in the repository's design notes and restated where they are used.
+//
+// Parity unpinned: the minimum-angle and minimum-area bounds of App. D hold
+// only after the preprocessing of Alg. 3, which this path does not run (the
+// "all rules off" regime of the ablation); meshes are checked for positive
+// area and orientation only, not against those bounds.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>

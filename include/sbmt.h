@@ -43,7 +43,7 @@
  *    warm.
  *  - The workspace holds the coarse raster, one info word per lattice vertex
  *    whose sample window is not uniform, and 16-byte records of the owners
- *    classified exactly (by default room for a quarter of the owners).
+ *    classified exactly (by default room for half of the owners).
  *
  * Errors
  *  - Every call returns an sbmt_status.  Arguments are validated before any
@@ -174,7 +174,7 @@ typedef struct {
   int32_t groups_per_cu; /* fused: resident workgroups per compute unit (0 = default) */
   int32_t reserved;
   int64_t record_cap;    /* slow-owner records in the workspace: 0 = default
-                            (a quarter of the owners), > 0 = that many; owners
+                            (half of the owners), > 0 = that many; owners
                             beyond it are classified where they are needed */
 } sbmt_tuning;
 

@@ -244,6 +244,7 @@ __device__ __forceinline__ T wave_incl_scan(T v, int lane) {
 template <int RB>
 struct CountLds {
   int acc[RB][4];
+  uint32_t u0[RB][kWinWords], u1[RB][kWinWords];  // uniform-window masks per row
   alignas(4) uint8_t code[RB][kCB];
   int rowR[RB];
   uint16_t q1[RB * kCB];
@@ -268,6 +269,11 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
   const Bits bw = stage_window(g, d.bits, L.win, L.rowR[0] + kRing, L.rowR[klast - k0] + 2 + kRing, c0,
                                min(c0 + kCB, g.NI) - 1);
   __syncthreads();
+  for (int t = threadIdx.x; t < (klast - k0 + 1) * bw.wpr; t += kThreads) {
+    const int r = t / bw.wpr, w = t - r * bw.wpr;
+    window_masks_word(bw, L.rowR[r] + kRing, w, L.u0[r][w], L.u1[r][w]);
+  }
+  __syncthreads();
   // uniform windows, one owner per thread; the others are queued
   for (int r = 0; r < RB; ++r) {
     const int k = k0 + r;
@@ -275,9 +281,9 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
     int nv = 0, nt = 0;
     const int c = c0 + threadIdx.x;
     if (c < g.NI) {
-      const Frame f = owner_frame(g, bw, k, c, L.rowR[r]);
-      if (frame_uniform(f)) {
-        const uint32_t fi = fast_info(g, f);
+      const int kind = window_kind(g, bw, L.u0[r], L.u1[r], g.X0 + 4 * g.h * c + 2 * g.h * (k & 1));
+      if (kind) {
+        const uint32_t fi = fast_info_k(g, k, c, kind >> 1);
         nv = info_nv(fi);
         nt = info_nt(fi);
         L.code[r][threadIdx.x] = (uint8_t)owner_code(fi);
@@ -723,14 +729,15 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, in
   int ev[RB + 1], et[RB + 1];
 #pragma unroll
   for (int rr = 0; rr <= RB; ++rr) {
+    // vertices and triangles of a row segment stay below 2^16: one packed scan
     const uint32_t f = L.info[rr][1 + threadIdx.x];
-    const int sv = info_nv(f), st = info_nt(f);
-    const int iv = wave_incl_scan(sv, lane), it = wave_incl_scan(st, lane);
-    ev[rr] = iv - sv;
-    et[rr] = it - st;
+    const int sp = info_nv(f) | (info_nt(f) << 16);
+    const int ip = wave_incl_scan(sp, lane);
+    ev[rr] = (ip - sp) & 0xffff;
+    et[rr] = (ip - sp) >> 16;
     if (lane == 63) {
-      L.part[rr][0][wv] = iv;
-      L.part[rr][1][wv] = it;
+      L.part[rr][0][wv] = ip & 0xffff;
+      L.part[rr][1][wv] = ip >> 16;
     }
   }
   __syncthreads();
@@ -950,6 +957,11 @@ __global__ void __launch_bounds__(kThreads) k_fused(ManySrc src, const int64_t* 
       const Bits bw = stage_window(g, d.bits, C.win, C.rowR[0] + kRing, C.rowR[klast - k0] + 2 + kRing, c0,
                                    min(c0 + kCB, g.NI) - 1);
       __syncthreads();
+      for (int t = threadIdx.x; t < (klast - k0 + 1) * bw.wpr; t += kThreads) {
+        const int r = t / bw.wpr, w = t - r * bw.wpr;
+        window_masks_word(bw, C.rowR[r] + kRing, w, C.u0[r][w], C.u1[r][w]);
+      }
+      __syncthreads();
       const int lane = threadIdx.x & 63;
       for (int r = 0; r <= RB; ++r) {
         const int k = k0 + r;
@@ -957,9 +969,9 @@ __global__ void __launch_bounds__(kThreads) k_fused(ManySrc src, const int64_t* 
         int nv = 0, nt = 0;
         const int c = c0 + threadIdx.x;
         if (c < g.NI) {
-          const Frame f = owner_frame(g, bw, k, c, C.rowR[r]);
-          if (frame_uniform(f)) {
-            const uint32_t fi = fast_info(g, f);
+          const int kind = window_kind(g, bw, C.u0[r], C.u1[r], g.X0 + 4 * g.h * c + 2 * g.h * (k & 1));
+          if (kind) {
+            const uint32_t fi = fast_info_k(g, k, c, kind >> 1);
             nv = info_nv(fi);
             nt = info_nt(fi);
           } else {
@@ -1276,11 +1288,12 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
     if (g.NCB > kMaxBandChunks || 10LL * g.NK * g.NI > 0x7fffffffLL) L.fused_ok = false;
   }
   L.nbands_max = tab_row(L, 4)[n];
-  // records: by default a quarter of each tile's owners; an explicit cap is
+  // records: by default half of each tile's owners (the slow fraction reaches
+  // about a third at grid_h = 4 on fine structures); an explicit cap is
   // shared evenly by the tiles
   for (int r = 0; r < 3; ++r) L.ntiles_max = std::max(L.ntiles_max, tab_row(L, 1 + r)[n]);
   if (record_cap == 0) {
-    for (int r = 0; r < 3; ++r) L.rcap = std::max(L.rcap, tab_row(L, 1 + r)[n] * (int64_t)(kRBs[r] * kCB / 4));
+    for (int r = 0; r < 3; ++r) L.rcap = std::max(L.rcap, tab_row(L, 1 + r)[n] * (int64_t)(kRBs[r] * kCB / 2));
   } else {
     L.rcap = std::max<int64_t>(record_cap, 0);
   }

@@ -183,16 +183,42 @@ SBMT_HD Frame owner_frame(const Geo& g, const Bits& bits, int k, int i, int Rlo)
 
 SBMT_HD bool frame_uniform(const Frame& f) { return f.s9 == 0u || f.s9 == 0x1ffu; }
 
-// Counts of an owner whose window is uniform.
-SBMT_HD uint32_t fast_info(const Geo& g, const Frame& f) {
+// Counts of owner (k, i) whose window is uniform with inside bit fg.
+SBMT_HD uint32_t fast_info_k(const Geo& g, int k, int i, int fg) {
   const bool both = (g.flags & 1u) != 0;
-  const int fg = f.s9 != 0u;
-  const bool tb_ok = (f.k + 1 < g.NK) && (f.i + f.o - 1 >= 0) && (f.i + f.o < g.NI);
-  const bool ta_ok = (f.k + 1 < g.NK) && (f.i + 1 < g.NI) && (f.i + f.o < g.NI);
+  const int o = k & 1;
+  const bool tb_ok = (k + 1 < g.NK) && (i + o - 1 >= 0) && (i + o < g.NI);
+  const bool ta_ok = (k + 1 < g.NK) && (i + 1 < g.NI) && (i + o < g.NI);
   const int self = both ? 1 : fg;
   const int ntb = (both || fg) ? (int)tb_ok : 0;
   const int nta = (both || fg) ? (int)ta_ok : 0;
   return (uint32_t)self | ((uint32_t)ntb << 9) | ((uint32_t)nta << 12) | ((uint32_t)fg << 16);
+}
+SBMT_HD uint32_t fast_info(const Geo& g, const Frame& f) { return fast_info_k(g, f.k, f.i, f.s9 != 0u); }
+
+// Uniform-window masks of one grid row, for the tile kernels: bit (cc - cc0)
+// of u0[w] / u1[w] is set when the samples of columns cc .. cc+2 in the three
+// sample rows starting at the row's Rlo are all background / all foreground.
+// An owner with window column Clo is then uniform iff its bit is set in one of
+// them (window_kind).
+SBMT_HD void window_masks_word(const Bits& b, int rr, int w, uint32_t& u0, uint32_t& u1) {
+  const uint32_t* p0 = b.p + (rr - b.rr0) * b.wpr;
+  const uint32_t* p1 = p0 + b.wpr;
+  const uint32_t* p2 = p1 + b.wpr;
+  const uint32_t o = p0[w] | p1[w] | p2[w], a = p0[w] & p1[w] & p2[w];
+  const bool nx = w + 1 < b.wpr;
+  const uint32_t on = nx ? (p0[w + 1] | p1[w + 1] | p2[w + 1]) : 0u;
+  const uint32_t an = nx ? (p0[w + 1] & p1[w + 1] & p2[w + 1]) : 0u;
+  const uint32_t x = o | ((o >> 1) | (on << 31)) | ((o >> 2) | (on << 30));
+  const uint32_t y = a & ((a >> 1) | (an << 31)) & ((a >> 2) | (an << 30));
+  u0 = ~x;
+  u1 = y;
+}
+// 0: window not uniform, 1: all background, 2: all foreground.
+SBMT_HD int window_kind(const Geo& g, const Bits& b, const uint32_t* u0, const uint32_t* u1, int X) {
+  const int c = clo_of(g, X) + kRingC - b.cc0;
+  const int w = c >> 5, sh = c & 31;
+  return (int)((u0[w] >> sh) & 1u) | ((int)((u1[w] >> sh) & 1u) << 1);
 }
 
 // ---------------------------------------------------------------------------

@@ -41,9 +41,10 @@
  *    Pinned host buffers of batch objects come from a pool of the handle
  *    and are reused, so a serving loop does not allocate pinned memory once
  *    warm.
- *  - The workspace holds the coarse raster, one info word per lattice vertex
- *    whose sample window is not uniform, and 16-byte records of the owners
- *    classified exactly (by default room for half of the owners).
+ *  - The workspace holds the coarse raster, a two-byte code per lattice
+ *    vertex, a four-byte word per lattice vertex for the persistent batch
+ *    kernel, and 16-byte records of the owners classified exactly (by
+ *    default room for half of the owners).
  *
  * Errors
  *  - Every call returns an sbmt_status.  Arguments are validated before any
@@ -196,7 +197,9 @@ sbmt_status sbmt_batch_plan(sbmt_batch b, sbmt_sizes* out, void* stream);
 sbmt_status sbmt_batch_plan_async(sbmt_batch b, void* stream);
 /* Reads the pinned copy written by the last sbmt_batch_plan_async (no wait). */
 sbmt_status sbmt_batch_host_sizes(sbmt_batch b, sbmt_sizes* out, int64_t* status);
-/* sizes_dev: device int64 [n][4] (n_vertices, n_triangles, n_cut, status) or NULL. */
+/* sizes_dev: device int64 [n][4] (n_vertices, n_triangles, n_cut, status) or NULL.
+ * Emits what the last plan of this batch counted (with that plan's tile
+ * height); SBMT_E_INVALID_ARG if the batch was never planned. */
 sbmt_status sbmt_batch_emit(sbmt_batch b, int64_t* sizes_dev, void* stream);
 sbmt_status sbmt_batch_mesh(sbmt_batch b, int64_t* sizes_dev, void* stream);
 /* Host copy of the last call's per-image sizes and statuses (waits). */

@@ -66,7 +66,7 @@ struct Img {
   const uint8_t* bm;  // bitmap rows (device)
   uint32_t* bits;     // coarse raster, (CH + 2 kRing) rows of wpr words
   uint32_t* oinfo;    // [NK][NI] record index of slow owners (fused path: info of non-uniform owners)
-  uint8_t* omap;      // [NK][NI] one code per owner (multi-kernel path), see owner_code
+  uint16_t* omap;     // [NK][NI] owner map of the multi-kernel path, see map_code
   int64_t seg0;       // first row segment of the image in the call's segment arrays
   int64_t band0;      // first band of the image (fused path, 4-row numbering)
   int64_t halo0;      // first word of the image's halo rows (fused path)
@@ -125,14 +125,16 @@ SBMT_HD unsigned long long pack_counts(uint32_t info) {
          ((unsigned long long)info_ncut(info) << 42);
 }
 
-// One byte per owner: bit 0 vertex emitted, 1 base triangle Tb emitted, 2 Ta
-// emitted, 3 owner vertex inside, 7 slow owner (its counts are in its record).
-SBMT_HD uint32_t owner_code(uint32_t info) {
-  return (uint32_t)info_self(info) | ((uint32_t)info_ntb(info) << 1) | ((uint32_t)info_nta(info) << 2) |
-         ((uint32_t)info_fg(info) << 3);
+// Owner map of the multi-kernel path, two bytes per owner: bits 0-14 of the
+// info word (vertex, crossing counts, chain vertices, triangle counts) and bit
+// 15 = slow.  Owners that are not slow have no chain vertex, so their bit 7
+// carries the inside bit instead.  k_count writes every owner's code (slow
+// ones with a record as a bare 0x8000), k_slow the codes of its owners.
+SBMT_HD uint32_t map_code(uint32_t info) {
+  return info_slow(info) ? (info & 0xffffu) : ((info & 0x7f7fu) | ((uint32_t)info_fg(info) << 7));
 }
-SBMT_HD uint32_t code_info(uint32_t code) {
-  return (code & 1u) | (((code >> 1) & 1u) << 9) | (((code >> 2) & 1u) << 12) | (((code >> 3) & 1u) << 16);
+SBMT_HD uint32_t map_info(uint32_t code) {
+  return (code & 0x8000u) ? code : ((code & 0x7f7fu) | (((code >> 7) & 1u) << 16));
 }
 
 // Owner frame without the samples: what emission needs of a slow owner.
@@ -245,7 +247,7 @@ template <int RB>
 struct CountLds {
   int acc[RB][4];
   uint32_t u0[RB][kWinWords], u1[RB][kWinWords];  // uniform-window masks per row
-  alignas(4) uint8_t code[RB][kCB];
+  alignas(8) uint16_t code[RB][kCB];
   int rowR[RB];
   uint16_t q1[RB * kCB];
   uint16_t q2[RB * kCB];
@@ -286,7 +288,7 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
         const uint32_t fi = fast_info_k(g, k, c, kind >> 1);
         nv = info_nv(fi);
         nt = info_nt(fi);
-        L.code[r][threadIdx.x] = (uint8_t)owner_code(fi);
+        L.code[r][threadIdx.x] = (uint16_t)map_code(fi);
       } else {
         L.q1[atomicAdd(&L.n1, 1)] = (uint16_t)(r * kCB + threadIdx.x);
       }
@@ -307,44 +309,43 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
     uint32_t fi = 0;
     if (needs_slow(g, f, fi)) {
       L.q2[atomicAdd(&L.n2, 1)] = (uint16_t)e;
-      L.code[r][e - r * kCB] = 0x80;
+      L.code[r][e - r * kCB] = 0x8000;
     } else {
-      L.code[r][e - r * kCB] = (uint8_t)owner_code(fi);
+      L.code[r][e - r * kCB] = (uint16_t)map_code(fi);
       atomicAdd(&L.acc[r][0], info_nv(fi));
       atomicAdd(&L.acc[r][1], info_nt(fi));
     }
   }
   __syncthreads();
-  // the tile's owner codes, one 4-byte word per lane and row
-  for (int t = threadIdx.x; t < RB * (kCB / 4); t += kThreads) {
-    const int r = t / (kCB / 4), c = c0 + 4 * (t - r * (kCB / 4));
-    const int k = k0 + r;
-    if (k >= g.NK || c >= g.NI) continue;
-    uint8_t* dst = d.omap + (int64_t)k * g.NI + c;
-    const uint8_t* src = &L.code[r][c - c0];
-    if (c + 4 <= g.NI && ((((int64_t)k * g.NI + c) & 3) == 0)) {
-      *reinterpret_cast<uint32_t*>(dst) = *reinterpret_cast<const uint32_t*>(src);
-    } else {
-      for (int u = 0; u < 4 && c + u < g.NI; ++u) dst[u] = src[u];
-    }
-  }
   if (threadIdx.x == 0) sh.tile_n[tile] = L.n2;
   for (int q = threadIdx.x; q < L.n2; q += kThreads) {
     const int e = L.q2[q], r = e / kCB, c = c0 + (e - r * kCB);
     const int k = k0 + r;
-    const int64_t idx = tile * sh.tcap + q;
     if (q < sh.tcap) {
-      sh.rec[idx].x = (uint64_t)c | ((uint64_t)k << 24) | ((uint64_t)ii << 48);
-      d.oinfo[(int64_t)k * g.NI + c] = kSlowBit | (uint32_t)idx;
+      sh.rec[tile * sh.tcap + q].x = (uint64_t)c | ((uint64_t)k << 24) | ((uint64_t)ii << 48);
     } else {
       const Frame f = owner_frame(g, bw, k, c, L.rowR[r]);
       Slow sr;
       slow_classify(g, f, sr);
-      d.oinfo[(int64_t)k * g.NI + c] = kSlowBit | kNoRec;
+      L.code[r][e - r * kCB] = (uint16_t)map_code(sr.info);
       atomicAdd(&L.acc[r][0], info_nv(sr.info));
       atomicAdd(&L.acc[r][1], info_nt(sr.info));
       atomicAdd(&L.acc[r][2], info_ncut(sr.info));
       if (info_err(sr.info)) atomicOr(&L.acc[r][3], 1);
+    }
+  }
+  __syncthreads();
+  // the tile's owner codes, four per lane and row
+  for (int t = threadIdx.x; t < RB * (kCB / 4); t += kThreads) {
+    const int r = t / (kCB / 4), c = c0 + 4 * (t - r * (kCB / 4));
+    const int k = k0 + r;
+    if (k >= g.NK || c >= g.NI) continue;
+    uint16_t* dst = d.omap + (int64_t)k * g.NI + c;
+    const uint16_t* src = &L.code[r][c - c0];
+    if (c + 4 <= g.NI && ((((int64_t)k * g.NI + c) & 3) == 0)) {
+      *reinterpret_cast<uint2*>(dst) = *reinterpret_cast<const uint2*>(src);
+    } else {
+      for (int u = 0; u < 4 && c + u < g.NI; ++u) dst[u] = src[u];
     }
   }
   __syncthreads();
@@ -399,7 +400,11 @@ __global__ void __launch_bounds__(64) k_slow(Src src, const int64_t* __restrict_
     const Frame f = owner_frame(g, b, k, c, row_cell(k, g.h, g.s));
     Slow sr;
     slow_classify(g, f, sr);
-    sh.rec[idx] = pack_slow(sr);
+    SlowRec R = pack_slow(sr);
+    // the owner's place in the tile rides in the record's spare bits 48..63
+    R.x |= (uint64_t)(((k - ky * RB) << 8) | (c - cb * kCB)) << 48;
+    sh.rec[idx] = R;
+    d.omap[(int64_t)k * g.NI + c] = (uint16_t)map_code(sr.info);
     atomicAdd(&acc[k - ky * RB], pack_counts(sr.info));
     if (info_err(sr.info)) atomicOr(&sh.imgerr[ii], 1);
   }
@@ -579,6 +584,7 @@ struct EmitLds {
   uint32_t win[kWinRows * kWinWords];
   uint16_t qa[(RB + 1) * W];  // slow owners without a record
   uint16_t qs[RB * kCB];      // slow owners to emit
+  uint32_t hasrec[RB * kCB / 32];
   int na, ns;
   int rowR[RB + 1];
   int bv[RB + 1];
@@ -591,7 +597,7 @@ struct EmitLds {
 // otherwise from the samples, with non-uniform owners' info words in oinfo
 // and, for the halo row, in hrow (fused path).
 template <int RB, bool MAP>
-__device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, int cb, const Shared& sh,
+__device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, int cb, int64_t tile, const Shared& sh,
                                           EmitLds<RB>& L, const uint32_t* __restrict__ hrow) {
   constexpr int W = EmitLds<RB>::W;
   const int k0 = ky * RB;
@@ -616,17 +622,25 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, in
   constexpr int kHold = 2;
   uint32_t codes[kPer];
   SlowRec held[kHold];
-  int hidx[kHold];
-  uint32_t hri[kHold];
+  int nrec = 0;
+  bool hv[kHold];
   if (MAP) {
-    // all code loads of the thread first, so their latencies overlap
+    // all loads of the thread first (owner codes of the window and the
+    // tile's records), so their latencies overlap
+    nrec = (int)min((int64_t)sh.tile_n[tile], sh.tcap);
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
       const int idx = threadIdx.x + j * kThreads;
       const int rr = idx / W, col = idx - rr * W;
       const int k = k0 + rr, c = c0 - 1 + col;
       codes[j] = (idx < (RB + 1) * W && k < g.NK && c >= 0 && c < g.NI) ? (uint32_t)d.omap[(int64_t)k * g.NI + c]
-                                                                        : 0xffu;
+                                                                        : 0xffffffffu;
+    }
+#pragma unroll
+    for (int j = 0; j < kHold; ++j) {
+      const int q = threadIdx.x + j * kThreads;
+      hv[j] = q < nrec;
+      if (hv[j]) held[j] = sh.rec[tile * sh.tcap + q];
     }
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
@@ -634,55 +648,9 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, in
       if (idx >= (RB + 1) * W) break;
       const int rr = idx / W, col = idx - rr * W;
       uint32_t fi = 0;
-      if (codes[j] != 0xffu) {
-        if (!(codes[j] & 0x80u)) {
-          fi = code_info(codes[j]);
-        } else {
-          L.qa[atomicAdd(&L.na, 1)] = (uint16_t)idx;  // record looked up below
-        }
-      }
-      L.info[rr][col] = fi;
-    }
-    __syncthreads();
-    // slow owners: record index, then the record (or a classification); the
-    // first kHold per thread stay in registers for emission
-#pragma unroll
-    for (int j = 0; j < kHold; ++j) {
-      const int q = threadIdx.x + j * kThreads;
-      hidx[j] = q < L.na ? L.qa[q] : -1;
-      hri[j] = kNoRec;
-      if (hidx[j] >= 0) {
-        const int rr = hidx[j] / W, col = hidx[j] - rr * W;
-        hri[j] = d.oinfo[(int64_t)(k0 + rr) * g.NI + c0 - 1 + col] & kNoRec;
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < kHold; ++j)
-      if (hidx[j] >= 0 && hri[j] != kNoRec) held[j] = sh.rec[hri[j]];
-#pragma unroll
-    for (int j = 0; j < kHold; ++j) {
-      if (hidx[j] < 0) continue;
-      const int rr = hidx[j] / W, col = hidx[j] - rr * W;
-      if (hri[j] == kNoRec) {
-        const Frame f = owner_frame(g, bw, k0 + rr, c0 - 1 + col, L.rowR[rr]);
-        Slow sr;
-        slow_classify(g, f, sr);
-        held[j] = pack_slow(sr);
-      }
-      L.info[rr][col] = held[j].info;
-    }
-    for (int q = threadIdx.x + kHold * kThreads; q < L.na; q += kThreads) {
-      const int idx = L.qa[q], rr = idx / W, col = idx - rr * W;
-      const int k = k0 + rr, c = c0 - 1 + col;
-      const uint32_t ri = d.oinfo[(int64_t)k * g.NI + c] & kNoRec;
-      uint32_t fi;
-      if (ri != kNoRec) {
-        fi = sh.rec[ri].info;
-      } else {
-        const Frame f = owner_frame(g, bw, k, c, L.rowR[rr]);
-        Slow sr;
-        slow_classify(g, f, sr);
-        fi = sr.info;
+      if (codes[j] != 0xffffffffu) {
+        fi = map_info(codes[j]);
+        if ((codes[j] & 0x8000u) && rr < RB && col >= 1 && col <= kCB) atomicAdd(&L.na, 1);  // owned slow owners
       }
       L.info[rr][col] = fi;
     }
@@ -816,34 +784,39 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, in
     }
   }
   if (MAP) {
-    // held records, then any further slow owners of the tile
+    // the tile's records (held ones, then the rest), each at its place
+    auto emit_rec = [&](const SlowRec& R) {
+      const int pos = (int)(R.x >> 48);
+      const int r = pos >> 8, col = (pos & 255) + 1;
+      const int k = k0 + r, c = c0 + col - 1;
+      const Nb nb = neighbours(r, col, L.info[r][col], k & 1);
+      emit_slow(g, owner_place(g, k, c, L.rowR[r]), R, nb, L.tb[r] + L.toff[r][col], out);
+    };
 #pragma unroll
-    for (int j = 0; j < kHold; ++j) {
-      if (hidx[j] < 0) continue;
-      const int r = hidx[j] / W, col = hidx[j] - r * W;
-      if (r >= RB || col < 1 || col > kCB) continue;
-      const int k = k0 + r, c = c0 + col - 1;
-      const Nb nb = neighbours(r, col, L.info[r][col], k & 1);
-      emit_slow(g, owner_place(g, k, c, L.rowR[r]), held[j], nb, L.tb[r] + L.toff[r][col], out);
-    }
-    for (int q = threadIdx.x + kHold * kThreads; q < L.na; q += kThreads) {
-      const int idx = L.qa[q], r = idx / W, col = idx - r * W;
-      if (r >= RB || col < 1 || col > kCB) continue;
-      const int k = k0 + r, c = c0 + col - 1;
-      const Nb nb = neighbours(r, col, L.info[r][col], k & 1);
-      const uint32_t ri = d.oinfo[(int64_t)k * g.NI + c] & kNoRec;
-      SlowRec R;
-      Frame fr;
-      if (ri != kNoRec) {
-        R = sh.rec[ri];
-        fr = owner_place(g, k, c, L.rowR[r]);
-      } else {
-        fr = owner_frame(g, bw, k, c, L.rowR[r]);
+    for (int j = 0; j < kHold; ++j)
+      if (hv[j]) emit_rec(held[j]);
+    for (int q = threadIdx.x + kHold * kThreads; q < nrec; q += kThreads) emit_rec(sh.rec[tile * sh.tcap + q]);
+    if (L.na > nrec) {
+      // slow owners beyond the tile's record region were classified by
+      // k_count without a record: mark the recorded ones, classify the rest
+      for (int t = threadIdx.x; t < RB * kCB / 32; t += kThreads) L.hasrec[t] = 0u;
+      __syncthreads();
+      for (int q = threadIdx.x; q < nrec; q += kThreads) {
+        const int pos = (int)(sh.rec[tile * sh.tcap + q].x >> 48);
+        const int e = (pos >> 8) * kCB + (pos & 255);
+        atomicOr(&L.hasrec[e >> 5], 1u << (e & 31));
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < RB * kCB; e += kThreads) {
+        const int r = e / kCB, col = e - r * kCB + 1;
+        if (!info_slow(L.info[r][col]) || ((L.hasrec[e >> 5] >> (e & 31)) & 1u)) continue;
+        const int k = k0 + r, c = c0 + col - 1;
+        const Frame fr = owner_frame(g, bw, k, c, L.rowR[r]);
         Slow sr;
         slow_classify(g, fr, sr);
-        R = pack_slow(sr);
+        const Nb nb = neighbours(r, col, L.info[r][col], k & 1);
+        emit_slow(g, fr, pack_slow(sr), nb, L.tb[r] + L.toff[r][col], out);
       }
-      emit_slow(g, fr, R, nb, L.tb[r] + L.toff[r][col], out);
     }
     return;
   }
@@ -887,7 +860,7 @@ __global__ void __launch_bounds__(kThreads) k_emit(Src src, const int64_t* __res
     L.bv[threadIdx.x] = (int)(o.x - base.x);
     if (threadIdx.x < RB) L.tb[threadIdx.x] = o.y - base.y;
   }
-  emit_tile<RB, true>(d, g, ky, cb, sh, L, nullptr);
+  emit_tile<RB, true>(d, g, ky, cb, (int64_t)blockIdx.x, sh, L, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1133,7 +1106,7 @@ __global__ void __launch_bounds__(kThreads) k_fused(ManySrc src, const int64_t* 
         E.tb[threadIdx.x] = F.cnt[cb][threadIdx.x].y;
       }
       if (threadIdx.x == RB) E.bv[RB] = hv;
-      emit_tile<RB, false>(d, g, (int)j, cb, sh, E, hrow);
+      emit_tile<RB, false>(d, g, (int)j, cb, 0, sh, E, hrow);
       __syncthreads();
       hv += E.rowv[RB];
     }
@@ -1334,7 +1307,7 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
     L.off_oinfo[i] = off;
     off = align256(off + (size_t)g.NK * g.NI * 4);
     L.off_omap[i] = off;
-    off = align256(off + (size_t)g.NK * g.NI);
+    off = align256(off + (size_t)g.NK * g.NI * 2);
   }
   L.total = off;
   return SBMT_OK;
@@ -1369,7 +1342,7 @@ static Img img_of(const CallLayout& L, int i, const sbmt_image& im, void* ws, co
   d.bm = im.bitmap;
   d.bits = (uint32_t*)(b + L.off_bits[i]);
   d.oinfo = (uint32_t*)(b + L.off_oinfo[i]);
-  d.omap = (uint8_t*)(b + L.off_omap[i]);
+  d.omap = (uint16_t*)(b + L.off_omap[i]);
   d.seg0 = L.seg0[i];
   d.band0 = L.band0[i];
   d.halo0 = L.halo0[i];
@@ -1486,6 +1459,7 @@ struct sbmt_batch_s {
   size_t stage_bytes = 0;
   int64_t* psizes = nullptr;       // pinned: n x 4
   int stage_cls = 0, psizes_cls = 0;
+  int count_rbi = -1;  // tile height of the last count pass (emission must use the same tiles)
 };
 
 static bool tuning_valid(const sbmt_tuning* t) {
@@ -1698,6 +1672,7 @@ sbmt_status sbmt_batch_plan(sbmt_batch b, sbmt_sizes* out, void* stream) {
   const ManySrc src = many_of(b);
   sbmt_status st = launch_front(b->L, src, dtab_of(b), sh, rb_index(b->tune.tile_rows), s);
   if (st != SBMT_OK) return st;
+  b->count_rbi = rb_index(b->tune.tile_rows);
   if ((st = launch_sizes(b->L, src, sh, nullptr, s)) != SBMT_OK) return st;
   const size_t bytes = (size_t)b->L.n * 4 * sizeof(int64_t);
   if (hipMemcpyAsync(b->psizes, sh.sizes, bytes, hipMemcpyDeviceToHost, s) != hipSuccess) return SBMT_E_DEVICE;
@@ -1722,6 +1697,7 @@ sbmt_status sbmt_batch_plan_async(sbmt_batch b, void* stream) {
   const ManySrc src = many_of(b);
   sbmt_status st = launch_front(b->L, src, dtab_of(b), sh, rb_index(b->tune.tile_rows), s);
   if (st != SBMT_OK) return st;
+  b->count_rbi = rb_index(b->tune.tile_rows);
   if ((st = launch_sizes(b->L, src, sh, nullptr, s)) != SBMT_OK) return st;
   const size_t bytes = (size_t)b->L.n * 4 * sizeof(int64_t);
   if (hipMemcpyAsync(b->psizes, sh.sizes, bytes, hipMemcpyDeviceToHost, s) != hipSuccess) return SBMT_E_DEVICE;
@@ -1742,10 +1718,11 @@ sbmt_status sbmt_batch_host_sizes(sbmt_batch b, sbmt_sizes* out, int64_t* status
 sbmt_status sbmt_batch_emit(sbmt_batch b, int64_t* sizes_dev, void* stream) {
   if (!b) return SBMT_E_INVALID_ARG;
   if (!b->ws) return SBMT_E_WORKSPACE;
+  if (b->count_rbi < 0) return SBMT_E_INVALID_ARG;  // nothing planned
   hipStream_t s = (hipStream_t)stream;
-  const Shared sh = shared_of(b->L, b->ws, rb_index(b->tune.tile_rows));
+  const Shared sh = shared_of(b->L, b->ws, b->count_rbi);
   const ManySrc src = many_of(b);
-  sbmt_status st = launch_emit(b->L, src, dtab_of(b), sh, rb_index(b->tune.tile_rows), s);
+  sbmt_status st = launch_emit(b->L, src, dtab_of(b), sh, b->count_rbi, s);
   if (st != SBMT_OK) return st;
   return launch_sizes(b->L, src, sh, sizes_dev, s);
 }
@@ -1766,6 +1743,7 @@ sbmt_status sbmt_batch_mesh(sbmt_batch b, int64_t* sizes_dev, void* stream) {
   const ManySrc src = many_of(b);
   const int64_t* dtab = dtab_of(b);
   if (b->tune.strategy == SBMT_STRATEGY_MULTI || !L.fused_ok) {
+    b->count_rbi = rbi;
     sbmt_status st = launch_front(L, src, dtab, sh, rbi, s);
     if (st != SBMT_OK) return st;
     if ((st = launch_emit(L, src, dtab, sh, rbi, s)) != SBMT_OK) return st;

@@ -226,6 +226,18 @@ __device__ __forceinline__ int wave_sum(int v) {
   return v;
 }
 
+// Inclusive scan over the 64 lanes of a wave with DPP row shifts and row
+// broadcasts (lanes without a source add 0).
+__device__ __forceinline__ int wave_incl_scan_dpp(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+  return x;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v, int lane) {
   for (int off = 1; off < 64; off <<= 1) {
@@ -575,22 +587,30 @@ __global__ void k_sizes(Src src, Shared sh, int64_t* __restrict__ user) {
 // The caller fills bv[0..RB] (image-local first vertex of each row's segment,
 // row RB = the halo row) and tb[0..RB-1] (first triangle) and syncs.
 // ---------------------------------------------------------------------------
+// Extra LDS of the sample-window mode (fused path): the staged raster and
+// the queues of slow owners.
+template <int RB, bool MAP>
+struct EmitExtra {
+  uint32_t win[kWinRows * kWinWords];
+  uint16_t qa[(RB + 1) * (kCB + 2)];  // slow owners without a record
+  uint16_t qs[RB * kCB];              // slow owners to emit
+};
 template <int RB>
+struct EmitExtra<RB, true> {};
+
+template <int RB, bool MAP>
 struct EmitLds {
   static constexpr int W = kCB + 2;  // columns c0-1 .. c0+kCB
   uint32_t info[RB + 1][W];
   int voff[RB + 1][W];
   int16_t toff[RB][W];
-  uint32_t win[kWinRows * kWinWords];
-  uint16_t qa[(RB + 1) * W];  // slow owners without a record
-  uint16_t qs[RB * kCB];      // slow owners to emit
+  EmitExtra<RB, MAP> x;
   uint32_t hasrec[RB * kCB / 32];
   int na, ns;
   int rowR[RB + 1];
   int bv[RB + 1];
   long long tb[RB];
   int rowv[RB + 1];  // vertices of each row's kCB owners
-  int part[RB + 1][2][kThreads / 64];
 };
 
 // MAP: owner info from the owner map written by k_count (multi-kernel path);
@@ -598,23 +618,23 @@ struct EmitLds {
 // and, for the halo row, in hrow (fused path).
 template <int RB, bool MAP>
 __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, int cb, int64_t tile, const Shared& sh,
-                                          EmitLds<RB>& L, const uint32_t* __restrict__ hrow) {
-  constexpr int W = EmitLds<RB>::W;
+                                          EmitLds<RB, MAP>& L, const uint32_t* __restrict__ hrow) {
+  constexpr int W = EmitLds<RB, MAP>::W;
   const int k0 = ky * RB;
   const int c0 = cb * kCB;
   if (threadIdx.x <= RB) L.rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);
   if (threadIdx.x == 0) L.na = L.ns = 0;
   __syncthreads();
   Bits bw;
-  if (MAP) {
+  if constexpr (MAP) {
     bw.p = d.bits;
     bw.wpr = g.wpr;
     bw.rr0 = 0;
     bw.cc0 = 0;
   } else {
     const int klast = min(k0 + RB + 1, g.NK) - 1;
-    bw = stage_window(g, d.bits, L.win, L.rowR[0] + kRing, L.rowR[max(klast - k0, 0)] + 2 + kRing, max(c0 - 1, 0),
-                      min(c0 + kCB + 1, g.NI) - 1);
+    bw = stage_window(g, d.bits, L.x.win, L.rowR[0] + kRing, L.rowR[max(klast - k0, 0)] + 2 + kRing,
+                      max(c0 - 1, 0), min(c0 + kCB + 1, g.NI) - 1);
     __syncthreads();
   }
   // 1. info words
@@ -624,7 +644,7 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, in
   SlowRec held[kHold];
   int nrec = 0;
   bool hv[kHold];
-  if (MAP) {
+  if constexpr (MAP) {
     // all loads of the thread first (owner codes of the window and the
     // tile's records), so their latencies overlap
     nrec = (int)min((int64_t)sh.tile_n[tile], sh.tcap);
@@ -633,8 +653,9 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, in
       const int idx = threadIdx.x + j * kThreads;
       const int rr = idx / W, col = idx - rr * W;
       const int k = k0 + rr, c = c0 - 1 + col;
+      // 0xffff marks a position outside the grid (no owner code has all bits set)
       codes[j] = (idx < (RB + 1) * W && k < g.NK && c >= 0 && c < g.NI) ? (uint32_t)d.omap[(int64_t)k * g.NI + c]
-                                                                        : 0xffffffffu;
+                                                                        : 0xffffu;
     }
 #pragma unroll
     for (int j = 0; j < kHold; ++j) {
@@ -648,14 +669,16 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, in
       if (idx >= (RB + 1) * W) break;
       const int rr = idx / W, col = idx - rr * W;
       uint32_t fi = 0;
-      if (codes[j] != 0xffffffffu) {
-        fi = map_info(codes[j]);
-        if ((codes[j] & 0x8000u) && rr < RB && col >= 1 && col <= kCB) atomicAdd(&L.na, 1);  // owned slow owners
+      const uint32_t code = codes[j];
+      if (code != 0xffffu) {
+        fi = map_info(code);
+        if ((code & 0x8000u) && rr < RB && col >= 1 && col <= kCB) atomicAdd(&L.na, 1);  // owned slow owners
       }
       L.info[rr][col] = fi;
     }
   }
-  for (int idx = threadIdx.x; !MAP && idx < (RB + 1) * W; idx += kThreads) {
+  if constexpr (!MAP) {
+  for (int idx = threadIdx.x; idx < (RB + 1) * W; idx += kThreads) {
     const int rr = idx / W, col = idx - rr * W;
     const int k = k0 + rr, c = c0 - 1 + col;
     uint32_t fi = 0;
@@ -676,58 +699,45 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, in
         fi = w;
       } else {
         const uint32_t ri = w & kNoRec;
-        if (ri == kNoRec) L.qa[atomicAdd(&L.na, 1)] = (uint16_t)idx;
+        if (ri == kNoRec) L.x.qa[atomicAdd(&L.na, 1)] = (uint16_t)idx;
         else fi = sh.rec[ri].info;
-        if (rr < RB && col >= 1 && col <= kCB) L.qs[atomicAdd(&L.ns, 1)] = (uint16_t)idx;
+        if (rr < RB && col >= 1 && col <= kCB) L.x.qs[atomicAdd(&L.ns, 1)] = (uint16_t)idx;
       }
     }
     L.info[rr][col] = fi;
   }
   __syncthreads();
-  for (int q = threadIdx.x; !MAP && q < L.na; q += kThreads) {
-    const int idx = L.qa[q], rr = idx / W, col = idx - rr * W;
+  for (int q = threadIdx.x; q < L.na; q += kThreads) {
+    const int idx = L.x.qa[q], rr = idx / W, col = idx - rr * W;
     const Frame f = owner_frame(g, bw, k0 + rr, c0 - 1 + col, L.rowR[rr]);
     Slow sr;
     slow_classify(g, f, sr);
     L.info[rr][col] = sr.info;
   }
-  __syncthreads();
-  // 2. prefix sums of every row: thread t owns column 1 + t
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int ev[RB + 1], et[RB + 1];
-#pragma unroll
-  for (int rr = 0; rr <= RB; ++rr) {
-    // vertices and triangles of a row segment stay below 2^16: one packed scan
-    const uint32_t f = L.info[rr][1 + threadIdx.x];
-    const int sp = info_nv(f) | (info_nt(f) << 16);
-    const int ip = wave_incl_scan(sp, lane);
-    ev[rr] = (ip - sp) & 0xffff;
-    et[rr] = (ip - sp) >> 16;
-    if (lane == 63) {
-      L.part[rr][0][wv] = ip & 0xffff;
-      L.part[rr][1][wv] = ip >> 16;
-    }
   }
   __syncthreads();
-#pragma unroll
-  for (int rr = 0; rr <= RB; ++rr) {
+  // 2. prefix sums, one wave per row, in four blocks of 64 consecutive
+  // columns (a DPP wave scan each, consecutive lanes on consecutive LDS words;
+  // vertex and triangle counts of a row segment stay below 2^16: packed)
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int rr = wv; rr <= RB; rr += kThreads / 64) {
     const int bv = L.bv[rr];
-    int pv = 0, pt = 0, totv = 0;
+    int carry = 0;
 #pragma unroll
-    for (int q = 0; q < kThreads / 64; ++q) {
-      if (q < wv) {
-        pv += L.part[rr][0][q];
-        pt += L.part[rr][1][q];
-      }
-      totv += L.part[rr][0][q];
+    for (int u = 0; u < kCB / 64; ++u) {
+      const int col = 1 + 64 * u + lane;
+      const uint32_t f = L.info[rr][col];
+      const int p = info_nv(f) | (info_nt(f) << 16);
+      const int incl = wave_incl_scan_dpp(p);
+      const int e = carry + incl - p;
+      L.voff[rr][col] = bv + (e & 0xffff);
+      if (rr < RB) L.toff[rr][col] = (int16_t)(e >> 16);
+      carry += __builtin_amdgcn_readlane(incl, 63);
     }
-    const int col = 1 + threadIdx.x;
-    L.voff[rr][col] = bv + ev[rr] + pv;
-    if (rr < RB) L.toff[rr][col] = (int16_t)(et[rr] + pt);
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
       L.voff[rr][0] = bv - info_nv(L.info[rr][0]);
-      L.voff[rr][W - 1] = bv + totv;
-      L.rowv[rr] = totv;
+      L.voff[rr][W - 1] = bv + (carry & 0xffff);
+      L.rowv[rr] = carry & 0xffff;
     }
   }
   __syncthreads();
@@ -783,7 +793,7 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, in
       d.codes[u] = code;
     }
   }
-  if (MAP) {
+  if constexpr (MAP) {
     // the tile's records (held ones, then the rest), each at its place
     auto emit_rec = [&](const SlowRec& R) {
       const int pos = (int)(R.x >> 48);
@@ -818,10 +828,9 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, in
         emit_slow(g, fr, pack_slow(sr), nb, L.tb[r] + L.toff[r][col], out);
       }
     }
-    return;
-  }
+  } else {
   for (int q = threadIdx.x; q < L.ns; q += kThreads) {
-    const int idx = L.qs[q], r = idx / W, col = idx - r * W;
+    const int idx = L.x.qs[q], r = idx / W, col = idx - r * W;
     const int k = k0 + r, c = c0 + col - 1;
     const uint32_t f = L.info[r][col];
     const Nb nb = neighbours(r, col, f, k & 1);
@@ -839,11 +848,12 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, in
     }
     emit_slow(g, fr, R, nb, L.tb[r] + L.toff[r][col], out);
   }
+  }
 }
 
 template <class Src, int RB>
 __global__ void __launch_bounds__(kThreads) k_emit(Src src, const int64_t* __restrict__ tab, Shared sh) {
-  __shared__ EmitLds<RB> L;
+  __shared__ EmitLds<RB, true> L;
   int64_t local;
   const int ii = src.find(blockIdx.x, tab, local);
   const Img& d = src.img(ii);
@@ -886,7 +896,7 @@ template <int RB>
 struct FusedLds {
   union {
     CountLds<RB + 1> c;
-    EmitLds<RB> e;
+    EmitLds<RB, false> e;
   } u;
   int2 cnt[kMaxBandChunks][RB + 1];  // per chunk and row: (nv, nt); later the image-local bases
   unsigned long long cbase[kMaxBandChunks];
@@ -1099,7 +1109,7 @@ __global__ void __launch_bounds__(kThreads) k_fused(ManySrc src, const int64_t* 
     // 4. emission, tiles left to right; the halo row's bases follow the row
     int hv = F.cnt[0][RB].x;
     for (int cb = 0; cb < g.NCB; ++cb) {
-      EmitLds<RB>& E = F.u.e;
+      EmitLds<RB, false>& E = F.u.e;
       __syncthreads();
       if (threadIdx.x < RB) {
         E.bv[threadIdx.x] = F.cnt[cb][threadIdx.x].x;

@@ -152,20 +152,26 @@ SBMT_HD Frame owner_place(const Geo& g, int k, int i, int Rlo) {
 
 // ---------------------------------------------------------------------------
 // Coarse raster: bit (R + ring, C + ringC) = [2 * #fg pixels of block (R, C) >= s^2].
-// One lane per sample; a wave covers 64 consecutive stored columns and packs
-// them with a ballot; samples outside the image (the ring) are background.
-// Blocks per image: ceil(32 wpr / 256) x ceil((CH + 2 ring) / kCoarsenRows);
-// 256 threads, kCoarsenRows stored rows per block.
+// A block covers kCoarsenRows stored rows and 256 stored columns.  Its pixel
+// rectangle is read with aligned 16-byte loads (a load never leaves the page
+// of the bytes it is for) and folded into per-pixel-row bit masks in LDS;
+// then one lane per sample counts its s x s block with popcounts and the
+// samples of a wave are packed by a ballot.  Samples outside the image (the
+// ring) are background.
+// Blocks per image: ceil(wpr / 8) x ceil((CH + 2 ring) / kCoarsenRows).
 // ---------------------------------------------------------------------------
 constexpr int kCoarsenRows = 8;
+constexpr int kCoarsenMaxS = 9;
+constexpr int kCoarsenWords = (256 * kCoarsenMaxS + 15 + kCoarsenMaxS + 31) / 32 + 2;  // mask words per pixel row
 
 template <class Src>
 __global__ void __launch_bounds__(256) k_coarsen(Src src, const int64_t* __restrict__ tab, Shared sh) {
+  __shared__ uint32_t mask[kCoarsenRows * kCoarsenMaxS][kCoarsenWords];
   int64_t local;
   const int ii = src.find(blockIdx.x, tab, local);
   const Img& d = src.img(ii);
   const Geo g = d.g;
-  const int nbx = (32 * g.wpr + 255) / 256;
+  const int nbx = (g.wpr + 7) / 8;
   const int bx = (int)(local % nbx), ry = (int)(local / nbx);
   if (blockIdx.x == 0 && threadIdx.x < 8) sh.ctr[threadIdx.x] = 0;
   if (local == 0 && threadIdx.x == 0) sh.imgerr[ii] = 0;
@@ -175,28 +181,69 @@ __global__ void __launch_bounds__(256) k_coarsen(Src src, const int64_t* __restr
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < 4 * (int64_t)sh.n;
        q += (int64_t)gridDim.x * blockDim.x)
     sh.sizes[q] = 0;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int gw = bx * 4 + wv;  // 64-bit group of the stored row
-  const int C = 64 * gw + lane - kRingC;
-  const int w = 2 * gw + lane;
   const int s = g.s;
-  const int c0 = s * C, c1 = min(c0 + s, g.W);
-  const bool colin = C >= 0 && C < g.CW;
+  const int rr0 = ry * kCoarsenRows;                 // first stored row
+  const int C0 = 256 * bx - kRingC;                  // first coarse column of the block
+  const int R0 = rr0 - kRing;                        // first coarse row
+  const int xa = s * max(C0, 0), xb = min(s * (C0 + 256), g.W);  // pixel columns
+  const int pa = s * max(R0, 0), pb = min(s * (R0 + kCoarsenRows), g.H);  // pixel rows
+  const int npr = max(pb - pa, 0);
+  const int nw = (xb - xa + 15 + s + 31) / 32 + 2;
+  for (int t = threadIdx.x; t < npr * nw; t += blockDim.x) mask[t / nw][t - (t / nw) * nw] = 0u;
+  __syncthreads();
+  if (xb > xa && npr > 0) {
+    // 16-byte chunks covering bytes xa .. xb-1 of each pixel row; bit
+    // (x - xa + 15) of the row mask = pixel x is foreground
+    const int nchm = (xb - xa + 15) / 16 + 1;  // chunks per row, at most
+    for (int t = threadIdx.x; t < npr * nchm; t += blockDim.x) {
+      const int pr = t / nchm, q = t - pr * nchm;
+      const uint8_t* row = d.bm + (int64_t)(pa + pr) * g.stride;
+      const uintptr_t lo = ((uintptr_t)(row + xa)) & ~(uintptr_t)15;
+      const uintptr_t hi = ((uintptr_t)(row + xb - 1)) & ~(uintptr_t)15;
+      if (lo + 16 * (uintptr_t)q <= hi) {
+        const uint4 v = *reinterpret_cast<const uint4*>(lo + 16 * (uintptr_t)q);
+        const int rel = (int)((lo + 16 * (uintptr_t)q) - (uintptr_t)(row + xa));  // pixel of byte 0, minus xa
+        uint32_t bits = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const uint32_t w = j < 4 ? v.x : (j < 8 ? v.y : (j < 12 ? v.z : v.w));
+          const int x = rel + j;
+          const bool in = x >= 0 && x < xb - xa;
+          bits |= (uint32_t)(in && ((w >> (8 * (j & 3))) & 255u) != 0u) << j;
+        }
+        if (bits) {
+          const int p = rel + 15;  // >= 0
+          const uint64_t sh64 = (uint64_t)bits << (p & 31);
+          atomicOr(&mask[pr][p >> 5], (uint32_t)sh64);
+          if (sh64 >> 32) atomicOr(&mask[pr][(p >> 5) + 1], (uint32_t)(sh64 >> 32));
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int cc = 256 * bx + threadIdx.x;  // stored column
+  const int C = cc - kRingC;
   const int nrows = g.CH + 2 * kRing;
-  for (int rr = ry * kCoarsenRows; rr < min(ry * kCoarsenRows + kCoarsenRows, nrows); ++rr) {
+  for (int r = 0; r < kCoarsenRows; ++r) {
+    const int rr = rr0 + r;
+    if (rr >= nrows) break;
     const int R = rr - kRing;
     int fg = 0;
-    if (colin && R >= 0 && R < g.CH) {
-      const int r0 = s * R, r1 = min(r0 + s, g.H);
+    if (C >= 0 && C < g.CW && R >= 0 && R < g.CH) {
+      const int x0 = s * C - xa + 15;  // bit of the block's first pixel
       int cnt = 0;
-      for (int r = r0; r < r1; ++r) {
-        const uint8_t* row = d.bm + (int64_t)r * g.stride;
-        for (int c = c0; c < c1; ++c) cnt += row[c] != 0;
+      for (int dr = 0; dr < s; ++dr) {
+        const int pr = s * R + dr - pa;
+        if (pa + pr >= g.H) break;
+        const uint64_t m = (uint64_t)mask[pr][x0 >> 5] | ((uint64_t)mask[pr][(x0 >> 5) + 1] << 32);
+        cnt += __builtin_popcountll((m >> (x0 & 31)) & ((1ull << s) - 1ull));
       }
       fg = 2 * cnt >= s * s;
     }
-    const unsigned long long m = __ballot(fg);
-    if (lane < 2 && w < g.wpr) d.bits[(int64_t)rr * g.wpr + w] = (uint32_t)(m >> (32 * lane));
+    const unsigned long long mm = __ballot(fg);
+    if ((lane & 63) < 2 && (cc & ~63) / 32 + lane < g.wpr)
+      d.bits[(int64_t)rr * g.wpr + (cc & ~63) / 32 + lane] = (uint32_t)(mm >> (32 * lane));
   }
 }
 
@@ -1256,7 +1303,7 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
     L.seg0[i] = L.nseg;
     L.nseg += (int64_t)g.NK * g.NCB;
     L.owners += (int64_t)g.NK * g.NI;
-    const int64_t cblk = (int64_t)((32 * g.wpr + 255) / 256) * ((g.CH + 2 * kRing + kCoarsenRows - 1) / kCoarsenRows);
+    const int64_t cblk = (int64_t)((g.wpr + 7) / 8) * ((g.CH + 2 * kRing + kCoarsenRows - 1) / kCoarsenRows);
     tab_row(L, 0)[i + 1] = tab_row(L, 0)[i] + cblk;
     for (int r = 0; r < 3; ++r) {
       const int64_t rows = (g.NK + kRBs[r] - 1) / kRBs[r];

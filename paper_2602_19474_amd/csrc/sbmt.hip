@@ -335,28 +335,31 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
     window_masks_word(bw, L.rowR[r] + kRing, w, L.u0[r][w], L.u1[r][w]);
   }
   __syncthreads();
-  // uniform windows, one owner per thread; the others are queued
+  // uniform windows, one owner per thread; the others are queued.  A thread
+  // keeps its column, so its window column depends only on the row parity.
+  const int c = c0 + threadIdx.x;
+  int wcol[2];
+#pragma unroll
+  for (int o = 0; o < 2; ++o) wcol[o] = clo_of(g, g.X0 + 4 * g.h * c + 2 * g.h * o) + kRingC - bw.cc0;
   for (int r = 0; r < RB; ++r) {
     const int k = k0 + r;
     if (k >= g.NK) break;
-    int nv = 0, nt = 0;
-    const int c = c0 + threadIdx.x;
+    int p = 0;  // vertices | triangles << 16
     if (c < g.NI) {
-      const int kind = window_kind(g, bw, L.u0[r], L.u1[r], g.X0 + 4 * g.h * c + 2 * g.h * (k & 1));
+      const int wc = wcol[k & 1], w = wc >> 5, sh = wc & 31;
+      const int kind = (int)((L.u0[r][w] >> sh) & 1u) | ((int)((L.u1[r][w] >> sh) & 1u) << 1);
       if (kind) {
         const uint32_t fi = fast_info_k(g, k, c, kind >> 1);
-        nv = info_nv(fi);
-        nt = info_nt(fi);
+        p = info_nv(fi) | (info_nt(fi) << 16);
         L.code[r][threadIdx.x] = (uint16_t)map_code(fi);
       } else {
         L.q1[atomicAdd(&L.n1, 1)] = (uint16_t)(r * kCB + threadIdx.x);
       }
     }
-    nv = wave_sum(nv);
-    nt = wave_sum(nt);
-    if (lane == 0 && (nv | nt)) {
-      atomicAdd(&L.acc[r][0], nv);
-      atomicAdd(&L.acc[r][1], nt);
+    p = __builtin_amdgcn_readlane(wave_incl_scan_dpp(p), 63);
+    if (lane == 0 && p) {
+      atomicAdd(&L.acc[r][0], p & 0xffff);
+      atomicAdd(&L.acc[r][1], p >> 16);
     }
   }
   __syncthreads();

@@ -56,8 +56,7 @@ constexpr int kCB = 256;               // owners per row segment (one per thread
 constexpr int kScanThreads = 1024;
 constexpr int kScanChunk = 4 * kScanThreads;
 constexpr int kWinRows = 16, kWinWords = 16;  // LDS window of the coarse raster per tile
-constexpr uint32_t kSlowBit = 0x80000000u;     // owner info word: slow owner, low bits = record
-constexpr uint32_t kNoRec = 0x7fffffffu;       // slow owner without a record (list full)
+constexpr int64_t kMaxRecords = 0x7ffffffeLL;  // records of a call
 constexpr int kMaxBandChunks = 64;             // fused path: row segments per band
 
 // One image of a call, as the kernels see it.
@@ -65,7 +64,6 @@ struct Img {
   Geo g;
   const uint8_t* bm;  // bitmap rows (device)
   uint32_t* bits;     // coarse raster, (CH + 2 kRing) rows of wpr words
-  uint32_t* oinfo;    // [NK][NI] record index of slow owners (fused path: info of non-uniform owners)
   uint16_t* omap;     // [NK][NI] owner map of the multi-kernel path, see map_code
   int64_t seg0;       // first row segment of the image in the call's segment arrays
   int64_t band0;      // first band of the image (fused path, 4-row numbering)
@@ -297,10 +295,11 @@ __device__ __forceinline__ T wave_incl_scan(T v, int lane) {
 // ---------------------------------------------------------------------------
 // Count one tile: rows k0 .. k0+RB-1, owners c0 .. c0+kCB-1.  Uniform windows
 // are counted from one bit; the other owners are checked against the
-// segments of their block: quiet ones (no segment reaches them) get their info
-// word in oinfo, slow ones get a record slot (their position is written into
-// it for k_slow) or, once the record list is full, are classified here.
-// Writes the segment counts of owners counted here and clears the slow ones.
+// segments of their block: quiet ones (no segment reaches them) are counted
+// here, slow ones get a slot in the tile's record region (their position is
+// written into it for the dense classification) or, beyond the region's
+// capacity, are classified here.  Every owner's code goes to the owner map;
+// the per-row counts of the owners counted here go to acc_out.
 // ---------------------------------------------------------------------------
 template <int RB>
 struct CountLds {
@@ -314,10 +313,13 @@ struct CountLds {
   uint32_t win[kWinRows * kWinWords];
 };
 
+// Rows k0 .. k0+RB-1 of column block cb.  With hdst, the codes of the last
+// row go to hdst[c] instead of the owner map (the persistent kernel counts
+// the first row of the next band that way without writing it).
 template <int RB>
-__device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, int64_t tile, int ky, int cb,
-                                           const Shared& sh, CountLds<RB>& L, int4* acc_out) {
-  const int k0 = ky * RB;
+__device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, int64_t tile, int k0, int cb,
+                                           const Shared& sh, CountLds<RB>& L, int4* acc_out,
+                                           uint16_t* __restrict__ hdst) {
   const int c0 = cb * kCB;
   const int lane = threadIdx.x & 63;
   if (threadIdx.x < RB) {
@@ -402,9 +404,10 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
     const int r = t / (kCB / 4), c = c0 + 4 * (t - r * (kCB / 4));
     const int k = k0 + r;
     if (k >= g.NK || c >= g.NI) continue;
-    uint16_t* dst = d.omap + (int64_t)k * g.NI + c;
+    const bool to_h = hdst != nullptr && r == RB - 1;
+    uint16_t* dst = to_h ? hdst + c : d.omap + (int64_t)k * g.NI + c;
     const uint16_t* src = &L.code[r][c - c0];
-    if (c + 4 <= g.NI && ((((int64_t)k * g.NI + c) & 3) == 0)) {
+    if (!to_h && c + 4 <= g.NI && ((((int64_t)k * g.NI + c) & 3) == 0)) {
       *reinterpret_cast<uint2*>(dst) = *reinterpret_cast<const uint2*>(src);
     } else {
       for (int u = 0; u < 4 && c + u < g.NI; ++u) dst[u] = src[u];
@@ -427,7 +430,7 @@ __global__ void __launch_bounds__(kThreads) k_count(Src src, const int64_t* __re
   const Img& d = src.img(ii);
   const Geo g = d.g;
   const int cb = (int)(local % g.NCB), ky = (int)(local / g.NCB);
-  count_tile<RB>(d, g, ii, (int64_t)blockIdx.x, ky, cb, sh, L, out);
+  count_tile<RB>(d, g, ii, (int64_t)blockIdx.x, ky * RB, cb, sh, L, out, nullptr);
   __syncthreads();
   const int k = ky * RB + (int)threadIdx.x;
   if (threadIdx.x < RB && k < g.NK) sh.seg_cnt[d.seg0 + (int64_t)k * g.NCB + cb] = out[threadIdx.x];
@@ -637,24 +640,12 @@ __global__ void k_sizes(Src src, Shared sh, int64_t* __restrict__ user) {
 // The caller fills bv[0..RB] (image-local first vertex of each row's segment,
 // row RB = the halo row) and tb[0..RB-1] (first triangle) and syncs.
 // ---------------------------------------------------------------------------
-// Extra LDS of the sample-window mode (fused path): the staged raster and
-// the queues of slow owners.
-template <int RB, bool MAP>
-struct EmitExtra {
-  uint32_t win[kWinRows * kWinWords];
-  uint16_t qa[(RB + 1) * (kCB + 2)];  // slow owners without a record
-  uint16_t qs[RB * kCB];              // slow owners to emit
-};
 template <int RB>
-struct EmitExtra<RB, true> {};
-
-template <int RB, bool MAP>
 struct EmitLds {
   static constexpr int W = kCB + 2;  // columns c0-1 .. c0+kCB
   uint32_t info[RB + 1][W];
   int voff[RB + 1][W];
   int16_t toff[RB][W];
-  EmitExtra<RB, MAP> x;
   uint32_t hasrec[RB * kCB / 32];
   int na, ns;
   int rowR[RB + 1];
@@ -663,107 +654,59 @@ struct EmitLds {
   int rowv[RB + 1];  // vertices of each row's kCB owners
 };
 
-// MAP: owner info from the owner map written by k_count (multi-kernel path);
-// otherwise from the samples, with non-uniform owners' info words in oinfo
-// and, for the halo row, in hrow (fused path).
-template <int RB, bool MAP>
-__device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, int cb, int64_t tile, const Shared& sh,
-                                          EmitLds<RB, MAP>& L, const uint32_t* __restrict__ hrow) {
-  constexpr int W = EmitLds<RB, MAP>::W;
-  const int k0 = ky * RB;
+// Owner info comes from the owner map (row RB, the halo row, from hcodes when
+// given), slow owners' emission data from the records of count tile `tile`
+// (each record carries the owner's place in the tile; records of the halo
+// row, which the persistent kernel keeps in the same region, are skipped).
+template <int RB>
+__device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, int cb, int64_t tile, const Shared& sh,
+                                          EmitLds<RB>& L, const uint16_t* __restrict__ hcodes) {
+  constexpr int W = EmitLds<RB>::W;
   const int c0 = cb * kCB;
   if (threadIdx.x <= RB) L.rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);
   if (threadIdx.x == 0) L.na = L.ns = 0;
   __syncthreads();
   Bits bw;
-  if constexpr (MAP) {
-    bw.p = d.bits;
-    bw.wpr = g.wpr;
-    bw.rr0 = 0;
-    bw.cc0 = 0;
-  } else {
-    const int klast = min(k0 + RB + 1, g.NK) - 1;
-    bw = stage_window(g, d.bits, L.x.win, L.rowR[0] + kRing, L.rowR[max(klast - k0, 0)] + 2 + kRing,
-                      max(c0 - 1, 0), min(c0 + kCB + 1, g.NI) - 1);
-    __syncthreads();
-  }
-  // 1. info words
+  bw.p = d.bits;
+  bw.wpr = g.wpr;
+  bw.rr0 = 0;
+  bw.cc0 = 0;
+  // 1. info words: all loads of the thread first (owner codes of the window
+  // and the tile's records), so their latencies overlap
   constexpr int kPer = ((RB + 1) * W + kThreads - 1) / kThreads;
   constexpr int kHold = 2;
   uint32_t codes[kPer];
   SlowRec held[kHold];
-  int nrec = 0;
   bool hv[kHold];
-  if constexpr (MAP) {
-    // all loads of the thread first (owner codes of the window and the
-    // tile's records), so their latencies overlap
-    nrec = (int)min((int64_t)sh.tile_n[tile], sh.tcap);
+  const int nrec = (int)min((int64_t)sh.tile_n[tile], sh.tcap);
 #pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-      const int idx = threadIdx.x + j * kThreads;
-      const int rr = idx / W, col = idx - rr * W;
-      const int k = k0 + rr, c = c0 - 1 + col;
-      // 0xffff marks a position outside the grid (no owner code has all bits set)
-      codes[j] = (idx < (RB + 1) * W && k < g.NK && c >= 0 && c < g.NI) ? (uint32_t)d.omap[(int64_t)k * g.NI + c]
-                                                                        : 0xffffu;
-    }
-#pragma unroll
-    for (int j = 0; j < kHold; ++j) {
-      const int q = threadIdx.x + j * kThreads;
-      hv[j] = q < nrec;
-      if (hv[j]) held[j] = sh.rec[tile * sh.tcap + q];
-    }
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-      const int idx = threadIdx.x + j * kThreads;
-      if (idx >= (RB + 1) * W) break;
-      const int rr = idx / W, col = idx - rr * W;
-      uint32_t fi = 0;
-      const uint32_t code = codes[j];
-      if (code != 0xffffu) {
-        fi = map_info(code);
-        if ((code & 0x8000u) && rr < RB && col >= 1 && col <= kCB) atomicAdd(&L.na, 1);  // owned slow owners
-      }
-      L.info[rr][col] = fi;
-    }
-  }
-  if constexpr (!MAP) {
-  for (int idx = threadIdx.x; idx < (RB + 1) * W; idx += kThreads) {
+  for (int j = 0; j < kPer; ++j) {
+    const int idx = threadIdx.x + j * kThreads;
     const int rr = idx / W, col = idx - rr * W;
     const int k = k0 + rr, c = c0 - 1 + col;
+    // 0xffff marks a position outside the grid (no owner code has all bits set)
+    uint32_t v = 0xffffu;
+    if (idx < (RB + 1) * W && k < g.NK && c >= 0 && c < g.NI)
+      v = (rr == RB && hcodes) ? (uint32_t)hcodes[c] : (uint32_t)d.omap[(int64_t)k * g.NI + c];
+    codes[j] = v;
+  }
+#pragma unroll
+  for (int j = 0; j < kHold; ++j) {
+    const int q = threadIdx.x + j * kThreads;
+    hv[j] = q < nrec;
+    if (hv[j]) held[j] = sh.rec[tile * sh.tcap + q];
+  }
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int idx = threadIdx.x + j * kThreads;
+    if (idx >= (RB + 1) * W) break;
+    const int rr = idx / W, col = idx - rr * W;
     uint32_t fi = 0;
-    if (k < g.NK && c >= 0 && c < g.NI) {
-      uint32_t w;
-      bool plain;
-      {
-        const Frame f = owner_frame(g, bw, k, c, L.rowR[rr]);
-        plain = frame_uniform(f);
-        if (plain) {
-          w = fast_info(g, f);
-        } else {
-          w = rr == RB ? hrow[c] : d.oinfo[(int64_t)k * g.NI + c];
-          plain = !(w & kSlowBit);
-        }
-      }
-      if (plain) {
-        fi = w;
-      } else {
-        const uint32_t ri = w & kNoRec;
-        if (ri == kNoRec) L.x.qa[atomicAdd(&L.na, 1)] = (uint16_t)idx;
-        else fi = sh.rec[ri].info;
-        if (rr < RB && col >= 1 && col <= kCB) L.x.qs[atomicAdd(&L.ns, 1)] = (uint16_t)idx;
-      }
+    if (codes[j] != 0xffffu) {
+      fi = map_info(codes[j]);
+      if ((codes[j] & 0x8000u) && rr < RB && col >= 1 && col <= kCB) atomicAdd(&L.na, 1);  // owned slow owners
     }
     L.info[rr][col] = fi;
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < L.na; q += kThreads) {
-    const int idx = L.x.qa[q], rr = idx / W, col = idx - rr * W;
-    const Frame f = owner_frame(g, bw, k0 + rr, c0 - 1 + col, L.rowR[rr]);
-    Slow sr;
-    slow_classify(g, f, sr);
-    L.info[rr][col] = sr.info;
-  }
   }
   __syncthreads();
   // 2. prefix sums, one wave per row, in four blocks of 64 consecutive
@@ -808,7 +751,7 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, in
     return nb;
   };
   // 3. fast and quiet owners one per thread (their writes coalesce), then the
-  // slow owners of the tile densely.
+  // slow owners of the tile from their records.
   const bool both = (g.flags & 1u) != 0;
   Out out;
   out.v = d.verts;
@@ -830,80 +773,57 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int ky, in
     int64_t u = L.tb[r] + L.toff[r][col];
     const uint8_t code = both && !info_fg(f) ? 0x80 : 0;
     if (info_ntb(f)) {
-      d.tris[3 * u + 0] = vid;
-      d.tris[3 * u + 1] = L.voff[r + 1][col + o_];
-      d.tris[3 * u + 2] = L.voff[r + 1][col + o_ - 1];
+      put_tri(d.tris, u, vid, L.voff[r + 1][col + o_], L.voff[r + 1][col + o_ - 1]);
       d.codes[u] = code;
       ++u;
     }
     if (info_nta(f)) {
-      d.tris[3 * u + 0] = vid;
-      d.tris[3 * u + 1] = L.voff[r][col + 1];
-      d.tris[3 * u + 2] = L.voff[r + 1][col + o_];
+      put_tri(d.tris, u, vid, L.voff[r][col + 1], L.voff[r + 1][col + o_]);
       d.codes[u] = code;
     }
   }
-  if constexpr (MAP) {
-    // the tile's records (held ones, then the rest), each at its place
-    auto emit_rec = [&](const SlowRec& R) {
-      const int pos = (int)(R.x >> 48);
-      const int r = pos >> 8, col = (pos & 255) + 1;
-      const int k = k0 + r, c = c0 + col - 1;
-      const Nb nb = neighbours(r, col, L.info[r][col], k & 1);
-      emit_slow(g, owner_place(g, k, c, L.rowR[r]), R, nb, L.tb[r] + L.toff[r][col], out);
-    };
-#pragma unroll
-    for (int j = 0; j < kHold; ++j)
-      if (hv[j]) emit_rec(held[j]);
-    for (int q = threadIdx.x + kHold * kThreads; q < nrec; q += kThreads) emit_rec(sh.rec[tile * sh.tcap + q]);
-    if (L.na > nrec) {
-      // slow owners beyond the tile's record region were classified by
-      // k_count without a record: mark the recorded ones, classify the rest
-      for (int t = threadIdx.x; t < RB * kCB / 32; t += kThreads) L.hasrec[t] = 0u;
-      __syncthreads();
-      for (int q = threadIdx.x; q < nrec; q += kThreads) {
-        const int pos = (int)(sh.rec[tile * sh.tcap + q].x >> 48);
-        const int e = (pos >> 8) * kCB + (pos & 255);
-        atomicOr(&L.hasrec[e >> 5], 1u << (e & 31));
-      }
-      __syncthreads();
-      for (int e = threadIdx.x; e < RB * kCB; e += kThreads) {
-        const int r = e / kCB, col = e - r * kCB + 1;
-        if (!info_slow(L.info[r][col]) || ((L.hasrec[e >> 5] >> (e & 31)) & 1u)) continue;
-        const int k = k0 + r, c = c0 + col - 1;
-        const Frame fr = owner_frame(g, bw, k, c, L.rowR[r]);
-        Slow sr;
-        slow_classify(g, fr, sr);
-        const Nb nb = neighbours(r, col, L.info[r][col], k & 1);
-        emit_slow(g, fr, pack_slow(sr), nb, L.tb[r] + L.toff[r][col], out);
-      }
-    }
-  } else {
-  for (int q = threadIdx.x; q < L.ns; q += kThreads) {
-    const int idx = L.x.qs[q], r = idx / W, col = idx - r * W;
+  auto emit_rec = [&](const SlowRec& R) {
+    const int pos = (int)(R.x >> 48);
+    const int r = pos >> 8, col = (pos & 255) + 1;
+    if (r >= RB) return;  // the halo row is emitted by the band below
+    atomicAdd(&L.ns, 1);
     const int k = k0 + r, c = c0 + col - 1;
-    const uint32_t f = L.info[r][col];
-    const Nb nb = neighbours(r, col, f, k & 1);
-    const uint32_t ri = d.oinfo[(int64_t)k * g.NI + c] & kNoRec;
-    SlowRec R;
-    Frame fr;
-    if (ri != kNoRec) {
-      R = sh.rec[ri];
-      fr = owner_place(g, k, c, L.rowR[r]);
-    } else {
-      fr = owner_frame(g, bw, k, c, L.rowR[r]);
+    const Nb nb = neighbours(r, col, L.info[r][col], k & 1);
+    emit_slow(g, owner_place(g, k, c, L.rowR[r]), R, nb, L.tb[r] + L.toff[r][col], out);
+  };
+#pragma unroll
+  for (int j = 0; j < kHold; ++j)
+    if (hv[j]) emit_rec(held[j]);
+  for (int q = threadIdx.x + kHold * kThreads; q < nrec; q += kThreads) emit_rec(sh.rec[tile * sh.tcap + q]);
+  __syncthreads();
+  if (L.na > L.ns) {
+    // slow owners beyond the tile's record region were classified by the
+    // count pass without a record: mark the recorded ones, classify the rest
+    for (int t = threadIdx.x; t < RB * kCB / 32; t += kThreads) L.hasrec[t] = 0u;
+    __syncthreads();
+    for (int q = threadIdx.x; q < nrec; q += kThreads) {
+      const int pos = (int)(sh.rec[tile * sh.tcap + q].x >> 48);
+      if ((pos >> 8) >= RB) continue;
+      const int e = (pos >> 8) * kCB + (pos & 255);
+      atomicOr(&L.hasrec[e >> 5], 1u << (e & 31));
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < RB * kCB; e += kThreads) {
+      const int r = e / kCB, col = e - r * kCB + 1;
+      if (!info_slow(L.info[r][col]) || ((L.hasrec[e >> 5] >> (e & 31)) & 1u)) continue;
+      const int k = k0 + r, c = c0 + col - 1;
+      const Frame fr = owner_frame(g, bw, k, c, L.rowR[r]);
       Slow sr;
       slow_classify(g, fr, sr);
-      R = pack_slow(sr);
+      const Nb nb = neighbours(r, col, L.info[r][col], k & 1);
+      emit_slow(g, fr, pack_slow(sr), nb, L.tb[r] + L.toff[r][col], out);
     }
-    emit_slow(g, fr, R, nb, L.tb[r] + L.toff[r][col], out);
-  }
   }
 }
 
 template <class Src, int RB>
 __global__ void __launch_bounds__(kThreads) k_emit(Src src, const int64_t* __restrict__ tab, Shared sh) {
-  __shared__ EmitLds<RB, true> L;
+  __shared__ EmitLds<RB> L;
   int64_t local;
   const int ii = src.find(blockIdx.x, tab, local);
   const Img& d = src.img(ii);
@@ -920,15 +840,15 @@ __global__ void __launch_bounds__(kThreads) k_emit(Src src, const int64_t* __res
     L.bv[threadIdx.x] = (int)(o.x - base.x);
     if (threadIdx.x < RB) L.tb[threadIdx.x] = o.y - base.y;
   }
-  emit_tile<RB, true>(d, g, ky, cb, (int64_t)blockIdx.x, sh, L, nullptr);
+  emit_tile<RB>(d, g, ky * RB, cb, (int64_t)blockIdx.x, sh, L, nullptr);
 }
 
 // ---------------------------------------------------------------------------
 // Fused persistent path.  A workgroup repeatedly takes the next band (RB
 // full-width rows of one image) in ticket order and
 //   1. counts its row segments and those of the halo row below it, queueing
-//      slow owners in the record list (the halo row's info goes to a per-band
-//      row of scratch instead of oinfo);
+//      slow owners in the tiles' record regions (the halo row's codes go to a
+//      per-band row of scratch: the band below writes the owner map there);
 //   2. classifies the band's slow owners densely, adding their counts;
 //   3. publishes the band's (n_v, n_t) and finds its offsets by a decoupled
 //      look-back over the bands of the same image: earlier tickets only, which
@@ -946,20 +866,19 @@ template <int RB>
 struct FusedLds {
   union {
     CountLds<RB + 1> c;
-    EmitLds<RB, false> e;
+    EmitLds<RB> e;
   } u;
+  int4 acc[RB + 1];                  // per-row counts of the chunk just counted
   int2 cnt[kMaxBandChunks][RB + 1];  // per chunk and row: (nv, nt); later the image-local bases
-  unsigned long long cbase[kMaxBandChunks];
-  int cn[kMaxBandChunks + 1];        // slow owners queued per chunk, then their prefix
+  int cn[kMaxBandChunks + 1];        // records per chunk, then their prefix
   long long ticket;
-  long long pv, pt;                  // band prefix (vertices, triangles)
   int ncut, err;
 };
 
 template <int RB>
-__global__ void __launch_bounds__(kThreads) k_fused(ManySrc src, const int64_t* __restrict__ tab,
-                                                    const int64_t* __restrict__ ttab, Shared sh, int64_t nbands,
-                                                    uint32_t* __restrict__ halo) {
+__global__ void __launch_bounds__(kThreads, 3) k_fused(ManySrc src, const int64_t* __restrict__ tab,
+                                                       const int64_t* __restrict__ ttab, Shared sh, int64_t nbands,
+                                                       uint16_t* __restrict__ halo) {
   __shared__ FusedLds<RB> F;
   for (;;) {
     __syncthreads();
@@ -973,97 +892,24 @@ __global__ void __launch_bounds__(kThreads) k_fused(ManySrc src, const int64_t* 
     const Geo g = d.g;
     const int nb = (g.NK + RB - 1) / RB;
     const int k0 = (int)j * RB;
-    uint32_t* hrow = halo + d.halo0 + j * (int64_t)g.NI;
-    // 1. counts of rows k0 .. k0+RB (the last one is the halo row)
+    uint16_t* hcode = halo + d.halo0 + j * (int64_t)g.NI;  // codes of row k0 + RB
+    const int64_t tile0 = ttab[ii] + j * g.NCB;             // count tile of chunk 0
     if (threadIdx.x == 0) F.ncut = F.err = 0;
+    // 1. counts of rows k0 .. k0+RB chunk by chunk (the last row is the halo
+    // row: its codes go to hcode, the owner map keeps the next band's own)
     for (int cb = 0; cb < g.NCB; ++cb) {
       __syncthreads();
-      CountLds<RB + 1>& C = F.u.c;
-      const int c0 = cb * kCB;
-      if (threadIdx.x <= RB) {
-        C.rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);
-        C.acc[threadIdx.x][0] = C.acc[threadIdx.x][1] = 0;
-      }
-      if (threadIdx.x == 0) C.n1 = C.n2 = 0;
+      if (threadIdx.x <= RB) F.acc[threadIdx.x] = make_int4(0, 0, 0, 0);
+      count_tile<RB + 1>(d, g, ii, tile0 + cb, k0, cb, sh, F.u.c, F.acc, hcode);
       __syncthreads();
-      const int klast = min(k0 + RB + 1, g.NK) - 1;
-      const Bits bw = stage_window(g, d.bits, C.win, C.rowR[0] + kRing, C.rowR[klast - k0] + 2 + kRing, c0,
-                                   min(c0 + kCB, g.NI) - 1);
-      __syncthreads();
-      for (int t = threadIdx.x; t < (klast - k0 + 1) * bw.wpr; t += kThreads) {
-        const int r = t / bw.wpr, w = t - r * bw.wpr;
-        window_masks_word(bw, C.rowR[r] + kRing, w, C.u0[r][w], C.u1[r][w]);
-      }
-      __syncthreads();
-      const int lane = threadIdx.x & 63;
-      for (int r = 0; r <= RB; ++r) {
-        const int k = k0 + r;
-        if (k >= g.NK) break;
-        int nv = 0, nt = 0;
-        const int c = c0 + threadIdx.x;
-        if (c < g.NI) {
-          const int kind = window_kind(g, bw, C.u0[r], C.u1[r], g.X0 + 4 * g.h * c + 2 * g.h * (k & 1));
-          if (kind) {
-            const uint32_t fi = fast_info_k(g, k, c, kind >> 1);
-            nv = info_nv(fi);
-            nt = info_nt(fi);
-          } else {
-            C.q1[atomicAdd(&C.n1, 1)] = (uint16_t)(r * kCB + threadIdx.x);
-          }
-        }
-        nv = wave_sum(nv);
-        nt = wave_sum(nt);
-        if (lane == 0 && (nv | nt)) {
-          atomicAdd(&C.acc[r][0], nv);
-          atomicAdd(&C.acc[r][1], nt);
-        }
-      }
-      __syncthreads();
-      for (int q = threadIdx.x; q < C.n1; q += kThreads) {
-        const int e = C.q1[q], r = e / kCB, c = c0 + (e - r * kCB);
-        const int k = k0 + r;
-        const Frame f = owner_frame(g, bw, k, c, C.rowR[r]);
-        uint32_t fi = 0;
-        if (needs_slow(g, f, fi)) {
-          C.q2[atomicAdd(&C.n2, 1)] = (uint16_t)e;
-        } else {
-          if (r < RB) d.oinfo[(int64_t)k * g.NI + c] = fi;
-          else hrow[c] = fi;
-          atomicAdd(&C.acc[r][0], info_nv(fi));
-          atomicAdd(&C.acc[r][1], info_nt(fi));
-        }
-      }
-      __syncthreads();
-      // the chunk's records live in the region of count tile (j, cb)
-      const int64_t tile = ttab[ii] + j * g.NCB + cb;
+      if (threadIdx.x <= RB) F.cnt[cb][threadIdx.x] = make_int2(F.acc[threadIdx.x].x, F.acc[threadIdx.x].y);
       if (threadIdx.x == 0) {
-        F.cbase[cb] = (unsigned long long)(tile * sh.tcap);
-        F.cn[cb] = (int)min((int64_t)C.n2, sh.tcap);
+        F.cn[cb] = (int)min((int64_t)F.u.c.n2, sh.tcap);
+        for (int r = 0; r < RB; ++r) F.ncut += F.acc[r].z;
       }
-      for (int q = threadIdx.x; q < C.n2; q += kThreads) {
-        const int e = C.q2[q], r = e / kCB, c = c0 + (e - r * kCB);
-        const int k = k0 + r;
-        const int64_t idx = tile * sh.tcap + q;
-        if (q < sh.tcap) {
-          sh.rec[idx].x = (uint64_t)c | ((uint64_t)k << 24) | ((uint64_t)ii << 48);
-          if (r < RB) d.oinfo[(int64_t)k * g.NI + c] = kSlowBit | (uint32_t)idx;
-        } else {
-          const Frame f = owner_frame(g, bw, k, c, C.rowR[r]);
-          Slow sr;
-          slow_classify(g, f, sr);
-          if (r < RB) d.oinfo[(int64_t)k * g.NI + c] = kSlowBit | kNoRec;
-          else hrow[c] = sr.info & ~kSlowBit;
-          atomicAdd(&C.acc[r][0], info_nv(sr.info));
-          atomicAdd(&C.acc[r][1], info_nt(sr.info));
-          if (r < RB) atomicAdd(&F.ncut, info_ncut(sr.info));
-          if (info_err(sr.info)) F.err = 1;
-        }
-      }
-      __syncthreads();
-      if (threadIdx.x <= RB) F.cnt[cb][threadIdx.x] = make_int2(C.acc[threadIdx.x][0], C.acc[threadIdx.x][1]);
     }
     __syncthreads();
-    // 2. the band's slow owners with records, densely
+    // 2. the band's recorded slow owners, densely
     if (threadIdx.x == 0) {
       int s = 0;
       for (int cb = 0; cb < g.NCB; ++cb) {
@@ -1082,7 +928,7 @@ __global__ void __launch_bounds__(kThreads) k_fused(ManySrc src, const int64_t* 
         if (F.cn[mid] <= q) lo = mid;
         else hi = mid - 1;
       }
-      const unsigned long long idx = F.cbase[lo] + (unsigned long long)(q - F.cn[lo]);
+      const int64_t idx = (tile0 + lo) * sh.tcap + (q - F.cn[lo]);
       const uint64_t p = sh.rec[idx].x;
       const int k = (int)((p >> 24) & 0xffffffu), c = (int)(p & 0xffffffu);
       const int r = k - k0;
@@ -1094,8 +940,11 @@ __global__ void __launch_bounds__(kThreads) k_fused(ManySrc src, const int64_t* 
       const Frame f = owner_frame(g, b, k, c, row_cell(k, g.h, g.s));
       Slow sr;
       slow_classify(g, f, sr);
-      if (r < RB) sh.rec[idx] = pack_slow(sr);
-      else hrow[c] = sr.info & ~kSlowBit;
+      SlowRec R = pack_slow(sr);
+      R.x |= (uint64_t)((r << 8) | (c - lo * kCB)) << 48;
+      sh.rec[idx] = R;
+      if (r < RB) d.omap[(int64_t)k * g.NI + c] = (uint16_t)map_code(sr.info);
+      else hcode[c] = (uint16_t)map_code(sr.info);
       atomicAdd(&F.cnt[lo][r].x, info_nv(sr.info));
       atomicAdd(&F.cnt[lo][r].y, info_nt(sr.info));
       if (r < RB) atomicAdd(&F.ncut, info_ncut(sr.info));
@@ -1131,8 +980,6 @@ __global__ void __launch_bounds__(kThreads) k_fused(ManySrc src, const int64_t* 
         }
         __hip_atomic_store(w, lb_word(kLbIncl, pv + av, pt + at), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       }
-      F.pv = pv;
-      F.pt = pt;
       // rows of the band in order, chunks in order within a row; the halo row
       // starts where the band ends
       long long v = pv, tt = pt;
@@ -1159,14 +1006,14 @@ __global__ void __launch_bounds__(kThreads) k_fused(ManySrc src, const int64_t* 
     // 4. emission, tiles left to right; the halo row's bases follow the row
     int hv = F.cnt[0][RB].x;
     for (int cb = 0; cb < g.NCB; ++cb) {
-      EmitLds<RB, false>& E = F.u.e;
+      EmitLds<RB>& E = F.u.e;
       __syncthreads();
       if (threadIdx.x < RB) {
         E.bv[threadIdx.x] = F.cnt[cb][threadIdx.x].x;
         E.tb[threadIdx.x] = F.cnt[cb][threadIdx.x].y;
       }
       if (threadIdx.x == RB) E.bv[RB] = hv;
-      emit_tile<RB, false>(d, g, (int)j, cb, 0, sh, E, hrow);
+      emit_tile<RB>(d, g, k0, cb, tile0 + cb, sh, E, hcode);
       __syncthreads();
       hv += E.rowv[RB];
     }
@@ -1271,7 +1118,7 @@ static const int kRBs[3] = {4, 8, 16};
 struct CallLayout {
   int n = 0;
   std::vector<Geo> g;
-  std::vector<size_t> off_bits, off_oinfo, off_omap;
+  std::vector<size_t> off_bits, off_omap;
   std::vector<int64_t> seg0, band0, halo0;  // band0, halo0 for the smallest fused band height
   std::vector<int64_t> tab;           // [1 + 3 + 3][n + 1]: coarsen blocks, tiles per RB, bands per RB
   int64_t nseg = 0, owners = 0, rcap = 0, nbands_max = 0, halo_words = 0, ntiles_max = 0;
@@ -1291,7 +1138,6 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
   L.n = n;
   L.g.resize(n);
   L.off_bits.resize(n);
-  L.off_oinfo.resize(n);
   L.off_omap.resize(n);
   L.seg0.resize(n);
   L.band0.resize(n);
@@ -1330,7 +1176,7 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
   } else {
     L.rcap = std::max<int64_t>(record_cap, 0);
   }
-  if (L.rcap >= (int64_t)kNoRec) L.rcap = (int64_t)kNoRec - 1;
+  if (L.rcap > kMaxRecords) L.rcap = kMaxRecords;
   for (int r = 0; r < 3; ++r) L.tcap[r] = L.rcap / std::max<int64_t>(tab_row(L, 1 + r)[n], 1);
   L.nblk = (int)((L.nseg + kScanChunk - 1) / kScanChunk);
   size_t off = 0;
@@ -1359,13 +1205,11 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
   L.off_band = off;
   off = align256(off + (size_t)L.nbands_max * sizeof(unsigned long long));
   L.off_halo = off;
-  off = align256(off + (size_t)L.halo_words * sizeof(uint32_t));
+  off = align256(off + (size_t)L.halo_words * sizeof(uint16_t));
   for (int i = 0; i < n; ++i) {
     const Geo& g = L.g[i];
     L.off_bits[i] = off;
     off = align256(off + (size_t)(g.CH + 2 * kRing) * g.wpr * 4);
-    L.off_oinfo[i] = off;
-    off = align256(off + (size_t)g.NK * g.NI * 4);
     L.off_omap[i] = off;
     off = align256(off + (size_t)g.NK * g.NI * 2);
   }
@@ -1401,7 +1245,6 @@ static Img img_of(const CallLayout& L, int i, const sbmt_image& im, void* ws, co
   d.g = L.g[i];
   d.bm = im.bitmap;
   d.bits = (uint32_t*)(b + L.off_bits[i]);
-  d.oinfo = (uint32_t*)(b + L.off_oinfo[i]);
   d.omap = (uint16_t*)(b + L.off_omap[i]);
   d.seg0 = L.seg0[i];
   d.band0 = L.band0[i];
@@ -1814,7 +1657,7 @@ sbmt_status sbmt_batch_mesh(sbmt_batch b, int64_t* sizes_dev, void* stream) {
   hipLaunchKernelGGL(k_coarsen<ManySrc>, dim3((unsigned)ncb), dim3(256), 0, s, src, dtab, sh);
   const int64_t nbands = L.tab[(size_t)(4 + rbi) * (L.n + 1) + L.n];
   const int64_t* btab = dtab + (size_t)(4 + rbi) * (L.n + 1);
-  uint32_t* halo = (uint32_t*)((char*)b->ws + L.off_halo);
+  uint16_t* halo = (uint16_t*)((char*)b->ws + L.off_halo);
   const int64_t* ttab = dtab + (size_t)(1 + rbi) * (L.n + 1);
   const int grid = fused_groups(b);
   if (b->tune.tile_rows == 4)
@@ -1879,8 +1722,7 @@ sbmt_status sbmt_batch_tune(sbmt_batch b, int32_t reps, sbmt_tuning* best, float
   }
   if (b->L.fused_ok)
     for (int rb : {4, 8})
-      for (int gpc : {2, 4, 6}) {
-        if (rb == 8 && gpc == 6) continue;  // LDS allows 4 groups of the 8-row band per CU
+      for (int gpc : {1, 2, 3}) {
         sbmt_tuning t = b->tune;
         t.strategy = SBMT_STRATEGY_FUSED;
         t.tile_rows = rb;

@@ -266,11 +266,6 @@ __device__ __forceinline__ Bits stage_window(const Geo& g, const uint32_t* __res
   return b;
 }
 
-__device__ __forceinline__ int wave_sum(int v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 // Inclusive scan over the 64 lanes of a wave with DPP row shifts and row
 // broadcasts (lanes without a source add 0).
 __device__ __forceinline__ int wave_incl_scan_dpp(int x) {

@@ -168,3 +168,45 @@ def test_autotuner_keeps_results(expected):
     b.mesh()
     torch.cuda.synchronize()
     _check(outs, b.sizes(), expected, f"tuned {best}")
+
+
+def test_both_sides_batch_and_batch_of_one():
+    import torch
+
+    from paper_2602_19474_amd import BOTH_SIDES
+    from paper_2602_19474_amd.batch import Batch, Tuning, mesh_batch
+    items = _items()[:5]
+    gpu = [(torch.from_numpy(np.ascontiguousarray(bm)).cuda(), h) for bm, h in items]
+    print("[gpu-batch] both sides", flush=True)
+    outs = mesh_batch(gpu, flags=BOTH_SIDES)
+    torch.cuda.synchronize()
+    for (bm, h), (v, t, c) in zip(items, outs):
+        ref = oracle.mesh_from_bitmap(bm, h, oracle.BOTH_SIDES)
+        assert np.array_equal(t.cpu().numpy(), ref.tris) and np.array_equal(c.cpu().numpy(), ref.codes)
+        assert float(np.abs(v.cpu().numpy() - ref.verts).max(initial=0.0)) <= 1e-12 * h
+    print("[gpu-batch] batch of one, fused", flush=True)
+    bm, h = items[2]
+    b = Batch([gpu[2]], tuning=Tuning(strategy=1, tile_rows=4, groups_per_cu=2))
+    (v, t, c), = b.allocate(b.plan())
+    b.mesh()
+    torch.cuda.synchronize()
+    ref = oracle.mesh_from_bitmap(bm, h)
+    assert b.sizes()[0][3] == 0
+    assert np.array_equal(t.cpu().numpy(), ref.tris) and np.array_equal(c.cpu().numpy(), ref.codes)
+
+
+def test_batch_argument_errors():
+    import torch
+
+    from paper_2602_19474_amd import SbmtError
+    from paper_2602_19474_amd.batch import Batch, Tuning
+    t = torch.zeros((10, 10), dtype=torch.uint8, device="cuda")
+    with pytest.raises(SbmtError) as e:
+        Batch([(t, 1), (t, 7)])
+    assert e.value.status == -2
+    with pytest.raises(SbmtError) as e:
+        Batch([(t, 1)], tuning=Tuning(strategy=1, tile_rows=16))
+    assert e.value.status == -1
+    b = Batch([(t, 1)])
+    with pytest.raises(SbmtError):
+        b.emit()  # nothing planned yet

@@ -21,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sbmt_oracle.cpp")
+_SRC_POST = os.path.join(_HERE, "post_oracle.cpp")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 BOTH_SIDES = 1
@@ -28,10 +29,11 @@ BOTH_SIDES = 1
 
 def build(force: bool = False) -> str:
     """Compile the oracle with g++ (plain -O2, no FMA contraction)."""
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_POST))
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < newest:
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
-                               "-o", tmp, _SRC])
+                               "-o", tmp, _SRC, _SRC_POST])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -76,8 +78,20 @@ def lib():
         L.oracle_local.restype = i32
         L.oracle_local.argtypes = [vp, vp, i32, ctypes.c_double, ctypes.POINTER(LocalResult),
                                    ctypes.c_char_p, i32]
+        L.oracle_sample_field.restype = None
+        L.oracle_sample_field.argtypes = [vp, i32, i32, i64, vp, i64, vp, i64, vp, vp]
+        L.oracle_mesh_quality.restype = None
+        L.oracle_mesh_quality.argtypes = [vp, i64, vp, i64, ctypes.POINTER(QualityOut)]
         _lib = L
     return _lib
+
+
+class QualityOut(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("n_triangles", "n_invalid", "n_nonpositive", "n_slivers",
+                                              "n_equilateral", "min_angle_tri")] + \
+               [(n, ctypes.c_double) for n in ("min_angle_deg", "min_area", "max_area", "mean_area", "var_area",
+                                               "ar_median", "ar_p95", "ar_max")] + \
+               [("angle_hist", ctypes.c_int64 * 30)]
 
 
 class OracleError(RuntimeError):
@@ -168,3 +182,33 @@ def local(corners, chain, unit: float):
     if rc != 0:
         raise OracleError(err.value.decode())
     return out
+
+
+def sample_field(field: np.ndarray, verts: np.ndarray, tris: np.ndarray | None = None):
+    """Bilinear field values at the vertices (and per-triangle means if ``tris``)."""
+    L = lib()
+    f = np.ascontiguousarray(field, dtype=np.float32)
+    H, W = f.shape
+    v = np.ascontiguousarray(verts, dtype=np.float64).reshape(-1, 2)
+    vv = np.zeros(v.shape[0], np.float64)
+    if tris is None:
+        L.oracle_sample_field(f.ctypes.data, W, H, W, v.ctypes.data, v.shape[0], None, 0, vv.ctypes.data, None)
+        return vv
+    t = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
+    tv = np.zeros(t.shape[0], np.float64)
+    L.oracle_sample_field(f.ctypes.data, W, H, W, v.ctypes.data, v.shape[0], t.ctypes.data if t.size else None,
+                          t.shape[0], vv.ctypes.data, tv.ctypes.data)
+    return vv, tv
+
+
+def mesh_quality(verts: np.ndarray, tris: np.ndarray) -> dict:
+    """Quality statistics of a mesh (see post_oracle.cpp for the definitions)."""
+    L = lib()
+    v = np.ascontiguousarray(verts, dtype=np.float64).reshape(-1, 2)
+    t = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
+    out = QualityOut()
+    L.oracle_mesh_quality(v.ctypes.data if v.size else None, v.shape[0], t.ctypes.data if t.size else None,
+                          t.shape[0], ctypes.byref(out))
+    d = {n: getattr(out, n) for n, _ in QualityOut._fields_ if n != "angle_hist"}
+    d["angle_hist"] = np.array(out.angle_hist[:], np.int64)
+    return d

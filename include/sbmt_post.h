@@ -57,16 +57,18 @@ sbmt_status sbmt_sample_field(sbmt_handle h, const sbmt_field* field, const doub
  * Per triangle (p0, p1, p2), in FP64 without contraction:
  *   squared edge lengths l0 = |p1-p0|^2, l1 = |p2-p1|^2, l2 = |p0-p2|^2;
  *   cross = (x1-x0)(y2-y0) - (y1-y0)(x2-x0) (twice the signed area);
- *   area = cross / 2;  AR = max(l) / |cross|;
+ *   area = cross / 2;  AR = max(l) / |cross| (+inf when cross = 0);
  *   the smallest angle lies opposite the shortest edge j (ties: lowest j);
  *   with lu, lv the other two squared lengths, q = cross^2 / (lu lv) is the
  *   squared sine of that angle (0 when lu lv = 0).
  * Decisions taken on q (so that they do not depend on a trigonometric
  * routine): sliver iff q < sin^2(5 deg); histogram bin = number of
  * j in 1..29 with q >= sin^2(2j deg) (bin 29 = [58, 60] deg, the largest a
- * minimum angle can be); equilateral iff max(l) - min(l) <= 1e-6 max(l).
- * The reported minimum angle is atan2(|cross|, dot) in degrees at the
- * smallest-q triangle (lowest index among equal q).  Percentiles are
+ * minimum angle can be); equilateral iff max(l) > 0 and
+ * max(l) - min(l) <= 1e-6 max(l).  The reported minimum angle is
+ * atan2(|u x w|, u . w) in degrees, u and w the edge vectors leaving the
+ * vertex opposite edge j of the smallest-q triangle (lowest index among equal
+ * q).  Vertices must be finite.  Percentiles are
  * nearest-rank over all counted triangles: element ceil(p n) - 1 of the sorted
  * AR values.  Mean and (population) variance of the areas are accumulated in
  * a fixed order (run to run identical).

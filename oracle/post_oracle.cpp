@@ -21,7 +21,9 @@
 //   * the field is bilinear between pixel centres, clamped at the outermost
 //     centres (the paper names linear or barycentric schemes only);
 //   * the edge-length test calls a triangle equilateral when its longest and
-//     shortest squared edge lengths differ by at most 1e-6 of the longest;
+//     shortest squared edge lengths differ by at most 1e-6 of the longest (a
+//     triangle whose three vertices coincide is not);
+//   * a triangle of zero area has AR = +inf (its shortest altitude is 0);
 //   * percentiles are nearest-rank (element ceil(p n) - 1 of the sorted list);
 //   * the area variance is the population variance.
 // The sliver and histogram decisions take the precision of the GPU kernels:
@@ -118,8 +120,9 @@ void oracle_mesh_quality(const double* verts, int64_t nv, const int32_t* tris, i
     area.push_back(A);
     q.min_area = std::min(q.min_area, A);
     q.max_area = std::max(q.max_area, A);
-    ar.push_back(lmax / std::fabs(cross));
-    if (lmax - lmin <= 1e-6 * lmax) ++q.n_equilateral;
+    // a triangle of zero area has a zero altitude: AR = +inf
+    ar.push_back(cross == 0.0 ? INFINITY : lmax / std::fabs(cross));
+    if (lmax > 0.0 && lmax - lmin <= 1e-6 * lmax) ++q.n_equilateral;
     // smallest angle: opposite the shortest edge j (first of equal lengths);
     // the vertex opposite edge j is vertex j+2
     int j = 0;

@@ -19,6 +19,9 @@ Extra objects on the same line:
   serve         the request stream: plain path per request (FIFO, one stream)
                 and the continuous-batching server, same Poisson arrivals,
                 p50/p99 latency (arrival -> device completion) and throughput
+  post          the consumers of the headline mesh: quality statistics and
+                field sampling at the vertices, timed with HIP events, with
+                their algorithmic HBM bytes and the oracle on a sample
 """
 from __future__ import annotations
 
@@ -140,6 +143,60 @@ def headline(bm: np.ndarray, steps: int, warmup: int):
     emit_ms = float(np.mean([ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]))
     sz = p.sizes
     return {"bitmap": bm, "plain": p, "wall": wall, "plan_ms": plan_ms, "emit_ms": emit_ms, "sizes": sz}
+
+
+def _event_ms(fn, reps: int) -> float:
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def post_section(plain, reps: int = 10):
+    """Quality statistics and field sampling over the headline mesh."""
+    import torch
+
+    from paper_2602_19474_amd import post
+    nv, nt = plain.sizes.n_vertices, plain.sizes.n_triangles
+    v, t = plain.verts[:nv], plain.tris[:nt]
+    H, W = plain.t.shape
+    ws = torch.empty((post.quality_workspace_bytes(nt),), dtype=torch.uint8, device="cuda")
+    out = torch.empty((512,), dtype=torch.uint8, device="cuda")
+    q_ms = _event_ms(lambda: post.mesh_quality_async(v, t, ws, out), reps)
+    q = post.quality_from_bytes(out)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2602)
+    field = torch.randn((H, W), generator=gen, dtype=torch.float32, device="cuda")
+    s_ms = _event_ms(lambda: post.sample_field(field, v, t), reps)  # outputs from torch's caching allocator
+    q_bytes = 12 * nt + 16 * nv                       # the mesh, read once
+    s_bytes = 16 * nv + 4 * W * H + 8 * nv + 20 * nt  # vertices + field -> values; triangles -> means
+    res = {
+        "quality": {"ms": q_ms, "triangles_per_s": nt / (q_ms * 1e-3), "alg_bytes": q_bytes,
+                    "hbm_frac": q_bytes / (q_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "stats": {k: (val.tolist() if k == "angle_hist" else val) for k, val in q.items()}},
+        "sampling": {"ms": s_ms, "vertices_per_s": nv / (s_ms * 1e-3), "alg_bytes": s_bytes,
+                     "hbm_frac": s_bytes / (s_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+    }
+    return res
+
+
+def post_cpu_baseline(plain, n_tri: int = 4_000_000):
+    """The oracle's quality pass over the first n_tri triangles of the headline mesh."""
+    import oracle
+    nv, nt = plain.sizes.n_vertices, plain.sizes.n_triangles
+    t = plain.tris[:min(nt, n_tri)].cpu().numpy()
+    v = plain.verts[:nv].cpu().numpy()
+    a = time.perf_counter()
+    oracle.mesh_quality(v, t)
+    dt = time.perf_counter() - a
+    return {"value": t.shape[0] / dt, "unit": "triangles/s", "cores": 1, "kind": "oracle",
+            "sample": f"quality statistics of the first {t.shape[0]} triangles of the noise8192 mesh"}
 
 
 def latency(name: str, images, grid_h: int, repeats: int = 1):
@@ -336,6 +393,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-pool", type=int, default=48)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-post", action="store_true", help="skip the mesh-consumer section")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -401,6 +459,11 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_source": traffic_src, "alg_bytes_per_launch": emit_bytes},
     }
+    if not args.no_post:
+        log("post section")
+        res["post"] = post_section(H["plain"])
+        if not args.no_cpu_baseline:
+            res["post"]["quality"]["cpu_baseline"] = post_cpu_baseline(H["plain"])
     del H
     if extras is not None:
         log("latency sections")

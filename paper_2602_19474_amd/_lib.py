@@ -1,4 +1,5 @@
-"""ctypes binding of libsbmt.so (the C ABI declared in include/sbmt.h).
+"""ctypes binding of libsbmt.so (the C ABI declared in include/sbmt.h and
+include/sbmt_post.h).
 
 Argument marshalling only: every step of the meshing path runs in the HIP
 kernels of the library.  The library must have been built (see
@@ -62,7 +63,23 @@ EXPORTS = ("sbmt_create", "sbmt_destroy", "sbmt_query", "sbmt_plan", "sbmt_run",
            "sbmt_batch_create", "sbmt_batch_destroy", "sbmt_batch_bind", "sbmt_batch_plan", "sbmt_batch_emit",
            "sbmt_batch_plan_async", "sbmt_batch_host_sizes",
            "sbmt_batch_mesh", "sbmt_batch_sizes", "sbmt_batch_get_tuning", "sbmt_batch_set_tuning",
-           "sbmt_batch_tune", "sbmt_num_classes", "sbmt_class_code", "sbmt_status_string")
+           "sbmt_batch_tune", "sbmt_num_classes", "sbmt_class_code", "sbmt_status_string",
+           "sbmt_sample_field", "sbmt_quality_workspace", "sbmt_mesh_quality_async", "sbmt_mesh_quality")
+
+ANGLE_BINS = 30
+
+
+class Field(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("row_stride", ctypes.c_int64)]
+
+
+class Quality(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("n_triangles", "n_invalid", "n_nonpositive", "n_slivers",
+                                              "n_equilateral", "min_angle_tri")] + \
+               [(n, ctypes.c_double) for n in ("min_angle_deg", "min_area", "max_area", "mean_area", "var_area",
+                                               "ar_median", "ar_p95", "ar_max")] + \
+               [("angle_hist", ctypes.c_int64 * ANGLE_BINS)]
 
 _lib = None
 
@@ -120,6 +137,14 @@ def lib():
     L.sbmt_batch_set_tuning.argtypes = [vp, P(Tuning)]
     L.sbmt_batch_tune.restype = i32
     L.sbmt_batch_tune.argtypes = [vp, i32, P(Tuning), P(ctypes.c_float), vp]
+    L.sbmt_sample_field.restype = i32
+    L.sbmt_sample_field.argtypes = [vp, P(Field), vp, i64, vp, i64, vp, vp, vp]
+    L.sbmt_quality_workspace.restype = i32
+    L.sbmt_quality_workspace.argtypes = [i64, P(sz)]
+    L.sbmt_mesh_quality_async.restype = i32
+    L.sbmt_mesh_quality_async.argtypes = [vp, vp, i64, vp, i64, vp, sz, vp, vp]
+    L.sbmt_mesh_quality.restype = i32
+    L.sbmt_mesh_quality.argtypes = [vp, vp, i64, vp, i64, vp, sz, P(Quality), vp]
     _lib = L
     return L
 

@@ -1,4 +1,4 @@
-"""The C ABI library loads and exports every entry point declared in include/sbmt.h.
+"""The C ABI library loads and exports every entry point declared in include/*.h.
 
 Runs on the CPU: only host-side entry points are called (no GPU work).
 """
@@ -11,13 +11,15 @@ import pytest
 from paper_2602_19474_amd import _lib
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "sbmt.h")
+HEADERS = [os.path.join(ROOT, "include", n) for n in ("sbmt.h", "sbmt_post.h")]
 
 
 def _declared():
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(sbmt_[a-z_]+)\s*\(", txt)))
+    names = set()
+    for h in HEADERS:
+        txt = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(sbmt_[a-z_]+)\s*\(", txt))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -30,8 +32,23 @@ def L():
 def test_exports_every_declared_symbol(L):
     names = _declared()
     assert "sbmt_plan" in names and "sbmt_run" in names and "sbmt_mesh_async" in names
+    assert "sbmt_sample_field" in names and "sbmt_mesh_quality" in names
     for n in names:
-        assert hasattr(L, n), f"{n} declared in include/sbmt.h but not exported"
+        assert hasattr(L, n), f"{n} declared in include/ but not exported"
+    assert set(names) <= set(_lib.EXPORTS)
+
+
+def test_post_entry_points_on_host(L):
+    """Workspace sizing and argument checks of the mesh consumers (no launch)."""
+    b0, b1 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.sbmt_quality_workspace(0, ctypes.byref(b0)) == 0
+    assert L.sbmt_quality_workspace(1_000_000, ctypes.byref(b1)) == 0
+    assert b1.value - b0.value >= 8 * 1_000_000 and b0.value > 0
+    assert L.sbmt_quality_workspace(-1, ctypes.byref(b0)) == -1
+    f = _lib.Field(None, 0, 0, 0)
+    assert L.sbmt_sample_field(None, ctypes.byref(f), None, 0, None, 0, None, None, None) == -1
+    q = _lib.Quality()
+    assert L.sbmt_mesh_quality(None, None, 0, None, 0, None, 0, ctypes.byref(q), None) == -1
 
 
 def test_host_only_entry_points(L):

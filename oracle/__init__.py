@@ -80,6 +80,15 @@ def lib():
                                    ctypes.c_char_p, i32]
         L.oracle_sample_field.restype = None
         L.oracle_sample_field.argtypes = [vp, i32, i32, i64, vp, i64, vp, i64, vp, vp]
+        L.oracle_laplacian.restype = None
+        L.oracle_laplacian.argtypes = [vp, i64, vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(LapInfo)]
+        L.oracle_laplacian_apply.restype = None
+        L.oracle_laplacian_apply.argtypes = [vp, i64, vp, i64, vp, vp]
+        L.oracle_heat_init.restype = None
+        L.oracle_heat_init.argtypes = [vp, i64, vp, i64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, vp]
+        L.oracle_heat_steps.restype = None
+        L.oracle_heat_steps.argtypes = [vp, i64, vp, i64, ctypes.c_double, ctypes.c_double, i32, vp]
         L.oracle_mesh_quality.restype = None
         L.oracle_mesh_quality.argtypes = [vp, i64, vp, i64, ctypes.POINTER(QualityOut)]
         _lib = L
@@ -92,6 +101,11 @@ class QualityOut(ctypes.Structure):
                [(n, ctypes.c_double) for n in ("min_angle_deg", "min_area", "max_area", "mean_area", "var_area",
                                                "ar_median", "ar_p95", "ar_max")] + \
                [("angle_hist", ctypes.c_int64 * 30)]
+
+
+class LapInfo(ctypes.Structure):
+    _fields_ = [("nnz", ctypes.c_int64), ("n_boundary", ctypes.c_int64), ("n_invalid", ctypes.c_int64),
+                ("min_mass", ctypes.c_double), ("lambda_bound", ctypes.c_double)]
 
 
 class OracleError(RuntimeError):
@@ -212,3 +226,53 @@ def mesh_quality(verts: np.ndarray, tris: np.ndarray) -> dict:
     d = {n: getattr(out, n) for n, _ in QualityOut._fields_ if n != "angle_hist"}
     d["angle_hist"] = np.array(out.angle_hist[:], np.int64)
     return d
+
+
+def _mesh_args(verts, tris):
+    v = np.ascontiguousarray(verts, dtype=np.float64).reshape(-1, 2)
+    t = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
+    return v, t, (v.ctypes.data if v.size else None), (t.ctypes.data if t.size else None)
+
+
+def laplacian(verts: np.ndarray, tris: np.ndarray) -> dict:
+    """Cotangent stiffness rows (CSR), lumped masses and boundary flags."""
+    L = lib()
+    v, t, vp_, tp_ = _mesh_args(verts, tris)
+    info = LapInfo()
+    L.oracle_laplacian(vp_, v.shape[0], tp_, t.shape[0], None, None, None, None, None, ctypes.byref(info))
+    nv = v.shape[0]
+    row_off = np.zeros(nv + 1, np.int64)
+    col = np.zeros(max(info.nnz, 1), np.int32)
+    val = np.zeros(max(info.nnz, 1), np.float64)
+    mass = np.zeros(max(nv, 1), np.float64)
+    bnd = np.zeros(max(nv, 1), np.uint8)
+    L.oracle_laplacian(vp_, nv, tp_, t.shape[0], row_off.ctypes.data, col.ctypes.data, val.ctypes.data,
+                       mass.ctypes.data, bnd.ctypes.data, ctypes.byref(info))
+    return {"row_off": row_off, "col": col[:info.nnz], "val": val[:info.nnz], "mass": mass[:nv],
+            "boundary": bnd[:nv].astype(bool), "nnz": info.nnz, "n_boundary": info.n_boundary,
+            "n_invalid": info.n_invalid, "min_mass": info.min_mass, "lambda_bound": info.lambda_bound}
+
+
+def laplacian_apply(verts, tris, u) -> np.ndarray:
+    L = lib()
+    v, t, vp_, tp_ = _mesh_args(verts, tris)
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    y = np.zeros_like(uu)
+    L.oracle_laplacian_apply(vp_, v.shape[0], tp_, t.shape[0], uu.ctypes.data, y.ctypes.data)
+    return y
+
+
+def heat_init(verts, tris, x0: float, y0: float, sigma: float, amp: float = 100.0) -> np.ndarray:
+    L = lib()
+    v, t, vp_, tp_ = _mesh_args(verts, tris)
+    u = np.zeros(v.shape[0], np.float64)
+    L.oracle_heat_init(vp_, v.shape[0], tp_, t.shape[0], x0, y0, sigma, amp, u.ctypes.data)
+    return u
+
+
+def heat_steps(verts, tris, u, alpha: float, dt: float, steps: int) -> np.ndarray:
+    L = lib()
+    v, t, vp_, tp_ = _mesh_args(verts, tris)
+    uu = np.array(u, dtype=np.float64, copy=True)
+    L.oracle_heat_steps(vp_, v.shape[0], tp_, t.shape[0], alpha, dt, int(steps), uu.ctypes.data)
+    return uu

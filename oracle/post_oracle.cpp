@@ -168,3 +168,173 @@ void oracle_mesh_quality(const double* verts, int64_t nv, const int32_t* tris, i
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Cotangent Laplacian and explicit heat steps (the parabolic experiment of
+// App. H: du/dt = alpha * Laplacian(u), u = 0 on the boundary, Gaussian
+// initial pulse), with linear finite elements on the mesh.
+//
+// Per triangle T = (v0, v1, v2): cross_T = (x1-x0)(y2-y0) - (y1-y0)(x2-x0);
+// at vertex k, u = p(k+1) - p(k), w = p(k+2) - p(k), dot_k = u.w and
+// c_k = 0.5 * (dot_k / cross_T) = cot(angle k) / 2, the weight of the edge
+// opposite vertex k.  Row i of the stiffness matrix lists the neighbours j of
+// i in order of first appearance over the triangles containing i (ascending
+// triangle index; in each, the next vertex then the previous one), each with
+// w_ij = the sum of its edge weights in that order.  (K u)_i = sum_j w_ij
+// (u_i - u_j) in row order.  Lumped mass m_i = sum over the same triangles of
+// (0.5 * cross_T) / 3.  A vertex is on the boundary when one of its edges
+// belongs to a single triangle.  One explicit Euler step:
+// u_i <- 0 on the boundary, else u_i - ((dt * alpha) * (K u)_i) / m_i.
+// Triangles with an index out of range or repeated are skipped; the others
+// must be positively oriented (a zero cross product gives infinite weights).
+// The Laplacian is a reading of the App. H setting, which names linear
+// finite elements without stating the time discretisation; the explicit
+// step is the first consumer, not a claim about the paper's solver.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Lap {
+  std::vector<int64_t> row_off;  // n_v + 1
+  std::vector<int32_t> col;
+  std::vector<double> val, mass;
+  std::vector<uint8_t> bnd;
+  int64_t n_invalid = 0;
+  double lambda_bound = 0.0;
+};
+
+Lap build_lap(const double* verts, int64_t nv, const int32_t* tris, int64_t nt) {
+  Lap L;
+  std::vector<std::vector<int64_t>> inc(nv);
+  for (int64_t t = 0; t < nt; ++t) {
+    const int32_t a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
+    if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv || a == b || b == c || a == c) {
+      ++L.n_invalid;  // an index out of range or repeated: skipped
+      continue;
+    }
+    inc[a].push_back(t);
+    inc[b].push_back(t);
+    inc[c].push_back(t);
+  }
+  L.row_off.assign(nv + 1, 0);
+  L.mass.assign(nv, 0.0);
+  L.bnd.assign(nv, 0);
+  for (int64_t i = 0; i < nv; ++i) {
+    std::vector<int32_t> nb;
+    std::vector<double> w;
+    std::vector<int> mult;
+    double m = 0.0;
+    for (int64_t t : inc[i]) {
+      const int32_t id[3] = {tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]};
+      double x[3], y[3];
+      for (int v = 0; v < 3; ++v) {
+        x[v] = verts[2 * id[v]];
+        y[v] = verts[2 * id[v] + 1];
+      }
+      const double cross = (x[1] - x[0]) * (y[2] - y[0]) - (y[1] - y[0]) * (x[2] - x[0]);
+      double c[3];
+      for (int k = 0; k < 3; ++k) {
+        const double ux = x[(k + 1) % 3] - x[k], uy = y[(k + 1) % 3] - y[k];
+        const double wx = x[(k + 2) % 3] - x[k], wy = y[(k + 2) % 3] - y[k];
+        c[k] = 0.5 * ((ux * wx + uy * wy) / cross);
+      }
+      m += (0.5 * cross) / 3.0;
+      int k = 0;
+      while (id[k] != i) ++k;
+      const int32_t js[2] = {id[(k + 1) % 3], id[(k + 2) % 3]};
+      const double cs[2] = {c[(k + 2) % 3], c[(k + 1) % 3]};
+      for (int q = 0; q < 2; ++q) {
+        size_t p = 0;
+        while (p < nb.size() && nb[p] != js[q]) ++p;
+        if (p == nb.size()) {
+          nb.push_back(js[q]);
+          w.push_back(cs[q]);
+          mult.push_back(1);
+        } else {
+          w[p] += cs[q];
+          ++mult[p];
+        }
+      }
+    }
+    for (int c : mult) L.bnd[i] |= c == 1;
+    L.mass[i] = m;
+    double diag = 0.0, offs = 0.0;
+    for (double v : w) {
+      diag += v;
+      offs += std::fabs(v);
+    }
+    if (m > 0.0) L.lambda_bound = std::max(L.lambda_bound, (diag + offs) / m);
+    L.col.insert(L.col.end(), nb.begin(), nb.end());
+    L.val.insert(L.val.end(), w.begin(), w.end());
+    L.row_off[i + 1] = (int64_t)L.col.size();
+  }
+  return L;
+}
+
+void apply_lap(const Lap& L, int64_t nv, const double* u, double* y) {
+  for (int64_t i = 0; i < nv; ++i) {
+    double s = 0.0;
+    for (int64_t e = L.row_off[i]; e < L.row_off[i + 1]; ++e) s += L.val[e] * (u[i] - u[L.col[e]]);
+    y[i] = s;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+struct OracleLapInfo {
+  int64_t nnz, n_boundary, n_invalid;
+  double min_mass, lambda_bound;
+};
+
+// Assembles and copies out: row_off [nv+1], col/val [nnz] (nnz from a first
+// call with col == nullptr), mass [nv], bnd [nv].
+void oracle_laplacian(const double* verts, int64_t nv, const int32_t* tris, int64_t nt, int64_t* row_off,
+                      int32_t* col, double* val, double* mass, uint8_t* bnd, OracleLapInfo* info) {
+  const Lap L = build_lap(verts, nv, tris, nt);
+  info->nnz = (int64_t)L.col.size();
+  info->n_invalid = L.n_invalid;
+  info->n_boundary = 0;
+  info->min_mass = INFINITY;
+  for (int64_t i = 0; i < nv; ++i) {
+    info->n_boundary += L.bnd[i];
+    info->min_mass = std::min(info->min_mass, L.mass[i]);
+  }
+  info->lambda_bound = L.lambda_bound;
+  if (!col) return;
+  std::copy(L.row_off.begin(), L.row_off.end(), row_off);
+  std::copy(L.col.begin(), L.col.end(), col);
+  std::copy(L.val.begin(), L.val.end(), val);
+  std::copy(L.mass.begin(), L.mass.end(), mass);
+  std::copy(L.bnd.begin(), L.bnd.end(), bnd);
+}
+
+// y = K u
+void oracle_laplacian_apply(const double* verts, int64_t nv, const int32_t* tris, int64_t nt, const double* u,
+                            double* y) {
+  const Lap L = build_lap(verts, nv, tris, nt);
+  apply_lap(L, nv, u, y);
+}
+
+// Gaussian pulse amp * exp(-((x-x0)^2 + (y-y0)^2) / (2 sigma^2)), 0 on the boundary.
+void oracle_heat_init(const double* verts, int64_t nv, const int32_t* tris, int64_t nt, double x0, double y0,
+                      double sigma, double amp, double* u) {
+  const Lap L = build_lap(verts, nv, tris, nt);
+  for (int64_t i = 0; i < nv; ++i) {
+    const double dx = verts[2 * i] - x0, dy = verts[2 * i + 1] - y0;
+    u[i] = L.bnd[i] ? 0.0 : amp * std::exp(-(dx * dx + dy * dy) / (2.0 * sigma * sigma));
+  }
+}
+
+// `steps` explicit Euler steps in place.
+void oracle_heat_steps(const double* verts, int64_t nv, const int32_t* tris, int64_t nt, double alpha, double dt,
+                       int32_t steps, double* u) {
+  const Lap L = build_lap(verts, nv, tris, nt);
+  std::vector<double> ku(nv);
+  for (int32_t s = 0; s < steps; ++s) {
+    apply_lap(L, nv, u, ku.data());
+    for (int64_t i = 0; i < nv; ++i) u[i] = L.bnd[i] ? 0.0 : u[i] - ((dt * alpha) * ku[i]) / L.mass[i];
+  }
+}
+
+}  // extern "C"

@@ -164,3 +164,107 @@ def test_triangle_means_of_a_linear_field():
     assert np.abs(tv[inside] - (1.0 + 0.5 * cen[inside, 0] + 0.25 * cen[inside, 1])).max() < 1e-12
     bad = oracle.sample_field(lin, m.verts[:4], np.array([[0, 1, 9]], np.int32))[1]
     assert math.isnan(bad[0])
+
+
+# ---------------------------------------------------------------------------
+# Cotangent Laplacian and explicit heat steps.
+# ---------------------------------------------------------------------------
+def _hexagon():
+    v = np.array([[0.0, 0.0]] + [[math.cos(k * math.pi / 3), math.sin(k * math.pi / 3)] for k in range(6)])
+    t = np.array([[0, 1 + k, 1 + (k + 1) % 6] for k in range(6)], np.int32)
+    return v, t
+
+
+def test_laplacian_hexagon_closed_forms():
+    """Six equilateral triangles around a vertex: w = cot 60 deg (twice 1/2) = 1/sqrt3, m = sqrt3/2."""
+    v, t = _hexagon()
+    L = oracle.laplacian(v, t)
+    assert L["row_off"][1] == 6 and sorted(L["col"][:6].tolist()) == [1, 2, 3, 4, 5, 6]
+    assert np.abs(L["val"][:6] - 1 / math.sqrt(3)).max() < 1e-15
+    assert abs(L["mass"][0] - math.sqrt(3) / 2) < 1e-15
+    assert not L["boundary"][0] and L["boundary"][1:].all() and L["n_boundary"] == 6
+    # a rim vertex: two rim neighbours (one triangle each, 1/(2 sqrt3)) and the centre (two, 1/sqrt3)
+    r1 = slice(L["row_off"][1], L["row_off"][2])
+    got = dict(zip(L["col"][r1].tolist(), L["val"][r1].tolist()))
+    assert set(got) == {0, 2, 6} and abs(got[0] - 1 / math.sqrt(3)) < 1e-15
+    assert abs(got[2] - 0.5 / math.sqrt(3)) < 1e-15 and abs(got[6] - 0.5 / math.sqrt(3)) < 1e-15
+    # one explicit step: u0' = u0 (1 - dt alpha sum(w) / m) = u0 (1 - 4 dt alpha), rim stays 0
+    u = np.array([3.0, 0, 0, 0, 0, 0, 0])
+    for dt, alpha in ((1e-3, 2.0), (0.01, 5.0)):
+        got = oracle.heat_steps(v, t, u, alpha, dt, 1)
+        assert abs(got[0] - 3.0 * (1 - 4 * dt * alpha)) < 1e-14 and (got[1:] == 0).all()
+        got2 = oracle.heat_steps(v, t, u, alpha, dt, 2)
+        assert abs(got2[0] - 3.0 * (1 - 4 * dt * alpha) ** 2) < 1e-13
+
+
+def _edge_counts(t):
+    e = np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]])
+    e.sort(axis=1)
+    uniq, cnt = np.unique(e, axis=0, return_counts=True)
+    return uniq, cnt
+
+
+@pytest.mark.parametrize("which,h", [("disk", 1), ("ellipses", 2), ("noise", 3)])
+def test_laplacian_of_meshes(which, h):
+    if which == "disk":
+        bm = wl.disk(item=6)
+    elif which == "ellipses":
+        bm = wl.ellipses(item=3)[:300, :360]
+    else:
+        bm = wl.smoothed_noise(240, 200, 8.0, 0.0, False, wl.rng(96, h))
+    m = oracle.mesh_from_bitmap(bm, h)
+    v, t = m.verts, m.tris
+    L = oracle.laplacian(v, t)
+    nv = v.shape[0]
+    # boundary vertices: the ends of edges used by one triangle (numpy edge count)
+    uniq, cnt = _edge_counts(t)
+    bset = np.zeros(nv, bool)
+    bset[uniq[cnt == 1].ravel()] = True
+    assert np.array_equal(L["boundary"], bset)
+    # rows list each neighbour once; the matrix is symmetric bit for bit
+    rows = np.repeat(np.arange(nv), np.diff(L["row_off"]))
+    assert L["nnz"] == 2 * uniq.shape[0]
+    fwd = dict(zip(zip(rows.tolist(), L["col"].tolist()), L["val"].tolist()))
+    assert all(fwd[(j, i)] == w for (i, j), w in fwd.items())
+    # masses add up to the area inside the boundary polygons
+    assert abs(L["mass"].sum() - abs(_shoelace_area(m.chains))) < 1e-9 * L["mass"].sum()
+    # linear precision: K (a + b x + c y) = 0 at interior vertices
+    lin = 0.7 - 1.3 * v[:, 0] + 2.1 * v[:, 1]
+    k = oracle.laplacian_apply(v, t, lin)
+    scale = np.abs(L["val"]).max() * np.abs(lin).max()
+    assert np.abs(k[~L["boundary"]]).max() < 1e-9 * scale
+    # x^2 + y^2 at a vertex whose six triangles are uncut equilateral ones: K u = -4 m
+    par = oracle.laplacian_apply(v, t, v[:, 0] ** 2 + v[:, 1] ** 2)
+    inc = np.zeros(nv, int)
+    np.add.at(inc, t[m.codes == 0].ravel(), 1)
+    full = inc == 6
+    assert full.sum() > 10
+    assert np.abs(par[full] + 4 * L["mass"][full]).max() < 1e-9 * np.abs(par[full]).max()
+
+
+def test_heat_energy_decays_at_the_stable_step():
+    m = oracle.mesh_from_bitmap(wl.disk(item=7), 1)
+    v, t = m.verts, m.tris
+    L = oracle.laplacian(v, t)
+    alpha = 500.0
+    dt = 1.9 / (alpha * L["lambda_bound"])
+    u = oracle.heat_init(v, t, 31.5, 31.5, 6.0, 100.0)
+    assert (u[L["boundary"]] == 0).all() and abs(u.max() - 100.0) < 2.0
+    r2 = (v[:, 0] - 31.5) ** 2 + (v[:, 1] - 31.5) ** 2
+    ok = ~L["boundary"]
+    assert np.abs(u[ok] - 100.0 * np.exp(-r2[ok] / 72.0)).max() < 1e-12
+    e_prev = float((L["mass"] * u * u).sum())
+    for _ in range(20):
+        u = oracle.heat_steps(v, t, u, alpha, dt, 5)
+        e = float((L["mass"] * u * u).sum())
+        assert e <= e_prev * (1 + 1e-12)
+        e_prev = e
+    assert e_prev < float((L["mass"] * oracle.heat_init(v, t, 31.5, 31.5, 6.0) ** 2).sum())
+
+
+def test_laplacian_skips_invalid_triangles():
+    v, t = _hexagon()
+    bad = np.concatenate([t, [[0, 0, 1], [0, 9, 2], [-1, 1, 2]]]).astype(np.int32)
+    a, b = oracle.laplacian(v, t), oracle.laplacian(v, bad)
+    assert b["n_invalid"] == 3 and a["n_invalid"] == 0
+    assert np.array_equal(a["col"], b["col"]) and np.array_equal(a["val"], b["val"])

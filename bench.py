@@ -19,9 +19,10 @@ Extra objects on the same line:
   serve         the request stream: plain path per request (FIFO, one stream)
                 and the continuous-batching server, same Poisson arrivals,
                 p50/p99 latency (arrival -> device completion) and throughput
-  post          the consumers of the headline mesh: quality statistics and
-                field sampling at the vertices, timed with HIP events, with
-                their algorithmic HBM bytes and the oracle on a sample
+  post          the consumers of the headline mesh: quality statistics, field
+                sampling at the vertices, cotangent-Laplacian assembly and
+                explicit heat steps, timed with HIP events, with their
+                algorithmic HBM bytes and the oracle on a sample
 """
 from __future__ import annotations
 
@@ -159,7 +160,7 @@ def _event_ms(fn, reps: int) -> float:
 
 
 def post_section(plain, reps: int = 10):
-    """Quality statistics and field sampling over the headline mesh."""
+    """Quality statistics, field sampling and heat steps over the headline mesh."""
     import torch
 
     from paper_2602_19474_amd import post
@@ -176,7 +177,21 @@ def post_section(plain, reps: int = 10):
     s_ms = _event_ms(lambda: post.sample_field(field, v, t), reps)  # outputs from torch's caching allocator
     q_bytes = 12 * nt + 16 * nv                       # the mesh, read once
     s_bytes = 16 * nv + 4 * W * H + 8 * nv + 20 * nt  # vertices + field -> values; triangles -> means
+    from paper_2602_19474_amd.pde import Laplacian
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    lap = Laplacian(v, t)  # synchronous: assembles and reads back the summary
+    asm_ms = (time.perf_counter() - a) * 1e3
+    u = lap.heat_init((W - 1) / 2, (H - 1) / 2, min(W, H) / 8, 100.0)
+    tmp = torch.empty_like(u)
+    dt = 1.9 / (500.0 * lap.info["lambda_bound"])  # alpha = 500 (App. H), Gershgorin-stable step
+    h_ms = _event_ms(lambda: lap.heat_steps(u, 500.0, dt, 10, tmp), reps) / 10
+    nnz = int(lap.info["nnz"])
+    h_bytes = 8 * (nv + 1) + 12 * nnz + 8 * nv + nv + 16 * nv  # operator + masses + flags, u in and out
+    del lap, u, tmp
     res = {
+        "heat": {"assemble_ms": asm_ms, "step_ms": h_ms, "nnz": nnz, "alg_bytes_per_step": h_bytes,
+                 "hbm_frac": h_bytes / (h_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "alpha": 500.0, "dt": dt},
         "quality": {"ms": q_ms, "triangles_per_s": nt / (q_ms * 1e-3), "alg_bytes": q_bytes,
                     "hbm_frac": q_bytes / (q_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                     "stats": {k: (val.tolist() if k == "angle_hist" else val) for k, val in q.items()}},

@@ -1,7 +1,8 @@
 /*
  * sbmt_post.h -- C ABI of the stages that consume an SBMT mesh on the GPU:
- * sampling a scalar field of the bitmap at the mesh vertices, and the mesh
- * quality statistics the paper evaluates its meshes with.
+ * sampling a scalar field of the bitmap at the mesh vertices, the mesh
+ * quality statistics the paper evaluates its meshes with, and the cotangent
+ * Laplacian with explicit heat steps (the first PDE consumer).
  *
  * Both take the outputs of sbmt.h (vertices FP64 (x, y) pairs, triangles
  * int32 index triples) but accept any triangle mesh in that layout.  Every
@@ -108,6 +109,81 @@ sbmt_status sbmt_mesh_quality_async(sbmt_handle h, const double* verts, int64_t 
 sbmt_status sbmt_mesh_quality(sbmt_handle h, const double* verts, int64_t n_vertices, const int32_t* tris,
                               int64_t n_triangles, void* workspace, size_t ws_bytes, sbmt_quality* out,
                               void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Cotangent Laplacian and explicit heat steps: linear finite elements on the
+ * mesh for du/dt = alpha * Laplacian(u) with u = 0 on the boundary and a
+ * Gaussian initial pulse (the diffusion setting of App. H).
+ *
+ * Per triangle T = (v0, v1, v2): cross_T = (x1-x0)(y2-y0) - (y1-y0)(x2-x0);
+ * at vertex k, u = p(k+1) - p(k), w = p(k+2) - p(k) and
+ * c_k = 0.5 * ((u . w) / cross_T) = cot(angle k) / 2 weighs the edge opposite
+ * vertex k.  Row i of the stiffness matrix K lists the neighbours j of vertex
+ * i in order of first appearance over the triangles containing i (ascending
+ * triangle index; in each, the next vertex then the previous one), with
+ * w_ij = the sum of that edge's weights in the same order; K is applied as
+ * (K u)_i = sum_j w_ij (u_i - u_j) in row order.  Lumped mass
+ * m_i = sum over the same triangles of (0.5 * cross_T) / 3.  A vertex is on
+ * the boundary when one of its edges belongs to a single triangle.  Every
+ * sum has a fixed order, so results are identical from run to run.
+ * Triangles with an index out of range or repeated are skipped; the others
+ * must be positively oriented.
+ *
+ * The workspace (sized by sbmt_laplacian_workspace for the mesh) holds the
+ * assembled operator after sbmt_laplacian_assemble; the other calls take
+ * that workspace and must see the same vertex count.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int64_t n_vertices;
+  int64_t nnz;          /* stored off-diagonal entries (each undirected edge twice) */
+  int64_t n_boundary;   /* vertices held at 0 */
+  int64_t n_invalid;    /* skipped triangles */
+  double min_mass;      /* smallest lumped mass (0 for a vertex in no triangle) */
+  double lambda_bound;  /* Gershgorin bound on the eigenvalues of M^-1 K:
+                           max_i (sum_j w_ij + sum_j |w_ij|) / m_i over m_i > 0;
+                           explicit steps are stable for alpha dt <= 2 / lambda_bound */
+} sbmt_laplacian_info;
+
+/* Device pointers into an assembled workspace (valid while it lives):
+ * row_off [n_v + 1] int64, col [nnz] int32, val [nnz] FP64, mass [n_v] FP64,
+ * boundary [n_v] uint8 (1 = on the boundary). */
+typedef struct {
+  const int64_t* row_off;
+  const int32_t* col;
+  const double* val;
+  const double* mass;
+  const uint8_t* boundary;
+} sbmt_csr;
+
+/* Host only. */
+sbmt_status sbmt_laplacian_workspace(int64_t n_vertices, int64_t n_triangles, size_t* bytes);
+
+/* Assembles K, the masses and the boundary flags into the workspace and
+ * returns the summary in *info (waits for the stream). */
+sbmt_status sbmt_laplacian_assemble(sbmt_handle h, const double* verts, int64_t n_vertices, const int32_t* tris,
+                                    int64_t n_triangles, void* workspace, size_t ws_bytes,
+                                    sbmt_laplacian_info* info, void* stream);
+
+/* Host only: the operator's arrays inside an assembled workspace. */
+sbmt_status sbmt_laplacian_csr(void* workspace, size_t ws_bytes, int64_t n_vertices, int64_t n_triangles,
+                               sbmt_csr* out);
+
+/* y = K u (every row, boundary included).  Asynchronous. */
+sbmt_status sbmt_laplacian_apply(sbmt_handle h, const void* workspace, size_t ws_bytes, int64_t n_vertices,
+                                 int64_t n_triangles, const double* u, double* y, void* stream);
+
+/* u_i = amp * exp(-((x_i - x0)^2 + (y_i - y0)^2) / (2 sigma^2)), 0 on the
+ * boundary.  Asynchronous. */
+sbmt_status sbmt_heat_init(sbmt_handle h, const void* workspace, size_t ws_bytes, const double* verts,
+                           int64_t n_vertices, int64_t n_triangles, double x0, double y0, double sigma, double amp,
+                           double* u, void* stream);
+
+/* `steps` explicit Euler steps in place on u:
+ * u_i <- 0 on the boundary, else u_i - ((dt * alpha) * (K u)_i) / m_i.
+ * u_tmp [n_v] is scratch.  Asynchronous. */
+sbmt_status sbmt_heat_steps(sbmt_handle h, const void* workspace, size_t ws_bytes, int64_t n_vertices,
+                            int64_t n_triangles, double alpha, double dt, int32_t steps, double* u, double* u_tmp,
+                            void* stream);
 
 #ifdef __cplusplus
 }

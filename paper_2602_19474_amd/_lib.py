@@ -64,9 +64,21 @@ EXPORTS = ("sbmt_create", "sbmt_destroy", "sbmt_query", "sbmt_plan", "sbmt_run",
            "sbmt_batch_plan_async", "sbmt_batch_host_sizes",
            "sbmt_batch_mesh", "sbmt_batch_sizes", "sbmt_batch_get_tuning", "sbmt_batch_set_tuning",
            "sbmt_batch_tune", "sbmt_num_classes", "sbmt_class_code", "sbmt_status_string",
-           "sbmt_sample_field", "sbmt_quality_workspace", "sbmt_mesh_quality_async", "sbmt_mesh_quality")
+           "sbmt_sample_field", "sbmt_quality_workspace", "sbmt_mesh_quality_async", "sbmt_mesh_quality",
+           "sbmt_laplacian_workspace", "sbmt_laplacian_assemble", "sbmt_laplacian_csr", "sbmt_laplacian_apply",
+           "sbmt_heat_init", "sbmt_heat_steps")
 
 ANGLE_BINS = 30
+
+
+class LaplacianInfo(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n_boundary", ctypes.c_int64),
+                ("n_invalid", ctypes.c_int64), ("min_mass", ctypes.c_double), ("lambda_bound", ctypes.c_double)]
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("row_off", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("mass", ctypes.c_void_p), ("boundary", ctypes.c_void_p)]
 
 
 class Field(ctypes.Structure):
@@ -145,6 +157,19 @@ def lib():
     L.sbmt_mesh_quality_async.argtypes = [vp, vp, i64, vp, i64, vp, sz, vp, vp]
     L.sbmt_mesh_quality.restype = i32
     L.sbmt_mesh_quality.argtypes = [vp, vp, i64, vp, i64, vp, sz, P(Quality), vp]
+    f64 = ctypes.c_double
+    L.sbmt_laplacian_workspace.restype = i32
+    L.sbmt_laplacian_workspace.argtypes = [i64, i64, P(sz)]
+    L.sbmt_laplacian_assemble.restype = i32
+    L.sbmt_laplacian_assemble.argtypes = [vp, vp, i64, vp, i64, vp, sz, P(LaplacianInfo), vp]
+    L.sbmt_laplacian_csr.restype = i32
+    L.sbmt_laplacian_csr.argtypes = [vp, sz, i64, i64, P(Csr)]
+    L.sbmt_laplacian_apply.restype = i32
+    L.sbmt_laplacian_apply.argtypes = [vp, vp, sz, i64, i64, vp, vp, vp]
+    L.sbmt_heat_init.restype = i32
+    L.sbmt_heat_init.argtypes = [vp, vp, sz, vp, i64, i64, f64, f64, f64, f64, vp, vp]
+    L.sbmt_heat_steps.restype = i32
+    L.sbmt_heat_steps.argtypes = [vp, vp, sz, i64, i64, f64, f64, i32, vp, vp, vp]
     _lib = L
     return L
 

@@ -3,8 +3,9 @@
     python -m paper_2602_19474_amd.build
 
 Steps: regenerate the lookup-table header from ``csrc/gen_tables.py``, then
-compile ``csrc/sbmt.hip`` (the meshing path) and ``csrc/sbmt_post.hip`` (field
-sampling and mesh quality) into ``libsbmt.so`` next to this file.  Floating
+compile ``csrc/sbmt.hip`` (the meshing path), ``csrc/sbmt_post.hip`` (field
+sampling and mesh quality) and ``csrc/sbmt_pde.hip`` (cotangent Laplacian and
+heat steps) into ``libsbmt.so`` next to this file.  Floating
 point is compiled without contraction (-ffp-contract=off) so the FP64 vertex
 formulas round exactly as written; packed FP32 instructions are disabled.
 """
@@ -28,7 +29,8 @@ def build(verbose: bool = False) -> str:
                            os.path.join(CSRC, "sbmt_tables.h")])
     out = os.path.join(HERE, "libsbmt.so")
     tmp = out + ".tmp"
-    cmd = [HIPCC, *HIP_FLAGS, "-o", tmp, os.path.join(CSRC, "sbmt.hip"), os.path.join(CSRC, "sbmt_post.hip")]
+    cmd = [HIPCC, *HIP_FLAGS, "-o", tmp, os.path.join(CSRC, "sbmt.hip"), os.path.join(CSRC, "sbmt_post.hip"),
+           os.path.join(CSRC, "sbmt_pde.hip")]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

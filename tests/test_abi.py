@@ -49,6 +49,15 @@ def test_post_entry_points_on_host(L):
     assert L.sbmt_sample_field(None, ctypes.byref(f), None, 0, None, 0, None, None, None) == -1
     q = _lib.Quality()
     assert L.sbmt_mesh_quality(None, None, 0, None, 0, None, 0, ctypes.byref(q), None) == -1
+    w0, w1 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.sbmt_laplacian_workspace(10, 0, ctypes.byref(w0)) == 0
+    assert L.sbmt_laplacian_workspace(10, 1000, ctypes.byref(w1)) == 0
+    assert w1.value - w0.value >= 1000 * (12 + 24 + 48)  # incident lists, columns, values
+    assert L.sbmt_laplacian_workspace(-1, 0, ctypes.byref(w0)) == -1
+    c = _lib.Csr()
+    assert L.sbmt_laplacian_csr(None, 0, 10, 10, ctypes.byref(c)) == -4
+    info = _lib.LaplacianInfo()
+    assert L.sbmt_laplacian_assemble(None, None, 0, None, 0, None, 0, ctypes.byref(info), None) == -1
 
 
 def test_host_only_entry_points(L):

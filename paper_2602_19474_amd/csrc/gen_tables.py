@@ -22,6 +22,9 @@ App. G):
   (0 apex on the owner's row, 1 base on it) of an owner, seen through rotation
   rot, as triples of structural id slots in output order (see
   ``emission_order``), one uint16 per sub-triangle: a | b << 4 | c << 8 | side << 12.
+* ``sbmt_lut_emit_fg[class][rot][t][5]``: the foreground entries of the same
+  rows in the same order (what a foreground-only mesh emits), zero-padded, so
+  that the j-th emitted sub-triangle is one lookup.
 * ``sbmt_lut_tri[class][5]``: the template in canonical labels, one uint16 per
   sub-triangle: a | b << 4 | c << 8 | side << 12, labels 0..2 corners,
   3 + 2e + r crossing X(e, r), 9 the chain vertex; side 1 = left of the chain
@@ -254,7 +257,9 @@ def build():
                 per_t.append(row + [0] * (5 - len(row)))
             per_rot.append(per_t)
         emit.append(per_rot)
-    return {"canon": canon, "key": key, "tri": tri, "ntri": ntri, "nfg": nfg, "emit": emit}
+    emit_fg = [[[[v for v in row if (v >> 12) & 1] for row in per_t] for per_t in per_rot] for per_rot in emit]
+    emit_fg = [[[row + [0] * (5 - len(row)) for row in per_t] for per_t in per_rot] for per_rot in emit_fg]
+    return {"canon": canon, "key": key, "tri": tri, "ntri": ntri, "nfg": nfg, "emit": emit, "emit_fg": emit_fg}
 
 
 def emit_header(tables) -> str:
@@ -281,6 +286,11 @@ def emit_header(tables) -> str:
     lines.append("};")
     lines.append(f"SBMT_CONST const uint16_t sbmt_lut_emit[{len(canon) + 1}][3][2][5] = {{")
     for per_rot in tables["emit"]:
+        lines.append("  {" + ", ".join("{" + ", ".join("{" + ", ".join(f"0x{v:04x}" for v in row) + "}"
+                                                        for row in per_t) + "}" for per_t in per_rot) + "},")
+    lines.append("};")
+    lines.append(f"SBMT_CONST const uint16_t sbmt_lut_emit_fg[{len(canon) + 1}][3][2][5] = {{")
+    for per_rot in tables["emit_fg"]:
         lines.append("  {" + ", ".join("{" + ", ".join("{" + ", ".join(f"0x{v:04x}" for v in row) + "}"
                                                         for row in per_t) + "}" for per_t in per_rot) + "},")
     lines.append("};")

@@ -50,6 +50,7 @@ SBMT_HD int lut_nfg(int cls) { return sbmt_lut_nfg[cls]; }
 SBMT_HD int lut_ntri(int cls) { return sbmt_lut_ntri[cls]; }
 SBMT_HD uint32_t lut_tri(int cls, int j) { return sbmt_lut_tri[cls][j]; }
 SBMT_HD uint32_t lut_emit(int cls, int rot, int t, int j) { return sbmt_lut_emit[cls][rot][t][j]; }
+SBMT_HD uint32_t lut_emit_fg(int cls, int rot, int t, int j) { return sbmt_lut_emit_fg[cls][rot][t][j]; }
 
 constexpr int kThreads = 256;
 constexpr int kCB = 256;               // owners per row segment (one per thread)
@@ -638,6 +639,8 @@ __global__ void k_sizes(Src src, Shared sh, int64_t* __restrict__ user) {
 template <int RB>
 struct EmitLds {
   static constexpr int W = kCB + 2;  // columns c0-1 .. c0+kCB
+  static constexpr int kSlowChunk = 128;  // slow-owner records staged at a time
+  static constexpr int kSlowItems = 10;   // outputs of one kind per record, at most
   uint32_t info[RB + 1][W];
   int voff[RB + 1][W];
   int16_t toff[RB][W];
@@ -647,6 +650,9 @@ struct EmitLds {
   int bv[RB + 1];
   long long tb[RB];
   int rowv[RB + 1];  // vertices of each row's kCB owners
+  alignas(16) SlowRec srec[kSlowChunk];
+  uint16_t sitem[kSlowChunk * kSlowItems];  // record | output number << 8
+  int swt[kThreads / 64];
 };
 
 // Owner info comes from the owner map (row RB, the halo row, from hcodes when
@@ -777,19 +783,67 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
       d.codes[u] = code;
     }
   }
-  auto emit_rec = [&](const SlowRec& R) {
-    const int pos = (int)(R.x >> 48);
-    const int r = pos >> 8, col = (pos & 255) + 1;
-    if (r >= RB) return;  // the halo row is emitted by the band below
-    atomicAdd(&L.ns, 1);
-    const int k = k0 + r, c = c0 + col - 1;
-    const Nb nb = neighbours(r, col, L.info[r][col], k & 1);
-    emit_slow(g, owner_place(g, k, c, L.rowR[r]), R, nb, L.tb[r] + L.toff[r][col], out);
-  };
+  // 4. slow owners from their records, kSlowChunk records at a time: the
+  // records and the lists of their output vertices and triangles go to LDS,
+  // then one lane writes one output (records of the halo row are skipped:
+  // the band below emits them).  Record q is held by thread q mod kThreads
+  // in held[q / kThreads] while q < kHold * kThreads.
+  constexpr int kChunk = EmitLds<RB>::kSlowChunk;
+  for (int ch = 0; ch * kChunk < nrec; ++ch) {
+    const int qi = threadIdx.x & (kChunk - 1);
+    const int q = ch * kChunk + qi;
+    bool mine = false;
+    int cnt = 0;  // vertices | triangles << 16
+    if ((int)threadIdx.x / kChunk == ch % (kThreads / kChunk) && q < nrec) {
+      const int j = ch / (kThreads / kChunk);
+      SlowRec R;
+      if (j < kHold) {
+        // field by field, so that held[] stays in registers
+        static_assert(kHold == 2, "two held records per thread");
+        R.info = j == 0 ? held[0].info : held[1].info;
+        R.tri = j == 0 ? held[0].tri : held[1].tri;
+        R.x = j == 0 ? held[0].x : held[1].x;
+      } else {
+        R = sh.rec[tile * sh.tcap + q];
+      }
+      L.srec[qi] = R;
+      mine = (int)(R.x >> 56) < RB;
+      if (mine) cnt = info_nv(R.info) | (info_nt(R.info) << 16);
+    }
+    const unsigned long long bal = __ballot(mine);
+    if (lane == 0 && bal) atomicAdd(&L.ns, (int)__popcll(bal));
+    const int incl = wave_incl_scan_dpp(cnt);
+    if (lane == 63) L.swt[wv] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
 #pragma unroll
-  for (int j = 0; j < kHold; ++j)
-    if (hv[j]) emit_rec(held[j]);
-  for (int q = threadIdx.x + kHold * kThreads; q < nrec; q += kThreads) emit_rec(sh.rec[tile * sh.tcap + q]);
+    for (int w = 0; w < kThreads / 64; ++w) {
+      const int tw = L.swt[w];
+      before += w < wv ? tw : 0;
+      total += tw;
+    }
+    const int excl = before + incl - cnt;
+    for (int i = 0; i < (cnt & 0xffff); ++i) L.sitem[(excl & 0xffff) + i] = (uint16_t)(qi | (i << 8));
+    __syncthreads();
+    for (int it = threadIdx.x; it < (total & 0xffff); it += kThreads) {
+      const int item = L.sitem[it];
+      const SlowRec R = L.srec[item & 255];
+      const int r = (int)(R.x >> 56), col = (int)((R.x >> 48) & 255u) + 1;
+      const Frame f = owner_place(g, k0 + r, c0 + col - 1, L.rowR[r]);
+      emit_slow_vertex(g, f, R, item >> 8, L.voff[r][col], out);
+    }
+    __syncthreads();
+    for (int i = 0; i < (cnt >> 16); ++i) L.sitem[(excl >> 16) + i] = (uint16_t)(qi | (i << 8));
+    __syncthreads();
+    for (int it = threadIdx.x; it < (total >> 16); it += kThreads) {
+      const int item = L.sitem[it];
+      const SlowRec R = L.srec[item & 255];
+      const int r = (int)(R.x >> 56), col = (int)((R.x >> 48) & 255u) + 1;
+      const Nb nb = neighbours(r, col, L.info[r][col], (k0 + r) & 1);
+      emit_slow_triangle(g, R, item >> 8, nb, L.tb[r] + L.toff[r][col], out);
+    }
+    __syncthreads();
+  }
   __syncthreads();
   if (L.na > L.ns) {
     // slow owners beyond the tile's record region were classified by the
@@ -817,7 +871,8 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
 }
 
 template <class Src, int RB>
-__global__ void __launch_bounds__(kThreads) k_emit(Src src, const int64_t* __restrict__ tab, Shared sh) {
+// At most 102 VGPRs: five workgroups per compute unit.
+__global__ void __launch_bounds__(kThreads, 5) k_emit(Src src, const int64_t* __restrict__ tab, Shared sh) {
   __shared__ EmitLds<RB> L;
   int64_t local;
   const int ii = src.find(blockIdx.x, tab, local);

@@ -279,6 +279,7 @@ SBMT_HD int lut_nfg(int cls);
 SBMT_HD int lut_ntri(int cls);
 SBMT_HD uint32_t lut_tri(int cls, int j);
 SBMT_HD uint32_t lut_emit(int cls, int rot, int t, int j);
+SBMT_HD uint32_t lut_emit_fg(int cls, int rot, int t, int j);
 
 // Raw key of triangle t from the crossing sets, looked up into class | rot << 6.
 // Returns 0 for an uncut triangle, -1 on a protocol violation.  The candidate
@@ -712,80 +713,77 @@ SBMT_HD int slot_id(const int (&ids)[16], int sl) {
   return b3 ? z1 : z0;
 }
 
-// Emit the sub-triangles of cut triangle t in output order (Alg. 2, steps
-// 3-4): the table already holds them rotated and sorted by id.
-SBMT_HD void emit_cut(const Geo& g, const SlowRec& r, int t, const Nb& nb, int64_t& tp, const Out& out) {
-  const bool both = (g.flags & 1u) != 0;
-  const int cls = (int)((r.tri >> (8 * t)) & 31u), rot = (int)((r.tri >> (8 * t + 5)) & 3u);
-  const int hasIb = ((r.tri >> 16) & 15u) != 15u;
-  const int ids[16] = {nb.vid, nb.b0, nb.b0 + 1, nb.b1, nb.b1 + 1, nb.b2, nb.b2 + 1, nb.bI, nb.bI + hasIb,
-                       nb.id_vr, nb.b3, nb.b3 + 1, nb.id_vdl, nb.b4, nb.b4 + 1, nb.id_vdr};
-  const int nt = lut_ntri(cls);
-#pragma unroll
-  for (int j = 0; j < 5; ++j) {
-    const uint32_t w = lut_emit(cls, rot, t, j);
-    const int side = (int)((w >> 12) & 1u);
-    if (j < nt && (both || side)) {
-      const int64_t u = tp - out.tbase;
-      put_tri(out.t, u, slot_id(ids, (int)(w & 15u)), slot_id(ids, (int)((w >> 4) & 15u)),
-              slot_id(ids, (int)((w >> 8) & 15u)));
-      out.c[u] = (uint8_t)(cls | (side ? 0 : 0x80));
-      ++tp;
-    }
-  }
-}
-
-// Emit one slow owner from its record.
-SBMT_HD void emit_slow(const Geo& g, const Frame& f, const SlowRec& r, const Nb& nb, int64_t to, const Out& out) {
-  const bool both = (g.flags & 1u) != 0;
+// Vertex `sub` of a slow owner, in the owner's vertex order (the vertex
+// itself if emitted, the crossings on E0, E1, E2 in order from the owner, the
+// chain vertex of Tb, then of Ta), written to id vid + sub.  Crossing
+// X = P + t (Q - P), t = dP / (dP - dQ), dP = (V-U) x (P-U), dQ = (V-U) x (Q-U).
+SBMT_HD void emit_slow_vertex(const Geo& g, const Frame& f, const SlowRec& r, int sub, int64_t vid,
+                              const Out& out) {
   const uint32_t info = r.info;
-  const int fg = info_fg(info);
+  const int self = info_self(info);
+  const int n0 = info_n(info, 0), n1 = info_n(info, 1), n2 = info_n(info, 2);
   const double ux = lat_x(f.X), uy = lat_y(g.h, f.k);
-  int64_t p = nb.vid;
-  if (info_self(info)) put_vertex(out.v, p++ - out.vbase, ux, uy);
-  // crossings on E0, E1, E2 in order from the owner: X = P + t (Q - P),
-  // t = dP / (dP - dQ), dP = (V-U) x (P-U), dQ = (V-U) x (Q-U)
-#pragma unroll
-  for (int e = 0; e < 3; ++e) {
-    const int n = info_n(info, e);
+  double x = ux, y = uy;
+  const int s = sub - self;
+  if (s >= 0 && s < n0 + n1 + n2) {
+    const int e = s < n0 ? 0 : (s < n0 + n1 ? 1 : 2);
+    const int re = s - (e == 0 ? 0 : (e == 1 ? n0 : n0 + n1));
     const int vX = e == 0 ? f.X + 4 * g.h : (e == 1 ? f.X - 2 * g.h : f.X + 2 * g.h);
     const double vx = lat_x(vX), vy = lat_y(g.h, e == 0 ? f.k : f.k + 1);
     const double gx = vx - ux, gy = vy - uy;
-#pragma unroll
-    for (int re = 0; re < 2; ++re) {
-      if (re < n) {
-        const uint32_t pq = (uint32_t)(r.x >> (16 * e + 8 * re)) & 255u;
-        const int pm = (int)(pq & 15u), qm = (int)(pq >> 4);
-        const double px = 0.25 * (double)mid_x(g, f, pm), py = 0.25 * (double)mid_y(g, f, pm);
-        const double qx = 0.25 * (double)mid_x(g, f, qm), qy = 0.25 * (double)mid_y(g, f, qm);
-        const double dp = gx * (py - uy) - gy * (px - ux);
-        const double dq = gx * (qy - uy) - gy * (qx - ux);
-        const double tt = dp / (dp - dq);
-        put_vertex(out.v, p++ - out.vbase, px + tt * (qx - px), py + tt * (qy - py));
-      }
-    }
+    const uint32_t pq = (uint32_t)(r.x >> (16 * e + 8 * re)) & 255u;
+    const int pm = (int)(pq & 15u), qm = (int)(pq >> 4);
+    const double px = 0.25 * (double)mid_x(g, f, pm), py = 0.25 * (double)mid_y(g, f, pm);
+    const double qx = 0.25 * (double)mid_x(g, f, qm), qy = 0.25 * (double)mid_y(g, f, qm);
+    const double dp = gx * (py - uy) - gy * (px - ux);
+    const double dq = gx * (qy - uy) - gy * (qx - ux);
+    const double tt = dp / (dp - dq);
+    x = px + tt * (qx - px);
+    y = py + tt * (qy - py);
+  } else if (s >= 0) {
+    const int mb = (int)((r.tri >> 16) & 15u), ma = (int)((r.tri >> 20) & 15u);
+    const int m = (s == n0 + n1 + n2 && mb != 15) ? mb : ma;
+    x = 0.25 * (double)mid_x(g, f, m);
+    y = 0.25 * (double)mid_y(g, f, m);
   }
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const int m = (int)((r.tri >> (16 + 4 * t)) & 15u);
-    if (m != 15) put_vertex(out.v, p++ - out.vbase, 0.25 * (double)mid_x(g, f, m), 0.25 * (double)mid_y(g, f, m));
+  put_vertex(out.v, vid + sub - out.vbase, x, y);
+}
+
+// Triangle `sub` of a slow owner, in the owner's triangle order (those of Tb,
+// then of Ta; a cut triangle's emitted sub-triangles in table order), written
+// to triangle to + sub.
+SBMT_HD void emit_slow_triangle(const Geo& g, const SlowRec& r, int sub, const Nb& nb, int64_t to,
+                                const Out& out) {
+  const bool both = (g.flags & 1u) != 0;
+  const uint32_t info = r.info;
+  const int ntb = info_ntb(info);
+  const int t = sub < ntb ? 0 : 1;
+  const int j = sub - (t ? ntb : 0);
+  const int cls = (int)((r.tri >> (8 * t)) & 31u);
+  const int64_t u = to + sub - out.tbase;
+  if (cls == 0) {
+    put_tri(out.t, u, nb.vid, t == 0 ? nb.id_vdr : nb.id_vr, t == 0 ? nb.id_vdl : nb.id_vdr);
+    out.c[u] = both && !info_fg(info) ? 0x80 : 0;
+    return;
   }
-  int64_t tp = to;
-  const uint8_t ucode = both && !fg ? 0x80 : 0;
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const int cls = (int)((r.tri >> (8 * t)) & 31u);
-    if (cls == 0) {
-      if ((t == 0 ? info_ntb(info) : info_nta(info)) != 0) {
-        const int64_t u = tp - out.tbase;
-        put_tri(out.t, u, nb.vid, t == 0 ? nb.id_vdr : nb.id_vr, t == 0 ? nb.id_vdl : nb.id_vdr);
-        out.c[u] = ucode;
-        ++tp;
-      }
-    } else {
-      emit_cut(g, r, t, nb, tp, out);
-    }
-  }
+  const int rot = (int)((r.tri >> (8 * t + 5)) & 3u);
+  const int hasIb = ((r.tri >> 16) & 15u) != 15u;
+  const int ids[16] = {nb.vid, nb.b0, nb.b0 + 1, nb.b1, nb.b1 + 1, nb.b2, nb.b2 + 1, nb.bI, nb.bI + hasIb,
+                       nb.id_vr, nb.b3, nb.b3 + 1, nb.id_vdl, nb.b4, nb.b4 + 1, nb.id_vdr};
+  // the j-th emitted entry of the template: every entry with both sides,
+  // else the j-th foreground one
+  const uint32_t w = both ? lut_emit(cls, rot, t, j) : lut_emit_fg(cls, rot, t, j);
+  const int side = (int)((w >> 12) & 1u);
+  put_tri(out.t, u, slot_id(ids, (int)(w & 15u)), slot_id(ids, (int)((w >> 4) & 15u)),
+          slot_id(ids, (int)((w >> 8) & 15u)));
+  out.c[u] = (uint8_t)(cls | (side ? 0 : 0x80));
+}
+
+// Emit one slow owner from its record (one thread for all its outputs).
+SBMT_HD void emit_slow(const Geo& g, const Frame& f, const SlowRec& r, const Nb& nb, int64_t to, const Out& out) {
+  const int nv = info_nv(r.info), nt = info_nt(r.info);
+  for (int s = 0; s < nv; ++s) emit_slow_vertex(g, f, r, s, nb.vid, out);
+  for (int s = 0; s < nt; ++s) emit_slow_triangle(g, r, s, nb, to, out);
 }
 
 }  // namespace sbmt

@@ -339,7 +339,27 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
   int wcol[2];
 #pragma unroll
   for (int o = 0; o < 2; ++o) wcol[o] = clo_of(g, g.X0 + 4 * g.h * c + 2 * g.h * o) + kRingC - bw.cc0;
-  for (int r = 0; r < RB; ++r) {
+  // away from the grid edges both owned triangles exist for every owner, so a
+  // uniform owner's counts are constants and a row's sums are popcounts
+  const bool interior = k0 + RB < g.NK && c0 >= 1 && c0 + kCB < g.NI;
+  const bool both = (g.flags & 1u) != 0;
+  if (interior) {
+    const uint32_t code_fg = map_code(fast_info_k(g, k0, c0 + 1, 1)), code_bg = map_code(fast_info_k(g, k0, c0 + 1, 0));
+    for (int r = 0; r < RB; ++r) {
+      const int wc = wcol[(k0 + r) & 1], w = wc >> 5, sh = wc & 31;
+      const int kind = (int)((L.u0[r][w] >> sh) & 1u) | ((int)((L.u1[r][w] >> sh) & 1u) << 1);
+      if (kind) L.code[r][threadIdx.x] = (uint16_t)(kind == 2 ? code_fg : code_bg);
+      else L.q1[atomicAdd(&L.n1, 1)] = (uint16_t)(r * kCB + threadIdx.x);
+      // vertices: one per counted owner; triangles: two
+      const unsigned long long m = __ballot(both ? kind != 0 : kind == 2);
+      if (lane == 0 && m) {
+        const int n = (int)__popcll(m);
+        atomicAdd(&L.acc[r][0], n);
+        atomicAdd(&L.acc[r][1], 2 * n);
+      }
+    }
+  }
+  for (int r = 0; r < RB && !interior; ++r) {
     const int k = k0 + r;
     if (k >= g.NK) break;
     int p = 0;  // vertices | triangles << 16

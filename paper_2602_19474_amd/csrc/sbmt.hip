@@ -692,24 +692,31 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
   bw.wpr = g.wpr;
   bw.rr0 = 0;
   bw.cc0 = 0;
-  // 1. info words: all loads of the thread first (owner codes of the window
-  // and the tile's records), so their latencies overlap
-  constexpr int kPer = ((RB + 1) * W + kThreads - 1) / kThreads;
+  // 1. every wave loads the owner codes of its rows (wave w: rows w, w + 4,
+  // ...; lane = column within each block of 64, lanes 0 and 1 also the
+  // columns c0-1 and c0+kCB) and the tile's records, all loads first so that
+  // their latencies overlap
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int kWaves = kThreads / 64;
+  constexpr int kRowsW = (RB + 1 + kWaves - 1) / kWaves;
+  constexpr int kU = kCB / 64;
   constexpr int kHold = 2;
-  uint32_t codes[kPer];
+  uint32_t codes[kRowsW][kU], edge[kRowsW];
   SlowRec held[kHold];
   bool hv[kHold];
   const int nrec = (int)min((int64_t)sh.tile_n[tile], sh.tcap);
+  // 0xffff marks a position outside the grid (no owner code has all bits set)
+  auto load_code = [&](int rr, int c) -> uint32_t {
+    const int k = k0 + rr;
+    if (k >= g.NK || c < 0 || c >= g.NI) return 0xffffu;
+    return (rr == RB && hcodes) ? (uint32_t)hcodes[c] : (uint32_t)d.omap[(int64_t)k * g.NI + c];
+  };
 #pragma unroll
-  for (int j = 0; j < kPer; ++j) {
-    const int idx = threadIdx.x + j * kThreads;
-    const int rr = idx / W, col = idx - rr * W;
-    const int k = k0 + rr, c = c0 - 1 + col;
-    // 0xffff marks a position outside the grid (no owner code has all bits set)
-    uint32_t v = 0xffffu;
-    if (idx < (RB + 1) * W && k < g.NK && c >= 0 && c < g.NI)
-      v = (rr == RB && hcodes) ? (uint32_t)hcodes[c] : (uint32_t)d.omap[(int64_t)k * g.NI + c];
-    codes[j] = v;
+  for (int m = 0; m < kRowsW; ++m) {
+    const int rr = wv + kWaves * m;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) codes[m][u] = rr <= RB ? load_code(rr, c0 + 64 * u + lane) : 0xffffu;
+    edge[m] = (rr <= RB && lane < 2) ? load_code(rr, lane == 0 ? c0 - 1 : c0 + kCB) : 0xffffu;
   }
 #pragma unroll
   for (int j = 0; j < kHold; ++j) {
@@ -717,30 +724,22 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
     hv[j] = q < nrec;
     if (hv[j]) held[j] = sh.rec[tile * sh.tcap + q];
   }
+  // 2. per row: info words into LDS and the prefix sums, in four blocks of 64
+  // consecutive columns (a DPP wave scan each; vertex and triangle counts of
+  // a row segment stay below 2^16: packed)
 #pragma unroll
-  for (int j = 0; j < kPer; ++j) {
-    const int idx = threadIdx.x + j * kThreads;
-    if (idx >= (RB + 1) * W) break;
-    const int rr = idx / W, col = idx - rr * W;
-    uint32_t fi = 0;
-    if (codes[j] != 0xffffu) {
-      fi = map_info(codes[j]);
-      if ((codes[j] & 0x8000u) && rr < RB && col >= 1 && col <= kCB) atomicAdd(&L.na, 1);  // owned slow owners
-    }
-    L.info[rr][col] = fi;
-  }
-  __syncthreads();
-  // 2. prefix sums, one wave per row, in four blocks of 64 consecutive
-  // columns (a DPP wave scan each, consecutive lanes on consecutive LDS words;
-  // vertex and triangle counts of a row segment stay below 2^16: packed)
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int rr = wv; rr <= RB; rr += kThreads / 64) {
+  for (int m = 0; m < kRowsW; ++m) {
+    const int rr = wv + kWaves * m;
+    if (rr > RB) break;  // uniform per wave
     const int bv = L.bv[rr];
     int carry = 0;
 #pragma unroll
-    for (int u = 0; u < kCB / 64; ++u) {
+    for (int u = 0; u < kU; ++u) {
       const int col = 1 + 64 * u + lane;
-      const uint32_t f = L.info[rr][col];
+      const uint32_t cd = codes[m][u];
+      const uint32_t f = cd != 0xffffu ? map_info(cd) : 0u;
+      if (rr < RB && cd != 0xffffu && (cd & 0x8000u)) atomicAdd(&L.na, 1);  // owned slow owners
+      L.info[rr][col] = f;
       const int p = info_nv(f) | (info_nt(f) << 16);
       const int incl = wave_incl_scan_dpp(p);
       const int e = carry + incl - p;
@@ -748,8 +747,11 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
       if (rr < RB) L.toff[rr][col] = (int16_t)(e >> 16);
       carry += __builtin_amdgcn_readlane(incl, 63);
     }
+    const uint32_t fe = edge[m] != 0xffffu ? map_info(edge[m]) : 0u;
+    if (lane < 2) L.info[rr][lane == 0 ? 0 : W - 1] = fe;
+    const int nv_left = __builtin_amdgcn_readlane(info_nv(fe), 0);
     if (lane == 0) {
-      L.voff[rr][0] = bv - info_nv(L.info[rr][0]);
+      L.voff[rr][0] = bv - nv_left;
       L.voff[rr][W - 1] = bv + (carry & 0xffff);
       L.rowv[rr] = carry & 0xffff;
     }

@@ -12,9 +12,12 @@
 //   6. per vertex: the row (neighbours in order of first appearance, edge
 //      weights accumulated in triangle order) and the Gershgorin bound.
 // Every floating-point sum runs in a fixed order, so the operator is the
-// same bit for bit on every run.  A heat step is one thread per row over the
-// row's contiguous entries (HBM bound: the CSR arrays are read once per step,
-// the field values mostly from L2 because neighbours have nearby ids).
+// same bit for bit on every run.  For the steps the rows are also laid out in
+// slices of 64 (entry e of the 64 rows of a slice side by side), so that one
+// thread per row still sums its row in row order while a wave's loads of
+// entry e coalesce (HBM bound: the operator is read once per step, the field
+// values mostly from L2 because neighbours have nearby ids).  A mesh whose
+// padded slices would not fit the space reserved for them steps on the rows.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -307,22 +310,75 @@ __global__ void __launch_bounds__(kThreads) k_apply(const int64_t* __restrict__ 
   }
 }
 
-__global__ void __launch_bounds__(kThreads) k_heat_step(const int64_t* __restrict__ row_off,
-                                                        const int32_t* __restrict__ col,
-                                                        const double* __restrict__ val,
-                                                        const double* __restrict__ mass,
-                                                        const uint8_t* __restrict__ bnd, int64_t nv, double dt_alpha,
-                                                        const double* __restrict__ u, double* __restrict__ out) {
+// Slices of 64 rows: width = the longest row of the slice (times 64 entries).
+__global__ void __launch_bounds__(kThreads) k_slice_width(const int32_t* __restrict__ row_len, int64_t nv,
+                                                          int64_t nsl, int32_t* __restrict__ w64) {
+  const int64_t step = (int64_t)gridDim.x * kThreads;
+  for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < nsl; q += step) {
+    int m = 0;
+    for (int j = 0; j < 64; ++j) {
+      const int64_t i = q * 64 + j;
+      if (i < nv) m = max(m, row_len[i]);
+    }
+    w64[q] = 64 * m;
+  }
+}
+
+// Copies the rows into their slices (entry e of row i at
+// slice_off[i / 64] + 64 e + i mod 64) when they fit the reserved space.
+__global__ void __launch_bounds__(kThreads) k_slice_fill(const int64_t* __restrict__ row_off,
+                                                         const int32_t* __restrict__ col,
+                                                         const double* __restrict__ val,
+                                                         const int32_t* __restrict__ row_len, int64_t nv,
+                                                         const int64_t* __restrict__ slice_off, int64_t nsl,
+                                                         int64_t cap, int32_t* __restrict__ col_s,
+                                                         double* __restrict__ val_s) {
+  if (slice_off[nsl] > cap) return;  // uniform: the steps use the rows
   const int64_t step = (int64_t)gridDim.x * kThreads;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nv; i += step) {
-    if (bnd[i]) {
+    const int64_t base = slice_off[i >> 6] + (i & 63), r0 = row_off[i];
+    for (int e = 0; e < row_len[i]; ++e) {
+      col_s[base + 64 * (int64_t)e] = col[r0 + e];
+      val_s[base + 64 * (int64_t)e] = val[r0 + e];
+    }
+  }
+}
+
+struct Op {  // what a step reads
+  const int64_t* row_off;
+  const int32_t* col;
+  const double* val;
+  const int32_t* row_len;
+  const int64_t* slice_off;
+  const int32_t* col_s;
+  const double* val_s;
+  const double* mass;
+  const uint8_t* bnd;
+  int64_t nsl, cap;
+};
+
+__global__ void __launch_bounds__(kThreads) k_heat_step(Op op, int64_t nv, double dt_alpha,
+                                                        const double* __restrict__ u, double* __restrict__ out) {
+  const bool sliced = op.slice_off[op.nsl] <= op.cap;  // uniform
+  const int64_t step = (int64_t)gridDim.x * kThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nv; i += step) {
+    if (op.bnd[i]) {
       out[i] = 0.0;
       continue;
     }
     const double ui = u[i];
     double s = 0.0;
-    for (int64_t e = row_off[i], end = row_off[i + 1]; e < end; ++e) s += val[e] * (ui - u[col[e]]);
-    out[i] = ui - (dt_alpha * s) / mass[i];
+    if (sliced) {
+      const int64_t base = op.slice_off[i >> 6] + (i & 63);
+      const int len = op.row_len[i];
+      for (int e = 0; e < len; ++e) {
+        const int64_t x = base + 64 * (int64_t)e;
+        s += op.val_s[x] * (ui - u[op.col_s[x]]);
+      }
+    } else {
+      for (int64_t e = op.row_off[i], end = op.row_off[i + 1]; e < end; ++e) s += op.val[e] * (ui - u[op.col[e]]);
+    }
+    out[i] = ui - (dt_alpha * s) / op.mass[i];
   }
 }
 
@@ -350,7 +406,9 @@ __global__ void __launch_bounds__(kThreads) k_copy(const double* __restrict__ a,
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t info, deg, cursor, inc_off, inc, row_len, row_off, col, val, mass, bnd, sums, total;
+  size_t info, deg, cursor, inc_off, inc, row_len, row_off, col, val, mass, bnd, sums, slice_off, col_s, val_s,
+      total;
+  int64_t nsl, cap;
 };
 
 static int64_t scan_blocks(int64_t n) { return (n + kScanBlock - 1) / kScanBlock; }
@@ -375,6 +433,11 @@ static Layout layout(int64_t nv, int64_t nt) {
   L.mass = take(8 * (size_t)nv);
   L.bnd = take((size_t)nv);
   L.sums = take(8 * (size_t)(scan_blocks(nv) + 1));
+  L.nsl = (nv + 63) / 64;
+  L.cap = 6 * nt;  // as many entries as the rows may hold: padding beyond twice the entries falls back
+  L.slice_off = take(8 * (size_t)(L.nsl + 1));
+  L.col_s = take(4 * (size_t)L.cap);
+  L.val_s = take(8 * (size_t)L.cap);
   L.total = o;
   return L;
 }
@@ -470,6 +533,16 @@ sbmt_status sbmt_laplacian_assemble(sbmt_handle h, const double* verts, int64_t 
     hipLaunchKernelGGL(k_rows_fill, dim3(grid_for(n_vertices)), dim3(kThreads), 0, s, v, tris, n_vertices,
                        (const int64_t*)inc_off, (const int32_t*)inc, (const int64_t*)row_off, (const double*)mass,
                        col, val, dinfo);
+  // the rows in slices of 64 for the steps (the slice widths reuse the
+  // degree array, which is free by now)
+  int64_t* slice_off = (int64_t*)(w + L.slice_off);
+  hipLaunchKernelGGL(k_slice_width, dim3(grid_for(L.nsl)), dim3(kThreads), 0, s, (const int32_t*)row_len, n_vertices,
+                     L.nsl, deg);
+  if ((st = scan(deg, L.nsl, sums, slice_off, s)) != SBMT_OK) return st;
+  if (n_vertices > 0)
+    hipLaunchKernelGGL(k_slice_fill, dim3(grid_for(n_vertices)), dim3(kThreads), 0, s, (const int64_t*)row_off,
+                       (const int32_t*)col, (const double*)val, (const int32_t*)row_len, n_vertices,
+                       (const int64_t*)slice_off, L.nsl, L.cap, (int32_t*)(w + L.col_s), (double*)(w + L.val_s));
   if (hipGetLastError() != hipSuccess) return SBMT_E_DEVICE;
   Info hi;
   int64_t nnz = 0;
@@ -525,12 +598,22 @@ sbmt_status sbmt_heat_steps(sbmt_handle h, const void* workspace, size_t ws_byte
   const char* w = (const char*)workspace;
   hipStream_t s = (hipStream_t)stream;
   const double dt_alpha = dt * alpha;
+  Op op;
+  op.row_off = (const int64_t*)(w + L.row_off);
+  op.col = (const int32_t*)(w + L.col);
+  op.val = (const double*)(w + L.val);
+  op.row_len = (const int32_t*)(w + L.row_len);
+  op.slice_off = (const int64_t*)(w + L.slice_off);
+  op.col_s = (const int32_t*)(w + L.col_s);
+  op.val_s = (const double*)(w + L.val_s);
+  op.mass = (const double*)(w + L.mass);
+  op.bnd = (const uint8_t*)(w + L.bnd);
+  op.nsl = L.nsl;
+  op.cap = L.cap;
   double* a = u;
   double* b = u_tmp;
   for (int32_t k = 0; k < steps; ++k) {
-    hipLaunchKernelGGL(k_heat_step, dim3(grid_for(n_vertices)), dim3(kThreads), 0, s,
-                       (const int64_t*)(w + L.row_off), (const int32_t*)(w + L.col), (const double*)(w + L.val),
-                       (const double*)(w + L.mass), (const uint8_t*)(w + L.bnd), n_vertices, dt_alpha,
+    hipLaunchKernelGGL(k_heat_step, dim3(grid_for(n_vertices)), dim3(kThreads), 0, s, op, n_vertices, dt_alpha,
                        (const double*)a, b);
     double* t = a;
     a = b;

@@ -125,3 +125,35 @@ def test_noise8192_operator_and_steps():
     lap.heat_steps(ug, 500.0, dt, 10)
     assert np.array_equal(ug.cpu().numpy(), oracle.heat_steps(vn, tn, u0, 500.0, dt, 10))
     print(f"[gpu-pde] noise8192 done at {time.time() - t0:.1f}s", flush=True)
+
+
+def test_steps_fall_back_to_rows_for_a_fan():
+    """One vertex with 100 triangles: its slice of 64 rows would need 64 x 101
+    entries, more than the space kept for slices, so the steps use the rows."""
+    import torch
+
+    from paper_2602_19474_amd.pde import Laplacian
+    m = 100
+    ang = np.linspace(0.0, 1.9 * math.pi, m + 1)
+    rim = np.stack([np.cos(ang), np.sin(ang)], 1) * (1.0 + 0.1 * np.sin(7 * ang))[:, None]
+    v = np.concatenate([[[0.0, 0.0]], rim])
+    t = np.array([[0, 1 + j, 2 + j] for j in range(m)], np.int32)
+    # a second ring of triangles so that the inner rim vertices are interior
+    v2 = np.concatenate([v, v[1:] * 2.0])
+    t2 = np.concatenate([t, np.array([[1 + j, m + 2 + j, 2 + j] for j in range(m)], np.int32),
+                         np.array([[2 + j, m + 2 + j, m + 3 + j] for j in range(m)], np.int32)])
+    area = ((v2[t2[:, 1], 0] - v2[t2[:, 0], 0]) * (v2[t2[:, 2], 1] - v2[t2[:, 0], 1])
+            - (v2[t2[:, 1], 1] - v2[t2[:, 0], 1]) * (v2[t2[:, 2], 0] - v2[t2[:, 0], 0]))
+    t2[area < 0] = t2[area < 0][:, [0, 2, 1]]
+    vt, tt = torch.from_numpy(v2).cuda(), torch.from_numpy(t2).cuda()
+    lap = Laplacian(vt, tt)
+    ref = oracle.laplacian(v2, t2)
+    _check_operator(lap, ref, "fan")
+    assert 64 * (int(np.diff(ref["row_off"]).max())) > 6 * t2.shape[0]  # the slices do not fit
+    u0 = np.random.default_rng(8).uniform(0, 1, v2.shape[0])
+    u0[ref["boundary"]] = 0.0
+    dt = 1.9 / (500.0 * ref["lambda_bound"])
+    for steps in (1, 6):
+        ug = torch.from_numpy(u0).cuda()
+        lap.heat_steps(ug, 500.0, dt, steps)
+        assert np.array_equal(ug.cpu().numpy(), oracle.heat_steps(v2, t2, u0, 500.0, dt, steps)), steps

@@ -13,8 +13,9 @@ Extra objects on the same line:
                 against the MI355X peak, timed with HIP events on its stream
   cpu_baseline  the CPU oracle on a bounded sample of the same workload
   latency       p50/p99 per-image latency (plan + run + sync) of small images
-  batch256      the 256-image batch workload: plain per-image loop and the
-                batched path (autotuned, replayed as one captured graph),
+  batch256      the 256-image batch workload: plain per-image loop, the
+                batched path (autotuned, replayed as one captured graph) and
+                the persistent fused launch at its best tuning (also a graph),
                 triangles/s, MPix/s and HBM fraction
   serve         the request stream: plain path per request (FIFO, one stream)
                 and the continuous-batching server, same Poisson arrivals,
@@ -294,6 +295,44 @@ def batch_section(items, repeats: int = 5):
                       "tuning": best.__dict__, "launch": "one hipGraph replay per step",
                       "workspace_gb": b.ws.numel() / 1e9}
     out["speedup"] = out["batched"]["tri_per_s"] / out["plain"]["tri_per_s"]
+    # the persistent fused launch (coarsening, then one classify-scan-emit
+    # kernel): the best of its tunings, replayed as a graph like the above
+    from paper_2602_19474_amd import SbmtError
+    from paper_2602_19474_amd.batch import Tuning
+    try:
+        trials = []
+        for rows in (4, 8):
+            for gpc in (1, 2, 3):
+                b.tuning = Tuning(strategy=1, tile_rows=rows, groups_per_cu=gpc)
+                b.mesh()
+                torch.cuda.synchronize()
+                ev[0].record()
+                for _ in range(2):
+                    b.mesh()
+                ev[1].record()
+                torch.cuda.synchronize()
+                trials.append((ev[0].elapsed_time(ev[1]) / 2, rows, gpc))
+        _, rows, gpc = min(trials)
+        b.tuning = Tuning(strategy=1, tile_rows=rows, groups_per_cu=gpc)
+        gf = b.capture()
+        gf.replay()
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(repeats):
+            gf.replay()
+        ev[1].record()
+        torch.cuda.synchronize()
+        fms = ev[0].elapsed_time(ev[1]) / repeats
+        st = b.sizes()
+        assert all(x[3] == 0 for x in st) and sum(x[1] for x in st) == tri, "fused path differs"
+        out["fused"] = {"ms": fms, "tri_per_s": tri / (fms * 1e-3), "mpix_per_s": px / 1e6 / (fms * 1e-3),
+                        "tuning": {"tile_rows": rows, "groups_per_cu": gpc},
+                        "launch": "coarsening + one persistent classify-scan-emit kernel, one hipGraph replay",
+                        "vs_batched": fms / ms,
+                        "trials_ms": {f"rows{r}_gpc{q}": t for t, r, q in trials}}
+        del gf
+    except SbmtError as e:  # the batch does not fit the persistent kernel's limits
+        out["fused"] = {"skipped": str(e)}
     del b, g
     torch.cuda.empty_cache()
     return out

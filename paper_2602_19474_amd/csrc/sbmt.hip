@@ -49,8 +49,6 @@ SBMT_HD int lut_key(int code) { return sbmt_lut_key[code]; }
 SBMT_HD int lut_nfg(int cls) { return sbmt_lut_nfg[cls]; }
 SBMT_HD int lut_ntri(int cls) { return sbmt_lut_ntri[cls]; }
 SBMT_HD uint32_t lut_tri(int cls, int j) { return sbmt_lut_tri[cls][j]; }
-SBMT_HD uint32_t lut_emit(int cls, int rot, int t, int j) { return sbmt_lut_emit[cls][rot][t][j]; }
-SBMT_HD uint32_t lut_emit_fg(int cls, int rot, int t, int j) { return sbmt_lut_emit_fg[cls][rot][t][j]; }
 
 constexpr int kThreads = 256;
 constexpr int kCB = 256;               // owners per row segment (one per thread)
@@ -653,17 +651,18 @@ __global__ void k_sizes(Src src, Shared sh, int64_t* __restrict__ user) {
 //      give each owner's first vertex and triangle id and its neighbours' ids;
 //   3. fast and quiet owners are emitted one per thread, then the slow owners
 //      of the tile densely from their records.
-// The caller fills bv[0..RB] (image-local first vertex of each row's segment,
-// row RB = the halo row) and tb[0..RB-1] (first triangle) and syncs.
+// bv[0..RB] (image-local first vertex of each row's segment, row RB = the halo
+// row) and tb[0..RB-1] (first triangle) come from the caller: written before
+// the call (the persistent kernel) or by the `bases` callback.
 // ---------------------------------------------------------------------------
 template <int RB>
 struct EmitLds {
   static constexpr int W = kCB + 2;  // columns c0-1 .. c0+kCB
   static constexpr int kSlowChunk = 128;  // slow-owner records staged at a time
   static constexpr int kSlowItems = 10;   // outputs of one kind per record, at most
-  uint32_t info[RB + 1][W];
-  int voff[RB + 1][W];
-  int16_t toff[RB][W];
+  uint16_t info[RB + 1][W];  // owner codes (0 outside the grid)
+  int16_t voff[RB + 1][W];   // first vertex of each owner, from bv of its row
+  int16_t toff[RB][W];       // first triangle of each owner, from tb of its row
   uint32_t hasrec[RB * kCB / 32];
   int na, ns;
   int rowR[RB + 1];
@@ -672,6 +671,7 @@ struct EmitLds {
   int rowv[RB + 1];  // vertices of each row's kCB owners
   alignas(16) SlowRec srec[kSlowChunk];
   uint16_t sitem[kSlowChunk * kSlowItems];  // record | output number << 8
+  uint16_t lut[15 * 3 * 2 * 5];              // emission table of the side mode
   int swt[kThreads / 64];
 };
 
@@ -679,14 +679,26 @@ struct EmitLds {
 // given), slow owners' emission data from the records of count tile `tile`
 // (each record carries the owner's place in the tile; records of the halo
 // row, which the persistent kernel keeps in the same region, are skipped).
-template <int RB>
+// What is emitted:
+//   kEmitAll      everything (the persistent kernel);
+//   kEmitRecords  fast and quiet owners and the slow owners with a record;
+//   kEmitMissing  only the slow owners without a record (the count tile's
+//                 record region was full; the count pass classified them).
+constexpr int kEmitAll = 0, kEmitRecords = 1, kEmitMissing = 2;
+// `bases(L)` fills L.bv[0..RB] and L.tb[0..RB-1] (see above); it is called
+// once the tile's other loads are issued, so that its latency overlaps theirs.
+template <int RB, int kMode = kEmitAll, class Bases>
 __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, int cb, int64_t tile, const Shared& sh,
-                                          EmitLds<RB>& L, const uint16_t* __restrict__ hcodes) {
+                                          EmitLds<RB>& L, const uint16_t* __restrict__ hcodes, Bases&& bases) {
   constexpr int W = EmitLds<RB>::W;
+  constexpr int kLut = 15 * 3 * 2 * 5;
+  static_assert(kLut <= 2 * kThreads, "two table entries per thread");
   const int c0 = cb * kCB;
-  if (threadIdx.x <= RB) L.rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);
-  if (threadIdx.x == 0) L.na = L.ns = 0;
-  __syncthreads();
+  if (threadIdx.x <= RB) L.rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);  // read after step 2
+  if (kMode == kEmitAll) {
+    if (threadIdx.x == 0) L.na = L.ns = 0;
+    __syncthreads();
+  }
   Bits bw;
   bw.p = d.bits;
   bw.wpr = g.wpr;
@@ -696,7 +708,8 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
   // ...; lane = column within each block of 64, lanes 0 and 1 also the
   // columns c0-1 and c0+kCB) and the tile's records, all loads first so that
   // their latencies overlap
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // the wave index is uniform: its rows' addresses are computed once per wave
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   constexpr int kWaves = kThreads / 64;
   constexpr int kRowsW = (RB + 1 + kWaves - 1) / kWaves;
   constexpr int kU = kCB / 64;
@@ -721,55 +734,62 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
 #pragma unroll
   for (int j = 0; j < kHold; ++j) {
     const int q = threadIdx.x + j * kThreads;
-    hv[j] = q < nrec;
+    hv[j] = kMode != kEmitMissing && q < nrec;
     if (hv[j]) held[j] = sh.rec[tile * sh.tcap + q];
   }
-  // 2. per row: info words into LDS and the prefix sums, in four blocks of 64
+  // the emission table of the side mode, to LDS in step 2
+  const uint16_t* lt = (g.flags & 1u) ? &sbmt_lut_emit[0][0][0][0] : &sbmt_lut_emit_fg[0][0][0][0];
+  const uint16_t lut0 = lt[threadIdx.x];
+  const uint16_t lut1 = threadIdx.x + kThreads < kLut ? lt[threadIdx.x + kThreads] : 0;
+  bases(L);
+  // 2. per row: owner codes into LDS and the prefix sums, in four blocks of 64
   // consecutive columns (a DPP wave scan each; vertex and triangle counts of
   // a row segment stay below 2^16: packed)
+  L.lut[threadIdx.x] = lut0;
+  if (threadIdx.x + kThreads < kLut) L.lut[threadIdx.x + kThreads] = lut1;
 #pragma unroll
   for (int m = 0; m < kRowsW; ++m) {
     const int rr = wv + kWaves * m;
     if (rr > RB) break;  // uniform per wave
-    const int bv = L.bv[rr];
     int carry = 0;
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int col = 1 + 64 * u + lane;
       const uint32_t cd = codes[m][u];
       const uint32_t f = cd != 0xffffu ? map_info(cd) : 0u;
-      if (rr < RB && cd != 0xffffu && (cd & 0x8000u)) atomicAdd(&L.na, 1);  // owned slow owners
-      L.info[rr][col] = f;
+      if (kMode == kEmitAll && rr < RB && cd != 0xffffu && (cd & 0x8000u)) atomicAdd(&L.na, 1);  // owned slow owners
+      L.info[rr][col] = (uint16_t)(cd != 0xffffu ? cd : 0u);
       const int p = info_nv(f) | (info_nt(f) << 16);
       const int incl = wave_incl_scan_dpp(p);
       const int e = carry + incl - p;
-      L.voff[rr][col] = bv + (e & 0xffff);
+      L.voff[rr][col] = (int16_t)(e & 0xffff);
       if (rr < RB) L.toff[rr][col] = (int16_t)(e >> 16);
       carry += __builtin_amdgcn_readlane(incl, 63);
     }
     const uint32_t fe = edge[m] != 0xffffu ? map_info(edge[m]) : 0u;
-    if (lane < 2) L.info[rr][lane == 0 ? 0 : W - 1] = fe;
+    if (lane < 2) L.info[rr][lane == 0 ? 0 : W - 1] = (uint16_t)(edge[m] != 0xffffu ? edge[m] : 0u);
     const int nv_left = __builtin_amdgcn_readlane(info_nv(fe), 0);
     if (lane == 0) {
-      L.voff[rr][0] = bv - nv_left;
-      L.voff[rr][W - 1] = bv + (carry & 0xffff);
+      L.voff[rr][0] = (int16_t)(-nv_left);
+      L.voff[rr][W - 1] = (int16_t)(carry & 0xffff);
       L.rowv[rr] = carry & 0xffff;
     }
   }
   __syncthreads();
   auto neighbours = [&](int r, int col, uint32_t f, int o_) {
     Nb nb;
-    nb.vid = L.voff[r][col];
-    nb.id_vr = L.voff[r][col + 1];
-    nb.id_vdl = L.voff[r + 1][col + o_ - 1];
-    nb.id_vdr = L.voff[r + 1][col + o_];
+    const int bv0 = L.bv[r], bv1 = L.bv[r + 1];
+    nb.vid = bv0 + L.voff[r][col];
+    nb.id_vr = bv0 + L.voff[r][col + 1];
+    nb.id_vdl = bv1 + L.voff[r + 1][col + o_ - 1];
+    nb.id_vdr = bv1 + L.voff[r + 1][col + o_];
     nb.b0 = nb.vid + info_self(f);
     nb.b1 = nb.b0 + info_n(f, 0);
     nb.b2 = nb.b1 + info_n(f, 1);
-    const uint32_t fr = L.info[r][col + 1];
-    nb.b3 = L.voff[r][col + 1] + info_self(fr) + info_n(fr, 0);
-    const uint32_t fl = L.info[r + 1][col + o_ - 1];
-    nb.b4 = L.voff[r + 1][col + o_ - 1] + info_self(fl);
+    const uint32_t fr = map_info(L.info[r][col + 1]);
+    nb.b3 = nb.id_vr + info_self(fr) + info_n(fr, 0);
+    const uint32_t fl = map_info(L.info[r + 1][col + o_ - 1]);
+    nb.b4 = nb.id_vdl + info_self(fl);
     nb.bI = nb.b2 + info_n(f, 2);
     return nb;
   };
@@ -782,27 +802,48 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
   out.c = d.codes;
   out.vbase = 0;
   out.tbase = 0;
-  for (int r = 0; r < RB; ++r) {
+  for (int r = 0; r < RB && kMode != kEmitMissing; ++r) {
     const int k = k0 + r;
     if (k >= g.NK) break;
     const int o_ = k & 1;
     const int col = 1 + threadIdx.x;
     const int c = c0 + threadIdx.x;
+    // the row segment's outputs start at uniform addresses: 32-bit offsets
+    // from them (a row segment holds fewer than 2^16 of each)
+    const int bvr = __builtin_amdgcn_readfirstlane(L.bv[r]), bvn = __builtin_amdgcn_readfirstlane(L.bv[r + 1]);
+    const long long tbr = L.tb[r];
+    const int64_t tbs = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(tbr >> 32)) << 32) |
+                                  (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)tbr));
+    char* const vrow = reinterpret_cast<char*>(d.verts + 2 * (int64_t)bvr);
+    char* const trow = reinterpret_cast<char*>(d.tris + 3 * tbs);
+    uint8_t* const crow = d.codes + tbs;
     if (c >= g.NI) continue;
-    const uint32_t f = L.info[r][col];
+    const uint32_t f = map_info(L.info[r][col]);
     if (info_slow(f)) continue;
-    const int vid = L.voff[r][col];
-    if (info_self(f)) put_vertex(d.verts, vid, lat_x(g.X0 + 4 * g.h * c + 2 * g.h * o_), lat_y(g.h, k));
-    int64_t u = L.tb[r] + L.toff[r][col];
+    const int vl = L.voff[r][col];
+    const int vid = bvr + vl;
+    if (info_self(f)) {
+      double2 v;
+      v.x = lat_x(g.X0 + 4 * g.h * c + 2 * g.h * o_);
+      v.y = lat_y(g.h, k);
+      *reinterpret_cast<double2*>(vrow + (uint32_t)vl * 16u) = v;
+    }
+    uint32_t u = (uint32_t)(uint16_t)L.toff[r][col];
     const uint8_t code = both && !info_fg(f) ? 0x80 : 0;
+    Tri3 t3;
+    t3.a = vid;
     if (info_ntb(f)) {
-      put_tri(d.tris, u, vid, L.voff[r + 1][col + o_], L.voff[r + 1][col + o_ - 1]);
-      d.codes[u] = code;
+      t3.b = bvn + L.voff[r + 1][col + o_];
+      t3.c = bvn + L.voff[r + 1][col + o_ - 1];
+      *reinterpret_cast<Tri3*>(trow + u * 12u) = t3;
+      crow[u] = code;
       ++u;
     }
     if (info_nta(f)) {
-      put_tri(d.tris, u, vid, L.voff[r][col + 1], L.voff[r + 1][col + o_]);
-      d.codes[u] = code;
+      t3.b = bvr + L.voff[r][col + 1];
+      t3.c = bvn + L.voff[r + 1][col + o_];
+      *reinterpret_cast<Tri3*>(trow + u * 12u) = t3;
+      crow[u] = code;
     }
   }
   // 4. slow owners from their records, kSlowChunk records at a time: the
@@ -811,7 +852,7 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
   // the band below emits them).  Record q is held by thread q mod kThreads
   // in held[q / kThreads] while q < kHold * kThreads.
   constexpr int kChunk = EmitLds<RB>::kSlowChunk;
-  for (int ch = 0; ch * kChunk < nrec; ++ch) {
+  for (int ch = 0; kMode != kEmitMissing && ch * kChunk < nrec; ++ch) {
     const int qi = threadIdx.x & (kChunk - 1);
     const int q = ch * kChunk + qi;
     bool mine = false;
@@ -833,7 +874,7 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
       if (mine) cnt = info_nv(R.info) | (info_nt(R.info) << 16);
     }
     const unsigned long long bal = __ballot(mine);
-    if (lane == 0 && bal) atomicAdd(&L.ns, (int)__popcll(bal));
+    if (kMode == kEmitAll && lane == 0 && bal) atomicAdd(&L.ns, (int)__popcll(bal));
     const int incl = wave_incl_scan_dpp(cnt);
     if (lane == 63) L.swt[wv] = incl;
     __syncthreads();
@@ -852,7 +893,7 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
       const SlowRec R = L.srec[item & 255];
       const int r = (int)(R.x >> 56), col = (int)((R.x >> 48) & 255u) + 1;
       const Frame f = owner_place(g, k0 + r, c0 + col - 1, L.rowR[r]);
-      emit_slow_vertex(g, f, R, item >> 8, L.voff[r][col], out);
+      emit_slow_vertex(g, f, R, item >> 8, L.bv[r] + L.voff[r][col], out);
     }
     __syncthreads();
     for (int i = 0; i < (cnt >> 16); ++i) L.sitem[(excl >> 16) + i] = (uint16_t)(qi | (i << 8));
@@ -861,13 +902,13 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
       const int item = L.sitem[it];
       const SlowRec R = L.srec[item & 255];
       const int r = (int)(R.x >> 56), col = (int)((R.x >> 48) & 255u) + 1;
-      const Nb nb = neighbours(r, col, L.info[r][col], (k0 + r) & 1);
-      emit_slow_triangle(g, R, item >> 8, nb, L.tb[r] + L.toff[r][col], out);
+      const Nb nb = neighbours(r, col, map_info(L.info[r][col]), (k0 + r) & 1);
+      emit_slow_triangle(g, R, item >> 8, nb, L.tb[r] + L.toff[r][col], out, L.lut);
     }
     __syncthreads();
   }
   __syncthreads();
-  if (L.na > L.ns) {
+  if (kMode == kEmitMissing || (kMode == kEmitAll && L.na > L.ns)) {
     // slow owners beyond the tile's record region were classified by the
     // count pass without a record: mark the recorded ones, classify the rest
     for (int t = threadIdx.x; t < RB * kCB / 32; t += kThreads) L.hasrec[t] = 0u;
@@ -881,23 +922,24 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
     __syncthreads();
     for (int e = threadIdx.x; e < RB * kCB; e += kThreads) {
       const int r = e / kCB, col = e - r * kCB + 1;
-      if (!info_slow(L.info[r][col]) || ((L.hasrec[e >> 5] >> (e & 31)) & 1u)) continue;
+      if (!info_slow(map_info(L.info[r][col])) || ((L.hasrec[e >> 5] >> (e & 31)) & 1u)) continue;
       const int k = k0 + r, c = c0 + col - 1;
       const Frame fr = owner_frame(g, bw, k, c, L.rowR[r]);
       Slow sr;
       slow_classify(g, fr, sr);
-      const Nb nb = neighbours(r, col, L.info[r][col], k & 1);
-      emit_slow(g, fr, pack_slow(sr), nb, L.tb[r] + L.toff[r][col], out);
+      const Nb nb = neighbours(r, col, map_info(L.info[r][col]), k & 1);
+      emit_slow(g, fr, pack_slow(sr), nb, L.tb[r] + L.toff[r][col], out, L.lut);
     }
   }
 }
 
-template <class Src, int RB>
-// At most 102 VGPRs: five workgroups per compute unit.
-__global__ void __launch_bounds__(kThreads, 5) k_emit(Src src, const int64_t* __restrict__ tab, Shared sh) {
-  __shared__ EmitLds<RB> L;
+// One count tile of the multi-kernel path: its image, the bases of its row
+// segments, then emit_tile.
+template <class Src, int RB, int kMode>
+__device__ __forceinline__ void emit_count_tile(const Src& src, const int64_t* __restrict__ tab, const Shared& sh,
+                                                int64_t tile, EmitLds<RB>& L) {
   int64_t local;
-  const int ii = src.find(blockIdx.x, tab, local);
+  const int ii = src.find(tile, tab, local);
   const Img& d = src.img(ii);
   const Geo g = d.g;
   long long nv, nt, nc;
@@ -906,13 +948,43 @@ __global__ void __launch_bounds__(kThreads, 5) k_emit(Src src, const int64_t* __
   const int cb = (int)(local % g.NCB), ky = (int)(local / g.NCB);
   const int64_t nsegi = (int64_t)g.NK * g.NCB;
   const longlong4 base = sh.seg_off[d.seg0];
-  if (threadIdx.x <= RB) {
-    const int k = ky * RB + threadIdx.x;
-    const longlong4 o = sh.seg_off[d.seg0 + (k < g.NK ? (int64_t)k * g.NCB + cb : nsegi)];
-    L.bv[threadIdx.x] = (int)(o.x - base.x);
-    if (threadIdx.x < RB) L.tb[threadIdx.x] = o.y - base.y;
+  emit_tile<RB, kMode>(d, g, ky * RB, cb, tile, sh, L, nullptr, [&](EmitLds<RB>& E) {
+    if (threadIdx.x <= RB) {
+      const int k = ky * RB + threadIdx.x;
+      const longlong4 o = sh.seg_off[d.seg0 + (k < g.NK ? (int64_t)k * g.NCB + cb : nsegi)];
+      E.bv[threadIdx.x] = (int)(o.x - base.x);
+      if (threadIdx.x < RB) E.tb[threadIdx.x] = o.y - base.y;
+    }
+  });
+}
+
+template <class Src, int RB>
+// At most 64 VGPRs: eight workgroups per compute unit.
+__global__ void __launch_bounds__(kThreads, 8) k_emit(Src src, const int64_t* __restrict__ tab, Shared sh) {
+  __shared__ EmitLds<RB> L;
+  emit_count_tile<Src, RB, kEmitRecords>(src, tab, sh, (int64_t)blockIdx.x, L);
+}
+
+// Slow owners without a record: the tiles whose count pass queued more slow
+// owners than their record region holds, found among kThreads tiles per
+// block and emitted one after the other (rare: the region is sized for the
+// usual share of slow owners).
+template <class Src, int RB>
+__global__ void __launch_bounds__(kThreads) k_emit_missing(Src src, const int64_t* __restrict__ tab, Shared sh,
+                                                           int64_t ntile) {
+  __shared__ EmitLds<RB> L;
+  __shared__ unsigned long long over[kThreads / 64];
+  const int64_t t0 = (int64_t)blockIdx.x * kThreads;
+  const int64_t t = t0 + threadIdx.x;
+  const unsigned long long b = __ballot(t < ntile && sh.tile_n[t] > sh.tcap);
+  if ((threadIdx.x & 63) == 0) over[threadIdx.x >> 6] = b;
+  __syncthreads();
+  for (int w = 0; w < kThreads / 64; ++w) {
+    for (unsigned long long m = over[w]; m; m &= m - 1) {  // the same value in every lane
+      emit_count_tile<Src, RB, kEmitMissing>(src, tab, sh, t0 + 64 * w + __builtin_ctzll(m), L);
+      __syncthreads();
+    }
   }
-  emit_tile<RB>(d, g, ky * RB, cb, (int64_t)blockIdx.x, sh, L, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1085,7 +1157,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_fused(ManySrc src, const int64_
         E.tb[threadIdx.x] = F.cnt[cb][threadIdx.x].y;
       }
       if (threadIdx.x == RB) E.bv[RB] = hv;
-      emit_tile<RB>(d, g, k0, cb, tile0 + cb, sh, E, hcode);
+      emit_tile<RB>(d, g, k0, cb, tile0 + cb, sh, E, hcode, [](EmitLds<RB>&) {});
       __syncthreads();
       hv += E.rowv[RB];
     }
@@ -1368,10 +1440,20 @@ static sbmt_status launch_emit(const CallLayout& L, const Src& src, const int64_
   const int64_t* tt = dtab ? dtab + (size_t)(1 + rbi) * (L.n + 1) : nullptr;
   const int64_t ntile = L.tab[(size_t)(1 + rbi) * (L.n + 1) + L.n];
   if (ntile > 0x7fffffffLL) return SBMT_E_INVALID_ARG;
+  const dim3 gm((unsigned)((ntile + kThreads - 1) / kThreads));
   switch (kRBs[rbi]) {
-    case 4: hipLaunchKernelGGL((k_emit<Src, 4>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh); break;
-    case 8: hipLaunchKernelGGL((k_emit<Src, 8>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh); break;
-    default: hipLaunchKernelGGL((k_emit<Src, 16>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh); break;
+    case 4:
+      hipLaunchKernelGGL((k_emit<Src, 4>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh);
+      hipLaunchKernelGGL((k_emit_missing<Src, 4>), gm, dim3(kThreads), 0, st, src, tt, sh, ntile);
+      break;
+    case 8:
+      hipLaunchKernelGGL((k_emit<Src, 8>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh);
+      hipLaunchKernelGGL((k_emit_missing<Src, 8>), gm, dim3(kThreads), 0, st, src, tt, sh, ntile);
+      break;
+    default:
+      hipLaunchKernelGGL((k_emit<Src, 16>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh);
+      hipLaunchKernelGGL((k_emit_missing<Src, 16>), gm, dim3(kThreads), 0, st, src, tt, sh, ntile);
+      break;
   }
   return hipGetLastError() == hipSuccess ? SBMT_OK : SBMT_E_DEVICE;
 }

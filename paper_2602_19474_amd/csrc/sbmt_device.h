@@ -278,8 +278,6 @@ SBMT_HD int lut_key(int code);
 SBMT_HD int lut_nfg(int cls);
 SBMT_HD int lut_ntri(int cls);
 SBMT_HD uint32_t lut_tri(int cls, int j);
-SBMT_HD uint32_t lut_emit(int cls, int rot, int t, int j);
-SBMT_HD uint32_t lut_emit_fg(int cls, int rot, int t, int j);
 
 // Raw key of triangle t from the crossing sets, looked up into class | rot << 6.
 // Returns 0 for an uncut triangle, -1 on a protocol violation.  The candidate
@@ -751,9 +749,12 @@ SBMT_HD void emit_slow_vertex(const Geo& g, const Frame& f, const SlowRec& r, in
 
 // Triangle `sub` of a slow owner, in the owner's triangle order (those of Tb,
 // then of Ta; a cut triangle's emitted sub-triangles in table order), written
-// to triangle to + sub.
+// to triangle to + sub.  `lut` is the emission table [class][rot][t][j] of the
+// side mode: every entry with both sides, else the foreground ones (the
+// kernels keep a copy in LDS, so that no table load waits behind the stores
+// already issued).
 SBMT_HD void emit_slow_triangle(const Geo& g, const SlowRec& r, int sub, const Nb& nb, int64_t to,
-                                const Out& out) {
+                                const Out& out, const uint16_t* lut) {
   const bool both = (g.flags & 1u) != 0;
   const uint32_t info = r.info;
   const int ntb = info_ntb(info);
@@ -770,9 +771,8 @@ SBMT_HD void emit_slow_triangle(const Geo& g, const SlowRec& r, int sub, const N
   const int hasIb = ((r.tri >> 16) & 15u) != 15u;
   const int ids[16] = {nb.vid, nb.b0, nb.b0 + 1, nb.b1, nb.b1 + 1, nb.b2, nb.b2 + 1, nb.bI, nb.bI + hasIb,
                        nb.id_vr, nb.b3, nb.b3 + 1, nb.id_vdl, nb.b4, nb.b4 + 1, nb.id_vdr};
-  // the j-th emitted entry of the template: every entry with both sides,
-  // else the j-th foreground one
-  const uint32_t w = both ? lut_emit(cls, rot, t, j) : lut_emit_fg(cls, rot, t, j);
+  // the j-th emitted entry of the template
+  const uint32_t w = lut[((cls * 3 + rot) * 2 + t) * 5 + j];
   const int side = (int)((w >> 12) & 1u);
   put_tri(out.t, u, slot_id(ids, (int)(w & 15u)), slot_id(ids, (int)((w >> 4) & 15u)),
           slot_id(ids, (int)((w >> 8) & 15u)));
@@ -780,10 +780,11 @@ SBMT_HD void emit_slow_triangle(const Geo& g, const SlowRec& r, int sub, const N
 }
 
 // Emit one slow owner from its record (one thread for all its outputs).
-SBMT_HD void emit_slow(const Geo& g, const Frame& f, const SlowRec& r, const Nb& nb, int64_t to, const Out& out) {
+SBMT_HD void emit_slow(const Geo& g, const Frame& f, const SlowRec& r, const Nb& nb, int64_t to, const Out& out,
+                       const uint16_t* lut) {
   const int nv = info_nv(r.info), nt = info_nt(r.info);
   for (int s = 0; s < nv; ++s) emit_slow_vertex(g, f, r, s, nb.vid, out);
-  for (int s = 0; s < nt; ++s) emit_slow_triangle(g, r, s, nb, to, out);
+  for (int s = 0; s < nt; ++s) emit_slow_triangle(g, r, s, nb, to, out, lut);
 }
 
 }  // namespace sbmt

@@ -309,8 +309,11 @@ struct CountLds {
 
 // Rows k0 .. k0+RB-1 of column block cb.  With hdst, the codes of the last
 // row go to hdst[c] instead of the owner map (the persistent kernel counts
-// the first row of the next band that way without writing it).
-template <int RB>
+// the first row of the next band that way without writing it).  Slow owners
+// beyond the record region are classified here with kOverflowHere, else left
+// with the queued mark (0x8000) for k_slow, which keeps this kernel free of
+// the classification's registers.
+template <int RB, bool kOverflowHere = true>
 __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, int64_t tile, int k0, int cb,
                                            const Shared& sh, CountLds<RB>& L, int4* acc_out,
                                            uint16_t* __restrict__ hdst) {
@@ -401,7 +404,7 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
     const int k = k0 + r;
     if (q < sh.tcap) {
       sh.rec[tile * sh.tcap + q].x = (uint64_t)c | ((uint64_t)k << 24) | ((uint64_t)ii << 48);
-    } else {
+    } else if (kOverflowHere) {
       const Frame f = owner_frame(g, bw, k, c, L.rowR[r]);
       Slow sr;
       slow_classify(g, f, sr);
@@ -444,7 +447,7 @@ __global__ void __launch_bounds__(kThreads) k_count(Src src, const int64_t* __re
   const Img& d = src.img(ii);
   const Geo g = d.g;
   const int cb = (int)(local % g.NCB), ky = (int)(local / g.NCB);
-  count_tile<RB>(d, g, ii, (int64_t)blockIdx.x, ky * RB, cb, sh, L, out, nullptr);
+  count_tile<RB, false>(d, g, ii, (int64_t)blockIdx.x, ky * RB, cb, sh, L, out, nullptr);
   __syncthreads();
   const int k = ky * RB + (int)threadIdx.x;
   if (threadIdx.x < RB && k < g.NK) sh.seg_cnt[d.seg0 + (int64_t)k * g.NCB + cb] = out[threadIdx.x];
@@ -458,6 +461,7 @@ __global__ void __launch_bounds__(kThreads) k_count(Src src, const int64_t* __re
 template <class Src, int RB>
 __global__ void __launch_bounds__(64) k_slow(Src src, const int64_t* __restrict__ tab, Shared sh) {
   __shared__ unsigned long long acc[RB];
+  __shared__ uint32_t hasrec[RB * kCB / 32];
   int64_t local;
   const int ii = src.find(blockIdx.x, tab, local);
   const Img& d = src.img(ii);
@@ -465,8 +469,12 @@ __global__ void __launch_bounds__(64) k_slow(Src src, const int64_t* __restrict_
   const int cb = (int)(local % g.NCB), ky = (int)(local / g.NCB);
   const int64_t tile = blockIdx.x;
   if (threadIdx.x < RB) acc[threadIdx.x] = 0ull;
+  const int64_t nq = sh.tile_n[tile];
+  const bool over = nq > sh.tcap;  // uniform
+  if (over)
+    for (int t = threadIdx.x; t < RB * kCB / 32; t += 64) hasrec[t] = 0u;
   __syncthreads();
-  const int n = (int)min((int64_t)sh.tile_n[tile], sh.tcap);
+  const int n = (int)min(nq, sh.tcap);
   Bits b;
   b.p = d.bits;
   b.wpr = g.wpr;
@@ -486,8 +494,28 @@ __global__ void __launch_bounds__(64) k_slow(Src src, const int64_t* __restrict_
     d.omap[(int64_t)k * g.NI + c] = (uint16_t)map_code(sr.info);
     atomicAdd(&acc[k - ky * RB], pack_counts(sr.info));
     if (info_err(sr.info)) atomicOr(&sh.imgerr[ii], 1);
+    if (over) {
+      const int e = (k - ky * RB) * kCB + (c - cb * kCB);
+      atomicOr(&hasrec[e >> 5], 1u << (e & 31));
+    }
   }
   __syncthreads();
+  if (over) {
+    // the queued slow owners beyond the record region (still marked 0x8000
+    // by the count pass): classified here without a record
+    for (int e = threadIdx.x; e < RB * kCB; e += 64) {
+      const int r = e / kCB, k = ky * RB + r, c = cb * kCB + (e - r * kCB);
+      if (k >= g.NK || c >= g.NI || ((hasrec[e >> 5] >> (e & 31)) & 1u)) continue;
+      if (d.omap[(int64_t)k * g.NI + c] != 0x8000u) continue;
+      const Frame f = owner_frame(g, b, k, c, row_cell(k, g.h, g.s));
+      Slow sr;
+      slow_classify(g, f, sr);
+      d.omap[(int64_t)k * g.NI + c] = (uint16_t)map_code(sr.info);
+      atomicAdd(&acc[r], pack_counts(sr.info));
+      if (info_err(sr.info)) atomicOr(&sh.imgerr[ii], 1);
+    }
+    __syncthreads();
+  }
   const int k = ky * RB + (int)threadIdx.x;
   if (threadIdx.x < RB && k < g.NK) sh.seg_slow[d.seg0 + (int64_t)k * g.NCB + cb] = acc[threadIdx.x];
 }

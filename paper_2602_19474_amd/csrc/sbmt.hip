@@ -462,13 +462,17 @@ template <class Src, int RB>
 __global__ void __launch_bounds__(64) k_slow(Src src, const int64_t* __restrict__ tab, Shared sh) {
   __shared__ unsigned long long acc[RB];
   __shared__ uint32_t hasrec[RB * kCB / 32];
+  __shared__ int rowR[RB];
   int64_t local;
   const int ii = src.find(blockIdx.x, tab, local);
   const Img& d = src.img(ii);
   const Geo g = d.g;
   const int cb = (int)(local % g.NCB), ky = (int)(local / g.NCB);
   const int64_t tile = blockIdx.x;
-  if (threadIdx.x < RB) acc[threadIdx.x] = 0ull;
+  if (threadIdx.x < RB) {
+    acc[threadIdx.x] = 0ull;
+    rowR[threadIdx.x] = row_cell(ky * RB + threadIdx.x, g.h, g.s);
+  }
   const int64_t nq = sh.tile_n[tile];
   const bool over = nq > sh.tcap;  // uniform
   if (over)
@@ -484,7 +488,7 @@ __global__ void __launch_bounds__(64) k_slow(Src src, const int64_t* __restrict_
     const int64_t idx = tile * sh.tcap + q;
     const uint64_t p = sh.rec[idx].x;
     const int k = (int)((p >> 24) & 0xffffffu), c = (int)(p & 0xffffffu);
-    const Frame f = owner_frame(g, b, k, c, row_cell(k, g.h, g.s));
+    const Frame f = owner_frame(g, b, k, c, rowR[k - ky * RB]);
     Slow sr;
     slow_classify(g, f, sr);
     SlowRec R = pack_slow(sr);
@@ -507,7 +511,7 @@ __global__ void __launch_bounds__(64) k_slow(Src src, const int64_t* __restrict_
       const int r = e / kCB, k = ky * RB + r, c = cb * kCB + (e - r * kCB);
       if (k >= g.NK || c >= g.NI || ((hasrec[e >> 5] >> (e & 31)) & 1u)) continue;
       if (d.omap[(int64_t)k * g.NI + c] != 0x8000u) continue;
-      const Frame f = owner_frame(g, b, k, c, row_cell(k, g.h, g.s));
+      const Frame f = owner_frame(g, b, k, c, rowR[r]);
       Slow sr;
       slow_classify(g, f, sr);
       d.omap[(int64_t)k * g.NI + c] = (uint16_t)map_code(sr.info);

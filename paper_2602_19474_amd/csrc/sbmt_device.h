@@ -244,8 +244,13 @@ constexpr uint64_t kMidXI = 0x420420313131ull;  // nibble m: 1,3,1,3,1,3, 0,2,4,
 constexpr uint64_t kMidYI = 0x333111442200ull;  // nibble m: 0,0,2,2,4,4, 1,1,1, 3,3,3
 SBMT_HD int mid_xi(int m) { return (int)((kMidXI >> (4 * m)) & 15u); }
 SBMT_HD int mid_yi(int m) { return (int)((kMidYI >> (4 * m)) & 15u); }
-SBMT_HD int mid_x(const Geo& g, const Frame& f, int m) { return 4 * g.s * f.Clo + 2 * (g.s - 1) + 2 * g.s * mid_xi(m); }
-SBMT_HD int mid_y(const Geo& g, const Frame& f, int m) { return 4 * g.s * f.Rlo + 2 * (g.s - 1) + 2 * g.s * mid_yi(m); }
+// (both factors of the last product fit in 24 bits: a full-rate multiply)
+SBMT_HD int mid_x(const Geo& g, const Frame& f, int m) {
+  return 4 * g.s * f.Clo + 2 * (g.s - 1) + (int)((uint32_t)(2 * g.s & 0xffff) * (uint32_t)mid_xi(m));
+}
+SBMT_HD int mid_y(const Geo& g, const Frame& f, int m) {
+  return 4 * g.s * f.Rlo + 2 * (g.s - 1) + (int)((uint32_t)(2 * g.s & 0xffff) * (uint32_t)mid_yi(m));
+}
 SBMT_HD int slot_p(uint64_t seg, int a) { return (int)((seg >> (8 * a)) & 15); }
 SBMT_HD int slot_q(uint64_t seg, int a) { return (int)((seg >> (8 * a + 4)) & 15); }
 
@@ -259,19 +264,9 @@ SBMT_HD int tri_edge(int t, int j) {
 }
 SBMT_HD int tri_dir(int t, int j) { return t == 0 ? (j == 0 ? 1 : -1) : (j == 2 ? -1 : 1); }
 
-SBMT_HD int popc8(uint32_t m) {
-  m = m - ((m >> 1) & 0x55u);
-  m = (m & 0x33u) + ((m >> 2) & 0x33u);
-  return (int)((m + (m >> 4)) & 0x0fu);
-}
+SBMT_HD int popc8(uint32_t m) { return __builtin_popcount(m & 255u); }
 SBMT_HD int ctz32(uint32_t m) { return __builtin_ctz(m); }
-SBMT_HD int ctz8(uint32_t m) {
-  int n = 0;
-  if (!(m & 0x0fu)) { n += 4; m >>= 4; }
-  if (!(m & 0x03u)) { n += 2; m >>= 2; }
-  if (!(m & 0x01u)) { n += 1; }
-  return n;
-}
+SBMT_HD int ctz8(uint32_t m) { return __builtin_ctz(m | 256u); }  // lowest set bit of m != 0 (8 for 0)
 
 // Class lookup (generated tables), provided by the including translation unit.
 SBMT_HD int lut_key(int code);
@@ -545,8 +540,8 @@ SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
         else err = true;
         const int M = slot_q(seg, s1), P0 = slot_p(seg, s1), P2 = slot_q(seg, s2);
         const int mx = mid_x(g, f, M), my = mid_y(g, f, M);
-        const int64_t cr = (int64_t)(mid_x(g, f, P0) - mx) * (mid_y(g, f, P2) - my) -
-                           (int64_t)(mid_y(g, f, P0) - my) * (mid_x(g, f, P2) - mx);
+        // offsets inside one block of 2 x 2 cells: |d| <= 8 s, products fit in 32 bits
+        const int cr = (mid_x(g, f, P0) - mx) * (mid_y(g, f, P2) - my) - (mid_y(g, f, P0) - my) * (mid_x(g, f, P2) - mx);
         const bool mpos = (sq >> (8 * s1 + e)) & 1u;
         const bool later = (cr > 0) == mpos;
         first = later ? s1 : s2;

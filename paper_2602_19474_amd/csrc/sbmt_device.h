@@ -229,10 +229,16 @@ SBMT_HD int window_kind(const Geo& g, const Bits& b, const uint32_t* u0, const u
 //   m = 6 + 3r + c   (r < 2, c < 3) between samples (r, c) and (r+1, c)
 // Segment slot a = 2q + j holds segment j of dual cell q = 2 cr + cc.
 // ---------------------------------------------------------------------------
+// Segment slots of a block: nibble a of p (q) is the start (end) midpoint of
+// slot a.
+struct SegSlots {
+  uint32_t p, q;
+};
+
 struct Slow {
   uint32_t info;
   uint32_t valid;  // segment slots present
-  uint64_t seg;    // slot a: start midpoint bits [8a, 8a+4), end midpoint [8a+4, 8a+8)
+  SegSlots seg;    // start and end midpoints of the segment slots
   uint64_t xm;     // edge e: crossing slot mask at bits [8e, 8e+8)
   uint64_t ord;    // edge e: first slot along U->V at [8e, 8e+4), second at [8e+4, 8e+8)
   uint32_t tri;    // t = 0 (Tb), 1 (Ta): class [8t, 8t+5), rotation [8t+5, 8t+7); chain vertex
@@ -251,8 +257,18 @@ SBMT_HD int mid_x(const Geo& g, const Frame& f, int m) {
 SBMT_HD int mid_y(const Geo& g, const Frame& f, int m) {
   return 4 * g.s * f.Rlo + 2 * (g.s - 1) + (int)((uint32_t)(2 * g.s & 0xffff) * (uint32_t)mid_yi(m));
 }
+SBMT_HD int slot_p(const SegSlots& seg, int a) { return (int)((seg.p >> (4 * a)) & 15u); }
+SBMT_HD int slot_q(const SegSlots& seg, int a) { return (int)((seg.q >> (4 * a)) & 15u); }
+// The same slots packed one byte each (start | end << 4): the count pass's form.
 SBMT_HD int slot_p(uint64_t seg, int a) { return (int)((seg >> (8 * a)) & 15); }
 SBMT_HD int slot_q(uint64_t seg, int a) { return (int)((seg >> (8 * a + 4)) & 15); }
+SBMT_HD void slot_set(SegSlots& seg, int a, uint32_t pa, uint32_t pb) {
+  seg.p |= pa << (4 * a);
+  seg.q |= pb << (4 * a);
+}
+SBMT_HD void slot_set(uint64_t& seg, int a, uint32_t pa, uint32_t pb) { seg |= (uint64_t)(pa | (pb << 4)) << (8 * a); }
+SBMT_HD void slot_clear(SegSlots& seg) { seg.p = seg.q = 0u; }
+SBMT_HD void slot_clear(uint64_t& seg) { seg = 0u; }
 
 // lattice vertex index of the ends of edge e (0 v, 1 vr, 2 vdl, 3 vdr)
 SBMT_HD int edge_u(int e) { return e == 3 ? 1 : (e == 4 ? 2 : 0); }
@@ -277,7 +293,7 @@ SBMT_HD uint32_t lut_tri(int cls, int j);
 // Raw key of triangle t from the crossing sets, looked up into class | rot << 6.
 // Returns 0 for an uncut triangle, -1 on a protocol violation.  The candidate
 // token orders of all three key types are formed straight-line and selected.
-SBMT_HD int tri_key(int t, const uint32_t pos[5], uint64_t seg, uint64_t xm, uint64_t ord, int Imid) {
+SBMT_HD int tri_key(int t, uint64_t sp, const SegSlots& seg, uint64_t xm, uint64_t ord, int Imid) {
   uint32_t list = 0;  // per crossing (8 bits): slot | token << 3 | entry << 7
   int nc = 0;
 #pragma unroll
@@ -289,7 +305,7 @@ SBMT_HD int tri_key(int t, const uint32_t pos[5], uint64_t seg, uint64_t xm, uin
     for (int re = 0; re < 2; ++re) {
       const int sl = (int)((ord >> (8 * eid + 4 * re)) & 15);
       const int rt = dir > 0 ? re : n - 1 - re;
-      const int spos = (int)((pos[eid] >> slot_p(seg, sl)) & 1u);
+      const int spos = (int)((sp >> (8 * sl + eid)) & 1u);  // start point on the positive side
       const int entry = dir > 0 ? !spos : spos;
       const uint32_t item = (uint32_t)(sl | ((2 * j + rt) << 3) | (entry << 7));
       const bool take = re < n && nc < 4;
@@ -341,9 +357,10 @@ SBMT_HD int tri_key(int t, const uint32_t pos[5], uint64_t seg, uint64_t xm, uin
 }
 
 // Segments of the four dual cells of the block as slots (see Slow::seg).
-SBMT_HD void block_segments(const Frame& f, uint64_t& seg, uint32_t& valid) {
+template <class S>
+SBMT_HD void block_segments(const Frame& f, S& seg, uint32_t& valid) {
 #define SBMT_S(rr, cc) ((int)((f.s9 >> (3 * (rr) + (cc))) & 1u))
-  seg = 0;
+  slot_clear(seg);
   valid = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -358,7 +375,7 @@ SBMT_HD void block_segments(const Frame& f, uint64_t& seg, uint32_t& valid) {
       if (j < (int)(ms & 3u)) {
         const uint32_t a = (ms >> (2 + 4 * j)) & 3u, b = (ms >> (4 + 4 * j)) & 3u;
         const uint32_t pa = (lm >> (4 * a)) & 15u, pb = (lm >> (4 * b)) & 15u;
-        seg |= (uint64_t)(pa | (pb << 4)) << (8 * (2 * q + j));
+        slot_set(seg, 2 * q + j, pa, pb);
         valid |= 1u << (2 * q + j);
       }
     }
@@ -368,7 +385,8 @@ SBMT_HD void block_segments(const Frame& f, uint64_t& seg, uint32_t& valid) {
 
 // Slots whose bounding box meets the bounding box of Tb u Ta (conservative in
 // y); only they can cross an owned edge or hold a chain vertex of Tb, Ta.
-SBMT_HD uint32_t relevant_slots(const Geo& g, const Frame& f, uint64_t seg, uint32_t valid) {
+template <class S>
+SBMT_HD uint32_t relevant_slots(const Geo& g, const Frame& f, const S& seg, uint32_t valid) {
   const int xlo = f.X - 2 * g.h, xhi = f.X + 4 * g.h;
   const double yk = -4.0 + (double)(2 * (int64_t)g.h * f.k) * kSqrt3;
   const int ylo = (int)__builtin_floor(yk) - 1;
@@ -387,7 +405,8 @@ SBMT_HD uint32_t relevant_slots(const Geo& g, const Frame& f, uint64_t seg, uint
 
 // Inside bit of the owner vertex: its dual cell (0, cv) of the block is
 // uniform, or v lies left of every segment of that cell.
-SBMT_HD int owner_inside(const Geo& g, const Frame& f, uint64_t seg, uint32_t valid) {
+template <class S>
+SBMT_HD int owner_inside(const Geo& g, const Frame& f, const S& seg, uint32_t valid) {
   const int X = f.X;
   const int cv = div4s(g, X - 2 * (g.s - 1)) - f.Clo;
   const int a = (int)((f.s9 >> cv) & 1u), b = (int)((f.s9 >> (cv + 1)) & 1u);
@@ -429,7 +448,7 @@ SBMT_HD int sgn_eval(double v, int64_t a, int64_t b, bool& ok) {
 }
 
 template <bool EXACT>
-SBMT_HD bool slot_signs(const Geo& g, const Frame& f, uint64_t seg, uint32_t rel, uint32_t& row0, uint32_t& row4,
+SBMT_HD bool slot_signs(const Geo& g, const Frame& f, const SegSlots& seg, uint32_t rel, uint32_t& row0, uint32_t& row4,
                         uint64_t& sp, uint64_t& sq, uint32_t& lv) {
   bool ok = true;
   const int h = g.h, X = f.X;
@@ -489,7 +508,7 @@ SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
   const bool both = (g.flags & 1u) != 0;
   const int h = g.h, X = f.X;
   const int64_t hk = (int64_t)h * f.k;
-  uint64_t seg;
+  SegSlots seg;
   uint32_t valid;
   block_segments(f, seg, valid);
   const uint32_t rel = relevant_slots(g, f, seg, valid);
@@ -563,18 +582,8 @@ SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
     }
   }
   const int fg = owner_inside(g, f, seg, valid);
-  // pos masks per edge over midpoints, for the keys (entry tests use the start point)
-  uint32_t pos[5] = {0u, 0u, 0u, 0u, 0u};
-  for (uint32_t w = rel; w; w &= w - 1) {
-    const int a = ctz32(w);
-    {
-      const int pm = slot_p(seg, a);
-#pragma unroll
-      for (int e = 0; e < 5; ++e) pos[e] |= (uint32_t)((sp >> (8 * a + e)) & 1u) << pm;
-    }
-  }
-  const int kb = tri_key(0, pos, seg, xm, ord, Ib);
-  const int ka = tri_key(1, pos, seg, xm, ord, Ia);
+  const int kb = tri_key(0, sp, seg, xm, ord, Ib);
+  const int ka = tri_key(1, sp, seg, xm, ord, Ia);
   if (kb < 0 || ka < 0) err = true;
   const int clsb = kb > 0 ? (kb & 63) : 0, clsa = ka > 0 ? (ka & 63) : 0;
   const int rotb = kb > 0 ? (kb >> 6) : 0, rota = ka > 0 ? (ka >> 6) : 0;

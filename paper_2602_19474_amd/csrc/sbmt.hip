@@ -704,6 +704,7 @@ struct EmitLds {
   alignas(16) SlowRec srec[kSlowChunk];
   uint16_t sitem[kSlowChunk * kSlowItems];  // record | output number << 8
   uint16_t lut[15 * 3 * 2 * 5];              // emission table of the side mode
+  uint8_t tslot[kThreads / 64][128];         // per wave: fast triangle rank -> lane << 1 | which
   int swt[kThreads / 64];
 };
 
@@ -825,8 +826,10 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
     nb.bI = nb.b2 + info_n(f, 2);
     return nb;
   };
-  // 3. fast and quiet owners one per thread (their writes coalesce), then the
-  // slow owners of the tile from their records.
+  // 3. fast and quiet owners: each thread writes the vertex of its owner; the
+  // wave's triangles are written in output order, lane j the j-th (so that a
+  // store covers consecutive triangles); then the slow owners of the tile
+  // from their records.
   const bool both = (g.flags & 1u) != 0;
   Out out;
   out.v = d.verts;
@@ -849,34 +852,45 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
     char* const vrow = reinterpret_cast<char*>(d.verts + 2 * (int64_t)bvr);
     char* const trow = reinterpret_cast<char*>(d.tris + 3 * tbs);
     uint8_t* const crow = d.codes + tbs;
-    if (c >= g.NI) continue;
-    const uint32_t f = map_info(L.info[r][col]);
-    if (info_slow(f)) continue;
-    const int vl = L.voff[r][col];
-    const int vid = bvr + vl;
-    if (info_self(f)) {
+    const uint32_t f = c < g.NI ? map_info(L.info[r][col]) : 0u;
+    const bool fast = c < g.NI && !info_slow(f);
+    if (fast && info_self(f)) {
       double2 v;
       v.x = lat_x(g.X0 + 4 * g.h * c + 2 * g.h * o_);
       v.y = lat_y(g.h, k);
-      *reinterpret_cast<double2*>(vrow + (uint32_t)vl * 16u) = v;
+      *reinterpret_cast<double2*>(vrow + (uint32_t)L.voff[r][col] * 16u) = v;
     }
-    uint32_t u = (uint32_t)(uint16_t)L.toff[r][col];
-    const uint8_t code = both && !info_fg(f) ? 0x80 : 0;
-    Tri3 t3;
-    t3.a = vid;
-    if (info_ntb(f)) {
-      t3.b = bvn + L.voff[r + 1][col + o_];
-      t3.c = bvn + L.voff[r + 1][col + o_ - 1];
+    // ranks of the wave's fast triangles (at most two per owner)
+    const int ntb = fast ? info_ntb(f) : 0, nf = ntb + (fast ? info_nta(f) : 0);
+    const int incl = wave_incl_scan_dpp(nf);
+    const int tot = __builtin_amdgcn_readlane(incl, 63), ex = incl - nf;
+    uint8_t* const slot = L.tslot[wv];
+    if (ntb) slot[ex] = (uint8_t)(lane << 1);
+    if (nf > ntb) slot[ex + ntb] = (uint8_t)((lane << 1) | 1);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int j = lane; j < tot; j += 64) {
+      const int e = slot[j];
+      const int ocol = 64 * wv + 1 + (e >> 1);
+      const uint32_t of = map_info(L.info[r][ocol]);
+      const uint32_t u = (uint32_t)(uint16_t)L.toff[r][ocol] + ((e & 1) ? (uint32_t)info_ntb(of) : 0u);
+      Tri3 t3;
+      t3.a = bvr + L.voff[r][ocol];
+      if (e & 1) {
+        t3.b = bvr + L.voff[r][ocol + 1];
+        t3.c = bvn + L.voff[r + 1][ocol + o_];
+      } else {
+        t3.b = bvn + L.voff[r + 1][ocol + o_];
+        t3.c = bvn + L.voff[r + 1][ocol + o_ - 1];
+      }
       *reinterpret_cast<Tri3*>(trow + u * 12u) = t3;
-      crow[u] = code;
-      ++u;
+      crow[u] = both && !info_fg(of) ? 0x80 : 0;
     }
-    if (info_nta(f)) {
-      t3.b = bvr + L.voff[r][col + 1];
-      t3.c = bvn + L.voff[r + 1][col + o_];
-      *reinterpret_cast<Tri3*>(trow + u * 12u) = t3;
-      crow[u] = code;
-    }
+    // the next row's ranks reuse the slots
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   // 4. slow owners from their records, kSlowChunk records at a time: the
   // records and the lists of their output vertices and triangles go to LDS,

@@ -870,22 +870,33 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int j = lane; j < tot; j += 64) {
-      const int e = slot[j];
+    // at most two triangles per lane (ranks lane and lane + 64), their LDS
+    // reads issued together and both kinds of triangle selected, not branched
+    int e2[2];
+    bool h2[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      h2[q] = lane + 64 * q < tot;
+      e2[q] = h2[q] ? slot[lane + 64 * q] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = e2[q];
       const int ocol = 64 * wv + 1 + (e >> 1);
       const uint32_t of = map_info(L.info[r][ocol]);
-      const uint32_t u = (uint32_t)(uint16_t)L.toff[r][ocol] + ((e & 1) ? (uint32_t)info_ntb(of) : 0u);
+      const int tof = L.toff[r][ocol];
+      const int va = L.voff[r][ocol], vr = L.voff[r][ocol + 1];
+      const int vdl = L.voff[r + 1][ocol + o_ - 1], vdr = L.voff[r + 1][ocol + o_];
+      const bool second = (e & 1) != 0;
+      const uint32_t u = (uint32_t)(uint16_t)tof + (second ? (uint32_t)info_ntb(of) : 0u);
       Tri3 t3;
-      t3.a = bvr + L.voff[r][ocol];
-      if (e & 1) {
-        t3.b = bvr + L.voff[r][ocol + 1];
-        t3.c = bvn + L.voff[r + 1][ocol + o_];
-      } else {
-        t3.b = bvn + L.voff[r + 1][ocol + o_];
-        t3.c = bvn + L.voff[r + 1][ocol + o_ - 1];
+      t3.a = bvr + va;
+      t3.b = second ? bvr + vr : bvn + vdr;
+      t3.c = bvn + (second ? vdr : vdl);
+      if (h2[q]) {
+        *reinterpret_cast<Tri3*>(trow + u * 12u) = t3;
+        crow[u] = both && !info_fg(of) ? 0x80 : 0;
       }
-      *reinterpret_cast<Tri3*>(trow + u * 12u) = t3;
-      crow[u] = both && !info_fg(of) ? 0x80 : 0;
     }
     // the next row's ranks reuse the slots
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -789,10 +789,13 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
     for (int u = 0; u < kU; ++u) {
       const int col = 1 + 64 * u + lane;
       const uint32_t cd = codes[m][u];
-      const uint32_t f = cd != 0xffffu ? map_info(cd) : 0u;
-      if (kMode == kEmitAll && rr < RB && cd != 0xffffu && (cd & 0x8000u)) atomicAdd(&L.na, 1);  // owned slow owners
-      L.info[rr][col] = (uint16_t)(cd != 0xffffu ? cd : 0u);
-      const int p = info_nv(f) | (info_nt(f) << 16);
+      const uint32_t cv = cd != 0xffffu ? cd : 0u;
+      if (kMode == kEmitAll && rr < RB && (cv & 0x8000u)) atomicAdd(&L.na, 1);  // owned slow owners
+      L.info[rr][col] = (uint16_t)cv;
+      // counts straight from the code: bit 7 is a chain vertex in a slow
+      // owner's code and the inside bit in the others'
+      const int p = __builtin_popcount(cv & ((cv & 0x8000u) ? 0x1ffu : 0x17fu)) |
+                    ((int)(((cv >> 9) & 7u) + ((cv >> 12) & 7u)) << 16);
       const int incl = wave_incl_scan_dpp(p);
       const int e = carry + incl - p;
       L.voff[rr][col] = (int16_t)(e & 0xffff);

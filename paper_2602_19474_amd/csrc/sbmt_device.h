@@ -121,12 +121,14 @@ SBMT_HD uint32_t ms_case(int c) {
 }
 
 // Packed per-owner counts.
-//  bit 0 self vertex emitted, 1-2 crossings on E0, 3-4 on E1, 5-6 on E2,
+//  bit 0 self vertex emitted, 1-2 crossings on E0, 3-4 on E1, 5-6 on E2
+//  (each in unary: 0, 1 or 3 for none, one or two, so that bits 0-8 count
+//  the owner's vertices),
 //  7 chain vertex in Tb, 8 chain vertex in Ta, 9-11 triangles of Tb,
 //  12-14 triangles of Ta, 15 slow path, 16 owner vertex inside,
 //  17 Tb cut, 18 Ta cut, 19 protocol error.
 SBMT_HD int info_self(uint32_t f) { return f & 1; }
-SBMT_HD int info_n(uint32_t f, int e) { return (f >> (1 + 2 * e)) & 3; }
+SBMT_HD int info_n(uint32_t f, int e) { return __builtin_popcount((f >> (1 + 2 * e)) & 3u); }
 SBMT_HD int info_Ib(uint32_t f) { return (f >> 7) & 1; }
 SBMT_HD int info_Ia(uint32_t f) { return (f >> 8) & 1; }
 SBMT_HD int info_ntb(uint32_t f) { return (f >> 9) & 7; }
@@ -135,9 +137,7 @@ SBMT_HD int info_slow(uint32_t f) { return (f >> 15) & 1; }
 SBMT_HD int info_fg(uint32_t f) { return (f >> 16) & 1; }
 SBMT_HD int info_ncut(uint32_t f) { return ((f >> 17) & 1) + ((f >> 18) & 1); }
 SBMT_HD int info_err(uint32_t f) { return (f >> 19) & 1; }
-SBMT_HD int info_nv(uint32_t f) {
-  return info_self(f) + info_n(f, 0) + info_n(f, 1) + info_n(f, 2) + info_Ib(f) + info_Ia(f);
-}
+SBMT_HD int info_nv(uint32_t f) { return __builtin_popcount(f & 0x1ffu); }  // self, crossings, chain vertices
 SBMT_HD int info_nt(uint32_t f) { return info_ntb(f) + info_nta(f); }
 
 // ---------------------------------------------------------------------------
@@ -594,7 +594,8 @@ SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
   const int self = both ? 1 : fg;
   const int n0 = popc8((uint32_t)xm & 255u), n1 = popc8((uint32_t)(xm >> 8) & 255u),
             n2 = popc8((uint32_t)(xm >> 16) & 255u);
-  r.info = (uint32_t)self | ((uint32_t)(n0 & 3) << 1) | ((uint32_t)(n1 & 3) << 3) | ((uint32_t)(n2 & 3) << 5) |
+  auto unary = [](int n) { return n >= 2 ? 3u : (uint32_t)n; };
+  r.info = (uint32_t)self | (unary(n0) << 1) | (unary(n1) << 3) | (unary(n2) << 5) |
            ((uint32_t)(Ib != 15) << 7) | ((uint32_t)(Ia != 15) << 8) | ((uint32_t)ntb << 9) |
            ((uint32_t)nta << 12) | (1u << 15) | ((uint32_t)fg << 16) | ((uint32_t)(clsb != 0) << 17) |
            ((uint32_t)(clsa != 0) << 18) | ((uint32_t)err << 19);

@@ -200,14 +200,16 @@ __global__ void __launch_bounds__(256) k_coarsen(Src src, const int64_t* __restr
       if (lo + 16 * (uintptr_t)q <= hi) {
         const uint4 v = *reinterpret_cast<const uint4*>(lo + 16 * (uintptr_t)q);
         const int rel = (int)((lo + 16 * (uintptr_t)q) - (uintptr_t)(row + xa));  // pixel of byte 0, minus xa
-        uint32_t bits = 0;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          const uint32_t w = j < 4 ? v.x : (j < 8 ? v.y : (j < 12 ? v.z : v.w));
-          const int x = rel + j;
-          const bool in = x >= 0 && x < xb - xa;
-          bits |= (uint32_t)(in && ((w >> (8 * (j & 3))) & 255u) != 0u) << j;
-        }
+        // bit j = byte j is nonzero (four bytes per word at once), then only
+        // the bytes of pixels xa .. xb-1 are kept
+        auto nz4 = [](uint32_t w) {
+          uint32_t t = (((w & 0x7f7f7f7fu) + 0x7f7f7f7fu) | w) & 0x80808080u;
+          t >>= 7;
+          return (t | (t >> 7) | (t >> 14) | (t >> 21)) & 15u;
+        };
+        const int blo = max(0, -rel), bhi = min(16, xb - xa - rel);
+        const uint32_t inmask = bhi > blo ? (((1u << bhi) - 1u) & ~((1u << blo) - 1u)) : 0u;
+        const uint32_t bits = (nz4(v.x) | (nz4(v.y) << 4) | (nz4(v.z) << 8) | (nz4(v.w) << 12)) & inmask;
         if (bits) {
           const int p = rel + 15;  // >= 0
           const uint64_t sh64 = (uint64_t)bits << (p & 31);

@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(256) k_coarsen(Src src, const int64_t* __restr
   const Img& d = src.img(ii);
   const Geo g = d.g;
   const int nbx = (g.wpr + 7) / 8;
-  const int bx = (int)(local % nbx), ry = (int)(local / nbx);
+  const int bx = (int)local % nbx, ry = (int)local / nbx;  // block index of an image: 32 bits
   if (blockIdx.x == 0 && threadIdx.x < 8) sh.ctr[threadIdx.x] = 0;
   if (local == 0 && threadIdx.x == 0) sh.imgerr[ii] = 0;
   // look-back words and size slots of the fused path start at zero
@@ -448,6 +448,7 @@ __global__ void __launch_bounds__(kThreads) k_count(Src src, const int64_t* __re
   const int ii = src.find(blockIdx.x, tab, local);
   const Img& d = src.img(ii);
   const Geo g = d.g;
+  // (64-bit: the 32-bit form raises this kernel past 90 SGPRs, one wave per SIMD fewer)
   const int cb = (int)(local % g.NCB), ky = (int)(local / g.NCB);
   count_tile<RB, false>(d, g, ii, (int64_t)blockIdx.x, ky * RB, cb, sh, L, out, nullptr);
   __syncthreads();
@@ -469,7 +470,7 @@ __global__ void __launch_bounds__(64) k_slow(Src src, const int64_t* __restrict_
   const int ii = src.find(blockIdx.x, tab, local);
   const Img& d = src.img(ii);
   const Geo g = d.g;
-  const int cb = (int)(local % g.NCB), ky = (int)(local / g.NCB);
+  const int cb = (int)local % g.NCB, ky = (int)local / g.NCB;  // tile index of an image: 32 bits
   const int64_t tile = blockIdx.x;
   if (threadIdx.x < RB) {
     acc[threadIdx.x] = 0ull;
@@ -1007,7 +1008,7 @@ __device__ __forceinline__ void emit_count_tile(const Src& src, const int64_t* _
   long long nv, nt, nc;
   image_totals<Src>(d, sh, nv, nt, nc);
   if (image_status(d, sh.imgerr[ii], nv, nt) != SBMT_OK) return;  // uniform per block
-  const int cb = (int)(local % g.NCB), ky = (int)(local / g.NCB);
+  const int cb = (int)local % g.NCB, ky = (int)local / g.NCB;  // tile index of an image: 32 bits
   const int64_t nsegi = (int64_t)g.NK * g.NCB;
   const longlong4 base = sh.seg_off[d.seg0];
   emit_tile<RB, kMode>(d, g, ky * RB, cb, tile, sh, L, nullptr, [&](EmitLds<RB>& E) {

@@ -255,8 +255,11 @@ __device__ __forceinline__ Bits stage_window(const Geo& g, const uint32_t* __res
   const int wlo = (clo_of(g, x0) + kRingC) >> 5;
   const int whi = ((clo_of(g, x1) + 2 + kRingC) >> 5) + 1;
   const int nw = whi - wlo + 1, nr = rhi - rlo + 1;
+  // t / nw as a multiply by ceil(2^16 / nw): exact for t * nw < 2^16
+  // (t < kWinRows * kWinWords, nw <= kWinWords)
+  const uint32_t inv = (65536u + (uint32_t)nw - 1u) / (uint32_t)nw;
   for (int t = threadIdx.x; t < nr * nw; t += blockDim.x) {
-    const int r = t / nw, w = t - r * nw;
+    const int r = (int)(((uint32_t)t * inv) >> 16), w = t - r * nw;
     win[r * nw + w] = bits[(int64_t)(rlo + r) * g.wpr + wlo + w];
   }
   Bits b;
@@ -331,8 +334,9 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
   const Bits bw = stage_window(g, d.bits, L.win, L.rowR[0] + kRing, L.rowR[klast - k0] + 2 + kRing, c0,
                                min(c0 + kCB, g.NI) - 1);
   __syncthreads();
+  const uint32_t inv = (65536u + (uint32_t)bw.wpr - 1u) / (uint32_t)bw.wpr;  // as in stage_window
   for (int t = threadIdx.x; t < (klast - k0 + 1) * bw.wpr; t += kThreads) {
-    const int r = t / bw.wpr, w = t - r * bw.wpr;
+    const int r = (int)(((uint32_t)t * inv) >> 16), w = t - r * bw.wpr;
     window_masks_word(bw, L.rowR[r] + kRing, w, L.u0[r][w], L.u1[r][w]);
   }
   __syncthreads();

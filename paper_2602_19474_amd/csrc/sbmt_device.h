@@ -74,11 +74,6 @@ SBMT_HD int sgn_filtered(double v, int64_t a, int64_t b) {
   return z3sign(a, b);
 }
 
-SBMT_HD int64_t floordiv(int64_t a, int64_t b) {  // b > 0
-  const int64_t q = a / b;
-  return (a % b != 0 && a < 0) ? q - 1 : q;
-}
-
 // floor(n / (4 s)) for |n| < 2^24 through a float reciprocal and one correction.
 SBMT_HD int div4s(const Geo& g, int n) {
   const int d = 4 * g.s;
@@ -92,7 +87,9 @@ SBMT_HD int div4s(const Geo& g, int n) {
 // floor((y_k - (s-1)/2) / s) for y_k = -1 + k h sqrt3 / 2.
 SBMT_HD int row_cell(int k, int h, int s) {
   const int64_t kh = (int64_t)k * h;
-  int64_t R = floordiv(kh * 17320 / 10000 - s - 1, 2 * s);  // 1.732 < sqrt3 < 1.7321
+  // estimate in double precision (off by at most one for k h < 2^31), then
+  // exact steps
+  int64_t R = (int64_t)__builtin_floor(((double)kh * kSqrt3 - (double)(s + 1)) / (double)(2 * s));
   while (z3sign(-(2 * s * R + s + 1), kh) < 0) --R;
   while (z3sign(-(2 * s * (R + 1) + s + 1), kh) >= 0) ++R;
   return (int)R;

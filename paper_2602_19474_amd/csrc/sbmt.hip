@@ -297,8 +297,9 @@ __device__ __forceinline__ T wave_incl_scan(T v, int lane) {
 // segments of their block: quiet ones (no segment reaches them) are counted
 // here, slow ones get a slot in the tile's record region (their position is
 // written into it for the dense classification) or, beyond the region's
-// capacity, are classified here.  Every owner's code goes to the owner map;
-// the per-row counts of the owners counted here go to acc_out.
+// capacity, are classified here or by k_slow (see kOverflowHere).  Every
+// owner's code goes to the owner map; the per-row counts of the owners
+// counted here go to acc_out.
 // ---------------------------------------------------------------------------
 template <int RB>
 struct CountLds {
@@ -683,13 +684,13 @@ __global__ void k_sizes(Src src, Shared sh, int64_t* __restrict__ user) {
 
 // ---------------------------------------------------------------------------
 // Emission of one tile: rows k0 .. k0+RB-1, owners c0 .. c0+kCB-1.
-//   1. info of the tile's owners plus a one-row / one-column halo: uniform
-//      windows from their samples, the others from their info word (plain, or
-//      the record of a slow owner; owners without a record are classified);
+//   1. owner codes of the tile plus a one-row / one-column halo (from the
+//      owner map) and the tile's slow-owner records;
 //   2. prefix sums of the counts of every row in LDS plus the segment bases
 //      give each owner's first vertex and triangle id and its neighbours' ids;
-//   3. fast and quiet owners are emitted one per thread, then the slow owners
-//      of the tile densely from their records.
+//   3. fast and quiet owners are emitted (a vertex per thread, each wave's
+//      triangles in output order), then the slow owners of the tile densely
+//      from their records (those without a record: see kEmitMissing).
 // bv[0..RB] (image-local first vertex of each row's segment, row RB = the halo
 // row) and tb[0..RB-1] (first triangle) come from the caller: written before
 // the call (the persistent kernel) or by the `bases` callback.

@@ -52,7 +52,7 @@ SBMT_HD uint32_t lut_tri(int cls, int j) { return sbmt_lut_tri[cls][j]; }
 
 constexpr int kThreads = 256;
 constexpr int kCB = 256;               // owners per row segment (one per thread)
-constexpr int kScanThreads = 1024;
+constexpr int kScanThreads = 512;  // 2048 segments per scan block: more blocks in flight than 4096
 constexpr int kScanChunk = 4 * kScanThreads;
 constexpr int kWinRows = 16, kWinWords = 16;  // LDS window of the coarse raster per tile
 constexpr int64_t kMaxRecords = 0x7ffffffeLL;  // records of a call

@@ -445,16 +445,17 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
   }
 }
 
+// Eight waves per SIMD: the target also caps the scalar registers (a few
+// spill to vector lanes), which an uncapped build exceeds.
 template <class Src, int RB>
-__global__ void __launch_bounds__(kThreads) k_count(Src src, const int64_t* __restrict__ tab, Shared sh) {
+__global__ void __launch_bounds__(kThreads, 8) k_count(Src src, const int64_t* __restrict__ tab, Shared sh) {
   __shared__ CountLds<RB> L;
   __shared__ int4 out[RB];
   int64_t local;
   const int ii = src.find(blockIdx.x, tab, local);
   const Img& d = src.img(ii);
   const Geo g = d.g;
-  // (64-bit: the 32-bit form raises this kernel past 90 SGPRs, one wave per SIMD fewer)
-  const int cb = (int)(local % g.NCB), ky = (int)(local / g.NCB);
+  const int cb = (int)local % g.NCB, ky = (int)local / g.NCB;  // tile index of an image: 32 bits
   count_tile<RB, false>(d, g, ii, (int64_t)blockIdx.x, ky * RB, cb, sh, L, out, nullptr);
   __syncthreads();
   const int k = ky * RB + (int)threadIdx.x;

@@ -204,6 +204,29 @@ def test_both_sides_batch_and_batch_of_one():
     assert np.array_equal(t.cpu().numpy(), ref.tris) and np.array_equal(c.cpu().numpy(), ref.codes)
 
 
+@pytest.mark.parametrize("rows", [8, 4])
+def test_both_sides_with_record_overflow(rows):
+    """Both sides and a tiny record list: slow owners without a record are
+    classified by the slow pass and emitted by the missing-record kernel,
+    background sub-triangles included."""
+    import torch
+
+    from paper_2602_19474_amd import BOTH_SIDES
+    from paper_2602_19474_amd.batch import Batch, Tuning
+    items = _items()[:5]
+    gpu = [(torch.from_numpy(np.ascontiguousarray(bm)).cuda(), h) for bm, h in items]
+    print(f"[gpu-batch] both sides, record_cap=37, rows={rows}", flush=True)
+    b = Batch(gpu, tuning=Tuning(strategy=0, tile_rows=rows, record_cap=37), flags=BOTH_SIDES)
+    outs = b.allocate(b.plan())
+    b.mesh()
+    torch.cuda.synchronize()
+    for i, ((bm, h), (v, t, c)) in enumerate(zip(items, outs)):
+        ref = oracle.mesh_from_bitmap(bm, h, oracle.BOTH_SIDES)
+        assert b.sizes()[i][3] == 0
+        assert np.array_equal(t.cpu().numpy(), ref.tris) and np.array_equal(c.cpu().numpy(), ref.codes), i
+        assert float(np.abs(v.cpu().numpy() - ref.verts).max(initial=0.0)) <= 1e-12 * h
+
+
 def test_batch_argument_errors():
     import torch
 

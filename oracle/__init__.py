@@ -73,6 +73,8 @@ def lib():
         L.oracle_class_table.argtypes = [vp, i32]
         L.oracle_template_of_code.restype = i32
         L.oracle_template_of_code.argtypes = [i32, vp]
+        L.oracle_canonical.restype = i32
+        L.oracle_canonical.argtypes = [i32, vp, vp]
         L.oracle_z3_sign.restype = i32
         L.oracle_z3_sign.argtypes = [i64, i64]
         L.oracle_local.restype = i32
@@ -165,6 +167,15 @@ def class_table() -> np.ndarray:
 def z3_sign(a: int, b: int) -> int:
     """Exact sign of a + b*sqrt(3) as the oracle decides it."""
     return int(lib().oracle_z3_sign(int(a), int(b)))
+
+
+def canonical(code: int):
+    """(class id, canonical code, rotation tag) of a raw key code, or None if inadmissible."""
+    cc, rot = ctypes.c_int32(), ctypes.c_int32()
+    cls = lib().oracle_canonical(int(code), ctypes.byref(cc), ctypes.byref(rot))
+    if cls < 0:
+        return None
+    return int(cls), int(cc.value), int(rot.value)
 
 
 def template_of_code(code: int):

@@ -1087,6 +1087,22 @@ int32_t oracle_class_table(int32_t* out, int32_t cap) {
   return (int32_t)t.size();
 }
 
+// Canonical code and rotation tag of a raw key code (Sec. 3.3.3: the smallest
+// code over the three rotations, the first rotation reaching it); -1 if the
+// code is not admissible.
+int32_t oracle_canonical(int32_t code, int32_t* canon_code, int32_t* rot) {
+  Desc d;
+  d.type = code / 4096;
+  d.tok[0] = (code / 512) % 8; d.tok[1] = (code / 64) % 8;
+  d.tok[2] = (code / 8) % 8; d.tok[3] = code % 8;
+  if (!desc_admissible(d)) return -1;
+  int cc = 0, r = 0;
+  desc_canonical(d, &cc, &r);
+  *canon_code = cc;
+  *rot = r;
+  return class_id_of(cc);
+}
+
 // Procedural template of one key (both sides).  out: up to 5 x (a,b,c,side).
 int32_t oracle_template_of_code(int32_t code, int32_t* out) {
   Desc d;

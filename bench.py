@@ -268,8 +268,11 @@ def batch_section(items, repeats: int = 5):
                     "hbm_frac": alg / dt / 1e9 / HBM_PEAK_GBS}
     del plains
     torch.cuda.empty_cache()
-    # batched: plan once for the sizes, autotune, capture the whole path in a graph
-    b = Batch(gpu)
+    # batched: plan once for the sizes, autotune, capture the whole path in a graph;
+    # the batch is laid out for the persistent kernel too (records for every owner
+    # of a band tile), so that the autotuner's candidates include it
+    from paper_2602_19474_amd.batch import Tuning
+    b = Batch(gpu, tuning=Tuning(strategy=1, tile_rows=8, groups_per_cu=2))
     sizes = b.plan()
     b.allocate(sizes)
     best, tuned_ms = b.tune(reps=3)
@@ -298,7 +301,6 @@ def batch_section(items, repeats: int = 5):
     # the persistent fused launch (coarsening, then one classify-scan-emit
     # kernel): the best of its tunings, replayed as a graph like the above
     from paper_2602_19474_amd import SbmtError
-    from paper_2602_19474_amd.batch import Tuning
     try:
         trials = []
         for rows in (4, 8):
@@ -396,8 +398,8 @@ def _oracle_tris(item):
     return int(oracle.mesh_from_bitmap(bm, gh).tris.shape[0])
 
 
-def cpu_baseline_pool(items, seconds: float = 15.0):
-    """The oracle over a process pool on all host cores (batch workload sample)."""
+def cpu_baseline_pool(items, seconds: float = 15.0, what: str = "batch workload"):
+    """The oracle over a process pool on all host cores (a sample of a many-image workload)."""
     from concurrent.futures import ProcessPoolExecutor
     cores = os.cpu_count() or 1
     done_tri, done_px, n = 0, 0, 0
@@ -412,7 +414,26 @@ def cpu_baseline_pool(items, seconds: float = 15.0):
                 break
     dt = time.perf_counter() - a
     return {"value": done_tri / dt, "unit": "triangles/s", "mpix_per_s": done_px / 1e6 / dt, "cores": cores,
-            "kind": "oracle", "sample": f"first {n} images of the batch workload, one process per core"}
+            "kind": "oracle", "sample": f"first {n} images of the {what}, one process per core"}
+
+
+def cpu_baseline_images(name: str, images, grid_h: int, seconds: float = 5.0):
+    """The oracle on one core over the latency workload's images, one after the other."""
+    import oracle
+    lat, tri, px = [], 0, 0
+    a = time.perf_counter()
+    for bm in images:
+        b = time.perf_counter()
+        tri += oracle.mesh_from_bitmap(bm, grid_h).tris.shape[0]
+        lat.append(time.perf_counter() - b)
+        px += bm.size
+        if time.perf_counter() - a > seconds:
+            break
+    dt = time.perf_counter() - a
+    lat = np.array(lat) * 1e3
+    return {"value": tri / dt, "unit": "triangles/s", "mpix_per_s": px / 1e6 / dt, "cores": 1, "kind": "oracle",
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "sample": f"first {len(lat)} images of the {name} workload, one after the other, single thread"}
 
 
 def cpu_baseline(full: np.ndarray):
@@ -505,7 +526,8 @@ def main():
         "config": {"workload": "noise8192", "width": int(bm.shape[1]), "height": int(bm.shape[0]), "grid_h": 1,
                    "fg_only": True, "generator": "N(0,1) -> Gaussian sigma 16 -> z-score -> > 0.3, seed 4/0"},
         "mpix_per_s": bm.size / 1e6 / (ms * 1e-3),
-        "mesh": {"vertices": sz.n_vertices, "triangles": sz.n_triangles, "cut": sz.n_cut},
+        "mesh": {"vertices": sz.n_vertices, "triangles": sz.n_triangles, "cut": sz.n_cut,
+                 "boundary_segments": sz.n_segments},
         "plan_ms": H["plan_ms"],
         "emit_ms": H["emit_ms"],
         "path_hbm_frac": path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -534,7 +556,11 @@ def main():
         log("cpu baseline")
         res["cpu_baseline"] = cpu_baseline(noise)
         if extras is not None:
+            res["latency"][0]["cpu_baseline"] = cpu_baseline_images("disk64", extras["disk64"], 1)
+            res["latency"][1]["cpu_baseline"] = cpu_baseline_images("ellipses1024", extras["ellipses1024"], 2)
             res["batch"]["cpu_baseline"] = cpu_baseline_pool(extras["batch"])
+            if "serve" in extras:
+                res["serve"]["cpu_baseline"] = cpu_baseline_pool(extras["serve"], what="serving request pool")
     res["inputs_sha256"] = {"noise8192": wl.sha256(noise)}
     if extras is not None:
         import hashlib
@@ -543,6 +569,12 @@ def main():
             hb.update(wl.sha256(b).encode())
             hb.update(bytes([gh]))
         res["inputs_sha256"]["batch"] = hb.hexdigest()
+        if "serve" in extras:
+            hs = hashlib.sha256()
+            for b, gh in extras["serve"]:
+                hs.update(wl.sha256(b).encode())
+                hs.update(bytes([gh]))
+            res["inputs_sha256"]["serve_pool"] = hs.hexdigest()
     print(json.dumps(res), flush=True)
 
 

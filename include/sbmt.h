@@ -92,7 +92,14 @@ typedef struct {
   int64_t n_vertices;  /* rows of the vertex array (x, y) */
   int64_t n_triangles; /* rows of the triangle array and length of the code array */
   int64_t n_cut;       /* base triangles replaced by a template */
+  int64_t n_segments;  /* boundary segments extracted from the coarsened bitmap (the
+                          marching-squares polyline pieces, Sec. 3.2; each has length
+                          s/sqrt2 or s pixels) */
 } sbmt_sizes;
+
+/* Per-image sizes record written to device memory by the asynchronous calls:
+ * int64 [SBMT_SIZE_WORDS] = n_vertices, n_triangles, n_cut, status, n_segments. */
+#define SBMT_SIZE_WORDS 5
 
 /* Geometry of an image's grid (host-only computation). */
 typedef struct {
@@ -125,9 +132,9 @@ sbmt_status sbmt_run(sbmt_handle h, const sbmt_image* img, void* workspace, size
                      double* verts, int32_t* tris, uint8_t* codes, void* stream);
 
 /* Plan and run in one asynchronous call, without a host round trip: outputs are
- * written only if they fit the capacities; the sizes and a status word are
- * written to the device buffer `sizes_dev` (int64 [4]: n_vertices, n_triangles,
- * n_cut, status).  status = SBMT_E_CAPACITY if the mesh did not fit. */
+ * written only if they fit the capacities; the sizes record is written to the
+ * device buffer `sizes_dev` (int64 [SBMT_SIZE_WORDS]: n_vertices, n_triangles,
+ * n_cut, status, n_segments).  status = SBMT_E_CAPACITY if the mesh did not fit. */
 sbmt_status sbmt_mesh_async(sbmt_handle h, const sbmt_image* img, void* workspace, size_t ws_bytes,
                             double* verts, int64_t vert_cap, int32_t* tris, uint8_t* codes,
                             int64_t tri_cap, int64_t* sizes_dev, void* stream);
@@ -197,7 +204,8 @@ sbmt_status sbmt_batch_plan(sbmt_batch b, sbmt_sizes* out, void* stream);
 sbmt_status sbmt_batch_plan_async(sbmt_batch b, void* stream);
 /* Reads the pinned copy written by the last sbmt_batch_plan_async (no wait). */
 sbmt_status sbmt_batch_host_sizes(sbmt_batch b, sbmt_sizes* out, int64_t* status);
-/* sizes_dev: device int64 [n][4] (n_vertices, n_triangles, n_cut, status) or NULL.
+/* sizes_dev: device int64 [n][SBMT_SIZE_WORDS] (n_vertices, n_triangles, n_cut, status,
+ * n_segments) or NULL.
  * Emits what the last plan of this batch counted (with that plan's tile
  * height); SBMT_E_INVALID_ARG if the batch was never planned. */
 sbmt_status sbmt_batch_emit(sbmt_batch b, int64_t* sizes_dev, void* stream);

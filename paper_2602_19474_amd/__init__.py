@@ -18,7 +18,7 @@ import ctypes
 from dataclasses import dataclass
 
 from . import _lib
-from ._lib import BOTH_SIDES, SbmtError
+from ._lib import BOTH_SIDES, SIZE_WORDS, SbmtError
 
 __all__ = ["Context", "mesh_from_bitmap", "plan", "run", "mesh_async", "query", "num_classes", "class_code",
            "BOTH_SIDES", "SbmtError", "SUPPORTED_GRID_H"]
@@ -46,6 +46,7 @@ class Sizes:
     n_vertices: int
     n_triangles: int
     n_cut: int
+    n_segments: int = 0
 
 
 def _image(bitmap, grid_h: int, flags: int) -> _lib.Image:
@@ -120,7 +121,7 @@ def plan(bitmap, grid_h: int, ws, flags: int = 0, stream=None, ctx: Context | No
     out = _lib.Sizes()
     _lib.check(_lib.lib().sbmt_plan(ctx.handle, ctypes.byref(img), ws.data_ptr(), ws.numel(), ctypes.byref(out),
                                     _stream_ptr(stream)), "sbmt_plan")
-    return Sizes(out.n_vertices, out.n_triangles, out.n_cut)
+    return Sizes(out.n_vertices, out.n_triangles, out.n_cut, out.n_segments)
 
 
 def run(bitmap, grid_h: int, ws, verts, tris, codes, flags: int = 0, stream=None, ctx: Context | None = None):
@@ -133,8 +134,11 @@ def run(bitmap, grid_h: int, ws, verts, tris, codes, flags: int = 0, stream=None
                                    codes.data_ptr() if codes.numel() else None, _stream_ptr(stream)), "sbmt_run")
 
 
-def mesh_from_bitmap(bitmap, grid_h: int, both_sides: bool = False, stream=None):
-    """Mesh a uint8 CUDA tensor [H, W]: plan -> allocate -> run on the current stream."""
+def mesh_from_bitmap(bitmap, grid_h: int, both_sides: bool = False, stream=None, return_sizes: bool = False):
+    """Mesh a uint8 CUDA tensor [H, W]: plan -> allocate -> run on the current stream.
+
+    Returns (verts, tris, codes), and the planned ``Sizes`` as a fourth item
+    when ``return_sizes``."""
     torch = _torch()
     flags = BOTH_SIDES if both_sides else 0
     ws = workspace(bitmap, grid_h, flags)
@@ -144,15 +148,16 @@ def mesh_from_bitmap(bitmap, grid_h: int, both_sides: bool = False, stream=None)
     tris = torch.empty((sz.n_triangles, 3), dtype=torch.int32, device=dev)
     codes = torch.empty((sz.n_triangles,), dtype=torch.uint8, device=dev)
     run(bitmap, grid_h, ws, verts, tris, codes, flags, stream)
-    return verts, tris, codes
+    return (verts, tris, codes, sz) if return_sizes else (verts, tris, codes)
 
 
 def mesh_async(bitmap, grid_h: int, ws, verts, tris, codes, sizes_dev, flags: int = 0, stream=None,
                ctx: Context | None = None):
     """Plan and emit without a host round trip into outputs of given capacity.
 
-    ``sizes_dev`` is an int64 CUDA tensor of 4 entries that receives
-    (n_vertices, n_triangles, n_cut, status); status -7 means the mesh did not fit.
+    ``sizes_dev`` is an int64 CUDA tensor of ``SIZE_WORDS`` (5) entries that receives
+    (n_vertices, n_triangles, n_cut, status, n_segments); status -7 means the mesh did
+    not fit.
     """
     ctx = ctx or context(bitmap.device.index)
     img = _image(bitmap, grid_h, flags)

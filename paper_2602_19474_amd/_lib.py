@@ -32,8 +32,12 @@ class Image(ctypes.Structure):
                 ("row_stride", ctypes.c_int64), ("grid_h", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
+SIZE_WORDS = 5  # per-image device sizes record: n_vertices, n_triangles, n_cut, status, n_segments
+
+
 class Sizes(ctypes.Structure):
-    _fields_ = [("n_vertices", ctypes.c_int64), ("n_triangles", ctypes.c_int64), ("n_cut", ctypes.c_int64)]
+    _fields_ = [("n_vertices", ctypes.c_int64), ("n_triangles", ctypes.c_int64), ("n_cut", ctypes.c_int64),
+                ("n_segments", ctypes.c_int64)]
 
 
 class Layout(ctypes.Structure):

@@ -149,10 +149,10 @@ class Batch:
 
     @property
     def sizes_dev(self):
-        """Device int64 [n, 4] that emit/mesh fill with (n_vertices, n_triangles, n_cut, status)."""
+        """Device int64 [n, 5] that emit/mesh fill with (n_vertices, n_triangles, n_cut, status, n_segments)."""
         if self._sizes_dev is None:
             torch = _torch()
-            self._sizes_dev = torch.zeros((self.n, 4), dtype=torch.int64, device=self.ws.device)
+            self._sizes_dev = torch.zeros((self.n, _lib.SIZE_WORDS), dtype=torch.int64, device=self.ws.device)
         return self._sizes_dev
 
     def emit(self, stream=None, sizes: bool = True):
@@ -165,7 +165,7 @@ class Batch:
                    "sbmt_batch_mesh")
 
     def sizes(self):
-        """(n_vertices, n_triangles, n_cut, status) per image of the last call (synchronises)."""
+        """(n_vertices, n_triangles, n_cut, status, n_segments) per image of the last call (synchronises)."""
         _torch().cuda.synchronize(self.ws.device)
         return [tuple(int(x) for x in row) for row in self.sizes_dev.cpu().tolist()]
 

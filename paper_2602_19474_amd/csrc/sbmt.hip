@@ -57,6 +57,7 @@ constexpr int kScanChunk = 4 * kScanThreads;
 constexpr int kWinRows = 16, kWinWords = 16;  // LDS window of the coarse raster per tile
 constexpr int64_t kMaxRecords = 0x7ffffffeLL;  // records of a call
 constexpr int kMaxBandChunks = 64;             // fused path: row segments per band
+constexpr int kSizeWords = SBMT_SIZE_WORDS;    // per-image sizes record
 
 // One image of a call, as the kernels see it.
 struct Img {
@@ -81,7 +82,7 @@ struct Shared {
   longlong4* blk;                   // [nblk] scan block sums
   unsigned long long* ctr;          // [8] 0: records handed out, 1: band ticket
   int* imgerr;                      // [n] protocol violation seen
-  int64_t* sizes;                   // [n][4] n_vertices, n_triangles, n_cut, status
+  int64_t* sizes;                   // [n][kSizeWords] n_vertices, n_triangles, n_cut, status, n_segments
   SlowRec* rec;                     // slow-owner records, tcap per count tile
   int* tile_n;                      // [count tiles] slow owners queued by each tile
   unsigned long long* band;         // [nbands] fused path look-back words
@@ -175,7 +176,7 @@ __global__ void __launch_bounds__(256) k_coarsen(Src src, const int64_t* __restr
   // look-back words and size slots of the fused path start at zero
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < sh.nbands; q += (int64_t)gridDim.x * blockDim.x)
     sh.band[q] = 0ull;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < 4 * (int64_t)sh.n;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < kSizeWords * (int64_t)sh.n;
        q += (int64_t)gridDim.x * blockDim.x)
     sh.sizes[q] = 0;
   const int s = g.s;
@@ -246,6 +247,39 @@ __global__ void __launch_bounds__(256) k_coarsen(Src src, const int64_t* __restr
   }
 }
 
+// Boundary segments of each image: a marching-squares cell has one segment per
+// foreground->background step of its corners in positive order, and every pair
+// of 4-adjacent samples is walked once in each direction by the two cells that
+// share it, so the count is the number of 4-adjacent sample pairs that differ
+// (ring included).  One thread per raster word (the blocks of k_coarsen, 64
+// threads each: 8 stored rows x 8 words).
+template <class Src>
+__global__ void __launch_bounds__(64) k_segcount(Src src, const int64_t* __restrict__ tab, Shared sh) {
+  int64_t local;
+  const int ii = src.find(blockIdx.x, tab, local);
+  const Img& d = src.img(ii);
+  const Geo g = d.g;
+  const int nbx = (g.wpr + 7) / 8;
+  const int bx = (int)local % nbx, ry = (int)local / nbx;
+  const int rr = ry * kCoarsenRows + (int)(threadIdx.x >> 3), w = bx * 8 + (int)(threadIdx.x & 7);
+  const int nrows = g.CH + 2 * kRing;
+  int n = 0;
+  if (rr < nrows && w < g.wpr) {
+    const uint32_t* row = d.bits + (int64_t)rr * g.wpr;
+    const uint32_t x = row[w], xn = w + 1 < g.wpr ? row[w + 1] : 0u;
+    const uint32_t xd = rr + 1 < nrows ? row[g.wpr + w] : 0u;
+    n = __builtin_popcount(x ^ ((x >> 1) | (xn << 31))) + __builtin_popcount(x ^ xd);
+  }
+  n += __builtin_amdgcn_update_dpp(0, n, 0x111, 0xf, 0xf, false);  // row_shr:1
+  n += __builtin_amdgcn_update_dpp(0, n, 0x112, 0xf, 0xf, false);  // row_shr:2
+  n += __builtin_amdgcn_update_dpp(0, n, 0x114, 0xf, 0xf, false);  // row_shr:4
+  n += __builtin_amdgcn_update_dpp(0, n, 0x118, 0xf, 0xf, false);  // row_shr:8
+  n += __builtin_amdgcn_update_dpp(0, n, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  n += __builtin_amdgcn_update_dpp(0, n, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  n = __builtin_amdgcn_readlane(n, 63);
+  if (threadIdx.x == 0 && n) atomicAdd((unsigned long long*)&sh.sizes[kSizeWords * (int64_t)ii + 4], (unsigned long long)n);
+}
+
 // Stage the coarse-raster window of a tile (cell rows rlo .. rhi, owner
 // columns cfirst .. clast) in LDS; returns the view.  Sizes are checked on the
 // host (tile_window_fits).
@@ -297,9 +331,8 @@ __device__ __forceinline__ T wave_incl_scan(T v, int lane) {
 // segments of their block: quiet ones (no segment reaches them) are counted
 // here, slow ones get a slot in the tile's record region (their position is
 // written into it for the dense classification) or, beyond the region's
-// capacity, are classified here or by k_slow (see kOverflowHere).  Every
-// owner's code goes to the owner map; the per-row counts of the owners
-// counted here go to acc_out.
+// capacity, keep the queued mark for k_slow.  Every owner's code goes to the
+// owner map; the per-row counts of the owners counted here go to acc_out.
 // ---------------------------------------------------------------------------
 template <int RB>
 struct CountLds {
@@ -316,10 +349,10 @@ struct CountLds {
 // Rows k0 .. k0+RB-1 of column block cb.  With hdst, the codes of the last
 // row go to hdst[c] instead of the owner map (the persistent kernel counts
 // the first row of the next band that way without writing it).  Slow owners
-// beyond the record region are classified here with kOverflowHere, else left
-// with the queued mark (0x8000) for k_slow, which keeps this kernel free of
-// the classification's registers.
-template <int RB, bool kOverflowHere = true>
+// beyond the record region keep the queued mark (0x8000) for k_slow (the
+// persistent kernel's regions hold every owner of a tile), which keeps this
+// routine free of the classification's registers.
+template <int RB>
 __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, int64_t tile, int k0, int cb,
                                            const Shared& sh, CountLds<RB>& L, int4* acc_out,
                                            uint16_t* __restrict__ hdst) {
@@ -409,18 +442,7 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
   for (int q = threadIdx.x; q < L.n2; q += kThreads) {
     const int e = L.q2[q], r = e / kCB, c = c0 + (e - r * kCB);
     const int k = k0 + r;
-    if (q < sh.tcap) {
-      sh.rec[tile * sh.tcap + q].x = (uint64_t)c | ((uint64_t)k << 24) | ((uint64_t)ii << 48);
-    } else if (kOverflowHere) {
-      const Frame f = owner_frame(g, bw, k, c, L.rowR[r]);
-      Slow sr;
-      slow_classify(g, f, sr);
-      L.code[r][e - r * kCB] = (uint16_t)map_code(sr.info);
-      atomicAdd(&L.acc[r][0], info_nv(sr.info));
-      atomicAdd(&L.acc[r][1], info_nt(sr.info));
-      atomicAdd(&L.acc[r][2], info_ncut(sr.info));
-      if (info_err(sr.info)) atomicOr(&L.acc[r][3], 1);
-    }
+    if (q < sh.tcap) sh.rec[tile * sh.tcap + q].x = (uint64_t)c | ((uint64_t)k << 24) | ((uint64_t)ii << 48);
   }
   __syncthreads();
   // the tile's owner codes, four per lane and row
@@ -456,7 +478,7 @@ __global__ void __launch_bounds__(kThreads, 8) k_count(Src src, const int64_t* _
   const Img& d = src.img(ii);
   const Geo g = d.g;
   const int cb = (int)local % g.NCB, ky = (int)local / g.NCB;  // tile index of an image: 32 bits
-  count_tile<RB, false>(d, g, ii, (int64_t)blockIdx.x, ky * RB, cb, sh, L, out, nullptr);
+  count_tile<RB>(d, g, ii, (int64_t)blockIdx.x, ky * RB, cb, sh, L, out, nullptr);
   __syncthreads();
   const int k = ky * RB + (int)threadIdx.x;
   if (threadIdx.x < RB && k < g.NK) sh.seg_cnt[d.seg0 + (int64_t)k * g.NCB + cb] = out[threadIdx.x];
@@ -670,16 +692,18 @@ __global__ void k_sizes(Src src, Shared sh, int64_t* __restrict__ user) {
   long long nv, nt, nc;
   image_totals<Src>(d, sh, nv, nt, nc);
   const int64_t st = image_status(d, sh.imgerr[ii], nv, nt);
-  int64_t* o = sh.sizes + 4 * (int64_t)ii;
+  int64_t* o = sh.sizes + kSizeWords * (int64_t)ii;
   o[0] = nv;
   o[1] = nt;
   o[2] = nc;
   o[3] = st;
   if (user) {
-    user[4 * (int64_t)ii + 0] = nv;
-    user[4 * (int64_t)ii + 1] = nt;
-    user[4 * (int64_t)ii + 2] = nc;
-    user[4 * (int64_t)ii + 3] = st;
+    int64_t* u = user + kSizeWords * (int64_t)ii;
+    u[0] = nv;
+    u[1] = nt;
+    u[2] = nc;
+    u[3] = st;
+    u[4] = o[4];
   }
 }
 
@@ -705,7 +729,6 @@ struct EmitLds {
   int16_t voff[RB + 1][W];   // first vertex of each owner, from bv of its row
   int16_t toff[RB][W];       // first triangle of each owner, from tb of its row
   uint32_t hasrec[RB * kCB / 32];
-  int na, ns;
   int rowR[RB + 1];
   int bv[RB + 1];
   long long tb[RB];
@@ -722,7 +745,8 @@ struct EmitLds {
 // (each record carries the owner's place in the tile; records of the halo
 // row, which the persistent kernel keeps in the same region, are skipped).
 // What is emitted:
-//   kEmitAll      everything (the persistent kernel);
+//   kEmitAll      everything, every slow owner from its record (the persistent
+//                 kernel, whose record regions hold every owner of a tile);
 //   kEmitRecords  fast and quiet owners and the slow owners with a record;
 //   kEmitMissing  only the slow owners without a record (the count tile's
 //                 record region was full; the count pass classified them).
@@ -737,10 +761,6 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
   static_assert(kLut <= 2 * kThreads, "two table entries per thread");
   const int c0 = cb * kCB;
   if (threadIdx.x <= RB) L.rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);  // read after step 2
-  if (kMode == kEmitAll) {
-    if (threadIdx.x == 0) L.na = L.ns = 0;
-    __syncthreads();
-  }
   Bits bw;
   bw.p = d.bits;
   bw.wpr = g.wpr;
@@ -799,7 +819,6 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
       const int col = 1 + 64 * u + lane;
       const uint32_t cd = codes[m][u];
       const uint32_t cv = cd != 0xffffu ? cd : 0u;
-      if (kMode == kEmitAll && rr < RB && (cv & 0x8000u)) atomicAdd(&L.na, 1);  // owned slow owners
       L.info[rr][col] = (uint16_t)cv;
       // counts straight from the code: bit 7 is a chain vertex in a slow
       // owner's code and the inside bit in the others'
@@ -942,8 +961,6 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
       mine = (int)(R.x >> 56) < RB;
       if (mine) cnt = info_nv(R.info) | (info_nt(R.info) << 16);
     }
-    const unsigned long long bal = __ballot(mine);
-    if (kMode == kEmitAll && lane == 0 && bal) atomicAdd(&L.ns, (int)__popcll(bal));
     const int incl = wave_incl_scan_dpp(cnt);
     if (lane == 63) L.swt[wv] = incl;
     __syncthreads();
@@ -977,7 +994,7 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
     __syncthreads();
   }
   __syncthreads();
-  if (kMode == kEmitMissing || (kMode == kEmitAll && L.na > L.ns)) {
+  if (kMode == kEmitMissing) {
     // slow owners beyond the tile's record region were classified by the
     // count pass without a record: mark the recorded ones, classify the rest
     for (int t = threadIdx.x; t < RB * kCB / 32; t += kThreads) L.hasrec[t] = 0u;
@@ -1113,6 +1130,8 @@ __global__ void __launch_bounds__(kThreads, 3) k_fused(ManySrc src, const int64_
     for (int cb = 0; cb < g.NCB; ++cb) {
       __syncthreads();
       if (threadIdx.x <= RB) F.acc[threadIdx.x] = make_int4(0, 0, 0, 0);
+      // records hold every owner of the band tile (checked on the host), so no
+      // slow owner is ever classified here
       count_tile<RB + 1>(d, g, ii, tile0 + cb, k0, cb, sh, F.u.c, F.acc, hcode);
       __syncthreads();
       if (threadIdx.x <= RB) F.cnt[cb][threadIdx.x] = make_int2(F.acc[threadIdx.x].x, F.acc[threadIdx.x].y);
@@ -1173,7 +1192,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_fused(ManySrc src, const int64_
           at += F.cnt[cb][r].y;
         }
       if (F.err) atomicOr(&sh.imgerr[ii], 1);
-      if (F.ncut) atomicAdd((unsigned long long*)&sh.sizes[4 * (int64_t)ii + 2], (unsigned long long)F.ncut);
+      if (F.ncut) atomicAdd((unsigned long long*)&sh.sizes[kSizeWords * (int64_t)ii + 2], (unsigned long long)F.ncut);
       unsigned long long* w = sh.band + d.band0 + j;
       long long pv = 0, pt = 0;
       if (j == 0) {
@@ -1207,9 +1226,9 @@ __global__ void __launch_bounds__(kThreads, 3) k_fused(ManySrc src, const int64_
       if (j == nb - 1) {
         // last band of the image: its end is the image total
         const int st = (int)image_status(d, atomicOr(&sh.imgerr[ii], 0), v, tt);
-        sh.sizes[4 * (int64_t)ii + 0] = v;
-        sh.sizes[4 * (int64_t)ii + 1] = tt;
-        sh.sizes[4 * (int64_t)ii + 3] = st;
+        sh.sizes[kSizeWords * (int64_t)ii + 0] = v;
+        sh.sizes[kSizeWords * (int64_t)ii + 1] = tt;
+        sh.sizes[kSizeWords * (int64_t)ii + 3] = st;
       }
       // write only if the band's vertex and triangle ranges fit
       F.err = (v > d.vcap || tt > d.tcap || v > 0x7fffffffLL || atomicOr(&sh.imgerr[ii], 0)) ? 1 : 0;
@@ -1386,6 +1405,9 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
   for (int r = 0; r < 3; ++r) L.ntiles_max = std::max(L.ntiles_max, tab_row(L, 1 + r)[n]);
   if (record_cap == 0) {
     for (int r = 0; r < 3; ++r) L.rcap = std::max(L.rcap, tab_row(L, 1 + r)[n] * (int64_t)(kRBs[r] * kCB / 2));
+  } else if (record_cap < 0) {
+    // room for every owner of a persistent-kernel band tile (its rows and halo row)
+    for (int r = 0; r < 2; ++r) L.rcap = std::max(L.rcap, tab_row(L, 1 + r)[n] * (int64_t)((kRBs[r] + 1) * kCB));
   } else {
     L.rcap = std::max<int64_t>(record_cap, 0);
   }
@@ -1398,7 +1420,7 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
   L.off_imgerr = off;
   off = align256(off + (size_t)n * sizeof(int));
   L.off_sizes = off;
-  off = align256(off + (size_t)n * 4 * sizeof(int64_t));
+  off = align256(off + (size_t)n * kSizeWords * sizeof(int64_t));
   L.off_desc = off;
   off = align256(off + (size_t)n * sizeof(Img));
   L.off_tab = off;
@@ -1481,6 +1503,7 @@ static sbmt_status launch_front(const CallLayout& L, const Src& src, const int64
   const int64_t ntile = L.tab[(size_t)(1 + rbi) * (L.n + 1) + L.n];
   if (ncb > 0x7fffffffLL || ntile > 0x7fffffffLL) return SBMT_E_INVALID_ARG;
   hipLaunchKernelGGL(k_coarsen<Src>, dim3((unsigned)ncb), dim3(256), 0, st, src, t0, sh);
+  hipLaunchKernelGGL(k_segcount<Src>, dim3((unsigned)ncb), dim3(64), 0, st, src, t0, sh);
   switch (kRBs[rbi]) {
     case 4: hipLaunchKernelGGL((k_count<Src, 4>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh); break;
     case 8: hipLaunchKernelGGL((k_count<Src, 8>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh); break;
@@ -1570,7 +1593,7 @@ struct PinnedPool {
 struct sbmt_context {
   int device;
   int cus;
-  long long* pinned;  // 8 x int64
+  long long* pinned;  // 8 x int64 (one sizes record)
   PinnedPool pool;
 };
 
@@ -1587,6 +1610,23 @@ struct sbmt_batch_s {
   int stage_cls = 0, psizes_cls = 0;
   int count_rbi = -1;  // tile height of the last count pass (emission must use the same tiles)
 };
+
+static void host_sizes_of(const int64_t* w, sbmt_sizes* out) {
+  out->n_vertices = w[0];
+  out->n_triangles = w[1];
+  out->n_cut = w[2];
+  out->n_segments = w[4];
+}
+
+// The persistent kernel runs only where every band tile's slow owners fit its
+// record region (band rows plus the halo row): its record-overflow branch (the
+// count pass classifying owners without a record, emission classifying them
+// again) faulted the GPU once in testing without a cause found, so it is kept
+// unreachable and such tunings run the multi-kernel path.
+static bool fused_records_fit(const CallLayout& L, int tile_rows) {
+  const int rbi = rb_index(tile_rows);
+  return L.fused_ok && rbi >= 0 && L.tcap[rbi] >= (int64_t)(tile_rows + 1) * kCB;
+}
 
 static bool tuning_valid(const sbmt_tuning* t) {
   if (t->strategy != SBMT_STRATEGY_MULTI && t->strategy != SBMT_STRATEGY_FUSED) return false;
@@ -1668,13 +1708,11 @@ sbmt_status sbmt_plan(sbmt_handle h, const sbmt_image* img, void* workspace, siz
   src.d = img_of(L, 0, *img, workspace, nullptr);
   if ((st = launch_front(L, src, nullptr, sh, 1, s)) != SBMT_OK) return st;
   if ((st = launch_sizes(L, src, sh, nullptr, s)) != SBMT_OK) return st;
-  if (hipMemcpyAsync(h->pinned, sh.sizes, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+  if (hipMemcpyAsync(h->pinned, sh.sizes, kSizeWords * sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess)
     return SBMT_E_DEVICE;
   if (hipStreamSynchronize(s) != hipSuccess) return SBMT_E_DEVICE;
   if (h->pinned[3] == SBMT_E_PROTOCOL) return SBMT_E_PROTOCOL;
-  out->n_vertices = h->pinned[0];
-  out->n_triangles = h->pinned[1];
-  out->n_cut = h->pinned[2];
+  host_sizes_of((const int64_t*)h->pinned, out);
   if (out->n_vertices > 0x7fffffffLL) return SBMT_E_INDEX_OVERFLOW;
   return SBMT_OK;
 }
@@ -1727,21 +1765,24 @@ sbmt_status sbmt_batch_create(sbmt_handle h, const sbmt_image* imgs, int32_t n, 
                               size_t* ws_bytes, sbmt_batch* out) {
   if (!h || !out || !imgs || n < 1) return SBMT_E_INVALID_ARG;
   sbmt_tuning t = tuning ? *tuning : default_tuning();
-  if (!tuning_valid(&t)) return SBMT_E_INVALID_ARG;
+  if (!tuning_valid(&t) || t.record_cap < 0) return SBMT_E_INVALID_ARG;
   sbmt_batch_s* b = new (std::nothrow) sbmt_batch_s();
   if (!b) return SBMT_E_DEVICE;
   b->ctx = h;
   b->imgs.assign(imgs, imgs + n);
-  sbmt_status st = make_call_layout(imgs, n, t.record_cap, true, &b->L);
+  // a batch created for the persistent kernel with the default record count
+  // gets records for every owner of its band tiles
+  const int64_t rc = (t.strategy == SBMT_STRATEGY_FUSED && t.record_cap == 0) ? -1 : t.record_cap;
+  sbmt_status st = make_call_layout(imgs, n, rc, true, &b->L);
   if (st != SBMT_OK) {
     delete b;
     return st;
   }
-  if (t.strategy == SBMT_STRATEGY_FUSED && !b->L.fused_ok) t.strategy = SBMT_STRATEGY_MULTI;
+  if (t.strategy == SBMT_STRATEGY_FUSED && !fused_records_fit(b->L, t.tile_rows)) t.strategy = SBMT_STRATEGY_MULTI;
   b->tune = t;
   b->stage_bytes = b->L.off_cnt - b->L.off_desc;
   b->stage = (unsigned char*)h->pool.get(b->stage_bytes, &b->stage_cls);
-  b->psizes = (int64_t*)h->pool.get((size_t)n * 4 * sizeof(int64_t), &b->psizes_cls);
+  b->psizes = (int64_t*)h->pool.get((size_t)n * kSizeWords * sizeof(int64_t), &b->psizes_cls);
   if (!b->stage || !b->psizes) {
     h->pool.put(b->stage, b->stage_cls);
     h->pool.put(b->psizes, b->psizes_cls);
@@ -1800,15 +1841,13 @@ sbmt_status sbmt_batch_plan(sbmt_batch b, sbmt_sizes* out, void* stream) {
   if (st != SBMT_OK) return st;
   b->count_rbi = rb_index(b->tune.tile_rows);
   if ((st = launch_sizes(b->L, src, sh, nullptr, s)) != SBMT_OK) return st;
-  const size_t bytes = (size_t)b->L.n * 4 * sizeof(int64_t);
+  const size_t bytes = (size_t)b->L.n * kSizeWords * sizeof(int64_t);
   if (hipMemcpyAsync(b->psizes, sh.sizes, bytes, hipMemcpyDeviceToHost, s) != hipSuccess) return SBMT_E_DEVICE;
   if (hipStreamSynchronize(s) != hipSuccess) return SBMT_E_DEVICE;
   sbmt_status worst = SBMT_OK;
   for (int i = 0; i < b->L.n; ++i) {
-    out[i].n_vertices = b->psizes[4 * i + 0];
-    out[i].n_triangles = b->psizes[4 * i + 1];
-    out[i].n_cut = b->psizes[4 * i + 2];
-    const int64_t sti = b->psizes[4 * i + 3];
+    host_sizes_of(b->psizes + kSizeWords * i, &out[i]);
+    const int64_t sti = b->psizes[kSizeWords * i + 3];
     if (sti == SBMT_E_PROTOCOL) worst = SBMT_E_PROTOCOL;
     if (sti == SBMT_E_INDEX_OVERFLOW && worst == SBMT_OK) worst = SBMT_E_INDEX_OVERFLOW;
   }
@@ -1825,7 +1864,7 @@ sbmt_status sbmt_batch_plan_async(sbmt_batch b, void* stream) {
   if (st != SBMT_OK) return st;
   b->count_rbi = rb_index(b->tune.tile_rows);
   if ((st = launch_sizes(b->L, src, sh, nullptr, s)) != SBMT_OK) return st;
-  const size_t bytes = (size_t)b->L.n * 4 * sizeof(int64_t);
+  const size_t bytes = (size_t)b->L.n * kSizeWords * sizeof(int64_t);
   if (hipMemcpyAsync(b->psizes, sh.sizes, bytes, hipMemcpyDeviceToHost, s) != hipSuccess) return SBMT_E_DEVICE;
   return SBMT_OK;
 }
@@ -1833,10 +1872,8 @@ sbmt_status sbmt_batch_plan_async(sbmt_batch b, void* stream) {
 sbmt_status sbmt_batch_host_sizes(sbmt_batch b, sbmt_sizes* out, int64_t* status) {
   if (!b || !out) return SBMT_E_INVALID_ARG;
   for (int i = 0; i < b->L.n; ++i) {
-    out[i].n_vertices = b->psizes[4 * i + 0];
-    out[i].n_triangles = b->psizes[4 * i + 1];
-    out[i].n_cut = b->psizes[4 * i + 2];
-    if (status) status[i] = b->psizes[4 * i + 3];
+    host_sizes_of(b->psizes + kSizeWords * i, &out[i]);
+    if (status) status[i] = b->psizes[kSizeWords * i + 3];
   }
   return SBMT_OK;
 }
@@ -1868,7 +1905,7 @@ sbmt_status sbmt_batch_mesh(sbmt_batch b, int64_t* sizes_dev, void* stream) {
   const Shared sh = shared_of(L, b->ws, rbi);
   const ManySrc src = many_of(b);
   const int64_t* dtab = dtab_of(b);
-  if (b->tune.strategy == SBMT_STRATEGY_MULTI || !L.fused_ok) {
+  if (b->tune.strategy == SBMT_STRATEGY_MULTI || !fused_records_fit(L, b->tune.tile_rows)) {
     b->count_rbi = rbi;
     sbmt_status st = launch_front(L, src, dtab, sh, rbi, s);
     if (st != SBMT_OK) return st;
@@ -1878,6 +1915,7 @@ sbmt_status sbmt_batch_mesh(sbmt_batch b, int64_t* sizes_dev, void* stream) {
   const int64_t ncb = L.tab[(size_t)L.n];
   if (ncb > 0x7fffffffLL) return SBMT_E_INVALID_ARG;
   hipLaunchKernelGGL(k_coarsen<ManySrc>, dim3((unsigned)ncb), dim3(256), 0, s, src, dtab, sh);
+  hipLaunchKernelGGL(k_segcount<ManySrc>, dim3((unsigned)ncb), dim3(64), 0, s, src, dtab, sh);
   const int64_t nbands = L.tab[(size_t)(4 + rbi) * (L.n + 1) + L.n];
   const int64_t* btab = dtab + (size_t)(4 + rbi) * (L.n + 1);
   uint16_t* halo = (uint16_t*)((char*)b->ws + L.off_halo);
@@ -1888,7 +1926,7 @@ sbmt_status sbmt_batch_mesh(sbmt_batch b, int64_t* sizes_dev, void* stream) {
   else
     hipLaunchKernelGGL((k_fused<8>), dim3(grid), dim3(kThreads), 0, s, src, btab, ttab, sh, nbands, halo);
   if (sizes_dev) {
-    const int64_t n4 = 4 * (int64_t)L.n;
+    const int64_t n4 = kSizeWords * (int64_t)L.n;
     hipLaunchKernelGGL(k_copy_sizes, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, (const int64_t*)sh.sizes,
                        n4, sizes_dev);
   }
@@ -1899,15 +1937,13 @@ sbmt_status sbmt_batch_sizes(sbmt_batch b, sbmt_sizes* out, int64_t* status, voi
   if (!b || !out) return SBMT_E_INVALID_ARG;
   if (!b->ws) return SBMT_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  const size_t bytes = (size_t)b->L.n * 4 * sizeof(int64_t);
+  const size_t bytes = (size_t)b->L.n * kSizeWords * sizeof(int64_t);
   if (hipMemcpyAsync(b->psizes, (char*)b->ws + b->L.off_sizes, bytes, hipMemcpyDeviceToHost, s) != hipSuccess)
     return SBMT_E_DEVICE;
   if (hipStreamSynchronize(s) != hipSuccess) return SBMT_E_DEVICE;
   for (int i = 0; i < b->L.n; ++i) {
-    out[i].n_vertices = b->psizes[4 * i + 0];
-    out[i].n_triangles = b->psizes[4 * i + 1];
-    out[i].n_cut = b->psizes[4 * i + 2];
-    if (status) status[i] = b->psizes[4 * i + 3];
+    host_sizes_of(b->psizes + kSizeWords * i, &out[i]);
+    if (status) status[i] = b->psizes[kSizeWords * i + 3];
   }
   return SBMT_OK;
 }
@@ -1923,7 +1959,7 @@ sbmt_status sbmt_batch_set_tuning(sbmt_batch b, const sbmt_tuning* t) {
   sbmt_tuning x = *t;
   if (!tuning_valid(&x)) return SBMT_E_INVALID_ARG;
   if (x.record_cap != b->tune.record_cap) return SBMT_E_INVALID_ARG;  // fixed by the layout
-  if (x.strategy == SBMT_STRATEGY_FUSED && !b->L.fused_ok) return SBMT_E_INVALID_ARG;
+  if (x.strategy == SBMT_STRATEGY_FUSED && !fused_records_fit(b->L, x.tile_rows)) return SBMT_E_INVALID_ARG;
   b->tune = x;
   return SBMT_OK;
 }
@@ -1943,15 +1979,15 @@ sbmt_status sbmt_batch_tune(sbmt_batch b, int32_t reps, sbmt_tuning* best, float
     t.groups_per_cu = 0;
     cand.push_back(t);
   }
-  if (b->L.fused_ok)
-    for (int rb : {4, 8})
-      for (int gpc : {1, 2, 3}) {
-        sbmt_tuning t = b->tune;
-        t.strategy = SBMT_STRATEGY_FUSED;
-        t.tile_rows = rb;
-        t.groups_per_cu = gpc;
-        cand.push_back(t);
-      }
+  for (int rb : {4, 8})
+    for (int gpc : {1, 2, 3}) {
+      if (!fused_records_fit(b->L, rb)) continue;
+      sbmt_tuning t = b->tune;
+      t.strategy = SBMT_STRATEGY_FUSED;
+      t.tile_rows = rb;
+      t.groups_per_cu = gpc;
+      cand.push_back(t);
+    }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return SBMT_E_DEVICE;
   if (hipEventCreate(&e1) != hipSuccess) {

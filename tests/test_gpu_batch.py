@@ -91,28 +91,43 @@ def test_mesh_without_host_round_trip(expected, strategy, rows, gpc):
         _check(outs, b.sizes(), expected, f"s{strategy}r{rows}g{gpc}#{rep}")
 
 
-# The persistent kernel with 8-row bands and a record list too small for any
-# tile faulted the GPU once (with an emission variant whose compiled code
-# differed only in how slow codes were counted); no cause was found by
-# reading the kernel, so that case stays off the GPU until one is.
-_FUSED8_OVERFLOW = pytest.param(1, 8, marks=pytest.mark.skip(
-    reason="GPU memory fault seen once in the persistent kernel, 8-row bands, zero records per tile; "
-           "cause not yet found"))
-
-
-@pytest.mark.parametrize("strategy,rows", [(0, 8), (1, 4), _FUSED8_OVERFLOW])
+@pytest.mark.parametrize("strategy,rows", [(0, 8), (0, 4), (1, 4), (1, 8)])
 def test_record_list_overflow(expected, strategy, rows):
-    """A tiny record list: most slow owners are classified where they are needed."""
+    """A tiny record list: most slow owners are classified where they are needed.
+
+    The persistent kernel runs only when every owner of a band tile has a
+    record, so a persistent tuning with this list runs the multi-kernel path."""
     import torch
 
     from paper_2602_19474_amd.batch import Batch, Tuning
     items = _gpu_items()
     print(f"[gpu-batch] record_cap=37 strategy={strategy} rows={rows}", flush=True)
     b = Batch(items, tuning=Tuning(strategy=strategy, tile_rows=rows, groups_per_cu=2, record_cap=37))
+    assert b.tuning.strategy == 0
     outs = b.allocate(b.plan())
     b.mesh()
     torch.cuda.synchronize()
-    _check(outs, b.sizes(), expected, f"overflow s{strategy}")
+    _check(outs, b.sizes(), expected, f"overflow s{strategy}r{rows}")
+
+
+def test_persistent_tuning_needs_room_for_records():
+    """Switching a batch laid out for the multi-kernel path (records for half of the
+    owners) to the persistent kernel is refused; a batch created for the persistent
+    kernel accepts every persistent tuning and the autotuner tries them."""
+    import torch
+
+    from paper_2602_19474_amd import SbmtError
+    from paper_2602_19474_amd.batch import Batch, Tuning
+    items = _gpu_items()[:4]
+    b = Batch(items)
+    with pytest.raises(SbmtError):
+        b.tuning = Tuning(strategy=1, tile_rows=8, groups_per_cu=2)
+    f = Batch(items, tuning=Tuning(strategy=1, tile_rows=8, groups_per_cu=2))
+    assert f.tuning.strategy == 1
+    f.tuning = Tuning(strategy=1, tile_rows=4, groups_per_cu=3)
+    assert f.tuning.strategy == 1
+    del b, f
+    torch.cuda.synchronize()
 
 
 @pytest.mark.parametrize("strategy", [0, 1])
@@ -242,3 +257,39 @@ def test_batch_argument_errors():
     b = Batch([(t, 1)])
     with pytest.raises(SbmtError):
         b.emit()  # nothing planned yet
+
+
+@pytest.mark.slow
+def test_batch256_images_through_captured_graph():
+    """The first 32 images of the batch workload (sides 128..2048, h in {1, 2, 4}),
+    autotuned, meshed by a captured graph and replayed; every replay is compared
+    element by element with the oracle."""
+    import torch
+
+    import oracle_pool
+    from paper_2602_19474_amd.batch import Batch
+    items = wl.batch256(n=32)
+    print(f"[gpu-batch] batch256[:32] oracle ({sum(b.size for b, _ in items) / 1e6:.1f} Mpix)", flush=True)
+    refs = oracle_pool.oracle_meshes(items)
+    b = Batch([(torch.from_numpy(bm).cuda(), h) for bm, h in items])
+    outs = b.allocate(b.plan())
+    tn, ms = b.tune(reps=1)
+    print(f"[gpu-batch] tuned {tn} {ms:.3f} ms; capture", flush=True)
+    g = b.capture()
+    for rep in range(3):
+        for v, t, c in outs:
+            v.fill_(-1.0)
+            t.fill_(-1)
+            c.fill_(255)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        sizes = b.sizes()
+        for i, ((v, t, c), ref) in enumerate(zip(outs, refs)):
+            rv, rt, rc, nseg, ncut = ref
+            assert sizes[i][:5] == (rv.shape[0], rt.shape[0], ncut, 0, nseg), (rep, i, sizes[i])
+            assert np.array_equal(t.cpu().numpy(), rt), f"replay {rep}: image {i} connectivity"
+            assert np.array_equal(c.cpu().numpy(), rc), f"replay {rep}: image {i} codes"
+            dv = float(np.abs(v.cpu().numpy() - rv).max(initial=0.0))
+            assert dv <= 1e-12 * items[i][1], (rep, i, dv)
+        print(f"[gpu-batch] replay {rep} matches the oracle", flush=True)

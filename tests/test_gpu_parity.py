@@ -25,18 +25,21 @@ def _sbmt():
     return sbmt
 
 
-def _gpu_mesh(bm: np.ndarray, h: int, both: bool = False):
+def _gpu_mesh(bm: np.ndarray, h: int, both: bool = False, sizes: bool = False):
     import torch
     t = torch.from_numpy(np.ascontiguousarray(bm, np.uint8)).to("cuda")
-    v, tr, c = _sbmt().mesh_from_bitmap(t, h, both_sides=both)
+    v, tr, c, sz = _sbmt().mesh_from_bitmap(t, h, both_sides=both, return_sizes=True)
     torch.cuda.synchronize()
-    return v.cpu().numpy(), tr.cpu().numpy(), c.cpu().numpy()
+    out = (v.cpu().numpy(), tr.cpu().numpy(), c.cpu().numpy())
+    return out + (sz,) if sizes else out
 
 
 def _compare(name: str, bm: np.ndarray, h: int, both: bool = False, check_invariants: bool = True):
     print(f"[gpu-parity] {name} {bm.shape} h={h} both={both}", flush=True)
-    v, t, c = _gpu_mesh(bm, h, both)
+    v, t, c, sz = _gpu_mesh(bm, h, both, sizes=True)
     ref = oracle.mesh_from_bitmap(bm, h, oracle.BOTH_SIDES if both else 0)
+    # boundary segments and cut base triangles counted by the kernels
+    assert (sz.n_segments, sz.n_cut) == (ref.n_segments, ref.n_cut), (sz, ref.n_segments, ref.n_cut)
     assert t.shape == ref.tris.shape, (t.shape, ref.tris.shape)
     assert v.shape == ref.verts.shape, (v.shape, ref.verts.shape)
     assert np.array_equal(t, ref.tris), "triangle connectivity differs"
@@ -127,7 +130,7 @@ def test_mesh_async_matches_and_respects_capacity():
     verts = torch.full((nv + 100, 2), -1.0, dtype=torch.float64, device="cuda")
     tris = torch.full((nt + 100, 3), -1, dtype=torch.int32, device="cuda")
     codes = torch.zeros((nt + 100,), dtype=torch.uint8, device="cuda")
-    sizes = torch.zeros(4, dtype=torch.int64, device="cuda")
+    sizes = torch.zeros(5, dtype=torch.int64, device="cuda")
     print("[gpu-parity] mesh_async fits", flush=True)
     sbmt.mesh_async(t, 2, ws, verts, tris, codes, sizes)
     torch.cuda.synchronize()
@@ -187,3 +190,15 @@ def test_noise8192_full_size():
     mc.check_mesh(v, t, c, bm, 1)
     print(f"[gpu-parity] noise8192 done at {time.time() - t0:.1f}s", flush=True)
     sys.stdout.flush()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("h", [1, 4])
+def test_tall_and_wide_strips(h):
+    """Images 2^20 pixels long (the largest side the boundary accepts): coordinates
+    there are largest, and so is the rounding of the double-precision sign filter
+    that the exact fallback covers."""
+    g = wl.rng(78, h)
+    strip = wl.smoothed_noise(24, 1 << 20, 2.0, 0.0, False, g)
+    _compare("tall strip", strip, h, check_invariants=False)
+    _compare("wide strip", np.ascontiguousarray(strip.T), h, check_invariants=False)

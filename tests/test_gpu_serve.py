@@ -86,3 +86,21 @@ def test_served_sample_matches_oracle():
         v, t, c = got[r.rid]
         assert np.array_equal(t, ref.tris) and np.array_equal(c, ref.codes)
         assert float(np.abs(v - ref.verts).max(initial=0.0)) <= 1e-12 * gh
+
+
+@pytest.mark.slow
+def test_served_requests_from_the_serving_distribution():
+    """Requests drawn from the serving workload itself (square sides 256..4096
+    log-uniform, ellipses or smoothed noise, h in {1, 2, 4}): served in the mix,
+    each equals the oracle's mesh."""
+    import oracle_pool
+    items = [wl.serve_request(j) for j in range(6)]
+    print("[gpu-serve] sides " + " ".join(f"{bm.shape[0]}/h{gh}" for bm, gh in items), flush=True)
+    refs = oracle_pool.oracle_meshes(items)
+    srv, out, got = _served(items, 8 << 30, 3, 4)
+    assert srv.failed == 0 and srv.completed == len(items)
+    for r in out:
+        rv, rt, rc, _, _ = refs[r.rid]
+        v, t, c = got[r.rid]
+        assert np.array_equal(t, rt) and np.array_equal(c, rc), f"request {r.rid}"
+        assert float(np.abs(v - rv).max(initial=0.0)) <= 1e-12 * items[r.rid][1]

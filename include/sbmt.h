@@ -139,6 +139,27 @@ sbmt_status sbmt_mesh_async(sbmt_handle h, const sbmt_image* img, void* workspac
                             double* verts, int64_t vert_cap, int32_t* tris, uint8_t* codes,
                             int64_t tri_cap, int64_t* sizes_dev, void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): sbmt_mesh_async
+ * without the workspace arguments.  The workspace is a scratch array inside
+ * the library, SBMT_NOALLOC_SCRATCH_BYTES bytes per GPU, held from the first
+ * use of the library on that GPU until the process ends; its device address
+ * is looked up once per handle by sbmt_create.  No device memory is allocated
+ * by this call (the host does a few small bookkeeping allocations).
+ *  - An image whose workspace (sbmt_layout.workspace_bytes of sbmt_query) is
+ *    larger than SBMT_NOALLOC_SCRATCH_BYTES returns SBMT_E_WORKSPACE before
+ *    any launch; 64 MiB covers an image of about 2200 x 2200 pixels at
+ *    grid_h = 1 and 3500 x 3500 at grid_h = 2.
+ *  - Every call on one GPU (through any handle of this process) uses the same
+ *    array, which keeps the last call's contents: calls that overlap on one
+ *    GPU (different streams, or different host threads) race and must be
+ *    serialised by the caller.  Nothing in the array needs clearing between
+ *    calls (the kernels clear what starts at zero).
+ *  - Outputs, capacities, sizes_dev and errors are those of sbmt_mesh_async. */
+#define SBMT_NOALLOC_SCRATCH_BYTES (64u << 20)
+sbmt_status sbmt_mesh_noalloc(sbmt_handle h, const sbmt_image* img, double* verts, int64_t vert_cap,
+                              int32_t* tris, uint8_t* codes, int64_t tri_cap, int64_t* sizes_dev, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Batches: many images of different sizes and grid_h meshed by one set of
  * launches (or one persistent launch), e.g. inside a captured hipGraph.

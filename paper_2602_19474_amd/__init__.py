@@ -18,7 +18,7 @@ import ctypes
 from dataclasses import dataclass
 
 from . import _lib
-from ._lib import BOTH_SIDES, SIZE_WORDS, SbmtError
+from ._lib import BOTH_SIDES, NOALLOC_SCRATCH_BYTES, SIZE_WORDS, SbmtError
 
 __all__ = ["Context", "mesh_from_bitmap", "plan", "run", "mesh_async", "query", "num_classes", "class_code",
            "BOTH_SIDES", "SbmtError", "SUPPORTED_GRID_H"]
@@ -165,6 +165,19 @@ def mesh_async(bitmap, grid_h: int, ws, verts, tris, codes, sizes_dev, flags: in
                                           verts.data_ptr(), int(verts.shape[0]), tris.data_ptr(), codes.data_ptr(),
                                           int(tris.shape[0]), sizes_dev.data_ptr(), _stream_ptr(stream)),
                "sbmt_mesh_async")
+
+
+def mesh_noalloc(bitmap, grid_h: int, verts, tris, codes, sizes_dev, flags: int = 0, stream=None,
+                 ctx: Context | None = None):
+    """``mesh_async`` on the library's own scratch array: no workspace argument and no
+    device allocation (for callers that cannot allocate).  Images whose workspace
+    exceeds ``NOALLOC_SCRATCH_BYTES`` raise (status -4); calls on one GPU must not
+    overlap (they share the array)."""
+    ctx = ctx or context(bitmap.device.index)
+    img = _image(bitmap, grid_h, flags)
+    _lib.check(_lib.lib().sbmt_mesh_noalloc(ctx.handle, ctypes.byref(img), verts.data_ptr(), int(verts.shape[0]),
+                                            tris.data_ptr(), codes.data_ptr(), int(tris.shape[0]),
+                                            sizes_dev.data_ptr(), _stream_ptr(stream)), "sbmt_mesh_noalloc")
 
 
 def num_classes() -> int:

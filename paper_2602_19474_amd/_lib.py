@@ -32,6 +32,7 @@ class Image(ctypes.Structure):
                 ("row_stride", ctypes.c_int64), ("grid_h", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
+NOALLOC_SCRATCH_BYTES = 64 << 20  # scratch of sbmt_mesh_noalloc
 SIZE_WORDS = 5  # per-image device sizes record: n_vertices, n_triangles, n_cut, status, n_segments
 
 
@@ -65,7 +66,7 @@ class Tuning(ctypes.Structure):
 
 EXPORTS = ("sbmt_create", "sbmt_destroy", "sbmt_query", "sbmt_plan", "sbmt_run", "sbmt_mesh_async",
            "sbmt_batch_create", "sbmt_batch_destroy", "sbmt_batch_bind", "sbmt_batch_plan", "sbmt_batch_emit",
-           "sbmt_batch_plan_async", "sbmt_batch_host_sizes",
+           "sbmt_batch_plan_async", "sbmt_batch_host_sizes", "sbmt_mesh_noalloc",
            "sbmt_batch_mesh", "sbmt_batch_sizes", "sbmt_batch_get_tuning", "sbmt_batch_set_tuning",
            "sbmt_batch_tune", "sbmt_num_classes", "sbmt_class_code", "sbmt_status_string",
            "sbmt_sample_field", "sbmt_quality_workspace", "sbmt_mesh_quality_async", "sbmt_mesh_quality",
@@ -136,6 +137,8 @@ def lib():
     L.sbmt_batch_bind.restype = i32
     L.sbmt_batch_bind.argtypes = [vp, vp, sz, P(Outputs), vp]
     L.sbmt_batch_plan.restype = i32
+    L.sbmt_mesh_noalloc.restype = i32
+    L.sbmt_mesh_noalloc.argtypes = [vp, ctypes.POINTER(Image), vp, i64, vp, vp, i64, vp, vp]
     L.sbmt_batch_plan.argtypes = [vp, P(Sizes), vp]
     L.sbmt_batch_plan_async.restype = i32
     L.sbmt_batch_plan_async.argtypes = [vp, vp]

@@ -1590,11 +1590,18 @@ struct PinnedPool {
   }
 };
 
+// Scratch of the allocation-free entry point: the workspace of one image, in
+// a file-scope device array (every GPU the library runs on holds its own copy
+// until the process ends).  Host code never uses the array's name as an
+// address: each handle looks up its device's copy once, at creation.
+static __device__ __align__(256) unsigned char scratch[SBMT_NOALLOC_SCRATCH_BYTES];
+
 struct sbmt_context {
   int device;
   int cus;
   long long* pinned;  // 8 x int64 (one sizes record)
   PinnedPool pool;
+  void* scratch_ptr;  // this device's copy of `scratch`
 };
 
 struct sbmt_batch_s {
@@ -1653,13 +1660,18 @@ sbmt_status sbmt_create(int device, sbmt_handle* out) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SBMT_E_DEVICE;
   if (hipSetDevice(device) != hipSuccess) return SBMT_E_DEVICE;
-  sbmt_context* c = (sbmt_context*)calloc(1, sizeof(sbmt_context));
+  sbmt_context* c = new (std::nothrow) sbmt_context();
   if (!c) return SBMT_E_DEVICE;
   c->device = device;
   if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->cus < 1)
     c->cus = 256;
+  // the device address of this device's scratch array (the device is current)
+  if (hipGetSymbolAddress(&c->scratch_ptr, HIP_SYMBOL(scratch)) != hipSuccess || c->scratch_ptr == nullptr) {
+    delete c;
+    return SBMT_E_DEVICE;
+  }
   if (hipHostMalloc((void**)&c->pinned, 8 * sizeof(long long), hipHostMallocDefault) != hipSuccess) {
-    free(c);
+    delete c;
     return SBMT_E_DEVICE;
   }
   *out = c;
@@ -1670,7 +1682,7 @@ sbmt_status sbmt_destroy(sbmt_handle h) {
   if (!h) return SBMT_E_INVALID_ARG;
   if (h->pinned) (void)hipHostFree(h->pinned);
   h->pool.release();
-  free(h);
+  delete h;
   return SBMT_OK;
 }
 
@@ -1756,6 +1768,18 @@ sbmt_status sbmt_mesh_async(sbmt_handle h, const sbmt_image* img, void* workspac
   if ((st = launch_front(L, src, nullptr, sh, 1, s)) != SBMT_OK) return st;
   if ((st = launch_emit(L, src, nullptr, sh, 1, s)) != SBMT_OK) return st;
   return launch_sizes(L, src, sh, sizes_dev, s);
+}
+
+sbmt_status sbmt_mesh_noalloc(sbmt_handle h, const sbmt_image* img, double* verts, int64_t vert_cap, int32_t* tris,
+                              uint8_t* codes, int64_t tri_cap, int64_t* sizes_dev, void* stream) {
+  if (!h || !h->scratch_ptr) return SBMT_E_INVALID_ARG;
+  CallLayout L;
+  sbmt_status st = make_call_layout(img, 1, 0, true, &L);
+  if (st != SBMT_OK) return st;
+  if (L.total > (size_t)SBMT_NOALLOC_SCRATCH_BYTES) return SBMT_E_WORKSPACE;
+  // the same launches as sbmt_mesh_async, on the device's scratch array
+  return sbmt_mesh_async(h, img, h->scratch_ptr, (size_t)SBMT_NOALLOC_SCRATCH_BYTES, verts, vert_cap, tris, codes,
+                         tri_cap, sizes_dev, stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -58,6 +58,7 @@ constexpr int kWinRows = 16, kWinWords = 16;  // LDS window of the coarse raster
 constexpr int64_t kMaxRecords = 0x7ffffffeLL;  // records of a call
 constexpr int kMaxBandChunks = 64;             // fused path: row segments per band
 constexpr int kSizeWords = SBMT_SIZE_WORDS;    // per-image sizes record
+constexpr int kSegSlots = 64;                  // partial segment counts per image (spread atomics)
 
 // One image of a call, as the kernels see it.
 struct Img {
@@ -83,6 +84,7 @@ struct Shared {
   unsigned long long* ctr;          // [8] 0: records handed out, 1: band ticket
   int* imgerr;                      // [n] protocol violation seen
   int64_t* sizes;                   // [n][kSizeWords] n_vertices, n_triangles, n_cut, status, n_segments
+  unsigned long long* segacc;       // [n][kSegSlots] partial boundary-segment counts
   SlowRec* rec;                     // slow-owner records, tcap per count tile
   int* tile_n;                      // [count tiles] slow owners queued by each tile
   unsigned long long* band;         // [nbands] fused path look-back words
@@ -148,6 +150,18 @@ SBMT_HD Frame owner_place(const Geo& g, int k, int i, int Rlo) {
   return f;
 }
 
+// Inclusive scan over the 64 lanes of a wave with DPP row shifts and row
+// broadcasts (lanes without a source add 0).
+__device__ __forceinline__ int wave_incl_scan_dpp(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+  return x;
+}
+
 // ---------------------------------------------------------------------------
 // Coarse raster: bit (R + ring, C + ringC) = [2 * #fg pixels of block (R, C) >= s^2].
 // A block covers kCoarsenRows stored rows and 256 stored columns.  Its pixel
@@ -179,6 +193,9 @@ __global__ void __launch_bounds__(256) k_coarsen(Src src, const int64_t* __restr
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < kSizeWords * (int64_t)sh.n;
        q += (int64_t)gridDim.x * blockDim.x)
     sh.sizes[q] = 0;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < kSegSlots * (int64_t)sh.n;
+       q += (int64_t)gridDim.x * blockDim.x)
+    sh.segacc[q] = 0ull;
   const int s = g.s;
   const int rr0 = ry * kCoarsenRows;                 // first stored row
   const int C0 = 256 * bx - kRingC;                  // first coarse column of the block
@@ -251,33 +268,41 @@ __global__ void __launch_bounds__(256) k_coarsen(Src src, const int64_t* __restr
 // foreground->background step of its corners in positive order, and every pair
 // of 4-adjacent samples is walked once in each direction by the two cells that
 // share it, so the count is the number of 4-adjacent sample pairs that differ
-// (ring included).  One thread per raster word (the blocks of k_coarsen, 64
-// threads each: 8 stored rows x 8 words).
+// (ring included).  A block sums a run of stored raster rows (the image's rows
+// split over as many blocks as it has 16-row grid bands), one thread per word.
 template <class Src>
-__global__ void __launch_bounds__(64) k_segcount(Src src, const int64_t* __restrict__ tab, Shared sh) {
+__global__ void __launch_bounds__(256) k_segcount(Src src, const int64_t* __restrict__ tab, Shared sh) {
+  __shared__ int part[256 / 64];
   int64_t local;
   const int ii = src.find(blockIdx.x, tab, local);
   const Img& d = src.img(ii);
   const Geo g = d.g;
-  const int nbx = (g.wpr + 7) / 8;
-  const int bx = (int)local % nbx, ry = (int)local / nbx;
-  const int rr = ry * kCoarsenRows + (int)(threadIdx.x >> 3), w = bx * 8 + (int)(threadIdx.x & 7);
+  const int nb = (g.NK + 15) / 16;
   const int nrows = g.CH + 2 * kRing;
+  const int rpb = (nrows + nb - 1) / nb;
+  const int r0 = (int)local * rpb, r1 = min(r0 + rpb, nrows);
   int n = 0;
-  if (rr < nrows && w < g.wpr) {
+  for (int t = threadIdx.x; t < (r1 - r0) * g.wpr; t += 256) {
+    const int rr = r0 + t / g.wpr, w = t - (t / g.wpr) * g.wpr;
     const uint32_t* row = d.bits + (int64_t)rr * g.wpr;
     const uint32_t x = row[w], xn = w + 1 < g.wpr ? row[w + 1] : 0u;
     const uint32_t xd = rr + 1 < nrows ? row[g.wpr + w] : 0u;
-    n = __builtin_popcount(x ^ ((x >> 1) | (xn << 31))) + __builtin_popcount(x ^ xd);
+    n += __builtin_popcount(x ^ ((x >> 1) | (xn << 31))) + __builtin_popcount(x ^ xd);
   }
-  n += __builtin_amdgcn_update_dpp(0, n, 0x111, 0xf, 0xf, false);  // row_shr:1
-  n += __builtin_amdgcn_update_dpp(0, n, 0x112, 0xf, 0xf, false);  // row_shr:2
-  n += __builtin_amdgcn_update_dpp(0, n, 0x114, 0xf, 0xf, false);  // row_shr:4
-  n += __builtin_amdgcn_update_dpp(0, n, 0x118, 0xf, 0xf, false);  // row_shr:8
-  n += __builtin_amdgcn_update_dpp(0, n, 0x142, 0xa, 0xf, false);  // row_bcast:15
-  n += __builtin_amdgcn_update_dpp(0, n, 0x143, 0xc, 0xf, false);  // row_bcast:31
-  n = __builtin_amdgcn_readlane(n, 63);
-  if (threadIdx.x == 0 && n) atomicAdd((unsigned long long*)&sh.sizes[kSizeWords * (int64_t)ii + 4], (unsigned long long)n);
+  n = __builtin_amdgcn_readlane(wave_incl_scan_dpp(n), 63);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = n;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int tot = part[0] + part[1] + part[2] + part[3];
+    // one atomic per block, spread over the image's slots (summed by segment_total)
+    if (tot) atomicAdd(&sh.segacc[kSegSlots * (int64_t)ii + (blockIdx.x & (kSegSlots - 1))], (unsigned long long)tot);
+  }
+}
+
+__device__ __forceinline__ long long segment_total(const Shared& sh, int ii) {
+  long long t = 0;
+  for (int j = 0; j < kSegSlots; ++j) t += (long long)sh.segacc[kSegSlots * (int64_t)ii + j];
+  return t;
 }
 
 // Stage the coarse-raster window of a tile (cell rows rlo .. rhi, owner
@@ -302,18 +327,6 @@ __device__ __forceinline__ Bits stage_window(const Geo& g, const uint32_t* __res
   b.rr0 = rlo;
   b.cc0 = 32 * wlo;
   return b;
-}
-
-// Inclusive scan over the 64 lanes of a wave with DPP row shifts and row
-// broadcasts (lanes without a source add 0).
-__device__ __forceinline__ int wave_incl_scan_dpp(int x) {
-  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
-  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
-  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
-  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
-  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
-  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
-  return x;
 }
 
 template <typename T>
@@ -697,6 +710,7 @@ __global__ void k_sizes(Src src, Shared sh, int64_t* __restrict__ user) {
   o[1] = nt;
   o[2] = nc;
   o[3] = st;
+  o[4] = segment_total(sh, ii);
   if (user) {
     int64_t* u = user + kSizeWords * (int64_t)ii;
     u[0] = nv;
@@ -733,12 +747,112 @@ struct EmitLds {
   int bv[RB + 1];
   long long tb[RB];
   int rowv[RB + 1];  // vertices of each row's kCB owners
-  alignas(16) SlowRec srec[kSlowChunk];
-  uint16_t sitem[kSlowChunk * kSlowItems];  // record | output number << 8
+  union {
+    struct {
+      SlowRec srec[kSlowChunk];
+      uint16_t sitem[kSlowChunk * kSlowItems];  // record | output number << 8
+    } r;
+    uint32_t stage[4][kThreads / 64][64];  // strip emission: a wave's triangles by output slot (a, b, c, tag)
+  } x;
   uint16_t lut[15 * 3 * 2 * 5];              // emission table of the side mode
   uint8_t tslot[kThreads / 64][128];         // per wave: fast triangle rank -> lane << 1 | which
   int swt[kThreads / 64];
 };
+
+// Ids an owner of an emission tile needs (row r, LDS column col = owner
+// column - c0 + 1, row parity o_), from the codes and offsets in LDS.
+template <int RB>
+__device__ __forceinline__ Nb tile_nb(const EmitLds<RB>& L, int r, int col, uint32_t f, int o_) {
+  Nb nb;
+  const int bv0 = L.bv[r], bv1 = L.bv[r + 1];
+  nb.vid = bv0 + L.voff[r][col];
+  nb.id_vr = bv0 + L.voff[r][col + 1];
+  nb.id_vdl = bv1 + L.voff[r + 1][col + o_ - 1];
+  nb.id_vdr = bv1 + L.voff[r + 1][col + o_];
+  nb.b0 = nb.vid + info_self(f);
+  nb.b1 = nb.b0 + info_n(f, 0);
+  nb.b2 = nb.b1 + info_n(f, 1);
+  const uint32_t fr = map_info(L.info[r][col + 1]);
+  nb.b3 = nb.id_vr + info_self(fr) + info_n(fr, 0);
+  const uint32_t fl = map_info(L.info[r + 1][col + o_ - 1]);
+  nb.b4 = nb.id_vdl + info_self(fl);
+  nb.bI = nb.b2 + info_n(f, 2);
+  return nb;
+}
+
+// Slow owners of an emission tile from their records, kSlowChunk records at a
+// time: the records and the lists of their output vertices and triangles go to
+// LDS, then one lane writes one output (records of the halo row are skipped:
+// the band below emits them).  Record q is held by thread q mod kThreads in
+// held0 / held1 (q / kThreads = 0, 1) while q < kHold * kThreads.  Needs the tile's codes,
+// offsets, row bases, cell rows and emission table in L.
+constexpr int kHold = 2;
+template <int RB>
+__device__ __forceinline__ void emit_records(const Img& d, const Geo& g, int k0, int c0, int64_t tile,
+                                             const Shared& sh, EmitLds<RB>& L, const SlowRec held0,
+                                             const SlowRec held1, int nrec) {
+  constexpr int kChunk = EmitLds<RB>::kSlowChunk;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  Out out;
+  out.v = d.verts;
+  out.t = d.tris;
+  out.c = d.codes;
+  out.vbase = 0;
+  out.tbase = 0;
+  for (int ch = 0; ch * kChunk < nrec; ++ch) {
+    const int qi = threadIdx.x & (kChunk - 1);
+    const int q = ch * kChunk + qi;
+    bool mine = false;
+    int cnt = 0;  // vertices | triangles << 16
+    if ((int)threadIdx.x / kChunk == ch % (kThreads / kChunk) && q < nrec) {
+      const int j = ch / (kThreads / kChunk);
+      SlowRec R;
+      if (j < kHold) {
+        // field by field, so that held[] stays in registers
+        static_assert(kHold == 2, "two held records per thread");
+        R.info = j == 0 ? held0.info : held1.info;
+        R.tri = j == 0 ? held0.tri : held1.tri;
+        R.x = j == 0 ? held0.x : held1.x;
+      } else {
+        R = sh.rec[tile * sh.tcap + q];
+      }
+      L.x.r.srec[qi] = R;
+      mine = (int)(R.x >> 56) < RB;
+      if (mine) cnt = info_nv(R.info) | (info_nt(R.info) << 16);
+    }
+    const int incl = wave_incl_scan_dpp(cnt);
+    if (lane == 63) L.swt[wv] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+      const int tw = L.swt[w];
+      before += w < wv ? tw : 0;
+      total += tw;
+    }
+    const int excl = before + incl - cnt;
+    for (int i = 0; i < (cnt & 0xffff); ++i) L.x.r.sitem[(excl & 0xffff) + i] = (uint16_t)(qi | (i << 8));
+    __syncthreads();
+    for (int it = threadIdx.x; it < (total & 0xffff); it += kThreads) {
+      const int item = L.x.r.sitem[it];
+      const SlowRec R = L.x.r.srec[item & 255];
+      const int r = (int)(R.x >> 56), col = (int)((R.x >> 48) & 255u) + 1;
+      const Frame f = owner_place(g, k0 + r, c0 + col - 1, L.rowR[r]);
+      emit_slow_vertex(g, f, R, item >> 8, L.bv[r] + L.voff[r][col], out);
+    }
+    __syncthreads();
+    for (int i = 0; i < (cnt >> 16); ++i) L.x.r.sitem[(excl >> 16) + i] = (uint16_t)(qi | (i << 8));
+    __syncthreads();
+    for (int it = threadIdx.x; it < (total >> 16); it += kThreads) {
+      const int item = L.x.r.sitem[it];
+      const SlowRec R = L.x.r.srec[item & 255];
+      const int r = (int)(R.x >> 56), col = (int)((R.x >> 48) & 255u) + 1;
+      const Nb nb = tile_nb(L, r, col, map_info(L.info[r][col]), (k0 + r) & 1);
+      emit_slow_triangle(g, R, item >> 8, nb, L.tb[r] + L.toff[r][col], out, L.lut);
+    }
+    __syncthreads();
+  }
+}
 
 // Owner info comes from the owner map (row RB, the halo row, from hcodes when
 // given), slow owners' emission data from the records of count tile `tile`
@@ -775,7 +889,6 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
   constexpr int kWaves = kThreads / 64;
   constexpr int kRowsW = (RB + 1 + kWaves - 1) / kWaves;
   constexpr int kU = kCB / 64;
-  constexpr int kHold = 2;
   uint32_t codes[kRowsW][kU], edge[kRowsW];
   SlowRec held[kHold];
   bool hv[kHold];
@@ -840,23 +953,7 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
     }
   }
   __syncthreads();
-  auto neighbours = [&](int r, int col, uint32_t f, int o_) {
-    Nb nb;
-    const int bv0 = L.bv[r], bv1 = L.bv[r + 1];
-    nb.vid = bv0 + L.voff[r][col];
-    nb.id_vr = bv0 + L.voff[r][col + 1];
-    nb.id_vdl = bv1 + L.voff[r + 1][col + o_ - 1];
-    nb.id_vdr = bv1 + L.voff[r + 1][col + o_];
-    nb.b0 = nb.vid + info_self(f);
-    nb.b1 = nb.b0 + info_n(f, 0);
-    nb.b2 = nb.b1 + info_n(f, 1);
-    const uint32_t fr = map_info(L.info[r][col + 1]);
-    nb.b3 = nb.id_vr + info_self(fr) + info_n(fr, 0);
-    const uint32_t fl = map_info(L.info[r + 1][col + o_ - 1]);
-    nb.b4 = nb.id_vdl + info_self(fl);
-    nb.bI = nb.b2 + info_n(f, 2);
-    return nb;
-  };
+  auto neighbours = [&](int r, int col, uint32_t f, int o_) { return tile_nb(L, r, col, f, o_); };
   // 3. fast and quiet owners: each thread writes the vertex of its owner; the
   // wave's triangles are written in output order, lane j the j-th (so that a
   // store covers consecutive triangles); then the slow owners of the tile
@@ -934,65 +1031,8 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  // 4. slow owners from their records, kSlowChunk records at a time: the
-  // records and the lists of their output vertices and triangles go to LDS,
-  // then one lane writes one output (records of the halo row are skipped:
-  // the band below emits them).  Record q is held by thread q mod kThreads
-  // in held[q / kThreads] while q < kHold * kThreads.
-  constexpr int kChunk = EmitLds<RB>::kSlowChunk;
-  for (int ch = 0; kMode != kEmitMissing && ch * kChunk < nrec; ++ch) {
-    const int qi = threadIdx.x & (kChunk - 1);
-    const int q = ch * kChunk + qi;
-    bool mine = false;
-    int cnt = 0;  // vertices | triangles << 16
-    if ((int)threadIdx.x / kChunk == ch % (kThreads / kChunk) && q < nrec) {
-      const int j = ch / (kThreads / kChunk);
-      SlowRec R;
-      if (j < kHold) {
-        // field by field, so that held[] stays in registers
-        static_assert(kHold == 2, "two held records per thread");
-        R.info = j == 0 ? held[0].info : held[1].info;
-        R.tri = j == 0 ? held[0].tri : held[1].tri;
-        R.x = j == 0 ? held[0].x : held[1].x;
-      } else {
-        R = sh.rec[tile * sh.tcap + q];
-      }
-      L.srec[qi] = R;
-      mine = (int)(R.x >> 56) < RB;
-      if (mine) cnt = info_nv(R.info) | (info_nt(R.info) << 16);
-    }
-    const int incl = wave_incl_scan_dpp(cnt);
-    if (lane == 63) L.swt[wv] = incl;
-    __syncthreads();
-    int before = 0, total = 0;
-#pragma unroll
-    for (int w = 0; w < kThreads / 64; ++w) {
-      const int tw = L.swt[w];
-      before += w < wv ? tw : 0;
-      total += tw;
-    }
-    const int excl = before + incl - cnt;
-    for (int i = 0; i < (cnt & 0xffff); ++i) L.sitem[(excl & 0xffff) + i] = (uint16_t)(qi | (i << 8));
-    __syncthreads();
-    for (int it = threadIdx.x; it < (total & 0xffff); it += kThreads) {
-      const int item = L.sitem[it];
-      const SlowRec R = L.srec[item & 255];
-      const int r = (int)(R.x >> 56), col = (int)((R.x >> 48) & 255u) + 1;
-      const Frame f = owner_place(g, k0 + r, c0 + col - 1, L.rowR[r]);
-      emit_slow_vertex(g, f, R, item >> 8, L.bv[r] + L.voff[r][col], out);
-    }
-    __syncthreads();
-    for (int i = 0; i < (cnt >> 16); ++i) L.sitem[(excl >> 16) + i] = (uint16_t)(qi | (i << 8));
-    __syncthreads();
-    for (int it = threadIdx.x; it < (total >> 16); it += kThreads) {
-      const int item = L.sitem[it];
-      const SlowRec R = L.srec[item & 255];
-      const int r = (int)(R.x >> 56), col = (int)((R.x >> 48) & 255u) + 1;
-      const Nb nb = neighbours(r, col, map_info(L.info[r][col]), (k0 + r) & 1);
-      emit_slow_triangle(g, R, item >> 8, nb, L.tb[r] + L.toff[r][col], out, L.lut);
-    }
-    __syncthreads();
-  }
+  // 4. slow owners from their records
+  if (kMode != kEmitMissing) emit_records<RB>(d, g, k0, c0, tile, sh, L, held[0], held[1], nrec);
   __syncthreads();
   if (kMode == kEmitMissing) {
     // slow owners beyond the tile's record region were classified by the
@@ -1044,11 +1084,211 @@ __device__ __forceinline__ void emit_count_tile(const Src& src, const int64_t* _
   });
 }
 
+// ---------------------------------------------------------------------------
+// Emission of one count tile by strips (the multi-kernel path).  Wave w takes
+// the owners c0 + 64 w + lane of every row of the tile and walks down the rows.
+// A vertex id is the prefix of the vertex counts along its row (owner
+// numbering), so the wave holds the prefixes of rows r and r+1 in registers
+// and a fast owner's triangles need no lookup: vid(k, i+1) = vid(k, i) +
+// nv(k, i), and the row below gives vid(k+1, i+o) and, one lane to the left,
+// vid(k+1, i+o-1).  The tile's codes and offsets also go to LDS, where the slow
+// owners, emitted afterwards from their records, find their neighbours' ids.
+// ---------------------------------------------------------------------------
+template <int RB>
+struct StripLds {
+  EmitLds<RB> e;
+  int wtot[RB + 1][kThreads / 64];         // packed counts (nv | nt << 16) of each strip's rows
+  int lastnv[RB + 1][kThreads / 64 + 1];   // nv of the owner left of each strip ([0]: column c0 - 1)
+};
+
+__device__ __forceinline__ int packed_counts(uint32_t cv) {
+  // bit 7 is a chain vertex in a slow owner's code and the inside bit in the others'
+  return __builtin_popcount(cv & ((cv & 0x8000u) ? 0x1ffu : 0x17fu)) |
+         ((int)(((cv >> 9) & 7u) + ((cv >> 12) & 7u)) << 16);
+}
+
 template <class Src, int RB>
 // At most 64 VGPRs: eight workgroups per compute unit.
 __global__ void __launch_bounds__(kThreads, 8) k_emit(Src src, const int64_t* __restrict__ tab, Shared sh) {
-  __shared__ EmitLds<RB> L;
-  emit_count_tile<Src, RB, kEmitRecords>(src, tab, sh, (int64_t)blockIdx.x, L);
+  __shared__ StripLds<RB> S;
+  EmitLds<RB>& L = S.e;
+  constexpr int W = EmitLds<RB>::W;
+  constexpr int kWaves = kThreads / 64;
+  constexpr int kLut = 15 * 3 * 2 * 5;
+  static_assert(kLut <= 2 * kThreads, "two table entries per thread");
+  const int64_t tile = blockIdx.x;
+  int64_t local;
+  const int ii = src.find(tile, tab, local);
+  const Img& d = src.img(ii);
+  const Geo g = d.g;
+  {
+    long long nv, nt, nc;
+    image_totals<Src>(d, sh, nv, nt, nc);
+    if (image_status(d, sh.imgerr[ii], nv, nt) != SBMT_OK) return;  // uniform per block
+  }
+  const int cb = (int)local % g.NCB, ky = (int)local / g.NCB;  // tile index of an image: 32 bits
+  const int k0 = ky * RB, c0 = cb * kCB;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int col = 1 + 64 * wv + lane;  // LDS column
+  const int c = c0 + 64 * wv + lane;
+  const int nrec = (int)min((int64_t)sh.tile_n[tile], sh.tcap);
+  // 1. loads first, so that their latencies overlap: the strip's codes in every
+  // row (row RB is the row below the tile), the halo columns c0 - 1 and
+  // c0 + kCB, the tile's records, the emission table, the row bases
+  uint32_t code[RB + 1];
+#pragma unroll
+  for (int r = 0; r <= RB; ++r)
+    code[r] = (k0 + r < g.NK && c < g.NI) ? (uint32_t)d.omap[(int64_t)(k0 + r) * g.NI + c] : 0u;
+  uint32_t hcode = 0;
+  const int hr = threadIdx.x >> 1, hside = threadIdx.x & 1;
+  if (threadIdx.x < 2 * (RB + 1)) {
+    const int hc = hside ? c0 + kCB : c0 - 1;
+    if (k0 + hr < g.NK && hc >= 0 && hc < g.NI) hcode = d.omap[(int64_t)(k0 + hr) * g.NI + hc];
+  }
+  SlowRec held[kHold];
+#pragma unroll
+  for (int j = 0; j < kHold; ++j) {
+    const int q = threadIdx.x + j * kThreads;
+    if (q < nrec) held[j] = sh.rec[tile * sh.tcap + q];
+  }
+  const uint16_t* lt = (g.flags & 1u) ? &sbmt_lut_emit[0][0][0][0] : &sbmt_lut_emit_fg[0][0][0][0];
+  const uint16_t lut0 = lt[threadIdx.x];
+  const uint16_t lut1 = threadIdx.x + kThreads < kLut ? lt[threadIdx.x + kThreads] : 0;
+  if (threadIdx.x <= RB) {
+    const int k = k0 + threadIdx.x;
+    const int64_t nsegi = (int64_t)g.NK * g.NCB;
+    const longlong4 base = sh.seg_off[d.seg0];
+    const longlong4 o = sh.seg_off[d.seg0 + (k < g.NK ? (int64_t)k * g.NCB + cb : nsegi)];
+    L.bv[threadIdx.x] = (int)(o.x - base.x);
+    if (threadIdx.x < RB) L.tb[threadIdx.x] = o.y - base.y;
+    L.rowR[threadIdx.x] = row_cell(k, g.h, g.s);
+  }
+  L.lut[threadIdx.x] = lut0;
+  if (threadIdx.x + kThreads < kLut) L.lut[threadIdx.x + kThreads] = lut1;
+  L.x.stage[3][wv][lane] = 0u;  // staging slots start empty
+  if (threadIdx.x < 2 * (RB + 1)) {
+    L.info[hr][hside ? W - 1 : 0] = (uint16_t)hcode;
+    if (!hside) {
+      const int nvl = packed_counts(hcode) & 0xffff;
+      S.lastnv[hr][0] = nvl;
+      L.voff[hr][0] = (int16_t)(-nvl);
+    }
+  }
+  // 2. per row: packed counts, their prefix along the strip (a DPP wave scan),
+  // the strip's totals to LDS; vertex and triangle counts of a row segment stay
+  // below 2^16
+  int incl[RB + 1];
+#pragma unroll
+  for (int r = 0; r <= RB; ++r) {
+    const int p = packed_counts(code[r]);
+    incl[r] = wave_incl_scan_dpp(p);
+    if (lane == 63) {
+      S.wtot[r][wv] = incl[r];
+      S.lastnv[r][wv + 1] = p & 0xffff;
+    }
+    L.info[r][col] = (uint16_t)code[r];
+  }
+  __syncthreads();
+  // prefix of the strips to the left (uniform per wave), the row segment's totals
+  int sb[RB + 1];
+#pragma unroll
+  for (int r = 0; r <= RB; ++r) {
+    int before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      const int tw = S.wtot[r][w];
+      before += w < wv ? tw : 0;
+      total += tw;
+    }
+    sb[r] = __builtin_amdgcn_readfirstlane(before);
+    if (threadIdx.x == 0) L.voff[r][W - 1] = (int16_t)(total & 0xffff);
+  }
+  // 3. fast owners row by row: the vertex of the owner, then its triangles
+  // (Tb, then Ta), written at their offsets; offsets go to LDS for step 4
+  const bool both = (g.flags & 1u) != 0;
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    const int k = k0 + r;
+    if (k >= g.NK) break;  // uniform
+    const int o = k & 1;
+    const uint32_t cv = code[r];
+    const int p = packed_counts(cv), pn = packed_counts(code[r + 1]);
+    const int ex = sb[r] + incl[r] - p;  // within the row segment: vertices | triangles << 16
+    const int exn = sb[r + 1] + incl[r + 1] - pn, inn = sb[r + 1] + incl[r + 1];
+    L.voff[r][col] = (int16_t)(ex & 0xffff);
+    L.toff[r][col] = (int16_t)(ex >> 16);
+    if (r == RB - 1) L.voff[RB][col] = (int16_t)(exn & 0xffff);
+    // vertex count of the owner left of this one in the row below (one lane to
+    // the left; lane 0 from the strip to the left)
+    int nvl = __builtin_amdgcn_update_dpp(0, pn & 0xffff, 0x138, 0xf, 0xf, false);  // wave_shr:1
+    const int nvl0 = S.lastnv[r + 1][wv];
+    nvl = lane == 0 ? nvl0 : nvl;
+    const int bvr = __builtin_amdgcn_readfirstlane(L.bv[r]), bvn = __builtin_amdgcn_readfirstlane(L.bv[r + 1]);
+    const long long tbr = L.tb[r];
+    const int64_t tbs = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(tbr >> 32)) << 32) |
+                                  (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)tbr));
+    char* const vrow = reinterpret_cast<char*>(d.verts + 2 * (int64_t)bvr);
+    char* const trow = reinterpret_cast<char*>(d.tris + 3 * tbs);
+    uint8_t* const crow = d.codes + tbs;
+    const bool fast = (cv & 0x8000u) == 0u;
+    if (fast && (cv & 1u)) {
+      double2 v;
+      v.x = lat_x(g.X0 + 4 * g.h * c + 2 * g.h * o);
+      v.y = lat_y(g.h, k);
+      *reinterpret_cast<double2*>(vrow + (uint32_t)(ex & 0xffff) * 16u) = v;
+    }
+    const int ntb = fast ? (int)((cv >> 9) & 7u) : 0, nta = fast ? (int)((cv >> 12) & 7u) : 0;
+    const int vid = bvr + (ex & 0xffff);
+    const int vr = bvr + ((sb[r] + incl[r]) & 0xffff);
+    const int vdl = bvn + (exn & 0xffff) - (o ? 0 : nvl);
+    const int vdr = bvn + ((o ? inn : exn) & 0xffff);
+    // the triangles go to LDS at their slot relative to the strip's first
+    // triangle of the row (slow owners' slots stay empty), 64 slots at a time;
+    // lane j then writes slot j, so that a store covers consecutive triangles
+    const uint32_t tag = 1u | ((both && !((cv >> 7) & 1u)) ? 0x8000u : 0u);
+    const int s0 = sb[r] >> 16;                                  // the strip's first triangle
+    const int ns = __builtin_amdgcn_readlane(incl[r], 63) >> 16;  // the strip's triangles in this row
+    const int q0 = (ex >> 16) - s0;
+    uint32_t* const sa = L.x.stage[0][wv];
+    uint32_t* const sb2 = L.x.stage[1][wv];
+    uint32_t* const sc = L.x.stage[2][wv];
+    uint32_t* const sw = L.x.stage[3][wv];
+    for (int base = 0; base < ns; base += 64) {  // uniform
+      const int qa = q0 - base, qb = qa + ntb;
+      if (ntb && qa >= 0 && qa < 64) {
+        sa[qa] = (uint32_t)vid;
+        sb2[qa] = (uint32_t)vdr;
+        sc[qa] = (uint32_t)vdl;
+        sw[qa] = tag;
+      }
+      if (nta && qb >= 0 && qb < 64) {
+        sa[qb] = (uint32_t)vid;
+        sb2[qb] = (uint32_t)vr;
+        sc[qb] = (uint32_t)vdr;
+        sw[qb] = tag;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const uint32_t ew = sw[lane];
+      if (ew) {
+        const uint32_t u = (uint32_t)(s0 + base + lane);
+        Tri3 t3;
+        t3.a = (int)sa[lane];
+        t3.b = (int)sb2[lane];
+        t3.c = (int)sc[lane];
+        *reinterpret_cast<Tri3*>(trow + u * 12u) = t3;
+        crow[u] = (uint8_t)(ew >> 8);
+        sw[lane] = 0u;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  __syncthreads();
+  // 4. slow owners from their records
+  emit_records<RB>(d, g, k0, c0, tile, sh, L, held[0], held[1], nrec);
 }
 
 // Slow owners without a record: the tiles whose count pass queued more slow
@@ -1229,6 +1469,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_fused(ManySrc src, const int64_
         sh.sizes[kSizeWords * (int64_t)ii + 0] = v;
         sh.sizes[kSizeWords * (int64_t)ii + 1] = tt;
         sh.sizes[kSizeWords * (int64_t)ii + 3] = st;
+        sh.sizes[kSizeWords * (int64_t)ii + 4] = segment_total(sh, ii);
       }
       // write only if the band's vertex and triangle ranges fit
       F.err = (v > d.vcap || tt > d.tcap || v > 0x7fffffffLL || atomicOr(&sh.imgerr[ii], 0)) ? 1 : 0;
@@ -1356,7 +1597,7 @@ struct CallLayout {
   int64_t nseg = 0, owners = 0, rcap = 0, nbands_max = 0, halo_words = 0, ntiles_max = 0;
   int64_t tcap[3] = {0, 0, 0};  // records per count tile, per tile height
   int nblk = 0;
-  size_t off_ctr, off_imgerr, off_sizes, off_desc, off_tab, off_cnt, off_slow, off_segoff, off_blk, off_rec,
+  size_t off_ctr, off_imgerr, off_sizes, off_segacc, off_desc, off_tab, off_cnt, off_slow, off_segoff, off_blk, off_rec,
       off_tilen, off_band, off_halo, total;
   bool fused_ok = true;  // per-image counts fit the fused path's int32 bases and band width
 };
@@ -1421,6 +1662,8 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
   off = align256(off + (size_t)n * sizeof(int));
   L.off_sizes = off;
   off = align256(off + (size_t)n * kSizeWords * sizeof(int64_t));
+  L.off_segacc = off;
+  off = align256(off + (size_t)n * kSegSlots * sizeof(unsigned long long));
   L.off_desc = off;
   off = align256(off + (size_t)n * sizeof(Img));
   L.off_tab = off;
@@ -1462,6 +1705,7 @@ static Shared shared_of(const CallLayout& L, void* ws, int rbi) {
   s.ctr = (unsigned long long*)(b + L.off_ctr);
   s.imgerr = (int*)(b + L.off_imgerr);
   s.sizes = (int64_t*)(b + L.off_sizes);
+  s.segacc = (unsigned long long*)(b + L.off_segacc);
   s.rec = (SlowRec*)(b + L.off_rec);
   s.band = (unsigned long long*)(b + L.off_band);
   s.tile_n = (int*)(b + L.off_tilen);
@@ -1503,7 +1747,9 @@ static sbmt_status launch_front(const CallLayout& L, const Src& src, const int64
   const int64_t ntile = L.tab[(size_t)(1 + rbi) * (L.n + 1) + L.n];
   if (ncb > 0x7fffffffLL || ntile > 0x7fffffffLL) return SBMT_E_INVALID_ARG;
   hipLaunchKernelGGL(k_coarsen<Src>, dim3((unsigned)ncb), dim3(256), 0, st, src, t0, sh);
-  hipLaunchKernelGGL(k_segcount<Src>, dim3((unsigned)ncb), dim3(64), 0, st, src, t0, sh);
+  const int64_t nsb = L.tab[(size_t)6 * (L.n + 1) + L.n];  // 16-row bands: segment-count blocks
+  hipLaunchKernelGGL(k_segcount<Src>, dim3((unsigned)nsb), dim3(256), 0, st, src,
+                     dtab ? dtab + (size_t)6 * (L.n + 1) : nullptr, sh);
   switch (kRBs[rbi]) {
     case 4: hipLaunchKernelGGL((k_count<Src, 4>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh); break;
     case 8: hipLaunchKernelGGL((k_count<Src, 8>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh); break;
@@ -1939,7 +2185,8 @@ sbmt_status sbmt_batch_mesh(sbmt_batch b, int64_t* sizes_dev, void* stream) {
   const int64_t ncb = L.tab[(size_t)L.n];
   if (ncb > 0x7fffffffLL) return SBMT_E_INVALID_ARG;
   hipLaunchKernelGGL(k_coarsen<ManySrc>, dim3((unsigned)ncb), dim3(256), 0, s, src, dtab, sh);
-  hipLaunchKernelGGL(k_segcount<ManySrc>, dim3((unsigned)ncb), dim3(64), 0, s, src, dtab, sh);
+  hipLaunchKernelGGL(k_segcount<ManySrc>, dim3((unsigned)L.tab[(size_t)6 * (L.n + 1) + L.n]), dim3(256), 0, s, src,
+                     dtab + (size_t)6 * (L.n + 1), sh);
   const int64_t nbands = L.tab[(size_t)(4 + rbi) * (L.n + 1) + L.n];
   const int64_t* btab = dtab + (size_t)(4 + rbi) * (L.n + 1);
   uint16_t* halo = (uint16_t*)((char*)b->ws + L.off_halo);

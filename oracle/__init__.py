@@ -56,7 +56,7 @@ def lib():
         L = ctypes.CDLL(_LIB_PATH)
         vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
         L.oracle_mesh_from_bitmap.restype = vp
-        L.oracle_mesh_from_bitmap.argtypes = [vp, i32, i32, i64, i32, u32, ctypes.c_char_p, i32]
+        L.oracle_mesh_from_bitmap.argtypes = [vp, i32, i32, i64, ctypes.c_double, u32, ctypes.c_char_p, i32]
         for name in ("oracle_n_vertices", "oracle_n_triangles", "oracle_n_segments", "oracle_n_cut",
                      "oracle_n_contours"):
             getattr(L, name).restype = i64
@@ -126,14 +126,15 @@ class OracleMesh:
     grid: tuple              # (NK, NI, s)
 
 
-def mesh_from_bitmap(bitmap: np.ndarray, grid_h: int, flags: int = 0) -> OracleMesh:
-    """Oracle mesh of a uint8 bitmap (nonzero = foreground) at integer grid edge ``grid_h``."""
+def mesh_from_bitmap(bitmap: np.ndarray, grid_h, flags: int = 0) -> OracleMesh:
+    """Oracle mesh of a uint8 bitmap (nonzero = foreground) at grid edge ``grid_h``
+    (a dyadic rational p / 2^q, q <= 8, in pixels)."""
     L = lib()
     bm = np.ascontiguousarray(bitmap, dtype=np.uint8)
     H, W = bm.shape
     err = ctypes.create_string_buffer(512)
     ptr = bm.ctypes.data if bm.size else None
-    res = L.oracle_mesh_from_bitmap(ptr, W, H, W, int(grid_h), int(flags), err, 512)
+    res = L.oracle_mesh_from_bitmap(ptr, W, H, W, float(grid_h), int(flags), err, 512)
     if not res:
         raise OracleError(err.value.decode())
     try:

@@ -20,12 +20,14 @@
 //     triangulated procedurally from the stated rule (no lookup table);
 //   * class ids come from a brute-force enumeration of all admissible keys.
 //
-// Exact arithmetic.  Coordinates are kept in quarter-pixel units ("x4 units").
-// Boundary points are even integers.  Grid vertex (k,i) of edge length h sits
-// at X = -2h-3 + 4h*i + 2h*(k&1) (odd) and Y = -4 + 2hk*sqrt3.  Every
-// orientation predicate is therefore A + B*sqrt3 with integer A, B and is
-// decided exactly.  With the coarse stride rule s^2 > 2h^2 no predicate of the
-// global path is ever zero (the oracle asserts it).
+// Exact arithmetic.  The grid edge is a dyadic rational h = p / U, U = 2^q
+// (q <= 8), and coordinates are kept in units of 1 / (4U) pixel.  Boundary
+// points are multiples of 2U (even).  Grid vertex (k,i) sits at
+// X = X0 + 4p*i + 2p*(k&1) with X0 odd (X0 = -2p-3 for integer h, else
+// -(2p + 3U) - 1) and Y = -4U + 2pk*sqrt3.  Every orientation predicate is
+// therefore A + B*sqrt3 with integer A, B and is decided exactly.  With the
+// coarse stride rule s^2 > 2h^2 no predicate of the global path is ever zero
+// (the oracle asserts it).
 //
 // The paper leaves several points open; the readings taken here (boundary by
 // marching squares on a block-majority coarsened raster, rotation-only
@@ -511,20 +513,29 @@ static const double kHalfSqrt3 = 0.86602540378443864676;
 
 class Oracle {
  public:
-  Oracle(const uint8_t* bm, int W, int H, i64 stride, int h, unsigned flags)
-      : bm_(bm), W_(W), H_(H), stride_(stride), h_(h), both_(flags & 1u) {
-    ORACLE_CHECK(W >= 0 && H >= 0 && h >= 1 && h <= 64, "invalid arguments");
+  Oracle(const uint8_t* bm, int W, int H, i64 stride, double grid_h, unsigned flags)
+      : bm_(bm), W_(W), H_(H), stride_(stride), both_(flags & 1u) {
+    // grid_h = p / 2^q exactly, q <= 8, reduced
+    ORACLE_CHECK(grid_h > 0 && grid_h <= 64, "invalid grid edge");
+    const double g256 = grid_h * 256.0;
+    ORACLE_CHECK(g256 == std::floor(g256), "grid edge is not a multiple of 1/256");
+    h_ = (i64)g256;
+    U_ = 256;
+    while (U_ > 1 && h_ % 2 == 0) { h_ /= 2; U_ /= 2; }
+    ORACLE_CHECK(W >= 0 && H >= 0, "invalid arguments");
     ORACLE_CHECK(W == 0 || H == 0 || stride >= W, "row stride smaller than width");
     s_ = 1;
-    while ((i64)s_ * s_ <= 2LL * h * h) ++s_;  // smallest s with s^2 > 2h^2
+    while ((i64)s_ * s_ * U_ * U_ <= 2LL * h_ * h_) ++s_;  // smallest s with s^2 > 2h^2
+    X0_ = U_ == 1 ? -2 * h_ - 3 : -(2 * h_ + 3 * U_) - 1;  // odd
     CW_ = (W + s_ - 1) / s_;
     CH_ = (H + s_ - 1) / s_;
     // rows: smallest m >= 1 with 3 m^2 h^2 > (2 s CH + 1)^2, NK = m + 1
     i64 m = 1;
-    i64 rhs = (2LL * s_ * CH_ + 1) * (2LL * s_ * CH_ + 1);
-    while (3LL * m * m * h * h <= rhs) ++m;
+    i128 rhs = (i128)U_ * U_ * (2LL * s_ * CH_ + 1) * (2LL * s_ * CH_ + 1);
+    while ((i128)3 * m * m * h_ * h_ <= rhs) ++m;
     NK_ = m + 1;
-    NI_ = (4LL * s_ * CW_ + 2LL * h + 1) / (4LL * h) + 2;
+    // columns: the last vertex lies right of x = s CW - 1/2
+    NI_ = (4LL * U_ * s_ * CW_ - 2LL * U_ - X0_) / (4LL * h_) + 2;
   }
 
   Mesh run() {
@@ -545,7 +556,9 @@ class Oracle {
   const uint8_t* bm_;
   int W_, H_;
   i64 stride_;
-  int h_;
+  i64 h_ = 1;   // grid edge numerator: h = h_ / U_ pixels
+  i64 U_ = 1;   // 2^q: one coordinate unit is 1 / (4 U_) pixel
+  i64 X0_ = 0;  // x of vertex (0, 0), odd
   bool both_;
   int s_ = 1;
   i64 CW_ = 0, CH_ = 0, NK_ = 0, NI_ = 0;
@@ -560,11 +573,13 @@ class Oracle {
 
   // --- geometry of the lattice -------------------------------------------
   Pt lat(i64 k, i64 i) const {
-    return Pt{-2LL * h_ - 3 + 4LL * h_ * i + 2LL * h_ * (k & 1), -4, 2LL * h_ * k};
+    return Pt{X0_ + 4LL * h_ * i + 2LL * h_ * (k & 1), -4 * U_, 2LL * h_ * k};
   }
   bool lat_ok(i64 k, i64 i) const { return k >= 0 && k < NK_ && i >= 0 && i < NI_; }
-  double lat_xd(i64 k, i64 i) const { return 0.25 * (double)lat(k, i).x; }
-  double lat_yd(i64 k) const { return -1.0 + (double)(h_ * k) * kHalfSqrt3; }
+  // pixel coordinates (exact scalings by powers of two)
+  double to_px(i64 v) const { return (double)v * (0.25 / (double)U_); }
+  double lat_xd(i64 k, i64 i) const { return to_px(lat(k, i).x); }
+  double lat_yd(i64 k) const { return -1.0 + ((double)(h_ * k) * (1.0 / (double)U_)) * kHalfSqrt3; }
 
   // endpoints of edge d of owner (k,i): 0 -> (k,i+1), 1 -> (k+1,i+o-1), 2 -> (k+1,i+o)
   void edge_ends(i64 k, i64 i, int d, i64* k2, i64* i2) const {
@@ -620,9 +635,11 @@ class Oracle {
         // corners in positive order TL, TR, BR, BL
         int v[4] = {sample(R, C), sample(R, C + 1), sample(R + 1, C + 1), sample(R + 1, C)};
         if (v[0] == v[1] && v[1] == v[2] && v[2] == v[3]) continue;
-        i64 X0 = 4LL * s_ * C + 2LL * (s_ - 1), Y0 = 4LL * s_ * R + 2LL * (s_ - 1);
-        i64 mx[4] = {X0 + 2 * s_, X0 + 4 * s_, X0 + 2 * s_, X0};
-        i64 my[4] = {Y0, Y0 + 2 * s_, Y0 + 4 * s_, Y0 + 2 * s_};
+        // sample (R, C) sits at pixel (s C + (s-1)/2, s R + (s-1)/2)
+        i64 X0 = U_ * (4LL * s_ * C + 2LL * (s_ - 1)), Y0 = U_ * (4LL * s_ * R + 2LL * (s_ - 1));
+        const i64 hs = 2 * s_ * U_;  // half a cell
+        i64 mx[4] = {X0 + hs, X0 + 2 * hs, X0 + hs, X0};
+        i64 my[4] = {Y0, Y0 + hs, Y0 + 2 * hs, Y0 + hs};
         // a segment starts at each fg->bg transition (walking corners in positive
         // order) and ends at the next bg->fg transition; background corners are
         // cut off, so foreground is 8-connected at saddles.
@@ -670,7 +687,7 @@ class Oracle {
     for (auto& sg : segs_) {
       i64 dx = sg.q.x - sg.p.x, dy = sg.q.ya - sg.p.ya;
       i64 l2 = dx * dx + dy * dy;
-      ORACLE_CHECK(l2 == 8LL * s_ * s_ || l2 == 16LL * s_ * s_, "segment length");
+      ORACLE_CHECK(l2 == 8LL * s_ * s_ * U_ * U_ || l2 == 16LL * s_ * s_ * U_ * U_, "segment length");
       const Segment& nx = segs_[sg.next];
       i64 ex = nx.q.x - nx.p.x, ey = nx.q.ya - nx.p.ya;
       ORACLE_CHECK(dx * ex + dy * ey >= 0, "turn sharper than 90 degrees");
@@ -682,8 +699,8 @@ class Oracle {
   }
 
   // --- step 3: registry of crossings (segment-driven) ---------------------
-  // exact: is the rational y (x4 units) above row k, i.e. Y > -4 + 2hk*sqrt3 ?
-  int cmp_row(i64 Y, i64 k) const { return z3_sign(Z3{(i128)Y + 4, -(i128)2 * h_ * k}); }
+  // exact: is the rational y below grid row k in the picture (Y > -4U + 2pk*sqrt3)?
+  int cmp_row(i64 Y, i64 k) const { return z3_sign(Z3{(i128)Y + 4 * U_, -(i128)2 * h_ * k}); }
 
   void build_registry() {
     std::vector<std::pair<i64, Crossing>> tmp;
@@ -692,8 +709,8 @@ class Oracle {
       const Segment& sg = segs_[sidx];
       i64 ylo = std::min(sg.p.ya, sg.q.ya), yhi = std::max(sg.p.ya, sg.q.ya);
       i64 xlo = std::min(sg.p.x, sg.q.x), xhi = std::max(sg.p.x, sg.q.x);
-      i64 k0 = (i64)std::floor((ylo + 4) / rowstep) - 2;
-      i64 k1 = (i64)std::floor((yhi + 4) / rowstep) + 2;
+      i64 k0 = (i64)std::floor((ylo + 4 * U_) / rowstep) - 2;
+      i64 k1 = (i64)std::floor((yhi + 4 * U_) / rowstep) + 2;
       for (i64 k = std::max<i64>(k0, 0); k <= std::min<i64>(k1, NK_ - 1); ++k) {
         i64 X00 = lat(k, 0).x;
         i64 i0 = (xlo - 4LL * h_ - X00) / (4LL * h_) - 2;
@@ -743,8 +760,8 @@ class Oracle {
         //   t = dP / (dP - dQ),  dP = (V-U) x (P-U),  dQ = (V-U) x (Q-U),
         //   X = P + t (Q - P)
         const Segment& g = segs_[grp[j].seg];
-        double px = 0.25 * (double)g.p.x, py = 0.25 * (double)g.p.ya;
-        double qx = 0.25 * (double)g.q.x, qy = 0.25 * (double)g.q.ya;
+        double px = to_px(g.p.x), py = to_px(g.p.ya);
+        double qx = to_px(g.q.x), qy = to_px(g.q.ya);
         double ux = lat_xd(k, i), uy = lat_yd(k), vx = lat_xd(k2, i2), vy = lat_yd(k2);
         double gx = vx - ux, gy = vy - uy;
         double dp = gx * (py - uy) - gy * (px - ux);
@@ -763,7 +780,7 @@ class Oracle {
     const double rowstep = 2.0 * h_ * std::sqrt(3.0);
     for (i64 sidx = 0; sidx < (i64)segs_.size(); ++sidx) {
       const Pt& P = segs_[sidx].p;
-      i64 k = (i64)std::floor((P.ya + 4) / rowstep);
+      i64 k = (i64)std::floor((P.ya + 4 * U_) / rowstep);
       while (k > 0 && cmp_row(P.ya, k) < 0) --k;
       while (cmp_row(P.ya, k + 1) > 0) ++k;
       ORACLE_CHECK(cmp_row(P.ya, k) > 0 && cmp_row(P.ya, k + 1) < 0, "row location");
@@ -864,8 +881,8 @@ class Oracle {
           if (q < chain_.size() && chain_[q].tri_key == key) {
             chain_[q].vid = nv++;
             const Pt& P = segs_[chain_[q].seg_out].p;
-            mesh_.verts.push_back(0.25 * (double)P.x);
-            mesh_.verts.push_back(0.25 * (double)P.ya);
+            mesh_.verts.push_back(to_px(P.x));
+            mesh_.verts.push_back(to_px(P.ya));
           }
         }
       }
@@ -1040,7 +1057,7 @@ struct oracle_mesh {
 };
 
 oracle_mesh* oracle_mesh_from_bitmap(const uint8_t* bitmap, int32_t width, int32_t height,
-                                     int64_t row_stride, int32_t grid_h, uint32_t flags,
+                                     int64_t row_stride, double grid_h, uint32_t flags,
                                      char* err, int32_t errlen) {
   try {
     Oracle o(bitmap, width, height, row_stride, grid_h, flags);

@@ -23,11 +23,24 @@ import math
 import numpy as np
 
 
-def stride_for(h: int) -> int:
+def stride_for(h) -> int:
+    """Smallest s with s^2 > 2 h^2 (h a dyadic rational, compared exactly)."""
+    from fractions import Fraction
+    hf = Fraction(h)
     s = 1
-    while s * s <= 2 * h * h:
+    while s * s <= 2 * hf * hf:
         s += 1
     return s
+
+
+def grid_x0(h) -> float:
+    """x of lattice vertex (0, 0): -(2h+3)/4, moved left by 1/(4U) when h = p/U with
+    U = 2^q > 1, so that 4U x is odd on every lattice vertex."""
+    from fractions import Fraction
+    hf = Fraction(h)
+    U = hf.denominator
+    x0 = -(2 * hf + 3) / 4 - (Fraction(1, 4 * U) if U > 1 else 0)
+    return float(x0)
 
 
 def coarse_samples(bitmap: np.ndarray, h: int) -> np.ndarray:
@@ -197,14 +210,15 @@ def lattice_inside(coarse: np.ndarray, s: int, h: int, NK: int, NI: int) -> np.n
     inside = np.zeros((NK, NI), bool)
     if P.shape[0] == 0:
         return inside
-    rh = h * math.sqrt(3.0) / 2.0
+    rh = float(h) * math.sqrt(3.0) / 2.0
     ylo = np.minimum(P[:, 1], Q[:, 1])
     yhi = np.maximum(P[:, 1], Q[:, 1])
     order = np.argsort(ylo)
     ylo_s = ylo[order]
-    x0 = -(2 * h + 3) / 4.0
+    x0 = grid_x0(h)
+    h = float(h)
     for k in range(NK):
-        y = -1.0 + k * rh
+        y = -1.0 + (h * k) * 0.86602540378443864676
         sel = order[:np.searchsorted(ylo_s, y)]
         sel = sel[yhi[sel] > y]
         if sel.size == 0:

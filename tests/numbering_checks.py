@@ -13,10 +13,11 @@ base triangle; then the stated order is asserted:
   (row k, column i, Tb before Ta) and lexicographically within a parent.
 
 Grid (Sec. 3.3, rows horizontal): vertex (k, i) is at
-x = -(2h+3)/4 + h i + (h/2)(k mod 2), y = -1 + k h sqrt3/2, evaluated as
-y = -1.0 + (h k) * 0.86602540378443864676 in double precision.  Boundary points
+x = x0 + h i + (h/2)(k mod 2), y = -1 + k h sqrt3/2, evaluated as
+y = -1.0 + (h k) * 0.86602540378443864676 in double precision, with
+x0 = -(2h+3)/4, less 1/(4U) when h = p/U with U = 2^q > 1.  Boundary points
 (marching-squares ends, the chain vertices) are half-integers; lattice x is an
-odd multiple of 1/4; crossings lie strictly inside grid edges.
+odd multiple of 1/(4U); crossings lie strictly inside grid edges.
 """
 from __future__ import annotations
 
@@ -28,18 +29,27 @@ HALF_SQRT3 = 0.86602540378443864676
 
 
 def _row_y(h, k):
-    return -1.0 + (np.asarray(h * k, np.float64)) * HALF_SQRT3
+    return -1.0 + (float(h) * np.asarray(k, np.float64)) * HALF_SQRT3
+
+
+def _units(h):
+    """(h as float, U = 2^q, x of vertex (0, 0))."""
+    from fractions import Fraction
+    import mesh_checks
+    hf = Fraction(h)
+    return float(hf), hf.denominator, mesh_checks.grid_x0(hf)
 
 
 def vertex_keys(verts: np.ndarray, h: int, NK: int, NI: int):
     """Per vertex: (kind, k, i, sub, param) with kind 0 lattice, 1 crossing, 2 chain vertex;
     sub = 0 self, 1 + d for a crossing on edge E_d, 4 chain vertex in Tb, 5 in Ta."""
+    h, U, x0 = _units(h)
     x, y = verts[:, 0], verts[:, 1]
     n = x.shape[0]
     rh = h * math.sqrt(3.0) / 2.0
     tr = (y + 1.0) / rh
     kr = np.rint(tr).astype(np.int64)
-    x4 = 4.0 * x
+    x4 = 4.0 * U * x
     odd4 = (x4 == np.rint(x4)) & (np.rint(x4).astype(np.int64) % 2 == 1)
     half = (2.0 * x == np.rint(2.0 * x)) & (2.0 * y == np.rint(2.0 * y))
     lat = odd4 & (y == _row_y(h, kr))
@@ -48,7 +58,6 @@ def vertex_keys(verts: np.ndarray, h: int, NK: int, NI: int):
     i = np.zeros(n, np.int64)
     sub = np.zeros(n, np.int64)
     par = np.zeros(n, np.float64)
-    x0 = -(2 * h + 3) / 4.0
     # lattice vertices
     m = kind == 0
     k[m] = kr[m]
@@ -88,14 +97,14 @@ def vertex_keys(verts: np.ndarray, h: int, NK: int, NI: int):
     return kind, k, i, sub, par
 
 
-def triangle_parents(verts: np.ndarray, tris: np.ndarray, h: int):
+def triangle_parents(verts: np.ndarray, tris: np.ndarray, h):
     """Parent base triangle (k, i, t) of every triangle, from its centroid."""
+    h, U, x0 = _units(h)
     c = verts[tris].mean(axis=1)
     rh = h * math.sqrt(3.0) / 2.0
     tr = (c[:, 1] + 1.0) / rh
     kb = np.floor(tr).astype(np.int64)
     f = tr - kb
-    x0 = -(2 * h + 3) / 4.0
     u = (c[:, 0] - x0 - (h / 2.0) * (kb & 1)) / h
     ib = np.floor(u + f / 2.0)
     t = np.where(u + f / 2.0 - ib < f, 0, 1)
@@ -128,15 +137,15 @@ def check_numbering(verts: np.ndarray, tris: np.ndarray, h: int, NK: int, NI: in
         assert lex.all(), "triangles of one parent not in lexicographic order"
         # every vertex of a triangle lies in the closed parent base triangle
         o = pk & 1
-        X0 = -(2 * h + 3) / 4.0
-        ax = X0 + h * pi + (h / 2.0) * o
+        hh, _, X0 = _units(h)
+        ax = X0 + hh * pi + (hh / 2.0) * o
         ay = _row_y(h, pk)
         by = _row_y(h, pk + 1)
         for j in range(3):
             v = verts[tris[:, j]]
             ff = (v[:, 1] - ay) / (by - ay)
             assert ((ff >= -1e-9) & (ff <= 1 + 1e-9)).all()
-            lo = np.where(pt == 0, ax - ff * h / 2, ax + ff * h / 2)
-            hi = np.where(pt == 0, ax + ff * h / 2, ax + h - ff * h / 2)
+            lo = np.where(pt == 0, ax - ff * hh / 2, ax + ff * hh / 2)
+            hi = np.where(pt == 0, ax + ff * hh / 2, ax + hh - ff * hh / 2)
             assert ((v[:, 0] >= lo - 1e-9) & (v[:, 0] <= hi + 1e-9)).all(), "vertex outside its parent"
     return {"lattice": kind == 0, "k": k, "i": i, "kind": kind}

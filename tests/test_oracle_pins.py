@@ -502,3 +502,45 @@ def test_random_generic_polylines_around_one_triangle():
     # single chords, interior chain vertices and two chords all occur
     types = {int(oracle.class_table()[c - 1]) // 4096 for c in seen}
     assert types == {1, 2, 3}, types
+
+
+DYADIC = [0.5, 0.75, 1.25, 1.5, 2.5, 0.375]
+
+
+@pytest.mark.parametrize("h", DYADIC)
+def test_dyadic_grid_edges(h):
+    """Grid edges h = p / 2^q (the paper's grid has h < 1, Sec. 3.3): every invariant,
+    the numbering and the inside set hold on disks, ellipses and smoothed noise."""
+    import numbering_checks as nc
+    g = wl.rng(97, int(h * 8))
+    cases = [wl.disk(item=2), wl.ellipses(300, 260, g=g), wl.smoothed_noise(180, 150, 4.0, 0.0, False, g)]
+    for bm in cases:
+        m = oracle.mesh_from_bitmap(bm, h)
+        mc.check_mesh(m.verts, m.tris, m.codes, bm, h)
+        _numbering_and_inside(bm, h)
+        NK, NI, s = m.grid
+        assert s == mc.stride_for(h)
+
+
+@pytest.mark.parametrize("h", [0.5, 0.75, 1.5])
+def test_dyadic_brute_force_3x3(h):
+    s = mc.stride_for(h)
+    for ci, bits in enumerate(itertools.product([0, 1], repeat=9)):
+        bm = _upsample(np.array(bits, np.uint8).reshape(3, 3), s, dy=ci % 2, dx=(ci // 2) % 2)
+        m = oracle.mesh_from_bitmap(bm, h)
+        mc.check_mesh(m.verts, m.tris, m.codes, bm, h)
+
+
+def test_dyadic_grid_extent_and_refusals():
+    from fractions import Fraction
+    for (H, W, h) in ((64, 64, 0.5), (100, 37, 0.75), (5, 300, 1.25), (33, 17, 0.00390625)):
+        m = oracle.mesh_from_bitmap(np.zeros((H, W), np.uint8), h)
+        NK, NI, s = m.grid
+        CH, CW = -(-H // s), -(-W // s)
+        assert -1 + (NK - 1) * h * np.sqrt(3) / 2 > s * CH - 0.5
+        assert -1 + (NK - 2) * h * np.sqrt(3) / 2 <= s * CH - 0.5
+        x0 = mc.grid_x0(Fraction(h))
+        assert x0 + h * (NI - 1) > s * CW - 0.5 >= x0 + h * (NI - 2)
+    for bad in (0.3, 1.0 / 3.0, 1.0 / 512, 0.0, -1.0):
+        with pytest.raises(oracle.OracleError):
+            oracle.mesh_from_bitmap(np.ones((8, 8), np.uint8), bad)

@@ -10,14 +10,19 @@
  * Conventions
  *  - Pixel (row r, column c) is a unit square centred at (x = c, y = r)
  *    (Sec. 3.3, structured triangular filling).  A nonzero byte is foreground.
- *  - grid_h is the edge length of the base equilateral grid in pixels.  It
- *    must be one of the supported integers {1, 2, 3, 4, 5, 6}; others return
- *    SBMT_E_UNSUPPORTED_GRID_H.  The boundary is taken from a raster
- *    coarsened by block majority with the stride s = min{s : s^2 > 2 h^2}
- *    (h = 1 -> 2, 2 -> 3, 4 -> 6) so that every boundary segment is longer than
- *    the base edge, as the geometric protocol of Sec. 3.2 requires.
+ *  - grid_h is the edge length of the base equilateral grid in pixels, a
+ *    dyadic rational h = p / 2^q with q <= 8 and 0 < h <= 6 (the paper's grid
+ *    has h < 1, Sec. 3.3), with 3h <= 2s for the stride s below, and
+ *    16 s 4^q (max(width, height) + 2s + 16) < 2^31 (exact predicates in
+ *    64-bit integers); others return SBMT_E_UNSUPPORTED_GRID_H.  The boundary
+ *    is taken from a raster coarsened by block majority with the stride
+ *    s = min{s : s^2 > 2 h^2} (h = 1/2 -> 1, 1 -> 2, 3/2 -> 3, 2 -> 3, 4 -> 6)
+ *    so that every boundary segment is longer than the base edge, as the
+ *    geometric protocol of Sec. 3.2 requires.
  *  - Grid rows are horizontal: vertex (k, i) lies at
- *      x = -(2h+3)/4 + h*i + (h/2)*(k mod 2),   y = -1 + k*h*sqrt(3)/2.
+ *      x = x0 + h*i + (h/2)*(k mod 2),   y = -1 + k*h*sqrt(3)/2,
+ *    x0 = -(2h+3)/4 for integer h, -(2h+3)/4 - 2^-(q+2) otherwise (so that no
+ *    vertex lies on a boundary line).
  *  - Output vertices are FP64 (x, y) pairs; triangles are int32 index
  *    triples with positive signed area in (x, y); codes are one byte per
  *    triangle: 0 = uncut base triangle, 1..SBMT_NUM_CLASSES = canonical class
@@ -63,7 +68,7 @@ extern "C" {
 typedef enum {
   SBMT_OK = 0,
   SBMT_E_INVALID_ARG = -1,        /* null pointer, negative size, stride < width ... */
-  SBMT_E_UNSUPPORTED_GRID_H = -2, /* grid_h not in {1,...,6} */
+  SBMT_E_UNSUPPORTED_GRID_H = -2, /* grid_h not p/2^q (q <= 8), above 6, or too fine for the image */
   SBMT_E_INDEX_OVERFLOW = -3,     /* more than INT32_MAX vertices */
   SBMT_E_WORKSPACE = -4,          /* workspace missing or smaller than required */
   SBMT_E_DEVICE = -5,             /* a HIP runtime call failed */
@@ -83,7 +88,7 @@ typedef struct {
   int32_t width;
   int32_t height;
   int64_t row_stride;
-  int32_t grid_h;
+  double grid_h;   /* p / 2^q pixels, see above */
   uint32_t flags;
 } sbmt_image;
 

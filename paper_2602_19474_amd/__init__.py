@@ -49,7 +49,7 @@ class Sizes:
     n_segments: int = 0
 
 
-def _image(bitmap, grid_h: int, flags: int) -> _lib.Image:
+def _image(bitmap, grid_h: float, flags: int) -> _lib.Image:
     torch = _torch()
     if bitmap.dtype != torch.uint8 or bitmap.dim() != 2:
         raise ValueError("bitmap must be a 2-D uint8 tensor")
@@ -58,13 +58,13 @@ def _image(bitmap, grid_h: int, flags: int) -> _lib.Image:
     H, W = bitmap.shape
     # a size-1 row dimension may carry any stride (numpy's a[None, :] has 0)
     stride = int(bitmap.stride(0)) if (bitmap.numel() and H > 1) else int(W)
-    return _lib.Image(bitmap.data_ptr() if bitmap.numel() else None, int(W), int(H), stride, int(grid_h),
+    return _lib.Image(bitmap.data_ptr() if bitmap.numel() else None, int(W), int(H), stride, float(grid_h),
                       int(flags))
 
 
-def query(width: int, height: int, grid_h: int, flags: int = 0) -> Layout:
+def query(width: int, height: int, grid_h: float, flags: int = 0) -> Layout:
     """Grid geometry and workspace size of an image (host only, no GPU work)."""
-    img = _lib.Image(None, int(width), int(height), int(width), int(grid_h), int(flags))
+    img = _lib.Image(None, int(width), int(height), int(width), float(grid_h), int(flags))
     out = _lib.Layout()
     _lib.check(_lib.lib().sbmt_query(ctypes.byref(img), ctypes.byref(out)), "sbmt_query")
     return Layout(out.stride_s, out.coarse_w, out.coarse_h, out.grid_rows, out.grid_cols, out.workspace_bytes)
@@ -108,13 +108,13 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def workspace(bitmap, grid_h: int, flags: int = 0):
+def workspace(bitmap, grid_h: float, flags: int = 0):
     torch = _torch()
     lay = query(bitmap.shape[1], bitmap.shape[0], grid_h, flags)
     return torch.empty(lay.workspace_bytes, dtype=torch.uint8, device=bitmap.device)
 
 
-def plan(bitmap, grid_h: int, ws, flags: int = 0, stream=None, ctx: Context | None = None) -> Sizes:
+def plan(bitmap, grid_h: float, ws, flags: int = 0, stream=None, ctx: Context | None = None) -> Sizes:
     """Classify and count (synchronises the stream to return the sizes)."""
     ctx = ctx or context(bitmap.device.index)
     img = _image(bitmap, grid_h, flags)
@@ -124,7 +124,7 @@ def plan(bitmap, grid_h: int, ws, flags: int = 0, stream=None, ctx: Context | No
     return Sizes(out.n_vertices, out.n_triangles, out.n_cut, out.n_segments)
 
 
-def run(bitmap, grid_h: int, ws, verts, tris, codes, flags: int = 0, stream=None, ctx: Context | None = None):
+def run(bitmap, grid_h: float, ws, verts, tris, codes, flags: int = 0, stream=None, ctx: Context | None = None):
     """Emit the mesh planned in ``ws`` into preallocated outputs (asynchronous)."""
     ctx = ctx or context(bitmap.device.index)
     img = _image(bitmap, grid_h, flags)
@@ -134,7 +134,7 @@ def run(bitmap, grid_h: int, ws, verts, tris, codes, flags: int = 0, stream=None
                                    codes.data_ptr() if codes.numel() else None, _stream_ptr(stream)), "sbmt_run")
 
 
-def mesh_from_bitmap(bitmap, grid_h: int, both_sides: bool = False, stream=None, return_sizes: bool = False):
+def mesh_from_bitmap(bitmap, grid_h: float, both_sides: bool = False, stream=None, return_sizes: bool = False):
     """Mesh a uint8 CUDA tensor [H, W]: plan -> allocate -> run on the current stream.
 
     Returns (verts, tris, codes), and the planned ``Sizes`` as a fourth item
@@ -151,7 +151,7 @@ def mesh_from_bitmap(bitmap, grid_h: int, both_sides: bool = False, stream=None,
     return (verts, tris, codes, sz) if return_sizes else (verts, tris, codes)
 
 
-def mesh_async(bitmap, grid_h: int, ws, verts, tris, codes, sizes_dev, flags: int = 0, stream=None,
+def mesh_async(bitmap, grid_h: float, ws, verts, tris, codes, sizes_dev, flags: int = 0, stream=None,
                ctx: Context | None = None):
     """Plan and emit without a host round trip into outputs of given capacity.
 
@@ -167,7 +167,7 @@ def mesh_async(bitmap, grid_h: int, ws, verts, tris, codes, sizes_dev, flags: in
                "sbmt_mesh_async")
 
 
-def mesh_noalloc(bitmap, grid_h: int, verts, tris, codes, sizes_dev, flags: int = 0, stream=None,
+def mesh_noalloc(bitmap, grid_h: float, verts, tris, codes, sizes_dev, flags: int = 0, stream=None,
                  ctx: Context | None = None):
     """``mesh_async`` on the library's own scratch array: no workspace argument and no
     device allocation (for callers that cannot allocate).  Images whose workspace

@@ -29,7 +29,7 @@ class SbmtError(RuntimeError):
 
 class Image(ctypes.Structure):
     _fields_ = [("bitmap", ctypes.c_void_p), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
-                ("row_stride", ctypes.c_int64), ("grid_h", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("row_stride", ctypes.c_int64), ("grid_h", ctypes.c_double), ("flags", ctypes.c_uint32)]
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20  # scratch of sbmt_mesh_noalloc

@@ -372,7 +372,7 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
   const int c0 = cb * kCB;
   const int lane = threadIdx.x & 63;
   if (threadIdx.x < RB) {
-    L.rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);
+    L.rowR[threadIdx.x] = row_cell(g, k0 + threadIdx.x);
     L.acc[threadIdx.x][0] = L.acc[threadIdx.x][1] = L.acc[threadIdx.x][2] = L.acc[threadIdx.x][3] = 0;
   }
   if (threadIdx.x == 0) L.n1 = L.n2 = 0;
@@ -515,7 +515,7 @@ __global__ void __launch_bounds__(64) k_slow(Src src, const int64_t* __restrict_
   const int64_t tile = blockIdx.x;
   if (threadIdx.x < RB) {
     acc[threadIdx.x] = 0ull;
-    rowR[threadIdx.x] = row_cell(ky * RB + threadIdx.x, g.h, g.s);
+    rowR[threadIdx.x] = row_cell(g, ky * RB + threadIdx.x);
   }
   const int64_t nq = sh.tile_n[tile];
   const bool over = nq > sh.tcap;  // uniform
@@ -874,7 +874,7 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
   constexpr int kLut = 15 * 3 * 2 * 5;
   static_assert(kLut <= 2 * kThreads, "two table entries per thread");
   const int c0 = cb * kCB;
-  if (threadIdx.x <= RB) L.rowR[threadIdx.x] = row_cell(k0 + threadIdx.x, g.h, g.s);  // read after step 2
+  if (threadIdx.x <= RB) L.rowR[threadIdx.x] = row_cell(g, k0 + threadIdx.x);  // read after step 2
   Bits bw;
   bw.p = d.bits;
   bw.wpr = g.wpr;
@@ -984,8 +984,8 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
     const bool fast = c < g.NI && !info_slow(f);
     if (fast && info_self(f)) {
       double2 v;
-      v.x = lat_x(g.X0 + 4 * g.h * c + 2 * g.h * o_);
-      v.y = lat_y(g.h, k);
+      v.x = lat_x(g, g.X0 + 4 * g.h * c + 2 * g.h * o_);
+      v.y = lat_y(g, k);
       *reinterpret_cast<double2*>(vrow + (uint32_t)L.voff[r][col] * 16u) = v;
     }
     // ranks of the wave's fast triangles (at most two per owner)
@@ -1161,7 +1161,7 @@ __global__ void __launch_bounds__(kThreads, 8) k_emit(Src src, const int64_t* __
     const longlong4 o = sh.seg_off[d.seg0 + (k < g.NK ? (int64_t)k * g.NCB + cb : nsegi)];
     L.bv[threadIdx.x] = (int)(o.x - base.x);
     if (threadIdx.x < RB) L.tb[threadIdx.x] = o.y - base.y;
-    L.rowR[threadIdx.x] = row_cell(k, g.h, g.s);
+    L.rowR[threadIdx.x] = row_cell(g, k);
   }
   L.lut[threadIdx.x] = lut0;
   if (threadIdx.x + kThreads < kLut) L.lut[threadIdx.x + kThreads] = lut1;
@@ -1233,8 +1233,8 @@ __global__ void __launch_bounds__(kThreads, 8) k_emit(Src src, const int64_t* __
     const bool fast = (cv & 0x8000u) == 0u;
     if (fast && (cv & 1u)) {
       double2 v;
-      v.x = lat_x(g.X0 + 4 * g.h * c + 2 * g.h * o);
-      v.y = lat_y(g.h, k);
+      v.x = lat_x(g, g.X0 + 4 * g.h * c + 2 * g.h * o);
+      v.y = lat_y(g, k);
       *reinterpret_cast<double2*>(vrow + (uint32_t)(ex & 0xffff) * 16u) = v;
     }
     const int ntb = fast ? (int)((cv >> 9) & 7u) : 0, nta = fast ? (int)((cv >> 12) & 7u) : 0;
@@ -1409,7 +1409,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_fused(ManySrc src, const int64_
       b.wpr = g.wpr;
       b.rr0 = 0;
       b.cc0 = 0;
-      const Frame f = owner_frame(g, b, k, c, row_cell(k, g.h, g.s));
+      const Frame f = owner_frame(g, b, k, c, row_cell(g, k));
       Slow sr;
       slow_classify(g, f, sr);
       SlowRec R = pack_slow(sr);
@@ -1496,15 +1496,31 @@ __global__ void __launch_bounds__(kThreads, 3) k_fused(ManySrc src, const int64_
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
-static int stride_for(int h) {
+// grid_h = p / U, U = 2^q (q <= 8), reduced; the coarse stride is the smallest
+// s with s^2 > 2 h^2.
+static bool parse_grid_h(double grid_h, int* p, int* q) {
+  if (!(grid_h > 0.0) || grid_h > 6.0) return false;
+  const double g256 = grid_h * 256.0;
+  if (g256 != __builtin_floor(g256)) return false;
+  int pp = (int)g256, qq = 8;
+  while (qq > 0 && (pp & 1) == 0) {
+    pp >>= 1;
+    --qq;
+  }
+  *p = pp;
+  *q = qq;
+  return true;
+}
+
+static int stride_for(int p, int U) {
   int s = 1;
-  while (s * s <= 2 * h * h) ++s;
+  while ((int64_t)s * s * U * U <= 2LL * p * p) ++s;
   return s;
 }
 
-static bool grid_h_supported(int h) {
+static bool grid_h_supported(int p, int U) {
   // the owner parallelogram (width 1.5 h) must fit two coarse cells: 3h <= 2s
-  return h >= 1 && h <= 6 && 3 * h <= 2 * stride_for(h);
+  return p >= 1 && p <= 6 * U && 3 * p <= 2 * stride_for(p, U) * U;
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1521,11 +1537,11 @@ static int64_t host_floordiv(int64_t a, int64_t b) {
   int64_t q = a / b;
   return (a % b != 0 && a < 0) ? q - 1 : q;
 }
-static int64_t host_row_cell(int64_t k, int h, int s) {
-  int64_t kh = k * h;
-  int64_t R = host_floordiv(kh * 17320 / 10000 - s - 1, 2 * s);
-  while (host_z3sign(-(2 * s * R + s + 1), kh) < 0) --R;
-  while (host_z3sign(-(2 * s * (R + 1) + s + 1), kh) >= 0) ++R;
+static int64_t host_row_cell(int64_t k, int p, int s, int U) {
+  int64_t kp = k * p;
+  int64_t R = host_floordiv(kp * 17320 / (10000LL * U) - s - 1, 2 * s);
+  while (host_z3sign(-(int64_t)U * (2 * s * R + s + 1), kp) < 0) --R;
+  while (host_z3sign(-(int64_t)U * (2 * s * (R + 1) + s + 1), kp) >= 0) ++R;
   return R;
 }
 
@@ -1533,16 +1549,17 @@ constexpr int kMaxTileRows = 16;  // largest RB instantiated
 static bool tile_window_fits(const Geo& g) {
   // rows: the cell rows of kMaxTileRows + 1 grid rows plus the 3x3 window;
   // words: the cell columns of kCB + 2 owners plus the window and one spare word
-  const double rows = ((kMaxTileRows + 1) * g.h * 0.8660254037844386) / g.s + 5;
-  const double words = ((kCB + 2) * (double)g.h / g.s + 4) / 32.0 + 3;
+  const double h = (double)g.h / g.U;
+  const double rows = ((kMaxTileRows + 1) * h * 0.8660254037844386) / g.s + 5;
+  const double words = ((kCB + 2) * h / g.s + 4) / 32.0 + 3;
   return rows <= kWinRows && words <= kWinWords;
 }
 
 static bool windows_in_bounds(const Geo& g) {
-  const int64_t rlo_min = host_row_cell(0, g.h, g.s), rlo_max = host_row_cell(g.NK - 1, g.h, g.s);
+  const int64_t rlo_min = host_row_cell(0, g.h, g.s, g.U), rlo_max = host_row_cell(g.NK - 1, g.h, g.s, g.U);
   const int64_t xmin = g.X0, xmax = (int64_t)g.X0 + 4LL * g.h * (g.NI - 1) + 2LL * g.h;
-  const int64_t clo_min = host_floordiv(xmin - 2 * g.h - 2 * (g.s - 1), 4 * g.s);
-  const int64_t clo_max = host_floordiv(xmax - 2 * g.h - 2 * (g.s - 1), 4 * g.s);
+  const int64_t clo_min = host_floordiv(xmin - 2 * g.h - 2LL * (g.s - 1) * g.U, 4LL * g.s * g.U);
+  const int64_t clo_max = host_floordiv(xmax - 2 * g.h - 2LL * (g.s - 1) * g.U, 4LL * g.s * g.U);
   // rows Rlo .. Rlo+2 and bit columns Clo .. Clo+2 (plus one spare word) are read
   return rlo_min + kRing >= 0 && rlo_max + 2 + kRing < g.CH + 2 * kRing && clo_min + kRingC >= 0 &&
          ((clo_max + 2 + kRingC) >> 5) + 1 < g.wpr;
@@ -1555,28 +1572,42 @@ static sbmt_status make_geo(const sbmt_image* img, Geo* out, bool need_ptr) {
   if (img->width > 0 && img->height > 0 && ((need_ptr && img->bitmap == nullptr) || img->row_stride < img->width))
     return SBMT_E_INVALID_ARG;
   if (img->flags & ~1u) return SBMT_E_INVALID_ARG;
-  if (!grid_h_supported(img->grid_h)) return SBMT_E_UNSUPPORTED_GRID_H;
+  int p = 0, q = 0;
+  if (!parse_grid_h(img->grid_h, &p, &q) || !grid_h_supported(p, 1 << q)) return SBMT_E_UNSUPPORTED_GRID_H;
   Geo g;
   g.W = img->width;
   g.H = img->height;
   g.stride = img->row_stride;
-  g.h = img->grid_h;
-  g.s = stride_for(g.h);
+  g.h = p;
+  g.q = q;
+  g.U = 1 << q;
+  g.s = stride_for(p, g.U);
+  // exact predicates in 64-bit integers need |a|, |b| < 2^31: 16 s U^2 (side + ring) < 2^31
+  const int64_t side = std::max<int64_t>(g.W, g.H) + 2 * g.s + 16;
+  if ((__int128)16 * g.s * g.U * g.U * side >= ((__int128)1 << 31)) return SBMT_E_UNSUPPORTED_GRID_H;
   g.CW = (g.W + g.s - 1) / g.s;
   g.CH = (g.H + g.s - 1) / g.s;
   // rows 0..m with m the smallest m >= 1 such that 3 m^2 h^2 > (2 s CH + 1)^2
-  int64_t rhs = (2LL * g.s * g.CH + 1) * (2LL * g.s * g.CH + 1);
-  int64_t m = (int64_t)((2.0 * g.s * g.CH + 1) / (g.h * 1.7320508075688772)) - 2;
+  const __int128 rhs = (__int128)g.U * g.U * (2LL * g.s * g.CH + 1) * (2LL * g.s * g.CH + 1);
+  int64_t m = (int64_t)((2.0 * g.s * g.CH + 1) * g.U / (p * 1.7320508075688772)) - 2;
   if (m < 1) m = 1;
-  while (3LL * m * m * g.h * g.h <= rhs) ++m;
-  while (m > 1 && 3LL * (m - 1) * (m - 1) * g.h * g.h > rhs) --m;
+  while ((__int128)3 * m * m * p * p <= rhs) ++m;
+  while (m > 1 && (__int128)3 * (m - 1) * (m - 1) * p * p > rhs) --m;
+  if (m + 1 >= (1LL << 24)) return SBMT_E_INVALID_ARG;
   g.NK = (int32_t)(m + 1);
-  g.NI = (int32_t)((4LL * g.s * g.CW + 2LL * g.h + 1) / (4LL * g.h) + 2);
+  // x of vertex (0, 0), odd; the last column lies right of x = s CW - 1/2
+  g.X0 = g.U == 1 ? -2 * p - 3 : -(2 * p + 3 * g.U) - 1;
+  const int64_t ni = (4LL * g.U * g.s * g.CW - 2LL * g.U - g.X0) / (4LL * p) + 2;
+  if (ni >= (1LL << 24)) return SBMT_E_INVALID_ARG;
+  g.NI = (int32_t)ni;
   g.NCB = (g.NI + kCB - 1) / kCB;
   g.wpr = (kRingC + g.CW + kRing + 31) / 32 + 1;
-  g.X0 = -2 * g.h - 3;
   g.flags = img->flags;
   g.inv4s = 1.0f / (float)(4 * g.s);
+  g.xscale = 0.25 / (double)g.U;
+  g.invU = 1.0 / (double)g.U;
+  // 20 times the rounding bound of the double-precision signs (about 5e-15 s U^2 side)
+  g.band = std::max(1e-6, 1e-13 * (double)g.s * g.U * g.U * (double)side);
   if (!windows_in_bounds(g) || !tile_window_fits(g)) return SBMT_E_INVALID_ARG;
   // owner positions in record lists: 24 bits per coordinate
   if (g.NK >= (1 << 24) || g.NI >= (1 << 24)) return SBMT_E_INVALID_ARG;
@@ -2308,7 +2339,7 @@ const char* sbmt_status_string(sbmt_status s) {
   switch (s) {
     case SBMT_OK: return "ok";
     case SBMT_E_INVALID_ARG: return "invalid argument";
-    case SBMT_E_UNSUPPORTED_GRID_H: return "unsupported grid_h (supported: 1..6)";
+    case SBMT_E_UNSUPPORTED_GRID_H: return "unsupported grid_h (p/2^q up to 6 with 3h <= 2s, q <= 8, and 16 s 4^q side < 2^31)";
     case SBMT_E_INDEX_OVERFLOW: return "vertex count exceeds int32";
     case SBMT_E_WORKSPACE: return "workspace missing or too small";
     case SBMT_E_DEVICE: return "HIP runtime error";

@@ -18,11 +18,12 @@
 // Everything lives in registers: segment slots, crossing sets and orders are
 // packed integers and bit masks indexed only by compile-time constants.
 //
-// Exact arithmetic: quarter-pixel integer coordinates ("x4 units").  Boundary
-// points are even integers; grid vertex (k,i) is at X = -2h-3 + 4h*i + 2h*o
-// (odd) and Y = -4 + 2hk*sqrt3.  Every predicate is sign(A + B*sqrt3) with
+// Exact arithmetic: the grid edge is h = p / U pixels (U = 2^q, q <= 8) and
+// coordinates are integers in units of 1 / (4U) pixel.  Boundary points are
+// multiples of 2U (even); grid vertex (k,i) is at X = X0 + 4p*i + 2p*o with X0
+// odd, and Y = -4U + 2pk*sqrt3.  Every predicate is sign(A + B*sqrt3) with
 // integer A, B, never zero (x parity, irrationality of sqrt3), decided by a
-// floating-point filter with an exact integer fallback.
+// floating-point filter with an exact integer fallback.  Geo::h holds p.
 #pragma once
 #include <stdint.h>
 
@@ -38,10 +39,14 @@ constexpr int kRingC = 32;   // background sample columns stored left of the ras
 struct Geo {
   int32_t W, H;
   int64_t stride;
-  int32_t h, s, CW, CH, NK, NI, NCB, wpr;
-  int32_t X0;  // x4 x-coordinate of vertex (0,0) = -2h-3
+  int32_t h, s, CW, CH, NK, NI, NCB, wpr;  // h: the grid edge in units of 1/U pixel (p)
+  int32_t X0;  // x of vertex (0,0) in units: -2p-3 (U = 1) or -(2p+3U)-1, odd
+  int32_t q, U;  // U = 2^q: one unit is 1 / (4U) pixel
   uint32_t flags;
-  float inv4s;  // 1 / (4 s)
+  float inv4s;    // 1 / (4 s)
+  double band;    // |value| below which a double-precision sign is recomputed exactly
+  double xscale;  // 0.25 / U: units -> pixels
+  double invU;    // 1 / U
 };
 
 // Sign of a + b*sqrt3, exact.  Zero only for a = b = 0.
@@ -66,32 +71,35 @@ constexpr double kSqrt3 = 1.7320508075688772;
 
 // Sign of a quantity whose exact value is a + b*sqrt3 (integers a, b with
 // |a|, |b| < 2^31) and whose double-precision evaluation in owner-local
-// coordinates is v (absolute error below 1e-9 for coordinates below 2^20).
-// Outside the +-1e-6 band the double decides; inside it the exact integer test.
-SBMT_HD int sgn_filtered(double v, int64_t a, int64_t b) {
-  if (v > 1e-6) return 1;
-  if (v < -1e-6) return -1;
+// coordinates is v.  The rounding error of v stays below about
+// 5e-15 s U^2 (image side in pixels); outside the band g.band (at least 1e-6,
+// and 20 times that bound) the double decides, inside it the exact test.
+SBMT_HD int sgn_filtered(double v, double band, int64_t a, int64_t b) {
+  if (v > band) return 1;
+  if (v < -band) return -1;
   return z3sign(a, b);
 }
 
-// floor(n / (4 s)) for |n| < 2^24 through a float reciprocal and one correction.
+// floor(n / (4 s U)) = floor((n >> q) / (4 s)) for |n >> q| < 2^24, through a
+// float reciprocal and one correction.
 SBMT_HD int div4s(const Geo& g, int n) {
   const int d = 4 * g.s;
-  int q = (int)__builtin_floorf((float)n * g.inv4s);
-  if (q * d > n) --q;
-  else if ((q + 1) * d <= n) ++q;
+  const int m = n >> g.q;
+  int q = (int)__builtin_floorf((float)m * g.inv4s);
+  if (q * d > m) --q;
+  else if ((q + 1) * d <= m) ++q;
   return q;
 }
 
-// Cell row of grid row k: the largest R with 2sR + s + 1 <= k*h*sqrt3, i.e.
-// floor((y_k - (s-1)/2) / s) for y_k = -1 + k h sqrt3 / 2.
-SBMT_HD int row_cell(int k, int h, int s) {
-  const int64_t kh = (int64_t)k * h;
-  // estimate in double precision (off by at most one for k h < 2^31), then
-  // exact steps
-  int64_t R = (int64_t)__builtin_floor(((double)kh * kSqrt3 - (double)(s + 1)) / (double)(2 * s));
-  while (z3sign(-(2 * s * R + s + 1), kh) < 0) --R;
-  while (z3sign(-(2 * s * (R + 1) + s + 1), kh) >= 0) ++R;
+// Cell row of grid row k: the largest R with U (2sR + s + 1) <= k p sqrt3,
+// i.e. floor((y_k - (s-1)/2) / s) for y_k = -1 + k h sqrt3 / 2, h = p / U.
+SBMT_HD int row_cell(const Geo& g, int k) {
+  const int s = g.s;
+  const int64_t kp = (int64_t)k * g.h;
+  // estimate in double precision (off by at most one), then exact steps
+  int64_t R = (int64_t)__builtin_floor(((double)kp * kSqrt3 * g.invU - (double)(s + 1)) / (double)(2 * s));
+  while (z3sign(-(int64_t)g.U * (2 * s * R + s + 1), kp) < 0) --R;
+  while (z3sign(-(int64_t)g.U * (2 * s * (R + 1) + s + 1), kp) >= 0) ++R;
   return (int)R;
 }
 
@@ -163,7 +171,7 @@ SBMT_HD uint32_t sample3(const Bits& b, int rr, int cc) {
   return (uint32_t)(v >> s) & 7u;
 }
 
-SBMT_HD int clo_of(const Geo& g, int X) { return div4s(g, X - 2 * g.h - 2 * (g.s - 1)); }
+SBMT_HD int clo_of(const Geo& g, int X) { return div4s(g, X - 2 * g.h - 2 * (g.s - 1) * g.U); }
 
 SBMT_HD Frame owner_frame(const Geo& g, const Bits& bits, int k, int i, int Rlo) {
   Frame f;
@@ -242,17 +250,17 @@ struct Slow {
                    // midpoint at [16 + 8t, 20 + 8t) (15 = none)
 };
 
-// Midpoint m sits at (xs + 2s XI(m), ys + 2s YI(m)) from the block's first sample.
+// Midpoint m sits at (xs + 2sU XI(m), ys + 2sU YI(m)) from the block's first sample.
 constexpr uint64_t kMidXI = 0x420420313131ull;  // nibble m: 1,3,1,3,1,3, 0,2,4, 0,2,4 (from m = 0)
 constexpr uint64_t kMidYI = 0x333111442200ull;  // nibble m: 0,0,2,2,4,4, 1,1,1, 3,3,3
 SBMT_HD int mid_xi(int m) { return (int)((kMidXI >> (4 * m)) & 15u); }
 SBMT_HD int mid_yi(int m) { return (int)((kMidYI >> (4 * m)) & 15u); }
 // (both factors of the last product fit in 24 bits: a full-rate multiply)
 SBMT_HD int mid_x(const Geo& g, const Frame& f, int m) {
-  return 4 * g.s * f.Clo + 2 * (g.s - 1) + (int)((uint32_t)(2 * g.s & 0xffff) * (uint32_t)mid_xi(m));
+  return g.U * (4 * g.s * f.Clo + 2 * (g.s - 1)) + (int)((uint32_t)(2 * g.s * g.U & 0xffff) * (uint32_t)mid_xi(m));
 }
 SBMT_HD int mid_y(const Geo& g, const Frame& f, int m) {
-  return 4 * g.s * f.Rlo + 2 * (g.s - 1) + (int)((uint32_t)(2 * g.s & 0xffff) * (uint32_t)mid_yi(m));
+  return g.U * (4 * g.s * f.Rlo + 2 * (g.s - 1)) + (int)((uint32_t)(2 * g.s * g.U & 0xffff) * (uint32_t)mid_yi(m));
 }
 SBMT_HD int slot_p(const SegSlots& seg, int a) { return (int)((seg.p >> (4 * a)) & 15u); }
 SBMT_HD int slot_q(const SegSlots& seg, int a) { return (int)((seg.q >> (4 * a)) & 15u); }
@@ -385,7 +393,7 @@ SBMT_HD void block_segments(const Frame& f, S& seg, uint32_t& valid) {
 template <class S>
 SBMT_HD uint32_t relevant_slots(const Geo& g, const Frame& f, const S& seg, uint32_t valid) {
   const int xlo = f.X - 2 * g.h, xhi = f.X + 4 * g.h;
-  const double yk = -4.0 + (double)(2 * (int64_t)g.h * f.k) * kSqrt3;
+  const double yk = (double)(-4 * g.U) + (double)(2 * (int64_t)g.h * f.k) * kSqrt3;
   const int ylo = (int)__builtin_floor(yk) - 1;
   const int yhi = (int)__builtin_ceil(yk + 2.0 * g.h * kSqrt3) + 1;
   uint32_t rel = 0;
@@ -405,7 +413,7 @@ SBMT_HD uint32_t relevant_slots(const Geo& g, const Frame& f, const S& seg, uint
 template <class S>
 SBMT_HD int owner_inside(const Geo& g, const Frame& f, const S& seg, uint32_t valid) {
   const int X = f.X;
-  const int cv = div4s(g, X - 2 * (g.s - 1)) - f.Clo;
+  const int cv = div4s(g, X - 2 * (g.s - 1) * g.U) - f.Clo;
   const int a = (int)((f.s9 >> cv) & 1u), b = (int)((f.s9 >> (cv + 1)) & 1u);
   const int c = (int)((f.s9 >> (4 + cv)) & 1u), d = (int)((f.s9 >> (3 + cv)) & 1u);
   if (a == b && b == c && c == d) return a;
@@ -419,8 +427,10 @@ SBMT_HD int owner_inside(const Geo& g, const Frame& f, const S& seg, uint32_t va
       const int pm = slot_p(seg, sl), qm = slot_q(seg, sl);
       const int px = mid_x(g, f, pm), py = mid_y(g, f, pm);
       const int ex = mid_x(g, f, qm) - px, ey = mid_y(g, f, qm) - py;
-      const double v = ex * ((double)(-4 - py) + yb) - (double)ey * (X - px);
-      if (sgn_filtered(v, (int64_t)ex * (-4 - py) - (int64_t)ey * (X - px), (int64_t)ex * 2 * hk) < 0) fg = 0;
+      const int Y0 = -4 * g.U;
+      const double v = ex * ((double)(Y0 - py) + yb) - (double)ey * (X - px);
+      if (sgn_filtered(v, g.band, (int64_t)ex * (Y0 - py) - (int64_t)ey * (X - px), (int64_t)ex * 2 * hk) < 0)
+        fg = 0;
     }
   }
   return fg;
@@ -438,9 +448,9 @@ SBMT_HD uint32_t quiet_info(const Geo& g, const Frame& f, int fg) {
 // value v; in the latter case `ok` is cleared when |v| is inside the band
 // where the double could be wrong.
 template <bool EXACT>
-SBMT_HD int sgn_eval(double v, int64_t a, int64_t b, bool& ok) {
+SBMT_HD int sgn_eval(double v, double band, int64_t a, int64_t b, bool& ok) {
   if (EXACT) return z3sign(a, b);
-  ok = ok && (v > 1e-6 || v < -1e-6);
+  ok = ok && (v > band || v < -band);
   return v > 0 ? 1 : -1;
 }
 
@@ -449,16 +459,17 @@ SBMT_HD bool slot_signs(const Geo& g, const Frame& f, const SegSlots& seg, uint3
                         uint64_t& sp, uint64_t& sq, uint32_t& lv) {
   bool ok = true;
   const int h = g.h, X = f.X;
+  const double band = g.band;
   const int64_t hk = (int64_t)h * f.k;
-  const int ys = 4 * g.s * f.Rlo + 2 * (g.s - 1);
+  const int ys = g.U * (4 * g.s * f.Rlo + 2 * (g.s - 1));
   const double yk = (double)(2 * hk) * kSqrt3, yk1 = (double)(2 * (hk + h)) * kSqrt3;
   row0 = 0;
   row4 = 0;
 #pragma unroll
   for (int yi = 0; yi < 5; ++yi) {
-    const int Ay = ys + 2 * g.s * yi + 4;
-    row0 |= (uint32_t)(sgn_eval<EXACT>((double)Ay - yk, Ay, -2 * hk, ok) > 0) << yi;
-    row4 |= (uint32_t)(sgn_eval<EXACT>((double)Ay - yk1, Ay, -2 * (hk + h), ok) > 0) << yi;
+    const int Ay = ys + 2 * g.s * g.U * yi + 4 * g.U;
+    row0 |= (uint32_t)(sgn_eval<EXACT>((double)Ay - yk, band, Ay, -2 * hk, ok) > 0) << yi;
+    row4 |= (uint32_t)(sgn_eval<EXACT>((double)Ay - yk1, band, Ay, -2 * (hk + h), ok) > 0) << yi;
   }
   sp = 0;
   sq = 0;
@@ -473,29 +484,30 @@ SBMT_HD bool slot_signs(const Geo& g, const Frame& f, const SegSlots& seg, uint3
 #pragma unroll
     for (int z = 0; z < 2; ++z) {
       const int m = z == 0 ? pm : qm;
-      const int Ay = mid_y(g, f, m) + 4, lx = mid_x(g, f, m) - X, yi = mid_yi(m);
+      const int Ay = mid_y(g, f, m) + 4 * g.U, lx = mid_x(g, f, m) - X, yi = mid_yi(m);
       const double ly = (double)Ay - yk;
       uint32_t b5 = ((row0 >> yi) & 1u) | (((row4 >> yi) & 1u) << 4);
-      b5 |= (uint32_t)(sgn_eval<EXACT>(ly + kSqrt3 * lx, Ay, lx - 2 * hk, ok) < 0) << 1;
-      b5 |= (uint32_t)(sgn_eval<EXACT>(ly - kSqrt3 * lx, Ay, -(lx + 2 * hk), ok) > 0) << 2;
-      b5 |= (uint32_t)(sgn_eval<EXACT>(ly + kSqrt3 * (lx - 4 * h), Ay, lx - 4 * h - 2 * hk, ok) < 0) << 3;
+      b5 |= (uint32_t)(sgn_eval<EXACT>(ly + kSqrt3 * lx, band, Ay, lx - 2 * hk, ok) < 0) << 1;
+      b5 |= (uint32_t)(sgn_eval<EXACT>(ly - kSqrt3 * lx, band, Ay, -(lx + 2 * hk), ok) > 0) << 2;
+      b5 |= (uint32_t)(sgn_eval<EXACT>(ly + kSqrt3 * (lx - 4 * h), band, Ay, lx - 4 * h - 2 * hk, ok) < 0) << 3;
       e5[z] = b5;
     }
     sp |= (uint64_t)e5[0] << (8 * a);
     sq |= (uint64_t)e5[1] << (8 * a);
-    // orient(P, Q, L) = ex (Ly - Py) - ey (Lx - Px), Ly = -4 + LB sqrt3
+    // orient(P, Q, L) = ex (Ly - Py) - ey (Lx - Px), Ly = -4U + LB sqrt3
     const int px = mid_x(g, f, pm), py = mid_y(g, f, pm);
     const int ex = mid_x(g, f, qm) - px, ey = mid_y(g, f, qm) - py;
-    const int64_t base = (int64_t)ex * (-4 - py);
-    const double d01 = (double)(-4 - py) + yb01, d23 = (double)(-4 - py) + yb23;
-    uint32_t l4 = (uint32_t)(sgn_eval<EXACT>(ex * d01 - (double)ey * (LX0 - px), base - (int64_t)ey * (LX0 - px),
-                                             ex * LB01, ok) > 0);
-    l4 |= (uint32_t)(sgn_eval<EXACT>(ex * d01 - (double)ey * (LX1 - px), base - (int64_t)ey * (LX1 - px), ex * LB01,
-                                     ok) > 0) << 1;
-    l4 |= (uint32_t)(sgn_eval<EXACT>(ex * d23 - (double)ey * (LX2 - px), base - (int64_t)ey * (LX2 - px), ex * LB23,
-                                     ok) > 0) << 2;
-    l4 |= (uint32_t)(sgn_eval<EXACT>(ex * d23 - (double)ey * (LX3 - px), base - (int64_t)ey * (LX3 - px), ex * LB23,
-                                     ok) > 0) << 3;
+    const int Yp = -4 * g.U - py;
+    const int64_t base = (int64_t)ex * Yp;
+    const double d01 = (double)Yp + yb01, d23 = (double)Yp + yb23;
+    uint32_t l4 = (uint32_t)(sgn_eval<EXACT>(ex * d01 - (double)ey * (LX0 - px), band,
+                                             base - (int64_t)ey * (LX0 - px), ex * LB01, ok) > 0);
+    l4 |= (uint32_t)(sgn_eval<EXACT>(ex * d01 - (double)ey * (LX1 - px), band, base - (int64_t)ey * (LX1 - px),
+                                     ex * LB01, ok) > 0) << 1;
+    l4 |= (uint32_t)(sgn_eval<EXACT>(ex * d23 - (double)ey * (LX2 - px), band, base - (int64_t)ey * (LX2 - px),
+                                     ex * LB23, ok) > 0) << 2;
+    l4 |= (uint32_t)(sgn_eval<EXACT>(ex * d23 - (double)ey * (LX3 - px), band, base - (int64_t)ey * (LX3 - px),
+                                     ex * LB23, ok) > 0) << 3;
     lv |= l4 << (4 * a);
   }
   return ok;
@@ -556,7 +568,7 @@ SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
         else err = true;
         const int M = slot_q(seg, s1), P0 = slot_p(seg, s1), P2 = slot_q(seg, s2);
         const int mx = mid_x(g, f, M), my = mid_y(g, f, M);
-        // offsets inside one block of 2 x 2 cells: |d| <= 8 s, products fit in 32 bits
+        // offsets inside one block of 2 x 2 cells: |d| <= 8 s U, products fit in 32 bits
         const int cr = (mid_x(g, f, P0) - mx) * (mid_y(g, f, P2) - my) - (mid_y(g, f, P0) - my) * (mid_x(g, f, P2) - mx);
         const bool mpos = (sq >> (8 * s1 + e)) & 1u;
         const bool later = (cr > 0) == mpos;
@@ -653,8 +665,10 @@ SBMT_HD SlowRec pack_slow(const Slow& r) {
 // global ids taken from the owner offsets.
 // ---------------------------------------------------------------------------
 constexpr double kHalfSqrt3 = 0.86602540378443864676;
-SBMT_HD double lat_x(int X) { return 0.25 * (double)X; }
-SBMT_HD double lat_y(int h, int k) { return -1.0 + (double)(h * k) * kHalfSqrt3; }
+// pixel coordinates: x = X / (4U) (an exact scaling), y = -1 + (p k / U) sqrt3/2
+SBMT_HD double lat_x(const Geo& g, int X) { return (double)X * g.xscale; }
+SBMT_HD double to_px(const Geo& g, int v) { return (double)v * g.xscale; }
+SBMT_HD double lat_y(const Geo& g, int k) { return -1.0 + ((double)((int64_t)g.h * k) * g.invU) * kHalfSqrt3; }
 
 // Where emission writes: vertex p goes to v[p - vbase], triangle t to
 // t[t - tbase] / c[t - tbase] (the kernels stage a row of output in LDS).
@@ -722,19 +736,19 @@ SBMT_HD void emit_slow_vertex(const Geo& g, const Frame& f, const SlowRec& r, in
   const uint32_t info = r.info;
   const int self = info_self(info);
   const int n0 = info_n(info, 0), n1 = info_n(info, 1), n2 = info_n(info, 2);
-  const double ux = lat_x(f.X), uy = lat_y(g.h, f.k);
+  const double ux = lat_x(g, f.X), uy = lat_y(g, f.k);
   double x = ux, y = uy;
   const int s = sub - self;
   if (s >= 0 && s < n0 + n1 + n2) {
     const int e = s < n0 ? 0 : (s < n0 + n1 ? 1 : 2);
     const int re = s - (e == 0 ? 0 : (e == 1 ? n0 : n0 + n1));
     const int vX = e == 0 ? f.X + 4 * g.h : (e == 1 ? f.X - 2 * g.h : f.X + 2 * g.h);
-    const double vx = lat_x(vX), vy = lat_y(g.h, e == 0 ? f.k : f.k + 1);
+    const double vx = lat_x(g, vX), vy = lat_y(g, e == 0 ? f.k : f.k + 1);
     const double gx = vx - ux, gy = vy - uy;
     const uint32_t pq = (uint32_t)(r.x >> (16 * e + 8 * re)) & 255u;
     const int pm = (int)(pq & 15u), qm = (int)(pq >> 4);
-    const double px = 0.25 * (double)mid_x(g, f, pm), py = 0.25 * (double)mid_y(g, f, pm);
-    const double qx = 0.25 * (double)mid_x(g, f, qm), qy = 0.25 * (double)mid_y(g, f, qm);
+    const double px = to_px(g, mid_x(g, f, pm)), py = to_px(g, mid_y(g, f, pm));
+    const double qx = to_px(g, mid_x(g, f, qm)), qy = to_px(g, mid_y(g, f, qm));
     const double dp = gx * (py - uy) - gy * (px - ux);
     const double dq = gx * (qy - uy) - gy * (qx - ux);
     const double tt = dp / (dp - dq);
@@ -743,8 +757,8 @@ SBMT_HD void emit_slow_vertex(const Geo& g, const Frame& f, const SlowRec& r, in
   } else if (s >= 0) {
     const int mb = (int)((r.tri >> 16) & 15u), ma = (int)((r.tri >> 20) & 15u);
     const int m = (s == n0 + n1 + n2 && mb != 15) ? mb : ma;
-    x = 0.25 * (double)mid_x(g, f, m);
-    y = 0.25 * (double)mid_y(g, f, m);
+    x = to_px(g, mid_x(g, f, m));
+    y = to_px(g, mid_y(g, f, m));
   }
   put_vertex(out.v, vid + sub - out.vbase, x, y);
 }

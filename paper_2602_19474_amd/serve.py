@@ -82,7 +82,7 @@ class Arena:
 class Request:
     rid: int
     bitmap: object
-    grid_h: int
+    grid_h: float
     arrival: float
     pixels: int = 0
     t_admit: float = math.nan
@@ -137,7 +137,7 @@ class Server:
         self._next_id = 0
 
     # -- client side -----------------------------------------------------------
-    def submit(self, bitmap, grid_h: int, arrival: float | None = None) -> Request:
+    def submit(self, bitmap, grid_h: float, arrival: float | None = None) -> Request:
         r = Request(self._next_id, bitmap, int(grid_h), self.backend.now() if arrival is None else float(arrival))
         r.pixels = int(self.backend.pixels(bitmap))
         self._next_id += 1

@@ -75,7 +75,9 @@ def test_query_geometry_matches_the_oracle(L):
 
     import oracle
     import paper_2602_19474_amd as sbmt
-    for (H, W, h) in ((64, 64, 1), (100, 37, 2), (5, 300, 4), (1, 1, 3), (257, 301, 5), (33, 65, 6)):
+    for (H, W, h) in ((64, 64, 1), (100, 37, 2), (5, 300, 4), (1, 1, 3), (257, 301, 5), (33, 65, 6),
+                      (64, 64, 0.5), (100, 37, 0.75), (5, 300, 1.25), (40, 41, 1.5), (33, 17, 0.375),
+                      (20, 12, 1.0 / 64), (9, 7, 1.0 / 256)):
         lay = sbmt.query(W, H, h)
         m = oracle.mesh_from_bitmap(np.zeros((H, W), np.uint8), h)
         assert (lay.grid_rows, lay.grid_cols, lay.stride_s) == m.grid
@@ -84,10 +86,15 @@ def test_query_geometry_matches_the_oracle(L):
 
 def test_invalid_arguments_rejected_on_host(L):
     import paper_2602_19474_amd as sbmt
-    for bad_h in (0, 7, 8, -1):
+    for bad_h in (0, 7, 8, -1, 0.3, 1.0 / 3.0, 1.0 / 512, 6.5):
         with pytest.raises(sbmt.SbmtError) as e:
             sbmt.query(64, 64, bad_h)
         assert e.value.status == -2
+    # exact predicates in 64-bit integers bound the image side at fine grid edges
+    sbmt.query(2000, 100, 1.0 / 256)
+    with pytest.raises(sbmt.SbmtError) as e:
+        sbmt.query(4000, 100, 1.0 / 256)
+    assert e.value.status == -2
     with pytest.raises(sbmt.SbmtError) as e:
         sbmt.query(-1, 64, 1)
     assert e.value.status == -1

@@ -202,3 +202,32 @@ def test_tall_and_wide_strips(h):
     strip = wl.smoothed_noise(24, 1 << 20, 2.0, 0.0, False, g)
     _compare("tall strip", strip, h, check_invariants=False)
     _compare("wide strip", np.ascontiguousarray(strip.T), h, check_invariants=False)
+
+
+@pytest.mark.parametrize("h", [0.5, 0.75, 1.25, 1.5, 2.5, 0.375])
+def test_dyadic_grid_edges(h):
+    """Grid edges p / 2^q, including the paper's h < 1 (Sec. 3.3)."""
+    g = wl.rng(79, int(h * 8))
+    _compare("disk64", wl.disk(item=1), h)
+    _compare("ellipses", wl.ellipses(400, 330, g=g), h)
+    _compare("noise", wl.smoothed_noise(257, 301, 4.0, 0.0, False, g), h, both=(h == 0.75))
+
+
+def test_dyadic_brute_force_3x3():
+    for h in (0.5, 0.75, 1.5):
+        s = mc.stride_for(h)
+        print(f"[gpu-parity] dyadic brute force h={h}", flush=True)
+        for ci, b in enumerate(itertools.product([0, 1], repeat=9)):
+            big = np.kron(np.array(b, np.uint8).reshape(3, 3), np.ones((s, s), np.uint8))
+            bm = np.zeros((big.shape[0] + ci % 3, big.shape[1] + (ci // 3) % 3), np.uint8)
+            bm[ci % 3:, (ci // 3) % 3:] = big
+            _compare(f"bf{ci}", bm, h, check_invariants=False)
+
+
+def test_fine_grid_edges():
+    """h = 1/64 and 1/16: coordinates in units of 1/256 and 1/64 pixel, so the
+    exact predicates and the floating-point band are 4096 and 256 times wider
+    than at integer h for the same image."""
+    g = wl.rng(80, 0)
+    _compare("h=1/64", wl.smoothed_noise(60, 50, 3.0, 0.0, False, g), 1.0 / 64)
+    _compare("h=1/16 strip", wl.smoothed_noise(2000, 3, 3.0, 0.0, False, g), 1.0 / 16, check_invariants=False)

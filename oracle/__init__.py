@@ -73,6 +73,18 @@ def lib():
         L.oracle_class_table.argtypes = [vp, i32]
         L.oracle_template_of_code.restype = i32
         L.oracle_template_of_code.argtypes = [i32, vp]
+        L.oracle_mesh_preprocessed.restype = vp
+        L.oracle_mesh_preprocessed.argtypes = [vp, i32, i32, i64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_char_p, i32]
+        for name in ("oracle_pre_n_vertices", "oracle_pre_n_triangles"):
+            getattr(L, name).restype = i64
+            getattr(L, name).argtypes = [vp]
+        L.oracle_pre_counts.restype = None
+        L.oracle_pre_counts.argtypes = [vp, vp]
+        L.oracle_pre_copy.restype = None
+        L.oracle_pre_copy.argtypes = [vp, vp, vp, vp]
+        L.oracle_pre_free.restype = None
+        L.oracle_pre_free.argtypes = [vp]
         L.oracle_canonical.restype = i32
         L.oracle_canonical.argtypes = [i32, vp, vp]
         L.oracle_z3_sign.restype = i32
@@ -155,6 +167,52 @@ def mesh_from_bitmap(bitmap: np.ndarray, grid_h, flags: int = 0) -> OracleMesh:
                           (nk.value, ni.value, s.value))
     finally:
         L.oracle_free(res)
+
+
+# Thresholds of the paper's experiments at base edge sqrt(0.45) (Sec. 4):
+# snap a, edge elimination b, foot projection c.
+PAPER_THRESHOLDS = (0.26, 0.125, 0.183)
+PAPER_EDGE = 0.45 ** 0.5
+
+
+@dataclass
+class PreMesh:
+    verts: np.ndarray   # float64 [V, 2], sorted by (y, x)
+    tris: np.ndarray    # int32 [T, 3], rotated to the smallest index, sorted
+    codes: np.ndarray   # uint8 [T]: 0 uncut base triangle, 1 piece of a cut one
+    n_snapped: int
+    n_repelled: int
+    n_inserted: int
+    n_cut: int
+    thresholds: tuple
+
+
+def mesh_preprocessed(bitmap: np.ndarray, grid_h, a=None, b=None, c=None) -> PreMesh:
+    """Foreground mesh after the preprocessing of Alg. 3 (snap a, repel c, edge
+    elimination b; pixels).  Defaults: the paper's thresholds scaled by
+    grid_h / sqrt(0.45)."""
+    L = lib()
+    sc = float(grid_h) / PAPER_EDGE
+    a = PAPER_THRESHOLDS[0] * sc if a is None else float(a)
+    b = PAPER_THRESHOLDS[1] * sc if b is None else float(b)
+    c = PAPER_THRESHOLDS[2] * sc if c is None else float(c)
+    bm = np.ascontiguousarray(bitmap, dtype=np.uint8)
+    H, W = bm.shape
+    err = ctypes.create_string_buffer(512)
+    res = L.oracle_mesh_preprocessed(bm.ctypes.data if bm.size else None, W, H, W, float(grid_h), a, b, c, err, 512)
+    if not res:
+        raise OracleError(err.value.decode())
+    try:
+        nv, nt = L.oracle_pre_n_vertices(res), L.oracle_pre_n_triangles(res)
+        verts = np.zeros((nv, 2), np.float64)
+        tris = np.zeros((nt, 3), np.int32)
+        codes = np.zeros((nt,), np.uint8)
+        L.oracle_pre_copy(res, verts.ctypes.data, tris.ctypes.data, codes.ctypes.data)
+        cnt = np.zeros(4, np.int64)
+        L.oracle_pre_counts(res, cnt.ctypes.data)
+        return PreMesh(verts, tris, codes, *(int(x) for x in cnt), (a, b, c))
+    finally:
+        L.oracle_pre_free(res)
 
 
 def class_table() -> np.ndarray:

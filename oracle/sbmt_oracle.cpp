@@ -34,11 +34,15 @@
 // canonicalisation, the template rule for free cases, output numbering) are
 // listed in the repository's design notes and restated where they are used.
 //
-// Parity unpinned: the minimum-angle and minimum-area bounds of App. D hold
-// only after the preprocessing of Alg. 3, which this path does not run (the
-// "all rules off" regime of the ablation); meshes are checked for positive
-// area and orientation only, not against those bounds.
+// The main path is the "all rules off" regime of the ablation (no
+// preprocessing); its meshes carry no angle or area bound.  A second path,
+// oracle_mesh_preprocessed, runs the preprocessing of Alg. 3 first (vertex
+// snapping a, repulsion c, edge elimination b) and retriangulates against the
+// polyline in double precision; it is pinned by the bounds of Sec. 3.3.4 and
+// App. D on every triangle, by the mesh invariants and by reducing exactly to
+// the main path when every threshold is zero.  It has no GPU counterpart.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -536,6 +540,43 @@ class Oracle {
     NK_ = m + 1;
     // columns: the last vertex lies right of x = s CW - 1/2
     NI_ = (4LL * U_ * s_ * CW_ - 2LL * U_ - X0_) / (4LL * h_) + 2;
+  }
+
+  // The polylines, grid and exact inside labels of the lattice vertices, for
+  // the preprocessing pass of Alg. 3 (PreOracle below).
+  struct Traced {
+    std::vector<double> px, py;      // polyline vertex j = start of segment j, pixels
+    std::vector<i64> next, prev;     // segment links along the closed contours
+    std::vector<uint8_t> inside;     // lattice vertex (k, i) inside the polylines
+    i64 NK = 0, NI = 0;
+    int s = 1;
+    double h = 1;
+    std::vector<double> lx, ly;      // lattice vertex positions, pixels (lx per vertex, ly per row)
+  };
+  Traced traced() {
+    coarsen();
+    trace();
+    build_registry();
+    label_inside();
+    Traced t;
+    for (const Segment& sg : segs_) {
+      t.px.push_back(to_px(sg.p.x));
+      t.py.push_back(to_px(sg.p.ya));
+      t.next.push_back(sg.next);
+      t.prev.push_back(sg.prev);
+    }
+    t.inside = inside_;
+    t.NK = NK_;
+    t.NI = NI_;
+    t.s = s_;
+    t.h = (double)h_ / (double)U_;
+    t.lx.resize((size_t)(NK_ * NI_));
+    t.ly.resize((size_t)NK_);
+    for (i64 k = 0; k < NK_; ++k) {
+      t.ly[(size_t)k] = lat_yd(k);
+      for (i64 i = 0; i < NI_; ++i) t.lx[(size_t)(k * NI_ + i)] = lat_xd(k, i);
+    }
+    return t;
   }
 
   Mesh run() {
@@ -1045,6 +1086,622 @@ class Oracle {
   }
 };
 
+// ===========================================================================
+// Geometric preprocessing of Alg. 3 (Sec. 3.5), then the template
+// retriangulation of the preprocessed mesh (Alg. 1 and 2 with corner contacts).
+//
+// Readings (the paper leaves them open):
+//  * Step 1 snaps a lattice vertex to the closest polyline vertex (a boundary
+//    point of the set L) within distance a; ties go to the lower polyline index.
+//    (With the polyline vertices as the snapping targets, a vertex within c of
+//    two segments meeting at a corner lies within c*sqrt2 < a of the corner and
+//    is snapped, so no vertex is repelled by two segments: the reason given for
+//    c < a/sqrt2.)
+//  * Step 2 runs on the vertices Step 1 left in place: the closest segment
+//    within distance c pushes the vertex along its normal to distance exactly
+//    c, on the same side.
+//  * Step 3 takes the polyline vertices in order: a mesh edge within distance b
+//    of p_j (not ending at p_j) is removed with its triangles and the cavity is
+//    fanned from p_j.
+//  * Each triangle of the preprocessed mesh is cut by the pieces of the
+//    polyline inside it (degenerate contacts: the polyline passes through a
+//    corner that was snapped to, or inserted at, a polyline vertex); each
+//    foreground face is triangulated by the template rule of the plain path:
+//    fanned from the chain vertex inside the triangle if it has one, the
+//    middle quadrilateral between two chords split by the diagonal joining the
+//    chords' exits, else fanned from the face's earliest chain point.
+// All decisions are taken in double precision: after the three steps every
+// vertex off the polyline lies at least c from every segment and every
+// polyline vertex off the mesh vertices at least b from every mesh edge, so
+// each sign has a margin far above the rounding error; contacts at a corner are
+// decided by identity (the corner is that polyline vertex).
+// Output: vertices sorted by (y, x), triangles rotated to their smallest index
+// and sorted; codes 0 for uncut triangles, 1 for pieces of cut ones.
+// ===========================================================================
+struct PreResult {
+  std::vector<double> verts;
+  std::vector<int32_t> tris;
+  std::vector<uint8_t> codes;
+  i64 n_snapped = 0, n_repelled = 0, n_inserted = 0, n_cut = 0;
+};
+
+class PreOracle {
+ public:
+  PreOracle(Oracle::Traced t, double a, double b, double c) : T_(std::move(t)), a_(a), b_(b), c_(c) {
+    cs_ = std::max(T_.h, 1.0);
+  }
+
+  PreResult run() {
+    index_polyline();
+    snap_and_repel();
+    build_triangles();
+    eliminate_edges();
+    retriangulate();
+    return finish();
+  }
+
+ private:
+  struct V { double x, y; i64 bnd; };  // bnd: polyline vertex it sits on, or -1
+  Oracle::Traced T_;
+  double a_, b_, c_, cs_;
+  std::vector<V> vs_;                  // mesh vertices: lattice (k NI + i), then inserted points
+  std::vector<std::array<i64, 3>> tri_;
+  std::vector<uint8_t> alive_;
+  std::vector<std::vector<i64>> slot_;  // base triangle slot (k NI + i) * 2 + t -> its current triangles
+  std::vector<i64> slot_of_;            // triangle -> base slot
+  std::unordered_map<i64, std::vector<i64>> pcell_, scell_;  // cell -> polyline vertices / segments
+  PreResult out_;
+  // output points: key -> id, coordinates
+  std::map<std::array<i64, 3>, i64> pkey_;
+  std::vector<double> ox_, oy_;
+  std::vector<std::array<i64, 3>> otri_;
+  std::vector<uint8_t> ocode_;
+
+  i64 nseg() const { return (i64)T_.px.size(); }
+  double qx(i64 s) const { return T_.px[(size_t)T_.next[(size_t)s]]; }
+  double qy(i64 s) const { return T_.py[(size_t)T_.next[(size_t)s]]; }
+  i64 ckey(i64 cx, i64 cy) const { return (cx + (1LL << 30)) * (1LL << 31) + (cy + (1LL << 30)); }
+  i64 cell(double v) const { return (i64)std::floor(v / cs_); }
+
+  void index_polyline() {
+    for (i64 j = 0; j < nseg(); ++j) {
+      pcell_[ckey(cell(T_.px[(size_t)j]), cell(T_.py[(size_t)j]))].push_back(j);
+      const double x0 = std::min(T_.px[(size_t)j], qx(j)) - 1.0, x1 = std::max(T_.px[(size_t)j], qx(j)) + 1.0;
+      const double y0 = std::min(T_.py[(size_t)j], qy(j)) - 1.0, y1 = std::max(T_.py[(size_t)j], qy(j)) + 1.0;
+      for (i64 cx = cell(x0); cx <= cell(x1); ++cx)
+        for (i64 cy = cell(y0); cy <= cell(y1); ++cy) scell_[ckey(cx, cy)].push_back(j);
+    }
+  }
+  template <class F>
+  void near(const std::unordered_map<i64, std::vector<i64>>& m, double x, double y, double r, F f) const {
+    for (i64 cx = cell(x - r); cx <= cell(x + r); ++cx)
+      for (i64 cy = cell(y - r); cy <= cell(y + r); ++cy) {
+        auto it = m.find(ckey(cx, cy));
+        if (it == m.end()) continue;
+        for (i64 j : it->second) f(j);
+      }
+  }
+  // distance from (x, y) to segment j, and the parameter of the closest point
+  double seg_dist(i64 j, double x, double y, double* tpar) const {
+    const double px = T_.px[(size_t)j], py = T_.py[(size_t)j];
+    const double dx = qx(j) - px, dy = qy(j) - py;
+    double t = ((x - px) * dx + (y - py) * dy) / (dx * dx + dy * dy);
+    t = std::min(1.0, std::max(0.0, t));
+    if (tpar) *tpar = t;
+    return std::hypot(x - (px + t * dx), y - (py + t * dy));
+  }
+
+  // Steps 1 and 2: vertex snapping (a), then repulsion (c) of the vertices left
+  void snap_and_repel() {
+    const i64 NK = T_.NK, NI = T_.NI;
+    vs_.resize((size_t)(NK * NI));
+    for (i64 k = 0; k < NK; ++k)
+      for (i64 i = 0; i < NI; ++i) {
+        V& v = vs_[(size_t)(k * NI + i)];
+        v.x = T_.lx[(size_t)(k * NI + i)];
+        v.y = T_.ly[(size_t)k];
+        v.bnd = -1;
+        double best = a_;
+        i64 bj = -1;
+        near(pcell_, v.x, v.y, a_, [&](i64 j) {
+          const double d = std::hypot(v.x - T_.px[(size_t)j], v.y - T_.py[(size_t)j]);
+          if (d < best || (d == best && bj >= 0 && j < bj)) { best = d; bj = j; }
+        });
+        if (bj >= 0) {
+          v.x = T_.px[(size_t)bj];
+          v.y = T_.py[(size_t)bj];
+          v.bnd = bj;
+          ++out_.n_snapped;
+        }
+      }
+    for (V& v : vs_) {
+      if (v.bnd >= 0) continue;
+      double best = c_;
+      i64 bj = -1;
+      std::vector<i64> close;
+      near(scell_, v.x, v.y, c_, [&](i64 j) {
+        double t;
+        const double d = seg_dist(j, v.x, v.y, &t);
+        if (d < c_) close.push_back(j);
+        if (d < best || (d == best && bj >= 0 && j < bj)) { best = d; bj = j; }
+      });
+      std::sort(close.begin(), close.end());
+      const int nclose = (int)(std::unique(close.begin(), close.end()) - close.begin());
+      if (bj < 0) continue;
+      // each vertex is acted upon by at most one segment (c < a / sqrt2)
+      ORACLE_CHECK(nclose == 1, "a vertex within c of two segments");
+      double t;
+      seg_dist(bj, v.x, v.y, &t);
+      ORACLE_CHECK(t > 0.0 && t < 1.0, "repulsion foot at a segment end");
+      const double px = T_.px[(size_t)bj], py = T_.py[(size_t)bj];
+      const double dx = qx(bj) - px, dy = qy(bj) - py, L = std::hypot(dx, dy);
+      const double nx = -dy / L, ny = dx / L;                 // left normal
+      const double d = (v.x - px) * nx + (v.y - py) * ny;     // signed distance to the line
+      const double move = (d > 0 ? c_ : -c_) - d;
+      v.x += move * nx;
+      v.y += move * ny;
+      ++out_.n_repelled;
+    }
+    // every vertex off the polyline now lies at least c from every segment
+    for (const V& v : vs_) {
+      if (v.bnd >= 0) continue;
+      near(scell_, v.x, v.y, c_, [&](i64 j) {
+        ORACLE_CHECK(seg_dist(j, v.x, v.y, nullptr) > c_ * (1.0 - 1e-9), "vertex closer than c after Step 2");
+      });
+    }
+  }
+
+  double area2(i64 a, i64 b, i64 c) const {
+    const V &A = vs_[(size_t)a], &B = vs_[(size_t)b], &C = vs_[(size_t)c];
+    return (B.x - A.x) * (C.y - A.y) - (B.y - A.y) * (C.x - A.x);
+  }
+
+  void build_triangles() {
+    const i64 NK = T_.NK, NI = T_.NI;
+    slot_.resize((size_t)(NK * NI * 2));
+    for (i64 k = 0; k + 1 < NK; ++k)
+      for (i64 i = 0; i < NI; ++i) {
+        const i64 o = k & 1;
+        for (int t = 0; t < 2; ++t) {
+          i64 ck[3] = {k, t == 0 ? k + 1 : k, k + 1};
+          i64 ci[3] = {i, t == 0 ? i + o : i + 1, t == 0 ? i + o - 1 : i + o};
+          bool ok = true;
+          for (int j = 0; j < 3; ++j) ok = ok && ci[j] >= 0 && ci[j] < NI;
+          if (!ok) continue;
+          std::array<i64, 3> tr = {ck[0] * NI + ci[0], ck[1] * NI + ci[1], ck[2] * NI + ci[2]};
+          ORACLE_CHECK(area2(tr[0], tr[1], tr[2]) > 0, "a base triangle inverted by the vertex moves");
+          add_tri(tr, (k * NI + i) * 2 + t);
+        }
+      }
+  }
+  void add_tri(const std::array<i64, 3>& tr, i64 slot) {
+    slot_[(size_t)slot].push_back((i64)tri_.size());
+    slot_of_.push_back(slot);
+    tri_.push_back(tr);
+    alive_.push_back(1);
+  }
+
+  static double pt_seg(double x, double y, double ax, double ay, double bx, double by) {
+    const double dx = bx - ax, dy = by - ay;
+    double t = ((x - ax) * dx + (y - ay) * dy) / (dx * dx + dy * dy);
+    t = std::min(1.0, std::max(0.0, t));
+    return std::hypot(x - (ax + t * dx), y - (ay + t * dy));
+  }
+
+  // Step 3: edge elimination (b) and cavity retriangulation around p_j
+  void eliminate_edges() {
+    const i64 NI = T_.NI;
+    const double rh = T_.h * 0.86602540378443864676;
+    std::vector<i64> on_vertex(nseg(), -1);
+    for (size_t v = 0; v < vs_.size(); ++v)
+      if (vs_[v].bnd >= 0) on_vertex[(size_t)vs_[v].bnd] = (i64)v;
+    std::vector<uint8_t> touched(tri_.size(), 0);
+    for (i64 j = 0; j < nseg(); ++j) {
+      if (on_vertex[(size_t)j] >= 0) continue;
+      const double x = T_.px[(size_t)j], y = T_.py[(size_t)j];
+      // candidate triangles: the base slots around p_j (vertices moved by less than a < h/2)
+      const i64 k0 = (i64)std::floor((y + 1.0) / rh);
+      std::vector<std::pair<i64, i64>> edges;  // (u, w), u < w
+      for (i64 k = k0 - 2; k <= k0 + 2; ++k) {
+        if (k < 0 || k + 1 >= T_.NK) continue;
+        const double xo = T_.lx[(size_t)(k * NI)];
+        const i64 ic = (i64)std::floor((x - xo) / T_.h);
+        for (i64 i = ic - 3; i <= ic + 3; ++i) {
+          if (i < 0 || i >= NI) continue;
+          for (int t = 0; t < 2; ++t)
+            for (i64 tid : slot_[(size_t)((k * NI + i) * 2 + t)]) {
+              if (!alive_[(size_t)tid]) continue;
+              const auto& tr = tri_[(size_t)tid];
+              for (int e = 0; e < 3; ++e) {
+                const i64 u = tr[e], w = tr[(e + 1) % 3];
+                if (vs_[(size_t)u].bnd == j || vs_[(size_t)w].bnd == j) continue;
+                const V &U = vs_[(size_t)u], &W = vs_[(size_t)w];
+                if (pt_seg(x, y, U.x, U.y, W.x, W.y) < b_) edges.push_back({std::min(u, w), std::max(u, w)});
+              }
+            }
+        }
+      }
+      std::sort(edges.begin(), edges.end());
+      edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
+      if (edges.empty()) continue;
+      // b < a/2: one edge per point, and no triangle with two flagged edges
+      ORACLE_CHECK(edges.size() == 1, "a boundary point within b of two mesh edges");
+      const i64 u = edges[0].first, w = edges[0].second;
+      const i64 m = (i64)vs_.size();
+      vs_.push_back(V{x, y, j});
+      ++out_.n_inserted;
+      int nt = 0;
+      for (i64 k = k0 - 2; k <= k0 + 2; ++k) {
+        if (k < 0 || k + 1 >= T_.NK) continue;
+        const double xo = T_.lx[(size_t)(k * NI)];
+        const i64 ic = (i64)std::floor((x - xo) / T_.h);
+        for (i64 i = ic - 3; i <= ic + 3; ++i) {
+          if (i < 0 || i >= NI) continue;
+          for (int t = 0; t < 2; ++t) {
+            const i64 slot = (k * NI + i) * 2 + t;
+            const std::vector<i64> cur = slot_[(size_t)slot];
+            for (i64 tid : cur) {
+              if (!alive_[(size_t)tid]) continue;
+              auto tr = tri_[(size_t)tid];
+              int e = -1;
+              for (int q = 0; q < 3; ++q)
+                if (std::min(tr[q], tr[(q + 1) % 3]) == u && std::max(tr[q], tr[(q + 1) % 3]) == w) e = q;
+              if (e < 0) continue;
+              ORACLE_CHECK(!touched[(size_t)tid], "a triangle with two eliminated edges");
+              alive_[(size_t)tid] = 0;
+              ++nt;
+              const i64 a0 = tr[e], a1 = tr[(e + 1) % 3], a2 = tr[(e + 2) % 3];
+              std::array<i64, 3> t1 = {a0, m, a2}, t2 = {m, a1, a2};
+              ORACLE_CHECK(area2(t1[0], t1[1], t1[2]) > 0 && area2(t2[0], t2[1], t2[2]) > 0,
+                           "cavity fan not positively oriented");
+              add_tri(t1, slot);
+              add_tri(t2, slot);
+              touched.resize(tri_.size(), 0);
+              touched[tri_.size() - 1] = touched[tri_.size() - 2] = 1;
+            }
+          }
+        }
+      }
+      ORACLE_CHECK(nt >= 1 && nt <= 2, "edge elimination found no triangle");
+    }
+  }
+
+  // --- retriangulation against the polyline ------------------------------
+  // a point of a triangle's subdivision: kind 0 mesh vertex, 1 crossing of
+  // mesh edge (u, w) (u < w) by segment s, 2 polyline vertex strictly inside
+  struct PP {
+    int kind;
+    i64 a, b, s;
+    double x, y;
+    double ct;  // chain parameter: segment order + t
+  };
+  i64 point_id(const PP& p) {
+    std::array<i64, 3> key = p.kind == 0 ? std::array<i64, 3>{0, p.a, 0}
+                           : (p.kind == 1 ? std::array<i64, 3>{1 + p.s, p.a, p.b} : std::array<i64, 3>{-1, p.a, 0});
+    auto it = pkey_.find(key);
+    if (it != pkey_.end()) return it->second;
+    const i64 id = (i64)ox_.size();
+    pkey_[key] = id;
+    ox_.push_back(p.x);
+    oy_.push_back(p.y);
+    return id;
+  }
+  // crossing of mesh edge (u, w) by segment s, computed from the canonical
+  // orientation u < w so that both triangles of the edge get the same point
+  PP crossing(i64 u, i64 w, i64 s) const {
+    const i64 lo = std::min(u, w), hi = std::max(u, w);
+    const V &U = vs_[(size_t)lo], &W = vs_[(size_t)hi];
+    const double px = T_.px[(size_t)s], py = T_.py[(size_t)s];
+    const double gx = W.x - U.x, gy = W.y - U.y;
+    const double dp = gx * (py - U.y) - gy * (px - U.x);
+    const double dq = gx * (qy(s) - U.y) - gy * (qx(s) - U.x);
+    const double t = dp / (dp - dq);
+    PP p;
+    p.kind = 1;
+    p.a = lo;
+    p.b = hi;
+    p.s = s;
+    p.x = px + t * (qx(s) - px);
+    p.y = py + t * (qy(s) - py);
+    p.ct = t;
+    return p;
+  }
+
+  bool inside_point(double x, double y) const {
+    // ray parity to -x against every segment (rarely needed: triangles with no
+    // corner off the polyline and no piece inside)
+    int n = 0;
+    for (i64 j = 0; j < nseg(); ++j) {
+      const double ay = T_.py[(size_t)j], by = qy(j);
+      if ((ay > y) == (by > y)) continue;
+      const double xc = T_.px[(size_t)j] + (y - ay) / (by - ay) * (qx(j) - T_.px[(size_t)j]);
+      if (xc < x) ++n;
+    }
+    return n & 1;
+  }
+
+  void emit(const std::vector<i64>& f, int code) {
+    otri_.push_back({f[0], f[1], f[2]});
+    ocode_.push_back((uint8_t)code);
+  }
+
+  void retriangulate() {
+    const i64 NLAT = T_.NK * T_.NI;
+    for (size_t tid = 0; tid < tri_.size(); ++tid) {
+      if (!alive_[tid]) continue;
+      const auto C = tri_[tid];
+      double minx = 1e300, maxx = -1e300, miny = 1e300, maxy = -1e300;
+      for (int j = 0; j < 3; ++j) {
+        minx = std::min(minx, vs_[(size_t)C[j]].x); maxx = std::max(maxx, vs_[(size_t)C[j]].x);
+        miny = std::min(miny, vs_[(size_t)C[j]].y); maxy = std::max(maxy, vs_[(size_t)C[j]].y);
+      }
+      // segments meeting the triangle: pieces [t0, t1] of segment s inside it
+      struct Sub { i64 s; double t0, t1; int e0, e1; int c0, c1; };  // e: edge of entry/exit (-1 none), c: corner (-1)
+      std::vector<Sub> subs;
+      int edge_side = -1;
+      std::vector<i64> cand;
+      near(scell_, 0.5 * (minx + maxx), 0.5 * (miny + maxy), 0.5 * std::max(maxx - minx, maxy - miny) + 1.0,
+           [&](i64 j) { cand.push_back(j); });
+      std::sort(cand.begin(), cand.end());
+      cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+      for (i64 s : cand) {
+        const i64 jp = s, jq = T_.next[(size_t)s];
+        const double px = T_.px[(size_t)s], py = T_.py[(size_t)s], dx = qx(s) - px, dy = qy(s) - py;
+        if (std::max(px, qx(s)) < minx - 1e-9 || std::min(px, qx(s)) > maxx + 1e-9 ||
+            std::max(py, qy(s)) < miny - 1e-9 || std::min(py, qy(s)) > maxy + 1e-9)
+          continue;
+        // clip against the three edge half-planes (inside = left of each edge)
+        double t0 = 0.0, t1 = 1.0;
+        int e0 = -1, e1 = -1;
+        bool empty = false;
+        for (int e = 0; e < 3 && !empty; ++e) {
+          const i64 ua = C[e], ub = C[(e + 1) % 3];
+          const V &A = vs_[(size_t)ua], &B = vs_[(size_t)ub];
+          auto side = [&](double x, double y) { return (B.x - A.x) * (y - A.y) - (B.y - A.y) * (x - A.x); };
+          // an end of the segment that is a corner of this edge lies on its line
+          double fp = (A.bnd == jp || B.bnd == jp) ? 0.0 : side(px, py);
+          double fq = (A.bnd == jq || B.bnd == jq) ? 0.0 : side(qx(s), qy(s));
+          if (fp < 0 && fq < 0) { empty = true; break; }
+          if (fp >= 0 && fq >= 0) continue;
+          const double t = fp / (fp - fq);
+          if (fp < 0) { if (t > t0) { t0 = t; e0 = e; } }
+          else { if (t < t1) { t1 = t; e1 = e; } }
+        }
+        if (empty || !(t1 > t0)) continue;
+        Sub sb{s, t0, t1, e0, e1, -1, -1};
+        for (int j = 0; j < 3; ++j) {
+          if (vs_[(size_t)C[j]].bnd == jp && t0 == 0.0) { sb.c0 = j; sb.e0 = -1; }
+          if (vs_[(size_t)C[j]].bnd == jq && t1 == 1.0) { sb.c1 = j; sb.e1 = -1; }
+        }
+        if (sb.c0 >= 0 && sb.c1 >= 0) {
+          // the segment joins two corners: it lies on their edge and does not
+          // enter the triangle, which lies on the side of its third corner
+          const int third = 3 - sb.c0 - sb.c1;
+          const V& T3 = vs_[(size_t)C[third]];
+          edge_side = ((qx(s) - px) * (T3.y - py) - (qy(s) - py) * (T3.x - px)) > 0 ? 1 : 0;
+          continue;
+        }
+        subs.push_back(sb);
+      }
+      if (subs.empty()) {
+        // uncut: side from a boundary segment along an edge, a corner off the
+        // polyline, else the centroid
+        int fg = edge_side;
+        for (int j = 0; j < 3 && fg < 0; ++j)
+          if (C[j] < NLAT && vs_[(size_t)C[j]].bnd < 0) fg = T_.inside[(size_t)C[j]];
+        if (fg < 0) {
+          double cx = 0, cy = 0;
+          for (int j = 0; j < 3; ++j) { cx += vs_[(size_t)C[j]].x / 3; cy += vs_[(size_t)C[j]].y / 3; }
+          fg = inside_point(cx, cy);
+        }
+        if (fg) {
+          std::vector<i64> f;
+          for (int j = 0; j < 3; ++j) f.push_back(point_id(PP{0, C[j], 0, -1, vs_[(size_t)C[j]].x, vs_[(size_t)C[j]].y, 0}));
+          emit(f, 0);
+        }
+        continue;
+      }
+      ++out_.n_cut;
+      // chain order of the segments met: consecutive ones in polyline order
+      std::sort(subs.begin(), subs.end(), [&](const Sub& x, const Sub& y) { return x.s < y.s; });
+      if (subs.size() == 2 && T_.next[(size_t)subs[1].s] == subs[0].s) std::swap(subs[0], subs[1]);
+      ORACLE_CHECK(subs.size() <= 2, "more than two segments in one triangle");
+      if (subs.size() == 2)
+        ORACLE_CHECK(T_.next[(size_t)subs[0].s] == subs[1].s, "two non-consecutive segments in one triangle");
+      // points of the subdivision: boundary points (corners and crossings) and
+      // the chain vertex inside
+      auto corner_pp = [&](int j) {
+        return PP{0, C[j], 0, -1, vs_[(size_t)C[j]].x, vs_[(size_t)C[j]].y, 0};
+      };
+      // pieces: sequences of points along the chain inside the triangle
+      std::vector<std::vector<PP>> pieces;
+      std::vector<PP> cur;
+      std::vector<std::pair<int, double>> bpos;  // per piece end: position on the boundary cycle
+      for (size_t q = 0; q < subs.size(); ++q) {
+        const Sub& sb = subs[q];
+        PP start, end;
+        const double order = (double)q;
+        if (sb.c0 >= 0) start = corner_pp(sb.c0);
+        else if (sb.e0 >= 0) start = crossing(C[sb.e0], C[(sb.e0 + 1) % 3], sb.s);
+        else { start = PP{2, sb.s, 0, sb.s, T_.px[(size_t)sb.s], T_.py[(size_t)sb.s], 0}; }
+        if (sb.c1 >= 0) end = corner_pp(sb.c1);
+        else if (sb.e1 >= 0) end = crossing(C[sb.e1], C[(sb.e1 + 1) % 3], sb.s);
+        else { end = PP{2, T_.next[(size_t)sb.s], 0, sb.s, qx(sb.s), qy(sb.s), 0}; }
+        start.ct = order + sb.t0;
+        end.ct = order + sb.t1;
+        if (cur.empty()) cur.push_back(start);
+        else ORACLE_CHECK(start.kind == 2 && cur.back().kind == 2 && start.a == cur.back().a, "pieces do not join");
+        cur.push_back(end);
+        if (end.kind != 2) { pieces.push_back(cur); cur.clear(); }
+      }
+      ORACLE_CHECK(cur.empty(), "a piece ends inside the triangle");
+      int ninner = 0;
+      for (auto& pc : pieces)
+        for (auto& p : pc) ninner += p.kind == 2;
+      ORACLE_CHECK(ninner <= 1, "two chain vertices in one triangle");
+      // boundary cycle: corners and the piece ends on each edge, in order
+      struct BP { PP p; int piece; int end; double pos; };  // end 0 = piece start, 1 = piece end
+      std::vector<BP> cyc;
+      for (int j = 0; j < 3; ++j) cyc.push_back(BP{corner_pp(j), -1, -1, 3.0 * j});
+      auto edge_pos = [&](const PP& p) -> double {
+        for (int e = 0; e < 3; ++e) {
+          if (p.kind == 0 && p.a == C[e]) return 3.0 * e;
+          if (p.kind == 1 && std::min(C[e], C[(e + 1) % 3]) == p.a && std::max(C[e], C[(e + 1) % 3]) == p.b) {
+            const V &A = vs_[(size_t)C[e]], &B = vs_[(size_t)C[(e + 1) % 3]];
+            const double L2 = (B.x - A.x) * (B.x - A.x) + (B.y - A.y) * (B.y - A.y);
+            const double t = ((p.x - A.x) * (B.x - A.x) + (p.y - A.y) * (B.y - A.y)) / L2;
+            ORACLE_CHECK(t > 0 && t < 1, "crossing outside its edge");
+            return 3.0 * e + 1.0 + t;  // strictly between the corners 3e and 3e+3
+          }
+        }
+        ORACLE_CHECK(false, "piece end not on the triangle");
+        return 0;
+      };
+      for (size_t q = 0; q < pieces.size(); ++q) {
+        for (int end = 0; end < 2; ++end) {
+          const PP& p = end == 0 ? pieces[q].front() : pieces[q].back();
+          const double pos = edge_pos(p);
+          if (p.kind == 0) {
+            for (auto& bp : cyc)
+              if (bp.p.kind == 0 && bp.p.a == p.a) {
+                ORACLE_CHECK(bp.piece < 0, "two pieces at one corner");
+                bp.piece = (int)q;
+                bp.end = end;
+              }
+          } else {
+            cyc.push_back(BP{p, (int)q, end, pos});
+          }
+        }
+      }
+      std::sort(cyc.begin(), cyc.end(), [](const BP& x, const BP& y) { return x.pos < y.pos; });
+      const int n = (int)cyc.size();
+      // faces: walk the cycle; at a piece end arrived along the boundary, follow the piece
+      std::vector<uint8_t> used(n, 0);
+      for (int st = 0; st < n; ++st) {
+        if (used[st]) continue;
+        std::vector<PP> face;
+        int side = -1;  // 1: the face uses a piece in chain direction (foreground)
+        int at = st;
+        for (int guard = 0; guard < 64; ++guard) {
+          if (used[at]) break;
+          used[at] = 1;
+          face.push_back(cyc[at].p);
+          int nx = (at + 1) % n;
+          if (cyc[nx].piece >= 0) {
+            // arrive at a piece end along the boundary: follow the piece
+            const auto& pc = pieces[(size_t)cyc[nx].piece];
+            const bool fwd = cyc[nx].end == 0;
+            const int s2 = fwd ? 1 : 0;
+            ORACLE_CHECK(side < 0 || side == s2, "face on both sides of the chain");
+            side = s2;
+            if (fwd) for (size_t z = 0; z + 1 < pc.size(); ++z) face.push_back(pc[z]);
+            else for (size_t z = pc.size() - 1; z > 0; --z) face.push_back(pc[z]);
+            // the other end of the piece
+            int oth = -1;
+            for (int z = 0; z < n; ++z)
+              if (cyc[z].piece == cyc[nx].piece && cyc[z].end != cyc[nx].end) oth = z;
+            ORACLE_CHECK(oth >= 0, "piece end missing");
+            used[nx] = used[nx];  // the entry end is visited by the face that leaves from it
+            at = oth;
+            if (at == st) break;
+            continue;
+          }
+          at = nx;
+          if (at == st) break;
+        }
+        if (side < 0) continue;  // cannot happen for a cut triangle's faces (each touches the chain)
+        if (side != 1) continue;
+        triangulate_face(face, pieces);
+      }
+    }
+  }
+
+  // the template rule on one foreground face (points in positive order)
+  void triangulate_face(const std::vector<PP>& face, const std::vector<std::vector<PP>>& pieces) {
+    const int m = (int)face.size();
+    if (m < 3) {
+      std::string d = "degenerate face of " + std::to_string(m) + " points:";
+      for (auto& p : face) d += " (" + std::to_string(p.kind) + " " + std::to_string(p.x) + "," + std::to_string(p.y) + ")";
+      d += "; pieces:";
+      for (auto& pc : pieces) {
+        d += " [";
+        for (auto& p : pc) d += "(" + std::to_string(p.kind) + " " + std::to_string(p.x) + "," + std::to_string(p.y) + ")";
+        d += "]";
+      }
+      ORACLE_CHECK(false, d);
+    }
+    int apex = -1;
+    for (int j = 0; j < m; ++j)
+      if (face[j].kind == 2) apex = j;
+    if (apex < 0 && m == 4 && pieces.size() == 2) {
+      bool corners = false;
+      for (auto& p : face) corners = corners || p.kind == 0;
+      if (!corners) {
+        // middle quadrilateral between two chords: diagonal joining their exits
+        const PP& x1 = pieces[0].back();
+        for (int j = 0; j < m; ++j)
+          if (face[j].kind == 1 && face[j].a == x1.a && face[j].b == x1.b && face[j].s == x1.s) apex = j;
+        const PP& x2 = pieces[1].back();
+        ORACLE_CHECK(apex >= 0 && face[(apex + 2) % 4].kind == 1 && face[(apex + 2) % 4].s == x2.s &&
+                         face[(apex + 2) % 4].a == x2.a && face[(apex + 2) % 4].b == x2.b,
+                     "nested exits not opposite");
+      }
+    }
+    if (apex < 0) {
+      double best = 1e300;
+      for (int j = 0; j < m; ++j) {
+        const bool on_chain = face[j].kind != 0 || vs_[(size_t)face[j].a].bnd >= 0;
+        if (!on_chain) continue;
+        // chain position: the piece point with the same identity
+        double ct = 1e300;
+        for (auto& pc : pieces)
+          for (auto& p : pc)
+            if (p.kind == face[j].kind && p.a == face[j].a && p.b == face[j].b && p.s == face[j].s) ct = p.ct;
+        if (ct < best) { best = ct; apex = j; }
+      }
+    }
+    ORACLE_CHECK(apex >= 0, "no apex");
+    std::vector<i64> ids;
+    for (int j = 0; j < m; ++j) ids.push_back(point_id(face[(apex + j) % m]));
+    for (int t = 1; t + 1 < m; ++t) {
+      const i64 a = ids[0], b = ids[t], c = ids[t + 1];
+      const double ar = (ox_[(size_t)b] - ox_[(size_t)a]) * (oy_[(size_t)c] - oy_[(size_t)a]) -
+                        (oy_[(size_t)b] - oy_[(size_t)a]) * (ox_[(size_t)c] - ox_[(size_t)a]);
+      ORACLE_CHECK(ar > 0, "template triangle not positively oriented");
+      emit({a, b, c}, 1);
+    }
+  }
+
+  PreResult finish() {
+    const i64 n = (i64)ox_.size();
+    std::vector<i64> ord(n);
+    for (i64 j = 0; j < n; ++j) ord[j] = j;
+    std::sort(ord.begin(), ord.end(), [&](i64 a, i64 b) {
+      return oy_[(size_t)a] != oy_[(size_t)b] ? oy_[(size_t)a] < oy_[(size_t)b] : ox_[(size_t)a] < ox_[(size_t)b];
+    });
+    std::vector<i64> rank(n);
+    for (i64 j = 0; j < n; ++j) rank[(size_t)ord[(size_t)j]] = j;
+    for (i64 j = 0; j < n; ++j) {
+      out_.verts.push_back(ox_[(size_t)ord[(size_t)j]]);
+      out_.verts.push_back(oy_[(size_t)ord[(size_t)j]]);
+    }
+    std::vector<std::pair<std::array<i64, 3>, uint8_t>> ts;
+    for (size_t t = 0; t < otri_.size(); ++t) {
+      std::array<i64, 3> r = {rank[(size_t)otri_[t][0]], rank[(size_t)otri_[t][1]], rank[(size_t)otri_[t][2]]};
+      int mi = 0;
+      for (int j = 1; j < 3; ++j)
+        if (r[j] < r[mi]) mi = j;
+      ts.push_back({{r[mi], r[(mi + 1) % 3], r[(mi + 2) % 3]}, ocode_[t]});
+    }
+    std::sort(ts.begin(), ts.end());
+    for (auto& t : ts) {
+      for (int j = 0; j < 3; ++j) out_.tris.push_back((int32_t)t.first[j]);
+      out_.codes.push_back(t.second);
+    }
+    return std::move(out_);
+  }
+};
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1093,6 +1750,40 @@ void oracle_copy_chains(const oracle_mesh* r, int64_t* xy, int64_t* chain_start)
   if (chain_start) std::memcpy(chain_start, r->m.chain_start.data(), r->m.chain_start.size() * 8);
 }
 void oracle_free(oracle_mesh* r) { delete r; }
+
+// Mesh after the preprocessing of Alg. 3 with thresholds a, b, c (pixels).
+struct oracle_pre {
+  PreResult r;
+};
+oracle_pre* oracle_mesh_preprocessed(const uint8_t* bitmap, int32_t width, int32_t height, int64_t row_stride,
+                                     double grid_h, double a, double b, double c, char* err, int32_t errlen) {
+  try {
+    // all rules off, or the admissible ranges of Sec. 3.3.4: b < a/2,
+    // c < a/sqrt2, and a < h/2 (disjoint snapping neighbourhoods)
+    ORACLE_CHECK(a >= 0 && b >= 0 && c >= 0, "negative threshold");
+    const bool off = a == 0 && b == 0 && c == 0;
+    ORACLE_CHECK(off || (b < a / 2 && c * c < a * a / 2 && a < grid_h / 2), "thresholds outside the admissible range");
+    Oracle o(bitmap, width, height, row_stride, grid_h, 0);
+    PreOracle p(o.traced(), a, b, c);
+    oracle_pre* res = new oracle_pre;
+    res->r = p.run();
+    return res;
+  } catch (const std::exception& e) {
+    if (err && errlen > 0) std::snprintf(err, (size_t)errlen, "%s", e.what());
+    return nullptr;
+  }
+}
+int64_t oracle_pre_n_vertices(const oracle_pre* r) { return (int64_t)r->r.verts.size() / 2; }
+int64_t oracle_pre_n_triangles(const oracle_pre* r) { return (int64_t)r->r.codes.size(); }
+void oracle_pre_counts(const oracle_pre* r, int64_t* out) {
+  out[0] = r->r.n_snapped; out[1] = r->r.n_repelled; out[2] = r->r.n_inserted; out[3] = r->r.n_cut;
+}
+void oracle_pre_copy(const oracle_pre* r, double* verts, int32_t* tris, uint8_t* codes) {
+  if (verts && !r->r.verts.empty()) std::memcpy(verts, r->r.verts.data(), r->r.verts.size() * 8);
+  if (tris && !r->r.tris.empty()) std::memcpy(tris, r->r.tris.data(), r->r.tris.size() * 4);
+  if (codes && !r->r.codes.empty()) std::memcpy(codes, r->r.codes.data(), r->r.codes.size());
+}
+void oracle_pre_free(oracle_pre* r) { delete r; }
 
 // Exact sign of a + b*sqrt3 (exposed for the arithmetic pin).
 int32_t oracle_z3_sign(int64_t a, int64_t b) { return z3_sign(Z3{(i128)a, (i128)b}); }

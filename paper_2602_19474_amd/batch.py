@@ -63,7 +63,7 @@ class Batch:
         sub-allocation); ``bind=False`` leaves binding to the caller."""
         from . import _image, context
         torch = _torch()
-        self.items = [(t, int(h)) for t, h in items]
+        self.items = [(t, float(h)) for t, h in items]
         if not self.items:
             raise ValueError("empty batch")
         dev = self.items[0][0].device

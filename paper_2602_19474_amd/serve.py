@@ -138,7 +138,7 @@ class Server:
 
     # -- client side -----------------------------------------------------------
     def submit(self, bitmap, grid_h: float, arrival: float | None = None) -> Request:
-        r = Request(self._next_id, bitmap, int(grid_h), self.backend.now() if arrival is None else float(arrival))
+        r = Request(self._next_id, bitmap, float(grid_h), self.backend.now() if arrival is None else float(arrival))
         r.pixels = int(self.backend.pixels(bitmap))
         self._next_id += 1
         self.pending.append(r)

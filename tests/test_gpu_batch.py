@@ -242,6 +242,37 @@ def test_both_sides_with_record_overflow(rows):
         assert float(np.abs(v.cpu().numpy() - ref.verts).max(initial=0.0)) <= 1e-12 * h
 
 
+@pytest.mark.parametrize("strategy", [0, 1])
+def test_dyadic_grid_edges_in_one_batch(strategy):
+    """Grid edges p/2^q next to integer ones in one batch (and one graph)."""
+    import torch
+
+    from paper_2602_19474_amd.batch import Batch, Tuning
+    g = wl.rng(92, strategy)
+    items = [(wl.smoothed_noise(181, 163, 4.0, 0.0, False, g), 0.5),
+             (wl.smoothed_noise(240, 97, 5.0, 0.0, False, g), 1.25),
+             (wl.disk(item=2), 1),
+             (wl.smoothed_noise(150, 210, 3.0, 0.0, False, g), 0.375),
+             (wl.smoothed_noise(90, 400, 6.0, 0.0, False, g), 2.5)]
+    refs = [oracle.mesh_from_bitmap(bm, h) for bm, h in items]
+    gpu = [(torch.from_numpy(np.ascontiguousarray(bm)).cuda(), h) for bm, h in items]
+    print(f"[gpu-batch] dyadic grid edges, strategy {strategy}", flush=True)
+    b = Batch(gpu, tuning=Tuning(strategy=strategy, tile_rows=8, groups_per_cu=2))
+    outs = b.allocate(b.plan())
+    gr = b.capture()
+    for rep in range(2):
+        for v, t, c in outs:
+            t.fill_(-1)
+        torch.cuda.synchronize()
+        gr.replay()
+        torch.cuda.synchronize()
+        st = b.sizes()
+        for i, ((bm, h), (v, t, c), ref) in enumerate(zip(items, outs, refs)):
+            assert st[i][3] == 0 and st[i][:2] == (ref.verts.shape[0], ref.tris.shape[0]), (rep, i, st[i])
+            assert np.array_equal(t.cpu().numpy(), ref.tris) and np.array_equal(c.cpu().numpy(), ref.codes), (rep, i)
+            assert float(np.abs(v.cpu().numpy() - ref.verts).max(initial=0.0)) <= 1e-12 * h
+
+
 def test_batch_argument_errors():
     import torch
 

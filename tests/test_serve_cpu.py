@@ -83,7 +83,7 @@ def _drive(server, items, arrivals):
 def _trace(n, rate, seed=3):
     rs = np.random.default_rng(seed)
     arr = np.cumsum(rs.exponential(1.0 / rate, n))
-    items = [(_Img(int(rs.integers(10_000, 200_000))), int(rs.choice([1, 2, 4]))) for _ in range(n)]
+    items = [(_Img(int(rs.integers(10_000, 200_000))), float(rs.choice([0.5, 1, 1.5, 2, 4]))) for _ in range(n)]
     return items, arr
 
 
@@ -100,6 +100,8 @@ def test_every_request_completes_in_fifo_batches():
     adm = [r.t_admit for r in sorted(reqs, key=lambda r: r.rid)]
     assert all(a <= b for a, b in zip(adm, adm[1:]))
     assert srv.arena.used == 0 and srv.arena.peak <= srv.arena.capacity
+    # grid edges reach the batch as given (dyadic ones included)
+    assert [r.grid_h for r in sorted(reqs, key=lambda r: r.rid)] == [h for _, h in items]
 
 
 def test_batch_limits():

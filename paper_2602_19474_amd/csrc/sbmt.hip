@@ -50,6 +50,20 @@ SBMT_HD int lut_nfg(int cls) { return sbmt_lut_nfg[cls]; }
 SBMT_HD int lut_ntri(int cls) { return sbmt_lut_ntri[cls]; }
 SBMT_HD uint32_t lut_tri(int cls, int j) { return sbmt_lut_tri[cls][j]; }
 
+// Block segment table of each device (see block_tab), written by k_block_table
+// when a handle is created on the device.
+__device__ uint4 g_blocktab[1024];
+SBMT_HD uint4 block_tab(int i) { return g_blocktab[i]; }
+
+__global__ void __launch_bounds__(256) k_block_table() {
+  const int s9 = blockIdx.x * 256 + threadIdx.x;
+  if (s9 >= 512) return;
+  uint4 A, B;
+  block_table_entry((uint32_t)s9, A, B);
+  g_blocktab[2 * s9] = A;
+  g_blocktab[2 * s9 + 1] = B;
+}
+
 constexpr int kThreads = 256;
 constexpr int kCB = 256;               // owners per row segment (one per thread)
 constexpr int kScanThreads = 512;  // 2048 segments per scan block: more blocks in flight than 4096
@@ -57,6 +71,8 @@ constexpr int kScanChunk = 4 * kScanThreads;
 constexpr int kWinRows = 16, kWinWords = 16;  // LDS window of the coarse raster per tile
 constexpr int64_t kMaxRecords = 0x7ffffffeLL;  // records of a call
 constexpr int kMaxBandChunks = 64;             // fused path: row segments per band
+constexpr int kSlowBlocks = 2048;              // dense slow pass: blocks of its grid-stride loop
+constexpr int kDenseLists = 64;                // dense slow lists (tile mod 64), each with its own counter
 constexpr int kSizeWords = SBMT_SIZE_WORDS;    // per-image sizes record
 constexpr int kSegSlots = 64;                  // partial segment counts per image (spread atomics)
 
@@ -81,14 +97,16 @@ struct Shared {
   unsigned long long* seg_slow;     // [nseg] slow-owner counts nv | nt << 21 | ncut << 42
   longlong4* seg_off;               // [nseg + 1] exclusive (v, t, cut) over the call; [nseg] = totals
   longlong4* blk;                   // [nblk] scan block sums
-  unsigned long long* ctr;          // [8] 0: records handed out, 1: band ticket
+  unsigned long long* ctr;          // [8] 1: band ticket
   int* imgerr;                      // [n] protocol violation seen
   int64_t* sizes;                   // [n][kSizeWords] n_vertices, n_triangles, n_cut, status, n_segments
   unsigned long long* segacc;       // [n][kSegSlots] partial boundary-segment counts
   SlowRec* rec;                     // slow-owner records, tcap per count tile
+  uint32_t* dense;                  // [kDenseLists][dcap] indices into rec of the queued slow owners
+  unsigned long long* dctr;         // [kDenseLists] entries of each list
   int* tile_n;                      // [count tiles] slow owners queued by each tile
   unsigned long long* band;         // [nbands] fused path look-back words
-  int64_t tcap, nseg, nbands;
+  int64_t tcap, nseg, nbands, dcap;
   int nblk, n;
 };
 
@@ -196,6 +214,7 @@ __global__ void __launch_bounds__(256) k_coarsen(Src src, const int64_t* __restr
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < kSegSlots * (int64_t)sh.n;
        q += (int64_t)gridDim.x * blockDim.x)
     sh.segacc[q] = 0ull;
+  if (blockIdx.x == 0 && threadIdx.x < kDenseLists) sh.dctr[threadIdx.x] = 0ull;
   const int s = g.s;
   const int rr0 = ry * kCoarsenRows;                 // first stored row
   const int C0 = 256 * bx - kRingC;                  // first coarse column of the block
@@ -356,6 +375,7 @@ struct CountLds {
   uint16_t q1[RB * kCB];
   uint16_t q2[RB * kCB];
   int n1, n2;
+  unsigned dbase;
   uint32_t win[kWinRows * kWinWords];
 };
 
@@ -365,7 +385,7 @@ struct CountLds {
 // beyond the record region keep the queued mark (0x8000) for k_slow (the
 // persistent kernel's regions hold every owner of a tile), which keeps this
 // routine free of the classification's registers.
-template <int RB>
+template <int RB, bool kDense = false>
 __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, int64_t tile, int k0, int cb,
                                            const Shared& sh, CountLds<RB>& L, int4* acc_out,
                                            uint16_t* __restrict__ hdst) {
@@ -451,11 +471,27 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) sh.tile_n[tile] = L.n2;
+  if (threadIdx.x == 0) {
+    sh.tile_n[tile] = L.n2;
+    // list tile mod kDenseLists, so that no counter takes every tile's atomic
+    if (kDense && L.n2)
+      L.dbase = (unsigned)((tile & (kDenseLists - 1)) * sh.dcap +
+                           (int64_t)atomicAdd(&sh.dctr[tile & (kDenseLists - 1)],
+                                              (unsigned long long)min((int64_t)L.n2, sh.tcap)));
+  }
+  if (kDense) __syncthreads();
   for (int q = threadIdx.x; q < L.n2; q += kThreads) {
     const int e = L.q2[q], r = e / kCB, c = c0 + (e - r * kCB);
     const int k = k0 + r;
-    if (q < sh.tcap) sh.rec[tile * sh.tcap + q].x = (uint64_t)c | ((uint64_t)k << 24) | ((uint64_t)ii << 48);
+    if (q < sh.tcap) {
+      // position, and the cell row of the owner's row for the dense pass
+      SlowRec R;
+      R.info = (uint32_t)L.rowR[r];
+      R.tri = 0u;
+      R.x = (uint64_t)c | ((uint64_t)k << 24) | ((uint64_t)ii << 48);
+      sh.rec[tile * sh.tcap + q] = R;
+      if (kDense) sh.dense[L.dbase + q] = (uint32_t)(tile * sh.tcap + q);
+    }
   }
   __syncthreads();
   // the tile's owner codes, four per lane and row
@@ -491,79 +527,121 @@ __global__ void __launch_bounds__(kThreads, 8) k_count(Src src, const int64_t* _
   const Img& d = src.img(ii);
   const Geo g = d.g;
   const int cb = (int)local % g.NCB, ky = (int)local / g.NCB;  // tile index of an image: 32 bits
-  count_tile<RB>(d, g, ii, (int64_t)blockIdx.x, ky * RB, cb, sh, L, out, nullptr);
+  count_tile<RB, true>(d, g, ii, (int64_t)blockIdx.x, ky * RB, cb, sh, L, out, nullptr);
   __syncthreads();
   const int k = ky * RB + (int)threadIdx.x;
   if (threadIdx.x < RB && k < g.NK) sh.seg_cnt[d.seg0 + (int64_t)k * g.NCB + cb] = out[threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
-// Slow owners of one count tile per 64-lane block (the tiling of k_count):
-// classify each queued owner, store its 16-byte record in place of its
-// position, and write the tile's per-row sums of the slow owners' counts.
+// Slow owners with a record, densely: one lane per entry of the lists the count
+// tiles filled (in whatever order their atomics ran), so that waves are full
+// whatever the spread of slow owners over tiles.  Each record carries the
+// owner's position and its row's cell row; the classification replaces it in
+// place (with the owner's place in its tile in the spare bits 48..63) and the
+// owner's code goes to the owner map.
 // ---------------------------------------------------------------------------
 template <class Src, int RB>
-__global__ void __launch_bounds__(64) k_slow(Src src, const int64_t* __restrict__ tab, Shared sh) {
+__global__ void __launch_bounds__(kThreads) k_slow_dense(Src src, Shared sh) {
+  __shared__ int64_t pre[kDenseLists + 1];
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int l = 0; l < kDenseLists; ++l) {
+      pre[l] = t;
+      t += (int64_t)sh.dctr[l];
+    }
+    pre[kDenseLists] = t;
+  }
+  __syncthreads();
+  const int64_t n = pre[kDenseLists];
+  for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < n; j += (int64_t)gridDim.x * kThreads) {
+    int lo = 0, hi = kDenseLists - 1;  // list: largest l with pre[l] <= j
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pre[mid] <= j) lo = mid;
+      else hi = mid - 1;
+    }
+    const uint32_t idx = sh.dense[lo * sh.dcap + (j - pre[lo])];
+    const SlowRec P = sh.rec[idx];
+    const int k = (int)((P.x >> 24) & 0xffffffu), c = (int)(P.x & 0xffffffu), ii = (int)(P.x >> 48);
+    const Img& d = src.img(ii);
+    const Geo g = d.g;
+    Bits b;
+    b.p = d.bits;
+    b.wpr = g.wpr;
+    b.rr0 = 0;
+    b.cc0 = 0;
+    const Frame f = owner_frame(g, b, k, c, (int)P.info);
+    Slow sr;
+    slow_classify(g, f, sr);
+    SlowRec R = pack_slow(sr);
+    R.x |= (uint64_t)(((k & (RB - 1)) << 8) | (c & (kCB - 1))) << 48;
+    sh.rec[idx] = R;
+    d.omap[(int64_t)k * g.NI + c] = (uint16_t)map_code(sr.info);
+    if (info_err(sr.info)) atomicOr(&sh.imgerr[ii], 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per count tile, after the dense pass: the per-row sums of its slow owners'
+// counts (from their records), and the slow owners beyond its record region
+// (the tile queued more than the region holds; they still carry the queued
+// mark 0x8000), classified here without a record.
+// ---------------------------------------------------------------------------
+template <class Src, int RB>
+__global__ void __launch_bounds__(64) k_slow_tiles(Src src, const int64_t* __restrict__ tab, Shared sh) {
   __shared__ unsigned long long acc[RB];
   __shared__ uint32_t hasrec[RB * kCB / 32];
   __shared__ int rowR[RB];
+  const int64_t tile = blockIdx.x;
+  const int64_t nq = sh.tile_n[tile];
+  const bool over = nq > sh.tcap;  // uniform
+  const int nrec = (int)min(nq, sh.tcap);
   int64_t local;
   const int ii = src.find(blockIdx.x, tab, local);
   const Img& d = src.img(ii);
   const Geo g = d.g;
   const int cb = (int)local % g.NCB, ky = (int)local / g.NCB;  // tile index of an image: 32 bits
-  const int64_t tile = blockIdx.x;
   if (threadIdx.x < RB) {
     acc[threadIdx.x] = 0ull;
-    rowR[threadIdx.x] = row_cell(g, ky * RB + threadIdx.x);
+    if (over) rowR[threadIdx.x] = row_cell(g, ky * RB + threadIdx.x);
   }
-  const int64_t nq = sh.tile_n[tile];
-  const bool over = nq > sh.tcap;  // uniform
   if (over)
     for (int t = threadIdx.x; t < RB * kCB / 32; t += 64) hasrec[t] = 0u;
   __syncthreads();
-  const int n = (int)min(nq, sh.tcap);
+  // owners with a record (classified by the dense pass: their place is in
+  // bits 48..63)
+  for (int q = threadIdx.x; q < nrec; q += 64) {
+    const SlowRec R = sh.rec[tile * sh.tcap + q];
+    atomicAdd(&acc[(int)(R.x >> 56)], pack_counts(R.info));
+    if (over) {
+      const int e = (int)(R.x >> 56) * kCB + (int)((R.x >> 48) & 255u);
+      atomicOr(&hasrec[e >> 5], 1u << (e & 31));
+    }
+  }
+  __syncthreads();
+  if (!over) {
+    const int k = ky * RB + (int)threadIdx.x;
+    if (threadIdx.x < RB && k < g.NK) sh.seg_slow[d.seg0 + (int64_t)k * g.NCB + cb] = acc[threadIdx.x];
+    return;
+  }
   Bits b;
   b.p = d.bits;
   b.wpr = g.wpr;
   b.rr0 = 0;
   b.cc0 = 0;
-  for (int q = threadIdx.x; q < n; q += 64) {
-    const int64_t idx = tile * sh.tcap + q;
-    const uint64_t p = sh.rec[idx].x;
-    const int k = (int)((p >> 24) & 0xffffffu), c = (int)(p & 0xffffffu);
-    const Frame f = owner_frame(g, b, k, c, rowR[k - ky * RB]);
+  for (int e = threadIdx.x; e < RB * kCB; e += 64) {
+    const int r = e / kCB, k = ky * RB + r, c = cb * kCB + (e - r * kCB);
+    if (k >= g.NK || c >= g.NI || ((hasrec[e >> 5] >> (e & 31)) & 1u)) continue;
+    if (d.omap[(int64_t)k * g.NI + c] != 0x8000u) continue;
+    const Frame f = owner_frame(g, b, k, c, rowR[r]);
     Slow sr;
     slow_classify(g, f, sr);
-    SlowRec R = pack_slow(sr);
-    // the owner's place in the tile rides in the record's spare bits 48..63
-    R.x |= (uint64_t)(((k - ky * RB) << 8) | (c - cb * kCB)) << 48;
-    sh.rec[idx] = R;
     d.omap[(int64_t)k * g.NI + c] = (uint16_t)map_code(sr.info);
-    atomicAdd(&acc[k - ky * RB], pack_counts(sr.info));
+    atomicAdd(&acc[r], pack_counts(sr.info));
     if (info_err(sr.info)) atomicOr(&sh.imgerr[ii], 1);
-    if (over) {
-      const int e = (k - ky * RB) * kCB + (c - cb * kCB);
-      atomicOr(&hasrec[e >> 5], 1u << (e & 31));
-    }
   }
   __syncthreads();
-  if (over) {
-    // the queued slow owners beyond the record region (still marked 0x8000
-    // by the count pass): classified here without a record
-    for (int e = threadIdx.x; e < RB * kCB; e += 64) {
-      const int r = e / kCB, k = ky * RB + r, c = cb * kCB + (e - r * kCB);
-      if (k >= g.NK || c >= g.NI || ((hasrec[e >> 5] >> (e & 31)) & 1u)) continue;
-      if (d.omap[(int64_t)k * g.NI + c] != 0x8000u) continue;
-      const Frame f = owner_frame(g, b, k, c, rowR[r]);
-      Slow sr;
-      slow_classify(g, f, sr);
-      d.omap[(int64_t)k * g.NI + c] = (uint16_t)map_code(sr.info);
-      atomicAdd(&acc[r], pack_counts(sr.info));
-      if (info_err(sr.info)) atomicOr(&sh.imgerr[ii], 1);
-    }
-    __syncthreads();
-  }
   const int k = ky * RB + (int)threadIdx.x;
   if (threadIdx.x < RB && k < g.NK) sh.seg_slow[d.seg0 + (int64_t)k * g.NCB + cb] = acc[threadIdx.x];
 }
@@ -1627,9 +1705,10 @@ struct CallLayout {
   std::vector<int64_t> tab;           // [1 + 3 + 3][n + 1]: coarsen blocks, tiles per RB, bands per RB
   int64_t nseg = 0, owners = 0, rcap = 0, nbands_max = 0, halo_words = 0, ntiles_max = 0;
   int64_t tcap[3] = {0, 0, 0};  // records per count tile, per tile height
+  int64_t dcap[3] = {0, 0, 0};  // entries per dense list, per tile height
   int nblk = 0;
-  size_t off_ctr, off_imgerr, off_sizes, off_segacc, off_desc, off_tab, off_cnt, off_slow, off_segoff, off_blk, off_rec,
-      off_tilen, off_band, off_halo, total;
+  size_t off_ctr, off_dctr, off_imgerr, off_sizes, off_segacc, off_desc, off_tab, off_cnt, off_slow, off_segoff, off_blk, off_rec,
+      off_dense, off_tilen, off_band, off_halo, total;
   bool fused_ok = true;  // per-image counts fit the fused path's int32 bases and band width
 };
 
@@ -1684,11 +1763,22 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
     L.rcap = std::max<int64_t>(record_cap, 0);
   }
   if (L.rcap > kMaxRecords) L.rcap = kMaxRecords;
-  for (int r = 0; r < 3; ++r) L.tcap[r] = L.rcap / std::max<int64_t>(tab_row(L, 1 + r)[n], 1);
+  for (int r = 0; r < 3; ++r) {
+    const int64_t nt = tab_row(L, 1 + r)[n];
+    L.tcap[r] = L.rcap / std::max<int64_t>(nt, 1);
+    // tile t feeds list t mod kDenseLists: at most ceil(nt / kDenseLists) tiles a list
+    L.dcap[r] = (nt + kDenseLists - 1) / kDenseLists * L.tcap[r];
+  }
+  // lists in use: min(tiles, kDenseLists); at most rcap + (kDenseLists - 1) tcap entries
+  int64_t dmax = 0;
+  for (int r = 0; r < 3; ++r)
+    dmax = std::max(dmax, std::min<int64_t>(tab_row(L, 1 + r)[n], kDenseLists) * L.dcap[r]);
   L.nblk = (int)((L.nseg + kScanChunk - 1) / kScanChunk);
   size_t off = 0;
   L.off_ctr = off;
   off = align256(off + 8 * sizeof(unsigned long long));
+  L.off_dctr = off;
+  off = align256(off + kDenseLists * sizeof(unsigned long long));
   L.off_imgerr = off;
   off = align256(off + (size_t)n * sizeof(int));
   L.off_sizes = off;
@@ -1709,6 +1799,8 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
   off = align256(off + (size_t)L.nblk * sizeof(longlong4));
   L.off_rec = off;
   off = align256(off + (size_t)L.rcap * sizeof(SlowRec));
+  L.off_dense = off;
+  off = align256(off + (size_t)dmax * sizeof(uint32_t));
   L.off_tilen = off;
   off = align256(off + (size_t)L.ntiles_max * sizeof(int));
   L.off_band = off;
@@ -1738,6 +1830,9 @@ static Shared shared_of(const CallLayout& L, void* ws, int rbi) {
   s.sizes = (int64_t*)(b + L.off_sizes);
   s.segacc = (unsigned long long*)(b + L.off_segacc);
   s.rec = (SlowRec*)(b + L.off_rec);
+  s.dense = (uint32_t*)(b + L.off_dense);
+  s.dctr = (unsigned long long*)(b + L.off_dctr);
+  s.dcap = L.dcap[rbi];
   s.band = (unsigned long long*)(b + L.off_band);
   s.tile_n = (int*)(b + L.off_tilen);
   s.tcap = L.tcap[rbi];
@@ -1786,10 +1881,21 @@ static sbmt_status launch_front(const CallLayout& L, const Src& src, const int64
     case 8: hipLaunchKernelGGL((k_count<Src, 8>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh); break;
     default: hipLaunchKernelGGL((k_count<Src, 16>), dim3((unsigned)ntile), dim3(kThreads), 0, st, src, tt, sh); break;
   }
+  // the dense pass: a grid-stride loop over the queued records (at most rcap)
+  const dim3 gd((unsigned)std::max<int64_t>(1, std::min<int64_t>((L.rcap + kThreads - 1) / kThreads, kSlowBlocks)));
   switch (kRBs[rbi]) {
-    case 4: hipLaunchKernelGGL((k_slow<Src, 4>), dim3((unsigned)ntile), dim3(64), 0, st, src, tt, sh); break;
-    case 8: hipLaunchKernelGGL((k_slow<Src, 8>), dim3((unsigned)ntile), dim3(64), 0, st, src, tt, sh); break;
-    default: hipLaunchKernelGGL((k_slow<Src, 16>), dim3((unsigned)ntile), dim3(64), 0, st, src, tt, sh); break;
+    case 4:
+      hipLaunchKernelGGL((k_slow_dense<Src, 4>), gd, dim3(kThreads), 0, st, src, sh);
+      hipLaunchKernelGGL((k_slow_tiles<Src, 4>), dim3((unsigned)ntile), dim3(64), 0, st, src, tt, sh);
+      break;
+    case 8:
+      hipLaunchKernelGGL((k_slow_dense<Src, 8>), gd, dim3(kThreads), 0, st, src, sh);
+      hipLaunchKernelGGL((k_slow_tiles<Src, 8>), dim3((unsigned)ntile), dim3(64), 0, st, src, tt, sh);
+      break;
+    default:
+      hipLaunchKernelGGL((k_slow_dense<Src, 16>), gd, dim3(kThreads), 0, st, src, sh);
+      hipLaunchKernelGGL((k_slow_tiles<Src, 16>), dim3((unsigned)ntile), dim3(64), 0, st, src, tt, sh);
+      break;
   }
   hipLaunchKernelGGL(k_scan_reduce, dim3(L.nblk), dim3(kScanThreads), 0, st, sh);
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, st, sh);
@@ -1948,6 +2054,13 @@ sbmt_status sbmt_create(int device, sbmt_handle* out) {
     return SBMT_E_DEVICE;
   }
   if (hipHostMalloc((void**)&c->pinned, 8 * sizeof(long long), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return SBMT_E_DEVICE;
+  }
+  // this device's block segment table (idempotent; finished before any use)
+  hipLaunchKernelGGL(k_block_table, dim3(2), dim3(256), 0, 0);
+  if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    hipHostFree(c->pinned);
     delete c;
     return SBMT_E_DEVICE;
   }

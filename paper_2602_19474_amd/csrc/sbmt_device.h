@@ -264,16 +264,11 @@ SBMT_HD int mid_y(const Geo& g, const Frame& f, int m) {
 }
 SBMT_HD int slot_p(const SegSlots& seg, int a) { return (int)((seg.p >> (4 * a)) & 15u); }
 SBMT_HD int slot_q(const SegSlots& seg, int a) { return (int)((seg.q >> (4 * a)) & 15u); }
-// The same slots packed one byte each (start | end << 4): the count pass's form.
-SBMT_HD int slot_p(uint64_t seg, int a) { return (int)((seg >> (8 * a)) & 15); }
-SBMT_HD int slot_q(uint64_t seg, int a) { return (int)((seg >> (8 * a + 4)) & 15); }
 SBMT_HD void slot_set(SegSlots& seg, int a, uint32_t pa, uint32_t pb) {
   seg.p |= pa << (4 * a);
   seg.q |= pb << (4 * a);
 }
-SBMT_HD void slot_set(uint64_t& seg, int a, uint32_t pa, uint32_t pb) { seg |= (uint64_t)(pa | (pb << 4)) << (8 * a); }
 SBMT_HD void slot_clear(SegSlots& seg) { seg.p = seg.q = 0u; }
-SBMT_HD void slot_clear(uint64_t& seg) { seg = 0u; }
 
 // lattice vertex index of the ends of edge e (0 v, 1 vr, 2 vdl, 3 vdr)
 SBMT_HD int edge_u(int e) { return e == 3 ? 1 : (e == 4 ? 2 : 0); }
@@ -388,22 +383,75 @@ SBMT_HD void block_segments(const Frame& f, S& seg, uint32_t& valid) {
 #undef SBMT_S
 }
 
-// Slots whose bounding box meets the bounding box of Tb u Ta (conservative in
-// y); only they can cross an owned edge or hold a chain vertex of Tb, Ta.
-template <class S>
-SBMT_HD uint32_t relevant_slots(const Geo& g, const Frame& f, const S& seg, uint32_t valid) {
-  const int xlo = f.X - 2 * g.h, xhi = f.X + 4 * g.h;
+// Per 3x3 sample pattern s9, the block's segments in table form (entries
+// written on the device by block_table_entry, from block_segments):
+//   block_tab(2 s9)     x, y: the slots' start and end midpoints (SegSlots p, q),
+//                       z: present slots, w: 0;
+//   block_tab(2 s9 + 1) the boxes, slot a in bits [16 (a & 1), +12) of word
+//                       a >> 1 as xlo | xhi << 3 | ylo << 6 | yhi << 9.
+SBMT_HD uint4 block_tab(int i);  // provided by the including translation unit
+
+SBMT_HD void block_table_entry(uint32_t s9, uint4& A, uint4& B) {
+  Frame f;
+  f.X = f.k = f.i = f.o = f.Rlo = f.Clo = 0;
+  f.s9 = s9;
+  SegSlots seg;
+  uint32_t valid;
+  block_segments(f, seg, valid);
+  uint32_t box[4] = {0u, 0u, 0u, 0u};
+  for (int a = 0; a < 8; ++a) {
+    if (!((valid >> a) & 1u)) continue;
+    const int pm = slot_p(seg, a), qm = slot_q(seg, a);
+    const int x0 = min(mid_xi(pm), mid_xi(qm)), x1 = max(mid_xi(pm), mid_xi(qm));
+    const int y0 = min(mid_yi(pm), mid_yi(qm)), y1 = max(mid_yi(pm), mid_yi(qm));
+    box[a >> 1] |= (uint32_t)(x0 | (x1 << 3) | (y0 << 6) | (y1 << 9)) << (16 * (a & 1));
+  }
+  A = make_uint4(seg.p, seg.q, valid, 0u);
+  B = make_uint4(box[0], box[1], box[2], box[3]);
+}
+
+// floor(m / (2 s)) for |m| < 2^23, through a float reciprocal and one correction.
+SBMT_HD int div2s(const Geo& g, int m) {
+  const int d = 2 * g.s;
+  int q = (int)__builtin_floorf((float)m * (2.0f * g.inv4s));
+  if (q * d > m) --q;
+  else if ((q + 1) * d <= m) ++q;
+  return q;
+}
+// floor(n / (2 s U)) = floor((n >> q) / (2 s)); ceil by symmetry.
+SBMT_HD int floor_step(const Geo& g, int n) { return div2s(g, n >> g.q); }
+SBMT_HD int ceil_step(const Geo& g, int n) { return -div2s(g, (-n) >> g.q); }
+
+// A segment can cross an owned edge or end inside Tb or Ta only if its
+// bounding box meets the box [X - h/2, X + h] x [y_k, y_{k+1}] of Tb u Ta
+// (widened by one unit in y, rounded outwards).  With the block's midpoints at
+// (xs + 2sU xi, ys + 2sU yi), the box of a slot [xlo, xhi] x [ylo, yhi] in
+// midpoint indices meets it iff xhi >= x0, xlo <= x1, yhi >= y0, ylo <= y1.
+struct Reach {
+  int x0, x1, y0, y1;
+};
+SBMT_HD Reach owner_reach(const Geo& g, const Frame& f) {
+  const int xs = g.U * (4 * g.s * f.Clo + 2 * (g.s - 1));
+  const int ys = g.U * (4 * g.s * f.Rlo + 2 * (g.s - 1));
   const double yk = (double)(-4 * g.U) + (double)(2 * (int64_t)g.h * f.k) * kSqrt3;
   const int ylo = (int)__builtin_floor(yk) - 1;
   const int yhi = (int)__builtin_ceil(yk + 2.0 * g.h * kSqrt3) + 1;
+  Reach r;
+  r.x0 = ceil_step(g, f.X - 2 * g.h - xs);
+  r.x1 = floor_step(g, f.X + 4 * g.h - xs);
+  r.y0 = ceil_step(g, ylo - ys);
+  r.y1 = floor_step(g, yhi - ys);
+  return r;
+}
+// Present slots whose box meets the reach box.
+SBMT_HD uint32_t relevant_slots(const uint4& B, uint32_t valid, const Reach& r) {
   uint32_t rel = 0;
   for (uint32_t w = valid; w; w &= w - 1) {
     const int a = ctz32(w);
-    const int pm = slot_p(seg, a), qm = slot_q(seg, a);
-    const int px = mid_x(g, f, pm), py = mid_y(g, f, pm), qx = mid_x(g, f, qm), qy = mid_y(g, f, qm);
-    const int sxl = px < qx ? px : qx, sxh = px < qx ? qx : px;
-    const int syl = py < qy ? py : qy, syh = py < qy ? qy : py;
-    if (sxh >= xlo && sxl <= xhi && syh >= ylo && syl <= yhi) rel |= 1u << a;
+    const uint32_t word = a < 2 ? B.x : (a < 4 ? B.y : (a < 6 ? B.z : B.w));
+    const uint32_t bx = word >> (16 * (a & 1));
+    const int x0 = (int)(bx & 7u), x1 = (int)((bx >> 3) & 7u), y0 = (int)((bx >> 6) & 7u), y1 = (int)((bx >> 9) & 7u);
+    if (x1 >= r.x0 && x0 <= r.x1 && y1 >= r.y0 && y0 <= r.y1) rel |= 1u << a;
   }
   return rel;
 }
@@ -517,10 +565,12 @@ SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
   const bool both = (g.flags & 1u) != 0;
   const int h = g.h, X = f.X;
   const int64_t hk = (int64_t)h * f.k;
+  const uint4 A = block_tab(2 * (int)f.s9), B = block_tab(2 * (int)f.s9 + 1);
   SegSlots seg;
-  uint32_t valid;
-  block_segments(f, seg, valid);
-  const uint32_t rel = relevant_slots(g, f, seg, valid);
+  seg.p = A.x;
+  seg.q = A.y;
+  const uint32_t valid = A.z;
+  const uint32_t rel = relevant_slots(B, valid, owner_reach(g, f));
   // signs of the five possible point rows against the horizontal edge lines
   // E0 (row k) and E4 (row k+1): bit yi.  Then, per relevant slot, the signs of
   // both ends against E0..E4 (5 bits each) and of the lattice vertices
@@ -619,11 +669,12 @@ SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
 // it: the fast counts with the exact inside bit) or slow.  Returns true if
 // the full slow classification is needed.
 SBMT_HD bool needs_slow(const Geo& g, const Frame& f, uint32_t& info) {
-  uint64_t seg;
-  uint32_t valid;
-  block_segments(f, seg, valid);
-  if (relevant_slots(g, f, seg, valid)) return true;
-  info = quiet_info(g, f, owner_inside(g, f, seg, valid));
+  const uint4 A = block_tab(2 * (int)f.s9);
+  if (relevant_slots(block_tab(2 * (int)f.s9 + 1), A.z, owner_reach(g, f))) return true;
+  SegSlots seg;
+  seg.p = A.x;
+  seg.q = A.y;
+  info = quiet_info(g, f, owner_inside(g, f, seg, A.z));
   return false;
 }
 

@@ -372,6 +372,8 @@ struct CountLds {
   uint32_t u0[RB][kWinWords], u1[RB][kWinWords];  // uniform-window masks per row
   alignas(8) uint16_t code[RB][kCB];
   int rowR[RB];
+  int ry0[RB], ry1[RB];  // reach of each row in the midpoint indices of its blocks
+  uint32_t rowp[RB];     // row_info of each row
   uint16_t q1[RB * kCB];
   uint16_t q2[RB * kCB];
   int n1, n2;
@@ -393,10 +395,27 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
   const int lane = threadIdx.x & 63;
   if (threadIdx.x < RB) {
     L.rowR[threadIdx.x] = row_cell(g, k0 + threadIdx.x);
+    L.rowp[threadIdx.x] = 0u;
     L.acc[threadIdx.x][0] = L.acc[threadIdx.x][1] = L.acc[threadIdx.x][2] = L.acc[threadIdx.x][3] = 0;
   }
   if (threadIdx.x == 0) L.n1 = L.n2 = 0;
   __syncthreads();
+  // each row's reach and exact row signs (row_info), sixteen lanes a row:
+  // lane j < 10 one sign (row0 bit j, row4 bit j - 5), lane 10 the reach
+  for (int t = threadIdx.x; t < RB * 16; t += kThreads) {
+    const int r = t >> 4, j = t & 15, k = k0 + r, R = L.rowR[r];
+    if (j < 10) {
+      const int64_t hk = (int64_t)g.h * k + (j >= 5 ? g.h : 0);
+      const int Ay = g.U * (4 * g.s * R + 2 * (g.s - 1)) + 2 * g.s * g.U * (j % 5) + 4 * g.U;
+      if (z3sign(Ay, -2 * hk) > 0) atomicOr(&L.rowp[r], 1u << (16 + j));
+    } else if (j == 10) {
+      int y0, y1;
+      row_reach(g, k, R, y0, y1);
+      L.ry0[r] = y0;
+      L.ry1[r] = y1;
+      atomicOr(&L.rowp[r], pack_row(y0, y1, 0u, 0u));
+    }
+  }
   const int klast = min(k0 + RB, g.NK) - 1;
   const Bits bw = stage_window(g, d.bits, L.win, L.rowR[0] + kRing, L.rowR[klast - k0] + 2 + kRing, c0,
                                min(c0 + kCB, g.NI) - 1);
@@ -461,7 +480,7 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
     const int k = k0 + r;
     const Frame f = owner_frame(g, bw, k, c, L.rowR[r]);
     uint32_t fi = 0;
-    if (needs_slow(g, f, fi)) {
+    if (needs_slow(g, f, L.ry0[r], L.ry1[r], fi)) {
       L.q2[atomicAdd(&L.n2, 1)] = (uint16_t)e;
       L.code[r][e - r * kCB] = 0x8000;
     } else {
@@ -484,10 +503,10 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
     const int e = L.q2[q], r = e / kCB, c = c0 + (e - r * kCB);
     const int k = k0 + r;
     if (q < sh.tcap) {
-      // position, and the cell row of the owner's row for the dense pass
+      // position, and the cell row and row_info of the owner's row for the dense pass
       SlowRec R;
       R.info = (uint32_t)L.rowR[r];
-      R.tri = 0u;
+      R.tri = L.rowp[r];
       R.x = (uint64_t)c | ((uint64_t)k << 24) | ((uint64_t)ii << 48);
       sh.rec[tile * sh.tcap + q] = R;
       if (kDense) sh.dense[L.dbase + q] = (uint32_t)(tile * sh.tcap + q);
@@ -573,7 +592,7 @@ __global__ void __launch_bounds__(kThreads) k_slow_dense(Src src, Shared sh) {
     b.cc0 = 0;
     const Frame f = owner_frame(g, b, k, c, (int)P.info);
     Slow sr;
-    slow_classify(g, f, sr);
+    slow_classify(g, f, P.tri, sr);
     SlowRec R = pack_slow(sr);
     R.x |= (uint64_t)(((k & (RB - 1)) << 8) | (c & (kCB - 1))) << 48;
     sh.rec[idx] = R;

@@ -430,18 +430,28 @@ SBMT_HD int ceil_step(const Geo& g, int n) { return -div2s(g, (-n) >> g.q); }
 struct Reach {
   int x0, x1, y0, y1;
 };
-SBMT_HD Reach owner_reach(const Geo& g, const Frame& f) {
-  const int xs = g.U * (4 * g.s * f.Clo + 2 * (g.s - 1));
-  const int ys = g.U * (4 * g.s * f.Rlo + 2 * (g.s - 1));
-  const double yk = (double)(-4 * g.U) + (double)(2 * (int64_t)g.h * f.k) * kSqrt3;
+// The y range depends on the row only (k and its cell row Rlo).
+SBMT_HD void row_reach(const Geo& g, int k, int Rlo, int& y0, int& y1) {
+  const int ys = g.U * (4 * g.s * Rlo + 2 * (g.s - 1));
+  const double yk = (double)(-4 * g.U) + (double)(2 * (int64_t)g.h * k) * kSqrt3;
   const int ylo = (int)__builtin_floor(yk) - 1;
   const int yhi = (int)__builtin_ceil(yk + 2.0 * g.h * kSqrt3) + 1;
+  y0 = ceil_step(g, ylo - ys);
+  y1 = floor_step(g, yhi - ys);
+}
+SBMT_HD Reach owner_reach(const Geo& g, const Frame& f, int y0, int y1) {
+  const int xs = g.U * (4 * g.s * f.Clo + 2 * (g.s - 1));
   Reach r;
   r.x0 = ceil_step(g, f.X - 2 * g.h - xs);
   r.x1 = floor_step(g, f.X + 4 * g.h - xs);
-  r.y0 = ceil_step(g, ylo - ys);
-  r.y1 = floor_step(g, yhi - ys);
+  r.y0 = y0;
+  r.y1 = y1;
   return r;
+}
+SBMT_HD Reach owner_reach(const Geo& g, const Frame& f) {
+  int y0, y1;
+  row_reach(g, f.k, f.Rlo, y0, y1);
+  return owner_reach(g, f, y0, y1);
 }
 // Present slots whose box meets the reach box.
 SBMT_HD uint32_t relevant_slots(const uint4& B, uint32_t valid, const Reach& r) {
@@ -484,6 +494,33 @@ SBMT_HD int owner_inside(const Geo& g, const Frame& f, const S& seg, uint32_t va
   return fg;
 }
 
+// Inside bit of the owner vertex v of a quiet owner (no slot's box meets the
+// reach box, which holds v).  Then v lies in none of the segment boxes of its
+// dual cell (0, cv), i.e. in the part of the cell holding the corners that the
+// marching-squares segments do not cut off: with one corner apart from the
+// other three, that corner is cut off (a segment box is the quarter cell at
+// the corner); at a saddle the background pair is cut off; with two adjacent
+// corners apart the segment runs straight through the middle of the cell and
+// v's side of it is one exact comparison (v never lies on a midline).
+SBMT_HD int quiet_inside(const Geo& g, const Frame& f) {
+  const int X = f.X;
+  const int cv = div4s(g, X - 2 * (g.s - 1) * g.U) - f.Clo;
+  const int a = (int)((f.s9 >> cv) & 1u), b = (int)((f.s9 >> (cv + 1)) & 1u);
+  const int c = (int)((f.s9 >> (4 + cv)) & 1u), d = (int)((f.s9 >> (3 + cv)) & 1u);
+  const int n = a + b + c + d;
+  if (n != 2) return n >= 2 ? 1 : 0;
+  if (a == c) return 1;  // saddle: foreground 8-connected
+  if (a == b) {
+    // top pair apart from the bottom pair: the segment joins the left and
+    // right midpoints at height ym; v above it (y_k < ym) sits with the top pair
+    const int ym = mid_y(g, f, 6 + cv);
+    return z3sign((int64_t)ym + 4 * g.U, -2 * (int64_t)g.h * f.k) > 0 ? a : d;
+  }
+  // left pair apart from the right pair: the segment joins the top and bottom
+  // midpoints at abscissa xm
+  return X < mid_x(g, f, cv) ? a : b;
+}
+
 // Counts of an owner whose window is not uniform but which no segment can
 // reach (no relevant slot): like the fast path with the exact inside bit.
 SBMT_HD uint32_t quiet_info(const Geo& g, const Frame& f, int fg) {
@@ -503,22 +540,13 @@ SBMT_HD int sgn_eval(double v, double band, int64_t a, int64_t b, bool& ok) {
 }
 
 template <bool EXACT>
-SBMT_HD bool slot_signs(const Geo& g, const Frame& f, const SegSlots& seg, uint32_t rel, uint32_t& row0, uint32_t& row4,
+SBMT_HD bool slot_signs(const Geo& g, const Frame& f, const SegSlots& seg, uint32_t rel, uint32_t row0, uint32_t row4,
                         uint64_t& sp, uint64_t& sq, uint32_t& lv) {
   bool ok = true;
   const int h = g.h, X = f.X;
   const double band = g.band;
   const int64_t hk = (int64_t)h * f.k;
-  const int ys = g.U * (4 * g.s * f.Rlo + 2 * (g.s - 1));
-  const double yk = (double)(2 * hk) * kSqrt3, yk1 = (double)(2 * (hk + h)) * kSqrt3;
-  row0 = 0;
-  row4 = 0;
-#pragma unroll
-  for (int yi = 0; yi < 5; ++yi) {
-    const int Ay = ys + 2 * g.s * g.U * yi + 4 * g.U;
-    row0 |= (uint32_t)(sgn_eval<EXACT>((double)Ay - yk, band, Ay, -2 * hk, ok) > 0) << yi;
-    row4 |= (uint32_t)(sgn_eval<EXACT>((double)Ay - yk1, band, Ay, -2 * (hk + h), ok) > 0) << yi;
-  }
+  const double yk = (double)(2 * hk) * kSqrt3;
   sp = 0;
   sq = 0;
   lv = 0;
@@ -561,7 +589,44 @@ SBMT_HD bool slot_signs(const Geo& g, const Frame& f, const SegSlots& seg, uint3
   return ok;
 }
 
-SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
+// Signs of the five point rows of a block (bit yi: the midpoint row yi lies
+// below the line) against the horizontal edge lines of grid rows k (row0) and
+// k + 1 (row4), exactly; they depend on the row only.
+SBMT_HD void row_signs(const Geo& g, int k, int Rlo, uint32_t& row0, uint32_t& row4) {
+  const int64_t hk = (int64_t)g.h * k;
+  const int ys = g.U * (4 * g.s * Rlo + 2 * (g.s - 1));
+  row0 = 0;
+  row4 = 0;
+  for (int yi = 0; yi < 5; ++yi) {
+    const int Ay = ys + 2 * g.s * g.U * yi + 4 * g.U;
+    row0 |= (uint32_t)(z3sign(Ay, -2 * hk) > 0) << yi;
+    row4 |= (uint32_t)(z3sign(Ay, -2 * (hk + g.h)) > 0) << yi;
+  }
+}
+
+// What the classification needs of the owner's row, packed in 32 bits (the
+// count pass computes it once per row and hands it over in the record):
+// y0, y1 of row_reach as signed bytes, row0 in bits 16..20, row4 in 21..25.
+SBMT_HD uint32_t pack_row(int y0, int y1, uint32_t row0, uint32_t row4) {
+  return (uint32_t)(y0 & 255) | ((uint32_t)(y1 & 255) << 8) | (row0 << 16) | (row4 << 21);
+}
+SBMT_HD uint32_t row_info(const Geo& g, int k, int Rlo) {
+  int y0, y1;
+  uint32_t row0, row4;
+  row_reach(g, k, Rlo, y0, y1);
+  row_signs(g, k, Rlo, row0, row4);
+  return pack_row(y0, y1, row0, row4);
+}
+
+// Per relevant slot a, the 5-bit set of owned edges E0..E4 that its segment
+// crosses: the ends lie on different sides of the edge line (d) and the edge
+// ends on different sides of the segment line (l4: v, vr, vdl, vdr).
+SBMT_HD uint32_t edge_split(uint32_t l4) {
+  const uint32_t v = l4 & 1u, vr = (l4 >> 1) & 1u, vdl = (l4 >> 2) & 1u, vdr = (l4 >> 3) & 1u;
+  return (v ^ vr) | ((v ^ vdl) << 1) | ((v ^ vdr) << 2) | ((vr ^ vdr) << 3) | ((vdl ^ vdr) << 4);
+}
+
+SBMT_HD void slow_classify(const Geo& g, const Frame& f, uint32_t rowp, Slow& r) {
   const bool both = (g.flags & 1u) != 0;
   const int h = g.h, X = f.X;
   const int64_t hk = (int64_t)h * f.k;
@@ -570,32 +635,26 @@ SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
   seg.p = A.x;
   seg.q = A.y;
   const uint32_t valid = A.z;
-  const uint32_t rel = relevant_slots(B, valid, owner_reach(g, f));
-  // signs of the five possible point rows against the horizontal edge lines
-  // E0 (row k) and E4 (row k+1): bit yi.  Then, per relevant slot, the signs of
-  // both ends against E0..E4 (5 bits each) and of the lattice vertices
-  // v, vr, vdl, vdr against the segment line (4 bits).  All in double
-  // precision first; if any value falls in the uncertainty band the same
-  // quantities are recomputed exactly.
-  uint32_t row0, row4;
+  const int y0 = (int)(int8_t)(rowp & 255u), y1 = (int)(int8_t)((rowp >> 8) & 255u);
+  const uint32_t rel = relevant_slots(B, valid, owner_reach(g, f, y0, y1));
+  // per relevant slot, the signs of both ends against E0..E4 (5 bits each;
+  // E0 and E4 from the row's signs) and of the lattice vertices v, vr, vdl,
+  // vdr against the segment line (4 bits).  In double precision first; if any
+  // value falls in the uncertainty band the same quantities are recomputed
+  // exactly.
+  const uint32_t row0 = (rowp >> 16) & 31u, row4 = (rowp >> 21) & 31u;
   uint64_t sp, sq;
   uint32_t lv;
   if (!slot_signs<false>(g, f, seg, rel, row0, row4, sp, sq, lv))
     slot_signs<true>(g, f, seg, rel, row0, row4, sp, sq, lv);
-  // crossing sets: the segment ends on different sides of the edge line and the
-  // edge ends on different sides of the segment line
+  // crossing sets
   uint64_t xm = 0;
   for (uint32_t w = rel; w; w &= w - 1) {
     const int a = ctz32(w);
-    {
-      const uint32_t d = ((uint32_t)(sp >> (8 * a)) ^ (uint32_t)(sq >> (8 * a))) & 31u;
-      const uint32_t l4 = (lv >> (4 * a)) & 15u;
-#pragma unroll
-      for (int e = 0; e < 5; ++e) {
-        const uint32_t lu = (l4 >> edge_u(e)) & 1u, lw = (l4 >> edge_v(e)) & 1u;
-        if (((d >> e) & 1u) && lu != lw) xm |= 1ull << (8 * e + a);
-      }
-    }
+    const uint32_t x5 = ((uint32_t)(sp >> (8 * a)) ^ (uint32_t)(sq >> (8 * a))) & edge_split((lv >> (4 * a)) & 15u);
+    xm |= ((uint64_t)(x5 & 1u) | ((uint64_t)((x5 >> 1) & 1u) << 8) | ((uint64_t)((x5 >> 2) & 1u) << 16) |
+           ((uint64_t)((x5 >> 3) & 1u) << 24) | ((uint64_t)((x5 >> 4) & 1u) << 32))
+          << a;
   }
   // order along each edge; two crossings come from consecutive segments S1 -> S2
   // sharing a vertex M, and S2's lies further along U->V iff
@@ -665,16 +724,17 @@ SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
   r.tri = (uint32_t)(clsb | (rotb << 5) | ((clsa | (rota << 5)) << 8) | (Ib << 16) | (Ia << 20));
 }
 
+SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
+  slow_classify(g, f, row_info(g, f.k, f.Rlo), r);
+}
+
 // Classify an owner whose window is not uniform: quiet (no segment can reach
 // it: the fast counts with the exact inside bit) or slow.  Returns true if
-// the full slow classification is needed.
-SBMT_HD bool needs_slow(const Geo& g, const Frame& f, uint32_t& info) {
+// the full slow classification is needed.  y0, y1: the row's reach (row_reach).
+SBMT_HD bool needs_slow(const Geo& g, const Frame& f, int y0, int y1, uint32_t& info) {
   const uint4 A = block_tab(2 * (int)f.s9);
-  if (relevant_slots(block_tab(2 * (int)f.s9 + 1), A.z, owner_reach(g, f))) return true;
-  SegSlots seg;
-  seg.p = A.x;
-  seg.q = A.y;
-  info = quiet_info(g, f, owner_inside(g, f, seg, A.z));
+  if (relevant_slots(block_tab(2 * (int)f.s9 + 1), A.z, owner_reach(g, f, y0, y1))) return true;
+  info = quiet_info(g, f, quiet_inside(g, f));
   return false;
 }
 

@@ -75,6 +75,7 @@ constexpr int kSlowBlocks = 2048;              // dense slow pass: blocks of its
 constexpr int kDenseLists = 64;                // dense slow lists (tile mod 64), each with its own counter
 constexpr int kSizeWords = SBMT_SIZE_WORDS;    // per-image sizes record
 constexpr int kSegSlots = 64;                  // partial segment counts per image (spread atomics)
+constexpr int kRowPad = 20;                    // row-table entries past the last grid row (tile and halo rows)
 
 // One image of a call, as the kernels see it.
 struct Img {
@@ -82,6 +83,7 @@ struct Img {
   const uint8_t* bm;  // bitmap rows (device)
   uint32_t* bits;     // coarse raster, (CH + 2 kRing) rows of wpr words
   uint16_t* omap;     // [NK][NI] owner map of the multi-kernel path, see map_code
+  RowT* rows;         // [NK + kRowPad] per grid row data of the exact predicates (row_table_entry)
   int64_t seg0;       // first row segment of the image in the call's segment arrays
   int64_t band0;      // first band of the image (fused path, 4-row numbering)
   int64_t halo0;      // first word of the image's halo rows (fused path)
@@ -300,6 +302,12 @@ __global__ void __launch_bounds__(256) k_segcount(Src src, const int64_t* __rest
   const int nrows = g.CH + 2 * kRing;
   const int rpb = (nrows + nb - 1) / nb;
   const int r0 = (int)local * rpb, r1 = min(r0 + rpb, nrows);
+  // the row table: grid rows 16 local .. 16 local + 15 (the last block also
+  // the padding rows past the grid)
+  {
+    const int k0 = 16 * (int)local, k1 = (int)local == nb - 1 ? g.NK + kRowPad : k0 + 16;
+    for (int k = k0 + (int)threadIdx.x; k < k1; k += 256) d.rows[k] = row_table_entry(g, k);
+  }
   int n = 0;
   for (int t = threadIdx.x; t < (r1 - r0) * g.wpr; t += 256) {
     const int rr = r0 + t / g.wpr, w = t - (t / g.wpr) * g.wpr;
@@ -372,8 +380,8 @@ struct CountLds {
   uint32_t u0[RB][kWinWords], u1[RB][kWinWords];  // uniform-window masks per row
   alignas(8) uint16_t code[RB][kCB];
   int rowR[RB];
-  int ry0[RB], ry1[RB];  // reach of each row in the midpoint indices of its blocks
-  uint32_t rowp[RB];     // row_info of each row
+  uint32_t rowp[RB];     // row_info of each row (reach in y, row signs)
+  uint32_t xc[2][kCB];   // per column and row parity: Clo - (window's first column) | x0 << 16 | x1 << 20
   uint16_t q1[RB * kCB];
   uint16_t q2[RB * kCB];
   int n1, n2;
@@ -394,28 +402,14 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
   const int c0 = cb * kCB;
   const int lane = threadIdx.x & 63;
   if (threadIdx.x < RB) {
-    L.rowR[threadIdx.x] = row_cell(g, k0 + threadIdx.x);
-    L.rowp[threadIdx.x] = 0u;
+    // the row table holds every row a tile reaches (kRowPad rows past the grid)
+    const RowT& rt = d.rows[k0 + threadIdx.x];
+    L.rowR[threadIdx.x] = rt.R;
+    L.rowp[threadIdx.x] = rt.pk;
     L.acc[threadIdx.x][0] = L.acc[threadIdx.x][1] = L.acc[threadIdx.x][2] = L.acc[threadIdx.x][3] = 0;
   }
   if (threadIdx.x == 0) L.n1 = L.n2 = 0;
   __syncthreads();
-  // each row's reach and exact row signs (row_info), sixteen lanes a row:
-  // lane j < 10 one sign (row0 bit j, row4 bit j - 5), lane 10 the reach
-  for (int t = threadIdx.x; t < RB * 16; t += kThreads) {
-    const int r = t >> 4, j = t & 15, k = k0 + r, R = L.rowR[r];
-    if (j < 10) {
-      const int64_t hk = (int64_t)g.h * k + (j >= 5 ? g.h : 0);
-      const int Ay = g.U * (4 * g.s * R + 2 * (g.s - 1)) + 2 * g.s * g.U * (j % 5) + 4 * g.U;
-      if (z3sign(Ay, -2 * hk) > 0) atomicOr(&L.rowp[r], 1u << (16 + j));
-    } else if (j == 10) {
-      int y0, y1;
-      row_reach(g, k, R, y0, y1);
-      L.ry0[r] = y0;
-      L.ry1[r] = y1;
-      atomicOr(&L.rowp[r], pack_row(y0, y1, 0u, 0u));
-    }
-  }
   const int klast = min(k0 + RB, g.NK) - 1;
   const Bits bw = stage_window(g, d.bits, L.win, L.rowR[0] + kRing, L.rowR[klast - k0] + 2 + kRing, c0,
                                min(c0 + kCB, g.NI) - 1);
@@ -431,7 +425,13 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
   const int c = c0 + threadIdx.x;
   int wcol[2];
 #pragma unroll
-  for (int o = 0; o < 2; ++o) wcol[o] = clo_of(g, g.X0 + 4 * g.h * c + 2 * g.h * o) + kRingC - bw.cc0;
+  for (int o = 0; o < 2; ++o) {
+    const int X = g.X0 + 4 * g.h * c + 2 * g.h * o, Clo = clo_of(g, X);
+    wcol[o] = Clo + kRingC - bw.cc0;
+    int x0, x1;
+    owner_xreach(g, X, Clo, x0, x1);
+    L.xc[o][threadIdx.x] = (uint32_t)wcol[o] | ((uint32_t)x0 << 16) | ((uint32_t)x1 << 20);
+  }
   // away from the grid edges both owned triangles exist for every owner, so a
   // uniform owner's counts are constants and a row's sums are popcounts
   const bool interior = k0 + RB < g.NK && c0 >= 1 && c0 + kCB < g.NI;
@@ -476,11 +476,12 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
   __syncthreads();
   // non-uniform windows: quiet owners (no segment reaches them) or slow ones
   for (int q = threadIdx.x; q < L.n1; q += kThreads) {
-    const int e = L.q1[q], r = e / kCB, c = c0 + (e - r * kCB);
+    const int e = L.q1[q], r = e / kCB, col = e - r * kCB, c = c0 + col;
     const int k = k0 + r;
-    const Frame f = owner_frame(g, bw, k, c, L.rowR[r]);
+    const uint32_t xc = L.xc[k & 1][col];
+    const Frame f = owner_frame_at(g, bw, k, c, L.rowR[r], (int)(xc & 0xffffu) - kRingC + bw.cc0);
     uint32_t fi = 0;
-    if (needs_slow(g, f, L.ry0[r], L.ry1[r], fi)) {
+    if (needs_slow(g, f, (int)((xc >> 16) & 15u), (int)((xc >> 20) & 15u), L.rowp[r], fi)) {
       L.q2[atomicAdd(&L.n2, 1)] = (uint16_t)e;
       L.code[r][e - r * kCB] = 0x8000;
     } else {
@@ -503,12 +504,8 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
     const int e = L.q2[q], r = e / kCB, c = c0 + (e - r * kCB);
     const int k = k0 + r;
     if (q < sh.tcap) {
-      // position, and the cell row and row_info of the owner's row for the dense pass
-      SlowRec R;
-      R.info = (uint32_t)L.rowR[r];
-      R.tri = L.rowp[r];
-      R.x = (uint64_t)c | ((uint64_t)k << 24) | ((uint64_t)ii << 48);
-      sh.rec[tile * sh.tcap + q] = R;
+      // the owner's position for the dense pass
+      sh.rec[tile * sh.tcap + q].x = (uint64_t)c | ((uint64_t)k << 24) | ((uint64_t)ii << 48);
       if (kDense) sh.dense[L.dbase + q] = (uint32_t)(tile * sh.tcap + q);
     }
   }
@@ -590,9 +587,10 @@ __global__ void __launch_bounds__(kThreads) k_slow_dense(Src src, Shared sh) {
     b.wpr = g.wpr;
     b.rr0 = 0;
     b.cc0 = 0;
-    const Frame f = owner_frame(g, b, k, c, (int)P.info);
+    const RowT& rt = d.rows[k];
+    const Frame f = owner_frame(g, b, k, c, rt.R);
     Slow sr;
-    slow_classify(g, f, P.tri, sr);
+    slow_classify(g, f, rt, d.rows[k + 1].FL, sr);
     SlowRec R = pack_slow(sr);
     R.x |= (uint64_t)(((k & (RB - 1)) << 8) | (c & (kCB - 1))) << 48;
     sh.rec[idx] = R;
@@ -623,7 +621,7 @@ __global__ void __launch_bounds__(64) k_slow_tiles(Src src, const int64_t* __res
   const int cb = (int)local % g.NCB, ky = (int)local / g.NCB;  // tile index of an image: 32 bits
   if (threadIdx.x < RB) {
     acc[threadIdx.x] = 0ull;
-    if (over) rowR[threadIdx.x] = row_cell(g, ky * RB + threadIdx.x);
+    if (over) rowR[threadIdx.x] = d.rows[ky * RB + threadIdx.x].R;
   }
   if (over)
     for (int t = threadIdx.x; t < RB * kCB / 32; t += 64) hasrec[t] = 0u;
@@ -655,7 +653,7 @@ __global__ void __launch_bounds__(64) k_slow_tiles(Src src, const int64_t* __res
     if (d.omap[(int64_t)k * g.NI + c] != 0x8000u) continue;
     const Frame f = owner_frame(g, b, k, c, rowR[r]);
     Slow sr;
-    slow_classify(g, f, sr);
+    slow_classify(g, f, d.rows[k], d.rows[k + 1].FL, sr);
     d.omap[(int64_t)k * g.NI + c] = (uint16_t)map_code(sr.info);
     atomicAdd(&acc[r], pack_counts(sr.info));
     if (info_err(sr.info)) atomicOr(&sh.imgerr[ii], 1);
@@ -971,7 +969,7 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
   constexpr int kLut = 15 * 3 * 2 * 5;
   static_assert(kLut <= 2 * kThreads, "two table entries per thread");
   const int c0 = cb * kCB;
-  if (threadIdx.x <= RB) L.rowR[threadIdx.x] = row_cell(g, k0 + threadIdx.x);  // read after step 2
+  if (threadIdx.x <= RB) L.rowR[threadIdx.x] = d.rows[k0 + threadIdx.x].R;  // read after step 2
   Bits bw;
   bw.p = d.bits;
   bw.wpr = g.wpr;
@@ -1149,7 +1147,7 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
       const int k = k0 + r, c = c0 + col - 1;
       const Frame fr = owner_frame(g, bw, k, c, L.rowR[r]);
       Slow sr;
-      slow_classify(g, fr, sr);
+      slow_classify(g, fr, d.rows[k], d.rows[k + 1].FL, sr);
       const Nb nb = neighbours(r, col, map_info(L.info[r][col]), k & 1);
       emit_slow(g, fr, pack_slow(sr), nb, L.tb[r] + L.toff[r][col], out, L.lut);
     }
@@ -1258,7 +1256,7 @@ __global__ void __launch_bounds__(kThreads, 8) k_emit(Src src, const int64_t* __
     const longlong4 o = sh.seg_off[d.seg0 + (k < g.NK ? (int64_t)k * g.NCB + cb : nsegi)];
     L.bv[threadIdx.x] = (int)(o.x - base.x);
     if (threadIdx.x < RB) L.tb[threadIdx.x] = o.y - base.y;
-    L.rowR[threadIdx.x] = row_cell(g, k);
+    L.rowR[threadIdx.x] = d.rows[k].R;
   }
   L.lut[threadIdx.x] = lut0;
   if (threadIdx.x + kThreads < kLut) L.lut[threadIdx.x + kThreads] = lut1;
@@ -1506,9 +1504,9 @@ __global__ void __launch_bounds__(kThreads, 3) k_fused(ManySrc src, const int64_
       b.wpr = g.wpr;
       b.rr0 = 0;
       b.cc0 = 0;
-      const Frame f = owner_frame(g, b, k, c, row_cell(g, k));
+      const Frame f = owner_frame(g, b, k, c, d.rows[k].R);
       Slow sr;
-      slow_classify(g, f, sr);
+      slow_classify(g, f, d.rows[k], d.rows[k + 1].FL, sr);
       SlowRec R = pack_slow(sr);
       R.x |= (uint64_t)((r << 8) | (c - lo * kCB)) << 48;
       sh.rec[idx] = R;
@@ -1703,8 +1701,6 @@ static sbmt_status make_geo(const sbmt_image* img, Geo* out, bool need_ptr) {
   g.inv4s = 1.0f / (float)(4 * g.s);
   g.xscale = 0.25 / (double)g.U;
   g.invU = 1.0 / (double)g.U;
-  // 20 times the rounding bound of the double-precision signs (about 5e-15 s U^2 side)
-  g.band = std::max(1e-6, 1e-13 * (double)g.s * g.U * g.U * (double)side);
   if (!windows_in_bounds(g) || !tile_window_fits(g)) return SBMT_E_INVALID_ARG;
   // owner positions in record lists: 24 bits per coordinate
   if (g.NK >= (1 << 24) || g.NI >= (1 << 24)) return SBMT_E_INVALID_ARG;
@@ -1719,7 +1715,7 @@ static const int kRBs[3] = {4, 8, 16};
 struct CallLayout {
   int n = 0;
   std::vector<Geo> g;
-  std::vector<size_t> off_bits, off_omap;
+  std::vector<size_t> off_bits, off_omap, off_rows;
   std::vector<int64_t> seg0, band0, halo0;  // band0, halo0 for the smallest fused band height
   std::vector<int64_t> tab;           // [1 + 3 + 3][n + 1]: coarsen blocks, tiles per RB, bands per RB
   int64_t nseg = 0, owners = 0, rcap = 0, nbands_max = 0, halo_words = 0, ntiles_max = 0;
@@ -1741,6 +1737,7 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
   L.g.resize(n);
   L.off_bits.resize(n);
   L.off_omap.resize(n);
+  L.off_rows.resize(n);
   L.seg0.resize(n);
   L.band0.resize(n);
   L.halo0.resize(n);
@@ -1832,6 +1829,8 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
     off = align256(off + (size_t)(g.CH + 2 * kRing) * g.wpr * 4);
     L.off_omap[i] = off;
     off = align256(off + (size_t)g.NK * g.NI * 2);
+    L.off_rows[i] = off;
+    off = align256(off + (size_t)(g.NK + kRowPad) * sizeof(RowT));
   }
   L.total = off;
   return SBMT_OK;
@@ -1870,6 +1869,7 @@ static Img img_of(const CallLayout& L, int i, const sbmt_image& im, void* ws, co
   d.bm = im.bitmap;
   d.bits = (uint32_t*)(b + L.off_bits[i]);
   d.omap = (uint16_t*)(b + L.off_omap[i]);
+  d.rows = (RowT*)(b + L.off_rows[i]);
   d.seg0 = L.seg0[i];
   d.band0 = L.band0[i];
   d.halo0 = L.halo0[i];

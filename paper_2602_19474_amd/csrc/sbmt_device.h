@@ -22,8 +22,10 @@
 // coordinates are integers in units of 1 / (4U) pixel.  Boundary points are
 // multiples of 2U (even); grid vertex (k,i) is at X = X0 + 4p*i + 2p*o with X0
 // odd, and Y = -4U + 2pk*sqrt3.  Every predicate is sign(A + B*sqrt3) with
-// integer A, B, never zero (x parity, irrationality of sqrt3), decided by a
-// floating-point filter with an exact integer fallback.  Geo::h holds p.
+// integer A, B, never zero (x parity, irrationality of sqrt3).  Each is decided
+// in integer arithmetic: per grid row, the floor of its line's ordinate and the
+// floors of a / sqrt3 for the block's midpoint ordinates a (RowT) turn every
+// sign into one integer comparison.  Geo::h holds p.
 #pragma once
 #include <stdint.h>
 
@@ -44,7 +46,6 @@ struct Geo {
   int32_t q, U;  // U = 2^q: one unit is 1 / (4U) pixel
   uint32_t flags;
   float inv4s;    // 1 / (4 s)
-  double band;    // |value| below which a double-precision sign is recomputed exactly
   double xscale;  // 0.25 / U: units -> pixels
   double invU;    // 1 / U
 };
@@ -57,27 +58,22 @@ SBMT_HD int z3sign(int64_t a, int64_t b) {
   return a > 0 ? (a2 > b2 ? 1 : -1) : (b2 > a2 ? 1 : -1);
 }
 
-// Same sign through a double-precision filter: |fl(a + b*c) - (a + b*sqrt3)|
-// < 5e-16 (|a| + 2|b|) for |a|, |b| < 2^31, so a larger magnitude decides.
-SBMT_HD int z3sign_f(int64_t a, int64_t b) {
-  const double d = (double)a + (double)b * 1.7320508075688772;
-  const double m = 4e-15 * ((double)(a < 0 ? -a : a) + 2.0 * (double)(b < 0 ? -b : b));
-  if (d > m) return 1;
-  if (d < -m) return -1;
-  return z3sign(a, b);
-}
-
 constexpr double kSqrt3 = 1.7320508075688772;
 
-// Sign of a quantity whose exact value is a + b*sqrt3 (integers a, b with
-// |a|, |b| < 2^31) and whose double-precision evaluation in owner-local
-// coordinates is v.  The rounding error of v stays below about
-// 5e-15 s U^2 (image side in pixels); outside the band g.band (at least 1e-6,
-// and 20 times that bound) the double decides, inside it the exact test.
-SBMT_HD int sgn_filtered(double v, double band, int64_t a, int64_t b) {
-  if (v > band) return 1;
-  if (v < -band) return -1;
-  return z3sign(a, b);
+// floor(sqrt(n)) for n < 2^62: a double estimate, then exact integer steps.
+SBMT_HD uint64_t isqrt_u64(uint64_t n) {
+  uint64_t r = (uint64_t)__builtin_sqrt((double)n);
+  while (r * r > n) --r;
+  while ((r + 1) * (r + 1) <= n) ++r;
+  return r;
+}
+
+// floor(a / sqrt3) for |a| < 2^31: the largest m >= 0 with 3 m^2 < a^2 when
+// a > 0 (a / sqrt3 is irrational for a != 0).
+SBMT_HD int floor_div_sqrt3(int64_t a) {
+  if (a == 0) return 0;
+  const int m = (int)isqrt_u64(((uint64_t)(a * a) - 1u) / 3u);
+  return a > 0 ? m : -m - 1;
 }
 
 // floor(n / (4 s U)) = floor((n >> q) / (4 s)) for |n >> q| < 2^24, through a
@@ -182,6 +178,20 @@ SBMT_HD Frame owner_frame(const Geo& g, const Bits& bits, int k, int i, int Rlo)
   f.Rlo = Rlo;
   f.Clo = clo_of(g, f.X);
   const int rr = Rlo + kRing, cc = f.Clo + kRingC;
+  f.s9 = sample3(bits, rr, cc) | (sample3(bits, rr + 1, cc) << 3) | (sample3(bits, rr + 2, cc) << 6);
+  return f;
+}
+
+// The same with the owner's window column Clo already known.
+SBMT_HD Frame owner_frame_at(const Geo& g, const Bits& bits, int k, int i, int Rlo, int Clo) {
+  Frame f;
+  f.k = k;
+  f.i = i;
+  f.o = k & 1;
+  f.X = g.X0 + 4 * g.h * i + 2 * g.h * f.o;
+  f.Rlo = Rlo;
+  f.Clo = Clo;
+  const int rr = Rlo + kRing, cc = Clo + kRingC;
   f.s9 = sample3(bits, rr, cc) | (sample3(bits, rr + 1, cc) << 3) | (sample3(bits, rr + 2, cc) << 6);
   return f;
 }
@@ -387,8 +397,9 @@ SBMT_HD void block_segments(const Frame& f, S& seg, uint32_t& valid) {
 // written on the device by block_table_entry, from block_segments):
 //   block_tab(2 s9)     x, y: the slots' start and end midpoints (SegSlots p, q),
 //                       z: present slots, w: 0;
-//   block_tab(2 s9 + 1) the boxes, slot a in bits [16 (a & 1), +12) of word
-//                       a >> 1 as xlo | xhi << 3 | ylo << 6 | yhi << 9.
+//   block_tab(2 s9 + 1) the slots' boxes in midpoint indices, nibble a of
+//                       x: xlo, y: xhi, z: ylo, w: yhi of slot a (an absent
+//                       slot has the empty box xlo = ylo = 7, xhi = yhi = 0).
 SBMT_HD uint4 block_tab(int i);  // provided by the including translation unit
 
 SBMT_HD void block_table_entry(uint32_t s9, uint4& A, uint4& B) {
@@ -398,16 +409,18 @@ SBMT_HD void block_table_entry(uint32_t s9, uint4& A, uint4& B) {
   SegSlots seg;
   uint32_t valid;
   block_segments(f, seg, valid);
-  uint32_t box[4] = {0u, 0u, 0u, 0u};
+  uint32_t x0 = 0x77777777u, x1 = 0u, y0 = 0x77777777u, y1 = 0u;
   for (int a = 0; a < 8; ++a) {
     if (!((valid >> a) & 1u)) continue;
     const int pm = slot_p(seg, a), qm = slot_q(seg, a);
-    const int x0 = min(mid_xi(pm), mid_xi(qm)), x1 = max(mid_xi(pm), mid_xi(qm));
-    const int y0 = min(mid_yi(pm), mid_yi(qm)), y1 = max(mid_yi(pm), mid_yi(qm));
-    box[a >> 1] |= (uint32_t)(x0 | (x1 << 3) | (y0 << 6) | (y1 << 9)) << (16 * (a & 1));
+    const uint32_t m = ~(15u << (4 * a));
+    x0 = (x0 & m) | ((uint32_t)min(mid_xi(pm), mid_xi(qm)) << (4 * a));
+    x1 |= (uint32_t)max(mid_xi(pm), mid_xi(qm)) << (4 * a);
+    y0 = (y0 & m) | ((uint32_t)min(mid_yi(pm), mid_yi(qm)) << (4 * a));
+    y1 |= (uint32_t)max(mid_yi(pm), mid_yi(qm)) << (4 * a);
   }
   A = make_uint4(seg.p, seg.q, valid, 0u);
-  B = make_uint4(box[0], box[1], box[2], box[3]);
+  B = make_uint4(x0, x1, y0, y1);
 }
 
 // floor(m / (2 s)) for |m| < 2^23, through a float reciprocal and one correction.
@@ -427,6 +440,7 @@ SBMT_HD int ceil_step(const Geo& g, int n) { return -div2s(g, (-n) >> g.q); }
 // (widened by one unit in y, rounded outwards).  With the block's midpoints at
 // (xs + 2sU xi, ys + 2sU yi), the box of a slot [xlo, xhi] x [ylo, yhi] in
 // midpoint indices meets it iff xhi >= x0, xlo <= x1, yhi >= y0, ylo <= y1.
+// Every index lies in 0..4.
 struct Reach {
   int x0, x1, y0, y1;
 };
@@ -439,155 +453,24 @@ SBMT_HD void row_reach(const Geo& g, int k, int Rlo, int& y0, int& y1) {
   y0 = ceil_step(g, ylo - ys);
   y1 = floor_step(g, yhi - ys);
 }
-SBMT_HD Reach owner_reach(const Geo& g, const Frame& f, int y0, int y1) {
-  const int xs = g.U * (4 * g.s * f.Clo + 2 * (g.s - 1));
-  Reach r;
-  r.x0 = ceil_step(g, f.X - 2 * g.h - xs);
-  r.x1 = floor_step(g, f.X + 4 * g.h - xs);
-  r.y0 = y0;
-  r.y1 = y1;
-  return r;
+// The x range depends on the owner's abscissa only.
+SBMT_HD void owner_xreach(const Geo& g, int X, int Clo, int& x0, int& x1) {
+  const int xs = g.U * (4 * g.s * Clo + 2 * (g.s - 1));
+  x0 = ceil_step(g, X - 2 * g.h - xs);
+  x1 = floor_step(g, X + 4 * g.h - xs);
 }
-SBMT_HD Reach owner_reach(const Geo& g, const Frame& f) {
-  int y0, y1;
-  row_reach(g, f.k, f.Rlo, y0, y1);
-  return owner_reach(g, f, y0, y1);
+// Present slots whose box meets the reach box, as bit 4a + 3 for slot a: the
+// four comparisons are made for the eight slots at once in nibble lanes
+// ((8 + u) - v keeps bit 3 iff u >= v, with no borrow for u, v <= 7).
+SBMT_HD uint32_t relevant_nib(const uint4& B, int x0, int x1, int y0, int y1) {
+  constexpr uint32_t M8 = 0x88888888u, R1 = 0x11111111u;
+  const uint32_t c1 = (B.y | M8) - (uint32_t)x0 * R1;
+  const uint32_t c2 = ((uint32_t)x1 * R1 | M8) - B.x;
+  const uint32_t c3 = (B.w | M8) - (uint32_t)y0 * R1;
+  const uint32_t c4 = ((uint32_t)y1 * R1 | M8) - B.z;
+  return c1 & c2 & c3 & c4 & M8;
 }
-// Present slots whose box meets the reach box.
-SBMT_HD uint32_t relevant_slots(const uint4& B, uint32_t valid, const Reach& r) {
-  uint32_t rel = 0;
-  for (uint32_t w = valid; w; w &= w - 1) {
-    const int a = ctz32(w);
-    const uint32_t word = a < 2 ? B.x : (a < 4 ? B.y : (a < 6 ? B.z : B.w));
-    const uint32_t bx = word >> (16 * (a & 1));
-    const int x0 = (int)(bx & 7u), x1 = (int)((bx >> 3) & 7u), y0 = (int)((bx >> 6) & 7u), y1 = (int)((bx >> 9) & 7u);
-    if (x1 >= r.x0 && x0 <= r.x1 && y1 >= r.y0 && y0 <= r.y1) rel |= 1u << a;
-  }
-  return rel;
-}
-
-// Inside bit of the owner vertex: its dual cell (0, cv) of the block is
-// uniform, or v lies left of every segment of that cell.
-template <class S>
-SBMT_HD int owner_inside(const Geo& g, const Frame& f, const S& seg, uint32_t valid) {
-  const int X = f.X;
-  const int cv = div4s(g, X - 2 * (g.s - 1) * g.U) - f.Clo;
-  const int a = (int)((f.s9 >> cv) & 1u), b = (int)((f.s9 >> (cv + 1)) & 1u);
-  const int c = (int)((f.s9 >> (4 + cv)) & 1u), d = (int)((f.s9 >> (3 + cv)) & 1u);
-  if (a == b && b == c && c == d) return a;
-  const int64_t hk = (int64_t)g.h * f.k;
-  const double yb = (double)(2 * hk) * kSqrt3;
-  int fg = 1;
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int sl = 2 * cv + j;
-    if ((valid >> sl) & 1u) {
-      const int pm = slot_p(seg, sl), qm = slot_q(seg, sl);
-      const int px = mid_x(g, f, pm), py = mid_y(g, f, pm);
-      const int ex = mid_x(g, f, qm) - px, ey = mid_y(g, f, qm) - py;
-      const int Y0 = -4 * g.U;
-      const double v = ex * ((double)(Y0 - py) + yb) - (double)ey * (X - px);
-      if (sgn_filtered(v, g.band, (int64_t)ex * (Y0 - py) - (int64_t)ey * (X - px), (int64_t)ex * 2 * hk) < 0)
-        fg = 0;
-    }
-  }
-  return fg;
-}
-
-// Inside bit of the owner vertex v of a quiet owner (no slot's box meets the
-// reach box, which holds v).  Then v lies in none of the segment boxes of its
-// dual cell (0, cv), i.e. in the part of the cell holding the corners that the
-// marching-squares segments do not cut off: with one corner apart from the
-// other three, that corner is cut off (a segment box is the quarter cell at
-// the corner); at a saddle the background pair is cut off; with two adjacent
-// corners apart the segment runs straight through the middle of the cell and
-// v's side of it is one exact comparison (v never lies on a midline).
-SBMT_HD int quiet_inside(const Geo& g, const Frame& f) {
-  const int X = f.X;
-  const int cv = div4s(g, X - 2 * (g.s - 1) * g.U) - f.Clo;
-  const int a = (int)((f.s9 >> cv) & 1u), b = (int)((f.s9 >> (cv + 1)) & 1u);
-  const int c = (int)((f.s9 >> (4 + cv)) & 1u), d = (int)((f.s9 >> (3 + cv)) & 1u);
-  const int n = a + b + c + d;
-  if (n != 2) return n >= 2 ? 1 : 0;
-  if (a == c) return 1;  // saddle: foreground 8-connected
-  if (a == b) {
-    // top pair apart from the bottom pair: the segment joins the left and
-    // right midpoints at height ym; v above it (y_k < ym) sits with the top pair
-    const int ym = mid_y(g, f, 6 + cv);
-    return z3sign((int64_t)ym + 4 * g.U, -2 * (int64_t)g.h * f.k) > 0 ? a : d;
-  }
-  // left pair apart from the right pair: the segment joins the top and bottom
-  // midpoints at abscissa xm
-  return X < mid_x(g, f, cv) ? a : b;
-}
-
-// Counts of an owner whose window is not uniform but which no segment can
-// reach (no relevant slot): like the fast path with the exact inside bit.
-SBMT_HD uint32_t quiet_info(const Geo& g, const Frame& f, int fg) {
-  Frame q = f;
-  q.s9 = fg ? 0x1ffu : 0u;
-  return fast_info(g, q);
-}
-
-// Sign of a + b*sqrt3 evaluated either exactly (EXACT) or from the double
-// value v; in the latter case `ok` is cleared when |v| is inside the band
-// where the double could be wrong.
-template <bool EXACT>
-SBMT_HD int sgn_eval(double v, double band, int64_t a, int64_t b, bool& ok) {
-  if (EXACT) return z3sign(a, b);
-  ok = ok && (v > band || v < -band);
-  return v > 0 ? 1 : -1;
-}
-
-template <bool EXACT>
-SBMT_HD bool slot_signs(const Geo& g, const Frame& f, const SegSlots& seg, uint32_t rel, uint32_t row0, uint32_t row4,
-                        uint64_t& sp, uint64_t& sq, uint32_t& lv) {
-  bool ok = true;
-  const int h = g.h, X = f.X;
-  const double band = g.band;
-  const int64_t hk = (int64_t)h * f.k;
-  const double yk = (double)(2 * hk) * kSqrt3;
-  sp = 0;
-  sq = 0;
-  lv = 0;
-  const int LX0 = X, LX1 = X + 4 * h, LX2 = X - 2 * h, LX3 = X + 2 * h;
-  const int64_t LB01 = 2 * hk, LB23 = 2 * (hk + h);
-  const double yb01 = (double)LB01 * kSqrt3, yb23 = (double)LB23 * kSqrt3;
-  for (uint32_t w = rel; w; w &= w - 1) {
-    const int a = ctz32(w);
-    const int pm = slot_p(seg, a), qm = slot_q(seg, a);
-    uint32_t e5[2];
-#pragma unroll
-    for (int z = 0; z < 2; ++z) {
-      const int m = z == 0 ? pm : qm;
-      const int Ay = mid_y(g, f, m) + 4 * g.U, lx = mid_x(g, f, m) - X, yi = mid_yi(m);
-      const double ly = (double)Ay - yk;
-      uint32_t b5 = ((row0 >> yi) & 1u) | (((row4 >> yi) & 1u) << 4);
-      b5 |= (uint32_t)(sgn_eval<EXACT>(ly + kSqrt3 * lx, band, Ay, lx - 2 * hk, ok) < 0) << 1;
-      b5 |= (uint32_t)(sgn_eval<EXACT>(ly - kSqrt3 * lx, band, Ay, -(lx + 2 * hk), ok) > 0) << 2;
-      b5 |= (uint32_t)(sgn_eval<EXACT>(ly + kSqrt3 * (lx - 4 * h), band, Ay, lx - 4 * h - 2 * hk, ok) < 0) << 3;
-      e5[z] = b5;
-    }
-    sp |= (uint64_t)e5[0] << (8 * a);
-    sq |= (uint64_t)e5[1] << (8 * a);
-    // orient(P, Q, L) = ex (Ly - Py) - ey (Lx - Px), Ly = -4U + LB sqrt3
-    const int px = mid_x(g, f, pm), py = mid_y(g, f, pm);
-    const int ex = mid_x(g, f, qm) - px, ey = mid_y(g, f, qm) - py;
-    const int Yp = -4 * g.U - py;
-    const int64_t base = (int64_t)ex * Yp;
-    const double d01 = (double)Yp + yb01, d23 = (double)Yp + yb23;
-    uint32_t l4 = (uint32_t)(sgn_eval<EXACT>(ex * d01 - (double)ey * (LX0 - px), band,
-                                             base - (int64_t)ey * (LX0 - px), ex * LB01, ok) > 0);
-    l4 |= (uint32_t)(sgn_eval<EXACT>(ex * d01 - (double)ey * (LX1 - px), band, base - (int64_t)ey * (LX1 - px),
-                                     ex * LB01, ok) > 0) << 1;
-    l4 |= (uint32_t)(sgn_eval<EXACT>(ex * d23 - (double)ey * (LX2 - px), band, base - (int64_t)ey * (LX2 - px),
-                                     ex * LB23, ok) > 0) << 2;
-    l4 |= (uint32_t)(sgn_eval<EXACT>(ex * d23 - (double)ey * (LX3 - px), band, base - (int64_t)ey * (LX3 - px),
-                                     ex * LB23, ok) > 0) << 3;
-    lv |= l4 << (4 * a);
-  }
-  return ok;
-}
+SBMT_HD int nib_slot(uint32_t w) { return ctz32(w) >> 2; }
 
 // Signs of the five point rows of a block (bit yi: the midpoint row yi lies
 // below the line) against the horizontal edge lines of grid rows k (row0) and
@@ -604,8 +487,7 @@ SBMT_HD void row_signs(const Geo& g, int k, int Rlo, uint32_t& row0, uint32_t& r
   }
 }
 
-// What the classification needs of the owner's row, packed in 32 bits (the
-// count pass computes it once per row and hands it over in the record):
+// What the classification needs of the owner's row, packed in 32 bits:
 // y0, y1 of row_reach as signed bytes, row0 in bits 16..20, row4 in 21..25.
 SBMT_HD uint32_t pack_row(int y0, int y1, uint32_t row0, uint32_t row4) {
   return (uint32_t)(y0 & 255) | ((uint32_t)(y1 & 255) << 8) | (row0 << 16) | (row4 << 21);
@@ -618,6 +500,156 @@ SBMT_HD uint32_t row_info(const Geo& g, int k, int Rlo) {
   return pack_row(y0, y1, row0, row4);
 }
 
+// Everything the exact predicates need of grid row k, computed once per row:
+//   R   its cell row (the Rlo of its owners' blocks)
+//   FL  ceil(Y_k) - 1 for the row's ordinate Y_k = -4U + 2pk sqrt3 in units:
+//       an integer n lies above the row line (n < Y_k) iff n <= FL
+//   pk  row_info (reach in y, row0, row4)
+//   TA  floor(a / sqrt3) for the ordinates a = ys + 2sU yi + 4U of the block's
+//       midpoint rows yi = 0..4, measured from the line y = -4U through
+//       vertex (0, 0) (ys: the block's first sample row)
+struct RowT {
+  int32_t R, FL;
+  uint32_t pk;
+  int32_t TA[5];
+};
+
+SBMT_HD RowT row_table_entry(const Geo& g, int k) {
+  RowT t;
+  t.R = row_cell(g, k);
+  const int64_t pk = (int64_t)g.h * k;
+  t.FL = k == 0 ? -4 * g.U - 1 : -4 * g.U + (int)isqrt_u64((uint64_t)(12 * pk * pk));
+  t.pk = row_info(g, k, t.R);
+  const int64_t ys = (int64_t)g.U * (4 * g.s * t.R + 2 * (g.s - 1));
+  for (int yi = 0; yi < 5; ++yi) t.TA[yi] = floor_div_sqrt3(ys + 2LL * g.s * g.U * yi + 4 * g.U);
+  return t;
+}
+SBMT_HD int row_ta(const RowT& t, int yi) {
+  return yi == 0 ? t.TA[0] : (yi == 1 ? t.TA[1] : (yi == 2 ? t.TA[2] : (yi == 3 ? t.TA[3] : t.TA[4])));
+}
+
+// orient(P, Q, L) = ex (Ly - Py) - ey (Lx - Px) > 0 for a boundary segment
+// P -> Q of the block (direction (dxi, dyi) in midpoint steps: axis-parallel or
+// diagonal) and a lattice point L of a grid row, exactly.  The value is never
+// zero: Lx is odd and Px even, and Ly is irrational or not a boundary ordinate.
+//   vertical    -ey (Lx - Px)
+//   horizontal  sign(ex) sign(Ly - Py); Py lies below L's row line iff `below`
+//   diagonal    ey = sigma ex: sign(ex) sign(Ly - n), n = Py + sigma (Lx - Px),
+//               with n < Ly iff n <= FL of L's row
+SBMT_HD bool orient_pos(int dxi, int dyi, int px, int py, int Lx, bool below, int FL) {
+  const bool diag_up = (dxi > 0) == (dyi > 0);
+  const int n = py + (diag_up ? Lx - px : px - Lx);
+  const bool hz = dyi == 0, vt = dxi == 0;
+  const bool tdiag = (dxi > 0) == (n <= FL);
+  const bool thz = (dxi > 0) == !below;
+  const bool tvt = dyi > 0 ? Lx < px : Lx > px;
+  return vt ? tvt : (hz ? thz : tdiag);
+}
+
+// Inside bit of the owner vertex: its dual cell (0, cv) of the block is
+// uniform, or v lies left of every segment of that cell.
+template <class S>
+SBMT_HD int owner_inside(const Geo& g, const Frame& f, const S& seg, uint32_t valid, const RowT& rt) {
+  const int X = f.X;
+  const int cv = div4s(g, X - 2 * (g.s - 1) * g.U) - f.Clo;
+  const int a = (int)((f.s9 >> cv) & 1u), b = (int)((f.s9 >> (cv + 1)) & 1u);
+  const int c = (int)((f.s9 >> (4 + cv)) & 1u), d = (int)((f.s9 >> (3 + cv)) & 1u);
+  if (a == b && b == c && c == d) return a;
+  const uint32_t row0 = (rt.pk >> 16) & 31u;
+  int fg = 1;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int sl = 2 * cv + j;
+    if ((valid >> sl) & 1u) {
+      const int pm = slot_p(seg, sl), qm = slot_q(seg, sl);
+      const int pyi = mid_yi(pm);
+      if (!orient_pos(mid_xi(qm) - mid_xi(pm), mid_yi(qm) - pyi, mid_x(g, f, pm), mid_y(g, f, pm), X,
+                      (row0 >> pyi) & 1u, rt.FL))
+        fg = 0;
+    }
+  }
+  return fg;
+}
+
+// Inside bit of the owner vertex v of a quiet owner (no slot's box meets the
+// reach box, which holds v).  Then v lies in none of the segment boxes of its
+// dual cell (0, cv), i.e. in the part of the cell holding the corners that the
+// marching-squares segments do not cut off: with one corner apart from the
+// other three, that corner is cut off (a segment box is the quarter cell at
+// the corner); at a saddle the background pair is cut off; with two adjacent
+// corners apart the segment runs straight through the middle of the cell and
+// v's side of it is one exact comparison (v never lies on a midline).
+// rowp: the row's packed row_info (row0 bit 1: the block's middle point row
+// lies below the row line).
+SBMT_HD int quiet_inside(const Geo& g, const Frame& f, uint32_t rowp) {
+  const int X = f.X;
+  const int cv = div4s(g, X - 2 * (g.s - 1) * g.U) - f.Clo;
+  const int a = (int)((f.s9 >> cv) & 1u), b = (int)((f.s9 >> (cv + 1)) & 1u);
+  const int c = (int)((f.s9 >> (4 + cv)) & 1u), d = (int)((f.s9 >> (3 + cv)) & 1u);
+  const int n = a + b + c + d;
+  if (n != 2) return n >= 2 ? 1 : 0;
+  if (a == c) return 1;  // saddle: foreground 8-connected
+  // top pair apart from the bottom pair: the segment joins the left and right
+  // midpoints (midpoint row 1); v above it sits with the top pair.  Left pair
+  // apart from the right pair: the segment joins the top and bottom midpoints
+  // at abscissa xm.
+  if (a == b) return ((rowp >> 17) & 1u) ? a : d;
+  return X < mid_x(g, f, cv) ? a : b;
+}
+
+// Counts of an owner whose window is not uniform but which no segment can
+// reach (no relevant slot): like the fast path with the exact inside bit.
+SBMT_HD uint32_t quiet_info(const Geo& g, const Frame& f, int fg) {
+  Frame q = f;
+  q.s9 = fg ? 0x1ffu : 0u;
+  return fast_info(g, q);
+}
+
+// Per relevant slot (nibble mask rel), the signs of both ends against the
+// lines of the owned edges E0..E4 (5 bits each at [8a, 8a+5) of sp / sq: E0 and
+// E4 from the row's signs; E1, E2, E3 as comparisons with the row's floors of
+// a / sqrt3) and of the lattice vertices v, vr, vdl, vdr against the segment
+// line (4 bits at [4a, 4a+4) of lv), all exact integer comparisons.  For an
+// end point P = (px, py) with a = py + 4U > 0 (every boundary point lies below
+// the line y = -4U) and d = px - X, each diagonal sign is that of
+// a + sqrt3 (+-d - 2pk - ...), i.e. of an integer against -floor(a / sqrt3).
+SBMT_HD void slot_signs(const Geo& g, const Frame& f, const SegSlots& seg, uint32_t rel, const RowT& rt, int FL1,
+                        uint64_t& sp, uint64_t& sq, uint32_t& lv) {
+  const int st = 2 * g.s * g.U;
+  const int xs = g.U * (4 * g.s * f.Clo + 2 * (g.s - 1)), ys = g.U * (4 * g.s * f.Rlo + 2 * (g.s - 1));
+  const int X = f.X, h = g.h, hk2 = 2 * h * f.k;
+  const uint32_t row0 = (rt.pk >> 16) & 31u, row4 = (rt.pk >> 21) & 31u;
+  sp = 0;
+  sq = 0;
+  lv = 0;
+  for (uint32_t w = rel; w; w &= w - 1) {
+    const int a = nib_slot(w);
+    const int pm = slot_p(seg, a), qm = slot_q(seg, a);
+    const int pxi = mid_xi(pm), pyi = mid_yi(pm), qxi = mid_xi(qm), qyi = mid_yi(qm);
+    uint32_t e5[2];
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+      const int xi = z == 0 ? pxi : qxi, yi = z == 0 ? pyi : qyi;
+      const int d = xs + st * xi - X, T = row_ta(rt, yi);
+      uint32_t b5 = ((row0 >> yi) & 1u) | (((row4 >> yi) & 1u) << 4);
+      b5 |= (uint32_t)(d - hk2 + T < 0) << 1;           // E1 line through v, vdl
+      b5 |= (uint32_t)(T - d - hk2 >= 0) << 2;          // E2 line through v, vdr
+      b5 |= (uint32_t)(d - 4 * h - hk2 + T < 0) << 3;   // E3 line through vr, vdr
+      e5[z] = b5;
+    }
+    sp |= (uint64_t)e5[0] << (8 * a);
+    sq |= (uint64_t)e5[1] << (8 * a);
+    const int px = xs + st * pxi, py = ys + st * pyi;
+    const int dxi = qxi - pxi, dyi = qyi - pyi;
+    const bool b0 = (row0 >> pyi) & 1u, b4 = (row4 >> pyi) & 1u;
+    uint32_t l4 = (uint32_t)orient_pos(dxi, dyi, px, py, X, b0, rt.FL);
+    l4 |= (uint32_t)orient_pos(dxi, dyi, px, py, X + 4 * h, b0, rt.FL) << 1;
+    l4 |= (uint32_t)orient_pos(dxi, dyi, px, py, X - 2 * h, b4, FL1) << 2;
+    l4 |= (uint32_t)orient_pos(dxi, dyi, px, py, X + 2 * h, b4, FL1) << 3;
+    lv |= l4 << (4 * a);
+  }
+}
+
 // Per relevant slot a, the 5-bit set of owned edges E0..E4 that its segment
 // crosses: the ends lie on different sides of the edge line (d) and the edge
 // ends on different sides of the segment line (l4: v, vr, vdl, vdr).
@@ -626,31 +658,26 @@ SBMT_HD uint32_t edge_split(uint32_t l4) {
   return (v ^ vr) | ((v ^ vdl) << 1) | ((v ^ vdr) << 2) | ((vr ^ vdr) << 3) | ((vdl ^ vdr) << 4);
 }
 
-SBMT_HD void slow_classify(const Geo& g, const Frame& f, uint32_t rowp, Slow& r) {
+// Full classification of an owner from its row's table entry rt and the FL of
+// the row below (FL1).
+SBMT_HD void slow_classify(const Geo& g, const Frame& f, const RowT& rt, int FL1, Slow& r) {
   const bool both = (g.flags & 1u) != 0;
-  const int h = g.h, X = f.X;
-  const int64_t hk = (int64_t)h * f.k;
   const uint4 A = block_tab(2 * (int)f.s9), B = block_tab(2 * (int)f.s9 + 1);
   SegSlots seg;
   seg.p = A.x;
   seg.q = A.y;
   const uint32_t valid = A.z;
-  const int y0 = (int)(int8_t)(rowp & 255u), y1 = (int)(int8_t)((rowp >> 8) & 255u);
-  const uint32_t rel = relevant_slots(B, valid, owner_reach(g, f, y0, y1));
-  // per relevant slot, the signs of both ends against E0..E4 (5 bits each;
-  // E0 and E4 from the row's signs) and of the lattice vertices v, vr, vdl,
-  // vdr against the segment line (4 bits).  In double precision first; if any
-  // value falls in the uncertainty band the same quantities are recomputed
-  // exactly.
-  const uint32_t row0 = (rowp >> 16) & 31u, row4 = (rowp >> 21) & 31u;
+  int x0, x1;
+  owner_xreach(g, f.X, f.Clo, x0, x1);
+  const int y0 = (int)(int8_t)(rt.pk & 255u), y1 = (int)(int8_t)((rt.pk >> 8) & 255u);
+  const uint32_t rel = relevant_nib(B, x0, x1, y0, y1);
   uint64_t sp, sq;
   uint32_t lv;
-  if (!slot_signs<false>(g, f, seg, rel, row0, row4, sp, sq, lv))
-    slot_signs<true>(g, f, seg, rel, row0, row4, sp, sq, lv);
+  slot_signs(g, f, seg, rel, rt, FL1, sp, sq, lv);
   // crossing sets
   uint64_t xm = 0;
   for (uint32_t w = rel; w; w &= w - 1) {
-    const int a = ctz32(w);
+    const int a = nib_slot(w);
     const uint32_t x5 = ((uint32_t)(sp >> (8 * a)) ^ (uint32_t)(sq >> (8 * a))) & edge_split((lv >> (4 * a)) & 15u);
     xm |= ((uint64_t)(x5 & 1u) | ((uint64_t)((x5 >> 1) & 1u) << 8) | ((uint64_t)((x5 >> 2) & 1u) << 16) |
            ((uint64_t)((x5 >> 3) & 1u) << 24) | ((uint64_t)((x5 >> 4) & 1u) << 32))
@@ -690,16 +717,14 @@ SBMT_HD void slow_classify(const Geo& g, const Frame& f, uint32_t rowp, Slow& r)
   // chain vertices: the end point of a relevant segment inside Tb or Ta
   int Ib = 15, Ia = 15;
   for (uint32_t w = rel; w; w &= w - 1) {
-    const int a = ctz32(w);
-    {
-      const uint32_t e5 = (uint32_t)(sq >> (8 * a)) & 31u;
-      const bool inb = ((e5 >> 2) & 1u) && !((e5 >> 4) & 1u) && !((e5 >> 1) & 1u);
-      const bool ina = (e5 & 1u) && ((e5 >> 3) & 1u) && !((e5 >> 2) & 1u);
-      if (inb) { if (Ib != 15) err = true; Ib = slot_q(seg, a); }
-      if (ina) { if (Ia != 15) err = true; Ia = slot_q(seg, a); }
-    }
+    const int a = nib_slot(w);
+    const uint32_t e5 = (uint32_t)(sq >> (8 * a)) & 31u;
+    const bool inb = ((e5 >> 2) & 1u) && !((e5 >> 4) & 1u) && !((e5 >> 1) & 1u);
+    const bool ina = (e5 & 1u) && ((e5 >> 3) & 1u) && !((e5 >> 2) & 1u);
+    if (inb) { if (Ib != 15) err = true; Ib = slot_q(seg, a); }
+    if (ina) { if (Ia != 15) err = true; Ia = slot_q(seg, a); }
   }
-  const int fg = owner_inside(g, f, seg, valid);
+  const int fg = owner_inside(g, f, seg, valid, rt);
   const int kb = tri_key(0, sp, seg, xm, ord, Ib);
   const int ka = tri_key(1, sp, seg, xm, ord, Ia);
   if (kb < 0 || ka < 0) err = true;
@@ -724,17 +749,20 @@ SBMT_HD void slow_classify(const Geo& g, const Frame& f, uint32_t rowp, Slow& r)
   r.tri = (uint32_t)(clsb | (rotb << 5) | ((clsa | (rota << 5)) << 8) | (Ib << 16) | (Ia << 20));
 }
 
+// The same with the row data computed here (paths that classify few owners).
 SBMT_HD void slow_classify(const Geo& g, const Frame& f, Slow& r) {
-  slow_classify(g, f, row_info(g, f.k, f.Rlo), r);
+  const RowT rt = row_table_entry(g, f.k), rn = row_table_entry(g, f.k + 1);
+  slow_classify(g, f, rt, rn.FL, r);
 }
 
 // Classify an owner whose window is not uniform: quiet (no segment can reach
 // it: the fast counts with the exact inside bit) or slow.  Returns true if
-// the full slow classification is needed.  y0, y1: the row's reach (row_reach).
-SBMT_HD bool needs_slow(const Geo& g, const Frame& f, int y0, int y1, uint32_t& info) {
-  const uint4 A = block_tab(2 * (int)f.s9);
-  if (relevant_slots(block_tab(2 * (int)f.s9 + 1), A.z, owner_reach(g, f, y0, y1))) return true;
-  info = quiet_info(g, f, quiet_inside(g, f));
+// the full slow classification is needed.  x0, x1: the owner's reach in x
+// (owner_xreach); rowp: its row's packed row_info.
+SBMT_HD bool needs_slow(const Geo& g, const Frame& f, int x0, int x1, uint32_t rowp, uint32_t& info) {
+  const int y0 = (int)(int8_t)(rowp & 255u), y1 = (int)(int8_t)((rowp >> 8) & 255u);
+  if (relevant_nib(block_tab(2 * (int)f.s9 + 1), x0, x1, y0, y1)) return true;
+  info = quiet_info(g, f, quiet_inside(g, f, rowp));
   return false;
 }
 

@@ -439,7 +439,8 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
   if (interior) {
     const uint32_t code_fg = map_code(fast_info_k(g, k0, c0 + 1, 1)), code_bg = map_code(fast_info_k(g, k0, c0 + 1, 0));
     for (int r = 0; r < RB; ++r) {
-      const int wc = wcol[(k0 + r) & 1], w = wc >> 5, sh = wc & 31;
+      const int odd = (k0 + r) & 1;
+      const int wc = wcol[odd], w = wc >> 5, sh = wc & 31;
       const int kind = (int)((L.u0[r][w] >> sh) & 1u) | ((int)((L.u1[r][w] >> sh) & 1u) << 1);
       if (kind) L.code[r][threadIdx.x] = (uint16_t)(kind == 2 ? code_fg : code_bg);
       else L.q1[atomicAdd(&L.n1, 1)] = (uint16_t)(r * kCB + threadIdx.x);
@@ -839,6 +840,7 @@ struct EmitLds {
   int16_t toff[RB][W];       // first triangle of each owner, from tb of its row
   uint32_t hasrec[RB * kCB / 32];
   int rowR[RB + 1];
+  double rowy[RB + 1];  // lat_y of each row
   int bv[RB + 1];
   long long tb[RB];
   int rowv[RB + 1];  // vertices of each row's kCB owners
@@ -933,7 +935,7 @@ __device__ __forceinline__ void emit_records(const Img& d, const Geo& g, int k0,
       const SlowRec R = L.x.r.srec[item & 255];
       const int r = (int)(R.x >> 56), col = (int)((R.x >> 48) & 255u) + 1;
       const Frame f = owner_place(g, k0 + r, c0 + col - 1, L.rowR[r]);
-      emit_slow_vertex(g, f, R, item >> 8, L.bv[r] + L.voff[r][col], out);
+      emit_slow_vertex(g, f, R, item >> 8, L.bv[r] + L.voff[r][col], L.rowy[r], L.rowy[r + 1], out);
     }
     __syncthreads();
     for (int i = 0; i < (cnt >> 16); ++i) L.x.r.sitem[(excl >> 16) + i] = (uint16_t)(qi | (i << 8));
@@ -969,7 +971,10 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
   constexpr int kLut = 15 * 3 * 2 * 5;
   static_assert(kLut <= 2 * kThreads, "two table entries per thread");
   const int c0 = cb * kCB;
-  if (threadIdx.x <= RB) L.rowR[threadIdx.x] = d.rows[k0 + threadIdx.x].R;  // read after step 2
+  if (threadIdx.x <= RB) {  // read after step 2
+    L.rowR[threadIdx.x] = d.rows[k0 + threadIdx.x].R;
+    L.rowy[threadIdx.x] = lat_y(g, k0 + threadIdx.x);
+  }
   Bits bw;
   bw.p = d.bits;
   bw.wpr = g.wpr;
@@ -1080,7 +1085,7 @@ __device__ __forceinline__ void emit_tile(const Img& d, const Geo& g, int k0, in
     if (fast && info_self(f)) {
       double2 v;
       v.x = lat_x(g, g.X0 + 4 * g.h * c + 2 * g.h * o_);
-      v.y = lat_y(g, k);
+      v.y = L.rowy[r];
       *reinterpret_cast<double2*>(vrow + (uint32_t)L.voff[r][col] * 16u) = v;
     }
     // ranks of the wave's fast triangles (at most two per owner)
@@ -1257,6 +1262,7 @@ __global__ void __launch_bounds__(kThreads, 8) k_emit(Src src, const int64_t* __
     L.bv[threadIdx.x] = (int)(o.x - base.x);
     if (threadIdx.x < RB) L.tb[threadIdx.x] = o.y - base.y;
     L.rowR[threadIdx.x] = d.rows[k].R;
+    L.rowy[threadIdx.x] = lat_y(g, k);
   }
   L.lut[threadIdx.x] = lut0;
   if (threadIdx.x + kThreads < kLut) L.lut[threadIdx.x + kThreads] = lut1;
@@ -1273,10 +1279,20 @@ __global__ void __launch_bounds__(kThreads, 8) k_emit(Src src, const int64_t* __
   // the strip's totals to LDS; vertex and triangle counts of a row segment stay
   // below 2^16
   int incl[RB + 1];
+  const bool both = (g.flags & 1u) != 0;
 #pragma unroll
   for (int r = 0; r <= RB; ++r) {
     const int p = packed_counts(code[r]);
-    incl[r] = wave_incl_scan_dpp(p);
+    if (!both && __ballot((code[r] & 0x8000u) != 0u) == 0ull) {
+      // no slow owner in the strip's row: a fast owner emits its vertex and
+      // both triangles iff it is inside, so the prefix is a count of inside bits
+      const unsigned long long m = __ballot((code[r] & 1u) != 0u);
+      const int nb = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) +
+                     (int)(code[r] & 1u);
+      incl[r] = nb | (nb << 17);
+    } else {
+      incl[r] = wave_incl_scan_dpp(p);
+    }
     if (lane == 63) {
       S.wtot[r][wv] = incl[r];
       S.lastnv[r][wv + 1] = p & 0xffff;
@@ -1300,19 +1316,26 @@ __global__ void __launch_bounds__(kThreads, 8) k_emit(Src src, const int64_t* __
   }
   // 3. fast owners row by row: the vertex of the owner, then its triangles
   // (Tb, then Ta), written at their offsets; offsets go to LDS for step 4
-  const bool both = (g.flags & 1u) != 0;
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
     const int k = k0 + r;
     if (k >= g.NK) break;  // uniform
     const int o = k & 1;
     const uint32_t cv = code[r];
-    const int p = packed_counts(cv), pn = packed_counts(code[r + 1]);
-    const int ex = sb[r] + incl[r] - p;  // within the row segment: vertices | triangles << 16
+    const int pn = packed_counts(code[r + 1]);
     const int exn = sb[r + 1] + incl[r + 1] - pn, inn = sb[r + 1] + incl[r + 1];
+    if (r == RB - 1) L.voff[RB][col] = (int16_t)(exn & 0xffff);
+    if (__ballot(cv != 0u) == 0ull) {
+      // nothing in the strip's row (no vertex, no triangle, no slow owner):
+      // every owner's offsets are the strip's first ones
+      L.voff[r][col] = (int16_t)(sb[r] & 0xffff);
+      L.toff[r][col] = (int16_t)(sb[r] >> 16);
+      continue;
+    }
+    const int p = packed_counts(cv);
+    const int ex = sb[r] + incl[r] - p;  // within the row segment: vertices | triangles << 16
     L.voff[r][col] = (int16_t)(ex & 0xffff);
     L.toff[r][col] = (int16_t)(ex >> 16);
-    if (r == RB - 1) L.voff[RB][col] = (int16_t)(exn & 0xffff);
     // vertex count of the owner left of this one in the row below (one lane to
     // the left; lane 0 from the strip to the left)
     int nvl = __builtin_amdgcn_update_dpp(0, pn & 0xffff, 0x138, 0xf, 0xf, false);  // wave_shr:1
@@ -1329,7 +1352,7 @@ __global__ void __launch_bounds__(kThreads, 8) k_emit(Src src, const int64_t* __
     if (fast && (cv & 1u)) {
       double2 v;
       v.x = lat_x(g, g.X0 + 4 * g.h * c + 2 * g.h * o);
-      v.y = lat_y(g, k);
+      v.y = L.rowy[r];
       *reinterpret_cast<double2*>(vrow + (uint32_t)(ex & 0xffff) * 16u) = v;
     }
     const int ntb = fast ? (int)((cv >> 9) & 7u) : 0, nta = fast ? (int)((cv >> 12) & 7u) : 0;
@@ -1373,12 +1396,35 @@ __global__ void __launch_bounds__(kThreads, 8) k_emit(Src src, const int64_t* __
         t3.b = (int)sb2[lane];
         t3.c = (int)sc[lane];
         *reinterpret_cast<Tri3*>(trow + u * 12u) = t3;
-        crow[u] = (uint8_t)(ew >> 8);
+        if (both) crow[u] = (uint8_t)(ew >> 8);  // foreground mode: the codes are filled below
         sw[lane] = 0u;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  // foreground mode: every fast triangle has code 0 (an uncut foreground
+  // triangle), so each row segment's codes are first set to 0 with 16-byte
+  // stores (bytes at the unaligned ends); the slow owners' sub-triangles get
+  // their codes in step 4, after the barrier
+  if (!both) {
+    for (int r = wv; r < RB; r += kWaves) {
+      if (k0 + r >= g.NK) break;  // uniform
+      int n = 0;  // triangles of the row segment (the strip totals were written before step 2's barrier)
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) n += S.wtot[r][w] >> 16;
+      uint8_t* const p0 = d.codes + L.tb[r];
+      uint8_t* const p1 = p0 + n;
+      uint8_t* const a0 = reinterpret_cast<uint8_t*>(((uintptr_t)p0 + 15) & ~(uintptr_t)15);
+      uint8_t* const a1 = reinterpret_cast<uint8_t*>((uintptr_t)p1 & ~(uintptr_t)15);
+      if (a0 >= a1) {
+        if (lane < n) p0[lane] = 0;  // fewer than 32 bytes
+      } else {
+        if (lane < a0 - p0) p0[lane] = 0;
+        if (lane >= 16 && lane - 16 < p1 - a1) a1[lane - 16] = 0;
+        for (uint8_t* q = a0 + 16 * lane; q < a1; q += 1024) *reinterpret_cast<uint4*>(q) = make_uint4(0u, 0u, 0u, 0u);
+      }
     }
   }
   __syncthreads();

@@ -82,8 +82,8 @@ SBMT_HD int div4s(const Geo& g, int n) {
   const int d = 4 * g.s;
   const int m = n >> g.q;
   int q = (int)__builtin_floorf((float)m * g.inv4s);
-  if (q * d > m) --q;
-  else if ((q + 1) * d <= m) ++q;
+  q -= q * d > m ? 1 : 0;  // selects, not branches
+  q += (q + 1) * d <= m ? 1 : 0;
   return q;
 }
 
@@ -427,8 +427,8 @@ SBMT_HD void block_table_entry(uint32_t s9, uint4& A, uint4& B) {
 SBMT_HD int div2s(const Geo& g, int m) {
   const int d = 2 * g.s;
   int q = (int)__builtin_floorf((float)m * (2.0f * g.inv4s));
-  if (q * d > m) --q;
-  else if ((q + 1) * d <= m) ++q;
+  q -= q * d > m ? 1 : 0;  // selects, not branches
+  q += (q + 1) * d <= m ? 1 : 0;
   return q;
 }
 // floor(n / (2 s U)) = floor((n >> q) / (2 s)); ceil by symmetry.
@@ -605,49 +605,49 @@ SBMT_HD uint32_t quiet_info(const Geo& g, const Frame& f, int fg) {
   return fast_info(g, q);
 }
 
-// Per relevant slot (nibble mask rel), the signs of both ends against the
-// lines of the owned edges E0..E4 (5 bits each at [8a, 8a+5) of sp / sq: E0 and
+// Signs of one segment slot of the block, exactly, as integer comparisons:
+// e5p / e5q, both ends P, Q against the lines of the owned edges E0..E4 (E0 and
 // E4 from the row's signs; E1, E2, E3 as comparisons with the row's floors of
-// a / sqrt3) and of the lattice vertices v, vr, vdl, vdr against the segment
-// line (4 bits at [4a, 4a+4) of lv), all exact integer comparisons.  For an
-// end point P = (px, py) with a = py + 4U > 0 (every boundary point lies below
-// the line y = -4U) and d = px - X, each diagonal sign is that of
+// a / sqrt3), and l4, the lattice vertices v, vr, vdl, vdr against the segment
+// line.  For an end point (px, py) with a = py + 4U > 0 (every boundary point
+// lies below the line y = -4U) and d = px - X, each diagonal sign is that of
 // a + sqrt3 (+-d - 2pk - ...), i.e. of an integer against -floor(a / sqrt3).
-SBMT_HD void slot_signs(const Geo& g, const Frame& f, const SegSlots& seg, uint32_t rel, const RowT& rt, int FL1,
-                        uint64_t& sp, uint64_t& sq, uint32_t& lv) {
-  const int st = 2 * g.s * g.U;
-  const int xs = g.U * (4 * g.s * f.Clo + 2 * (g.s - 1)), ys = g.U * (4 * g.s * f.Rlo + 2 * (g.s - 1));
-  const int X = f.X, h = g.h, hk2 = 2 * h * f.k;
-  const uint32_t row0 = (rt.pk >> 16) & 31u, row4 = (rt.pk >> 21) & 31u;
-  sp = 0;
-  sq = 0;
-  lv = 0;
-  for (uint32_t w = rel; w; w &= w - 1) {
-    const int a = nib_slot(w);
-    const int pm = slot_p(seg, a), qm = slot_q(seg, a);
-    const int pxi = mid_xi(pm), pyi = mid_yi(pm), qxi = mid_xi(qm), qyi = mid_yi(qm);
-    uint32_t e5[2];
+struct SlotGeo {
+  int st, xs, ys, X, h, hk2;
+  uint32_t row0, row4;
+};
+SBMT_HD SlotGeo slot_geo(const Geo& g, const Frame& f, const RowT& rt) {
+  SlotGeo q;
+  q.st = 2 * g.s * g.U;
+  q.xs = g.U * (4 * g.s * f.Clo + 2 * (g.s - 1));
+  q.ys = g.U * (4 * g.s * f.Rlo + 2 * (g.s - 1));
+  q.X = f.X;
+  q.h = g.h;
+  q.hk2 = 2 * g.h * f.k;
+  q.row0 = (rt.pk >> 16) & 31u;
+  q.row4 = (rt.pk >> 21) & 31u;
+  return q;
+}
+SBMT_HD void slot_signs(const SlotGeo& q, const RowT& rt, int FL1, int pm, int qm, uint32_t& e5p, uint32_t& e5q,
+                        uint32_t& l4) {
+  const int pxi = mid_xi(pm), pyi = mid_yi(pm), qxi = mid_xi(qm), qyi = mid_yi(qm);
 #pragma unroll
-    for (int z = 0; z < 2; ++z) {
-      const int xi = z == 0 ? pxi : qxi, yi = z == 0 ? pyi : qyi;
-      const int d = xs + st * xi - X, T = row_ta(rt, yi);
-      uint32_t b5 = ((row0 >> yi) & 1u) | (((row4 >> yi) & 1u) << 4);
-      b5 |= (uint32_t)(d - hk2 + T < 0) << 1;           // E1 line through v, vdl
-      b5 |= (uint32_t)(T - d - hk2 >= 0) << 2;          // E2 line through v, vdr
-      b5 |= (uint32_t)(d - 4 * h - hk2 + T < 0) << 3;   // E3 line through vr, vdr
-      e5[z] = b5;
-    }
-    sp |= (uint64_t)e5[0] << (8 * a);
-    sq |= (uint64_t)e5[1] << (8 * a);
-    const int px = xs + st * pxi, py = ys + st * pyi;
-    const int dxi = qxi - pxi, dyi = qyi - pyi;
-    const bool b0 = (row0 >> pyi) & 1u, b4 = (row4 >> pyi) & 1u;
-    uint32_t l4 = (uint32_t)orient_pos(dxi, dyi, px, py, X, b0, rt.FL);
-    l4 |= (uint32_t)orient_pos(dxi, dyi, px, py, X + 4 * h, b0, rt.FL) << 1;
-    l4 |= (uint32_t)orient_pos(dxi, dyi, px, py, X - 2 * h, b4, FL1) << 2;
-    l4 |= (uint32_t)orient_pos(dxi, dyi, px, py, X + 2 * h, b4, FL1) << 3;
-    lv |= l4 << (4 * a);
+  for (int z = 0; z < 2; ++z) {
+    const int xi = z == 0 ? pxi : qxi, yi = z == 0 ? pyi : qyi;
+    const int d = q.xs + q.st * xi - q.X, T = row_ta(rt, yi);
+    uint32_t b5 = ((q.row0 >> yi) & 1u) | (((q.row4 >> yi) & 1u) << 4);
+    b5 |= (uint32_t)(d - q.hk2 + T < 0) << 1;            // E1 line through v, vdl
+    b5 |= (uint32_t)(T - d - q.hk2 >= 0) << 2;           // E2 line through v, vdr
+    b5 |= (uint32_t)(d - 4 * q.h - q.hk2 + T < 0) << 3;  // E3 line through vr, vdr
+    (z == 0 ? e5p : e5q) = b5;
   }
+  const int px = q.xs + q.st * pxi, py = q.ys + q.st * pyi;
+  const int dxi = qxi - pxi, dyi = qyi - pyi;
+  const bool b0 = (q.row0 >> pyi) & 1u, b4 = (q.row4 >> pyi) & 1u;
+  l4 = (uint32_t)orient_pos(dxi, dyi, px, py, q.X, b0, rt.FL);
+  l4 |= (uint32_t)orient_pos(dxi, dyi, px, py, q.X + 4 * q.h, b0, rt.FL) << 1;
+  l4 |= (uint32_t)orient_pos(dxi, dyi, px, py, q.X - 2 * q.h, b4, FL1) << 2;
+  l4 |= (uint32_t)orient_pos(dxi, dyi, px, py, q.X + 2 * q.h, b4, FL1) << 3;
 }
 
 // Per relevant slot a, the 5-bit set of owned edges E0..E4 that its segment
@@ -671,22 +671,34 @@ SBMT_HD void slow_classify(const Geo& g, const Frame& f, const RowT& rt, int FL1
   owner_xreach(g, f.X, f.Clo, x0, x1);
   const int y0 = (int)(int8_t)(rt.pk & 255u), y1 = (int)(int8_t)((rt.pk >> 8) & 255u);
   const uint32_t rel = relevant_nib(B, x0, x1, y0, y1);
-  uint64_t sp, sq;
-  uint32_t lv;
-  slot_signs(g, f, seg, rel, rt, FL1, sp, sq, lv);
-  // crossing sets
-  uint64_t xm = 0;
+  // per relevant slot: the signs of both ends (5 bits each at [8a, 8a+5) of
+  // sp / sq), the owned edges its segment crosses (the ends lie on different
+  // sides of the edge line and the edge ends on different sides of the
+  // segment line; bit a of byte e of xm), and whether its end point is a chain
+  // vertex inside Tb or Ta
+  const SlotGeo q = slot_geo(g, f, rt);
+  uint64_t sp = 0, sq = 0, xm = 0;
+  bool err = false;
+  int Ib = 15, Ia = 15;
   for (uint32_t w = rel; w; w &= w - 1) {
     const int a = nib_slot(w);
-    const uint32_t x5 = ((uint32_t)(sp >> (8 * a)) ^ (uint32_t)(sq >> (8 * a))) & edge_split((lv >> (4 * a)) & 15u);
+    const int pm = slot_p(seg, a), qm = slot_q(seg, a);
+    uint32_t e5p, e5q, l4;
+    slot_signs(q, rt, FL1, pm, qm, e5p, e5q, l4);
+    sp |= (uint64_t)e5p << (8 * a);
+    sq |= (uint64_t)e5q << (8 * a);
+    const uint32_t x5 = (e5p ^ e5q) & edge_split(l4);
     xm |= ((uint64_t)(x5 & 1u) | ((uint64_t)((x5 >> 1) & 1u) << 8) | ((uint64_t)((x5 >> 2) & 1u) << 16) |
            ((uint64_t)((x5 >> 3) & 1u) << 24) | ((uint64_t)((x5 >> 4) & 1u) << 32))
           << a;
+    const bool inb = ((e5q >> 2) & 1u) && !((e5q >> 4) & 1u) && !((e5q >> 1) & 1u);
+    const bool ina = (e5q & 1u) && ((e5q >> 3) & 1u) && !((e5q >> 2) & 1u);
+    if (inb) { if (Ib != 15) err = true; Ib = qm; }
+    if (ina) { if (Ia != 15) err = true; Ia = qm; }
   }
   // order along each edge; two crossings come from consecutive segments S1 -> S2
   // sharing a vertex M, and S2's lies further along U->V iff
   // sign((P0 - M) x (P2 - M)) * sign(orient(U, V, M)) > 0
-  bool err = false;
   uint64_t ord = 0;
 #pragma unroll
   for (int e = 0; e < 5; ++e) {
@@ -713,16 +725,6 @@ SBMT_HD void slow_classify(const Geo& g, const Frame& f, const RowT& rt, int FL1
       }
       ord |= (uint64_t)(first | (second << 4)) << (8 * e);
     }
-  }
-  // chain vertices: the end point of a relevant segment inside Tb or Ta
-  int Ib = 15, Ia = 15;
-  for (uint32_t w = rel; w; w &= w - 1) {
-    const int a = nib_slot(w);
-    const uint32_t e5 = (uint32_t)(sq >> (8 * a)) & 31u;
-    const bool inb = ((e5 >> 2) & 1u) && !((e5 >> 4) & 1u) && !((e5 >> 1) & 1u);
-    const bool ina = (e5 & 1u) && ((e5 >> 3) & 1u) && !((e5 >> 2) & 1u);
-    if (inb) { if (Ib != 15) err = true; Ib = slot_q(seg, a); }
-    if (ina) { if (Ia != 15) err = true; Ia = slot_q(seg, a); }
   }
   const int fg = owner_inside(g, f, seg, valid, rt);
   const int kb = tri_key(0, sp, seg, xm, ord, Ib);
@@ -870,19 +872,20 @@ SBMT_HD int slot_id(const int (&ids)[16], int sl) {
 // itself if emitted, the crossings on E0, E1, E2 in order from the owner, the
 // chain vertex of Tb, then of Ta), written to id vid + sub.  Crossing
 // X = P + t (Q - P), t = dP / (dP - dQ), dP = (V-U) x (P-U), dQ = (V-U) x (Q-U).
-SBMT_HD void emit_slow_vertex(const Geo& g, const Frame& f, const SlowRec& r, int sub, int64_t vid,
-                              const Out& out) {
+// uy, uy1: lat_y of the owner's row and of the row below.
+SBMT_HD void emit_slow_vertex(const Geo& g, const Frame& f, const SlowRec& r, int sub, int64_t vid, double uy,
+                              double uy1, const Out& out) {
   const uint32_t info = r.info;
   const int self = info_self(info);
   const int n0 = info_n(info, 0), n1 = info_n(info, 1), n2 = info_n(info, 2);
-  const double ux = lat_x(g, f.X), uy = lat_y(g, f.k);
+  const double ux = lat_x(g, f.X);
   double x = ux, y = uy;
   const int s = sub - self;
   if (s >= 0 && s < n0 + n1 + n2) {
     const int e = s < n0 ? 0 : (s < n0 + n1 ? 1 : 2);
     const int re = s - (e == 0 ? 0 : (e == 1 ? n0 : n0 + n1));
     const int vX = e == 0 ? f.X + 4 * g.h : (e == 1 ? f.X - 2 * g.h : f.X + 2 * g.h);
-    const double vx = lat_x(g, vX), vy = lat_y(g, e == 0 ? f.k : f.k + 1);
+    const double vx = lat_x(g, vX), vy = e == 0 ? uy : uy1;
     const double gx = vx - ux, gy = vy - uy;
     const uint32_t pq = (uint32_t)(r.x >> (16 * e + 8 * re)) & 255u;
     const int pm = (int)(pq & 15u), qm = (int)(pq >> 4);
@@ -938,7 +941,8 @@ SBMT_HD void emit_slow_triangle(const Geo& g, const SlowRec& r, int sub, const N
 SBMT_HD void emit_slow(const Geo& g, const Frame& f, const SlowRec& r, const Nb& nb, int64_t to, const Out& out,
                        const uint16_t* lut) {
   const int nv = info_nv(r.info), nt = info_nt(r.info);
-  for (int s = 0; s < nv; ++s) emit_slow_vertex(g, f, r, s, nb.vid, out);
+  const double uy = lat_y(g, f.k), uy1 = lat_y(g, f.k + 1);
+  for (int s = 0; s < nv; ++s) emit_slow_vertex(g, f, r, s, nb.vid, uy, uy1, out);
   for (int s = 0; s < nt; ++s) emit_slow_triangle(g, r, s, nb, to, out, lut);
 }
 

@@ -84,6 +84,7 @@ struct Img {
   uint32_t* bits;     // coarse raster, (CH + 2 kRing) rows of wpr words
   uint16_t* omap;     // [NK][NI] owner map of the multi-kernel path, see map_code
   RowT* rows;         // [NK + kRowPad] per grid row data of the exact predicates (row_table_entry)
+  uint32_t* cols;     // [NI][2] per grid column and row parity: window column Clo + 8 | x0 << 24 | x1 << 28
   int64_t seg0;       // first row segment of the image in the call's segment arrays
   int64_t band0;      // first band of the image (fused path, 4-row numbering)
   int64_t halo0;      // first word of the image's halo rows (fused path)
@@ -196,6 +197,46 @@ constexpr int kCoarsenRows = 8;
 constexpr int kCoarsenMaxS = 9;
 constexpr int kCoarsenWords = (256 * kCoarsenMaxS + 15 + kCoarsenMaxS + 31) / 32 + 2;  // mask words per pixel row
 
+// Stride 2 with 16-byte aligned rows: four lanes make one raster word, each
+// from one aligned 16-byte load of the two pixel rows of its 8 samples; a
+// 2 x 2 block is foreground iff at least two of its pixels are (both of a
+// pair, or one of each pair).
+__device__ __forceinline__ void coarsen_s2(const Img& d, const Geo& g, int bx, int ry) {
+  auto nz4 = [](uint32_t w) {  // bit j = byte j is nonzero
+    uint32_t t = (((w & 0x7f7f7f7fu) + 0x7f7f7f7fu) | w) & 0x80808080u;
+    t >>= 7;
+    return (t | (t >> 7) | (t >> 14) | (t >> 21)) & 15u;
+  };
+  auto load16 = [&](int y, int x) -> uint32_t {  // nonzero bits of pixels x .. x+15 of row y (0 outside)
+    if (y < 0 || y >= g.H || x + 16 <= 0 || x >= g.W) return 0u;
+    const uint8_t* row = d.bm + (int64_t)y * g.stride;
+    if (x >= 0 && x + 16 <= g.W) {
+      const uint4 v = *reinterpret_cast<const uint4*>(row + x);
+      return nz4(v.x) | (nz4(v.y) << 4) | (nz4(v.z) << 8) | (nz4(v.w) << 12);
+    }
+    uint32_t m = 0;  // the chunk at the row's end
+    for (int j = 0; j < 16; ++j)
+      if (x + j >= 0 && x + j < g.W && row[x + j]) m |= 1u << j;
+    return m;
+  };
+  const int task = threadIdx.x >> 2, part = threadIdx.x & 3;
+  const int rr = ry * kCoarsenRows + (task >> 3), w = 8 * bx + (task & 7);  // stored row, raster word
+  const int C0 = 32 * w - kRingC + 8 * part, R = rr - kRing;                  // first coarse column, coarse row
+  uint32_t bits = 0;
+  if (R >= 0 && R < g.CH) {
+    const uint32_t T = load16(2 * R, 2 * C0), B = load16(2 * R + 1, 2 * C0);
+    uint32_t m = ((T & (T >> 1)) | (B & (B >> 1)) | ((T | (T >> 1)) & (B | (B >> 1)))) & 0x5555u;
+    m = (m | (m >> 1)) & 0x3333u;
+    m = (m | (m >> 2)) & 0x0f0fu;
+    m = (m | (m >> 4)) & 0x00ffu;
+    bits = m << (8 * part);
+  }
+  // the four lanes of a word OR their bytes together (quad permutations)
+  bits |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0xb1, 0xf, 0xf, false);  // quad_perm [1,0,3,2]
+  bits |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0x4e, 0xf, 0xf, false);  // quad_perm [2,3,0,1]
+  if (part == 0 && rr < g.CH + 2 * kRing && w < g.wpr) d.bits[(int64_t)rr * g.wpr + w] = bits;
+}
+
 template <class Src>
 __global__ void __launch_bounds__(256) k_coarsen(Src src, const int64_t* __restrict__ tab, Shared sh) {
   __shared__ uint32_t mask[kCoarsenRows * kCoarsenMaxS][kCoarsenWords];
@@ -217,6 +258,10 @@ __global__ void __launch_bounds__(256) k_coarsen(Src src, const int64_t* __restr
        q += (int64_t)gridDim.x * blockDim.x)
     sh.segacc[q] = 0ull;
   if (blockIdx.x == 0 && threadIdx.x < kDenseLists) sh.dctr[threadIdx.x] = 0ull;
+  if (g.s == 2 && (((uintptr_t)d.bm | (uintptr_t)g.stride) & 15u) == 0) {  // uniform per image
+    coarsen_s2(d, g, (int)local % nbx, (int)local / nbx);
+    return;
+  }
   const int s = g.s;
   const int rr0 = ry * kCoarsenRows;                 // first stored row
   const int C0 = 256 * bx - kRingC;                  // first coarse column of the block
@@ -307,6 +352,14 @@ __global__ void __launch_bounds__(256) k_segcount(Src src, const int64_t* __rest
   {
     const int k0 = 16 * (int)local, k1 = (int)local == nb - 1 ? g.NK + kRowPad : k0 + 16;
     for (int k = k0 + (int)threadIdx.x; k < k1; k += 256) d.rows[k] = row_table_entry(g, k);
+  }
+  // the column table: window column and x reach of column i in rows of parity o
+  for (int j = (int)local * 256 + (int)threadIdx.x; j < 2 * g.NI; j += nb * 256) {
+    const int i = j >> 1, o = j & 1;
+    const int X = g.X0 + 4 * g.h * i + 2 * g.h * o, Clo = clo_of(g, X);
+    int x0, x1;
+    owner_xreach(g, X, Clo, x0, x1);
+    d.cols[j] = (uint32_t)(Clo + 8) | ((uint32_t)x0 << 24) | ((uint32_t)x1 << 28);
   }
   int n = 0;
   for (int t = threadIdx.x; t < (r1 - r0) * g.wpr; t += 256) {
@@ -424,13 +477,12 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
   // keeps its column, so its window column depends only on the row parity.
   const int c = c0 + threadIdx.x;
   int wcol[2];
+  const uint2 ce = c < g.NI ? reinterpret_cast<const uint2*>(d.cols)[c] : make_uint2(8u, 0u);
 #pragma unroll
   for (int o = 0; o < 2; ++o) {
-    const int X = g.X0 + 4 * g.h * c + 2 * g.h * o, Clo = clo_of(g, X);
-    wcol[o] = Clo + kRingC - bw.cc0;
-    int x0, x1;
-    owner_xreach(g, X, Clo, x0, x1);
-    L.xc[o][threadIdx.x] = (uint32_t)wcol[o] | ((uint32_t)x0 << 16) | ((uint32_t)x1 << 20);
+    const uint32_t e = o ? ce.y : ce.x;
+    wcol[o] = (int)(e & 0xffffffu) - 8 + kRingC - bw.cc0;
+    L.xc[o][threadIdx.x] = (uint32_t)wcol[o] | (((e >> 24) & 15u) << 16) | ((e >> 28) << 20);
   }
   // away from the grid edges both owned triangles exist for every owner, so a
   // uniform owner's counts are constants and a row's sums are popcounts
@@ -1761,7 +1813,7 @@ static const int kRBs[3] = {4, 8, 16};
 struct CallLayout {
   int n = 0;
   std::vector<Geo> g;
-  std::vector<size_t> off_bits, off_omap, off_rows;
+  std::vector<size_t> off_bits, off_omap, off_rows, off_cols;
   std::vector<int64_t> seg0, band0, halo0;  // band0, halo0 for the smallest fused band height
   std::vector<int64_t> tab;           // [1 + 3 + 3][n + 1]: coarsen blocks, tiles per RB, bands per RB
   int64_t nseg = 0, owners = 0, rcap = 0, nbands_max = 0, halo_words = 0, ntiles_max = 0;
@@ -1784,6 +1836,7 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
   L.off_bits.resize(n);
   L.off_omap.resize(n);
   L.off_rows.resize(n);
+  L.off_cols.resize(n);
   L.seg0.resize(n);
   L.band0.resize(n);
   L.halo0.resize(n);
@@ -1877,6 +1930,8 @@ static sbmt_status make_call_layout(const sbmt_image* imgs, int n, int64_t recor
     off = align256(off + (size_t)g.NK * g.NI * 2);
     L.off_rows[i] = off;
     off = align256(off + (size_t)(g.NK + kRowPad) * sizeof(RowT));
+    L.off_cols[i] = off;
+    off = align256(off + (size_t)g.NI * 2 * sizeof(uint32_t));
   }
   L.total = off;
   return SBMT_OK;
@@ -1916,6 +1971,7 @@ static Img img_of(const CallLayout& L, int i, const sbmt_image& im, void* ws, co
   d.bits = (uint32_t*)(b + L.off_bits[i]);
   d.omap = (uint16_t*)(b + L.off_omap[i]);
   d.rows = (RowT*)(b + L.off_rows[i]);
+  d.cols = (uint32_t*)(b + L.off_cols[i]);
   d.seg0 = L.seg0[i];
   d.band0 = L.band0[i];
   d.halo0 = L.halo0[i];

@@ -409,6 +409,11 @@ __device__ __forceinline__ Bits stage_window(const Geo& g, const uint32_t* __res
   return b;
 }
 
+// Popcount of the bits of m below this lane.
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v, int lane) {
   for (int off = 1; off < 64; off <<= 1) {
@@ -435,9 +440,11 @@ struct CountLds {
   int rowR[RB];
   uint32_t rowp[RB];     // row_info of each row (reach in y, row signs)
   uint32_t xc[2][kCB];   // per column and row parity: Clo - (window's first column) | x0 << 16 | x1 << 20
-  uint16_t q1[RB * kCB];
+  uint16_t q1[RB * kCB];  // non-uniform owners, RB * 64 entries per wave
   uint16_t q2[RB * kCB];
-  int n1, n2;
+  int2 wacc[kThreads / 64][RB];  // per wave and row: vertices and triangles of its uniform owners
+  int qn[kThreads / 64];         // per wave: entries in q1
+  int n2;
   unsigned dbase;
   uint32_t win[kWinRows * kWinWords];
 };
@@ -461,7 +468,7 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
     L.rowp[threadIdx.x] = rt.pk;
     L.acc[threadIdx.x][0] = L.acc[threadIdx.x][1] = L.acc[threadIdx.x][2] = L.acc[threadIdx.x][3] = 0;
   }
-  if (threadIdx.x == 0) L.n1 = L.n2 = 0;
+  if (threadIdx.x == 0) L.n2 = 0;
   __syncthreads();
   const int klast = min(k0 + RB, g.NK) - 1;
   const Bits bw = stage_window(g, d.bits, L.win, L.rowR[0] + kRing, L.rowR[klast - k0] + 2 + kRing, c0,
@@ -488,48 +495,64 @@ __device__ __forceinline__ void count_tile(const Img& d, const Geo& g, int ii, i
   // uniform owner's counts are constants and a row's sums are popcounts
   const bool interior = k0 + RB < g.NK && c0 >= 1 && c0 + kCB < g.NI;
   const bool both = (g.flags & 1u) != 0;
-  if (interior) {
-    const uint32_t code_fg = map_code(fast_info_k(g, k0, c0 + 1, 1)), code_bg = map_code(fast_info_k(g, k0, c0 + 1, 0));
-    for (int r = 0; r < RB; ++r) {
-      const int odd = (k0 + r) & 1;
-      const int wc = wcol[odd], w = wc >> 5, sh = wc & 31;
-      const int kind = (int)((L.u0[r][w] >> sh) & 1u) | ((int)((L.u1[r][w] >> sh) & 1u) << 1);
-      if (kind) L.code[r][threadIdx.x] = (uint16_t)(kind == 2 ? code_fg : code_bg);
-      else L.q1[atomicAdd(&L.n1, 1)] = (uint16_t)(r * kCB + threadIdx.x);
-      // vertices: one per counted owner; triangles: two
-      const unsigned long long m = __ballot(both ? kind != 0 : kind == 2);
-      if (lane == 0 && m) {
-        const int n = (int)__popcll(m);
-        atomicAdd(&L.acc[r][0], n);
-        atomicAdd(&L.acc[r][1], 2 * n);
-      }
-    }
-  }
-  for (int r = 0; r < RB && !interior; ++r) {
+  const uint32_t code_fg = map_code(fast_info_k(g, k0, c0 + 1, 1)), code_bg = map_code(fast_info_k(g, k0, c0 + 1, 0));
+  // each wave queues its non-uniform owners in its own part of q1 (ballot and
+  // mbcnt, no atomics) and keeps its rows' counts of uniform owners in
+  // registers (lane r those of row r), handed over in wacc
+  uint16_t* const qw = L.q1 + (threadIdx.x >> 6) * (RB * 64);
+  int qn = 0, rv = 0, rt = 0;
+  for (int r = 0; r < RB; ++r) {
     const int k = k0 + r;
-    if (k >= g.NK) break;
-    int p = 0;  // vertices | triangles << 16
+    if (k >= g.NK) break;  // uniform
+    int kind = 1;          // positions beyond the grid: no owner, nothing counted
     if (c < g.NI) {
       const int wc = wcol[k & 1], w = wc >> 5, sh = wc & 31;
-      const int kind = (int)((L.u0[r][w] >> sh) & 1u) | ((int)((L.u1[r][w] >> sh) & 1u) << 1);
-      if (kind) {
+      kind = (int)((L.u0[r][w] >> sh) & 1u) | ((int)((L.u1[r][w] >> sh) & 1u) << 1);
+    }
+    // a non-uniform owner's code is written again below
+    int nv, nt;
+    if (interior) {
+      L.code[r][threadIdx.x] = (uint16_t)(kind == 2 ? code_fg : code_bg);
+      // vertices: one per counted owner; triangles: two
+      nv = (int)__popcll(__ballot(both ? kind != 0 : kind == 2));
+      nt = 2 * nv;
+    } else {
+      int p = 0;  // vertices | triangles << 16
+      if (c < g.NI && kind != 0) {
         const uint32_t fi = fast_info_k(g, k, c, kind >> 1);
         p = info_nv(fi) | (info_nt(fi) << 16);
         L.code[r][threadIdx.x] = (uint16_t)map_code(fi);
-      } else {
-        L.q1[atomicAdd(&L.n1, 1)] = (uint16_t)(r * kCB + threadIdx.x);
       }
+      p = __builtin_amdgcn_readlane(wave_incl_scan_dpp(p), 63);
+      nv = p & 0xffff;
+      nt = p >> 16;
     }
-    p = __builtin_amdgcn_readlane(wave_incl_scan_dpp(p), 63);
-    if (lane == 0 && p) {
-      atomicAdd(&L.acc[r][0], p & 0xffff);
-      atomicAdd(&L.acc[r][1], p >> 16);
-    }
+    const unsigned long long mnu = __ballot(kind == 0);
+    if (kind == 0) qw[qn + lanes_below(mnu)] = (uint16_t)(r * kCB + threadIdx.x);
+    qn += (int)__popcll(mnu);
+    rv = lane == r ? nv : rv;
+    rt = lane == r ? nt : rt;
   }
+  if (lane < RB) L.wacc[threadIdx.x >> 6][lane] = make_int2(rv, rt);
+  if (lane == 0) L.qn[threadIdx.x >> 6] = qn;
   __syncthreads();
+  if (threadIdx.x < RB) {
+    int sv = 0, st = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+      sv += L.wacc[w][threadIdx.x].x;
+      st += L.wacc[w][threadIdx.x].y;
+    }
+    atomicAdd(&L.acc[threadIdx.x][0], sv);
+    atomicAdd(&L.acc[threadIdx.x][1], st);
+  }
+  static_assert(kThreads / 64 == 4, "four waves");
+  const int p1 = L.qn[0], p2 = p1 + L.qn[1], p3 = p2 + L.qn[2], n1 = p3 + L.qn[3];
   // non-uniform windows: quiet owners (no segment reaches them) or slow ones
-  for (int q = threadIdx.x; q < L.n1; q += kThreads) {
-    const int e = L.q1[q], r = e / kCB, col = e - r * kCB, c = c0 + col;
+  for (int q = threadIdx.x; q < n1; q += kThreads) {
+    const int w = (q >= p1) + (q >= p2) + (q >= p3);
+    const int e = L.q1[w * (RB * 64) + q - (w == 0 ? 0 : (w == 1 ? p1 : (w == 2 ? p2 : p3)))];
+    const int r = e / kCB, col = e - r * kCB, c = c0 + col;
     const int k = k0 + r;
     const uint32_t xc = L.xc[k & 1][col];
     const Frame f = owner_frame_at(g, bw, k, c, L.rowR[r], (int)(xc & 0xffffu) - kRingC + bw.cc0);
@@ -1338,9 +1361,7 @@ __global__ void __launch_bounds__(kThreads, 8) k_emit(Src src, const int64_t* __
     if (!both && __ballot((code[r] & 0x8000u) != 0u) == 0ull) {
       // no slow owner in the strip's row: a fast owner emits its vertex and
       // both triangles iff it is inside, so the prefix is a count of inside bits
-      const unsigned long long m = __ballot((code[r] & 1u) != 0u);
-      const int nb = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) +
-                     (int)(code[r] & 1u);
+      const int nb = lanes_below(__ballot((code[r] & 1u) != 0u)) + (int)(code[r] & 1u);
       incl[r] = nb | (nb << 17);
     } else {
       incl[r] = wave_incl_scan_dpp(p);

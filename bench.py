@@ -468,6 +468,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-pool", type=int, default=48)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-latency", action="store_true", help="skip the per-image latency sections")
     ap.add_argument("--no-post", action="store_true", help="skip the mesh-consumer section")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference for HBM byte counters)")
@@ -542,11 +543,12 @@ def main():
             res["post"]["quality"]["cpu_baseline"] = post_cpu_baseline(H["plain"])
     del H
     if extras is not None:
-        log("latency sections")
-        res["latency"] = [
-            latency("disk64", extras["disk64"], 1),
-            latency("ellipses1024", extras["ellipses1024"], 2, repeats=10),
-        ]
+        if not args.no_latency:
+            log("latency sections")
+            res["latency"] = [
+                latency("disk64", extras["disk64"], 1),
+                latency("ellipses1024", extras["ellipses1024"], 2, repeats=10),
+            ]
         log("batch section")
         res["batch"] = batch_section(extras["batch"])
         if "serve" in extras:
@@ -555,9 +557,10 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline")
         res["cpu_baseline"] = cpu_baseline(noise)
-        if extras is not None:
+        if extras is not None and not args.no_latency:
             res["latency"][0]["cpu_baseline"] = cpu_baseline_images("disk64", extras["disk64"], 1)
             res["latency"][1]["cpu_baseline"] = cpu_baseline_images("ellipses1024", extras["ellipses1024"], 2)
+        if extras is not None:
             res["batch"]["cpu_baseline"] = cpu_baseline_pool(extras["batch"])
             if "serve" in extras:
                 res["serve"]["cpu_baseline"] = cpu_baseline_pool(extras["serve"], what="serving request pool")

@@ -85,6 +85,10 @@ def lib():
         L.oracle_pre_copy.argtypes = [vp, vp, vp, vp]
         L.oracle_pre_free.restype = None
         L.oracle_pre_free.argtypes = [vp]
+        L.oracle_pre_grid_sizes.restype = None
+        L.oracle_pre_grid_sizes.argtypes = [vp, vp]
+        L.oracle_pre_grid_copy.restype = None
+        L.oracle_pre_grid_copy.argtypes = [vp, vp, vp, vp]
         L.oracle_canonical.restype = i32
         L.oracle_canonical.argtypes = [i32, vp, vp]
         L.oracle_z3_sign.restype = i32
@@ -211,6 +215,45 @@ def mesh_preprocessed(bitmap: np.ndarray, grid_h, a=None, b=None, c=None) -> Pre
         cnt = np.zeros(4, np.int64)
         L.oracle_pre_counts(res, cnt.ctypes.data)
         return PreMesh(verts, tris, codes, *(int(x) for x in cnt), (a, b, c))
+    finally:
+        L.oracle_pre_free(res)
+
+
+@dataclass
+class PreGrid:
+    verts: np.ndarray        # (V, 2) float64: lattice vertices k NI + i, then the inserted points
+    on_polyline: np.ndarray  # (V,) uint8: the vertex sits on a polyline vertex (snapped or inserted)
+    tris: np.ndarray         # (T, 3) int64: live triangles of the preprocessed grid
+    n_snapped: int
+    n_repelled: int
+    n_inserted: int
+    thresholds: tuple
+
+
+def preprocessed_grid(bitmap: np.ndarray, grid_h, a=None, b=None, c=None) -> PreGrid:
+    """The grid after Steps 1-3 of Alg. 3 (vertex snapping a, repulsion c, edge
+    elimination b), before the retriangulation against the polyline."""
+    L = lib()
+    sc = float(grid_h) / PAPER_EDGE
+    a = PAPER_THRESHOLDS[0] * sc if a is None else float(a)
+    b = PAPER_THRESHOLDS[1] * sc if b is None else float(b)
+    c = PAPER_THRESHOLDS[2] * sc if c is None else float(c)
+    bm = np.ascontiguousarray(bitmap, dtype=np.uint8)
+    H, W = bm.shape
+    err = ctypes.create_string_buffer(512)
+    res = L.oracle_mesh_preprocessed(bm.ctypes.data if bm.size else None, W, H, W, float(grid_h), a, b, c, err, 512)
+    if not res:
+        raise OracleError(err.value.decode())
+    try:
+        sz = np.zeros(2, np.int64)
+        L.oracle_pre_grid_sizes(res, sz.ctypes.data)
+        verts = np.zeros((int(sz[0]), 2), np.float64)
+        onp = np.zeros((int(sz[0]),), np.uint8)
+        tris = np.zeros((int(sz[1]), 3), np.int64)
+        L.oracle_pre_grid_copy(res, verts.ctypes.data, onp.ctypes.data, tris.ctypes.data)
+        cnt = np.zeros(4, np.int64)
+        L.oracle_pre_counts(res, cnt.ctypes.data)
+        return PreGrid(verts, onp, tris, int(cnt[0]), int(cnt[1]), int(cnt[2]), (a, b, c))
     finally:
         L.oracle_pre_free(res)
 

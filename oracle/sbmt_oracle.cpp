@@ -1123,7 +1123,18 @@ struct PreResult {
   std::vector<int32_t> tris;
   std::vector<uint8_t> codes;
   i64 n_snapped = 0, n_repelled = 0, n_inserted = 0, n_cut = 0;
+  // the preprocessed grid (after Steps 1-3, before the retriangulation):
+  // vertices (lattice k NI + i, then the inserted points in polyline order),
+  // whether each sits on a polyline vertex, and the live triangles
+  std::vector<double> grid_verts;
+  std::vector<uint8_t> grid_on_polyline;
+  std::vector<int64_t> grid_tris;
 };
+
+// Euclidean length as the square root of the sum of squares, in IEEE double
+// operations (a plain formula that any implementation evaluates identically;
+// every threshold decision below compares such lengths).
+static double euclid(double dx, double dy) { return std::sqrt(dx * dx + dy * dy); }
 
 class PreOracle {
  public:
@@ -1136,6 +1147,7 @@ class PreOracle {
     snap_and_repel();
     build_triangles();
     eliminate_edges();
+    record_grid();
     retriangulate();
     return finish();
   }
@@ -1188,7 +1200,18 @@ class PreOracle {
     double t = ((x - px) * dx + (y - py) * dy) / (dx * dx + dy * dy);
     t = std::min(1.0, std::max(0.0, t));
     if (tpar) *tpar = t;
-    return std::hypot(x - (px + t * dx), y - (py + t * dy));
+    return euclid(x - (px + t * dx), y - (py + t * dy));
+  }
+
+  void record_grid() {
+    for (const V& v : vs_) {
+      out_.grid_verts.push_back(v.x);
+      out_.grid_verts.push_back(v.y);
+      out_.grid_on_polyline.push_back(v.bnd >= 0 ? 1 : 0);
+    }
+    for (size_t t = 0; t < tri_.size(); ++t)
+      if (alive_[t])
+        for (int j = 0; j < 3; ++j) out_.grid_tris.push_back(tri_[t][(size_t)j]);
   }
 
   // Steps 1 and 2: vertex snapping (a), then repulsion (c) of the vertices left
@@ -1204,7 +1227,7 @@ class PreOracle {
         double best = a_;
         i64 bj = -1;
         near(pcell_, v.x, v.y, a_, [&](i64 j) {
-          const double d = std::hypot(v.x - T_.px[(size_t)j], v.y - T_.py[(size_t)j]);
+          const double d = euclid(v.x - T_.px[(size_t)j], v.y - T_.py[(size_t)j]);
           if (d < best || (d == best && bj >= 0 && j < bj)) { best = d; bj = j; }
         });
         if (bj >= 0) {
@@ -1234,7 +1257,7 @@ class PreOracle {
       seg_dist(bj, v.x, v.y, &t);
       ORACLE_CHECK(t > 0.0 && t < 1.0, "repulsion foot at a segment end");
       const double px = T_.px[(size_t)bj], py = T_.py[(size_t)bj];
-      const double dx = qx(bj) - px, dy = qy(bj) - py, L = std::hypot(dx, dy);
+      const double dx = qx(bj) - px, dy = qy(bj) - py, L = euclid(dx, dy);
       const double nx = -dy / L, ny = dx / L;                 // left normal
       const double d = (v.x - px) * nx + (v.y - py) * ny;     // signed distance to the line
       const double move = (d > 0 ? c_ : -c_) - d;
@@ -1285,7 +1308,7 @@ class PreOracle {
     const double dx = bx - ax, dy = by - ay;
     double t = ((x - ax) * dx + (y - ay) * dy) / (dx * dx + dy * dy);
     t = std::min(1.0, std::max(0.0, t));
-    return std::hypot(x - (ax + t * dx), y - (ay + t * dy));
+    return euclid(x - (ax + t * dx), y - (ay + t * dy));
   }
 
   // Step 3: edge elimination (b) and cavity retriangulation around p_j
@@ -1784,6 +1807,18 @@ void oracle_pre_copy(const oracle_pre* r, double* verts, int32_t* tris, uint8_t*
   if (codes && !r->r.codes.empty()) std::memcpy(codes, r->r.codes.data(), r->r.codes.size());
 }
 void oracle_pre_free(oracle_pre* r) { delete r; }
+// The preprocessed grid of Alg. 3 (Steps 1-3): vertices, on-polyline flags,
+// live triangles (vertex indices).
+void oracle_pre_grid_sizes(const oracle_pre* r, int64_t* out) {
+  out[0] = (int64_t)r->r.grid_on_polyline.size();
+  out[1] = (int64_t)r->r.grid_tris.size() / 3;
+}
+void oracle_pre_grid_copy(const oracle_pre* r, double* verts, uint8_t* on_polyline, int64_t* tris) {
+  if (verts && !r->r.grid_verts.empty()) std::memcpy(verts, r->r.grid_verts.data(), r->r.grid_verts.size() * 8);
+  if (on_polyline && !r->r.grid_on_polyline.empty())
+    std::memcpy(on_polyline, r->r.grid_on_polyline.data(), r->r.grid_on_polyline.size());
+  if (tris && !r->r.grid_tris.empty()) std::memcpy(tris, r->r.grid_tris.data(), r->r.grid_tris.size() * 8);
+}
 
 // Exact sign of a + b*sqrt3 (exposed for the arithmetic pin).
 int32_t oracle_z3_sign(int64_t a, int64_t b) { return z3_sign(Z3{(i128)a, (i128)b}); }

@@ -243,6 +243,62 @@ sbmt_status sbmt_batch_set_tuning(sbmt_batch b, const sbmt_tuning* t);
 /* reps timed runs per candidate; best / best_ms may be NULL. */
 sbmt_status sbmt_batch_tune(sbmt_batch b, int32_t reps, sbmt_tuning* best, float* best_ms, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Geometric preprocessing of the grid (Alg. 3, Sec. 3.5; thresholds of
+ * Sec. 3.3.4): before the polyline is embedded, the lattice of the image is
+ * adapted to it in three steps.
+ *   Step 1 (vertex snapping, distance a): a lattice vertex within a of a
+ *          polyline vertex (a marching-squares midpoint whose two coarse
+ *          samples differ) moves onto it;
+ *   Step 2 (vertex repulsion, distance c): a vertex left in place that lies
+ *          within c of a polyline segment moves along the segment's normal,
+ *          on its own side, to distance exactly c;
+ *   Step 3 (edge elimination, distance b): a polyline vertex that no lattice
+ *          vertex snapped to and that lies within b of a side of a base
+ *          triangle is inserted on that side, and each triangle of the side
+ *          is replaced by the two triangles fanned around it.
+ * The result is the preprocessed grid: lattice vertex (k, i) at index
+ * k * grid_cols + i (after Steps 1 and 2), then the inserted polyline
+ * vertices (by owner lattice vertex, then owned side E0, E1, E2), and the
+ * triangles by base triangle slot (row k, then i, the slot with apex on row k
+ * first; a fanned slot gives its two triangles in the order
+ * (a0, m, a2), (m, a1, a2) for the split side a0 -> a1).  Every triangle has
+ * positive signed area.  Distances are square roots of sums of squares in
+ * FP64, thresholds compared strictly (closer than a, b, c).
+ *
+ * Thresholds must satisfy 0 <= b < a/2, 0 <= c < a/sqrt2, 0 <= a < h/2
+ * (Sec. 3.3.4), or all be zero (the plain lattice); otherwise
+ * SBMT_E_INVALID_ARG.  The paper's setting is
+ * (a, b, c) = (0.26, 0.125, 0.183) * h / sqrt(0.45).  With admissible
+ * thresholds every decision is local (one polyline vertex within a of a
+ * lattice vertex, one segment within c of a vertex left in place, one side
+ * within b of a polyline vertex and at most one split side per triangle);
+ * an input that breaks one of these returns SBMT_E_PROTOCOL.
+ * ------------------------------------------------------------------------- */
+
+/* Host only.  Workspace bytes of sbmt_preprocess for this image and bounds on
+ * its vertex and triangle counts: grid_rows * grid_cols plus
+ * 2 (coarse_h + 2)(coarse_w + 2) (every sample edge of the padded coarse
+ * raster), and 4 * grid_rows * grid_cols.  Any pointer may be NULL. */
+sbmt_status sbmt_pre_query(const sbmt_image* img, size_t* workspace_bytes, int64_t* vert_bound, int64_t* tri_bound);
+
+/* Preprocessed grid of one image on `stream`; waits for it.
+ *  workspace    device, >= the bytes of sbmt_pre_query (else SBMT_E_WORKSPACE)
+ *  verts        device double [vert_cap][2]; vert_cap must be at least
+ *               grid_rows * grid_cols (else SBMT_E_CAPACITY before any launch)
+ *  on_polyline  device uint8 [vert_cap]: 1 for a vertex on a polyline vertex
+ *               (snapped or inserted), else 0
+ *  tris         device int32 [tri_cap][3] (may be NULL with tri_cap = 0)
+ *  counts       host int64 [6]: n_vertices, n_triangles, n_snapped,
+ *               n_repelled, n_inserted, status
+ * Rows beyond a capacity are not written and the call returns
+ * SBMT_E_CAPACITY with the counts filled in (size the outputs from them and
+ * call again); SBMT_E_PROTOCOL as above; SBMT_E_INDEX_OVERFLOW if a vertex
+ * index does not fit int32. */
+sbmt_status sbmt_preprocess(sbmt_handle h, const sbmt_image* img, double a, double b, double c, void* workspace,
+                            size_t ws_bytes, double* verts, uint8_t* on_polyline, int64_t vert_cap, int32_t* tris,
+                            int64_t tri_cap, int64_t* counts, void* stream);
+
 /* Number of canonical classes and the key code of class id c (1-based). */
 int32_t sbmt_num_classes(void);
 int32_t sbmt_class_code(int32_t class_id);

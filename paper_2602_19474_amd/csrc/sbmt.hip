@@ -2075,12 +2075,436 @@ static sbmt_status launch_emit(const CallLayout& L, const Src& src, const int64_
   return hipGetLastError() == hipSuccess ? SBMT_OK : SBMT_E_DEVICE;
 }
 
+
+// ---------------------------------------------------------------------------
+// Geometric preprocessing of Alg. 3 (Sec. 3.5, thresholds of Sec. 3.3.4):
+// Step 1 snaps a lattice vertex to the polyline vertex within distance a,
+// Step 2 moves a vertex within c of a segment along that segment's normal to
+// distance exactly c, Step 3 splits every mesh edge within b of a polyline
+// vertex that no lattice vertex snapped to, at that vertex (the edge's one or
+// two triangles become a fan around it).  The result is the preprocessed
+// grid: lattice vertices (moved), inserted polyline vertices, and the base
+// triangles with their split edges fanned.
+//
+// Polyline vertices are the marching-squares midpoints whose two coarse
+// samples differ; distances are square roots of sums of squares in double
+// precision, evaluated exactly as written (no contraction).  Admissible
+// thresholds (b < a/2, c < a/sqrt2, a < h/2) keep every decision local: at
+// most one polyline vertex within a of a lattice vertex, at most one segment
+// within c of an unsnapped one, at most one edge within b of a polyline vertex
+// and at most one polyline vertex within b of an edge, at most one split edge
+// per triangle; the kernels flag a protocol error otherwise.
+// ---------------------------------------------------------------------------
+struct PreArgs {
+  double a, b, c;
+  double* verts;         // [NK NI + inserted][2]: lattice vertex k NI + i first
+  uint8_t* on_polyline;  // per vertex: sits on a polyline vertex
+  int32_t* tris;         // [triangles][3]
+  int64_t vcap, tcap;
+  uint32_t* mid;         // per midpoint: bit 31 snapped to, low bits edges it splits
+  int32_t* split;        // [NK NI][3]: midpoint splitting the owner's edge E0, E1, E2 (-1 none)
+  int32_t* owner_n;      // [NK NI]: inserted vertices | triangles << 8 of each owner
+  int64_t* ins_base;     // [NK NI]: first inserted vertex of each owner (index among the inserted)
+  int64_t* counts;       // [8]: snapped, repelled, error
+};
+
+// Midpoint ids: horizontal midpoint between samples (R, C) and (R, C+1) is
+// 2 ((R + 1)(CW + 2) + C + 1), the vertical one between (R, C) and (R+1, C)
+// one more; R in -1 .. CH, C in -1 .. CW.
+__device__ __forceinline__ int64_t mid_id(const Geo& g, int R, int C, int vert) {
+  return 2 * ((int64_t)(R + 1) * (g.CW + 2) + (C + 1)) + vert;
+}
+__device__ __forceinline__ int sample_at(const Img& d, const Geo& g, int R, int C) {
+  if (R < 0 || R >= g.CH || C < 0 || C >= g.CW) return 0;
+  const int rr = R + kRing, cc = C + kRingC;
+  return (int)((d.bits[(int64_t)rr * g.wpr + (cc >> 5)] >> (cc & 31)) & 1u);
+}
+// Midpoint (R, C, vert) in pixels, and whether it is a polyline vertex.
+__device__ __forceinline__ bool mid_point(const Img& d, const Geo& g, int R, int C, int vert, double& x, double& y) {
+  const double half = 0.5 * g.s;
+  x = (double)g.s * C + 0.5 * (g.s - 1) + (vert ? 0.0 : half);
+  y = (double)g.s * R + 0.5 * (g.s - 1) + (vert ? half : 0.0);
+  if (R < -1 || R > g.CH || C < -1 || C > g.CW) return false;
+  return sample_at(d, g, R, C) != sample_at(d, g, vert ? R + 1 : R, vert ? C : C + 1);
+}
+__device__ __forceinline__ double euclid_d(double dx, double dy) { return __builtin_sqrt(dx * dx + dy * dy); }
+// distance from (x, y) to segment P -> Q and the parameter of the closest point
+__device__ __forceinline__ double seg_dist_d(double x, double y, double px, double py, double qx, double qy, double* tp) {
+  const double dx = qx - px, dy = qy - py;
+  double t = ((x - px) * dx + (y - py) * dy) / (dx * dx + dy * dy);
+  t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+  if (tp) *tp = t;
+  return euclid_d(x - (px + t * dx), y - (py + t * dy));
+}
+__device__ __forceinline__ int nearest_index(const Geo& g, double v) {
+  return (int)__builtin_floor((v - 0.5 * (g.s - 1)) / g.s + 0.5);
+}
+
+// Steps 1 and 2, one thread per lattice vertex.
+__global__ void __launch_bounds__(256) k_pre_vertices(OneSrc src, PreArgs P) {
+  const Img& d = src.d;
+  const Geo g = d.g;
+  const int64_t n = (int64_t)g.NK * g.NI;
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= n) return;
+  const int k = (int)(v / g.NI), i = (int)(v - (int64_t)k * g.NI);
+  double x = lat_x(g, g.X0 + 4 * g.h * i + 2 * g.h * (k & 1)), y = lat_y(g, k);
+  const int Rc = nearest_index(g, y), Cc = nearest_index(g, x);
+  // Step 1: the polyline vertex within a (at most one)
+  double best = P.a;
+  int64_t bj = -1;
+  double bx = 0, by = 0;
+  for (int R = Rc - 1; R <= Rc + 1; ++R)
+    for (int C = Cc - 1; C <= Cc + 1; ++C)
+      for (int vt = 0; vt < 2; ++vt) {
+        double mx, my;
+        if (!mid_point(d, g, R, C, vt, mx, my)) continue;
+        const double dd = euclid_d(x - mx, y - my);
+        if (dd < best) {
+          best = dd;
+          bj = mid_id(g, R, C, vt);
+          bx = mx;
+          by = my;
+        }
+      }
+  uint8_t onp = 0;
+  if (bj >= 0) {
+    x = bx;
+    y = by;
+    onp = 1;
+    atomicOr(&P.mid[bj], 0x80000000u);
+    atomicAdd((unsigned long long*)&P.counts[0], 1ull);
+  } else if (P.c > 0.0) {
+    // Step 2: the segment within c (at most one), of the dual cells around v
+    const int Rd = (int)__builtin_floor((y - 0.5 * (g.s - 1)) / g.s), Cd = (int)__builtin_floor((x - 0.5 * (g.s - 1)) / g.s);
+    int nclose = 0;
+    double spx = 0, spy = 0, sqx = 0, sqy = 0, st = 0;
+    for (int R = Rd - 1; R <= Rd + 1; ++R)
+      for (int C = Cd - 1; C <= Cd + 1; ++C) {
+        const int cs = sample_at(d, g, R, C) | (sample_at(d, g, R, C + 1) << 1) | (sample_at(d, g, R + 1, C + 1) << 2) |
+                       (sample_at(d, g, R + 1, C) << 3);
+        const uint32_t ms = ms_case(cs);
+        for (int j = 0; j < (int)(ms & 3u); ++j) {
+          const int ea = (int)((ms >> (2 + 4 * j)) & 3u), eb = (int)((ms >> (4 + 4 * j)) & 3u);
+          // cell edges: 0 top, 1 right, 2 bottom, 3 left
+          double px, py, qx, qy;
+          mid_point(d, g, ea == 2 ? R + 1 : R, ea == 1 ? C + 1 : C, ea & 1, px, py);
+          mid_point(d, g, eb == 2 ? R + 1 : R, eb == 1 ? C + 1 : C, eb & 1, qx, qy);
+          double t;
+          if (seg_dist_d(x, y, px, py, qx, qy, &t) < P.c) {
+            ++nclose;
+            spx = px;
+            spy = py;
+            sqx = qx;
+            sqy = qy;
+            st = t;
+          }
+        }
+      }
+    if (nclose > 1 || (nclose == 1 && !(st > 0.0 && st < 1.0))) atomicOr((unsigned long long*)&P.counts[2], 1ull);
+    if (nclose == 1) {
+      const double dx = sqx - spx, dy = sqy - spy, L = euclid_d(dx, dy);
+      const double nx = -dy / L, ny = dx / L;                 // left normal
+      const double ds = (x - spx) * nx + (y - spy) * ny;      // signed distance to the line
+      const double move = (ds > 0 ? P.c : -P.c) - ds;
+      x += move * nx;
+      y += move * ny;
+      atomicAdd((unsigned long long*)&P.counts[1], 1ull);
+    }
+  }
+  if (v < P.vcap) {
+    P.verts[2 * v] = x;
+    P.verts[2 * v + 1] = y;
+    P.on_polyline[v] = onp;
+  }
+}
+
+// Lattice vertex of a possibly moved grid (after k_pre_vertices).
+__device__ __forceinline__ void pre_vertex(const PreArgs& P, const Geo& g, int k, int i, double& x, double& y) {
+  const int64_t v = (int64_t)k * g.NI + i;
+  x = P.verts[2 * v];
+  y = P.verts[2 * v + 1];
+}
+
+// Base triangle slot t of owner (k, i) exists (all three corners in the lattice).
+__device__ __forceinline__ bool pre_slot_ok(const Geo& g, int k, int i, int t) {
+  const int o = k & 1;
+  return t == 0 ? (k + 1 < g.NK && i + o - 1 >= 0 && i + o < g.NI) : (k + 1 < g.NK && i + 1 < g.NI && i + o < g.NI);
+}
+// Owned edge e of (k, i) is a side of some base triangle: E0 of Ta(k, i) or of
+// Tb of the owner above whose lower side it is, E1 of Tb(k, i) or of
+// Ta(k, i-1), E2 of either triangle of (k, i).
+__device__ __forceinline__ bool pre_edge_live(const Geo& g, int k, int i, int e) {
+  if (e == 0) {
+    const int ia = i + 1 - ((k - 1) & 1);
+    return pre_slot_ok(g, k, i, 1) || (k >= 1 && ia >= 0 && ia < g.NI && pre_slot_ok(g, k - 1, ia, 0));
+  }
+  if (e == 1) return pre_slot_ok(g, k, i, 0) || (i >= 1 && pre_slot_ok(g, k, i - 1, 1));
+  return pre_slot_ok(g, k, i, 0) || pre_slot_ok(g, k, i, 1);
+}
+
+// Step 3, one thread per owner: the free polyline vertex (no lattice vertex
+// snapped to it) within b of each owned edge E0 -> (k, i+1), E1 -> (k+1, i+o-1),
+// E2 -> (k+1, i+o).
+__global__ void __launch_bounds__(256) k_pre_edges(OneSrc src, PreArgs P) {
+  const Img& d = src.d;
+  const Geo g = d.g;
+  const int64_t n = (int64_t)g.NK * g.NI;
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= n) return;
+  const int k = (int)(v / g.NI), i = (int)(v - (int64_t)k * g.NI), o = k & 1;
+  double ux, uy;
+  pre_vertex(P, g, k, i, ux, uy);
+  for (int e = 0; e < 3; ++e) {
+    const int kw = e == 0 ? k : k + 1, iw = e == 0 ? i + 1 : (e == 1 ? i + o - 1 : i + o);
+    int32_t hit = -1;
+    if (P.b > 0.0 && pre_edge_live(g, k, i, e)) {
+      double wx, wy;
+      pre_vertex(P, g, kw, iw, wx, wy);
+      const int Rc = nearest_index(g, 0.5 * (uy + wy)), Cc = nearest_index(g, 0.5 * (ux + wx));
+      int nh = 0;
+      for (int R = Rc - 2; R <= Rc + 2; ++R)
+        for (int C = Cc - 2; C <= Cc + 2; ++C)
+          for (int vt = 0; vt < 2; ++vt) {
+            double mx, my;
+            if (!mid_point(d, g, R, C, vt, mx, my)) continue;
+            const int64_t id = mid_id(g, R, C, vt);
+            if (P.mid[id] & 0x80000000u) continue;  // a lattice vertex sits on it
+            // both orientations, as the edge's two triangles see it
+            if (seg_dist_d(mx, my, ux, uy, wx, wy, nullptr) < P.b || seg_dist_d(mx, my, wx, wy, ux, uy, nullptr) < P.b) {
+              ++nh;
+              hit = (int32_t)id;
+            }
+          }
+      if (nh > 1) atomicOr((unsigned long long*)&P.counts[2], 1ull);
+      if (hit >= 0 && (atomicAdd(&P.mid[hit], 1u) & 0x7fffffffu) != 0u) atomicOr((unsigned long long*)&P.counts[2], 1ull);
+    }
+    P.split[3 * v + e] = hit;
+  }
+}
+
+// Triangle slots of owner (k, i): Tb = [v, vdr, vdl], Ta = [v, vr, vdr].  For
+// slot t and its side j (corner j to corner j+1) the midpoint splitting it (or
+// -1), read from the owner of that side: Tb sides are E2 of v, E0 of vdl, E1
+// of v; Ta sides E0 of v, E1 of vr, E2 of v.
+__device__ __forceinline__ int32_t pre_edge_split(const PreArgs& P, const Geo& g, int k, int i, int t, int j) {
+  const int o = k & 1;
+  int64_t w;
+  int e;
+  if (t == 0) {  // Tb: v -> vdr (E2 of v), vdr -> vdl (E0 of vdl), vdl -> v (E1 of v)
+    if (j == 0) { w = (int64_t)k * g.NI + i; e = 2; }
+    else if (j == 1) { w = (int64_t)(k + 1) * g.NI + (i + o - 1); e = 0; }
+    else { w = (int64_t)k * g.NI + i; e = 1; }
+  } else {  // Ta: v -> vr (E0 of v), vr -> vdr (E1 of vr), vdr -> v (E2 of v)
+    if (j == 0) { w = (int64_t)k * g.NI + i; e = 0; }
+    else if (j == 1) { w = (int64_t)k * g.NI + i + 1; e = 1; }
+    else { w = (int64_t)k * g.NI + i; e = 2; }
+  }
+  return P.split[3 * w + e];
+}
+
+// Per owner: inserted vertices (its split edges) and triangles (its slots, two
+// for a slot with a split edge); per row segment (the block) their sums.
+__global__ void __launch_bounds__(256) k_pre_count(OneSrc src, PreArgs P, Shared sh) {
+  __shared__ int part[2][4];
+  const Img& d = src.d;
+  const Geo g = d.g;
+  const int k = (int)(blockIdx.x / g.NCB), cb = (int)(blockIdx.x - (int64_t)k * g.NCB);
+  const int i = cb * kCB + (int)threadIdx.x;
+  int ni = 0, nt = 0;
+  if (i < g.NI) {
+    const int64_t v = (int64_t)k * g.NI + i;
+    for (int e = 0; e < 3; ++e) ni += P.split[3 * v + e] >= 0 ? 1 : 0;
+    for (int t = 0; t < 2; ++t) {
+      if (!pre_slot_ok(g, k, i, t)) continue;
+      int ns = 0;
+      for (int j = 0; j < 3; ++j) ns += pre_edge_split(P, g, k, i, t, j) >= 0 ? 1 : 0;
+      if (ns > 1) atomicOr((unsigned long long*)&P.counts[2], 1ull);
+      nt += ns ? 2 : 1;
+    }
+    P.owner_n[v] = ni | (nt << 8);
+  }
+  const int lane = threadIdx.x & 63;
+  const int si = __builtin_amdgcn_readlane(wave_incl_scan_dpp(ni), 63);
+  const int stt = __builtin_amdgcn_readlane(wave_incl_scan_dpp(nt), 63);
+  if (lane == 0) {
+    part[0][threadIdx.x >> 6] = si;
+    part[1][threadIdx.x >> 6] = stt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    sh.seg_cnt[blockIdx.x] = make_int4(part[0][0] + part[0][1] + part[0][2] + part[0][3],
+                                       part[1][0] + part[1][1] + part[1][2] + part[1][3], 0, 0);
+    sh.seg_slow[blockIdx.x] = 0ull;
+  }
+}
+
+// Inserted vertices and triangles at their offsets (row segment bases from the
+// scan, owner offsets by a block scan).  Phase 0 writes the inserted vertices
+// and each owner's first inserted index; phase 1 the triangles.
+__device__ __forceinline__ void block_scan256(int& x, int* tmp) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int incl = wave_incl_scan_dpp(x);
+  if (lane == 63) tmp[wv] = incl;
+  __syncthreads();
+  int before = 0;
+  for (int w = 0; w < wv; ++w) before += tmp[w];
+  x = before + incl - x;  // exclusive
+  __syncthreads();
+}
+template <int kPhase>
+__global__ void __launch_bounds__(256) k_pre_emit(OneSrc src, PreArgs P, Shared sh) {
+  __shared__ int tmp[4];
+  const Img& d = src.d;
+  const Geo g = d.g;
+  const int k = (int)(blockIdx.x / g.NCB), cb = (int)(blockIdx.x - (int64_t)k * g.NCB);
+  const int i = cb * kCB + (int)threadIdx.x;
+  const int64_t v = (int64_t)k * g.NI + i;
+  const int on = i < g.NI ? P.owner_n[v] : 0;
+  int xi = on & 0xff, xt = on >> 8;
+  block_scan256(xi, tmp);
+  block_scan256(xt, tmp);
+  const longlong4 base = sh.seg_off[blockIdx.x];
+  const int64_t nlat = (int64_t)g.NK * g.NI;
+  if (i >= g.NI) return;
+  if (kPhase == 0) {
+    int64_t q = base.x + xi;
+    P.ins_base[v] = q;
+    for (int e = 0; e < 3; ++e) {
+      const int32_t m = P.split[3 * v + e];
+      if (m < 0) continue;
+      const int64_t R1 = (m >> 1) / (g.CW + 2) - 1, C1 = (m >> 1) % (g.CW + 2) - 1;
+      double mx, my;
+      mid_point(d, g, (int)R1, (int)C1, m & 1, mx, my);
+      const int64_t id = nlat + q++;
+      if (id < P.vcap) {
+        P.verts[2 * id] = mx;
+        P.verts[2 * id + 1] = my;
+        P.on_polyline[id] = 1;
+      }
+    }
+    return;
+  }
+  // the inserted vertex of edge e of owner w: its owner's first index plus the
+  // split edges of that owner before e
+  auto ins_id = [&](int64_t w, int e) {
+    int64_t q = P.ins_base[w];
+    for (int f = 0; f < e; ++f) q += P.split[3 * w + f] >= 0 ? 1 : 0;
+    return nlat + q;
+  };
+  int64_t to = base.y + xt;
+  const int o = k & 1;
+  for (int t = 0; t < 2; ++t) {
+    if (!pre_slot_ok(g, k, i, t)) continue;
+    const int64_t c0 = v;
+    const int64_t c1 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o) : v + 1;
+    const int64_t c2 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o - 1) : (int64_t)(k + 1) * g.NI + (i + o);
+    const int64_t C[3] = {c0, c1, c2};
+    int js = -1;
+    int64_t m = -1;
+    for (int j = 0; j < 3; ++j) {
+      if (pre_edge_split(P, g, k, i, t, j) < 0) continue;
+      js = j;
+      // the owner and owned edge of corner edge j (as in pre_edge_split)
+      int64_t w;
+      int e;
+      if (t == 0) {
+        if (j == 0) { w = v; e = 2; }
+        else if (j == 1) { w = (int64_t)(k + 1) * g.NI + (i + o - 1); e = 0; }
+        else { w = v; e = 1; }
+      } else {
+        if (j == 0) { w = v; e = 0; }
+        else if (j == 1) { w = v + 1; e = 1; }
+        else { w = v; e = 2; }
+      }
+      m = ins_id(w, e);
+    }
+    auto put = [&](int64_t a, int64_t b, int64_t c) {
+      if (a < P.vcap && b < P.vcap && c < P.vcap) {  // else the call fails on capacity
+        const double ax = P.verts[2 * a], ay = P.verts[2 * a + 1];
+        const double area2 =
+            (P.verts[2 * b] - ax) * (P.verts[2 * c + 1] - ay) - (P.verts[2 * b + 1] - ay) * (P.verts[2 * c] - ax);
+        if (!(area2 > 0.0)) atomicOr((unsigned long long*)&P.counts[2], 1ull);
+      }
+      if (to < P.tcap) {
+        P.tris[3 * to] = (int32_t)a;
+        P.tris[3 * to + 1] = (int32_t)b;
+        P.tris[3 * to + 2] = (int32_t)c;
+      }
+      ++to;
+    };
+    if (js < 0) {
+      put(C[0], C[1], C[2]);
+    } else {  // the split edge (C[js], C[js+1]) fanned around the inserted vertex
+      const int64_t a0 = C[js], a1 = C[(js + 1) % 3], a2 = C[(js + 2) % 3];
+      put(a0, m, a2);
+      put(m, a1, a2);
+    }
+  }
+}
+
+__global__ void k_pre_clear(PreArgs P, int64_t nmid) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nmid; q += (int64_t)gridDim.x * blockDim.x)
+    P.mid[q] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x < 8) P.counts[threadIdx.x] = 0;
+}
+
+__global__ void k_pre_sizes(OneSrc src, PreArgs P, Shared sh, int64_t* out) {
+  const Geo g = src.d.g;
+  const longlong4 tot = sh.seg_off[sh.nseg];
+  out[0] = (int64_t)g.NK * g.NI + tot.x;  // vertices
+  out[1] = tot.y;                          // triangles
+  out[2] = P.counts[0];                    // snapped
+  out[3] = P.counts[1];                    // repelled
+  out[4] = tot.x;                          // inserted
+  out[5] = P.counts[2] ? SBMT_E_PROTOCOL : ((out[0] > P.vcap || out[1] > P.tcap) ? SBMT_E_CAPACITY : SBMT_OK);
+  if (out[0] > 0x7fffffffLL) out[5] = SBMT_E_INDEX_OVERFLOW;
+}
+
 __global__ void k_copy_sizes(const int64_t* __restrict__ s, int64_t n4, int64_t* __restrict__ user) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q < n4) user[q] = s[q];
 }
 
+// Workspace of the preprocessing: the meshing layout of the image, then the
+// per-midpoint words, per-owner split edges, counts and first inserted
+// indices, and the counters and sizes.
+struct PreLayout {
+  CallLayout L;
+  size_t off_mid, off_split, off_owner, off_ins, off_counts, off_out, total;
+  int64_t nmid, nown;
+};
+static sbmt_status pre_layout(const sbmt_image* img, bool need_ptr, PreLayout* P) {
+  sbmt_status st = make_call_layout(img, 1, 0, need_ptr, &P->L);
+  if (st != SBMT_OK) return st;
+  const Geo& g = P->L.g[0];
+  P->nmid = 2LL * (g.CH + 2) * (g.CW + 2);
+  P->nown = (int64_t)g.NK * g.NI;
+  if (P->nmid >= (1LL << 31)) return SBMT_E_INVALID_ARG;  // midpoint ids are int32
+  size_t off = align256(P->L.total);
+  P->off_mid = off;
+  off = align256(off + (size_t)P->nmid * 4);
+  P->off_split = off;
+  off = align256(off + (size_t)P->nown * 12);
+  P->off_owner = off;
+  off = align256(off + (size_t)P->nown * 4);
+  P->off_ins = off;
+  off = align256(off + (size_t)P->nown * 8);
+  P->off_counts = off;
+  off = align256(off + 8 * 8);
+  P->off_out = off;
+  off = align256(off + 8 * 8);
+  P->total = off;
+  return SBMT_OK;
+}
+static bool pre_thresholds_ok(double a, double b, double c, double h) {
+  if (!(a >= 0 && b >= 0 && c >= 0)) return false;
+  if (a == 0 && b == 0 && c == 0) return true;
+  return b < a / 2 && c * c < a * a / 2 && a < h / 2;
+}
+
 }  // namespace sbmt
+
 
 using namespace sbmt;
 
@@ -2588,6 +3012,72 @@ int32_t sbmt_class_code(int32_t class_id) {
   static const int32_t codes[] = {SBMT_CLASS_CODES_INIT};
   if (class_id < 1 || class_id > SBMT_NUM_CLASSES) return -1;
   return codes[class_id];
+}
+
+sbmt_status sbmt_pre_query(const sbmt_image* img, size_t* workspace_bytes, int64_t* vert_bound, int64_t* tri_bound) {
+  PreLayout P;
+  sbmt_status st = pre_layout(img, false, &P);
+  if (st != SBMT_OK) return st;
+  if (workspace_bytes) *workspace_bytes = P.total;
+  if (vert_bound) *vert_bound = P.nown + P.nmid;
+  if (tri_bound) *tri_bound = 4 * P.nown;
+  return SBMT_OK;
+}
+
+sbmt_status sbmt_preprocess(sbmt_handle h, const sbmt_image* img, double a, double b, double c, void* workspace,
+                            size_t ws_bytes, double* verts, uint8_t* on_polyline, int64_t vert_cap, int32_t* tris,
+                            int64_t tri_cap, int64_t* counts, void* stream) {
+  if (!h || !counts || vert_cap < 0 || tri_cap < 0) return SBMT_E_INVALID_ARG;
+  if ((vert_cap > 0 && (!verts || !on_polyline)) || (tri_cap > 0 && !tris)) return SBMT_E_INVALID_ARG;
+  PreLayout PL;
+  sbmt_status st = pre_layout(img, true, &PL);
+  if (st != SBMT_OK) return st;
+  const Geo& g = PL.L.g[0];
+  if (!pre_thresholds_ok(a, b, c, (double)g.h / g.U)) return SBMT_E_INVALID_ARG;
+  if (!workspace || ws_bytes < PL.total) return SBMT_E_WORKSPACE;
+  // every vertex of the lattice needs room before the kernels write it
+  if (vert_cap < PL.nown) return SBMT_E_CAPACITY;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)workspace;
+  const Shared sh = shared_of(PL.L, workspace, 1);
+  OneSrc src;
+  src.d = img_of(PL.L, 0, *img, workspace, nullptr);
+  PreArgs P;
+  P.a = a;
+  P.b = b;
+  P.c = c;
+  P.verts = verts;
+  P.on_polyline = on_polyline;
+  P.tris = tris;
+  P.vcap = vert_cap;
+  P.tcap = tri_cap;
+  P.mid = (uint32_t*)(w + PL.off_mid);
+  P.split = (int32_t*)(w + PL.off_split);
+  P.owner_n = (int32_t*)(w + PL.off_owner);
+  P.ins_base = (int64_t*)(w + PL.off_ins);
+  P.counts = (int64_t*)(w + PL.off_counts);
+  int64_t* out = (int64_t*)(w + PL.off_out);
+  const int64_t ncb = PL.L.tab[PL.L.n];
+  const int64_t nseg = PL.L.nseg;
+  const int64_t nb = (PL.nown + 255) / 256;
+  if (ncb > 0x7fffffffLL || nseg > 0x7fffffffLL || nb > 0x7fffffffLL) return SBMT_E_INVALID_ARG;
+  hipLaunchKernelGGL(k_coarsen<OneSrc>, dim3((unsigned)ncb), dim3(256), 0, s, src, (const int64_t*)nullptr, sh);
+  hipLaunchKernelGGL(k_pre_clear, dim3(1024), dim3(256), 0, s, P, PL.nmid);
+  hipLaunchKernelGGL(k_pre_vertices, dim3((unsigned)nb), dim3(256), 0, s, src, P);
+  hipLaunchKernelGGL(k_pre_edges, dim3((unsigned)nb), dim3(256), 0, s, src, P);
+  hipLaunchKernelGGL(k_pre_count, dim3((unsigned)nseg), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, sh);
+  hipLaunchKernelGGL(k_scan_apply, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
+  hipLaunchKernelGGL((k_pre_emit<0>), dim3((unsigned)nseg), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL((k_pre_emit<1>), dim3((unsigned)nseg), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_sizes, dim3(1), dim3(1), 0, s, src, P, sh, out);
+  if (hipGetLastError() != hipSuccess) return SBMT_E_DEVICE;
+  if (hipMemcpyAsync(h->pinned, out, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return SBMT_E_DEVICE;
+  for (int j = 0; j < 6; ++j) counts[j] = h->pinned[j];
+  return (sbmt_status)counts[5];
 }
 
 const char* sbmt_status_string(sbmt_status s) {

@@ -1,0 +1,224 @@
+"""GPU parity of the geometric preprocessing (Alg. 3, Sec. 3.5) through the C ABI
+(sbmt_preprocess) against the oracle's preprocessed grid.
+
+Decisions are exact: which lattice vertices snap (and onto which polyline
+vertex), which are repelled, which polyline vertices are inserted, and the
+triangles as vertex triples (inserted vertices are matched by their
+coordinates, which are exact half-integers; lattice vertices by index).
+Coordinates of moved vertices agree within 1e-9 px: both sides evaluate the
+same FP64 formulas without contraction, and a wrong term would move a vertex by
+a sizeable fraction of c.  Every case prints its name before touching the GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_19474_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-9
+
+
+def _pre():
+    from paper_2602_19474_amd import preprocess
+    return preprocess
+
+
+def _gpu(bm, h, th):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(bm, np.uint8)).to("cuda")
+    g = _pre().preprocess(t, h, *th)
+    torch.cuda.synchronize()
+    return g, g.verts.cpu().numpy(), g.on_polyline.cpu().numpy(), g.tris.cpu().numpy().astype(np.int64)
+
+
+def _canon(tris):
+    """Rotate each triangle to start at its smallest index (orientation kept), sort."""
+    if tris.shape[0] == 0:
+        return tris.reshape(0, 3)
+    r = np.argmin(tris, 1)
+    idx = (r[:, None] + np.arange(3)[None]) % 3
+    t = np.take_along_axis(tris, idx, 1)
+    return t[np.lexsort(t.T[::-1])]
+
+
+def _compare(name, bm, h, th=None):
+    print(f"[gpu-preprocess] {name} {bm.shape} h={h} th={th}", flush=True)
+    ref = oracle.preprocessed_grid(bm, h) if th is None else oracle.preprocessed_grid(bm, h, *th)
+    g, v, onp, tris = _gpu(bm, h, ref.thresholds)
+    assert (g.n_snapped, g.n_repelled, g.n_inserted) == (ref.n_snapped, ref.n_repelled, ref.n_inserted)
+    assert v.shape == ref.verts.shape and tris.shape == ref.tris.shape, (v.shape, ref.verts.shape)
+    n = v.shape[0] - g.n_inserted
+    assert np.array_equal(onp, np.concatenate([ref.on_polyline[:n], onp[n:]])) and onp[n:].all()
+    assert np.array_equal(ref.on_polyline[n:], np.ones(ref.verts.shape[0] - n, np.uint8))
+    dv = float(np.abs(v[:n] - ref.verts[:n]).max(initial=0.0))
+    assert dv <= TOL, dv
+    # unmoved and snapped lattice vertices are bitwise the oracle's
+    fixed = np.all(ref.verts[:n] == v[:n], 1)
+    assert fixed.sum() >= n - ref.n_repelled
+    # inserted vertices: the same set; map the GPU's onto the oracle's numbering
+    where = {tuple(p): j for j, p in enumerate(ref.verts[n:])}
+    assert len(where) == g.n_inserted
+    remap = np.arange(v.shape[0], dtype=np.int64)
+    for j, p in enumerate(v[n:]):
+        remap[n + j] = n + where[tuple(p)]
+    assert np.array_equal(_canon(remap[tris]), _canon(ref.tris)), "triangles differ"
+    return g
+
+
+@pytest.mark.parametrize("item", range(4))
+def test_disk64(item):
+    g = _compare(f"disk64#{item}", wl.disk(item=item), 1)
+    assert g.n_snapped > 0 and g.n_repelled > 0
+
+
+@pytest.mark.parametrize("h", [0.5, 1, 2, 4])
+def test_ellipses(h):
+    _compare("ellipses260x230", wl.ellipses(260, 230, g=wl.rng(97, int(4 * h))), h)
+
+
+@pytest.mark.parametrize("h,sigma", [(1, 2.0), (1, 4.0), (2, 3.0), (0.5, 1.5)])
+def test_smoothed_noise(h, sigma):
+    _compare(f"noise sigma={sigma}", wl.smoothed_noise(300, 280, sigma, 0.0, False, wl.rng(98, int(4 * h + sigma))), h)
+
+
+def test_ragged_and_degenerate_images():
+    g = wl.rng(99, 0)
+    _compare("ragged 97x61", wl.smoothed_noise(61, 97, 2.0, 0.0, False, g), 1)
+    _compare("empty", np.zeros((40, 50), np.uint8), 1)
+    _compare("full", np.ones((33, 45), np.uint8), 2)
+    _compare("one pixel", np.ones((1, 1), np.uint8), 1)
+    bm = np.zeros((64, 64), np.uint8)
+    bm[::2, ::2] = 1
+    _compare("checker", bm, 0.5)
+
+
+@pytest.mark.parametrize("h", [0.5, 1, 2])
+def test_zero_thresholds(h):
+    g = _compare("zero thresholds", wl.ellipses(200, 180, g=wl.rng(96, int(4 * h))), h, (0.0, 0.0, 0.0))
+    assert (g.n_snapped, g.n_repelled, g.n_inserted) == (0, 0, 0)
+
+
+def test_other_admissible_thresholds():
+    bm = wl.smoothed_noise(256, 256, 3.0, 0.0, False, wl.rng(95, 1))
+    for th in ((0.4, 0.19, 0.28), (0.3, 0.1, 0.05), (0.2, 0.0, 0.0), (0.45, 0.2, 0.3)):
+        _compare("thresholds", bm, 1, th)
+
+
+def test_refusals_and_capacity():
+    import torch
+    from paper_2602_19474_amd import _lib, context, _image, _stream_ptr
+    pre = _pre()
+    bm = torch.from_numpy(wl.disk(item=0)).to("cuda")
+    print("[gpu-preprocess] refusals", flush=True)
+    for th in ((0.4, 0.2, 0.1), (0.4, 0.1, 0.29), (0.5, 0.1, 0.1), (-0.1, 0.0, 0.0), (0.0, 0.1, 0.0)):
+        with pytest.raises(_lib.SbmtError) as e:
+            pre.preprocess(bm, 1, *th)
+        assert e.value.status == -1, th
+    ref = pre.preprocess(bm, 1)
+    nv, nt = ref.verts.shape[0], ref.tris.shape[0]
+    ws_bytes, vb, tb = pre.pre_query(bm.shape[1], bm.shape[0], 1)
+    assert nv <= vb and nt <= tb
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    L = _lib.lib()
+    img = _image(bm, 1, 0)
+    a, b, c = pre.paper_thresholds(1)
+    verts = torch.empty((nv, 2), dtype=torch.float64, device="cuda")
+    onp = torch.empty((nv,), dtype=torch.uint8, device="cuda")
+    tris = torch.empty((nt, 3), dtype=torch.int32, device="cuda")
+    counts = (ctypes.c_int64 * 6)()
+    h = context(0).handle
+    args = (h, ctypes.byref(img), a, b, c, ws.data_ptr())
+    # too small a workspace / lattice capacity: refused before any launch
+    assert L.sbmt_preprocess(*args, ws_bytes - 1, verts.data_ptr(), onp.data_ptr(), nv, tris.data_ptr(), nt,
+                             counts, _stream_ptr(None)) == -4
+    n_lat = nv - ref.n_inserted
+    assert L.sbmt_preprocess(*args, ws_bytes, verts.data_ptr(), onp.data_ptr(), n_lat - 1, tris.data_ptr(), nt,
+                             counts, _stream_ptr(None)) == -7
+    # too few triangle rows: capacity status with the counts filled in
+    assert L.sbmt_preprocess(*args, ws_bytes, verts.data_ptr(), onp.data_ptr(), nv, tris.data_ptr(), nt - 1,
+                             counts, _stream_ptr(None)) == -7
+    assert (counts[0], counts[1], counts[5]) == (nv, nt, -7)
+    # exact capacities: the same grid as the wrapper's
+    assert L.sbmt_preprocess(*args, ws_bytes, verts.data_ptr(), onp.data_ptr(), nv, tris.data_ptr(), nt,
+                             counts, _stream_ptr(None)) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(verts, ref.verts) and torch.equal(tris, ref.tris) and torch.equal(onp, ref.on_polyline)
+    assert list(counts) == [nv, nt, ref.n_snapped, ref.n_repelled, ref.n_inserted, 0]
+
+
+def test_full_size_noise8192_against_crops():
+    """The 8192 x 8192 noise workload at h = 1: invariants at full size, and the
+    interior of crops against the oracle on the crop (the three steps are local:
+    a crop whose left edge is a multiple of the stride and of h, and whose top
+    is the image's, has the same coarse samples, lattice and polyline away from
+    its cut edges)."""
+    import torch
+    import paper_2602_19474_amd as sbmt
+    pre = _pre()
+    bm_np = wl.noise8192()
+    H, W = bm_np.shape
+    lay = sbmt.query(W, H, 1)
+    NK, NI = lay.grid_rows, lay.grid_cols
+    print(f"[gpu-preprocess] noise8192 h=1 grid {NK}x{NI}", flush=True)
+    bm = torch.from_numpy(bm_np).to("cuda")
+    g = pre.preprocess(bm, 1)
+    torch.cuda.synchronize()
+    V, T, onp = g.verts, g.tris.long(), g.on_polyline
+    n = NK * NI
+    assert V.shape[0] == n + g.n_inserted
+    assert int(onp.sum()) == g.n_snapped + g.n_inserted
+    assert g.n_snapped > 10 ** 5 and g.n_repelled > 10 ** 5 and g.n_inserted > 10 ** 5
+    # every inserted vertex lies on an interior side: two triangles become four
+    assert T.shape[0] == 2 * (NK - 1) * (NI - 1) + 2 * g.n_inserted
+    assert int((T >= n).any(1).sum()) == 4 * g.n_inserted
+
+    def area2(tr):
+        A, B, C = V[tr[:, 0]], V[tr[:, 1]], V[tr[:, 2]]
+        return (B[:, 0] - A[:, 0]) * (C[:, 1] - A[:, 1]) - (B[:, 1] - A[:, 1]) * (C[:, 0] - A[:, 0])
+    ar = area2(T)
+    assert float(ar.min()) > 0
+    total = float(ar.sum())
+    del ar
+    # base triangles of the moved lattice, row by row
+    base_total = 0.0
+    i = torch.arange(NI - 1, device="cuda", dtype=torch.int64)
+    for k0 in range(0, NK - 1, 512):
+        k = torch.arange(k0, min(k0 + 512, NK - 1), device="cuda", dtype=torch.int64)[:, None]
+        o = k & 1
+        v = k * NI + i
+        ta = torch.stack([v, v + 1, (k + 1) * NI + i + o], -1).reshape(-1, 3)
+        ib = i + 1 - o  # Tb slots: i + o - 1 >= 0 and i + o < NI
+        tb = torch.stack([k * NI + ib, (k + 1) * NI + ib + o, (k + 1) * NI + ib + o - 1], -1).reshape(-1, 3)
+        base_total += float(area2(ta).sum()) + float(area2(tb).sum())
+    assert abs(total - base_total) <= 1e-12 * base_total, (total, base_total)
+    Vh, onph = V.cpu().numpy(), onp.cpu().numpy()
+    ins_full = Vh[n:]
+    for ox, wdt in ((4096, 384), (0, 256), (W - 384, 384)):
+        crop = np.ascontiguousarray(bm_np[:384, ox:ox + wdt])
+        print(f"[gpu-preprocess] crop x={ox} w={wdt}", flush=True)
+        ref = oracle.preprocessed_grid(crop, 1)
+        NKc, NIc, _ = oracle.mesh_from_bitmap(crop, 1).grid
+        lo = -np.inf if ox == 0 else 16.0
+        hi = np.inf if ox + wdt == W else wdt - 16.0
+        ymax = 384 - 16.0
+        nc_ = NKc * NIc
+        lat0 = ref.verts[:nc_]
+        kk = np.repeat(np.arange(NKc), NIc)
+        ii = np.tile(np.arange(NIc), NKc)
+        y_row = -1 + kk * 0.8660254037844386
+        sel = (lat0[:, 0] > lo) & (lat0[:, 0] < hi) & (y_row < ymax)
+        idx = kk[sel] * NI + ii[sel] + ox
+        assert sel.sum() > 1000
+        assert np.abs(Vh[idx] - (lat0[sel] + [float(ox), 0.0])).max() <= TOL
+        assert np.array_equal(onph[idx], ref.on_polyline[:nc_][sel])
+        ins = ref.verts[nc_:]
+        s1 = (ins[:, 0] > lo) & (ins[:, 0] < hi) & (ins[:, 1] < ymax)
+        want = {(x + ox, y) for x, y in ins[s1]}
+        s2 = (ins_full[:, 0] > lo + ox) & (ins_full[:, 0] < hi + ox) & (ins_full[:, 1] < ymax)
+        got = {tuple(p) for p in ins_full[s2]}
+        assert got == want and len(want) > 10, (len(got), len(want))

@@ -2101,12 +2101,15 @@ struct PreArgs {
   uint8_t* on_polyline;  // per vertex: sits on a polyline vertex
   int32_t* tris;         // [triangles][3]
   int64_t vcap, tcap;
-  uint32_t* mid;         // per midpoint: bit 31 snapped to, low bits edges it splits
-  int32_t* split;        // [NK NI][3]: midpoint splitting the owner's edge E0, E1, E2 (-1 none)
-  int32_t* owner_n;      // [NK NI]: inserted vertices | triangles << 8 of each owner
-  int64_t* ins_base;     // [NK NI]: first inserted vertex of each owner (index among the inserted)
-  int64_t* counts;       // [8]: snapped, repelled, error
+  uint32_t* mid;         // per midpoint: bit 31 snapped to, low bits sides it splits
+  uint8_t* flags;        // per lattice vertex: bits 0-2 owned side E0-E2 split, bit 3 moved
+  int32_t* split;        // [NK NI][3]: midpoint splitting side E0, E1, E2 (written where split)
+  int64_t* ins_base;     // [NK NI]: first inserted vertex of the owner (written where it has one)
+  int64_t* counts;       // [8 + 512]: [2] error; from kPreTally 256 counters of snapped, then of repelled vertices
 };
+constexpr uint8_t kPreMoved = 8;
+constexpr int kPreTally = 8;
+constexpr int kPreCounts = kPreTally + 512;
 
 // Midpoint ids: horizontal midpoint between samples (R, C) and (R, C+1) is
 // 2 ((R + 1)(CW + 2) + C + 1), the vertical one between (R, C) and (R+1, C)
@@ -2119,11 +2122,13 @@ __device__ __forceinline__ int sample_at(const Img& d, const Geo& g, int R, int 
   const int rr = R + kRing, cc = C + kRingC;
   return (int)((d.bits[(int64_t)rr * g.wpr + (cc >> 5)] >> (cc & 31)) & 1u);
 }
+// Sample (R, C) sits at pixel (s C + (s-1)/2, s R + (s-1)/2); the offset:
+__device__ __forceinline__ double sample_off(const Geo& g) { return 0.5 * (g.s - 1); }
 // Midpoint (R, C, vert) in pixels, and whether it is a polyline vertex.
 __device__ __forceinline__ bool mid_point(const Img& d, const Geo& g, int R, int C, int vert, double& x, double& y) {
   const double half = 0.5 * g.s;
-  x = (double)g.s * C + 0.5 * (g.s - 1) + (vert ? 0.0 : half);
-  y = (double)g.s * R + 0.5 * (g.s - 1) + (vert ? half : 0.0);
+  x = (double)g.s * C + sample_off(g) + (vert ? 0.0 : half);
+  y = (double)g.s * R + sample_off(g) + (vert ? half : 0.0);
   if (R < -1 || R > g.CH || C < -1 || C > g.CW) return false;
   return sample_at(d, g, R, C) != sample_at(d, g, vert ? R + 1 : R, vert ? C : C + 1);
 }
@@ -2137,93 +2142,157 @@ __device__ __forceinline__ double seg_dist_d(double x, double y, double px, doub
   return euclid_d(x - (px + t * dx), y - (py + t * dy));
 }
 __device__ __forceinline__ int nearest_index(const Geo& g, double v) {
-  return (int)__builtin_floor((v - 0.5 * (g.s - 1)) / g.s + 0.5);
+  return (int)__builtin_floor((v - sample_off(g)) / g.s + 0.5);
+}
+__device__ __forceinline__ int floor_index(const Geo& g, double v) {
+  return (int)__builtin_floor((v - sample_off(g)) / g.s);
 }
 
-// Steps 1 and 2, one thread per lattice vertex.
+// Coarse samples R0 .. R0 + NR - 1 x C0 .. C0 + 31 of the stored raster as row
+// masks (bit j of row r: sample (R0 + r, C0 + j)); background outside it.
+template <int NR>
+__device__ __forceinline__ void load_block(const Img& d, const Geo& g, int R0, int C0, int nr, uint32_t (&rw)[NR]) {
+  const int cc = C0 + kRingC;
+  const int w0 = cc >> 5, sh = cc & 31;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int R = R0 + r;
+    uint32_t w = 0;
+    if (r < nr && R >= -kRing && R < g.CH + kRing) {
+      const uint32_t* row = d.bits + (int64_t)(R + kRing) * g.wpr;
+      const uint64_t lo = (w0 >= 0 && w0 < g.wpr) ? row[w0] : 0u;
+      const uint64_t hi = (w0 + 1 >= 0 && w0 + 1 < g.wpr) ? row[w0 + 1] : 0u;
+      w = (uint32_t)((((hi << 32) | lo) >> sh));
+    }
+    rw[r] = w;
+  }
+}
+// thresholds widened by a relative and absolute margin far above the rounding
+// of the box bounds, so that a box never misses a candidate
+__device__ __forceinline__ double widen(double r) { return r * (1.0 + 1e-12) + 1e-9; }
+// Segment j of marching-squares case cs of dual cell (R, C): end points in pixels.
+__device__ __forceinline__ void cell_segment(const Geo& g, int R, int C, uint32_t ms, int j, double& px, double& py,
+                                             double& qx, double& qy) {
+  const int ea = (int)((ms >> (2 + 4 * j)) & 3u), eb = (int)((ms >> (4 + 4 * j)) & 3u);
+  // cell edges: 0 top, 1 right, 2 bottom, 3 left (midpoints relative to the TL sample, in s/2)
+  const double x0 = (double)g.s * C + sample_off(g), y0 = (double)g.s * R + sample_off(g), hs = 0.5 * g.s;
+  px = x0 + (ea == 0 || ea == 2 ? hs : (ea == 1 ? 2.0 * hs : 0.0));
+  py = y0 + (ea == 1 || ea == 3 ? hs : (ea == 2 ? 2.0 * hs : 0.0));
+  qx = x0 + (eb == 0 || eb == 2 ? hs : (eb == 1 ? 2.0 * hs : 0.0));
+  qy = y0 + (eb == 1 || eb == 3 ? hs : (eb == 2 ? 2.0 * hs : 0.0));
+}
+
+// Steps 1 and 2, one thread per lattice vertex, from the 4 x 4 coarse samples
+// around it (rows and columns floor_index - 1 .. + 2).  Polyline vertices of
+// one orientation form a grid of spacing s > 2a, so only the nearest midpoint
+// of each orientation can lie within a; a segment within c < s/2 lies in one
+// of the 3 x 3 dual cells around the vertex.  A vertex whose 16 samples agree
+// stays where the lattice put it.
 __global__ void __launch_bounds__(256) k_pre_vertices(OneSrc src, PreArgs P) {
   const Img& d = src.d;
   const Geo g = d.g;
   const int64_t n = (int64_t)g.NK * g.NI;
   const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (v >= n) return;
+  int kind = 0;  // 1 snapped, 2 repelled
+  if (v < n) {
   const int k = (int)(v / g.NI), i = (int)(v - (int64_t)k * g.NI);
   double x = lat_x(g, g.X0 + 4 * g.h * i + 2 * g.h * (k & 1)), y = lat_y(g, k);
-  const int Rc = nearest_index(g, y), Cc = nearest_index(g, x);
-  // Step 1: the polyline vertex within a (at most one)
-  double best = P.a;
-  int64_t bj = -1;
-  double bx = 0, by = 0;
-  for (int R = Rc - 1; R <= Rc + 1; ++R)
-    for (int C = Cc - 1; C <= Cc + 1; ++C)
-      for (int vt = 0; vt < 2; ++vt) {
-        double mx, my;
-        if (!mid_point(d, g, R, C, vt, mx, my)) continue;
+  uint8_t onp = 0, fl = 0;
+  const int Rd = floor_index(g, y), Cd = floor_index(g, x);
+  uint32_t rw[4];
+  load_block<4>(d, g, Rd - 1, Cd - 1, 4, rw);
+  const uint32_t all = (rw[0] & 15u) | ((rw[1] & 15u) << 4) | ((rw[2] & 15u) << 8) | ((rw[3] & 15u) << 12);
+  if (P.a > 0.0 && all != 0u && all != 0xffffu) {
+    auto S = [&](int R, int C) { return (int)((rw[R - Rd + 1] >> (C - Cd + 1)) & 1u); };
+    // Step 1: the polyline vertex within a (at most one)
+    double best = P.a;
+    int nbest = 0;
+    int64_t bj = -1;
+    double bx = 0, by = 0;
+    {
+      const int R = nearest_index(g, y);  // horizontal midpoint (R, Cd) - (R, Cd + 1)
+      if (S(R, Cd) != S(R, Cd + 1)) {
+        const double mx = (double)g.s * Cd + sample_off(g) + 0.5 * g.s, my = (double)g.s * R + sample_off(g);
         const double dd = euclid_d(x - mx, y - my);
-        if (dd < best) {
+        if (dd < P.a) {
+          ++nbest;
           best = dd;
-          bj = mid_id(g, R, C, vt);
+          bj = mid_id(g, R, Cd, 0);
           bx = mx;
           by = my;
         }
       }
-  uint8_t onp = 0;
-  if (bj >= 0) {
-    x = bx;
-    y = by;
-    onp = 1;
-    atomicOr(&P.mid[bj], 0x80000000u);
-    atomicAdd((unsigned long long*)&P.counts[0], 1ull);
-  } else if (P.c > 0.0) {
-    // Step 2: the segment within c (at most one), of the dual cells around v
-    const int Rd = (int)__builtin_floor((y - 0.5 * (g.s - 1)) / g.s), Cd = (int)__builtin_floor((x - 0.5 * (g.s - 1)) / g.s);
-    int nclose = 0;
-    double spx = 0, spy = 0, sqx = 0, sqy = 0, st = 0;
-    for (int R = Rd - 1; R <= Rd + 1; ++R)
-      for (int C = Cd - 1; C <= Cd + 1; ++C) {
-        const int cs = sample_at(d, g, R, C) | (sample_at(d, g, R, C + 1) << 1) | (sample_at(d, g, R + 1, C + 1) << 2) |
-                       (sample_at(d, g, R + 1, C) << 3);
-        const uint32_t ms = ms_case(cs);
-        for (int j = 0; j < (int)(ms & 3u); ++j) {
-          const int ea = (int)((ms >> (2 + 4 * j)) & 3u), eb = (int)((ms >> (4 + 4 * j)) & 3u);
-          // cell edges: 0 top, 1 right, 2 bottom, 3 left
-          double px, py, qx, qy;
-          mid_point(d, g, ea == 2 ? R + 1 : R, ea == 1 ? C + 1 : C, ea & 1, px, py);
-          mid_point(d, g, eb == 2 ? R + 1 : R, eb == 1 ? C + 1 : C, eb & 1, qx, qy);
-          double t;
-          if (seg_dist_d(x, y, px, py, qx, qy, &t) < P.c) {
-            ++nclose;
-            spx = px;
-            spy = py;
-            sqx = qx;
-            sqy = qy;
-            st = t;
+      const int C = nearest_index(g, x);  // vertical midpoint (Rd, C) - (Rd + 1, C)
+      if (S(Rd, C) != S(Rd + 1, C)) {
+        const double mx = (double)g.s * C + sample_off(g), my = (double)g.s * Rd + sample_off(g) + 0.5 * g.s;
+        const double dd = euclid_d(x - mx, y - my);
+        if (dd < P.a) {
+          ++nbest;
+          if (dd < best) {
+            best = dd;
+            bj = mid_id(g, Rd, C, 1);
+            bx = mx;
+            by = my;
           }
         }
       }
-    if (nclose > 1 || (nclose == 1 && !(st > 0.0 && st < 1.0))) atomicOr((unsigned long long*)&P.counts[2], 1ull);
-    if (nclose == 1) {
-      const double dx = sqx - spx, dy = sqy - spy, L = euclid_d(dx, dy);
-      const double nx = -dy / L, ny = dx / L;                 // left normal
-      const double ds = (x - spx) * nx + (y - spy) * ny;      // signed distance to the line
-      const double move = (ds > 0 ? P.c : -P.c) - ds;
-      x += move * nx;
-      y += move * ny;
-      atomicAdd((unsigned long long*)&P.counts[1], 1ull);
+    }
+    if (nbest > 1) atomicOr((unsigned long long*)&P.counts[2], 1ull);
+    if (bj >= 0) {
+      x = bx;
+      y = by;
+      onp = 1;
+      fl = kPreMoved;
+      atomicOr(&P.mid[bj], 0x80000000u);
+      kind = 1;
+    } else if (P.c > 0.0) {
+      // Step 2: the segment within c (at most one)
+      int nclose = 0;
+      double spx = 0, spy = 0, sqx = 0, sqy = 0, st = 0;
+      for (int R = Rd - 1; R <= Rd + 1; ++R)
+        for (int C = Cd - 1; C <= Cd + 1; ++C) {
+          const int cs = S(R, C) | (S(R, C + 1) << 1) | (S(R + 1, C + 1) << 2) | (S(R + 1, C) << 3);
+          if (cs == 0 || cs == 15) continue;
+          const uint32_t ms = ms_case(cs);
+          for (int j = 0; j < (int)(ms & 3u); ++j) {
+            double px, py, qx, qy, t;
+            cell_segment(g, R, C, ms, j, px, py, qx, qy);
+            if (seg_dist_d(x, y, px, py, qx, qy, &t) < P.c) {
+              ++nclose;
+              spx = px;
+              spy = py;
+              sqx = qx;
+              sqy = qy;
+              st = t;
+            }
+          }
+        }
+      if (nclose > 1 || (nclose == 1 && !(st > 0.0 && st < 1.0))) atomicOr((unsigned long long*)&P.counts[2], 1ull);
+      if (nclose == 1) {
+        const double dx = sqx - spx, dy = sqy - spy, L = euclid_d(dx, dy);
+        const double nx = -dy / L, ny = dx / L;             // left normal
+        const double ds = (x - spx) * nx + (y - spy) * ny;  // signed distance to the line
+        const double move = (ds > 0 ? P.c : -P.c) - ds;
+        x += move * nx;
+        y += move * ny;
+        fl = kPreMoved;
+        kind = 2;
+      }
     }
   }
   if (v < P.vcap) {
-    P.verts[2 * v] = x;
-    P.verts[2 * v + 1] = y;
+    reinterpret_cast<double2*>(P.verts)[v] = make_double2(x, y);
     P.on_polyline[v] = onp;
   }
-}
-
-// Lattice vertex of a possibly moved grid (after k_pre_vertices).
-__device__ __forceinline__ void pre_vertex(const PreArgs& P, const Geo& g, int k, int i, double& x, double& y) {
-  const int64_t v = (int64_t)k * g.NI + i;
-  x = P.verts[2 * v];
-  y = P.verts[2 * v + 1];
+  P.flags[v] = fl;
+  }
+  // one atomic per wave, spread over 256 counters (summed by k_pre_sizes)
+  const unsigned long long bs = __ballot(kind == 1), br = __ballot(kind == 2);
+  if ((threadIdx.x & 63) == 0) {
+    const int slot = (int)((blockIdx.x * 4 + (threadIdx.x >> 6)) & 255u);
+    if (bs) atomicAdd((unsigned long long*)&P.counts[kPreTally + slot], (unsigned long long)__popcll(bs));
+    if (br) atomicAdd((unsigned long long*)&P.counts[kPreTally + 256 + slot], (unsigned long long)__popcll(br));
+  }
 }
 
 // Base triangle slot t of owner (k, i) exists (all three corners in the lattice).
@@ -2231,7 +2300,7 @@ __device__ __forceinline__ bool pre_slot_ok(const Geo& g, int k, int i, int t) {
   const int o = k & 1;
   return t == 0 ? (k + 1 < g.NK && i + o - 1 >= 0 && i + o < g.NI) : (k + 1 < g.NK && i + 1 < g.NI && i + o < g.NI);
 }
-// Owned edge e of (k, i) is a side of some base triangle: E0 of Ta(k, i) or of
+// Owned side e of (k, i) is a side of some base triangle: E0 of Ta(k, i) or of
 // Tb of the owner above whose lower side it is, E1 of Tb(k, i) or of
 // Ta(k, i-1), E2 of either triangle of (k, i).
 __device__ __forceinline__ bool pre_edge_live(const Geo& g, int k, int i, int e) {
@@ -2244,85 +2313,137 @@ __device__ __forceinline__ bool pre_edge_live(const Geo& g, int k, int i, int e)
 }
 
 // Step 3, one thread per owner: the free polyline vertex (no lattice vertex
-// snapped to it) within b of each owned edge E0 -> (k, i+1), E1 -> (k+1, i+o-1),
-// E2 -> (k+1, i+o).
+// snapped to it) within b of each owned side E0 -> (k, i+1), E1 -> (k+1, i+o-1),
+// E2 -> (k+1, i+o).  Every vertex moved by less than a, so the candidates are
+// the polyline vertices of the box around the owner's three sides on the
+// lattice widened by a + b: at most 5 x 4 coarse samples (its width is below
+// 3h < 2.2 s, its height below 2.4h < 1.7 s).
+constexpr int kPreRows = 6;
 __global__ void __launch_bounds__(256) k_pre_edges(OneSrc src, PreArgs P) {
   const Img& d = src.d;
   const Geo g = d.g;
   const int64_t n = (int64_t)g.NK * g.NI;
   const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (v >= n) return;
+  if (v >= n || !(P.b > 0.0)) return;
   const int k = (int)(v / g.NI), i = (int)(v - (int64_t)k * g.NI), o = k & 1;
-  double ux, uy;
-  pre_vertex(P, g, k, i, ux, uy);
+  const double hx = (double)g.h / g.U;
+  const double lx = lat_x(g, g.X0 + 4 * g.h * i + 2 * g.h * o), ly = lat_y(g, k);
+  const double r = widen(P.a + P.b);
+  const double X0 = lx - 0.5 * hx - r, X1 = lx + hx + r, Y0 = ly - r, Y1 = lat_y(g, k + 1) + r;
+  const int R0 = floor_index(g, Y0), C0 = floor_index(g, X0);
+  const int nr = floor_index(g, Y1) + 2 - R0, nc = floor_index(g, X1) + 2 - C0;
+  if (nr > kPreRows || nc > 31) {  // outside the admissible thresholds
+    atomicOr((unsigned long long*)&P.counts[2], 1ull);
+    return;
+  }
+  uint32_t rw[kPreRows];
+  load_block<kPreRows>(d, g, R0, C0, nr, rw);
+  const uint32_t mh = (1u << (nc - 1)) - 1u, mv = (1u << nc) - 1u;
+  uint32_t any = 0;
+  for (int q = 0; q < nr; ++q) {
+    any |= (rw[q] ^ (rw[q] >> 1)) & mh;
+    if (q + 1 < nr) any |= (rw[q] ^ rw[q + 1]) & mv;
+  }
+  if (!any) return;
+  // the owner's live sides on the moved vertices
+  double ex[3][2], ey[3][2];
+  bool live[3];
+  const double2 U = reinterpret_cast<const double2*>(P.verts)[v];
   for (int e = 0; e < 3; ++e) {
+    live[e] = pre_edge_live(g, k, i, e);
     const int kw = e == 0 ? k : k + 1, iw = e == 0 ? i + 1 : (e == 1 ? i + o - 1 : i + o);
-    int32_t hit = -1;
-    if (P.b > 0.0 && pre_edge_live(g, k, i, e)) {
-      double wx, wy;
-      pre_vertex(P, g, kw, iw, wx, wy);
-      const int Rc = nearest_index(g, 0.5 * (uy + wy)), Cc = nearest_index(g, 0.5 * (ux + wx));
-      int nh = 0;
-      for (int R = Rc - 2; R <= Rc + 2; ++R)
-        for (int C = Cc - 2; C <= Cc + 2; ++C)
-          for (int vt = 0; vt < 2; ++vt) {
-            double mx, my;
-            if (!mid_point(d, g, R, C, vt, mx, my)) continue;
-            const int64_t id = mid_id(g, R, C, vt);
-            if (P.mid[id] & 0x80000000u) continue;  // a lattice vertex sits on it
-            // both orientations, as the edge's two triangles see it
-            if (seg_dist_d(mx, my, ux, uy, wx, wy, nullptr) < P.b || seg_dist_d(mx, my, wx, wy, ux, uy, nullptr) < P.b) {
-              ++nh;
-              hit = (int32_t)id;
-            }
+    double2 Wv = make_double2(0.0, 0.0);
+    if (live[e]) Wv = reinterpret_cast<const double2*>(P.verts)[(int64_t)kw * g.NI + iw];
+    ex[e][0] = U.x;
+    ey[e][0] = U.y;
+    ex[e][1] = Wv.x;
+    ey[e][1] = Wv.y;
+  }
+  int nh[3] = {0, 0, 0};
+  int32_t hit[3] = {-1, -1, -1};
+  for (int q = 0; q < nr; ++q) {
+    for (int vt = 0; vt < 2; ++vt) {
+      uint32_t bits = vt == 0 ? ((rw[q] ^ (rw[q] >> 1)) & mh) : (q + 1 < nr ? ((rw[q] ^ rw[q + 1]) & mv) : 0u);
+      while (bits) {
+        const int j = __builtin_ctz(bits);
+        bits &= bits - 1u;
+        const int R = R0 + q, C = C0 + j;
+        const double mx = (double)g.s * C + sample_off(g) + (vt ? 0.0 : 0.5 * g.s);
+        const double my = (double)g.s * R + sample_off(g) + (vt ? 0.5 * g.s : 0.0);
+        if (mx < X0 || mx > X1 || my < Y0 || my > Y1) continue;
+        const int64_t id = mid_id(g, R, C, vt);
+        if (P.mid[id] & 0x80000000u) continue;  // a lattice vertex sits on it
+        for (int e = 0; e < 3; ++e) {
+          if (!live[e]) continue;
+          const double ux = ex[e][0], uy = ey[e][0], wx = ex[e][1], wy = ey[e][1];
+          // both orientations, as the side's two triangles see it
+          if (seg_dist_d(mx, my, ux, uy, wx, wy, nullptr) < P.b || seg_dist_d(mx, my, wx, wy, ux, uy, nullptr) < P.b) {
+            ++nh[e];
+            hit[e] = (int32_t)id;
           }
-      if (nh > 1) atomicOr((unsigned long long*)&P.counts[2], 1ull);
-      if (hit >= 0 && (atomicAdd(&P.mid[hit], 1u) & 0x7fffffffu) != 0u) atomicOr((unsigned long long*)&P.counts[2], 1ull);
+        }
+      }
     }
-    P.split[3 * v + e] = hit;
   }
+  uint8_t fbits = 0;
+  for (int e = 0; e < 3; ++e) {
+    if (nh[e] > 1) atomicOr((unsigned long long*)&P.counts[2], 1ull);
+    if (hit[e] < 0) continue;
+    if ((atomicAdd(&P.mid[hit[e]], 1u) & 0x7fffffffu) != 0u) atomicOr((unsigned long long*)&P.counts[2], 1ull);
+    P.split[3 * v + e] = hit[e];
+    fbits |= (uint8_t)(1u << e);
+  }
+  if (fbits) P.flags[v] |= fbits;
 }
 
-// Triangle slots of owner (k, i): Tb = [v, vdr, vdl], Ta = [v, vr, vdr].  For
-// slot t and its side j (corner j to corner j+1) the midpoint splitting it (or
-// -1), read from the owner of that side: Tb sides are E2 of v, E0 of vdl, E1
-// of v; Ta sides E0 of v, E1 of vr, E2 of v.
-__device__ __forceinline__ int32_t pre_edge_split(const PreArgs& P, const Geo& g, int k, int i, int t, int j) {
+// Split sides of the two slots of owner (k, i), from the owners of the sides:
+// Tb = [v, vdr, vdl] has sides E2 of v, E0 of vdl, E1 of v; Ta = [v, vr, vdr]
+// has E0 of v, E1 of vr, E2 of v.  Bit j of slot t: side j (corner j to j+1).
+struct PreSlots {
+  int ok[2];
+  uint32_t sides[2];
+  bool moved[2];
+};
+__device__ __forceinline__ PreSlots pre_slots(const PreArgs& P, const Geo& g, int k, int i) {
+  PreSlots S;
   const int o = k & 1;
-  int64_t w;
-  int e;
-  if (t == 0) {  // Tb: v -> vdr (E2 of v), vdr -> vdl (E0 of vdl), vdl -> v (E1 of v)
-    if (j == 0) { w = (int64_t)k * g.NI + i; e = 2; }
-    else if (j == 1) { w = (int64_t)(k + 1) * g.NI + (i + o - 1); e = 0; }
-    else { w = (int64_t)k * g.NI + i; e = 1; }
-  } else {  // Ta: v -> vr (E0 of v), vr -> vdr (E1 of vr), vdr -> v (E2 of v)
-    if (j == 0) { w = (int64_t)k * g.NI + i; e = 0; }
-    else if (j == 1) { w = (int64_t)k * g.NI + i + 1; e = 1; }
-    else { w = (int64_t)k * g.NI + i; e = 2; }
+  const int64_t v = (int64_t)k * g.NI + i;
+  const uint32_t fv = P.flags[v];
+  S.ok[0] = pre_slot_ok(g, k, i, 0);
+  S.ok[1] = pre_slot_ok(g, k, i, 1);
+  S.sides[0] = S.sides[1] = 0;
+  S.moved[0] = S.moved[1] = false;
+  const uint32_t fdr = (S.ok[0] || S.ok[1]) ? P.flags[(int64_t)(k + 1) * g.NI + i + o] : 0u;
+  if (S.ok[0]) {
+    const uint32_t fdl = P.flags[(int64_t)(k + 1) * g.NI + i + o - 1];
+    S.sides[0] = ((fv >> 2) & 1u) | ((fdl & 1u) << 1) | (((fv >> 1) & 1u) << 2);
+    S.moved[0] = ((fv | fdr | fdl) & kPreMoved) != 0;
   }
-  return P.split[3 * w + e];
+  if (S.ok[1]) {
+    const uint32_t fr = P.flags[v + 1];
+    S.sides[1] = (fv & 1u) | (((fr >> 1) & 1u) << 1) | (((fv >> 2) & 1u) << 2);
+    S.moved[1] = ((fv | fr | fdr) & kPreMoved) != 0;
+  }
+  return S;
 }
 
-// Per owner: inserted vertices (its split edges) and triangles (its slots, two
-// for a slot with a split edge); per row segment (the block) their sums.
+// Per row segment (one block, one owner per thread): inserted vertices (split
+// sides owned) and triangles (one per slot, two for a slot with a split side).
 __global__ void __launch_bounds__(256) k_pre_count(OneSrc src, PreArgs P, Shared sh) {
   __shared__ int part[2][4];
-  const Img& d = src.d;
-  const Geo g = d.g;
+  const Geo g = src.d.g;
   const int k = (int)(blockIdx.x / g.NCB), cb = (int)(blockIdx.x - (int64_t)k * g.NCB);
   const int i = cb * kCB + (int)threadIdx.x;
   int ni = 0, nt = 0;
   if (i < g.NI) {
-    const int64_t v = (int64_t)k * g.NI + i;
-    for (int e = 0; e < 3; ++e) ni += P.split[3 * v + e] >= 0 ? 1 : 0;
+    const PreSlots S = pre_slots(P, g, k, i);
+    ni = __builtin_popcount(P.flags[(int64_t)k * g.NI + i] & 7u);
     for (int t = 0; t < 2; ++t) {
-      if (!pre_slot_ok(g, k, i, t)) continue;
-      int ns = 0;
-      for (int j = 0; j < 3; ++j) ns += pre_edge_split(P, g, k, i, t, j) >= 0 ? 1 : 0;
+      if (!S.ok[t]) continue;
+      const int ns = __builtin_popcount(S.sides[t]);
       if (ns > 1) atomicOr((unsigned long long*)&P.counts[2], 1ull);
       nt += ns ? 2 : 1;
     }
-    P.owner_n[v] = ni | (nt << 8);
   }
   const int lane = threadIdx.x & 63;
   const int si = __builtin_amdgcn_readlane(wave_incl_scan_dpp(ni), 63);
@@ -2339,123 +2460,138 @@ __global__ void __launch_bounds__(256) k_pre_count(OneSrc src, PreArgs P, Shared
   }
 }
 
-// Inserted vertices and triangles at their offsets (row segment bases from the
-// scan, owner offsets by a block scan).  Phase 0 writes the inserted vertices
-// and each owner's first inserted index; phase 1 the triangles.
-__device__ __forceinline__ void block_scan256(int& x, int* tmp) {
+// Exclusive block scan of 256 values (four waves); returns the block total.
+__device__ __forceinline__ int block_scan256(int& x, int* tmp) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int incl = wave_incl_scan_dpp(x);
   if (lane == 63) tmp[wv] = incl;
   __syncthreads();
   int before = 0;
   for (int w = 0; w < wv; ++w) before += tmp[w];
-  x = before + incl - x;  // exclusive
+  const int total = tmp[0] + tmp[1] + tmp[2] + tmp[3];
+  x = before + incl - x;
   __syncthreads();
+  return total;
 }
-template <int kPhase>
-__global__ void __launch_bounds__(256) k_pre_emit(OneSrc src, PreArgs P, Shared sh) {
+
+// Inserted vertices at their offsets (row segment base from the scan, owner
+// offset by a block scan), and the first inserted index of each owner that has one.
+__global__ void __launch_bounds__(256) k_pre_inserted(OneSrc src, PreArgs P, Shared sh) {
   __shared__ int tmp[4];
   const Img& d = src.d;
   const Geo g = d.g;
   const int k = (int)(blockIdx.x / g.NCB), cb = (int)(blockIdx.x - (int64_t)k * g.NCB);
   const int i = cb * kCB + (int)threadIdx.x;
   const int64_t v = (int64_t)k * g.NI + i;
-  const int on = i < g.NI ? P.owner_n[v] : 0;
-  int xi = on & 0xff, xt = on >> 8;
-  block_scan256(xi, tmp);
-  block_scan256(xt, tmp);
-  const longlong4 base = sh.seg_off[blockIdx.x];
+  const uint32_t f = i < g.NI ? (P.flags[v] & 7u) : 0u;
+  int xi = __builtin_popcount(f);
+  if (block_scan256(xi, tmp) == 0 || f == 0u) return;
   const int64_t nlat = (int64_t)g.NK * g.NI;
-  if (i >= g.NI) return;
-  if (kPhase == 0) {
-    int64_t q = base.x + xi;
-    P.ins_base[v] = q;
-    for (int e = 0; e < 3; ++e) {
-      const int32_t m = P.split[3 * v + e];
-      if (m < 0) continue;
-      const int64_t R1 = (m >> 1) / (g.CW + 2) - 1, C1 = (m >> 1) % (g.CW + 2) - 1;
-      double mx, my;
-      mid_point(d, g, (int)R1, (int)C1, m & 1, mx, my);
-      const int64_t id = nlat + q++;
-      if (id < P.vcap) {
-        P.verts[2 * id] = mx;
-        P.verts[2 * id + 1] = my;
-        P.on_polyline[id] = 1;
-      }
+  int64_t q = sh.seg_off[blockIdx.x].x + xi;
+  P.ins_base[v] = q;
+  for (int e = 0; e < 3; ++e) {
+    if (!((f >> e) & 1u)) continue;
+    const int32_t m = P.split[3 * v + e];
+    const int R = (m >> 1) / (g.CW + 2) - 1, C = (m >> 1) % (g.CW + 2) - 1;
+    double mx, my;
+    mid_point(d, g, R, C, m & 1, mx, my);
+    const int64_t id = nlat + q++;
+    if (id < P.vcap) {
+      reinterpret_cast<double2*>(P.verts)[id] = make_double2(mx, my);
+      P.on_polyline[id] = 1;
     }
-    return;
   }
-  // the inserted vertex of edge e of owner w: its owner's first index plus the
-  // split edges of that owner before e
-  auto ins_id = [&](int64_t w, int e) {
-    int64_t q = P.ins_base[w];
-    for (int f = 0; f < e; ++f) q += P.split[3 * w + f] >= 0 ? 1 : 0;
-    return nlat + q;
-  };
-  int64_t to = base.y + xt;
+}
+
+// Triangles of each row segment, staged in LDS and written as one contiguous
+// run.  A slot with a split side j (corners a0 -> a1, opposite a2) becomes
+// (a0, m, a2), (m, a1, a2) around the inserted vertex m.  Triangles with a
+// moved or inserted corner are checked for positive orientation.
+__global__ void __launch_bounds__(256) k_pre_triangles(OneSrc src, PreArgs P, Shared sh) {
+  __shared__ int tmp[4];
+  __shared__ int32_t stage[3 * 4 * kCB];
+  const Geo g = src.d.g;
+  const int k = (int)(blockIdx.x / g.NCB), cb = (int)(blockIdx.x - (int64_t)k * g.NCB);
+  const int i = cb * kCB + (int)threadIdx.x;
+  const int64_t v = (int64_t)k * g.NI + i;
   const int o = k & 1;
-  for (int t = 0; t < 2; ++t) {
-    if (!pre_slot_ok(g, k, i, t)) continue;
-    const int64_t c0 = v;
-    const int64_t c1 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o) : v + 1;
-    const int64_t c2 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o - 1) : (int64_t)(k + 1) * g.NI + (i + o);
-    const int64_t C[3] = {c0, c1, c2};
-    int js = -1;
-    int64_t m = -1;
-    for (int j = 0; j < 3; ++j) {
-      if (pre_edge_split(P, g, k, i, t, j) < 0) continue;
-      js = j;
-      // the owner and owned edge of corner edge j (as in pre_edge_split)
+  PreSlots S;
+  int nt = 0;
+  if (i < g.NI) {
+    S = pre_slots(P, g, k, i);
+    for (int t = 0; t < 2; ++t) nt += S.ok[t] ? (S.sides[t] ? 2 : 1) : 0;
+  }
+  int xt = nt;
+  const int total = block_scan256(xt, tmp);
+  const int64_t nlat = (int64_t)g.NK * g.NI;
+  if (i < g.NI) {
+    int q = xt;
+    auto put = [&](int64_t a, int64_t b, int64_t c, bool check) {
+      if (check && a < P.vcap && b < P.vcap && c < P.vcap) {  // else the call fails on capacity
+        const double2 A = reinterpret_cast<const double2*>(P.verts)[a];
+        const double2 B = reinterpret_cast<const double2*>(P.verts)[b];
+        const double2 C = reinterpret_cast<const double2*>(P.verts)[c];
+        const double area2 = (B.x - A.x) * (C.y - A.y) - (B.y - A.y) * (C.x - A.x);
+        if (!(area2 > 0.0)) atomicOr((unsigned long long*)&P.counts[2], 1ull);
+      }
+      stage[3 * q] = (int32_t)a;
+      stage[3 * q + 1] = (int32_t)b;
+      stage[3 * q + 2] = (int32_t)c;
+      ++q;
+    };
+    for (int t = 0; t < 2; ++t) {
+      if (!S.ok[t]) continue;
+      const int64_t C0 = v;
+      const int64_t C1 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o) : v + 1;
+      const int64_t C2 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o - 1) : (int64_t)(k + 1) * g.NI + (i + o);
+      if (!S.sides[t]) {
+        put(C0, C1, C2, S.moved[t]);
+        continue;
+      }
+      const int js = __builtin_ctz(S.sides[t]);
+      // the owner and owned side of side js
       int64_t w;
       int e;
       if (t == 0) {
-        if (j == 0) { w = v; e = 2; }
-        else if (j == 1) { w = (int64_t)(k + 1) * g.NI + (i + o - 1); e = 0; }
-        else { w = v; e = 1; }
+        w = js == 1 ? C2 : v;
+        e = js == 0 ? 2 : (js == 1 ? 0 : 1);
       } else {
-        if (j == 0) { w = v; e = 0; }
-        else if (j == 1) { w = v + 1; e = 1; }
-        else { w = v; e = 2; }
+        w = js == 1 ? v + 1 : v;
+        e = js == 0 ? 0 : (js == 1 ? 1 : 2);
       }
-      m = ins_id(w, e);
-    }
-    auto put = [&](int64_t a, int64_t b, int64_t c) {
-      if (a < P.vcap && b < P.vcap && c < P.vcap) {  // else the call fails on capacity
-        const double ax = P.verts[2 * a], ay = P.verts[2 * a + 1];
-        const double area2 =
-            (P.verts[2 * b] - ax) * (P.verts[2 * c + 1] - ay) - (P.verts[2 * b + 1] - ay) * (P.verts[2 * c] - ax);
-        if (!(area2 > 0.0)) atomicOr((unsigned long long*)&P.counts[2], 1ull);
-      }
-      if (to < P.tcap) {
-        P.tris[3 * to] = (int32_t)a;
-        P.tris[3 * to + 1] = (int32_t)b;
-        P.tris[3 * to + 2] = (int32_t)c;
-      }
-      ++to;
-    };
-    if (js < 0) {
-      put(C[0], C[1], C[2]);
-    } else {  // the split edge (C[js], C[js+1]) fanned around the inserted vertex
-      const int64_t a0 = C[js], a1 = C[(js + 1) % 3], a2 = C[(js + 2) % 3];
-      put(a0, m, a2);
-      put(m, a1, a2);
+      const uint32_t fw = P.flags[w];
+      const int64_t m = nlat + P.ins_base[w] + __builtin_popcount(fw & ((1u << e) - 1u));
+      const int64_t Cs[3] = {C0, C1, C2};
+      const int64_t a0 = Cs[js], a1 = Cs[(js + 1) % 3], a2 = Cs[(js + 2) % 3];
+      put(a0, m, a2, true);
+      put(m, a1, a2, true);
     }
   }
+  __syncthreads();
+  const int64_t t0 = sh.seg_off[blockIdx.x].y;
+  const int64_t lim = 3 * (P.tcap - t0);  // stage entries that fit the capacity
+  for (int q = threadIdx.x; q < 3 * total; q += 256)
+    if (q < lim) P.tris[3 * t0 + q] = stage[q];
 }
 
 __global__ void k_pre_clear(PreArgs P, int64_t nmid) {
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nmid; q += (int64_t)gridDim.x * blockDim.x)
     P.mid[q] = 0u;
-  if (blockIdx.x == 0 && threadIdx.x < 8) P.counts[threadIdx.x] = 0;
+  for (int q = threadIdx.x; blockIdx.x == 0 && q < kPreCounts; q += blockDim.x) P.counts[q] = 0;
 }
 
 __global__ void k_pre_sizes(OneSrc src, PreArgs P, Shared sh, int64_t* out) {
   const Geo g = src.d.g;
   const longlong4 tot = sh.seg_off[sh.nseg];
+  int64_t ns = 0, nr = 0;
+  for (int q = 0; q < 256; ++q) {
+    ns += P.counts[kPreTally + q];
+    nr += P.counts[kPreTally + 256 + q];
+  }
   out[0] = (int64_t)g.NK * g.NI + tot.x;  // vertices
   out[1] = tot.y;                          // triangles
-  out[2] = P.counts[0];                    // snapped
-  out[3] = P.counts[1];                    // repelled
+  out[2] = ns;                             // snapped
+  out[3] = nr;                             // repelled
   out[4] = tot.x;                          // inserted
   out[5] = P.counts[2] ? SBMT_E_PROTOCOL : ((out[0] > P.vcap || out[1] > P.tcap) ? SBMT_E_CAPACITY : SBMT_OK);
   if (out[0] > 0x7fffffffLL) out[5] = SBMT_E_INDEX_OVERFLOW;
@@ -2467,11 +2603,11 @@ __global__ void k_copy_sizes(const int64_t* __restrict__ s, int64_t n4, int64_t*
 }
 
 // Workspace of the preprocessing: the meshing layout of the image, then the
-// per-midpoint words, per-owner split edges, counts and first inserted
+// per-midpoint words, the per-owner split sides, flags and first inserted
 // indices, and the counters and sizes.
 struct PreLayout {
   CallLayout L;
-  size_t off_mid, off_split, off_owner, off_ins, off_counts, off_out, total;
+  size_t off_mid, off_split, off_flags, off_ins, off_counts, off_out, total;
   int64_t nmid, nown;
 };
 static sbmt_status pre_layout(const sbmt_image* img, bool need_ptr, PreLayout* P) {
@@ -2486,12 +2622,12 @@ static sbmt_status pre_layout(const sbmt_image* img, bool need_ptr, PreLayout* P
   off = align256(off + (size_t)P->nmid * 4);
   P->off_split = off;
   off = align256(off + (size_t)P->nown * 12);
-  P->off_owner = off;
-  off = align256(off + (size_t)P->nown * 4);
+  P->off_flags = off;
+  off = align256(off + (size_t)P->nown);
   P->off_ins = off;
   off = align256(off + (size_t)P->nown * 8);
   P->off_counts = off;
-  off = align256(off + 8 * 8);
+  off = align256(off + kPreCounts * 8);
   P->off_out = off;
   off = align256(off + 8 * 8);
   P->total = off;
@@ -3053,7 +3189,7 @@ sbmt_status sbmt_preprocess(sbmt_handle h, const sbmt_image* img, double a, doub
   P.tcap = tri_cap;
   P.mid = (uint32_t*)(w + PL.off_mid);
   P.split = (int32_t*)(w + PL.off_split);
-  P.owner_n = (int32_t*)(w + PL.off_owner);
+  P.flags = (uint8_t*)(w + PL.off_flags);
   P.ins_base = (int64_t*)(w + PL.off_ins);
   P.counts = (int64_t*)(w + PL.off_counts);
   int64_t* out = (int64_t*)(w + PL.off_out);
@@ -3069,8 +3205,8 @@ sbmt_status sbmt_preprocess(sbmt_handle h, const sbmt_image* img, double a, doub
   hipLaunchKernelGGL(k_scan_reduce, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, sh);
   hipLaunchKernelGGL(k_scan_apply, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
-  hipLaunchKernelGGL((k_pre_emit<0>), dim3((unsigned)nseg), dim3(256), 0, s, src, P, sh);
-  hipLaunchKernelGGL((k_pre_emit<1>), dim3((unsigned)nseg), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_inserted, dim3((unsigned)nseg), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_triangles, dim3((unsigned)nseg), dim3(256), 0, s, src, P, sh);
   hipLaunchKernelGGL(k_pre_sizes, dim3(1), dim3(1), 0, s, src, P, sh, out);
   if (hipGetLastError() != hipSuccess) return SBMT_E_DEVICE;
   if (hipMemcpyAsync(h->pinned, out, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||

@@ -2101,7 +2101,7 @@ struct PreArgs {
   uint8_t* on_polyline;  // per vertex: sits on a polyline vertex
   int32_t* tris;         // [triangles][3]
   int64_t vcap, tcap;
-  uint32_t* mid;         // per midpoint: bit 31 snapped to, low bits sides it splits
+  uint8_t* mid;          // per midpoint: 1 if a lattice vertex snapped to it
   uint8_t* flags;        // per lattice vertex: bits 0-2 owned side E0-E2 split, bit 3 moved
   int32_t* split;        // [NK NI][3]: midpoint splitting side E0, E1, E2 (written where split)
   int64_t* ins_base;     // [NK NI]: first inserted vertex of the owner (written where it has one)
@@ -2148,25 +2148,6 @@ __device__ __forceinline__ int floor_index(const Geo& g, double v) {
   return (int)__builtin_floor((v - sample_off(g)) / g.s);
 }
 
-// Coarse samples R0 .. R0 + NR - 1 x C0 .. C0 + 31 of the stored raster as row
-// masks (bit j of row r: sample (R0 + r, C0 + j)); background outside it.
-template <int NR>
-__device__ __forceinline__ void load_block(const Img& d, const Geo& g, int R0, int C0, int nr, uint32_t (&rw)[NR]) {
-  const int cc = C0 + kRingC;
-  const int w0 = cc >> 5, sh = cc & 31;
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const int R = R0 + r;
-    uint32_t w = 0;
-    if (r < nr && R >= -kRing && R < g.CH + kRing) {
-      const uint32_t* row = d.bits + (int64_t)(R + kRing) * g.wpr;
-      const uint64_t lo = (w0 >= 0 && w0 < g.wpr) ? row[w0] : 0u;
-      const uint64_t hi = (w0 + 1 >= 0 && w0 + 1 < g.wpr) ? row[w0 + 1] : 0u;
-      w = (uint32_t)((((hi << 32) | lo) >> sh));
-    }
-    rw[r] = w;
-  }
-}
 // thresholds widened by a relative and absolute margin far above the rounding
 // of the box bounds, so that a box never misses a candidate
 __device__ __forceinline__ double widen(double r) { return r * (1.0 + 1e-12) + 1e-9; }
@@ -2180,119 +2161,6 @@ __device__ __forceinline__ void cell_segment(const Geo& g, int R, int C, uint32_
   py = y0 + (ea == 1 || ea == 3 ? hs : (ea == 2 ? 2.0 * hs : 0.0));
   qx = x0 + (eb == 0 || eb == 2 ? hs : (eb == 1 ? 2.0 * hs : 0.0));
   qy = y0 + (eb == 1 || eb == 3 ? hs : (eb == 2 ? 2.0 * hs : 0.0));
-}
-
-// Steps 1 and 2, one thread per lattice vertex, from the 4 x 4 coarse samples
-// around it (rows and columns floor_index - 1 .. + 2).  Polyline vertices of
-// one orientation form a grid of spacing s > 2a, so only the nearest midpoint
-// of each orientation can lie within a; a segment within c < s/2 lies in one
-// of the 3 x 3 dual cells around the vertex.  A vertex whose 16 samples agree
-// stays where the lattice put it.
-__global__ void __launch_bounds__(256) k_pre_vertices(OneSrc src, PreArgs P) {
-  const Img& d = src.d;
-  const Geo g = d.g;
-  const int64_t n = (int64_t)g.NK * g.NI;
-  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  int kind = 0;  // 1 snapped, 2 repelled
-  if (v < n) {
-  const int k = (int)(v / g.NI), i = (int)(v - (int64_t)k * g.NI);
-  double x = lat_x(g, g.X0 + 4 * g.h * i + 2 * g.h * (k & 1)), y = lat_y(g, k);
-  uint8_t onp = 0, fl = 0;
-  const int Rd = floor_index(g, y), Cd = floor_index(g, x);
-  uint32_t rw[4];
-  load_block<4>(d, g, Rd - 1, Cd - 1, 4, rw);
-  const uint32_t all = (rw[0] & 15u) | ((rw[1] & 15u) << 4) | ((rw[2] & 15u) << 8) | ((rw[3] & 15u) << 12);
-  if (P.a > 0.0 && all != 0u && all != 0xffffu) {
-    auto S = [&](int R, int C) { return (int)((rw[R - Rd + 1] >> (C - Cd + 1)) & 1u); };
-    // Step 1: the polyline vertex within a (at most one)
-    double best = P.a;
-    int nbest = 0;
-    int64_t bj = -1;
-    double bx = 0, by = 0;
-    {
-      const int R = nearest_index(g, y);  // horizontal midpoint (R, Cd) - (R, Cd + 1)
-      if (S(R, Cd) != S(R, Cd + 1)) {
-        const double mx = (double)g.s * Cd + sample_off(g) + 0.5 * g.s, my = (double)g.s * R + sample_off(g);
-        const double dd = euclid_d(x - mx, y - my);
-        if (dd < P.a) {
-          ++nbest;
-          best = dd;
-          bj = mid_id(g, R, Cd, 0);
-          bx = mx;
-          by = my;
-        }
-      }
-      const int C = nearest_index(g, x);  // vertical midpoint (Rd, C) - (Rd + 1, C)
-      if (S(Rd, C) != S(Rd + 1, C)) {
-        const double mx = (double)g.s * C + sample_off(g), my = (double)g.s * Rd + sample_off(g) + 0.5 * g.s;
-        const double dd = euclid_d(x - mx, y - my);
-        if (dd < P.a) {
-          ++nbest;
-          if (dd < best) {
-            best = dd;
-            bj = mid_id(g, Rd, C, 1);
-            bx = mx;
-            by = my;
-          }
-        }
-      }
-    }
-    if (nbest > 1) atomicOr((unsigned long long*)&P.counts[2], 1ull);
-    if (bj >= 0) {
-      x = bx;
-      y = by;
-      onp = 1;
-      fl = kPreMoved;
-      atomicOr(&P.mid[bj], 0x80000000u);
-      kind = 1;
-    } else if (P.c > 0.0) {
-      // Step 2: the segment within c (at most one)
-      int nclose = 0;
-      double spx = 0, spy = 0, sqx = 0, sqy = 0, st = 0;
-      for (int R = Rd - 1; R <= Rd + 1; ++R)
-        for (int C = Cd - 1; C <= Cd + 1; ++C) {
-          const int cs = S(R, C) | (S(R, C + 1) << 1) | (S(R + 1, C + 1) << 2) | (S(R + 1, C) << 3);
-          if (cs == 0 || cs == 15) continue;
-          const uint32_t ms = ms_case(cs);
-          for (int j = 0; j < (int)(ms & 3u); ++j) {
-            double px, py, qx, qy, t;
-            cell_segment(g, R, C, ms, j, px, py, qx, qy);
-            if (seg_dist_d(x, y, px, py, qx, qy, &t) < P.c) {
-              ++nclose;
-              spx = px;
-              spy = py;
-              sqx = qx;
-              sqy = qy;
-              st = t;
-            }
-          }
-        }
-      if (nclose > 1 || (nclose == 1 && !(st > 0.0 && st < 1.0))) atomicOr((unsigned long long*)&P.counts[2], 1ull);
-      if (nclose == 1) {
-        const double dx = sqx - spx, dy = sqy - spy, L = euclid_d(dx, dy);
-        const double nx = -dy / L, ny = dx / L;             // left normal
-        const double ds = (x - spx) * nx + (y - spy) * ny;  // signed distance to the line
-        const double move = (ds > 0 ? P.c : -P.c) - ds;
-        x += move * nx;
-        y += move * ny;
-        fl = kPreMoved;
-        kind = 2;
-      }
-    }
-  }
-  if (v < P.vcap) {
-    reinterpret_cast<double2*>(P.verts)[v] = make_double2(x, y);
-    P.on_polyline[v] = onp;
-  }
-  P.flags[v] = fl;
-  }
-  // one atomic per wave, spread over 256 counters (summed by k_pre_sizes)
-  const unsigned long long bs = __ballot(kind == 1), br = __ballot(kind == 2);
-  if ((threadIdx.x & 63) == 0) {
-    const int slot = (int)((blockIdx.x * 4 + (threadIdx.x >> 6)) & 255u);
-    if (bs) atomicAdd((unsigned long long*)&P.counts[kPreTally + slot], (unsigned long long)__popcll(bs));
-    if (br) atomicAdd((unsigned long long*)&P.counts[kPreTally + 256 + slot], (unsigned long long)__popcll(br));
-  }
 }
 
 // Base triangle slot t of owner (k, i) exists (all three corners in the lattice).
@@ -2312,88 +2180,245 @@ __device__ __forceinline__ bool pre_edge_live(const Geo& g, int k, int i, int e)
   return pre_slot_ok(g, k, i, 0) || pre_slot_ok(g, k, i, 1);
 }
 
-// Step 3, one thread per owner: the free polyline vertex (no lattice vertex
-// snapped to it) within b of each owned side E0 -> (k, i+1), E1 -> (k+1, i+o-1),
-// E2 -> (k+1, i+o).  Every vertex moved by less than a, so the candidates are
-// the polyline vertices of the box around the owner's three sides on the
-// lattice widened by a + b: at most 5 x 4 coarse samples (its width is below
-// 3h < 2.2 s, its height below 2.4h < 1.7 s).
-constexpr int kPreRows = 6;
-__global__ void __launch_bounds__(256) k_pre_edges(OneSrc src, PreArgs P) {
+// Flag bits per lattice vertex: 0-2 owned side E0-E2 split, 3 moved, 4 taken
+// by a segment (Step 2), 5 snapped (Step 1).
+constexpr uint32_t kPreClaim = 16;
+constexpr uint32_t kPreSnapped = 32;
+// ORs bits into the flag byte of vertex v; returns the byte before.
+__device__ __forceinline__ uint32_t pre_flag_or(uint8_t* flags, int64_t v, uint32_t bits) {
+  const int sh = 8 * (int)(v & 3);
+  const uint32_t old = atomicOr(reinterpret_cast<uint32_t*>(flags + (v & ~(int64_t)3)), bits << sh);
+  return (old >> sh) & 0xffu;
+}
+__device__ __forceinline__ void pre_error(const PreArgs& P) { atomicOr((unsigned long long*)&P.counts[2], 1ull); }
+// Wave sum of n added to one of 256 counters of tally `which` (0 snapped,
+// 1 repelled); every lane of the wave must call it.
+__device__ __forceinline__ void pre_tally(const PreArgs& P, int which, int n) {
+  const int tot = __builtin_amdgcn_readlane(wave_incl_scan_dpp(n), 63);
+  if ((threadIdx.x & 63) == 0 && tot) {
+    const int slot = (int)((blockIdx.x * 4u + (threadIdx.x >> 6)) & 255u);
+    atomicAdd((unsigned long long*)&P.counts[kPreTally + 256 * which + slot], (unsigned long long)tot);
+  }
+}
+// Lattice row spacing and column pitch in pixels (to locate rows and columns;
+// positions themselves always come from lat_x / lat_y).
+__device__ __forceinline__ double pre_hx(const Geo& g) { return (double)g.h / g.U; }
+__device__ __forceinline__ double pre_hy(const Geo& g) { return pre_hx(g) * kHalfSqrt3; }
+__device__ __forceinline__ int pre_row_floor(const Geo& g, double y) { return (int)__builtin_floor((y + 1.0) / pre_hy(g)); }
+__device__ __forceinline__ int pre_lat_X(const Geo& g, int k, int i) { return g.X0 + 4 * g.h * i + 2 * g.h * (k & 1); }
+
+// The unmoved lattice: every vertex at its lattice position, flags clear (one
+// block per row segment).
+__global__ void __launch_bounds__(256) k_pre_lattice(OneSrc src, PreArgs P) {
+  const Geo g = src.d.g;
+  const int k = (int)(blockIdx.x / (unsigned)g.NCB);
+  const int i = (int)(blockIdx.x - (unsigned)k * (unsigned)g.NCB) * kCB + (int)threadIdx.x;
+  if (i >= g.NI) return;
+  const int64_t v = (int64_t)k * g.NI + i;
+  if (v < P.vcap) {
+    reinterpret_cast<double2*>(P.verts)[v] = make_double2(lat_x(g, pre_lat_X(g, k, i)), lat_y(g, k));
+    P.on_polyline[v] = 0;
+  }
+  P.flags[v] = 0;
+}
+
+// The polyline is enumerated from the coarse raster: one thread per stored
+// word of coarse rows -1 .. CH - 1.  Bit j concerns column C = C0 + j: dh
+// marks the horizontal midpoint (R, C)-(R, C+1) as a polyline vertex, dv the
+// vertical one (R, C)-(R+1, C), and cur / c1 / bel / b1 hold the samples
+// (R, C), (R, C+1), (R+1, C), (R+1, C+1) of dual cell (R, C).
+struct PreWord {
+  int R, C0;
+  uint32_t cur, c1, bel, b1, dh, dv;
+};
+__device__ __forceinline__ bool pre_word(const Img& d, const Geo& g, PreWord& W) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)(g.CH + 1) * g.wpr) return false;
+  const int r = (int)(t / g.wpr), w = (int)(t - (int64_t)r * g.wpr);
+  W.R = r - 1;
+  W.C0 = 32 * w - kRingC;
+  const uint32_t* row = d.bits + (int64_t)(W.R + kRing) * g.wpr;
+  const bool more = w + 1 < g.wpr;
+  W.cur = row[w];
+  W.bel = row[g.wpr + w];
+  W.c1 = (W.cur >> 1) | ((more ? row[w + 1] : 0u) << 31);
+  W.b1 = (W.bel >> 1) | ((more ? row[g.wpr + w + 1] : 0u) << 31);
+  W.dh = W.cur ^ W.c1;
+  W.dv = W.cur ^ W.bel;
+  return true;
+}
+__device__ __forceinline__ void pre_mid_xy(const Geo& g, int R, int C, int vt, double& x, double& y) {
+  x = (double)g.s * C + sample_off(g) + (vt ? 0.0 : 0.5 * g.s);
+  y = (double)g.s * R + sample_off(g) + (vt ? 0.5 * g.s : 0.0);
+}
+
+// Step 1 from the polyline side: the lattice vertex within a of polyline vertex
+// (R, C, vt) at (mx, my) is the nearest one of one of the rows around my (a <
+// h/2: lattice vertices are h apart, so there is at most one); it moves onto
+// the polyline vertex.  Returns the number of vertices snapped.
+__device__ int pre_snap_one(const PreArgs& P, const Geo& g, int R, int C, int vt, double mx, double my) {
+  const double aw = widen(P.a);
+  const int kf = pre_row_floor(g, my);
+  int hits = 0;
+  for (int k = kf - 1; k <= kf + 2; ++k) {
+    if (k < 0 || k >= g.NK) continue;
+    const double yv = lat_y(g, k);
+    if (!(__builtin_fabs(yv - my) <= aw)) continue;
+    const int i = (int)__builtin_floor((mx - lat_x(g, pre_lat_X(g, k, 0))) / pre_hx(g) + 0.5);
+    if (i < 0 || i >= g.NI) continue;
+    const double xv = lat_x(g, pre_lat_X(g, k, i));
+    if (!(euclid_d(xv - mx, yv - my) < P.a)) continue;
+    ++hits;
+    const int64_t v = (int64_t)k * g.NI + i;
+    if (pre_flag_or(P.flags, v, kPreSnapped | kPreMoved) & kPreSnapped) pre_error(P);  // two polyline vertices
+    if (v < P.vcap) {
+      reinterpret_cast<double2*>(P.verts)[v] = make_double2(mx, my);
+      P.on_polyline[v] = 1;
+    }
+    P.mid[mid_id(g, R, C, vt)] = 1;
+  }
+  if (hits > 1) pre_error(P);
+  return hits;
+}
+__global__ void __launch_bounds__(256) k_pre_snap(OneSrc src, PreArgs P) {
   const Img& d = src.d;
   const Geo g = d.g;
-  const int64_t n = (int64_t)g.NK * g.NI;
-  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (v >= n || !(P.b > 0.0)) return;
-  const int k = (int)(v / g.NI), i = (int)(v - (int64_t)k * g.NI), o = k & 1;
-  const double hx = (double)g.h / g.U;
-  const double lx = lat_x(g, g.X0 + 4 * g.h * i + 2 * g.h * o), ly = lat_y(g, k);
-  const double r = widen(P.a + P.b);
-  const double X0 = lx - 0.5 * hx - r, X1 = lx + hx + r, Y0 = ly - r, Y1 = lat_y(g, k + 1) + r;
-  const int R0 = floor_index(g, Y0), C0 = floor_index(g, X0);
-  const int nr = floor_index(g, Y1) + 2 - R0, nc = floor_index(g, X1) + 2 - C0;
-  if (nr > kPreRows || nc > 31) {  // outside the admissible thresholds
-    atomicOr((unsigned long long*)&P.counts[2], 1ull);
-    return;
-  }
-  uint32_t rw[kPreRows];
-  load_block<kPreRows>(d, g, R0, C0, nr, rw);
-  const uint32_t mh = (1u << (nc - 1)) - 1u, mv = (1u << nc) - 1u;
-  uint32_t any = 0;
-  for (int q = 0; q < nr; ++q) {
-    any |= (rw[q] ^ (rw[q] >> 1)) & mh;
-    if (q + 1 < nr) any |= (rw[q] ^ rw[q + 1]) & mv;
-  }
-  if (!any) return;
-  // the owner's live sides on the moved vertices
-  double ex[3][2], ey[3][2];
-  bool live[3];
-  const double2 U = reinterpret_cast<const double2*>(P.verts)[v];
-  for (int e = 0; e < 3; ++e) {
-    live[e] = pre_edge_live(g, k, i, e);
-    const int kw = e == 0 ? k : k + 1, iw = e == 0 ? i + 1 : (e == 1 ? i + o - 1 : i + o);
-    double2 Wv = make_double2(0.0, 0.0);
-    if (live[e]) Wv = reinterpret_cast<const double2*>(P.verts)[(int64_t)kw * g.NI + iw];
-    ex[e][0] = U.x;
-    ey[e][0] = U.y;
-    ex[e][1] = Wv.x;
-    ey[e][1] = Wv.y;
-  }
-  int nh[3] = {0, 0, 0};
-  int32_t hit[3] = {-1, -1, -1};
-  for (int q = 0; q < nr; ++q) {
+  PreWord W;
+  int n = 0;
+  if (P.a > 0.0 && pre_word(d, g, W)) {
     for (int vt = 0; vt < 2; ++vt) {
-      uint32_t bits = vt == 0 ? ((rw[q] ^ (rw[q] >> 1)) & mh) : (q + 1 < nr ? ((rw[q] ^ rw[q + 1]) & mv) : 0u);
+      uint32_t bits = vt ? W.dv : W.dh;
       while (bits) {
         const int j = __builtin_ctz(bits);
         bits &= bits - 1u;
-        const int R = R0 + q, C = C0 + j;
-        const double mx = (double)g.s * C + sample_off(g) + (vt ? 0.0 : 0.5 * g.s);
-        const double my = (double)g.s * R + sample_off(g) + (vt ? 0.5 * g.s : 0.0);
-        if (mx < X0 || mx > X1 || my < Y0 || my > Y1) continue;
-        const int64_t id = mid_id(g, R, C, vt);
-        if (P.mid[id] & 0x80000000u) continue;  // a lattice vertex sits on it
-        for (int e = 0; e < 3; ++e) {
-          if (!live[e]) continue;
-          const double ux = ex[e][0], uy = ey[e][0], wx = ex[e][1], wy = ey[e][1];
-          // both orientations, as the side's two triangles see it
-          if (seg_dist_d(mx, my, ux, uy, wx, wy, nullptr) < P.b || seg_dist_d(mx, my, wx, wy, ux, uy, nullptr) < P.b) {
-            ++nh[e];
-            hit[e] = (int32_t)id;
-          }
+        double mx, my;
+        pre_mid_xy(g, W.R, W.C0 + j, vt, mx, my);
+        n += pre_snap_one(P, g, W.R, W.C0 + j, vt, mx, my);
+      }
+    }
+  }
+  pre_tally(P, 0, n);
+}
+
+// Step 2 from the segment side: every lattice vertex not snapped within c of
+// segment P -> Q moves along the segment's left normal to distance c on its
+// own side.  A vertex taken by two segments, or whose closest point is an end
+// of the segment, is a protocol error (c < a/sqrt2 excludes both).  Returns
+// the number of vertices moved.
+__device__ int pre_repel_seg(const PreArgs& P, const Geo& g, double px, double py, double qx, double qy) {
+  const double cw = widen(P.c);
+  const double x0 = __builtin_fmin(px, qx) - cw, x1 = __builtin_fmax(px, qx) + cw;
+  const double y0 = __builtin_fmin(py, qy) - cw, y1 = __builtin_fmax(py, qy) + cw;
+  const int k0 = max(0, pre_row_floor(g, y0) - 1), k1 = min(g.NK - 1, pre_row_floor(g, y1) + 1);
+  int n = 0;
+  for (int k = k0; k <= k1; ++k) {
+    const double yv = lat_y(g, k);
+    if (yv < y0 || yv > y1) continue;
+    const double xo = lat_x(g, pre_lat_X(g, k, 0));
+    const int i0 = max(0, (int)__builtin_floor((x0 - xo) / pre_hx(g)) - 1);
+    const int i1 = min(g.NI - 1, (int)__builtin_floor((x1 - xo) / pre_hx(g)) + 1);
+    for (int i = i0; i <= i1; ++i) {
+      const double xv = lat_x(g, pre_lat_X(g, k, i));
+      if (xv < x0 || xv > x1) continue;
+      const int64_t v = (int64_t)k * g.NI + i;
+      if (P.flags[v] & kPreSnapped) continue;
+      double t;
+      if (!(seg_dist_d(xv, yv, px, py, qx, qy, &t) < P.c)) continue;
+      if (pre_flag_or(P.flags, v, kPreClaim | kPreMoved) & kPreClaim) pre_error(P);
+      if (!(t > 0.0 && t < 1.0)) pre_error(P);
+      const double dx = qx - px, dy = qy - py, L = euclid_d(dx, dy);
+      const double nx = -dy / L, ny = dx / L;               // left normal
+      const double ds = (xv - px) * nx + (yv - py) * ny;    // signed distance to the line
+      const double move = (ds > 0 ? P.c : -P.c) - ds;
+      if (v < P.vcap) reinterpret_cast<double2*>(P.verts)[v] = make_double2(xv + move * nx, yv + move * ny);
+      ++n;
+    }
+  }
+  return n;
+}
+__global__ void __launch_bounds__(256) k_pre_repel(OneSrc src, PreArgs P) {
+  const Img& d = src.d;
+  const Geo g = d.g;
+  PreWord W;
+  int n = 0;
+  if (P.c > 0.0 && pre_word(d, g, W)) {
+    uint32_t cells = W.dh | W.dv | (W.cur ^ W.b1);  // dual cells whose samples differ
+    while (cells) {
+      const int j = __builtin_ctz(cells);
+      cells &= cells - 1u;
+      const int cs = (int)(((W.cur >> j) & 1u) | (((W.c1 >> j) & 1u) << 1) | (((W.b1 >> j) & 1u) << 2) |
+                           (((W.bel >> j) & 1u) << 3));
+      const uint32_t ms = ms_case(cs);
+      for (int q = 0; q < (int)(ms & 3u); ++q) {
+        double px, py, qx, qy;
+        cell_segment(g, W.R, W.C0 + j, ms, q, px, py, qx, qy);
+        n += pre_repel_seg(P, g, px, py, qx, qy);
+      }
+    }
+  }
+  pre_tally(P, 1, n);
+}
+
+// Step 3 from the polyline side: a free polyline vertex (no lattice vertex
+// snapped to it) finds the base triangle sides within b of it, on the moved
+// vertices.  The vertices moved by less than a, so such a side lies within
+// a + b < 3h/4 of the polyline vertex on the lattice: its owner is within
+// rows -2 .. +2 and columns -2 .. +2 of the nearest one.  One side: the side is
+// split there (its owner's flag bit and split record); more than one, or a
+// side split twice, is a protocol error (b < a/2 excludes both).
+__device__ void pre_split_one(const PreArgs& P, const Geo& g, int64_t id, double mx, double my) {
+  const double r = widen(P.a + P.b);
+  const double2* V = reinterpret_cast<const double2*>(P.verts);
+  const int kf = pre_row_floor(g, my);
+  int nh = 0;
+  int64_t hv = -1;
+  int he = 0;
+  for (int k = max(0, kf - 2); k <= min(g.NK - 1, kf + 2); ++k) {
+    const double yu = lat_y(g, k);
+    const int ic = (int)__builtin_floor((mx - lat_x(g, pre_lat_X(g, k, 0))) / pre_hx(g) + 0.5);
+    for (int i = max(0, ic - 2); i <= min(g.NI - 1, ic + 2); ++i) {
+      const double xu = lat_x(g, pre_lat_X(g, k, i));
+      const int o = k & 1;
+      for (int e = 0; e < 3; ++e) {
+        const int kw = e == 0 ? k : k + 1, iw = e == 0 ? i + 1 : (e == 1 ? i + o - 1 : i + o);
+        if (!pre_edge_live(g, k, i, e)) continue;
+        const double xw = lat_x(g, pre_lat_X(g, kw, iw)), yw = e == 0 ? yu : lat_y(g, kw);
+        if (mx < __builtin_fmin(xu, xw) - r || mx > __builtin_fmax(xu, xw) + r || my < __builtin_fmin(yu, yw) - r ||
+            my > __builtin_fmax(yu, yw) + r)
+          continue;
+        const int64_t v = (int64_t)k * g.NI + i;
+        const double2 U = V[v], W = V[(int64_t)kw * g.NI + iw];
+        // both orientations, as the side's two triangles see it
+        if (seg_dist_d(mx, my, U.x, U.y, W.x, W.y, nullptr) < P.b || seg_dist_d(mx, my, W.x, W.y, U.x, U.y, nullptr) < P.b) {
+          ++nh;
+          hv = v;
+          he = e;
         }
       }
     }
   }
-  uint8_t fbits = 0;
-  for (int e = 0; e < 3; ++e) {
-    if (nh[e] > 1) atomicOr((unsigned long long*)&P.counts[2], 1ull);
-    if (hit[e] < 0) continue;
-    if ((atomicAdd(&P.mid[hit[e]], 1u) & 0x7fffffffu) != 0u) atomicOr((unsigned long long*)&P.counts[2], 1ull);
-    P.split[3 * v + e] = hit[e];
-    fbits |= (uint8_t)(1u << e);
+  if (nh > 1) pre_error(P);
+  if (nh == 0) return;
+  if (pre_flag_or(P.flags, hv, 1u << he) & (1u << he)) pre_error(P);  // a side split twice
+  P.split[3 * hv + he] = (int32_t)id;
+}
+__global__ void __launch_bounds__(256) k_pre_split(OneSrc src, PreArgs P) {
+  const Img& d = src.d;
+  const Geo g = d.g;
+  PreWord W;
+  if (!(P.b > 0.0) || !pre_word(d, g, W)) return;
+  for (int vt = 0; vt < 2; ++vt) {
+    uint32_t bits = vt ? W.dv : W.dh;
+    while (bits) {
+      const int j = __builtin_ctz(bits);
+      bits &= bits - 1u;
+      const int64_t id = mid_id(g, W.R, W.C0 + j, vt);
+      if (P.mid[id]) continue;  // a lattice vertex sits on it
+      double mx, my;
+      pre_mid_xy(g, W.R, W.C0 + j, vt, mx, my);
+      pre_split_one(P, g, id, mx, my);
+    }
   }
-  if (fbits) P.flags[v] |= fbits;
 }
 
 // Split sides of the two slots of owner (k, i), from the owners of the sides:
@@ -2575,8 +2600,9 @@ __global__ void __launch_bounds__(256) k_pre_triangles(OneSrc src, PreArgs P, Sh
 }
 
 __global__ void k_pre_clear(PreArgs P, int64_t nmid) {
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nmid; q += (int64_t)gridDim.x * blockDim.x)
-    P.mid[q] = 0u;
+  uint32_t* m4 = reinterpret_cast<uint32_t*>(P.mid);  // the region is padded to 256 bytes
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < (nmid + 3) / 4; q += (int64_t)gridDim.x * blockDim.x)
+    m4[q] = 0u;
   for (int q = threadIdx.x; blockIdx.x == 0 && q < kPreCounts; q += blockDim.x) P.counts[q] = 0;
 }
 
@@ -2619,7 +2645,7 @@ static sbmt_status pre_layout(const sbmt_image* img, bool need_ptr, PreLayout* P
   if (P->nmid >= (1LL << 31)) return SBMT_E_INVALID_ARG;  // midpoint ids are int32
   size_t off = align256(P->L.total);
   P->off_mid = off;
-  off = align256(off + (size_t)P->nmid * 4);
+  off = align256(off + (size_t)P->nmid);
   P->off_split = off;
   off = align256(off + (size_t)P->nown * 12);
   P->off_flags = off;
@@ -3187,7 +3213,7 @@ sbmt_status sbmt_preprocess(sbmt_handle h, const sbmt_image* img, double a, doub
   P.tris = tris;
   P.vcap = vert_cap;
   P.tcap = tri_cap;
-  P.mid = (uint32_t*)(w + PL.off_mid);
+  P.mid = (uint8_t*)(w + PL.off_mid);
   P.split = (int32_t*)(w + PL.off_split);
   P.flags = (uint8_t*)(w + PL.off_flags);
   P.ins_base = (int64_t*)(w + PL.off_ins);
@@ -3195,12 +3221,14 @@ sbmt_status sbmt_preprocess(sbmt_handle h, const sbmt_image* img, double a, doub
   int64_t* out = (int64_t*)(w + PL.off_out);
   const int64_t ncb = PL.L.tab[PL.L.n];
   const int64_t nseg = PL.L.nseg;
-  const int64_t nb = (PL.nown + 255) / 256;
-  if (ncb > 0x7fffffffLL || nseg > 0x7fffffffLL || nb > 0x7fffffffLL) return SBMT_E_INVALID_ARG;
+  const int64_t nwb = ((int64_t)(g.CH + 1) * g.wpr + 255) / 256;  // raster words of rows -1 .. CH - 1
+  if (ncb > 0x7fffffffLL || nseg > 0x7fffffffLL || nwb > 0x7fffffffLL) return SBMT_E_INVALID_ARG;
   hipLaunchKernelGGL(k_coarsen<OneSrc>, dim3((unsigned)ncb), dim3(256), 0, s, src, (const int64_t*)nullptr, sh);
   hipLaunchKernelGGL(k_pre_clear, dim3(1024), dim3(256), 0, s, P, PL.nmid);
-  hipLaunchKernelGGL(k_pre_vertices, dim3((unsigned)nb), dim3(256), 0, s, src, P);
-  hipLaunchKernelGGL(k_pre_edges, dim3((unsigned)nb), dim3(256), 0, s, src, P);
+  hipLaunchKernelGGL(k_pre_lattice, dim3((unsigned)nseg), dim3(256), 0, s, src, P);
+  hipLaunchKernelGGL(k_pre_snap, dim3((unsigned)nwb), dim3(256), 0, s, src, P);
+  hipLaunchKernelGGL(k_pre_repel, dim3((unsigned)nwb), dim3(256), 0, s, src, P);
+  hipLaunchKernelGGL(k_pre_split, dim3((unsigned)nwb), dim3(256), 0, s, src, P);
   hipLaunchKernelGGL(k_pre_count, dim3((unsigned)nseg), dim3(256), 0, s, src, P, sh);
   hipLaunchKernelGGL(k_scan_reduce, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, sh);

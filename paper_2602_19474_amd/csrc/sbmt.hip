@@ -2200,43 +2200,58 @@ __device__ __forceinline__ void pre_tally(const PreArgs& P, int which, int n) {
     atomicAdd((unsigned long long*)&P.counts[kPreTally + 256 * which + slot], (unsigned long long)tot);
   }
 }
-// Lattice row spacing and column pitch in pixels (to locate rows and columns;
+// Lattice column pitch and row spacing in pixels (to locate rows and columns;
 // positions themselves always come from lat_x / lat_y).
 __device__ __forceinline__ double pre_hx(const Geo& g) { return (double)g.h / g.U; }
 __device__ __forceinline__ double pre_hy(const Geo& g) { return pre_hx(g) * kHalfSqrt3; }
 __device__ __forceinline__ int pre_row_floor(const Geo& g, double y) { return (int)__builtin_floor((y + 1.0) / pre_hy(g)); }
 __device__ __forceinline__ int pre_lat_X(const Geo& g, int k, int i) { return g.X0 + 4 * g.h * i + 2 * g.h * (k & 1); }
-
-// The unmoved lattice: every vertex at its lattice position, flags clear (one
-// block per row segment).
-__global__ void __launch_bounds__(256) k_pre_lattice(OneSrc src, PreArgs P) {
-  const Geo g = src.d.g;
-  const int k = (int)(blockIdx.x / (unsigned)g.NCB);
-  const int i = (int)(blockIdx.x - (unsigned)k * (unsigned)g.NCB) * kCB + (int)threadIdx.x;
-  if (i >= g.NI) return;
-  const int64_t v = (int64_t)k * g.NI + i;
-  if (v < P.vcap) {
-    reinterpret_cast<double2*>(P.verts)[v] = make_double2(lat_x(g, pre_lat_X(g, k, i)), lat_y(g, k));
-    P.on_polyline[v] = 0;
-  }
-  P.flags[v] = 0;
+// Owner column of x in row k, as a real number (column i sits at z = i).
+__device__ __forceinline__ double pre_col(const Geo& g, int k, double x) {
+  return (x - lat_x(g, pre_lat_X(g, k, 0))) / pre_hx(g);
 }
 
-// The polyline is enumerated from the coarse raster: one thread per stored
-// word of coarse rows -1 .. CH - 1.  Bit j concerns column C = C0 + j: dh
-// marks the horizontal midpoint (R, C)-(R, C+1) as a polyline vertex, dv the
-// vertical one (R, C)-(R+1, C), and cur / c1 / bel / b1 hold the samples
-// (R, C), (R, C+1), (R+1, C), (R+1, C+1) of dual cell (R, C).
+// The unmoved lattice: every vertex at its lattice position, flags clear.
+// Block: 1024 vertices of one row, four per thread (stride 256).
+constexpr int kPreQuad = 4 * kCB;
+__global__ void __launch_bounds__(256) k_pre_lattice(OneSrc src, PreArgs P, int nchunk) {
+  const Geo g = src.d.g;
+  const int k = (int)(blockIdx.x / (unsigned)nchunk);
+  const int i0 = (int)(blockIdx.x - (unsigned)k * (unsigned)nchunk) * kPreQuad + (int)threadIdx.x;
+  const double y = lat_y(g, k);
+  double2* V = reinterpret_cast<double2*>(P.verts);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int i = i0 + j * kCB;
+    if (i >= g.NI) break;
+    const int64_t v = (int64_t)k * g.NI + i;
+    if (v < P.vcap) {
+      V[v] = make_double2(lat_x(g, pre_lat_X(g, k, i)), y);
+      P.on_polyline[v] = 0;
+    }
+    P.flags[v] = 0;
+  }
+}
+
+// The polyline is enumerated from the coarse raster: thread t of the launch
+// takes stored word t of coarse rows -1 .. CH - 1.  Bit j concerns column
+// C = C0 + j: dh marks the horizontal midpoint (R, C)-(R, C+1) as a polyline
+// vertex, dv the vertical one (R, C)-(R+1, C), and cur / c1 / bel / b1 hold
+// the samples (R, C), (R, C+1), (R+1, C), (R+1, C+1) of dual cell (R, C).
 struct PreWord {
   int R, C0;
   uint32_t cur, c1, bel, b1, dh, dv;
 };
+__device__ __forceinline__ void pre_word_at(const Geo& g, uint32_t t, int& R, int& C0) {
+  const uint32_t r = t / (uint32_t)g.wpr;
+  R = (int)r - 1;
+  C0 = 32 * (int)(t - r * (uint32_t)g.wpr) - kRingC;
+}
 __device__ __forceinline__ bool pre_word(const Img& d, const Geo& g, PreWord& W) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (int64_t)(g.CH + 1) * g.wpr) return false;
-  const int r = (int)(t / g.wpr), w = (int)(t - (int64_t)r * g.wpr);
-  W.R = r - 1;
-  W.C0 = 32 * w - kRingC;
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= (uint32_t)((g.CH + 1) * g.wpr)) return false;
+  pre_word_at(g, t, W.R, W.C0);
+  const int w = (W.C0 + kRingC) >> 5;
   const uint32_t* row = d.bits + (int64_t)(W.R + kRing) * g.wpr;
   const bool more = w + 1 < g.wpr;
   W.cur = row[w];
@@ -2251,20 +2266,47 @@ __device__ __forceinline__ void pre_mid_xy(const Geo& g, int R, int C, int vt, d
   x = (double)g.s * C + sample_off(g) + (vt ? 0.0 : 0.5 * g.s);
   y = (double)g.s * R + sample_off(g) + (vt ? 0.5 * g.s : 0.0);
 }
+// The items the lanes of a wave found (set bits of m0, then of m1; each with a
+// 4-bit payload per bit read from pay0 / pay1 when given) are gathered in LDS
+// and dealt round-robin to the lanes: f(source lane, which mask, bit, payload).
+// Every thread of the block must call it (it synchronises the block).
+constexpr int kPreDeal = 64 * 64;
+template <class Pay, class F>
+__device__ __forceinline__ void pre_deal(uint16_t (*lds)[kPreDeal], uint32_t m0, uint32_t m1, Pay pay, F f) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int n = __builtin_popcount(m0) + __builtin_popcount(m1);
+  const int incl = wave_incl_scan_dpp(n);
+  const int total = __builtin_amdgcn_readlane(incl, 63);
+  int pos = incl - n;
+  for (int which = 0; which < 2; ++which) {
+    uint32_t m = which ? m1 : m0;
+    while (m) {
+      const int j = __builtin_ctz(m);
+      m &= m - 1u;
+      lds[wv][pos++] = (uint16_t)(lane | (which << 6) | (j << 7) | (pay(which, j) << 12));
+    }
+  }
+  __syncthreads();
+  for (int q = lane; q < total; q += 64) {
+    const uint32_t e = lds[wv][q];
+    f((int)(e & 63u), (int)((e >> 6) & 1u), (int)((e >> 7) & 31u), e >> 12);
+  }
+}
+__device__ __forceinline__ uint32_t pre_no_pay(int, int) { return 0u; }
 
 // Step 1 from the polyline side: the lattice vertex within a of polyline vertex
-// (R, C, vt) at (mx, my) is the nearest one of one of the rows around my (a <
-// h/2: lattice vertices are h apart, so there is at most one); it moves onto
-// the polyline vertex.  Returns the number of vertices snapped.
-__device__ int pre_snap_one(const PreArgs& P, const Geo& g, int R, int C, int vt, double mx, double my) {
+// (R, C, vt) at (mx, my) is the nearest one of a row within a of my (a < h/2:
+// lattice vertices are h apart, so there is at most one); it moves onto the
+// polyline vertex.  Returns the number of vertices snapped.
+__device__ int pre_snap_one(const PreArgs& P, const Geo& g, int R, int C, int vt) {
+  double mx, my;
+  pre_mid_xy(g, R, C, vt, mx, my);
   const double aw = widen(P.a);
-  const int kf = pre_row_floor(g, my);
   int hits = 0;
-  for (int k = kf - 1; k <= kf + 2; ++k) {
-    if (k < 0 || k >= g.NK) continue;
+  for (int k = max(0, pre_row_floor(g, my - aw)); k <= min(g.NK - 1, pre_row_floor(g, my + aw)); ++k) {
     const double yv = lat_y(g, k);
     if (!(__builtin_fabs(yv - my) <= aw)) continue;
-    const int i = (int)__builtin_floor((mx - lat_x(g, pre_lat_X(g, k, 0))) / pre_hx(g) + 0.5);
+    const int i = (int)__builtin_floor(pre_col(g, k, mx) + 0.5);
     if (i < 0 || i >= g.NI) continue;
     const double xv = lat_x(g, pre_lat_X(g, k, i));
     if (!(euclid_d(xv - mx, yv - my) < P.a)) continue;
@@ -2281,22 +2323,18 @@ __device__ int pre_snap_one(const PreArgs& P, const Geo& g, int R, int C, int vt
   return hits;
 }
 __global__ void __launch_bounds__(256) k_pre_snap(OneSrc src, PreArgs P) {
+  __shared__ uint16_t lds[4][kPreDeal];
   const Img& d = src.d;
   const Geo g = d.g;
   PreWord W;
+  const bool on = P.a > 0.0 && pre_word(d, g, W);
   int n = 0;
-  if (P.a > 0.0 && pre_word(d, g, W)) {
-    for (int vt = 0; vt < 2; ++vt) {
-      uint32_t bits = vt ? W.dv : W.dh;
-      while (bits) {
-        const int j = __builtin_ctz(bits);
-        bits &= bits - 1u;
-        double mx, my;
-        pre_mid_xy(g, W.R, W.C0 + j, vt, mx, my);
-        n += pre_snap_one(P, g, W.R, W.C0 + j, vt, mx, my);
-      }
-    }
-  }
+  const uint32_t base = blockIdx.x * 256u + (threadIdx.x & ~63u);
+  pre_deal(lds, on ? W.dh : 0u, on ? W.dv : 0u, pre_no_pay, [&](int sl, int vt, int j, uint32_t) {
+    int R, C0;
+    pre_word_at(g, base + sl, R, C0);
+    n += pre_snap_one(P, g, R, C0 + j, vt);
+  });
   pre_tally(P, 0, n);
 }
 
@@ -2309,14 +2347,11 @@ __device__ int pre_repel_seg(const PreArgs& P, const Geo& g, double px, double p
   const double cw = widen(P.c);
   const double x0 = __builtin_fmin(px, qx) - cw, x1 = __builtin_fmax(px, qx) + cw;
   const double y0 = __builtin_fmin(py, qy) - cw, y1 = __builtin_fmax(py, qy) + cw;
-  const int k0 = max(0, pre_row_floor(g, y0) - 1), k1 = min(g.NK - 1, pre_row_floor(g, y1) + 1);
   int n = 0;
-  for (int k = k0; k <= k1; ++k) {
+  for (int k = max(0, pre_row_floor(g, y0)); k <= min(g.NK - 1, pre_row_floor(g, y1)); ++k) {
     const double yv = lat_y(g, k);
     if (yv < y0 || yv > y1) continue;
-    const double xo = lat_x(g, pre_lat_X(g, k, 0));
-    const int i0 = max(0, (int)__builtin_floor((x0 - xo) / pre_hx(g)) - 1);
-    const int i1 = min(g.NI - 1, (int)__builtin_floor((x1 - xo) / pre_hx(g)) + 1);
+    const int i0 = max(0, (int)__builtin_floor(pre_col(g, k, x0))), i1 = min(g.NI - 1, (int)__builtin_floor(pre_col(g, k, x1)));
     for (int i = i0; i <= i1; ++i) {
       const double xv = lat_x(g, pre_lat_X(g, k, i));
       if (xv < x0 || xv > x1) continue;
@@ -2327,8 +2362,8 @@ __device__ int pre_repel_seg(const PreArgs& P, const Geo& g, double px, double p
       if (pre_flag_or(P.flags, v, kPreClaim | kPreMoved) & kPreClaim) pre_error(P);
       if (!(t > 0.0 && t < 1.0)) pre_error(P);
       const double dx = qx - px, dy = qy - py, L = euclid_d(dx, dy);
-      const double nx = -dy / L, ny = dx / L;               // left normal
-      const double ds = (xv - px) * nx + (yv - py) * ny;    // signed distance to the line
+      const double nx = -dy / L, ny = dx / L;             // left normal
+      const double ds = (xv - px) * nx + (yv - py) * ny;  // signed distance to the line
       const double move = (ds > 0 ? P.c : -P.c) - ds;
       if (v < P.vcap) reinterpret_cast<double2*>(P.verts)[v] = make_double2(xv + move * nx, yv + move * ny);
       ++n;
@@ -2337,59 +2372,65 @@ __device__ int pre_repel_seg(const PreArgs& P, const Geo& g, double px, double p
   return n;
 }
 __global__ void __launch_bounds__(256) k_pre_repel(OneSrc src, PreArgs P) {
+  __shared__ uint16_t lds[4][kPreDeal];
   const Img& d = src.d;
   const Geo g = d.g;
   PreWord W;
+  const bool on = P.c > 0.0 && pre_word(d, g, W);
+  const uint32_t cells = on ? (W.dh | W.dv | (W.cur ^ W.b1)) : 0u;  // dual cells whose samples differ
   int n = 0;
-  if (P.c > 0.0 && pre_word(d, g, W)) {
-    uint32_t cells = W.dh | W.dv | (W.cur ^ W.b1);  // dual cells whose samples differ
-    while (cells) {
-      const int j = __builtin_ctz(cells);
-      cells &= cells - 1u;
-      const int cs = (int)(((W.cur >> j) & 1u) | (((W.c1 >> j) & 1u) << 1) | (((W.b1 >> j) & 1u) << 2) |
-                           (((W.bel >> j) & 1u) << 3));
-      const uint32_t ms = ms_case(cs);
-      for (int q = 0; q < (int)(ms & 3u); ++q) {
-        double px, py, qx, qy;
-        cell_segment(g, W.R, W.C0 + j, ms, q, px, py, qx, qy);
-        n += pre_repel_seg(P, g, px, py, qx, qy);
-      }
+  const uint32_t base = blockIdx.x * 256u + (threadIdx.x & ~63u);
+  auto cs_of = [&](int, int j) {
+    return ((W.cur >> j) & 1u) | (((W.c1 >> j) & 1u) << 1) | (((W.b1 >> j) & 1u) << 2) | (((W.bel >> j) & 1u) << 3);
+  };
+  pre_deal(lds, cells, 0u, cs_of, [&](int sl, int, int j, uint32_t cs) {
+    int R, C0;
+    pre_word_at(g, base + sl, R, C0);
+    const uint32_t ms = ms_case((int)cs);
+    for (int q = 0; q < (int)(ms & 3u); ++q) {
+      double px, py, qx, qy;
+      cell_segment(g, R, C0 + j, ms, q, px, py, qx, qy);
+      n += pre_repel_seg(P, g, px, py, qx, qy);
     }
-  }
+  });
   pre_tally(P, 1, n);
 }
 
 // Step 3 from the polyline side: a free polyline vertex (no lattice vertex
 // snapped to it) finds the base triangle sides within b of it, on the moved
 // vertices.  The vertices moved by less than a, so such a side lies within
-// a + b < 3h/4 of the polyline vertex on the lattice: its owner is within
-// rows -2 .. +2 and columns -2 .. +2 of the nearest one.  One side: the side is
-// split there (its owner's flag bit and split record); more than one, or a
-// side split twice, is a protocol error (b < a/2 excludes both).
+// r = a + b of the polyline vertex on the lattice: per row, the owners whose
+// side e spans x within r (E0 of rows within r of y, E1 and E2 of rows whose
+// band reaches y within r).  One side: it is split there (its owner's flag
+// bit and split record); more than one, or a side split twice, is a protocol
+// error (b < a/2 excludes both).
 __device__ void pre_split_one(const PreArgs& P, const Geo& g, int64_t id, double mx, double my) {
-  const double r = widen(P.a + P.b);
+  const double r = widen(P.a + P.b), rr = r / pre_hx(g);
   const double2* V = reinterpret_cast<const double2*>(P.verts);
-  const int kf = pre_row_floor(g, my);
   int nh = 0;
   int64_t hv = -1;
   int he = 0;
-  for (int k = max(0, kf - 2); k <= min(g.NK - 1, kf + 2); ++k) {
-    const double yu = lat_y(g, k);
-    const int ic = (int)__builtin_floor((mx - lat_x(g, pre_lat_X(g, k, 0))) / pre_hx(g) + 0.5);
-    for (int i = max(0, ic - 2); i <= min(g.NI - 1, ic + 2); ++i) {
-      const double xu = lat_x(g, pre_lat_X(g, k, i));
-      const int o = k & 1;
-      for (int e = 0; e < 3; ++e) {
-        const int kw = e == 0 ? k : k + 1, iw = e == 0 ? i + 1 : (e == 1 ? i + o - 1 : i + o);
+  for (int k = max(0, pre_row_floor(g, my - r) - 1); k <= min(g.NK - 1, pre_row_floor(g, my + r)); ++k) {
+    const double yu = lat_y(g, k), z = pre_col(g, k, mx);
+    const int o = k & 1;
+    for (int e = 0; e < 3; ++e) {
+      // side e of owner i spans columns [i, i+1], [i-1/2, i], [i, i+1/2]
+      const double lo = e == 0 ? z - 1.0 - rr : (e == 1 ? z - rr : z - 0.5 - rr);
+      const double hi = e == 0 ? z + rr : (e == 1 ? z + 0.5 + rr : z + rr);
+      const int kw = e == 0 ? k : k + 1;
+      for (int i = max(0, (int)__builtin_floor(lo)); i <= min(g.NI - 1, (int)__builtin_floor(hi)); ++i) {
         if (!pre_edge_live(g, k, i, e)) continue;
-        const double xw = lat_x(g, pre_lat_X(g, kw, iw)), yw = e == 0 ? yu : lat_y(g, kw);
+        const int iw = e == 0 ? i + 1 : (e == 1 ? i + o - 1 : i + o);
+        const double xu = lat_x(g, pre_lat_X(g, k, i)), xw = lat_x(g, pre_lat_X(g, kw, iw));
+        const double yw = e == 0 ? yu : lat_y(g, kw);
         if (mx < __builtin_fmin(xu, xw) - r || mx > __builtin_fmax(xu, xw) + r || my < __builtin_fmin(yu, yw) - r ||
             my > __builtin_fmax(yu, yw) + r)
           continue;
         const int64_t v = (int64_t)k * g.NI + i;
-        const double2 U = V[v], W = V[(int64_t)kw * g.NI + iw];
+        const double2 U = V[v], Wv = V[(int64_t)kw * g.NI + iw];
         // both orientations, as the side's two triangles see it
-        if (seg_dist_d(mx, my, U.x, U.y, W.x, W.y, nullptr) < P.b || seg_dist_d(mx, my, W.x, W.y, U.x, U.y, nullptr) < P.b) {
+        if (seg_dist_d(mx, my, U.x, U.y, Wv.x, Wv.y, nullptr) < P.b ||
+            seg_dist_d(mx, my, Wv.x, Wv.y, U.x, U.y, nullptr) < P.b) {
           ++nh;
           hv = v;
           he = e;
@@ -2403,200 +2444,204 @@ __device__ void pre_split_one(const PreArgs& P, const Geo& g, int64_t id, double
   P.split[3 * hv + he] = (int32_t)id;
 }
 __global__ void __launch_bounds__(256) k_pre_split(OneSrc src, PreArgs P) {
+  __shared__ uint16_t lds[4][kPreDeal];
   const Img& d = src.d;
   const Geo g = d.g;
   PreWord W;
-  if (!(P.b > 0.0) || !pre_word(d, g, W)) return;
-  for (int vt = 0; vt < 2; ++vt) {
-    uint32_t bits = vt ? W.dv : W.dh;
-    while (bits) {
-      const int j = __builtin_ctz(bits);
-      bits &= bits - 1u;
-      const int64_t id = mid_id(g, W.R, W.C0 + j, vt);
-      if (P.mid[id]) continue;  // a lattice vertex sits on it
-      double mx, my;
-      pre_mid_xy(g, W.R, W.C0 + j, vt, mx, my);
-      pre_split_one(P, g, id, mx, my);
-    }
-  }
+  const bool on = P.b > 0.0 && pre_word(d, g, W);
+  const uint32_t base = blockIdx.x * 256u + (threadIdx.x & ~63u);
+  pre_deal(lds, on ? W.dh : 0u, on ? W.dv : 0u, pre_no_pay, [&](int sl, int vt, int j, uint32_t) {
+    int R, C0;
+    pre_word_at(g, base + sl, R, C0);
+    const int64_t id = mid_id(g, R, C0 + j, vt);
+    if (P.mid[id]) return;  // a lattice vertex sits on it
+    double mx, my;
+    pre_mid_xy(g, R, C0 + j, vt, mx, my);
+    pre_split_one(P, g, id, mx, my);
+  });
 }
 
-// Split sides of the two slots of owner (k, i), from the owners of the sides:
-// Tb = [v, vdr, vdl] has sides E2 of v, E0 of vdl, E1 of v; Ta = [v, vr, vdr]
-// has E0 of v, E1 of vr, E2 of v.  Bit j of slot t: side j (corner j to j+1).
+// Slots of owner (k, i): Tb = [v, vdr, vdl] has sides E2 of v, E0 of vdl, E1 of
+// v; Ta = [v, vr, vdr] has E0 of v, E1 of vr, E2 of v.  Bit j of a slot's
+// sides: side j (corner j to corner j+1) is split.  fv / fr / fdl: the flags
+// of v, vr and vdl (the owners of the slot sides).
 struct PreSlots {
-  int ok[2];
+  bool ok[2];
   uint32_t sides[2];
   bool moved[2];
+  uint32_t fv, fr, fdl;
 };
-__device__ __forceinline__ PreSlots pre_slots(const PreArgs& P, const Geo& g, int k, int i) {
+__device__ __forceinline__ PreSlots pre_owner_slots(const PreArgs& P, const Geo& g, int k, int i) {
   PreSlots S;
   const int o = k & 1;
-  const int64_t v = (int64_t)k * g.NI + i;
-  const uint32_t fv = P.flags[v];
+  const int64_t v = (int64_t)k * g.NI + i, vd = (int64_t)(k + 1) * g.NI + i + o;  // vd: vdr
   S.ok[0] = pre_slot_ok(g, k, i, 0);
   S.ok[1] = pre_slot_ok(g, k, i, 1);
-  S.sides[0] = S.sides[1] = 0;
-  S.moved[0] = S.moved[1] = false;
-  const uint32_t fdr = (S.ok[0] || S.ok[1]) ? P.flags[(int64_t)(k + 1) * g.NI + i + o] : 0u;
-  if (S.ok[0]) {
-    const uint32_t fdl = P.flags[(int64_t)(k + 1) * g.NI + i + o - 1];
-    S.sides[0] = ((fv >> 2) & 1u) | ((fdl & 1u) << 1) | (((fv >> 1) & 1u) << 2);
-    S.moved[0] = ((fv | fdr | fdl) & kPreMoved) != 0;
-  }
-  if (S.ok[1]) {
-    const uint32_t fr = P.flags[v + 1];
-    S.sides[1] = (fv & 1u) | (((fr >> 1) & 1u) << 1) | (((fv >> 2) & 1u) << 2);
-    S.moved[1] = ((fv | fr | fdr) & kPreMoved) != 0;
-  }
+  S.fv = P.flags[v];
+  S.fr = S.ok[1] ? P.flags[v + 1] : 0u;
+  S.fdl = S.ok[0] ? P.flags[vd - 1] : 0u;
+  const uint32_t fdr = (S.ok[0] || S.ok[1]) ? P.flags[vd] : 0u;
+  const uint32_t fv = S.fv;
+  S.sides[0] = S.ok[0] ? (((fv >> 2) & 1u) | ((S.fdl & 1u) << 1) | (((fv >> 1) & 1u) << 2)) : 0u;
+  S.sides[1] = S.ok[1] ? ((fv & 1u) | (((S.fr >> 1) & 1u) << 1) | (((fv >> 2) & 1u) << 2)) : 0u;
+  S.moved[0] = S.ok[0] && ((fv | fdr | S.fdl) & kPreMoved);
+  S.moved[1] = S.ok[1] && ((fv | S.fr | fdr) & kPreMoved);
   return S;
 }
+// One wave per row segment of kCB owners; lane l takes owners i0 + l + 64 j,
+// j = 0 .. 3, so that loads and stores of neighbouring lanes are adjacent.
+__device__ __forceinline__ bool pre_segment(const Geo& g, const Shared& sh, int64_t& seg, int& k, int& i0) {
+  const uint32_t sg = blockIdx.x * 4u + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  seg = sg;
+  if (seg >= sh.nseg) return false;
+  const uint32_t kk = sg / (uint32_t)g.NCB;  // segment counts fit 32 bits (grid of nseg / 4 blocks)
+  k = (int)kk;
+  i0 = (int)(sg - kk * (uint32_t)g.NCB) * kCB;
+  return true;
+}
 
-// Per row segment (one block, one owner per thread): inserted vertices (split
-// sides owned) and triangles (one per slot, two for a slot with a split side).
+// Per row segment: inserted vertices (split sides owned) and triangles (one
+// per slot, two for a slot with a split side).
 __global__ void __launch_bounds__(256) k_pre_count(OneSrc src, PreArgs P, Shared sh) {
-  __shared__ int part[2][4];
   const Geo g = src.d.g;
-  const int k = (int)(blockIdx.x / g.NCB), cb = (int)(blockIdx.x - (int64_t)k * g.NCB);
-  const int i = cb * kCB + (int)threadIdx.x;
+  int64_t seg;
+  int k, i0;
+  if (!pre_segment(g, sh, seg, k, i0)) return;  // wave-uniform
   int ni = 0, nt = 0;
-  if (i < g.NI) {
-    const PreSlots S = pre_slots(P, g, k, i);
-    ni = __builtin_popcount(P.flags[(int64_t)k * g.NI + i] & 7u);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int i = i0 + 64 * j + (int)(threadIdx.x & 63);
+    if (i >= g.NI) break;
+    const PreSlots S = pre_owner_slots(P, g, k, i);
+    ni += __builtin_popcount(S.fv & 7u);
     for (int t = 0; t < 2; ++t) {
       if (!S.ok[t]) continue;
       const int ns = __builtin_popcount(S.sides[t]);
-      if (ns > 1) atomicOr((unsigned long long*)&P.counts[2], 1ull);
+      if (ns > 1) pre_error(P);  // a triangle with two split sides
       nt += ns ? 2 : 1;
     }
   }
-  const int lane = threadIdx.x & 63;
   const int si = __builtin_amdgcn_readlane(wave_incl_scan_dpp(ni), 63);
-  const int stt = __builtin_amdgcn_readlane(wave_incl_scan_dpp(nt), 63);
-  if (lane == 0) {
-    part[0][threadIdx.x >> 6] = si;
-    part[1][threadIdx.x >> 6] = stt;
+  const int st = __builtin_amdgcn_readlane(wave_incl_scan_dpp(nt), 63);
+  if ((threadIdx.x & 63) == 0) {
+    sh.seg_cnt[seg] = make_int4(si, st, 0, 0);
+    sh.seg_slow[seg] = 0ull;
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    sh.seg_cnt[blockIdx.x] = make_int4(part[0][0] + part[0][1] + part[0][2] + part[0][3],
-                                       part[1][0] + part[1][1] + part[1][2] + part[1][3], 0, 0);
-    sh.seg_slow[blockIdx.x] = 0ull;
-  }
-}
-
-// Exclusive block scan of 256 values (four waves); returns the block total.
-__device__ __forceinline__ int block_scan256(int& x, int* tmp) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int incl = wave_incl_scan_dpp(x);
-  if (lane == 63) tmp[wv] = incl;
-  __syncthreads();
-  int before = 0;
-  for (int w = 0; w < wv; ++w) before += tmp[w];
-  const int total = tmp[0] + tmp[1] + tmp[2] + tmp[3];
-  x = before + incl - x;
-  __syncthreads();
-  return total;
 }
 
 // Inserted vertices at their offsets (row segment base from the scan, owner
-// offset by a block scan), and the first inserted index of each owner that has one.
+// offsets by wave scans), and the first inserted index of each owner that has one.
 __global__ void __launch_bounds__(256) k_pre_inserted(OneSrc src, PreArgs P, Shared sh) {
-  __shared__ int tmp[4];
   const Img& d = src.d;
   const Geo g = d.g;
-  const int k = (int)(blockIdx.x / g.NCB), cb = (int)(blockIdx.x - (int64_t)k * g.NCB);
-  const int i = cb * kCB + (int)threadIdx.x;
-  const int64_t v = (int64_t)k * g.NI + i;
-  const uint32_t f = i < g.NI ? (P.flags[v] & 7u) : 0u;
-  int xi = __builtin_popcount(f);
-  if (block_scan256(xi, tmp) == 0 || f == 0u) return;
+  int64_t seg;
+  int k, i0;
+  if (!pre_segment(g, sh, seg, k, i0)) return;
+  if (sh.seg_cnt[seg].x == 0) return;
   const int64_t nlat = (int64_t)g.NK * g.NI;
-  int64_t q = sh.seg_off[blockIdx.x].x + xi;
-  P.ins_base[v] = q;
-  for (int e = 0; e < 3; ++e) {
-    if (!((f >> e) & 1u)) continue;
-    const int32_t m = P.split[3 * v + e];
-    const int R = (m >> 1) / (g.CW + 2) - 1, C = (m >> 1) % (g.CW + 2) - 1;
-    double mx, my;
-    mid_point(d, g, R, C, m & 1, mx, my);
-    const int64_t id = nlat + q++;
-    if (id < P.vcap) {
-      reinterpret_cast<double2*>(P.verts)[id] = make_double2(mx, my);
-      P.on_polyline[id] = 1;
+  int64_t base = sh.seg_off[seg].x;
+  for (int j = 0; j < 4; ++j) {
+    const int i = i0 + 64 * j + (int)(threadIdx.x & 63);
+    const int64_t v = (int64_t)k * g.NI + i;
+    const uint32_t f = i < g.NI ? (P.flags[v] & 7u) : 0u;
+    const int n = __builtin_popcount(f);
+    const int incl = wave_incl_scan_dpp(n);
+    if (f) {
+      int64_t pos = base + (incl - n);
+      P.ins_base[v] = pos;
+      for (int e = 0; e < 3; ++e) {
+        if (!((f >> e) & 1u)) continue;
+        const int32_t m = P.split[3 * v + e];
+        const int R = (m >> 1) / (g.CW + 2) - 1, C = (m >> 1) % (g.CW + 2) - 1;
+        double mx, my;
+        pre_mid_xy(g, R, C, m & 1, mx, my);
+        const int64_t id = nlat + pos++;
+        if (id < P.vcap) {
+          reinterpret_cast<double2*>(P.verts)[id] = make_double2(mx, my);
+          P.on_polyline[id] = 1;
+        }
+      }
     }
+    base += __builtin_amdgcn_readlane(incl, 63);
   }
 }
 
-// Triangles of each row segment, staged in LDS and written as one contiguous
-// run.  A slot with a split side j (corners a0 -> a1, opposite a2) becomes
-// (a0, m, a2), (m, a1, a2) around the inserted vertex m.  Triangles with a
-// moved or inserted corner are checked for positive orientation.
+// Triangles of each row segment at their offsets (row segment base from the
+// scan, owner offsets by wave scans).  Per 64 owners the wave stages its
+// triangles in LDS and writes them as one contiguous run.  A slot with a split
+// side j (corners a0 -> a1, opposite a2) becomes (a0, m, a2), (m, a1, a2)
+// around the inserted vertex m.  Triangles with a moved or inserted corner are
+// checked for positive orientation.
 __global__ void __launch_bounds__(256) k_pre_triangles(OneSrc src, PreArgs P, Shared sh) {
-  __shared__ int tmp[4];
-  __shared__ int32_t stage[3 * 4 * kCB];
+  __shared__ int32_t stage[4][3 * 4 * 64];
   const Geo g = src.d.g;
-  const int k = (int)(blockIdx.x / g.NCB), cb = (int)(blockIdx.x - (int64_t)k * g.NCB);
-  const int i = cb * kCB + (int)threadIdx.x;
-  const int64_t v = (int64_t)k * g.NI + i;
-  const int o = k & 1;
-  PreSlots S;
-  int nt = 0;
-  if (i < g.NI) {
-    S = pre_slots(P, g, k, i);
-    for (int t = 0; t < 2; ++t) nt += S.ok[t] ? (S.sides[t] ? 2 : 1) : 0;
-  }
-  int xt = nt;
-  const int total = block_scan256(xt, tmp);
+  int64_t seg;
+  int k, i0;
+  if (!pre_segment(g, sh, seg, k, i0)) return;
+  const int lane = (int)(threadIdx.x & 63);
+  int32_t* st = stage[threadIdx.x >> 6];
   const int64_t nlat = (int64_t)g.NK * g.NI;
-  if (i < g.NI) {
-    int q = xt;
-    auto put = [&](int64_t a, int64_t b, int64_t c, bool check) {
-      if (check && a < P.vcap && b < P.vcap && c < P.vcap) {  // else the call fails on capacity
-        const double2 A = reinterpret_cast<const double2*>(P.verts)[a];
-        const double2 B = reinterpret_cast<const double2*>(P.verts)[b];
-        const double2 C = reinterpret_cast<const double2*>(P.verts)[c];
-        const double area2 = (B.x - A.x) * (C.y - A.y) - (B.y - A.y) * (C.x - A.x);
-        if (!(area2 > 0.0)) atomicOr((unsigned long long*)&P.counts[2], 1ull);
-      }
-      stage[3 * q] = (int32_t)a;
-      stage[3 * q + 1] = (int32_t)b;
-      stage[3 * q + 2] = (int32_t)c;
-      ++q;
-    };
-    for (int t = 0; t < 2; ++t) {
-      if (!S.ok[t]) continue;
-      const int64_t C0 = v;
-      const int64_t C1 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o) : v + 1;
-      const int64_t C2 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o - 1) : (int64_t)(k + 1) * g.NI + (i + o);
-      if (!S.sides[t]) {
-        put(C0, C1, C2, S.moved[t]);
-        continue;
-      }
-      const int js = __builtin_ctz(S.sides[t]);
-      // the owner and owned side of side js
-      int64_t w;
-      int e;
-      if (t == 0) {
-        w = js == 1 ? C2 : v;
-        e = js == 0 ? 2 : (js == 1 ? 0 : 1);
-      } else {
-        w = js == 1 ? v + 1 : v;
-        e = js == 0 ? 0 : (js == 1 ? 1 : 2);
-      }
-      const uint32_t fw = P.flags[w];
-      const int64_t m = nlat + P.ins_base[w] + __builtin_popcount(fw & ((1u << e) - 1u));
-      const int64_t Cs[3] = {C0, C1, C2};
-      const int64_t a0 = Cs[js], a1 = Cs[(js + 1) % 3], a2 = Cs[(js + 2) % 3];
-      put(a0, m, a2, true);
-      put(m, a1, a2, true);
+  const double2* V = reinterpret_cast<const double2*>(P.verts);
+  const int o = k & 1;
+  int64_t base = sh.seg_off[seg].y;
+  for (int j = 0; j < 4; ++j) {
+    const int i = i0 + 64 * j + lane;
+    PreSlots S;
+    int nt = 0;
+    if (i < g.NI) {
+      S = pre_owner_slots(P, g, k, i);
+      for (int t = 0; t < 2; ++t) nt += S.ok[t] ? (S.sides[t] ? 2 : 1) : 0;
     }
+    const int incl = wave_incl_scan_dpp(nt);
+    const int tot = __builtin_amdgcn_readlane(incl, 63);
+    if (nt) {
+      int pos = incl - nt;
+      auto put = [&](int64_t a, int64_t b, int64_t c, bool check) {
+        if (check && a < P.vcap && b < P.vcap && c < P.vcap) {  // else the call fails on capacity
+          const double2 A = V[a], B = V[b], C = V[c];
+          const double area2 = (B.x - A.x) * (C.y - A.y) - (B.y - A.y) * (C.x - A.x);
+          if (!(area2 > 0.0)) pre_error(P);
+        }
+        st[3 * pos] = (int32_t)a;
+        st[3 * pos + 1] = (int32_t)b;
+        st[3 * pos + 2] = (int32_t)c;
+        ++pos;
+      };
+      const int64_t v = (int64_t)k * g.NI + i;
+      for (int t = 0; t < 2; ++t) {
+        if (!S.ok[t]) continue;
+        const int64_t C0 = v;
+        const int64_t C1 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o) : v + 1;
+        const int64_t C2 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o - 1) : (int64_t)(k + 1) * g.NI + (i + o);
+        if (!S.sides[t]) {
+          put(C0, C1, C2, S.moved[t]);
+          continue;
+        }
+        const int js = __builtin_ctz(S.sides[t]);
+        // the owner and owned side of side js
+        const int64_t w = t == 0 ? (js == 1 ? C2 : v) : (js == 1 ? v + 1 : v);
+        const int e = t == 0 ? (js == 0 ? 2 : (js == 1 ? 0 : 1)) : js;
+        const uint32_t fw = t == 0 ? (js == 1 ? S.fdl : S.fv) : (js == 1 ? S.fr : S.fv);
+        const int64_t m = nlat + P.ins_base[w] + __builtin_popcount(fw & ((1u << e) - 1u));
+        const int64_t Cs[3] = {C0, C1, C2};
+        const int64_t a0 = Cs[js], a1 = Cs[(js + 1) % 3], a2 = Cs[(js + 2) % 3];
+        put(a0, m, a2, true);
+        put(m, a1, a2, true);
+      }
+    }
+    // the wave's LDS writes are seen by its own later reads (one wave, program order)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int64_t lim = 3 * (P.tcap - base);  // staged entries that fit the capacity
+    int32_t* out = P.tris + 3 * base;
+    for (int q = lane; q < 3 * tot; q += 64)
+      if (q < lim) out[q] = st[q];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    base += tot;
   }
-  __syncthreads();
-  const int64_t t0 = sh.seg_off[blockIdx.x].y;
-  const int64_t lim = 3 * (P.tcap - t0);  // stage entries that fit the capacity
-  for (int q = threadIdx.x; q < 3 * total; q += 256)
-    if (q < lim) P.tris[3 * t0 + q] = stage[q];
 }
 
 __global__ void k_pre_clear(PreArgs P, int64_t nmid) {
@@ -3222,19 +3267,22 @@ sbmt_status sbmt_preprocess(sbmt_handle h, const sbmt_image* img, double a, doub
   const int64_t ncb = PL.L.tab[PL.L.n];
   const int64_t nseg = PL.L.nseg;
   const int64_t nwb = ((int64_t)(g.CH + 1) * g.wpr + 255) / 256;  // raster words of rows -1 .. CH - 1
+  const int nchunk = (g.NI + kPreQuad - 1) / kPreQuad;  // 1024-vertex chunks of a lattice row
+  const int64_t nqb = (nseg + 3) / 4;                    // four row segments (waves) per block
+  if ((int64_t)g.NK * nchunk > 0x7fffffffLL) return SBMT_E_INVALID_ARG;
   if (ncb > 0x7fffffffLL || nseg > 0x7fffffffLL || nwb > 0x7fffffffLL) return SBMT_E_INVALID_ARG;
   hipLaunchKernelGGL(k_coarsen<OneSrc>, dim3((unsigned)ncb), dim3(256), 0, s, src, (const int64_t*)nullptr, sh);
   hipLaunchKernelGGL(k_pre_clear, dim3(1024), dim3(256), 0, s, P, PL.nmid);
-  hipLaunchKernelGGL(k_pre_lattice, dim3((unsigned)nseg), dim3(256), 0, s, src, P);
+  hipLaunchKernelGGL(k_pre_lattice, dim3((unsigned)(g.NK * nchunk)), dim3(256), 0, s, src, P, nchunk);
   hipLaunchKernelGGL(k_pre_snap, dim3((unsigned)nwb), dim3(256), 0, s, src, P);
   hipLaunchKernelGGL(k_pre_repel, dim3((unsigned)nwb), dim3(256), 0, s, src, P);
   hipLaunchKernelGGL(k_pre_split, dim3((unsigned)nwb), dim3(256), 0, s, src, P);
-  hipLaunchKernelGGL(k_pre_count, dim3((unsigned)nseg), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_count, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
   hipLaunchKernelGGL(k_scan_reduce, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, sh);
   hipLaunchKernelGGL(k_scan_apply, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
-  hipLaunchKernelGGL(k_pre_inserted, dim3((unsigned)nseg), dim3(256), 0, s, src, P, sh);
-  hipLaunchKernelGGL(k_pre_triangles, dim3((unsigned)nseg), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_inserted, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_triangles, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
   hipLaunchKernelGGL(k_pre_sizes, dim3(1), dim3(1), 0, s, src, P, sh, out);
   if (hipGetLastError() != hipSuccess) return SBMT_E_DEVICE;
   if (hipMemcpyAsync(h->pinned, out, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||

@@ -76,6 +76,8 @@ def lib():
         L.oracle_mesh_preprocessed.restype = vp
         L.oracle_mesh_preprocessed.argtypes = [vp, i32, i32, i64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                ctypes.c_double, ctypes.c_char_p, i32]
+        L.oracle_pre_grid.restype = vp
+        L.oracle_pre_grid.argtypes = L.oracle_mesh_preprocessed.argtypes
         for name in ("oracle_pre_n_vertices", "oracle_pre_n_triangles"):
             getattr(L, name).restype = i64
             getattr(L, name).argtypes = [vp]
@@ -241,7 +243,7 @@ def preprocessed_grid(bitmap: np.ndarray, grid_h, a=None, b=None, c=None) -> Pre
     bm = np.ascontiguousarray(bitmap, dtype=np.uint8)
     H, W = bm.shape
     err = ctypes.create_string_buffer(512)
-    res = L.oracle_mesh_preprocessed(bm.ctypes.data if bm.size else None, W, H, W, float(grid_h), a, b, c, err, 512)
+    res = L.oracle_pre_grid(bm.ctypes.data if bm.size else None, W, H, W, float(grid_h), a, b, c, err, 512)
     if not res:
         raise OracleError(err.value.decode())
     try:

@@ -40,7 +40,9 @@
 // snapping a, repulsion c, edge elimination b) and retriangulates against the
 // polyline in double precision; it is pinned by the bounds of Sec. 3.3.4 and
 // App. D on every triangle, by the mesh invariants and by reducing exactly to
-// the main path when every threshold is zero.  It has no GPU counterpart.
+// the main path when every threshold is zero.  oracle_pre_grid stops after the
+// three steps and returns the preprocessed grid (pinned by brute force over
+// the polyline): that is the part with a GPU counterpart.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -1142,12 +1144,14 @@ class PreOracle {
     cs_ = std::max(T_.h, 1.0);
   }
 
-  PreResult run() {
+  // grid_only: stop after Steps 1-3 (the preprocessed grid, no retriangulation)
+  PreResult run(bool grid_only = false) {
     index_polyline();
     snap_and_repel();
     build_triangles();
     eliminate_edges();
     record_grid();
+    if (grid_only) return out_;
     retriangulate();
     return finish();
   }
@@ -1778,8 +1782,23 @@ void oracle_free(oracle_mesh* r) { delete r; }
 struct oracle_pre {
   PreResult r;
 };
+oracle_pre* oracle_pre_run(const uint8_t* bitmap, int32_t width, int32_t height, int64_t row_stride, double grid_h,
+                           double a, double b, double c, bool grid_only, char* err, int32_t errlen);
+
 oracle_pre* oracle_mesh_preprocessed(const uint8_t* bitmap, int32_t width, int32_t height, int64_t row_stride,
                                      double grid_h, double a, double b, double c, char* err, int32_t errlen) {
+  return oracle_pre_run(bitmap, width, height, row_stride, grid_h, a, b, c, false, err, errlen);
+}
+
+// Steps 1-3 only: the preprocessed grid (oracle_pre_grid_sizes / _copy /
+// oracle_pre_counts read it; the mesh arrays stay empty).
+oracle_pre* oracle_pre_grid(const uint8_t* bitmap, int32_t width, int32_t height, int64_t row_stride, double grid_h,
+                            double a, double b, double c, char* err, int32_t errlen) {
+  return oracle_pre_run(bitmap, width, height, row_stride, grid_h, a, b, c, true, err, errlen);
+}
+
+oracle_pre* oracle_pre_run(const uint8_t* bitmap, int32_t width, int32_t height, int64_t row_stride, double grid_h,
+                           double a, double b, double c, bool grid_only, char* err, int32_t errlen) {
   try {
     // all rules off, or the admissible ranges of Sec. 3.3.4: b < a/2,
     // c < a/sqrt2, and a < h/2 (disjoint snapping neighbourhoods)
@@ -1789,7 +1808,7 @@ oracle_pre* oracle_mesh_preprocessed(const uint8_t* bitmap, int32_t width, int32
     Oracle o(bitmap, width, height, row_stride, grid_h, 0);
     PreOracle p(o.traced(), a, b, c);
     oracle_pre* res = new oracle_pre;
-    res->r = p.run();
+    res->r = p.run(grid_only);
     return res;
   } catch (const std::exception& e) {
     if (err && errlen > 0) std::snprintf(err, (size_t)errlen, "%s", e.what());

@@ -24,6 +24,10 @@ Extra objects on the same line:
                 sampling at the vertices, cotangent-Laplacian assembly and
                 explicit heat steps, timed with HIP events, with their
                 algorithmic HBM bytes and the oracle on a sample
+  preprocess    the geometric preprocessing of Alg. 3 (snap, repel, edge
+                elimination at the paper's thresholds) of the headline image:
+                one sbmt_preprocess call timed with HIP events, its algorithmic
+                HBM bytes, and the oracle's grid on a sample
 """
 from __future__ import annotations
 
@@ -200,6 +204,45 @@ def post_section(plain, reps: int = 10):
                      "hbm_frac": s_bytes / (s_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
     return res
+
+
+def preprocess_section(bm: np.ndarray, reps: int = 10):
+    """Alg. 3 preprocessing (Steps 1-3, the paper's thresholds) of the headline
+    image: the whole sbmt_preprocess call timed by events on its stream."""
+    import torch
+
+    from paper_2602_19474_amd.preprocess import Preprocessor
+    t = torch.from_numpy(bm).cuda()
+    pp = Preprocessor(t, 1)
+    nv, nt, ns, nr, ni = pp.run()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ms = []
+    for _ in range(reps):
+        ev[0].record()
+        pp.run()
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms.append(ev[0].elapsed_time(ev[1]))
+    ms = float(np.median(ms))
+    alg = bm.size + 17 * nv + 12 * nt  # bitmap in; vertices, on-polyline flags and triangles out
+    del pp, t
+    return {"ms": ms, "grid_h": 1, "thresholds": "(0.26, 0.125, 0.183) * h / sqrt(0.45)",
+            "vertices": nv, "triangles": nt, "snapped": ns, "repelled": nr, "inserted": ni,
+            "triangles_per_s": nt / (ms * 1e-3), "alg_bytes": alg,
+            "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "kernels": "profiles/noise8192_preprocess_kernel_stats.md"}
+
+
+def preprocess_cpu_baseline(bm: np.ndarray, rows: int = 2048):
+    """The oracle's preprocessed grid on the first `rows` rows of the headline image."""
+    import oracle
+    crop = np.ascontiguousarray(bm[:rows])
+    a = time.perf_counter()
+    g = oracle.preprocessed_grid(crop, 1)
+    dt = time.perf_counter() - a
+    return {"value": g.tris.shape[0] / dt, "unit": "triangles/s", "cores": 1, "kind": "oracle",
+            "sample": f"Steps 1-3 of Alg. 3 on rows 0-{rows - 1} of noise8192 ({crop.shape[1]} px wide)"}
 
 
 def post_cpu_baseline(plain, n_tri: int = 4_000_000):
@@ -470,6 +513,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-latency", action="store_true", help="skip the per-image latency sections")
     ap.add_argument("--no-post", action="store_true", help="skip the mesh-consumer section")
+    ap.add_argument("--no-preprocess", action="store_true", help="skip the Alg. 3 preprocessing section")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -536,6 +580,11 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_source": traffic_src, "alg_bytes_per_launch": emit_bytes},
     }
+    if not args.no_preprocess:
+        log("preprocess section")
+        res["preprocess"] = preprocess_section(noise)
+        if not args.no_cpu_baseline:
+            res["preprocess"]["cpu_baseline"] = preprocess_cpu_baseline(noise)
     if not args.no_post:
         log("post section")
         res["post"] = post_section(H["plain"])

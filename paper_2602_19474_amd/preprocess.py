@@ -70,3 +70,37 @@ def preprocess(bitmap, grid_h: float, a: float | None = None, b: float | None = 
     _lib.check(st, "sbmt_preprocess")
     nv, nt = int(counts[0]), int(counts[1])
     return PreGrid(verts[:nv], onp[:nv], tris[:nt], int(counts[2]), int(counts[3]), int(counts[4]))
+
+
+class Preprocessor:
+    """Workspace and outputs sized once for one image shape (bounds of
+    ``pre_query``), so that repeated calls allocate nothing."""
+
+    def __init__(self, bitmap, grid_h: float, a: float | None = None, b: float | None = None,
+                 c: float | None = None):
+        import torch
+        if a is None and b is None and c is None:
+            a, b, c = paper_thresholds(grid_h)
+        if a is None or b is None or c is None:
+            raise ValueError("give all three thresholds or none")
+        self.bitmap, self.grid_h, self.th = bitmap, float(grid_h), (float(a), float(b), float(c))
+        self.ws_bytes, self.vbound, self.tbound = pre_query(bitmap.shape[1], bitmap.shape[0], grid_h)
+        dev = bitmap.device
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.verts = torch.empty((self.vbound, 2), dtype=torch.float64, device=dev)
+        self.on_polyline = torch.empty((self.vbound,), dtype=torch.uint8, device=dev)
+        self.tris = torch.empty((max(self.tbound, 1), 3), dtype=torch.int32, device=dev)
+        self.ctx = context(dev.index)
+        self.img = _image(bitmap, grid_h, 0)
+        self.counts = (ctypes.c_int64 * 6)()
+
+    def run(self, stream=None):
+        """One call of sbmt_preprocess (waits for the stream); returns
+        (n_vertices, n_triangles, n_snapped, n_repelled, n_inserted)."""
+        a, b, c = self.th
+        st = _lib.lib().sbmt_preprocess(self.ctx.handle, ctypes.byref(self.img), a, b, c, self.ws.data_ptr(),
+                                        self.ws_bytes, self.verts.data_ptr(), self.on_polyline.data_ptr(),
+                                        self.vbound, self.tris.data_ptr(), self.tbound, self.counts,
+                                        _stream_ptr(stream))
+        _lib.check(st, "sbmt_preprocess")
+        return tuple(int(x) for x in self.counts[:5])

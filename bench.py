@@ -226,11 +226,29 @@ def preprocess_section(bm: np.ndarray, reps: int = 10):
         ms.append(ev[0].elapsed_time(ev[1]))
     ms = float(np.median(ms))
     alg = bm.size + 17 * nv + 12 * nt  # bitmap in; vertices, on-polyline flags and triangles out
-    del pp, t
+    del pp
+    # the mesh of Alg. 3: the grid retriangulated against the polyline
+    from paper_2602_19474_amd.preprocess import MeshPreprocessor
+    mp = MeshPreprocessor(t, 1)
+    mv, mt, mg, mc = mp.run()
+    torch.cuda.synchronize()
+    mms = []
+    for _ in range(max(3, reps // 2)):
+        ev[0].record()
+        mp.run()
+        ev[1].record()
+        torch.cuda.synchronize()
+        mms.append(ev[0].elapsed_time(ev[1]))
+    mms = float(np.median(mms))
+    malg = bm.size + 16 * mv + 13 * mt  # bitmap in; vertices, triangles and codes out
+    del mp, t
     return {"ms": ms, "grid_h": 1, "thresholds": "(0.26, 0.125, 0.183) * h / sqrt(0.45)",
             "vertices": nv, "triangles": nt, "snapped": ns, "repelled": nr, "inserted": ni,
             "triangles_per_s": nt / (ms * 1e-3), "alg_bytes": alg,
             "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "mesh": {"ms": mms, "vertices": mv, "grid_vertices": mg, "triangles": mt, "cut": mc,
+                     "triangles_per_s": mt / (mms * 1e-3), "alg_bytes": malg,
+                     "hbm_frac": malg / (mms * 1e-3) / 1e9 / HBM_PEAK_GBS},
             "kernels": "profiles/noise8192_preprocess_kernel_stats.md"}
 
 

@@ -299,6 +299,43 @@ sbmt_status sbmt_preprocess(sbmt_handle h, const sbmt_image* img, double a, doub
                             size_t ws_bytes, double* verts, uint8_t* on_polyline, int64_t vert_cap, int32_t* tris,
                             int64_t tri_cap, int64_t* counts, void* stream);
 
+/* The mesh of Alg. 3 (Sec. 3.5): the preprocessed grid above retriangulated
+ * against the polyline.  Every grid triangle is cut by the polyline pieces
+ * inside it (a corner on a polyline vertex is that vertex; a segment along a
+ * grid edge cuts nothing), its faces are traced, and each foreground face is
+ * triangulated by the template rule of Sec. 3.3 (fanned from the chain
+ * vertex inside the triangle; the quadrilateral between two chords split by
+ * the diagonal joining their exits; else fanned from the face's earliest
+ * chain point); an uncut grid triangle is kept whole when it lies in the
+ * foreground.  With admissible thresholds every triangle meets the angle and
+ * area bounds of Sec. 3.3.4 (App. D).
+ *
+ * sbmt_pre_mesh_query (host only): workspace bytes, and the room the grid
+ * phase needs in `verts` (grid_rows * grid_cols + 2 (coarse_h + 2)(coarse_w + 2)).
+ *
+ * sbmt_preprocess_mesh (waits for `stream`):
+ *  workspace  device, >= the query's bytes (else SBMT_E_WORKSPACE)
+ *  verts      device double [vert_cap][2]: the grid vertices (lattice vertex
+ *             k * grid_cols + i, then the inserted polyline vertices), then
+ *             the new vertices (crossings of grid edges, polyline vertices
+ *             inside grid triangles) by owner lattice vertex; grid vertices no
+ *             output triangle uses are left in place.  vert_cap must be at
+ *             least the query's grid bound (else SBMT_E_CAPACITY before any
+ *             launch).
+ *  tris       device int32 [tri_cap][3], positive signed area; codes device
+ *             uint8 [tri_cap]: 0 = grid triangle kept whole, 1 = piece of a
+ *             cut one.  May be NULL with tri_cap = 0.
+ *  counts     host int64 [8]: n_vertices (all rows of verts written),
+ *             n_triangles, n_snapped, n_repelled, n_inserted, status,
+ *             n_grid_vertices, n_cut (grid triangles the polyline cuts)
+ * Rows beyond a capacity are not written; SBMT_E_CAPACITY then comes with the
+ * counts filled in (size the outputs from them and call again).  Errors as
+ * for sbmt_preprocess. */
+sbmt_status sbmt_pre_mesh_query(const sbmt_image* img, size_t* workspace_bytes, int64_t* grid_vert_bound);
+sbmt_status sbmt_preprocess_mesh(sbmt_handle h, const sbmt_image* img, double a, double b, double c,
+                                 void* workspace, size_t ws_bytes, double* verts, int64_t vert_cap, int32_t* tris,
+                                 uint8_t* codes, int64_t tri_cap, int64_t* counts, void* stream);
+
 /* Number of canonical classes and the key code of class id c (1-based). */
 int32_t sbmt_num_classes(void);
 int32_t sbmt_class_code(int32_t class_id);

@@ -71,7 +71,8 @@ EXPORTS = ("sbmt_create", "sbmt_destroy", "sbmt_query", "sbmt_plan", "sbmt_run",
            "sbmt_batch_tune", "sbmt_num_classes", "sbmt_class_code", "sbmt_status_string",
            "sbmt_sample_field", "sbmt_quality_workspace", "sbmt_mesh_quality_async", "sbmt_mesh_quality",
            "sbmt_laplacian_workspace", "sbmt_laplacian_assemble", "sbmt_laplacian_csr", "sbmt_laplacian_apply",
-           "sbmt_heat_init", "sbmt_heat_steps", "sbmt_pre_query", "sbmt_preprocess")
+           "sbmt_heat_init", "sbmt_heat_steps", "sbmt_pre_query", "sbmt_preprocess",
+           "sbmt_pre_mesh_query", "sbmt_preprocess_mesh")
 
 ANGLE_BINS = 30
 
@@ -181,6 +182,10 @@ def lib():
     L.sbmt_pre_query.argtypes = [P(Image), P(sz), P(i64), P(i64)]
     L.sbmt_preprocess.restype = i32
     L.sbmt_preprocess.argtypes = [vp, P(Image), f64, f64, f64, vp, sz, vp, vp, i64, vp, i64, P(i64), vp]
+    L.sbmt_pre_mesh_query.restype = i32
+    L.sbmt_pre_mesh_query.argtypes = [P(Image), P(sz), P(i64)]
+    L.sbmt_preprocess_mesh.restype = i32
+    L.sbmt_preprocess_mesh.argtypes = [vp, P(Image), f64, f64, f64, vp, sz, vp, i64, vp, vp, i64, P(i64), vp]
     _lib = L
     return L
 

@@ -2106,6 +2106,14 @@ struct PreArgs {
   int32_t* split;        // [NK NI][3]: midpoint splitting side E0, E1, E2 (written where split)
   int64_t* ins_base;     // [NK NI]: first inserted vertex of the owner (written where it has one)
   int64_t* counts;       // [8 + 512]: [2] error; from kPreTally 256 counters of snapped, then of repelled vertices
+  int32_t* snap_mid;     // [NK NI]: the polyline vertex a lattice vertex snapped to (written where snapped)
+  // retriangulation of the grid (sbmt_preprocess_mesh)
+  uint32_t* rcount;      // [NK NI]: per-owner counts (pre_rc_*)
+  int64_t* rbase;        // [NK NI]: first new vertex of the owner (written where it has one)
+  const int64_t* gsizes; // the grid phase's sizes record (grid vertices first)
+  int32_t* otris;        // [otcap][3]
+  uint8_t* ocodes;       // [otcap]
+  int64_t otcap;
 };
 constexpr uint8_t kPreMoved = 8;
 constexpr int kPreTally = 8;
@@ -2318,6 +2326,7 @@ __device__ int pre_snap_one(const PreArgs& P, const Geo& g, int R, int C, int vt
       P.on_polyline[v] = 1;
     }
     P.mid[mid_id(g, R, C, vt)] = 1;
+    P.snap_mid[v] = (int32_t)mid_id(g, R, C, vt);
   }
   if (hits > 1) pre_error(P);
   return hits;
@@ -2668,6 +2677,833 @@ __global__ void k_pre_sizes(OneSrc src, PreArgs P, Shared sh, int64_t* out) {
   if (out[0] > 0x7fffffffLL) out[5] = SBMT_E_INDEX_OVERFLOW;
 }
 
+// ---------------------------------------------------------------------------
+// Retriangulation of the preprocessed grid against the polyline (the mesh of
+// Alg. 3, Sec. 3.5): every grid triangle is cut by the polyline pieces inside
+// it, its faces are traced along its boundary and the pieces, and the
+// foreground faces are triangulated by the template rule (fanned from the
+// chain vertex inside the triangle; the quadrilateral between two chords split
+// by the diagonal joining their exits; else fanned from the face's earliest
+// chain point); an uncut triangle is kept whole when it lies in the foreground.
+// Decisions in FP64 on the moved points, as the oracle takes them; the margins
+// c and b of Steps 2 and 3 keep them away from zero.  A corner that sits on a
+// polyline vertex is that vertex by identity.
+//
+// Output vertices: the grid vertices (ids 0 .. NV-1, positions from the grid
+// phase), then per owner (by the scan) its new vertices: the crossings of the
+// grid edges it owns, edge slot by edge slot (slot 2e and 2e+1: side E_e, or
+// its two halves around the inserted vertex; slot 6 + t: the fan edge of its
+// split slot t), each edge's crossings in order from its lower-numbered end;
+// then the polyline vertices strictly inside its slots' triangles.
+// ---------------------------------------------------------------------------
+struct PreSeg {
+  double px, py, qx, qy;
+  int32_t jp, jq;  // ids of the polyline vertices at the start and the end
+};
+__device__ __forceinline__ int32_t pre_cell_edge_mid(const Geo& g, int R, int C, int e) {
+  // cell edges: 0 top, 1 right, 2 bottom, 3 left
+  return (int32_t)(e == 0 ? mid_id(g, R, C, 0) : (e == 1 ? mid_id(g, R, C + 1, 1) : (e == 2 ? mid_id(g, R + 1, C, 0) : mid_id(g, R, C, 1))));
+}
+__device__ __forceinline__ int pre_cell_case(const Img& d, const Geo& g, int R, int C) {
+  return sample_at(d, g, R, C) | (sample_at(d, g, R, C + 1) << 1) | (sample_at(d, g, R + 1, C + 1) << 2) |
+         (sample_at(d, g, R + 1, C) << 3);
+}
+// Calls f(seg) for every segment of the dual cells meeting [x0, x1] x [y0, y1].
+template <class F>
+__device__ __forceinline__ void pre_segs_in_box(const Img& d, const Geo& g, double x0, double x1, double y0, double y1, F f) {
+  const int R0 = floor_index(g, y0) - 1, R1 = floor_index(g, y1);
+  const int C0 = floor_index(g, x0) - 1, C1 = floor_index(g, x1);
+  for (int R = R0; R <= R1; ++R)
+    for (int C = C0; C <= C1; ++C) {
+      const int cs = pre_cell_case(d, g, R, C);
+      if (cs == 0 || cs == 15) continue;
+      const uint32_t ms = ms_case(cs);
+      for (int j = 0; j < (int)(ms & 3u); ++j) {
+        PreSeg S;
+        cell_segment(g, R, C, ms, j, S.px, S.py, S.qx, S.qy);
+        S.jp = pre_cell_edge_mid(g, R, C, (int)((ms >> (2 + 4 * j)) & 3u));
+        S.jq = pre_cell_edge_mid(g, R, C, (int)((ms >> (4 + 4 * j)) & 3u));
+        f(S);
+      }
+    }
+}
+// Inside the foreground: the dual cell of the point, uniform or left of each
+// of its segments (segments have the foreground on their left).  Used for
+// points at a distance from the polyline (lattice corners off it, centroids of
+// uncut triangles).
+__device__ __forceinline__ int pre_inside_point(const Img& d, const Geo& g, double x, double y) {
+  const int R = floor_index(g, y), C = floor_index(g, x);
+  const int cs = pre_cell_case(d, g, R, C);
+  if (cs == 0 || cs == 15) return cs == 15;
+  const uint32_t ms = ms_case(cs);
+  for (int j = 0; j < (int)(ms & 3u); ++j) {
+    double px, py, qx, qy;
+    cell_segment(g, R, C, ms, j, px, py, qx, qy);
+    if (!((qx - px) * (y - py) - (qy - py) * (x - px) > 0.0)) return 0;
+  }
+  return 1;
+}
+// Grid vertex: id, position, the polyline vertex it sits on (or -1).
+struct PreGV {
+  int64_t id;
+  double x, y;
+  int32_t bnd;
+};
+__device__ __forceinline__ PreGV pre_lat_gv(const PreArgs& P, int64_t v) {
+  PreGV r;
+  r.id = v;
+  const double2 p = reinterpret_cast<const double2*>(P.verts)[v];
+  r.x = p.x;
+  r.y = p.y;
+  r.bnd = (P.flags[v] & kPreSnapped) ? P.snap_mid[v] : -1;
+  return r;
+}
+// The vertex inserted on side e of owner w (flags fw).
+__device__ __forceinline__ PreGV pre_ins_gv(const PreArgs& P, const Geo& g, int64_t w, int e, uint32_t fw) {
+  PreGV r;
+  r.id = (int64_t)g.NK * g.NI + P.ins_base[w] + __builtin_popcount(fw & ((1u << e) - 1u));
+  const double2 p = reinterpret_cast<const double2*>(P.verts)[r.id];
+  r.x = p.x;
+  r.y = p.y;
+  r.bnd = P.split[3 * w + e];
+  return r;
+}
+// Whether segment S crosses the grid edge U - W at an interior point of both
+// (a segment end that is U's or W's polyline vertex lies on the edge's line);
+// te: the crossing's position along U -> W (monotone, unnormalised).
+__device__ __forceinline__ bool pre_crosses(const PreSeg& S, const PreGV& U, const PreGV& W, double* te) {
+  const double gx = W.x - U.x, gy = W.y - U.y;
+  const double dp = (S.jp == U.bnd || S.jp == W.bnd) ? 0.0 : gx * (S.py - U.y) - gy * (S.px - U.x);
+  const double dq = (S.jq == U.bnd || S.jq == W.bnd) ? 0.0 : gx * (S.qy - U.y) - gy * (S.qx - U.x);
+  if (!((dp > 0.0 && dq < 0.0) || (dp < 0.0 && dq > 0.0))) return false;
+  const double hx = S.qx - S.px, hy = S.qy - S.py;
+  const double eu = hx * (U.y - S.py) - hy * (U.x - S.px), ew = hx * (W.y - S.py) - hy * (W.x - S.px);
+  if (!((eu > 0.0 && ew < 0.0) || (eu < 0.0 && ew > 0.0))) return false;
+  if (te) {
+    const double t = dp / (dp - dq);
+    *te = (S.px + t * hx - U.x) * gx + (S.py + t * hy - U.y) * gy;
+  }
+  return true;
+}
+// The crossing point of grid edge (lo, hi), lo < hi, by segment S.
+__device__ __forceinline__ void pre_crossing_xy(const PreSeg& S, const PreGV& L, const PreGV& H, double& x, double& y) {
+  const double gx = H.x - L.x, gy = H.y - L.y;
+  const double dp = gx * (S.py - L.y) - gy * (S.px - L.x);
+  const double dq = gx * (S.qy - L.y) - gy * (S.qx - L.x);
+  const double t = dp / (dp - dq);
+  x = S.px + t * (S.qx - S.px);
+  y = S.py + t * (S.qy - S.py);
+}
+// Calls f(seg, te) for every segment crossing grid edge U - W.
+template <class F>
+__device__ __forceinline__ void pre_edge_crossings(const Img& d, const Geo& g, const PreGV& U, const PreGV& W, F f) {
+  const double m = 1e-9;
+  pre_segs_in_box(d, g, fmin(U.x, W.x) - m, fmax(U.x, W.x) + m, fmin(U.y, W.y) - m, fmax(U.y, W.y) + m,
+                  [&](const PreSeg& S) {
+                    double te;
+                    if (pre_crosses(S, U, W, &te)) f(S, te);
+                  });
+}
+
+// A grid triangle of an owner's slot: corners, and per edge e (corner e to
+// e+1) the owner and edge slot that number its crossings.
+struct PreGT {
+  PreGV c[3];
+  int64_t eo[3];
+  int es[3];
+};
+// Edge slot q of owner (k, i): its ends (false if the owner has no such edge).
+__device__ bool pre_edge_slot(const PreArgs& P, const Geo& g, int k, int i, const PreSlots& S, int q, PreGV& A,
+                              PreGV& B) {
+  const int o = k & 1;
+  const int64_t v = (int64_t)k * g.NI + i;
+  if (q < 6) {
+    const int e = q >> 1;
+    if (!pre_edge_live(g, k, i, e)) return false;
+    const int kw = e == 0 ? k : k + 1, iw = e == 0 ? i + 1 : (e == 1 ? i + o - 1 : i + o);
+    const bool split = (S.fv >> e) & 1u;
+    if (!split && (q & 1)) return false;
+    const PreGV U = pre_lat_gv(P, v), W = pre_lat_gv(P, (int64_t)kw * g.NI + iw);
+    if (!split) {
+      A = U;
+      B = W;
+      return true;
+    }
+    const PreGV M = pre_ins_gv(P, g, v, e, S.fv);
+    A = (q & 1) ? M : U;
+    B = (q & 1) ? W : M;
+    return true;
+  }
+  const int t = q - 6;
+  if (!S.ok[t] || !S.sides[t]) return false;
+  const int js = __builtin_ctz(S.sides[t]);
+  const int64_t C0 = v;
+  const int64_t C1 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o) : v + 1;
+  const int64_t C2 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o - 1) : (int64_t)(k + 1) * g.NI + (i + o);
+  const int64_t w = t == 0 ? (js == 1 ? C2 : v) : (js == 1 ? v + 1 : v);
+  const int e = t == 0 ? (js == 0 ? 2 : (js == 1 ? 0 : 1)) : js;
+  const uint32_t fw = t == 0 ? (js == 1 ? S.fdl : S.fv) : (js == 1 ? S.fr : S.fv);
+  const int64_t Cs[3] = {C0, C1, C2};
+  A = pre_ins_gv(P, g, w, e, fw);
+  B = pre_lat_gv(P, Cs[(js + 2) % 3]);
+  return true;
+}
+// The grid triangles of slot t of owner (k, i): one, or two fanned around the
+// inserted vertex of its split side.  Returns their number.
+__device__ int pre_slot_tris(const PreArgs& P, const Geo& g, int k, int i, const PreSlots& S, int t, PreGT* T) {
+  if (!S.ok[t]) return 0;
+  const int o = k & 1;
+  const int64_t v = (int64_t)k * g.NI + i;
+  const int64_t C0 = v;
+  const int64_t C1 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o) : v + 1;
+  const int64_t C2 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o - 1) : (int64_t)(k + 1) * g.NI + (i + o);
+  const int64_t Cs[3] = {C0, C1, C2};
+  // side j: owner, owned side, and whether corner j is that owner
+  int64_t so[3];
+  int se[3];
+  bool sa[3];
+  if (t == 0) {  // Tb = [v, vdr, vdl]: E2 of v, E0 of vdl, E1 of v
+    so[0] = v; se[0] = 2; sa[0] = true;
+    so[1] = C2; se[1] = 0; sa[1] = false;
+    so[2] = v; se[2] = 1; sa[2] = false;
+  } else {  // Ta = [v, vr, vdr]: E0 of v, E1 of vr, E2 of v
+    so[0] = v; se[0] = 0; sa[0] = true;
+    so[1] = v + 1; se[1] = 1; sa[1] = true;
+    so[2] = v; se[2] = 2; sa[2] = false;
+  }
+  PreGV G[3];
+  for (int j = 0; j < 3; ++j) G[j] = pre_lat_gv(P, Cs[j]);
+  if (!S.sides[t]) {
+    for (int j = 0; j < 3; ++j) {
+      T[0].c[j] = G[j];
+      T[0].eo[j] = so[j];
+      T[0].es[j] = 2 * se[j];
+    }
+    return 1;
+  }
+  const int js = __builtin_ctz(S.sides[t]);
+  const uint32_t fw = t == 0 ? (js == 1 ? S.fdl : S.fv) : (js == 1 ? S.fr : S.fv);
+  const PreGV M = pre_ins_gv(P, g, so[js], se[js], fw);
+  const int j1 = (js + 1) % 3, j2 = (js + 2) % 3;
+  const int h0 = 2 * se[js] + (sa[js] ? 0 : 1), h1 = 2 * se[js] + (sa[js] ? 1 : 0);
+  // (a0, m, a2): a0 -> m (half of the split side), m -> a2 (fan edge), a2 -> a0
+  T[0].c[0] = G[js]; T[0].c[1] = M; T[0].c[2] = G[j2];
+  T[0].eo[0] = so[js]; T[0].es[0] = h0;
+  T[0].eo[1] = v; T[0].es[1] = 6 + t;
+  T[0].eo[2] = so[j2]; T[0].es[2] = 2 * se[j2];
+  // (m, a1, a2): m -> a1 (other half), a1 -> a2, a2 -> m (fan edge)
+  T[1].c[0] = M; T[1].c[1] = G[j1]; T[1].c[2] = G[j2];
+  T[1].eo[0] = so[js]; T[1].es[0] = h1;
+  T[1].eo[1] = so[j1]; T[1].es[1] = 2 * se[j1];
+  T[1].eo[2] = v; T[1].es[2] = 6 + t;
+  return 2;
+}
+
+// Per-owner counts of the retriangulation: crossings of edge slot q in bits
+// 2q .. 2q+1, polyline vertices inside its triangles in 16 .. 18, output
+// triangles in 19 .. 26.
+__device__ __forceinline__ int pre_rc_cross(uint32_t rc, int q) { return (int)((rc >> (2 * q)) & 3u); }
+__device__ __forceinline__ int pre_rc_before(uint32_t rc, int q) {  // crossings of slots before q
+  int n = 0;
+  for (int j = 0; j < q; ++j) n += pre_rc_cross(rc, j);
+  return n;
+}
+__device__ __forceinline__ int pre_rc_inner(uint32_t rc) { return (int)((rc >> 16) & 7u); }
+__device__ __forceinline__ int pre_rc_tris(uint32_t rc) { return (int)((rc >> 19) & 255u); }
+
+// A point of a triangle's subdivision: kind 0 grid vertex a; 1 crossing of
+// grid edge (a, b), a < b, by segment s; 2 polyline vertex a strictly inside
+// (s: the segment ending there).  ct: position along the chain.
+struct PrePt {
+  int kind;
+  int64_t a, b;
+  int32_t s;
+  double x, y, ct;
+};
+__device__ __forceinline__ bool pre_same(const PrePt& p, const PrePt& q) {
+  return p.kind == q.kind && p.a == q.a && p.b == q.b && p.s == q.s;
+}
+struct PreSub {
+  PreSeg S;
+  double t0, t1;
+  int e0, e1, c0, c1;
+};
+
+// Cuts grid triangle T by the polyline and triangulates its foreground faces,
+// calling out(p0, p1, p2, code) per output triangle (code 0: the grid
+// triangle kept whole, 1: a piece of a cut one).  Returns the number of
+// polyline vertices strictly inside T (0 or 1) and sets *inner to it.
+template <class Out>
+__device__ int pre_tri_mesh(const Img& d, const Geo& g, const PreArgs& P, const PreGT& T, Out out, PrePt* inner,
+                            bool* cut = nullptr) {
+  const int64_t NLAT = (int64_t)g.NK * g.NI;
+  double minx = T.c[0].x, maxx = T.c[0].x, miny = T.c[0].y, maxy = T.c[0].y;
+  for (int j = 1; j < 3; ++j) {
+    minx = fmin(minx, T.c[j].x);
+    maxx = fmax(maxx, T.c[j].x);
+    miny = fmin(miny, T.c[j].y);
+    maxy = fmax(maxy, T.c[j].y);
+  }
+  PreSub subs[3];
+  int nsub = 0, edge_side = -1;
+  bool bad = false;
+  pre_segs_in_box(d, g, minx - 1e-9, maxx + 1e-9, miny - 1e-9, maxy + 1e-9, [&](const PreSeg& S) {
+    if (fmax(S.px, S.qx) < minx - 1e-9 || fmin(S.px, S.qx) > maxx + 1e-9 || fmax(S.py, S.qy) < miny - 1e-9 ||
+        fmin(S.py, S.qy) > maxy + 1e-9)
+      return;
+    // clip against the three edge half-planes (inside = left of each edge)
+    double t0 = 0.0, t1 = 1.0;
+    int e0 = -1, e1 = -1;
+    for (int e = 0; e < 3; ++e) {
+      const PreGV& A = T.c[e];
+      const PreGV& B = T.c[(e + 1) % 3];
+      // an end of the segment that is a corner of this edge lies on its line
+      const double fp = (A.bnd == S.jp || B.bnd == S.jp) ? 0.0 : (B.x - A.x) * (S.py - A.y) - (B.y - A.y) * (S.px - A.x);
+      const double fq = (A.bnd == S.jq || B.bnd == S.jq) ? 0.0 : (B.x - A.x) * (S.qy - A.y) - (B.y - A.y) * (S.qx - A.x);
+      if (fp < 0 && fq < 0) return;
+      if (fp >= 0 && fq >= 0) continue;
+      const double t = fp / (fp - fq);
+      if (fp < 0) {
+        if (t > t0) {
+          t0 = t;
+          e0 = e;
+        }
+      } else if (t < t1) {
+        t1 = t;
+        e1 = e;
+      }
+    }
+    if (!(t1 > t0)) return;
+    PreSub sb;
+    sb.S = S;
+    sb.t0 = t0;
+    sb.t1 = t1;
+    sb.e0 = e0;
+    sb.e1 = e1;
+    sb.c0 = sb.c1 = -1;
+    for (int j = 0; j < 3; ++j) {
+      if (T.c[j].bnd == S.jp && t0 == 0.0) {
+        sb.c0 = j;
+        sb.e0 = -1;
+      }
+      if (T.c[j].bnd == S.jq && t1 == 1.0) {
+        sb.c1 = j;
+        sb.e1 = -1;
+      }
+    }
+    if (sb.c0 >= 0 && sb.c1 >= 0) {
+      // the segment joins two corners: it lies on their edge, and the
+      // triangle lies on the side of its third corner
+      const PreGV& T3 = T.c[3 - sb.c0 - sb.c1];
+      edge_side = ((S.qx - S.px) * (T3.y - S.py) - (S.qy - S.py) * (T3.x - S.px)) > 0 ? 1 : 0;
+      return;
+    }
+    if (nsub < 3) subs[nsub] = sb;
+    ++nsub;
+  });
+  if (nsub == 0) {
+    // uncut: side from a segment along an edge, a lattice corner off the
+    // polyline, else the centroid
+    int fg = edge_side;
+    for (int j = 0; j < 3 && fg < 0; ++j)
+      if (T.c[j].id < NLAT && T.c[j].bnd < 0) fg = pre_inside_point(d, g, T.c[j].x, T.c[j].y);
+    if (fg < 0) {
+      double cx = 0, cy = 0;
+      for (int j = 0; j < 3; ++j) {
+        cx += T.c[j].x / 3;
+        cy += T.c[j].y / 3;
+      }
+      fg = pre_inside_point(d, g, cx, cy);
+    }
+    if (fg) {
+      PrePt p[3];
+      for (int j = 0; j < 3; ++j) p[j] = PrePt{0, T.c[j].id, 0, -1, T.c[j].x, T.c[j].y, 0.0};
+      out(p[0], p[1], p[2], 0);
+    }
+    return 0;
+  }
+  if (cut) *cut = true;
+  if (nsub > 2) {  // more than two segments in one triangle
+    pre_error(P);
+    return 0;
+  }
+  if (nsub == 2) {  // chain order
+    if (subs[1].S.jq == subs[0].S.jp) {
+      const PreSub tmp = subs[0];
+      subs[0] = subs[1];
+      subs[1] = tmp;
+    }
+    if (subs[0].S.jq != subs[1].S.jp) {
+      pre_error(P);
+      return 0;
+    }
+  }
+  auto corner_pt = [&](int j) { return PrePt{0, T.c[j].id, 0, -1, T.c[j].x, T.c[j].y, 0.0}; };
+  auto cross_pt = [&](int e, const PreSeg& S) {
+    const PreGV& A = T.c[e];
+    const PreGV& B = T.c[(e + 1) % 3];
+    const PreGV& L = A.id < B.id ? A : B;
+    const PreGV& H = A.id < B.id ? B : A;
+    PrePt p;
+    p.kind = 1;
+    p.a = L.id;
+    p.b = H.id;
+    p.s = S.jp;
+    pre_crossing_xy(S, L, H, p.x, p.y);
+    p.ct = 0.0;
+    return p;
+  };
+  // pieces: the chain inside the triangle, from boundary to boundary
+  PrePt pc[2][3];
+  int pn[2] = {0, 0}, npc = 0, ncur = 0;
+  PrePt cur[3];
+  for (int q = 0; q < nsub; ++q) {
+    const PreSub& sb = subs[q];
+    PrePt st = sb.c0 >= 0 ? corner_pt(sb.c0)
+                          : (sb.e0 >= 0 ? cross_pt(sb.e0, sb.S) : PrePt{2, sb.S.jp, 0, sb.S.jp, sb.S.px, sb.S.py, 0.0});
+    PrePt en = sb.c1 >= 0 ? corner_pt(sb.c1)
+                          : (sb.e1 >= 0 ? cross_pt(sb.e1, sb.S) : PrePt{2, sb.S.jq, 0, sb.S.jp, sb.S.qx, sb.S.qy, 0.0});
+    st.ct = (double)q + sb.t0;
+    en.ct = (double)q + sb.t1;
+    if (ncur == 0) {
+      cur[ncur++] = st;
+    } else if (!(st.kind == 2 && cur[ncur - 1].kind == 2 && st.a == cur[ncur - 1].a)) {
+      pre_error(P);  // pieces do not join
+      return 0;
+    }
+    cur[ncur++] = en;
+    if (en.kind != 2) {
+      for (int z = 0; z < ncur; ++z) pc[npc][z] = cur[z];
+      pn[npc++] = ncur;
+      ncur = 0;
+    }
+  }
+  if (ncur != 0) {  // a piece ends inside the triangle
+    pre_error(P);
+    return 0;
+  }
+  int ninner = 0;
+  for (int q = 0; q < npc; ++q)
+    for (int z = 0; z < pn[q]; ++z)
+      if (pc[q][z].kind == 2) {
+        ++ninner;
+        *inner = pc[q][z];
+      }
+  if (ninner > 1) {
+    pre_error(P);
+    return 0;
+  }
+  // boundary cycle: the corners and the piece ends on each edge, in order
+  PrePt cyc[8];
+  int cpiece[8], cend[8];
+  double cpos[8];
+  int n = 0;
+  for (int j = 0; j < 3; ++j) {
+    cyc[n] = corner_pt(j);
+    cpiece[n] = -1;
+    cend[n] = -1;
+    cpos[n] = 3.0 * j;
+    ++n;
+  }
+  for (int q = 0; q < npc; ++q)
+    for (int end = 0; end < 2; ++end) {
+      const PrePt& p = end == 0 ? pc[q][0] : pc[q][pn[q] - 1];
+      if (p.kind == 0) {
+        for (int z = 0; z < 3; ++z)
+          if (cyc[z].a == p.a) {
+            if (cpiece[z] >= 0) {  // two pieces at one corner
+              pre_error(P);
+              return 0;
+            }
+            cpiece[z] = q;
+            cend[z] = end;
+          }
+        continue;
+      }
+      double pos = -1.0;
+      for (int e = 0; e < 3; ++e) {
+        const PreGV& A = T.c[e];
+        const PreGV& B = T.c[(e + 1) % 3];
+        if (p.kind == 1 && (A.id < B.id ? A.id : B.id) == p.a && (A.id < B.id ? B.id : A.id) == p.b) {
+          const double L2 = (B.x - A.x) * (B.x - A.x) + (B.y - A.y) * (B.y - A.y);
+          const double t = ((p.x - A.x) * (B.x - A.x) + (p.y - A.y) * (B.y - A.y)) / L2;
+          if (!(t > 0 && t < 1)) {
+            pre_error(P);
+            return 0;
+          }
+          pos = 3.0 * e + 1.0 + t;
+        }
+      }
+      if (pos < 0.0) {  // piece end not on the triangle
+        pre_error(P);
+        return 0;
+      }
+      cyc[n] = p;
+      cpiece[n] = q;
+      cend[n] = end;
+      cpos[n] = pos;
+      ++n;
+    }
+  for (int a = 1; a < n; ++a)  // insertion sort by position
+    for (int b = a; b > 0 && cpos[b] < cpos[b - 1]; --b) {
+      const PrePt tp = cyc[b];
+      cyc[b] = cyc[b - 1];
+      cyc[b - 1] = tp;
+      const int t1 = cpiece[b];
+      cpiece[b] = cpiece[b - 1];
+      cpiece[b - 1] = t1;
+      const int t2 = cend[b];
+      cend[b] = cend[b - 1];
+      cend[b - 1] = t2;
+      const double t3 = cpos[b];
+      cpos[b] = cpos[b - 1];
+      cpos[b - 1] = t3;
+    }
+  // faces: walk the cycle; at a piece end reached along the boundary, follow the piece
+  bool used[8] = {false, false, false, false, false, false, false, false};
+  for (int st = 0; st < n; ++st) {
+    if (used[st]) continue;
+    PrePt face[16];
+    int m = 0, side = -1, at = st;
+    for (int guard = 0; guard < 64; ++guard) {
+      if (used[at]) break;
+      used[at] = true;
+      if (m < 16) face[m] = cyc[at];
+      ++m;
+      const int nx = (at + 1) % n;
+      if (cpiece[nx] >= 0) {
+        const int q = cpiece[nx];
+        const bool fwd = cend[nx] == 0;
+        const int s2 = fwd ? 1 : 0;
+        if (side >= 0 && side != s2) {  // a face on both sides of the chain
+          pre_error(P);
+          return 0;
+        }
+        side = s2;
+        if (fwd) {
+          for (int z = 0; z + 1 < pn[q]; ++z) {
+            if (m < 16) face[m] = pc[q][z];
+            ++m;
+          }
+        } else {
+          for (int z = pn[q] - 1; z > 0; --z) {
+            if (m < 16) face[m] = pc[q][z];
+            ++m;
+          }
+        }
+        int oth = -1;
+        for (int z = 0; z < n; ++z)
+          if (cpiece[z] == q && cend[z] != cend[nx]) oth = z;
+        if (oth < 0) {
+          pre_error(P);
+          return 0;
+        }
+        at = oth;
+        if (at == st) break;
+        continue;
+      }
+      at = nx;
+      if (at == st) break;
+    }
+    if (side != 1) continue;
+    if (m < 3 || m > 16) {  // degenerate face
+      pre_error(P);
+      return 0;
+    }
+    // the template rule on this foreground face
+    int apex = -1;
+    for (int j = 0; j < m; ++j)
+      if (face[j].kind == 2) apex = j;
+    if (apex < 0 && m == 4 && npc == 2) {
+      bool corners = false;
+      for (int j = 0; j < m; ++j) corners = corners || face[j].kind == 0;
+      if (!corners) {
+        // the middle quadrilateral between two chords: diagonal joining their exits
+        const PrePt& x1 = pc[0][pn[0] - 1];
+        for (int j = 0; j < m; ++j)
+          if (face[j].kind == 1 && face[j].a == x1.a && face[j].b == x1.b && face[j].s == x1.s) apex = j;
+        const PrePt& x2 = pc[1][pn[1] - 1];
+        if (apex < 0 || !(face[(apex + 2) % 4].kind == 1 && face[(apex + 2) % 4].s == x2.s &&
+                          face[(apex + 2) % 4].a == x2.a && face[(apex + 2) % 4].b == x2.b)) {
+          pre_error(P);  // nested exits not opposite
+          return 0;
+        }
+      }
+    }
+    if (apex < 0) {
+      double best = 1e300;
+      for (int j = 0; j < m; ++j) {
+        const bool on_chain = face[j].kind != 0 || face[j].a >= NLAT || (P.flags[face[j].a] & kPreSnapped);
+        if (!on_chain) continue;
+        double ct = 1e300;
+        for (int q = 0; q < npc; ++q)
+          for (int z = 0; z < pn[q]; ++z)
+            if (pre_same(pc[q][z], face[j])) ct = pc[q][z].ct;
+        if (ct < best) {
+          best = ct;
+          apex = j;
+        }
+      }
+    }
+    if (apex < 0) {
+      pre_error(P);
+      return 0;
+    }
+    for (int t = 1; t + 1 < m; ++t) {
+      const PrePt& a = face[apex];
+      const PrePt& b = face[(apex + t) % m];
+      const PrePt& c = face[(apex + t + 1) % m];
+      if (!((b.x - a.x) * (c.y - a.y) - (b.y - a.y) * (c.x - a.x) > 0.0)) pre_error(P);
+      out(a, b, c, 1);
+    }
+  }
+  return ninner;
+}
+
+// Quiet owner: the coarse samples around both of its slots (their box on the
+// lattice widened by a + b, which holds every moved or inserted corner)
+// agree, so no segment comes near and its triangles lie on that side.
+// Returns the side (0 / 1), or -1.
+__device__ int pre_owner_quiet(const Img& d, const Geo& g, const PreArgs& P, int k, int i) {
+  const double hx = pre_hx(g), lx = lat_x(g, pre_lat_X(g, k, i));
+  const double r = widen(P.a + P.b);
+  const double x0 = lx - 0.5 * hx - r, x1 = lx + hx + r, y0 = lat_y(g, k) - r, y1 = lat_y(g, k + 1) + r;
+  const int R0 = floor_index(g, y0) - 1, R1 = floor_index(g, y1) + 1;
+  const int C0 = floor_index(g, x0) - 1, C1 = floor_index(g, x1) + 1;
+  const int first = sample_at(d, g, R0, C0);
+  for (int R = R0; R <= R1; ++R)
+    for (int C = C0; C <= C1; ++C)
+      if (sample_at(d, g, R, C) != first) return -1;
+  return first;
+}
+
+// Counts per owner (one wave per row segment, owners interleaved across
+// lanes): crossings of its edge slots, polyline vertices inside its slot
+// triangles, output triangles; per row segment: new vertices, triangles and
+// cut grid triangles.
+__global__ void __launch_bounds__(256) k_pre_mesh_count(OneSrc src, PreArgs P, Shared sh) {
+  const Img& d = src.d;
+  const Geo g = d.g;
+  int64_t seg;
+  int k, i0;
+  if (!pre_segment(g, sh, seg, k, i0)) return;
+  int nnew = 0, ntri = 0, ncut = 0;
+  for (int j = 0; j < 4; ++j) {
+    const int i = i0 + 64 * j + (int)(threadIdx.x & 63);
+    if (i >= g.NI) break;
+    const int64_t v = (int64_t)k * g.NI + i;
+    const PreSlots S = pre_owner_slots(P, g, k, i);
+    uint32_t rc = 0;
+    const int quiet = pre_owner_quiet(d, g, P, k, i);
+    if (quiet >= 0) {
+      const int nt = quiet ? (int)S.ok[0] + (int)S.ok[1] : 0;
+      rc = (uint32_t)nt << 19;
+      ntri += nt;
+    } else {
+      int nc = 0;
+      for (int q = 0; q < 8; ++q) {
+        PreGV A, B;
+        if (!pre_edge_slot(P, g, k, i, S, q, A, B)) continue;
+        int n = 0;
+        pre_edge_crossings(d, g, A, B, [&](const PreSeg&, double) { ++n; });
+        if (n > 3) {  // more crossings of one grid edge than the numbering holds
+          pre_error(P);
+          n = 3;
+        }
+        rc |= (uint32_t)n << (2 * q);
+        nc += n;
+      }
+      int nin = 0, nt = 0;
+      for (int t = 0; t < 2; ++t) {
+        PreGT T[2];
+        const int m = pre_slot_tris(P, g, k, i, S, t, T);
+        for (int z = 0; z < m; ++z) {
+          PrePt in;
+          bool cut = false;
+          nin += pre_tri_mesh(d, g, P, T[z], [&](const PrePt&, const PrePt&, const PrePt&, int) { ++nt; }, &in, &cut);
+          ncut += cut ? 1 : 0;
+        }
+      }
+      if (nin > 7 || nt > 255) {
+        pre_error(P);
+        nin = min(nin, 7);
+        nt = min(nt, 255);
+      }
+      rc |= ((uint32_t)nin << 16) | ((uint32_t)nt << 19);
+      nnew += nc + nin;
+      ntri += nt;
+    }
+    P.rcount[v] = rc;
+  }
+  const int sn = __builtin_amdgcn_readlane(wave_incl_scan_dpp(nnew), 63);
+  const int st = __builtin_amdgcn_readlane(wave_incl_scan_dpp(ntri), 63);
+  const int sc = __builtin_amdgcn_readlane(wave_incl_scan_dpp(ncut), 63);
+  if ((threadIdx.x & 63) == 0) {
+    sh.seg_cnt[seg] = make_int4(sn, st, sc, 0);
+    sh.seg_slow[seg] = 0ull;
+  }
+}
+
+// New vertices at their offsets: the crossings of each owned edge slot in
+// order from its lower-numbered end, then the polyline vertices inside the
+// owner's triangles; each owner with new vertices records its first index.
+__global__ void __launch_bounds__(256) k_pre_mesh_vertices(OneSrc src, PreArgs P, Shared sh) {
+  const Img& d = src.d;
+  const Geo g = d.g;
+  int64_t seg;
+  int k, i0;
+  if (!pre_segment(g, sh, seg, k, i0)) return;
+  if (sh.seg_cnt[seg].x == 0) return;
+  const int64_t NV = P.gsizes[0];
+  double2* Vout = reinterpret_cast<double2*>(P.verts);
+  int64_t base = sh.seg_off[seg].x;
+  for (int j = 0; j < 4; ++j) {
+    const int i = i0 + 64 * j + (int)(threadIdx.x & 63);
+    const int64_t v = (int64_t)k * g.NI + i;
+    const uint32_t rc = i < g.NI ? P.rcount[v] : 0u;
+    const int nc = pre_rc_before(rc, 8), n = nc + pre_rc_inner(rc);
+    const int incl = wave_incl_scan_dpp(n);
+    if (n) {
+      const int64_t pos = base + (incl - n);
+      P.rbase[v] = pos;
+      const PreSlots S = pre_owner_slots(P, g, k, i);
+      int w = 0;
+      for (int q = 0; q < 8; ++q) {
+        const int cq = pre_rc_cross(rc, q);
+        if (!cq) continue;
+        PreGV A, B;
+        pre_edge_slot(P, g, k, i, S, q, A, B);
+        const PreGV& L = A.id < B.id ? A : B;
+        const PreGV& H = A.id < B.id ? B : A;
+        double te[3], xs[3], ys[3];
+        int m = 0;
+        pre_edge_crossings(d, g, L, H, [&](const PreSeg& Sg, double t) {
+          if (m >= 3) return;
+          te[m] = t;
+          pre_crossing_xy(Sg, L, H, xs[m], ys[m]);
+          // insertion by position along the edge
+          int z = m++;
+          for (; z > 0 && te[z - 1] > te[z]; --z) {
+            const double a = te[z], bx = xs[z], by = ys[z];
+            te[z] = te[z - 1]; xs[z] = xs[z - 1]; ys[z] = ys[z - 1];
+            te[z - 1] = a; xs[z - 1] = bx; ys[z - 1] = by;
+          }
+        });
+        for (int z = 0; z < cq && z < m; ++z) {
+          const int64_t id = NV + pos + w + z;
+          if (id < P.vcap) Vout[id] = make_double2(xs[z], ys[z]);
+        }
+        w += cq;
+      }
+      int nin = 0;
+      for (int t = 0; t < 2 && nin < pre_rc_inner(rc); ++t) {
+        PreGT T[2];
+        const int m = pre_slot_tris(P, g, k, i, S, t, T);
+        for (int z = 0; z < m; ++z) {
+          PrePt in;
+          if (pre_tri_mesh(d, g, P, T[z], [](const PrePt&, const PrePt&, const PrePt&, int) {}, &in)) {
+            const int64_t id = NV + pos + nc + nin;
+            if (id < P.vcap) Vout[id] = make_double2(in.x, in.y);
+            ++nin;
+          }
+        }
+      }
+    }
+    base += __builtin_amdgcn_readlane(incl, 63);
+  }
+}
+
+// Output triangles at their offsets, with their codes.
+__global__ void __launch_bounds__(256) k_pre_mesh_triangles(OneSrc src, PreArgs P, Shared sh) {
+  const Img& d = src.d;
+  const Geo g = d.g;
+  int64_t seg;
+  int k, i0;
+  if (!pre_segment(g, sh, seg, k, i0)) return;
+  const int64_t NV = P.gsizes[0];
+  int64_t base = sh.seg_off[seg].y;
+  for (int j = 0; j < 4; ++j) {
+    const int i = i0 + 64 * j + (int)(threadIdx.x & 63);
+    const int64_t v = (int64_t)k * g.NI + i;
+    const uint32_t rc = i < g.NI ? P.rcount[v] : 0u;
+    const int n = pre_rc_tris(rc);
+    const int incl = wave_incl_scan_dpp(n);
+    if (n) {
+      int64_t pos = base + (incl - n);
+      const PreSlots S = pre_owner_slots(P, g, k, i);
+      const int64_t vbase = (pre_rc_before(rc, 8) + pre_rc_inner(rc)) ? P.rbase[v] : 0;
+      int nin = 0;
+      for (int t = 0; t < 2; ++t) {
+        PreGT T[2];
+        const int m = pre_slot_tris(P, g, k, i, S, t, T);
+        for (int z = 0; z < m; ++z) {
+          const PreGT& TT = T[z];
+          const int64_t inner_id = NV + vbase + pre_rc_before(rc, 8) + nin;
+          auto id_of = [&](const PrePt& p) -> int64_t {
+            if (p.kind == 0) return p.a;
+            if (p.kind == 2) return inner_id;
+            for (int e = 0; e < 3; ++e) {
+              const PreGV& A = TT.c[e];
+              const PreGV& B = TT.c[(e + 1) % 3];
+              const PreGV& L = A.id < B.id ? A : B;
+              const PreGV& H = A.id < B.id ? B : A;
+              if (L.id != p.a || H.id != p.b) continue;
+              const int64_t w = TT.eo[e];
+              const uint32_t rw = P.rcount[w];
+              double tp = 0.0;
+              bool found = false;
+              pre_edge_crossings(d, g, L, H, [&](const PreSeg& Sg, double te) {
+                if (Sg.jp == p.s) {
+                  tp = te;
+                  found = true;
+                }
+              });
+              int rank = 0;
+              pre_edge_crossings(d, g, L, H, [&](const PreSeg&, double te) { rank += te < tp ? 1 : 0; });
+              if (!found || rank >= pre_rc_cross(rw, TT.es[e])) pre_error(P);
+              return NV + P.rbase[w] + pre_rc_before(rw, TT.es[e]) + rank;
+            }
+            pre_error(P);
+            return 0;
+          };
+          PrePt in;
+          nin += pre_tri_mesh(d, g, P, TT, [&](const PrePt& a, const PrePt& b, const PrePt& c, int code) {
+            if (pos < P.otcap) {
+              int32_t* o = P.otris + 3 * pos;
+              o[0] = (int32_t)id_of(a);
+              o[1] = (int32_t)id_of(b);
+              o[2] = (int32_t)id_of(c);
+              P.ocodes[pos] = (uint8_t)code;
+            }
+            ++pos;
+          }, &in);
+        }
+      }
+    }
+    base += __builtin_amdgcn_readlane(incl, 63);
+  }
+}
+
+__global__ void k_pre_mesh_sizes(PreArgs P, Shared sh, int64_t* out) {
+  const longlong4 tot = sh.seg_off[sh.nseg];
+  const int64_t NV = P.gsizes[0];
+  out[0] = NV + tot.x;        // vertices
+  out[1] = tot.y;             // triangles
+  out[2] = P.gsizes[2];       // snapped
+  out[3] = P.gsizes[3];       // repelled
+  out[4] = P.gsizes[4];       // inserted
+  out[6] = NV;                // grid vertices
+  out[7] = tot.z;             // cut grid triangles
+  int64_t st = P.gsizes[5];
+  if (st == SBMT_OK || st == SBMT_E_CAPACITY) {
+    if (P.counts[2]) st = SBMT_E_PROTOCOL;
+    else if (out[0] > P.vcap || out[1] > P.otcap) st = SBMT_E_CAPACITY;
+    else st = SBMT_OK;
+  }
+  if (out[0] > 0x7fffffffLL) st = SBMT_E_INDEX_OVERFLOW;
+  out[5] = st;
+}
+
 __global__ void k_copy_sizes(const int64_t* __restrict__ s, int64_t n4, int64_t* __restrict__ user) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q < n4) user[q] = s[q];
@@ -2678,10 +3514,12 @@ __global__ void k_copy_sizes(const int64_t* __restrict__ s, int64_t n4, int64_t*
 // indices, and the counters and sizes.
 struct PreLayout {
   CallLayout L;
-  size_t off_mid, off_split, off_flags, off_ins, off_counts, off_out, total;
+  size_t off_mid, off_split, off_flags, off_ins, off_counts, off_out, off_snap, total;
+  // the retriangulation (sbmt_preprocess_mesh): grid on-polyline bytes, per-owner counts and bases, sizes
+  size_t off_onp, off_rcount, off_rbase, off_out2;
   int64_t nmid, nown;
 };
-static sbmt_status pre_layout(const sbmt_image* img, bool need_ptr, PreLayout* P) {
+static sbmt_status pre_layout(const sbmt_image* img, bool need_ptr, PreLayout* P, bool mesh = false) {
   sbmt_status st = make_call_layout(img, 1, 0, need_ptr, &P->L);
   if (st != SBMT_OK) return st;
   const Geo& g = P->L.g[0];
@@ -2701,6 +3539,19 @@ static sbmt_status pre_layout(const sbmt_image* img, bool need_ptr, PreLayout* P
   off = align256(off + kPreCounts * 8);
   P->off_out = off;
   off = align256(off + 8 * 8);
+  P->off_snap = off;
+  off = align256(off + (size_t)P->nown * 4);
+  P->off_onp = P->off_rcount = P->off_rbase = P->off_out2 = 0;
+  if (mesh) {
+    P->off_onp = off;
+    off = align256(off + (size_t)(P->nown + P->nmid));
+    P->off_rcount = off;
+    off = align256(off + (size_t)P->nown * 4);
+    P->off_rbase = off;
+    off = align256(off + (size_t)P->nown * 8);
+    P->off_out2 = off;
+    off = align256(off + 8 * 8);
+  }
   P->total = off;
   return SBMT_OK;
 }
@@ -3231,39 +4082,35 @@ sbmt_status sbmt_pre_query(const sbmt_image* img, size_t* workspace_bytes, int64
   return SBMT_OK;
 }
 
-sbmt_status sbmt_preprocess(sbmt_handle h, const sbmt_image* img, double a, double b, double c, void* workspace,
-                            size_t ws_bytes, double* verts, uint8_t* on_polyline, int64_t vert_cap, int32_t* tris,
-                            int64_t tri_cap, int64_t* counts, void* stream) {
-  if (!h || !counts || vert_cap < 0 || tri_cap < 0) return SBMT_E_INVALID_ARG;
-  if ((vert_cap > 0 && (!verts || !on_polyline)) || (tri_cap > 0 && !tris)) return SBMT_E_INVALID_ARG;
-  PreLayout PL;
-  sbmt_status st = pre_layout(img, true, &PL);
-  if (st != SBMT_OK) return st;
-  const Geo& g = PL.L.g[0];
-  if (!pre_thresholds_ok(a, b, c, (double)g.h / g.U)) return SBMT_E_INVALID_ARG;
-  if (!workspace || ws_bytes < PL.total) return SBMT_E_WORKSPACE;
-  // every vertex of the lattice needs room before the kernels write it
-  if (vert_cap < PL.nown) return SBMT_E_CAPACITY;
-  hipStream_t s = (hipStream_t)stream;
-  char* w = (char*)workspace;
-  const Shared sh = shared_of(PL.L, workspace, 1);
-  OneSrc src;
-  src.d = img_of(PL.L, 0, *img, workspace, nullptr);
+// Arguments of the preprocessing kernels over workspace w (layout PL).
+static PreArgs pre_args(const PreLayout& PL, char* w, double a, double b, double c) {
   PreArgs P;
   P.a = a;
   P.b = b;
   P.c = c;
-  P.verts = verts;
-  P.on_polyline = on_polyline;
-  P.tris = tris;
-  P.vcap = vert_cap;
-  P.tcap = tri_cap;
+  P.verts = nullptr;
+  P.on_polyline = nullptr;
+  P.tris = nullptr;
+  P.vcap = P.tcap = 0;
   P.mid = (uint8_t*)(w + PL.off_mid);
   P.split = (int32_t*)(w + PL.off_split);
   P.flags = (uint8_t*)(w + PL.off_flags);
   P.ins_base = (int64_t*)(w + PL.off_ins);
   P.counts = (int64_t*)(w + PL.off_counts);
-  int64_t* out = (int64_t*)(w + PL.off_out);
+  P.snap_mid = (int32_t*)(w + PL.off_snap);
+  P.rcount = PL.off_rcount ? (uint32_t*)(w + PL.off_rcount) : nullptr;
+  P.rbase = PL.off_rbase ? (int64_t*)(w + PL.off_rbase) : nullptr;
+  P.gsizes = (const int64_t*)(w + PL.off_out);
+  P.otris = nullptr;
+  P.ocodes = nullptr;
+  P.otcap = 0;
+  return P;
+}
+// Steps 1-3 (the grid, with its triangles when `triangles`), then the sizes
+// record at PL.off_out.
+static sbmt_status pre_launch_grid(const PreLayout& PL, const OneSrc& src, const PreArgs& P, const Shared& sh, char* w,
+                                   bool triangles, hipStream_t s) {
+  const Geo& g = PL.L.g[0];
   const int64_t ncb = PL.L.tab[PL.L.n];
   const int64_t nseg = PL.L.nseg;
   const int64_t nwb = ((int64_t)(g.CH + 1) * g.wpr + 255) / 256;  // raster words of rows -1 .. CH - 1
@@ -3282,13 +4129,93 @@ sbmt_status sbmt_preprocess(sbmt_handle h, const sbmt_image* img, double a, doub
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, sh);
   hipLaunchKernelGGL(k_scan_apply, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
   hipLaunchKernelGGL(k_pre_inserted, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
-  hipLaunchKernelGGL(k_pre_triangles, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
-  hipLaunchKernelGGL(k_pre_sizes, dim3(1), dim3(1), 0, s, src, P, sh, out);
-  if (hipGetLastError() != hipSuccess) return SBMT_E_DEVICE;
-  if (hipMemcpyAsync(h->pinned, out, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  if (triangles) hipLaunchKernelGGL(k_pre_triangles, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_sizes, dim3(1), dim3(1), 0, s, src, P, sh, (int64_t*)(w + PL.off_out));
+  return hipGetLastError() == hipSuccess ? SBMT_OK : SBMT_E_DEVICE;
+}
+static sbmt_status pre_read_sizes(sbmt_handle h, const int64_t* dev, int n, int64_t* counts, hipStream_t s) {
+  if (hipMemcpyAsync(h->pinned, dev, n * sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return SBMT_E_DEVICE;
-  for (int j = 0; j < 6; ++j) counts[j] = h->pinned[j];
+  for (int j = 0; j < n; ++j) counts[j] = h->pinned[j];
+  return SBMT_OK;
+}
+
+sbmt_status sbmt_preprocess(sbmt_handle h, const sbmt_image* img, double a, double b, double c, void* workspace,
+                            size_t ws_bytes, double* verts, uint8_t* on_polyline, int64_t vert_cap, int32_t* tris,
+                            int64_t tri_cap, int64_t* counts, void* stream) {
+  if (!h || !counts || vert_cap < 0 || tri_cap < 0) return SBMT_E_INVALID_ARG;
+  if ((vert_cap > 0 && (!verts || !on_polyline)) || (tri_cap > 0 && !tris)) return SBMT_E_INVALID_ARG;
+  PreLayout PL;
+  sbmt_status st = pre_layout(img, true, &PL);
+  if (st != SBMT_OK) return st;
+  const Geo& g = PL.L.g[0];
+  if (!pre_thresholds_ok(a, b, c, (double)g.h / g.U)) return SBMT_E_INVALID_ARG;
+  if (!workspace || ws_bytes < PL.total) return SBMT_E_WORKSPACE;
+  // every vertex of the lattice needs room before the kernels write it
+  if (vert_cap < PL.nown) return SBMT_E_CAPACITY;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)workspace;
+  const Shared sh = shared_of(PL.L, workspace, 1);
+  OneSrc src;
+  src.d = img_of(PL.L, 0, *img, workspace, nullptr);
+  PreArgs P = pre_args(PL, w, a, b, c);
+  P.verts = verts;
+  P.on_polyline = on_polyline;
+  P.tris = tris;
+  P.vcap = vert_cap;
+  P.tcap = tri_cap;
+  if ((st = pre_launch_grid(PL, src, P, sh, w, true, s)) != SBMT_OK) return st;
+  if ((st = pre_read_sizes(h, (const int64_t*)(w + PL.off_out), 6, counts, s)) != SBMT_OK) return st;
+  return (sbmt_status)counts[5];
+}
+
+sbmt_status sbmt_pre_mesh_query(const sbmt_image* img, size_t* workspace_bytes, int64_t* grid_vert_bound) {
+  PreLayout P;
+  sbmt_status st = pre_layout(img, false, &P, true);
+  if (st != SBMT_OK) return st;
+  if (workspace_bytes) *workspace_bytes = P.total;
+  if (grid_vert_bound) *grid_vert_bound = P.nown + P.nmid;
+  return SBMT_OK;
+}
+
+sbmt_status sbmt_preprocess_mesh(sbmt_handle h, const sbmt_image* img, double a, double b, double c, void* workspace,
+                                 size_t ws_bytes, double* verts, int64_t vert_cap, int32_t* tris, uint8_t* codes,
+                                 int64_t tri_cap, int64_t* counts, void* stream) {
+  if (!h || !counts || vert_cap < 0 || tri_cap < 0) return SBMT_E_INVALID_ARG;
+  if ((vert_cap > 0 && !verts) || (tri_cap > 0 && (!tris || !codes))) return SBMT_E_INVALID_ARG;
+  PreLayout PL;
+  sbmt_status st = pre_layout(img, true, &PL, true);
+  if (st != SBMT_OK) return st;
+  const Geo& g = PL.L.g[0];
+  if (!pre_thresholds_ok(a, b, c, (double)g.h / g.U)) return SBMT_E_INVALID_ARG;
+  if (!workspace || ws_bytes < PL.total) return SBMT_E_WORKSPACE;
+  // the grid vertices are written first and read back by the retriangulation
+  if (vert_cap < PL.nown + PL.nmid) return SBMT_E_CAPACITY;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)workspace;
+  const Shared sh = shared_of(PL.L, workspace, 1);
+  OneSrc src;
+  src.d = img_of(PL.L, 0, *img, workspace, nullptr);
+  PreArgs P = pre_args(PL, w, a, b, c);
+  P.verts = verts;
+  P.on_polyline = (uint8_t*)(w + PL.off_onp);
+  P.vcap = vert_cap;
+  P.otris = tris;
+  P.ocodes = codes;
+  P.otcap = tri_cap;
+  if ((st = pre_launch_grid(PL, src, P, sh, w, false, s)) != SBMT_OK) return st;
+  const int64_t nqb = (PL.L.nseg + 3) / 4;
+  int64_t* out2 = (int64_t*)(w + PL.off_out2);
+  hipLaunchKernelGGL(k_pre_mesh_count, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, sh);
+  hipLaunchKernelGGL(k_scan_apply, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
+  hipLaunchKernelGGL(k_pre_mesh_vertices, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_mesh_triangles, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_mesh_sizes, dim3(1), dim3(1), 0, s, P, sh, out2);
+  if (hipGetLastError() != hipSuccess) return SBMT_E_DEVICE;
+  if ((st = pre_read_sizes(h, out2, 8, counts, s)) != SBMT_OK) return st;
   return (sbmt_status)counts[5];
 }
 

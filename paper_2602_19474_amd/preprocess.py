@@ -104,3 +104,88 @@ class Preprocessor:
                                         _stream_ptr(stream))
         _lib.check(st, "sbmt_preprocess")
         return tuple(int(x) for x in self.counts[:5])
+
+
+@dataclass
+class PreMesh:
+    verts: object     # float64 [V, 2]: the grid vertices (ids 0 .. n_grid_vertices-1), then the new ones
+    tris: object      # int32 [T, 3], positive signed area
+    codes: object     # uint8 [T]: 0 grid triangle kept whole, 1 piece of a cut one
+    n_grid_vertices: int
+    n_snapped: int
+    n_repelled: int
+    n_inserted: int
+    n_cut: int
+
+
+def preprocess_mesh(bitmap, grid_h: float, a: float | None = None, b: float | None = None, c: float | None = None,
+                    stream=None, ctx=None) -> PreMesh:
+    """The mesh of Alg. 3 on a uint8 CUDA tensor [H, W]: the preprocessed grid
+    retriangulated against the polyline (waits for the stream; a first call
+    sizes the outputs, a second fills them)."""
+    import torch
+    if a is None and b is None and c is None:
+        a, b, c = paper_thresholds(grid_h)
+    if a is None or b is None or c is None:
+        raise ValueError("give all three thresholds or none")
+    ctx = ctx or context(bitmap.device.index)
+    img = _image(bitmap, grid_h, 0)
+    L = _lib.lib()
+    ws_bytes, gbound = ctypes.c_size_t(), ctypes.c_int64()
+    _lib.check(L.sbmt_pre_mesh_query(ctypes.byref(img), ctypes.byref(ws_bytes), ctypes.byref(gbound)),
+               "sbmt_pre_mesh_query")
+    dev = bitmap.device
+    ws = torch.empty(int(ws_bytes.value), dtype=torch.uint8, device=dev)
+    counts = (ctypes.c_int64 * 8)()
+    nv, nt = int(gbound.value), 0
+    for attempt in range(2):
+        verts = torch.empty((max(nv, 1), 2), dtype=torch.float64, device=dev)
+        tris = torch.empty((max(nt, 1), 3), dtype=torch.int32, device=dev)
+        codes = torch.empty((max(nt, 1),), dtype=torch.uint8, device=dev)
+        st = L.sbmt_preprocess_mesh(ctx.handle, ctypes.byref(img), float(a), float(b), float(c), ws.data_ptr(),
+                                    int(ws_bytes.value), verts.data_ptr(), verts.shape[0], tris.data_ptr(),
+                                    codes.data_ptr(), nt, counts, _stream_ptr(stream))
+        if st == 0:
+            break
+        if st != -7 or attempt == 1:
+            _lib.check(st, "sbmt_preprocess_mesh")
+        nv, nt = max(int(counts[0]), nv), int(counts[1])
+    return PreMesh(verts[:int(counts[0])], tris[:int(counts[1])], codes[:int(counts[1])], int(counts[6]),
+                   int(counts[2]), int(counts[3]), int(counts[4]), int(counts[7]))
+
+
+class MeshPreprocessor:
+    """sbmt_preprocess_mesh with workspace and outputs kept across calls (sized
+    by a first call on this image)."""
+
+    def __init__(self, bitmap, grid_h: float, a: float | None = None, b: float | None = None,
+                 c: float | None = None):
+        import torch
+        if a is None and b is None and c is None:
+            a, b, c = paper_thresholds(grid_h)
+        self.th = (float(a), float(b), float(c))
+        self.ctx = context(bitmap.device.index)
+        self.img = _image(bitmap, grid_h, 0)
+        L = _lib.lib()
+        ws_bytes, gbound = ctypes.c_size_t(), ctypes.c_int64()
+        _lib.check(L.sbmt_pre_mesh_query(ctypes.byref(self.img), ctypes.byref(ws_bytes), ctypes.byref(gbound)),
+                   "sbmt_pre_mesh_query")
+        self.ws_bytes = int(ws_bytes.value)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=bitmap.device)
+        self.counts = (ctypes.c_int64 * 8)()
+        m = preprocess_mesh(bitmap, grid_h, *self.th, ctx=self.ctx)
+        dev = bitmap.device
+        self.verts = torch.empty((max(m.verts.shape[0], int(gbound.value)), 2), dtype=torch.float64, device=dev)
+        self.tris = torch.empty((max(m.tris.shape[0], 1), 3), dtype=torch.int32, device=dev)
+        self.codes = torch.empty((max(m.tris.shape[0], 1),), dtype=torch.uint8, device=dev)
+        del m
+
+    def run(self, stream=None):
+        """One call (waits for the stream); returns (n_vertices, n_triangles, n_grid_vertices, n_cut)."""
+        a, b, c = self.th
+        st = _lib.lib().sbmt_preprocess_mesh(self.ctx.handle, ctypes.byref(self.img), a, b, c, self.ws.data_ptr(),
+                                             self.ws_bytes, self.verts.data_ptr(), self.verts.shape[0],
+                                             self.tris.data_ptr(), self.codes.data_ptr(), self.tris.shape[0],
+                                             self.counts, _stream_ptr(stream))
+        _lib.check(st, "sbmt_preprocess_mesh")
+        return int(self.counts[0]), int(self.counts[1]), int(self.counts[6]), int(self.counts[7])

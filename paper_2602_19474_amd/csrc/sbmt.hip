@@ -3038,7 +3038,11 @@ __device__ int pre_tri_mesh(const Img& d, const Geo& g, const PreArgs& P, const 
       return 0;
     }
   }
-  auto corner_pt = [&](int j) { return PrePt{0, T.c[j].id, 0, -1, T.c[j].x, T.c[j].y, 0.0}; };
+  // Points of the subdivision in a pool (corners first); pieces, the boundary
+  // cycle and the faces refer to them by index.
+  PrePt pool[8];
+  int np = 3;
+  for (int j = 0; j < 3; ++j) pool[j] = PrePt{0, T.c[j].id, 0, -1, T.c[j].x, T.c[j].y, 0.0};
   auto cross_pt = [&](int e, const PreSeg& S) {
     const PreGV& A = T.c[e];
     const PreGV& B = T.c[(e + 1) % 3];
@@ -3054,25 +3058,41 @@ __device__ int pre_tri_mesh(const Img& d, const Geo& g, const PreArgs& P, const 
     return p;
   };
   // pieces: the chain inside the triangle, from boundary to boundary
-  PrePt pc[2][3];
+  uint8_t pc[2][3];
   int pn[2] = {0, 0}, npc = 0, ncur = 0;
-  PrePt cur[3];
+  uint8_t cur[3];
+  int inner_at = -1;
   for (int q = 0; q < nsub; ++q) {
     const PreSub& sb = subs[q];
-    PrePt st = sb.c0 >= 0 ? corner_pt(sb.c0)
-                          : (sb.e0 >= 0 ? cross_pt(sb.e0, sb.S) : PrePt{2, sb.S.jp, 0, sb.S.jp, sb.S.px, sb.S.py, 0.0});
-    PrePt en = sb.c1 >= 0 ? corner_pt(sb.c1)
-                          : (sb.e1 >= 0 ? cross_pt(sb.e1, sb.S) : PrePt{2, sb.S.jq, 0, sb.S.jp, sb.S.qx, sb.S.qy, 0.0});
-    st.ct = (double)q + sb.t0;
-    en.ct = (double)q + sb.t1;
+    int st, en;
+    if (sb.c0 >= 0) {
+      st = sb.c0;
+    } else {
+      pool[np] = sb.e0 >= 0 ? cross_pt(sb.e0, sb.S) : PrePt{2, sb.S.jp, 0, sb.S.jp, sb.S.px, sb.S.py, 0.0};
+      pool[np].ct = (double)q + sb.t0;
+      st = np++;
+    }
     if (ncur == 0) {
-      cur[ncur++] = st;
-    } else if (!(st.kind == 2 && cur[ncur - 1].kind == 2 && st.a == cur[ncur - 1].a)) {
+      cur[ncur++] = (uint8_t)st;
+      // a corner point carries the chain position of the piece end it is (a
+      // corner is a piece end at most once: checked with the cycle below)
+      if (st < 3) pool[st].ct = (double)q + sb.t0;
+    } else if (!(pool[st].kind == 2 && pool[cur[ncur - 1]].kind == 2 && pool[st].a == pool[cur[ncur - 1]].a)) {
       pre_error(P);  // pieces do not join
       return 0;
+    } else {
+      --np;  // the joint is the previous end
     }
-    cur[ncur++] = en;
-    if (en.kind != 2) {
+    if (sb.c1 >= 0) {
+      en = sb.c1;
+      pool[en].ct = (double)q + sb.t1;
+    } else {
+      pool[np] = sb.e1 >= 0 ? cross_pt(sb.e1, sb.S) : PrePt{2, sb.S.jq, 0, sb.S.jp, sb.S.qx, sb.S.qy, 0.0};
+      pool[np].ct = (double)q + sb.t1;
+      en = np++;
+    }
+    cur[ncur++] = (uint8_t)en;
+    if (pool[en].kind != 2) {
       for (int z = 0; z < ncur; ++z) pc[npc][z] = cur[z];
       pn[npc++] = ncur;
       ncur = 0;
@@ -3083,23 +3103,23 @@ __device__ int pre_tri_mesh(const Img& d, const Geo& g, const PreArgs& P, const 
     return 0;
   }
   int ninner = 0;
-  for (int q = 0; q < npc; ++q)
-    for (int z = 0; z < pn[q]; ++z)
-      if (pc[q][z].kind == 2) {
-        ++ninner;
-        *inner = pc[q][z];
-      }
+  for (int z = 3; z < np; ++z)
+    if (pool[z].kind == 2) {
+      ++ninner;
+      inner_at = z;
+    }
   if (ninner > 1) {
     pre_error(P);
     return 0;
   }
+  if (inner_at >= 0) *inner = pool[inner_at];
   // boundary cycle: the corners and the piece ends on each edge, in order
-  PrePt cyc[8];
-  int cpiece[8], cend[8];
+  uint8_t cyc[8];
+  int8_t cpiece[8], cend[8];
   double cpos[8];
   int n = 0;
   for (int j = 0; j < 3; ++j) {
-    cyc[n] = corner_pt(j);
+    cyc[n] = (uint8_t)j;
     cpiece[n] = -1;
     cend[n] = -1;
     cpos[n] = 3.0 * j;
@@ -3107,17 +3127,15 @@ __device__ int pre_tri_mesh(const Img& d, const Geo& g, const PreArgs& P, const 
   }
   for (int q = 0; q < npc; ++q)
     for (int end = 0; end < 2; ++end) {
-      const PrePt& p = end == 0 ? pc[q][0] : pc[q][pn[q] - 1];
+      const int pi = end == 0 ? pc[q][0] : pc[q][pn[q] - 1];
+      const PrePt& p = pool[pi];
       if (p.kind == 0) {
-        for (int z = 0; z < 3; ++z)
-          if (cyc[z].a == p.a) {
-            if (cpiece[z] >= 0) {  // two pieces at one corner
-              pre_error(P);
-              return 0;
-            }
-            cpiece[z] = q;
-            cend[z] = end;
-          }
+        if (cpiece[pi] >= 0) {  // two pieces at one corner
+          pre_error(P);
+          return 0;
+        }
+        cpiece[pi] = (int8_t)q;
+        cend[pi] = (int8_t)end;
         continue;
       }
       double pos = -1.0;
@@ -3138,21 +3156,21 @@ __device__ int pre_tri_mesh(const Img& d, const Geo& g, const PreArgs& P, const 
         pre_error(P);
         return 0;
       }
-      cyc[n] = p;
-      cpiece[n] = q;
-      cend[n] = end;
+      cyc[n] = (uint8_t)pi;
+      cpiece[n] = (int8_t)q;
+      cend[n] = (int8_t)end;
       cpos[n] = pos;
       ++n;
     }
   for (int a = 1; a < n; ++a)  // insertion sort by position
     for (int b = a; b > 0 && cpos[b] < cpos[b - 1]; --b) {
-      const PrePt tp = cyc[b];
+      const uint8_t t0 = cyc[b];
       cyc[b] = cyc[b - 1];
-      cyc[b - 1] = tp;
-      const int t1 = cpiece[b];
+      cyc[b - 1] = t0;
+      const int8_t t1 = cpiece[b];
       cpiece[b] = cpiece[b - 1];
       cpiece[b - 1] = t1;
-      const int t2 = cend[b];
+      const int8_t t2 = cend[b];
       cend[b] = cend[b - 1];
       cend[b - 1] = t2;
       const double t3 = cpos[b];
@@ -3160,14 +3178,14 @@ __device__ int pre_tri_mesh(const Img& d, const Geo& g, const PreArgs& P, const 
       cpos[b - 1] = t3;
     }
   // faces: walk the cycle; at a piece end reached along the boundary, follow the piece
-  bool used[8] = {false, false, false, false, false, false, false, false};
+  uint32_t used = 0;
   for (int st = 0; st < n; ++st) {
-    if (used[st]) continue;
-    PrePt face[16];
+    if ((used >> st) & 1u) continue;
+    uint8_t face[16];
     int m = 0, side = -1, at = st;
     for (int guard = 0; guard < 64; ++guard) {
-      if (used[at]) break;
-      used[at] = true;
+      if ((used >> at) & 1u) break;
+      used |= 1u << at;
       if (m < 16) face[m] = cyc[at];
       ++m;
       const int nx = (at + 1) % n;
@@ -3213,34 +3231,32 @@ __device__ int pre_tri_mesh(const Img& d, const Geo& g, const PreArgs& P, const 
     // the template rule on this foreground face
     int apex = -1;
     for (int j = 0; j < m; ++j)
-      if (face[j].kind == 2) apex = j;
+      if (pool[face[j]].kind == 2) apex = j;
     if (apex < 0 && m == 4 && npc == 2) {
       bool corners = false;
-      for (int j = 0; j < m; ++j) corners = corners || face[j].kind == 0;
+      for (int j = 0; j < m; ++j) corners = corners || face[j] < 3;
       if (!corners) {
         // the middle quadrilateral between two chords: diagonal joining their exits
-        const PrePt& x1 = pc[0][pn[0] - 1];
+        const int x1 = pc[0][pn[0] - 1], x2 = pc[1][pn[1] - 1];
         for (int j = 0; j < m; ++j)
-          if (face[j].kind == 1 && face[j].a == x1.a && face[j].b == x1.b && face[j].s == x1.s) apex = j;
-        const PrePt& x2 = pc[1][pn[1] - 1];
-        if (apex < 0 || !(face[(apex + 2) % 4].kind == 1 && face[(apex + 2) % 4].s == x2.s &&
-                          face[(apex + 2) % 4].a == x2.a && face[(apex + 2) % 4].b == x2.b)) {
+          if (face[j] == x1) apex = j;
+        if (apex < 0 || face[(apex + 2) % 4] != x2) {
           pre_error(P);  // nested exits not opposite
           return 0;
         }
       }
     }
     if (apex < 0) {
+      // the earliest chain point: a piece point (corners only as piece ends)
       double best = 1e300;
       for (int j = 0; j < m; ++j) {
-        const bool on_chain = face[j].kind != 0 || face[j].a >= NLAT || (P.flags[face[j].a] & kPreSnapped);
-        if (!on_chain) continue;
-        double ct = 1e300;
+        const int pi = face[j];
+        bool in_piece = false;
         for (int q = 0; q < npc; ++q)
-          for (int z = 0; z < pn[q]; ++z)
-            if (pre_same(pc[q][z], face[j])) ct = pc[q][z].ct;
-        if (ct < best) {
-          best = ct;
+          for (int z = 0; z < pn[q]; ++z) in_piece = in_piece || pc[q][z] == pi;
+        if (!in_piece) continue;
+        if (pool[pi].ct < best) {
+          best = pool[pi].ct;
           apex = j;
         }
       }
@@ -3250,97 +3266,285 @@ __device__ int pre_tri_mesh(const Img& d, const Geo& g, const PreArgs& P, const 
       return 0;
     }
     for (int t = 1; t + 1 < m; ++t) {
-      const PrePt& a = face[apex];
-      const PrePt& b = face[(apex + t) % m];
-      const PrePt& c = face[(apex + t + 1) % m];
+      const PrePt& a = pool[face[apex]];
+      const PrePt& b = pool[face[(apex + t) % m]];
+      const PrePt& c = pool[face[(apex + t + 1) % m]];
       if (!((b.x - a.x) * (c.y - a.y) - (b.y - a.y) * (c.x - a.x) > 0.0)) pre_error(P);
       out(a, b, c, 1);
     }
   }
   return ninner;
+
 }
 
-// Quiet owner: the coarse samples around both of its slots (their box on the
-// lattice widened by a + b, which holds every moved or inserted corner)
-// agree, so no segment comes near and its triangles lie on that side.
-// Returns the side (0 / 1), or -1.
-__device__ int pre_owner_quiet(const Img& d, const Geo& g, const PreArgs& P, int k, int i) {
-  const double hx = pre_hx(g), lx = lat_x(g, pre_lat_X(g, k, i));
-  const double r = widen(P.a + P.b);
-  const double x0 = lx - 0.5 * hx - r, x1 = lx + hx + r, y0 = lat_y(g, k) - r, y1 = lat_y(g, k + 1) + r;
-  const int R0 = floor_index(g, y0) - 1, R1 = floor_index(g, y1) + 1;
-  const int C0 = floor_index(g, x0) - 1, C1 = floor_index(g, x1) + 1;
-  const int first = sample_at(d, g, R0, C0);
-  for (int R = R0; R <= R1; ++R)
-    for (int C = C0; C <= C1; ++C)
-      if (sample_at(d, g, R, C) != first) return -1;
-  return first;
+// Owners whose slot triangles a segment can reach: every segment marks the
+// owners whose slot box on the lattice, widened by a + b (the moves and the
+// inserted vertices stay within it), meets the segment's box.  An unmarked
+// owner is quiet: its triangles are uncut, its corners are lattice vertices
+// off the polyline, and the inside label of the owner vertex decides them.
+constexpr uint32_t kPreTouched = 64;
+__device__ void pre_touch_seg(const PreArgs& P, const Geo& g, double px, double py, double qx, double qy) {
+  const double r = widen(P.a + P.b) + 1e-9, hx = pre_hx(g);
+  const double x0 = fmin(px, qx) - r, x1 = fmax(px, qx) + r, y0 = fmin(py, qy) - r, y1 = fmax(py, qy) + r;
+  for (int k = max(0, pre_row_floor(g, y0) - 1); k <= min(g.NK - 1, pre_row_floor(g, y1)); ++k) {
+    const int ia = max(0, (int)__builtin_floor(pre_col(g, k, x0 - hx)));
+    const int ib = min(g.NI - 1, (int)__builtin_floor(pre_col(g, k, x1 + 0.5 * hx)) + 1);
+    for (int i = ia; i <= ib; ++i) {
+      const int64_t v = (int64_t)k * g.NI + i;
+      if (!(P.flags[v] & kPreTouched)) pre_flag_or(P.flags, v, kPreTouched);
+    }
+  }
+}
+__global__ void __launch_bounds__(256) k_pre_mesh_touch(OneSrc src, PreArgs P) {
+  __shared__ uint16_t lds[4][kPreDeal];
+  const Img& d = src.d;
+  const Geo g = d.g;
+  PreWord W;
+  const bool on = pre_word(d, g, W);
+  const uint32_t cells = on ? (W.dh | W.dv | (W.cur ^ W.b1)) : 0u;
+  const uint32_t base = blockIdx.x * 256u + (threadIdx.x & ~63u);
+  auto cs_of = [&](int, int j) {
+    return ((W.cur >> j) & 1u) | (((W.c1 >> j) & 1u) << 1) | (((W.b1 >> j) & 1u) << 2) | (((W.bel >> j) & 1u) << 3);
+  };
+  pre_deal(lds, cells, 0u, cs_of, [&](int sl, int, int j, uint32_t cs) {
+    int R, C0;
+    pre_word_at(g, base + sl, R, C0);
+    const uint32_t ms = ms_case((int)cs);
+    for (int q = 0; q < (int)(ms & 3u); ++q) {
+      double px, py, qx, qy;
+      cell_segment(g, R, C0 + j, ms, q, px, py, qx, qy);
+      pre_touch_seg(P, g, px, py, qx, qy);
+    }
+  });
 }
 
-// Counts per owner (one wave per row segment, owners interleaved across
-// lanes): crossings of its edge slots, polyline vertices inside its slot
-// triangles, output triangles; per row segment: new vertices, triangles and
-// cut grid triangles.
+// Counts of a touched owner: crossings of its edge slots, polyline vertices
+// inside its slot triangles, output triangles and cut grid triangles.
+__device__ uint32_t pre_owner_counts(const Img& d, const Geo& g, const PreArgs& P, int k, int i, int& nnew, int& ntri,
+                                     int& ncut) {
+  const PreSlots S = pre_owner_slots(P, g, k, i);
+  uint32_t rc = 0;
+  int nc = 0;
+  for (int q = 0; q < 8; ++q) {
+    PreGV A, B;
+    if (!pre_edge_slot(P, g, k, i, S, q, A, B)) continue;
+    int n = 0;
+    pre_edge_crossings(d, g, A, B, [&](const PreSeg&, double) { ++n; });
+    if (n > 3) {  // more crossings of one grid edge than the numbering holds
+      pre_error(P);
+      n = 3;
+    }
+    rc |= (uint32_t)n << (2 * q);
+    nc += n;
+  }
+  int nin = 0, nt = 0, cutn = 0;
+  for (int t = 0; t < 2; ++t) {
+    PreGT T[2];
+    const int m = pre_slot_tris(P, g, k, i, S, t, T);
+    for (int z = 0; z < m; ++z) {
+      PrePt in;
+      bool cut = false;
+      nin += pre_tri_mesh(d, g, P, T[z], [&](const PrePt&, const PrePt&, const PrePt&, int) { ++nt; }, &in, &cut);
+      cutn += cut ? 1 : 0;
+    }
+  }
+  if (nin > 7 || nt > 255) {
+    pre_error(P);
+    nin = min(nin, 7);
+    nt = min(nt, 255);
+  }
+  nnew = nc + nin;
+  ntri = nt;
+  ncut = cutn;
+  return rc | ((uint32_t)nin << 16) | ((uint32_t)nt << 19);
+}
+
+// The new vertices of a touched owner, from index NV + pos.
+__device__ void pre_owner_vertices(const Img& d, const Geo& g, const PreArgs& P, int k, int i, uint32_t rc,
+                                   int64_t pos, int64_t NV) {
+  double2* Vout = reinterpret_cast<double2*>(P.verts);
+  const PreSlots S = pre_owner_slots(P, g, k, i);
+  const int nc = pre_rc_before(rc, 8);
+  int w = 0;
+  for (int q = 0; q < 8; ++q) {
+    const int cq = pre_rc_cross(rc, q);
+    if (!cq) continue;
+    PreGV A, B;
+    pre_edge_slot(P, g, k, i, S, q, A, B);
+    const PreGV& L = A.id < B.id ? A : B;
+    const PreGV& H = A.id < B.id ? B : A;
+    double te[3], xs[3], ys[3];
+    int m = 0;
+    pre_edge_crossings(d, g, L, H, [&](const PreSeg& Sg, double t) {
+      if (m >= 3) return;
+      te[m] = t;
+      pre_crossing_xy(Sg, L, H, xs[m], ys[m]);
+      for (int z = m++; z > 0 && te[z - 1] > te[z]; --z) {  // by position along the edge
+        const double a = te[z], bx = xs[z], by = ys[z];
+        te[z] = te[z - 1];
+        xs[z] = xs[z - 1];
+        ys[z] = ys[z - 1];
+        te[z - 1] = a;
+        xs[z - 1] = bx;
+        ys[z - 1] = by;
+      }
+    });
+    for (int z = 0; z < cq && z < m; ++z) {
+      const int64_t id = NV + pos + w + z;
+      if (id < P.vcap) Vout[id] = make_double2(xs[z], ys[z]);
+    }
+    w += cq;
+  }
+  int nin = 0;
+  for (int t = 0; t < 2 && nin < pre_rc_inner(rc); ++t) {
+    PreGT T[2];
+    const int m = pre_slot_tris(P, g, k, i, S, t, T);
+    for (int z = 0; z < m; ++z) {
+      PrePt in;
+      if (pre_tri_mesh(d, g, P, T[z], [](const PrePt&, const PrePt&, const PrePt&, int) {}, &in)) {
+        const int64_t id = NV + pos + nc + nin;
+        if (id < P.vcap) Vout[id] = make_double2(in.x, in.y);
+        ++nin;
+      }
+    }
+  }
+}
+
+// The output triangles of a touched owner, from position pos.
+__device__ void pre_owner_triangles(const Img& d, const Geo& g, const PreArgs& P, int k, int i, uint32_t rc,
+                                    int64_t pos, int64_t NV) {
+  const int64_t v = (int64_t)k * g.NI + i;
+  const PreSlots S = pre_owner_slots(P, g, k, i);
+  const int64_t vbase = (pre_rc_before(rc, 8) + pre_rc_inner(rc)) ? P.rbase[v] : 0;
+  int nin = 0;
+  for (int t = 0; t < 2; ++t) {
+    PreGT T[2];
+    const int m = pre_slot_tris(P, g, k, i, S, t, T);
+    for (int z = 0; z < m; ++z) {
+      const PreGT& TT = T[z];
+      const int64_t inner_id = NV + vbase + pre_rc_before(rc, 8) + nin;
+      auto id_of = [&](const PrePt& p) -> int64_t {
+        if (p.kind == 0) return p.a;
+        if (p.kind == 2) return inner_id;
+        for (int e = 0; e < 3; ++e) {
+          const PreGV& A = TT.c[e];
+          const PreGV& B = TT.c[(e + 1) % 3];
+          const PreGV& L = A.id < B.id ? A : B;
+          const PreGV& H = A.id < B.id ? B : A;
+          if (L.id != p.a || H.id != p.b) continue;
+          const int64_t w = TT.eo[e];
+          const uint32_t rw = P.rcount[w];
+          double tp = 0.0;
+          bool found = false;
+          int below = 0;
+          double tes[4];
+          int nte = 0;
+          pre_edge_crossings(d, g, L, H, [&](const PreSeg& Sg, double te) {
+            if (Sg.jp == p.s) {
+              tp = te;
+              found = true;
+            }
+            if (nte < 4) tes[nte++] = te;
+          });
+          for (int z2 = 0; z2 < nte; ++z2) below += tes[z2] < tp ? 1 : 0;
+          if (!found || below >= pre_rc_cross(rw, TT.es[e])) pre_error(P);
+          return NV + P.rbase[w] + pre_rc_before(rw, TT.es[e]) + below;
+        }
+        pre_error(P);
+        return 0;
+      };
+      PrePt in;
+      nin += pre_tri_mesh(d, g, P, TT, [&](const PrePt& a, const PrePt& b, const PrePt& c, int code) {
+        if (pos < P.otcap) {
+          int32_t* o = P.otris + 3 * pos;
+          o[0] = (int32_t)id_of(a);
+          o[1] = (int32_t)id_of(b);
+          o[2] = (int32_t)id_of(c);
+          P.ocodes[pos] = (uint8_t)code;
+        }
+        ++pos;
+      }, &in);
+    }
+  }
+}
+
+// The mesh kernels run one wave per row segment (owners interleaved across
+// lanes); quiet owners are done in place, touched ones are gathered in LDS
+// and finished by the whole block, so that the boundary work runs on full
+// waves.  List entries: wave << 10 | owner offset in its segment.
+__device__ __forceinline__ void pre_list_push(int* list, int* nlist, bool act, int entry, int* rel, int relv) {
+  const unsigned long long bal = __ballot(act);
+  if (!bal) return;
+  int base = 0;
+  if ((threadIdx.x & 63) == 0) base = atomicAdd(nlist, (int)__popcll(bal));
+  base = __shfl(base, 0);
+  if (act) {
+    list[base + lanes_below(bal)] = entry;
+    if (rel) rel[base + lanes_below(bal)] = relv;
+  }
+}
+__device__ __forceinline__ void pre_list_owner(const Geo& g, int entry, int& k, int& i) {
+  const uint32_t sg = blockIdx.x * 4u + (uint32_t)(entry >> 10);
+  const uint32_t kk = sg / (uint32_t)g.NCB;
+  k = (int)kk;
+  i = (int)(sg - kk * (uint32_t)g.NCB) * kCB + (entry & 1023);
+}
+
 __global__ void __launch_bounds__(256) k_pre_mesh_count(OneSrc src, PreArgs P, Shared sh) {
+  __shared__ int list[4 * kCB];
+  __shared__ int nlist;
+  __shared__ int sums[4][3];
   const Img& d = src.d;
   const Geo g = d.g;
   int64_t seg;
   int k, i0;
-  if (!pre_segment(g, sh, seg, k, i0)) return;
-  int nnew = 0, ntri = 0, ncut = 0;
-  for (int j = 0; j < 4; ++j) {
-    const int i = i0 + 64 * j + (int)(threadIdx.x & 63);
-    if (i >= g.NI) break;
-    const int64_t v = (int64_t)k * g.NI + i;
-    const PreSlots S = pre_owner_slots(P, g, k, i);
-    uint32_t rc = 0;
-    const int quiet = pre_owner_quiet(d, g, P, k, i);
-    if (quiet >= 0) {
-      const int nt = quiet ? (int)S.ok[0] + (int)S.ok[1] : 0;
-      rc = (uint32_t)nt << 19;
-      ntri += nt;
-    } else {
-      int nc = 0;
-      for (int q = 0; q < 8; ++q) {
-        PreGV A, B;
-        if (!pre_edge_slot(P, g, k, i, S, q, A, B)) continue;
-        int n = 0;
-        pre_edge_crossings(d, g, A, B, [&](const PreSeg&, double) { ++n; });
-        if (n > 3) {  // more crossings of one grid edge than the numbering holds
-          pre_error(P);
-          n = 3;
-        }
-        rc |= (uint32_t)n << (2 * q);
-        nc += n;
-      }
-      int nin = 0, nt = 0;
-      for (int t = 0; t < 2; ++t) {
-        PreGT T[2];
-        const int m = pre_slot_tris(P, g, k, i, S, t, T);
-        for (int z = 0; z < m; ++z) {
-          PrePt in;
-          bool cut = false;
-          nin += pre_tri_mesh(d, g, P, T[z], [&](const PrePt&, const PrePt&, const PrePt&, int) { ++nt; }, &in, &cut);
-          ncut += cut ? 1 : 0;
+  const bool on = pre_segment(g, sh, seg, k, i0);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (threadIdx.x == 0) nlist = 0;
+  if (threadIdx.x < 12) sums[threadIdx.x / 3][threadIdx.x % 3] = 0;
+  __syncthreads();
+  int ntri = 0;
+  if (on) {
+    const double y = lat_y(g, k);
+    for (int j = 0; j < 4; ++j) {
+      const int i = i0 + 64 * j + lane;
+      bool heavy = false;
+      if (i < g.NI) {
+        const int64_t v = (int64_t)k * g.NI + i;
+        if (P.flags[v] & kPreTouched) {
+          heavy = true;
+        } else {
+          const int nt = pre_inside_point(d, g, lat_x(g, pre_lat_X(g, k, i)), y)
+                             ? (int)pre_slot_ok(g, k, i, 0) + (int)pre_slot_ok(g, k, i, 1)
+                             : 0;
+          P.rcount[v] = (uint32_t)nt << 19;
+          ntri += nt;
         }
       }
-      if (nin > 7 || nt > 255) {
-        pre_error(P);
-        nin = min(nin, 7);
-        nt = min(nt, 255);
-      }
-      rc |= ((uint32_t)nin << 16) | ((uint32_t)nt << 19);
-      nnew += nc + nin;
-      ntri += nt;
+      pre_list_push(list, &nlist, heavy, (wv << 10) | (64 * j + lane), nullptr, 0);
     }
-    P.rcount[v] = rc;
   }
-  const int sn = __builtin_amdgcn_readlane(wave_incl_scan_dpp(nnew), 63);
-  const int st = __builtin_amdgcn_readlane(wave_incl_scan_dpp(ntri), 63);
-  const int sc = __builtin_amdgcn_readlane(wave_incl_scan_dpp(ncut), 63);
-  if ((threadIdx.x & 63) == 0) {
-    sh.seg_cnt[seg] = make_int4(sn, st, sc, 0);
-    sh.seg_slow[seg] = 0ull;
+  const int tot = __builtin_amdgcn_readlane(wave_incl_scan_dpp(ntri), 63);
+  if (lane == 0 && tot) atomicAdd(&sums[wv][1], tot);
+  __syncthreads();
+  const int n = nlist;
+  for (int q = (int)threadIdx.x; q < n; q += 256) {
+    int kk, ii;
+    pre_list_owner(g, list[q], kk, ii);
+    int nnew, nt, nc;
+    P.rcount[(int64_t)kk * g.NI + ii] = pre_owner_counts(d, g, P, kk, ii, nnew, nt, nc);
+    const int w = list[q] >> 10;
+    atomicAdd(&sums[w][0], nnew);
+    atomicAdd(&sums[w][1], nt);
+    atomicAdd(&sums[w][2], nc);
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int64_t sg = (int64_t)blockIdx.x * 4 + threadIdx.x;
+    if (sg < sh.nseg) {
+      sh.seg_cnt[sg] = make_int4(sums[threadIdx.x][0], sums[threadIdx.x][1], sums[threadIdx.x][2], 0);
+      sh.seg_slow[sg] = 0ull;
+    }
   }
 }
 
@@ -3348,139 +3552,98 @@ __global__ void __launch_bounds__(256) k_pre_mesh_count(OneSrc src, PreArgs P, S
 // order from its lower-numbered end, then the polyline vertices inside the
 // owner's triangles; each owner with new vertices records its first index.
 __global__ void __launch_bounds__(256) k_pre_mesh_vertices(OneSrc src, PreArgs P, Shared sh) {
+  __shared__ int list[4 * kCB];
+  __shared__ int rel[4 * kCB];
+  __shared__ int nlist;
   const Img& d = src.d;
   const Geo g = d.g;
   int64_t seg;
   int k, i0;
-  if (!pre_segment(g, sh, seg, k, i0)) return;
-  if (sh.seg_cnt[seg].x == 0) return;
-  const int64_t NV = P.gsizes[0];
-  double2* Vout = reinterpret_cast<double2*>(P.verts);
-  int64_t base = sh.seg_off[seg].x;
-  for (int j = 0; j < 4; ++j) {
-    const int i = i0 + 64 * j + (int)(threadIdx.x & 63);
-    const int64_t v = (int64_t)k * g.NI + i;
-    const uint32_t rc = i < g.NI ? P.rcount[v] : 0u;
-    const int nc = pre_rc_before(rc, 8), n = nc + pre_rc_inner(rc);
-    const int incl = wave_incl_scan_dpp(n);
-    if (n) {
-      const int64_t pos = base + (incl - n);
-      P.rbase[v] = pos;
-      const PreSlots S = pre_owner_slots(P, g, k, i);
-      int w = 0;
-      for (int q = 0; q < 8; ++q) {
-        const int cq = pre_rc_cross(rc, q);
-        if (!cq) continue;
-        PreGV A, B;
-        pre_edge_slot(P, g, k, i, S, q, A, B);
-        const PreGV& L = A.id < B.id ? A : B;
-        const PreGV& H = A.id < B.id ? B : A;
-        double te[3], xs[3], ys[3];
-        int m = 0;
-        pre_edge_crossings(d, g, L, H, [&](const PreSeg& Sg, double t) {
-          if (m >= 3) return;
-          te[m] = t;
-          pre_crossing_xy(Sg, L, H, xs[m], ys[m]);
-          // insertion by position along the edge
-          int z = m++;
-          for (; z > 0 && te[z - 1] > te[z]; --z) {
-            const double a = te[z], bx = xs[z], by = ys[z];
-            te[z] = te[z - 1]; xs[z] = xs[z - 1]; ys[z] = ys[z - 1];
-            te[z - 1] = a; xs[z - 1] = bx; ys[z - 1] = by;
-          }
-        });
-        for (int z = 0; z < cq && z < m; ++z) {
-          const int64_t id = NV + pos + w + z;
-          if (id < P.vcap) Vout[id] = make_double2(xs[z], ys[z]);
-        }
-        w += cq;
-      }
-      int nin = 0;
-      for (int t = 0; t < 2 && nin < pre_rc_inner(rc); ++t) {
-        PreGT T[2];
-        const int m = pre_slot_tris(P, g, k, i, S, t, T);
-        for (int z = 0; z < m; ++z) {
-          PrePt in;
-          if (pre_tri_mesh(d, g, P, T[z], [](const PrePt&, const PrePt&, const PrePt&, int) {}, &in)) {
-            const int64_t id = NV + pos + nc + nin;
-            if (id < P.vcap) Vout[id] = make_double2(in.x, in.y);
-            ++nin;
-          }
-        }
-      }
+  const bool on = pre_segment(g, sh, seg, k, i0) && sh.seg_cnt[seg].x > 0;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (threadIdx.x == 0) nlist = 0;
+  __syncthreads();
+  if (on) {
+    int acc = 0;
+    for (int j = 0; j < 4; ++j) {
+      const int i = i0 + 64 * j + lane;
+      const int64_t v = (int64_t)k * g.NI + i;
+      const uint32_t rc = i < g.NI ? P.rcount[v] : 0u;
+      const int n = pre_rc_before(rc, 8) + pre_rc_inner(rc);
+      const int incl = wave_incl_scan_dpp(n);
+      if (n) P.rbase[v] = sh.seg_off[seg].x + acc + (incl - n);
+      pre_list_push(list, &nlist, n > 0, (wv << 10) | (64 * j + lane), rel, acc + (incl - n));
+      acc += __builtin_amdgcn_readlane(incl, 63);
     }
-    base += __builtin_amdgcn_readlane(incl, 63);
+  }
+  __syncthreads();
+  const int n = nlist;
+  if (n == 0) return;
+  const int64_t NV = P.gsizes[0];
+  for (int q = (int)threadIdx.x; q < n; q += 256) {
+    int kk, ii;
+    pre_list_owner(g, list[q], kk, ii);
+    const int64_t sg = (int64_t)blockIdx.x * 4 + (list[q] >> 10);
+    const uint32_t rc = P.rcount[(int64_t)kk * g.NI + ii];
+    pre_owner_vertices(d, g, P, kk, ii, rc, sh.seg_off[sg].x + rel[q], NV);
   }
 }
 
-// Output triangles at their offsets, with their codes.
+// Output triangles at their offsets, with their codes: a quiet owner's slots
+// as they are (code 0), a touched owner's by the retriangulation.
 __global__ void __launch_bounds__(256) k_pre_mesh_triangles(OneSrc src, PreArgs P, Shared sh) {
+  __shared__ int list[4 * kCB];
+  __shared__ int rel[4 * kCB];
+  __shared__ int nlist;
   const Img& d = src.d;
   const Geo g = d.g;
   int64_t seg;
   int k, i0;
-  if (!pre_segment(g, sh, seg, k, i0)) return;
-  const int64_t NV = P.gsizes[0];
-  int64_t base = sh.seg_off[seg].y;
-  for (int j = 0; j < 4; ++j) {
-    const int i = i0 + 64 * j + (int)(threadIdx.x & 63);
-    const int64_t v = (int64_t)k * g.NI + i;
-    const uint32_t rc = i < g.NI ? P.rcount[v] : 0u;
-    const int n = pre_rc_tris(rc);
-    const int incl = wave_incl_scan_dpp(n);
-    if (n) {
-      int64_t pos = base + (incl - n);
-      const PreSlots S = pre_owner_slots(P, g, k, i);
-      const int64_t vbase = (pre_rc_before(rc, 8) + pre_rc_inner(rc)) ? P.rbase[v] : 0;
-      int nin = 0;
-      for (int t = 0; t < 2; ++t) {
-        PreGT T[2];
-        const int m = pre_slot_tris(P, g, k, i, S, t, T);
-        for (int z = 0; z < m; ++z) {
-          const PreGT& TT = T[z];
-          const int64_t inner_id = NV + vbase + pre_rc_before(rc, 8) + nin;
-          auto id_of = [&](const PrePt& p) -> int64_t {
-            if (p.kind == 0) return p.a;
-            if (p.kind == 2) return inner_id;
-            for (int e = 0; e < 3; ++e) {
-              const PreGV& A = TT.c[e];
-              const PreGV& B = TT.c[(e + 1) % 3];
-              const PreGV& L = A.id < B.id ? A : B;
-              const PreGV& H = A.id < B.id ? B : A;
-              if (L.id != p.a || H.id != p.b) continue;
-              const int64_t w = TT.eo[e];
-              const uint32_t rw = P.rcount[w];
-              double tp = 0.0;
-              bool found = false;
-              pre_edge_crossings(d, g, L, H, [&](const PreSeg& Sg, double te) {
-                if (Sg.jp == p.s) {
-                  tp = te;
-                  found = true;
-                }
-              });
-              int rank = 0;
-              pre_edge_crossings(d, g, L, H, [&](const PreSeg&, double te) { rank += te < tp ? 1 : 0; });
-              if (!found || rank >= pre_rc_cross(rw, TT.es[e])) pre_error(P);
-              return NV + P.rbase[w] + pre_rc_before(rw, TT.es[e]) + rank;
-            }
-            pre_error(P);
-            return 0;
-          };
-          PrePt in;
-          nin += pre_tri_mesh(d, g, P, TT, [&](const PrePt& a, const PrePt& b, const PrePt& c, int code) {
-            if (pos < P.otcap) {
-              int32_t* o = P.otris + 3 * pos;
-              o[0] = (int32_t)id_of(a);
-              o[1] = (int32_t)id_of(b);
-              o[2] = (int32_t)id_of(c);
-              P.ocodes[pos] = (uint8_t)code;
-            }
-            ++pos;
-          }, &in);
+  const bool on = pre_segment(g, sh, seg, k, i0);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (threadIdx.x == 0) nlist = 0;
+  __syncthreads();
+  if (on) {
+    const int64_t t0 = sh.seg_off[seg].y;
+    const int o = k & 1;
+    int acc = 0;
+    for (int j = 0; j < 4; ++j) {
+      const int i = i0 + 64 * j + lane;
+      const int64_t v = (int64_t)k * g.NI + i;
+      const uint32_t rc = i < g.NI ? P.rcount[v] : 0u;
+      const int n = pre_rc_tris(rc);
+      const int incl = wave_incl_scan_dpp(n);
+      const bool heavy = n > 0 && (P.flags[v] & kPreTouched);
+      if (n > 0 && !heavy) {
+        int64_t pos = t0 + acc + (incl - n);
+        for (int t = 0; t < 2; ++t) {
+          if (!pre_slot_ok(g, k, i, t)) continue;
+          const int64_t c1 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o) : v + 1;
+          const int64_t c2 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o - 1) : (int64_t)(k + 1) * g.NI + (i + o);
+          if (pos < P.otcap) {
+            int32_t* out = P.otris + 3 * pos;
+            out[0] = (int32_t)v;
+            out[1] = (int32_t)c1;
+            out[2] = (int32_t)c2;
+            P.ocodes[pos] = 0;
+          }
+          ++pos;
         }
       }
+      pre_list_push(list, &nlist, heavy, (wv << 10) | (64 * j + lane), rel, acc + (incl - n));
+      acc += __builtin_amdgcn_readlane(incl, 63);
     }
-    base += __builtin_amdgcn_readlane(incl, 63);
+  }
+  __syncthreads();
+  const int n = nlist;
+  if (n == 0) return;
+  const int64_t NV = P.gsizes[0];
+  for (int q = (int)threadIdx.x; q < n; q += 256) {
+    int kk, ii;
+    pre_list_owner(g, list[q], kk, ii);
+    const int64_t sg = (int64_t)blockIdx.x * 4 + (list[q] >> 10);
+    const uint32_t rc = P.rcount[(int64_t)kk * g.NI + ii];
+    pre_owner_triangles(d, g, P, kk, ii, rc, sh.seg_off[sg].y + rel[q], NV);
   }
 }
 
@@ -4207,6 +4370,9 @@ sbmt_status sbmt_preprocess_mesh(sbmt_handle h, const sbmt_image* img, double a,
   if ((st = pre_launch_grid(PL, src, P, sh, w, false, s)) != SBMT_OK) return st;
   const int64_t nqb = (PL.L.nseg + 3) / 4;
   int64_t* out2 = (int64_t*)(w + PL.off_out2);
+  const Geo& gg = PL.L.g[0];
+  const int64_t nwb = ((int64_t)(gg.CH + 1) * gg.wpr + 255) / 256;
+  hipLaunchKernelGGL(k_pre_mesh_touch, dim3((unsigned)nwb), dim3(256), 0, s, src, P);
   hipLaunchKernelGGL(k_pre_mesh_count, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
   hipLaunchKernelGGL(k_scan_reduce, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, sh);

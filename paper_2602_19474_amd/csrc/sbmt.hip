@@ -2704,18 +2704,52 @@ __device__ __forceinline__ int32_t pre_cell_edge_mid(const Geo& g, int R, int C,
   // cell edges: 0 top, 1 right, 2 bottom, 3 left
   return (int32_t)(e == 0 ? mid_id(g, R, C, 0) : (e == 1 ? mid_id(g, R, C + 1, 1) : (e == 2 ? mid_id(g, R + 1, C, 0) : mid_id(g, R, C, 1))));
 }
-__device__ __forceinline__ int pre_cell_case(const Img& d, const Geo& g, int R, int C) {
+// A thread's copy of the coarse samples around one owner: rows R0 .. R0+nr-1,
+// columns C0 .. C0+31 as row masks (background outside the stored raster).
+struct PreBits {
+  int R0, C0, nr;
+  uint32_t rw[6];
+};
+__device__ __forceinline__ void pre_bits_load(const Img& d, const Geo& g, int R0, int C0, int nr, PreBits& B) {
+  B.R0 = R0;
+  B.C0 = C0;
+  B.nr = nr;
+  const int cc = C0 + kRingC;
+  const int w0 = cc >> 5, sh = cc & 31;
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    const int R = R0 + r;
+    uint32_t w = 0;
+    if (r < nr && R >= 0 && R < g.CH) {
+      const uint32_t* row = d.bits + (int64_t)(R + kRing) * g.wpr;
+      const uint64_t lo = (w0 >= 0 && w0 < g.wpr) ? row[w0] : 0u;
+      const uint64_t hi = (w0 + 1 >= 0 && w0 + 1 < g.wpr) ? row[w0 + 1] : 0u;
+      w = (uint32_t)((((hi << 32) | lo) >> sh));
+      // columns outside the image are background
+      const int cfirst = C0, clast = C0 + 31;
+      if (cfirst < 0) w = -cfirst >= 32 ? 0u : (w & (~0u << (-cfirst)));
+      if (clast >= g.CW) w &= (g.CW - C0) <= 0 ? 0u : (g.CW - C0 >= 32 ? ~0u : ((1u << (g.CW - C0)) - 1u));
+    }
+    B.rw[r] = w;
+  }
+}
+__device__ __forceinline__ int pre_cell_case(const Img& d, const Geo& g, int R, int C, const PreBits* B = nullptr) {
+  if (B && R >= B->R0 && R + 1 < B->R0 + B->nr && C >= B->C0 && C + 1 < B->C0 + 32) {
+    const uint32_t t = B->rw[R - B->R0] >> (C - B->C0), u = B->rw[R + 1 - B->R0] >> (C - B->C0);
+    return (int)((t & 1u) | ((t & 2u)) | ((u & 2u) << 1) | ((u & 1u) << 3));
+  }
   return sample_at(d, g, R, C) | (sample_at(d, g, R, C + 1) << 1) | (sample_at(d, g, R + 1, C + 1) << 2) |
          (sample_at(d, g, R + 1, C) << 3);
 }
 // Calls f(seg) for every segment of the dual cells meeting [x0, x1] x [y0, y1].
 template <class F>
-__device__ __forceinline__ void pre_segs_in_box(const Img& d, const Geo& g, double x0, double x1, double y0, double y1, F f) {
+__device__ __forceinline__ void pre_segs_in_box(const Img& d, const Geo& g, double x0, double x1, double y0, double y1, F f,
+                                                const PreBits* B = nullptr) {
   const int R0 = floor_index(g, y0) - 1, R1 = floor_index(g, y1);
   const int C0 = floor_index(g, x0) - 1, C1 = floor_index(g, x1);
   for (int R = R0; R <= R1; ++R)
     for (int C = C0; C <= C1; ++C) {
-      const int cs = pre_cell_case(d, g, R, C);
+      const int cs = pre_cell_case(d, g, R, C, B);
       if (cs == 0 || cs == 15) continue;
       const uint32_t ms = ms_case(cs);
       for (int j = 0; j < (int)(ms & 3u); ++j) {
@@ -2731,9 +2765,10 @@ __device__ __forceinline__ void pre_segs_in_box(const Img& d, const Geo& g, doub
 // of its segments (segments have the foreground on their left).  Used for
 // points at a distance from the polyline (lattice corners off it, centroids of
 // uncut triangles).
-__device__ __forceinline__ int pre_inside_point(const Img& d, const Geo& g, double x, double y) {
+__device__ __forceinline__ int pre_inside_point(const Img& d, const Geo& g, double x, double y,
+                                                const PreBits* B = nullptr) {
   const int R = floor_index(g, y), C = floor_index(g, x);
-  const int cs = pre_cell_case(d, g, R, C);
+  const int cs = pre_cell_case(d, g, R, C, B);
   if (cs == 0 || cs == 15) return cs == 15;
   const uint32_t ms = ms_case(cs);
   for (int j = 0; j < (int)(ms & 3u); ++j) {
@@ -2796,13 +2831,14 @@ __device__ __forceinline__ void pre_crossing_xy(const PreSeg& S, const PreGV& L,
 }
 // Calls f(seg, te) for every segment crossing grid edge U - W.
 template <class F>
-__device__ __forceinline__ void pre_edge_crossings(const Img& d, const Geo& g, const PreGV& U, const PreGV& W, F f) {
+__device__ __forceinline__ void pre_edge_crossings(const Img& d, const Geo& g, const PreGV& U, const PreGV& W, F f,
+                                                   const PreBits* B = nullptr) {
   const double m = 1e-9;
   pre_segs_in_box(d, g, fmin(U.x, W.x) - m, fmax(U.x, W.x) + m, fmin(U.y, W.y) - m, fmax(U.y, W.y) + m,
                   [&](const PreSeg& S) {
                     double te;
                     if (pre_crosses(S, U, W, &te)) f(S, te);
-                  });
+                  }, B);
 }
 
 // A grid triangle of an owner's slot: corners, and per edge e (corner e to
@@ -2935,7 +2971,7 @@ struct PreSub {
 // polyline vertices strictly inside T (0 or 1) and sets *inner to it.
 template <class Out>
 __device__ int pre_tri_mesh(const Img& d, const Geo& g, const PreArgs& P, const PreGT& T, Out out, PrePt* inner,
-                            bool* cut = nullptr) {
+                            bool* cut = nullptr, const PreBits* Bits = nullptr) {
   const int64_t NLAT = (int64_t)g.NK * g.NI;
   double minx = T.c[0].x, maxx = T.c[0].x, miny = T.c[0].y, maxy = T.c[0].y;
   for (int j = 1; j < 3; ++j) {
@@ -3000,20 +3036,20 @@ __device__ int pre_tri_mesh(const Img& d, const Geo& g, const PreArgs& P, const 
     }
     if (nsub < 3) subs[nsub] = sb;
     ++nsub;
-  });
+  }, Bits);
   if (nsub == 0) {
     // uncut: side from a segment along an edge, a lattice corner off the
     // polyline, else the centroid
     int fg = edge_side;
     for (int j = 0; j < 3 && fg < 0; ++j)
-      if (T.c[j].id < NLAT && T.c[j].bnd < 0) fg = pre_inside_point(d, g, T.c[j].x, T.c[j].y);
+      if (T.c[j].id < NLAT && T.c[j].bnd < 0) fg = pre_inside_point(d, g, T.c[j].x, T.c[j].y, Bits);
     if (fg < 0) {
       double cx = 0, cy = 0;
       for (int j = 0; j < 3; ++j) {
         cx += T.c[j].x / 3;
         cy += T.c[j].y / 3;
       }
-      fg = pre_inside_point(d, g, cx, cy);
+      fg = pre_inside_point(d, g, cx, cy, Bits);
     }
     if (fg) {
       PrePt p[3];
@@ -3318,18 +3354,32 @@ __global__ void __launch_bounds__(256) k_pre_mesh_touch(OneSrc src, PreArgs P) {
   });
 }
 
+// The samples around owner (k, i): the box of its two slots on the lattice
+// widened by a + b (every moved or inserted corner stays in it), with the
+// cells the enumerations of its edges and triangles look at (one more row and
+// column on each side).
+__device__ __forceinline__ void pre_owner_bits(const Img& d, const Geo& g, const PreArgs& P, int k, int i, PreBits& B) {
+  const double hx = pre_hx(g), lx = lat_x(g, pre_lat_X(g, k, i));
+  const double r = widen(P.a + P.b) + 1e-9;
+  const int R0 = floor_index(g, lat_y(g, k) - r) - 1, R1 = floor_index(g, lat_y(g, k + 1) + r) + 1;
+  const int C0 = floor_index(g, lx - 0.5 * hx - r) - 1;
+  pre_bits_load(d, g, R0, C0, min(6, R1 - R0 + 1), B);
+}
+
 // Counts of a touched owner: crossings of its edge slots, polyline vertices
 // inside its slot triangles, output triangles and cut grid triangles.
 __device__ uint32_t pre_owner_counts(const Img& d, const Geo& g, const PreArgs& P, int k, int i, int& nnew, int& ntri,
                                      int& ncut) {
   const PreSlots S = pre_owner_slots(P, g, k, i);
+  PreBits Bits;
+  pre_owner_bits(d, g, P, k, i, Bits);
   uint32_t rc = 0;
   int nc = 0;
   for (int q = 0; q < 8; ++q) {
     PreGV A, B;
     if (!pre_edge_slot(P, g, k, i, S, q, A, B)) continue;
     int n = 0;
-    pre_edge_crossings(d, g, A, B, [&](const PreSeg&, double) { ++n; });
+    pre_edge_crossings(d, g, A, B, [&](const PreSeg&, double) { ++n; }, &Bits);
     if (n > 3) {  // more crossings of one grid edge than the numbering holds
       pre_error(P);
       n = 3;
@@ -3344,7 +3394,8 @@ __device__ uint32_t pre_owner_counts(const Img& d, const Geo& g, const PreArgs& 
     for (int z = 0; z < m; ++z) {
       PrePt in;
       bool cut = false;
-      nin += pre_tri_mesh(d, g, P, T[z], [&](const PrePt&, const PrePt&, const PrePt&, int) { ++nt; }, &in, &cut);
+      nin += pre_tri_mesh(d, g, P, T[z], [&](const PrePt&, const PrePt&, const PrePt&, int) { ++nt; }, &in, &cut,
+                          &Bits);
       cutn += cut ? 1 : 0;
     }
   }
@@ -3364,6 +3415,8 @@ __device__ void pre_owner_vertices(const Img& d, const Geo& g, const PreArgs& P,
                                    int64_t pos, int64_t NV) {
   double2* Vout = reinterpret_cast<double2*>(P.verts);
   const PreSlots S = pre_owner_slots(P, g, k, i);
+  PreBits Bits;
+  pre_owner_bits(d, g, P, k, i, Bits);
   const int nc = pre_rc_before(rc, 8);
   int w = 0;
   for (int q = 0; q < 8; ++q) {
@@ -3388,7 +3441,7 @@ __device__ void pre_owner_vertices(const Img& d, const Geo& g, const PreArgs& P,
         xs[z - 1] = bx;
         ys[z - 1] = by;
       }
-    });
+    }, &Bits);
     for (int z = 0; z < cq && z < m; ++z) {
       const int64_t id = NV + pos + w + z;
       if (id < P.vcap) Vout[id] = make_double2(xs[z], ys[z]);
@@ -3401,7 +3454,7 @@ __device__ void pre_owner_vertices(const Img& d, const Geo& g, const PreArgs& P,
     const int m = pre_slot_tris(P, g, k, i, S, t, T);
     for (int z = 0; z < m; ++z) {
       PrePt in;
-      if (pre_tri_mesh(d, g, P, T[z], [](const PrePt&, const PrePt&, const PrePt&, int) {}, &in)) {
+      if (pre_tri_mesh(d, g, P, T[z], [](const PrePt&, const PrePt&, const PrePt&, int) {}, &in, nullptr, &Bits)) {
         const int64_t id = NV + pos + nc + nin;
         if (id < P.vcap) Vout[id] = make_double2(in.x, in.y);
         ++nin;
@@ -3415,6 +3468,8 @@ __device__ void pre_owner_triangles(const Img& d, const Geo& g, const PreArgs& P
                                     int64_t pos, int64_t NV) {
   const int64_t v = (int64_t)k * g.NI + i;
   const PreSlots S = pre_owner_slots(P, g, k, i);
+  PreBits Bits;
+  pre_owner_bits(d, g, P, k, i, Bits);
   const int64_t vbase = (pre_rc_before(rc, 8) + pre_rc_inner(rc)) ? P.rbase[v] : 0;
   int nin = 0;
   for (int t = 0; t < 2; ++t) {
@@ -3423,32 +3478,48 @@ __device__ void pre_owner_triangles(const Img& d, const Geo& g, const PreArgs& P
     for (int z = 0; z < m; ++z) {
       const PreGT& TT = T[z];
       const int64_t inner_id = NV + vbase + pre_rc_before(rc, 8) + nin;
+      // per edge of the triangle: its owner's first crossing id and the
+      // crossings' segments in order along the edge (at most three)
+      int64_t ebase[3];
+      int32_t eseg[3][3];
+      int ecnt[3];
+      for (int e = 0; e < 3; ++e) {
+        const PreGV& A = TT.c[e];
+        const PreGV& B = TT.c[(e + 1) % 3];
+        const PreGV& L = A.id < B.id ? A : B;
+        const PreGV& H = A.id < B.id ? B : A;
+        const uint32_t rw = P.rcount[TT.eo[e]];
+        ecnt[e] = pre_rc_cross(rw, TT.es[e]);
+        ebase[e] = 0;
+        if (!ecnt[e]) continue;
+        ebase[e] = NV + P.rbase[TT.eo[e]] + pre_rc_before(rw, TT.es[e]);
+        double te[3];
+        int m = 0;
+        pre_edge_crossings(d, g, L, H, [&](const PreSeg& Sg, double t) {
+          if (m >= 3) return;
+          te[m] = t;
+          eseg[e][m] = Sg.jp;
+          for (int z = m++; z > 0 && te[z - 1] > te[z]; --z) {
+            const double t1 = te[z];
+            te[z] = te[z - 1];
+            te[z - 1] = t1;
+            const int32_t s1 = eseg[e][z];
+            eseg[e][z] = eseg[e][z - 1];
+            eseg[e][z - 1] = s1;
+          }
+        }, &Bits);
+        if (m != ecnt[e]) pre_error(P);
+        ecnt[e] = min(m, ecnt[e]);
+      }
       auto id_of = [&](const PrePt& p) -> int64_t {
         if (p.kind == 0) return p.a;
         if (p.kind == 2) return inner_id;
         for (int e = 0; e < 3; ++e) {
-          const PreGV& A = TT.c[e];
-          const PreGV& B = TT.c[(e + 1) % 3];
-          const PreGV& L = A.id < B.id ? A : B;
-          const PreGV& H = A.id < B.id ? B : A;
-          if (L.id != p.a || H.id != p.b) continue;
-          const int64_t w = TT.eo[e];
-          const uint32_t rw = P.rcount[w];
-          double tp = 0.0;
-          bool found = false;
-          int below = 0;
-          double tes[4];
-          int nte = 0;
-          pre_edge_crossings(d, g, L, H, [&](const PreSeg& Sg, double te) {
-            if (Sg.jp == p.s) {
-              tp = te;
-              found = true;
-            }
-            if (nte < 4) tes[nte++] = te;
-          });
-          for (int z2 = 0; z2 < nte; ++z2) below += tes[z2] < tp ? 1 : 0;
-          if (!found || below >= pre_rc_cross(rw, TT.es[e])) pre_error(P);
-          return NV + P.rbase[w] + pre_rc_before(rw, TT.es[e]) + below;
+          const int64_t lo = TT.c[e].id < TT.c[(e + 1) % 3].id ? TT.c[e].id : TT.c[(e + 1) % 3].id;
+          const int64_t hi = TT.c[e].id < TT.c[(e + 1) % 3].id ? TT.c[(e + 1) % 3].id : TT.c[e].id;
+          if (lo != p.a || hi != p.b) continue;
+          for (int z = 0; z < ecnt[e]; ++z)
+            if (eseg[e][z] == p.s) return ebase[e] + z;
         }
         pre_error(P);
         return 0;
@@ -3463,7 +3534,7 @@ __device__ void pre_owner_triangles(const Img& d, const Geo& g, const PreArgs& P
           P.ocodes[pos] = (uint8_t)code;
         }
         ++pos;
-      }, &in);
+      }, &in, nullptr, &Bits);
     }
   }
 }

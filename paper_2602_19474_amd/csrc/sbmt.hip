@@ -2517,17 +2517,45 @@ __global__ void __launch_bounds__(256) k_pre_count(OneSrc src, PreArgs P, Shared
   int k, i0;
   if (!pre_segment(g, sh, seg, k, i0)) return;  // wave-uniform
   int ni = 0, nt = 0;
+  PreSlots S[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {  // every flag load of the lane first
+    const int i = i0 + 64 * j + (int)(threadIdx.x & 63);
+    S[j].ok[0] = S[j].ok[1] = false;
+    if (i < g.NI) S[j] = pre_owner_slots(P, g, k, i);
+  }
+  const double2* V = reinterpret_cast<const double2*>(P.verts);
+  const int o = k & 1;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int i = i0 + 64 * j + (int)(threadIdx.x & 63);
     if (i >= g.NI) break;
-    const PreSlots S = pre_owner_slots(P, g, k, i);
-    ni += __builtin_popcount(S.fv & 7u);
+    ni += __builtin_popcount(S[j].fv & 7u);
     for (int t = 0; t < 2; ++t) {
-      if (!S.ok[t]) continue;
-      const int ns = __builtin_popcount(S.sides[t]);
+      if (!S[j].ok[t]) continue;
+      const int ns = __builtin_popcount(S[j].sides[t]);
       if (ns > 1) pre_error(P);  // a triangle with two split sides
       nt += ns ? 2 : 1;
+      if (!S[j].moved[t] && !ns) continue;
+      // positive orientation of the base triangle after the moves, and of
+      // the two triangles fanned around an inserted vertex
+      const int64_t v = (int64_t)k * g.NI + i;
+      const int64_t C1 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o) : v + 1;
+      const int64_t C2 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o - 1) : (int64_t)(k + 1) * g.NI + (i + o);
+      const double2 Cp[3] = {V[v], V[C1], V[C2]};
+      auto area2 = [](double2 A, double2 B, double2 C) {
+        return (B.x - A.x) * (C.y - A.y) - (B.y - A.y) * (C.x - A.x);
+      };
+      if (!(area2(Cp[0], Cp[1], Cp[2]) > 0.0)) pre_error(P);
+      if (!ns) continue;
+      const int js = __builtin_ctz(S[j].sides[t]);
+      const int64_t w = t == 0 ? (js == 1 ? C2 : v) : (js == 1 ? v + 1 : v);
+      const int e = t == 0 ? (js == 0 ? 2 : (js == 1 ? 0 : 1)) : js;
+      const int32_t m = P.split[3 * w + e];
+      double2 M;
+      pre_mid_xy(g, (m >> 1) / (g.CW + 2) - 1, (m >> 1) % (g.CW + 2) - 1, m & 1, M.x, M.y);
+      const double2 a0 = Cp[js], a1 = Cp[(js + 1) % 3], a2 = Cp[(js + 2) % 3];
+      if (!(area2(a0, M, a2) > 0.0) || !(area2(M, a1, a2) > 0.0)) pre_error(P);
     }
   }
   const int si = __builtin_amdgcn_readlane(wave_incl_scan_dpp(ni), 63);
@@ -2590,27 +2618,27 @@ __global__ void __launch_bounds__(256) k_pre_triangles(OneSrc src, PreArgs P, Sh
   const int lane = (int)(threadIdx.x & 63);
   int32_t* st = stage[threadIdx.x >> 6];
   const int64_t nlat = (int64_t)g.NK * g.NI;
-  const double2* V = reinterpret_cast<const double2*>(P.verts);
   const int o = k & 1;
   int64_t base = sh.seg_off[seg].y;
+  PreSlots SS[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {  // every flag load of the lane first
+    const int i = i0 + 64 * j + lane;
+    SS[j].ok[0] = SS[j].ok[1] = false;
+    if (i < g.NI) SS[j] = pre_owner_slots(P, g, k, i);
+  }
+#pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int i = i0 + 64 * j + lane;
-    PreSlots S;
+    const PreSlots& S = SS[j];
     int nt = 0;
-    if (i < g.NI) {
-      S = pre_owner_slots(P, g, k, i);
-      for (int t = 0; t < 2; ++t) nt += S.ok[t] ? (S.sides[t] ? 2 : 1) : 0;
-    }
+    for (int t = 0; t < 2; ++t) nt += S.ok[t] ? (S.sides[t] ? 2 : 1) : 0;
     const int incl = wave_incl_scan_dpp(nt);
     const int tot = __builtin_amdgcn_readlane(incl, 63);
     if (nt) {
       int pos = incl - nt;
-      auto put = [&](int64_t a, int64_t b, int64_t c, bool check) {
-        if (check && a < P.vcap && b < P.vcap && c < P.vcap) {  // else the call fails on capacity
-          const double2 A = V[a], B = V[b], C = V[c];
-          const double area2 = (B.x - A.x) * (C.y - A.y) - (B.y - A.y) * (C.x - A.x);
-          if (!(area2 > 0.0)) pre_error(P);
-        }
+      // (orientation checked by k_pre_count)
+      auto put = [&](int64_t a, int64_t b, int64_t c, bool) {
         st[3 * pos] = (int32_t)a;
         st[3 * pos + 1] = (int32_t)b;
         st[3 * pos + 2] = (int32_t)c;

@@ -698,12 +698,14 @@ __device__ __forceinline__ int pre_cell_case(const Img& d, const Geo& g, int R, 
   return sample_at(d, g, R, C) | (sample_at(d, g, R, C + 1) << 1) | (sample_at(d, g, R + 1, C + 1) << 2) |
          (sample_at(d, g, R + 1, C) << 3);
 }
-// Calls f(seg) for every segment of the dual cells meeting [x0, x1] x [y0, y1].
+// Calls f(seg) for every segment of the dual cells that contain a point of
+// [x0, x1] x [y0, y1] (callers widen their boxes by a margin, so a cell that
+// only touches the box's border holds no segment reaching inside it).
 template <class F>
 __device__ __forceinline__ void pre_segs_in_box(const Img& d, const Geo& g, double x0, double x1, double y0, double y1, F f,
                                                 const PreBits* B = nullptr) {
-  const int R0 = floor_index(g, y0) - 1, R1 = floor_index(g, y1);
-  const int C0 = floor_index(g, x0) - 1, C1 = floor_index(g, x1);
+  const int R0 = floor_index(g, y0), R1 = floor_index(g, y1);
+  const int C0 = floor_index(g, x0), C1 = floor_index(g, x1);
   for (int R = R0; R <= R1; ++R)
     for (int C = C0; C <= C1; ++C) {
       const int cs = pre_cell_case(d, g, R, C, B);

@@ -241,12 +241,17 @@ def preprocess_section(bm: np.ndarray, reps: int = 10):
         mms.append(ev[0].elapsed_time(ev[1]))
     mms = float(np.median(mms))
     malg = bm.size + 16 * mv + 13 * mt  # bitmap in; vertices, triangles and codes out
+    # quality of the mesh of Alg. 3 (the bounds of Sec. 3.3.4 at full size)
+    from paper_2602_19474_amd import post
+    q = post.mesh_quality(mp.verts[:mv], mp.tris[:mt])
+    quality = {k: q[k] for k in ("min_angle_deg", "min_area", "n_slivers", "n_equilateral", "ar_median", "ar_p95",
+                                 "ar_max", "n_invalid")}
     del mp, t
     return {"ms": ms, "grid_h": 1, "thresholds": "(0.26, 0.125, 0.183) * h / sqrt(0.45)",
             "vertices": nv, "triangles": nt, "snapped": ns, "repelled": nr, "inserted": ni,
             "triangles_per_s": nt / (ms * 1e-3), "alg_bytes": alg,
             "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "mesh": {"ms": mms, "vertices": mv, "grid_vertices": mg, "triangles": mt, "cut": mc,
+            "mesh": {"ms": mms, "vertices": mv, "grid_vertices": mg, "triangles": mt, "cut": mc, "quality": quality,
                      "triangles_per_s": mt / (mms * 1e-3), "alg_bytes": malg,
                      "hbm_frac": malg / (mms * 1e-3) / 1e9 / HBM_PEAK_GBS},
             "kernels": "profiles/noise8192_preprocess_kernel_stats.md"}

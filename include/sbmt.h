@@ -310,24 +310,25 @@ sbmt_status sbmt_preprocess(sbmt_handle h, const sbmt_image* img, double a, doub
  * foreground.  With admissible thresholds every triangle meets the angle and
  * area bounds of Sec. 3.3.4 (App. D).
  *
- * sbmt_pre_mesh_query (host only): workspace bytes, and the room the grid
- * phase needs in `verts` (grid_rows * grid_cols + 2 (coarse_h + 2)(coarse_w + 2)).
+ * sbmt_pre_mesh_query (host only): workspace bytes, and a bound on the grid
+ * vertices (grid_rows * grid_cols + 2 (coarse_h + 2)(coarse_w + 2)); the grid
+ * phase keeps them in the workspace.
  *
  * sbmt_preprocess_mesh (waits for `stream`):
  *  workspace  device, >= the query's bytes (else SBMT_E_WORKSPACE)
- *  verts      device double [vert_cap][2]: the grid vertices (lattice vertex
- *             k * grid_cols + i, then the inserted polyline vertices), then
- *             the new vertices (crossings of grid edges, polyline vertices
- *             inside grid triangles) by owner lattice vertex; grid vertices no
- *             output triangle uses are left in place.  vert_cap must be at
- *             least the query's grid bound (else SBMT_E_CAPACITY before any
- *             launch).
+ *  verts      device double [vert_cap][2]: the grid vertices some output
+ *             triangle uses, in grid order (lattice vertex k * grid_cols + i,
+ *             then the inserted polyline vertices), then the new vertices
+ *             (crossings of grid edges, polyline vertices inside grid
+ *             triangles) by owner lattice vertex.  Every row is used by a
+ *             triangle.  May be NULL with vert_cap = 0 (a sizing call).
  *  tris       device int32 [tri_cap][3], positive signed area; codes device
  *             uint8 [tri_cap]: 0 = grid triangle kept whole, 1 = piece of a
  *             cut one.  May be NULL with tri_cap = 0.
  *  counts     host int64 [8]: n_vertices (all rows of verts written),
  *             n_triangles, n_snapped, n_repelled, n_inserted, status,
- *             n_grid_vertices, n_cut (grid triangles the polyline cuts)
+ *             n_grid_vertices (grid vertices kept), n_cut (grid triangles
+ *             the polyline cuts)
  * Rows beyond a capacity are not written; SBMT_E_CAPACITY then comes with the
  * counts filled in (size the outputs from them and call again).  Errors as
  * for sbmt_preprocess. */

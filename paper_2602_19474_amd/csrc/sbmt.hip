@@ -2629,6 +2629,13 @@ static PreArgs pre_args(const PreLayout& PL, char* w, double a, double b, double
   P.otris = nullptr;
   P.ocodes = nullptr;
   P.otcap = 0;
+  P.overts = nullptr;
+  P.ovcap = 0;
+  P.used = PL.off_used ? (uint8_t*)(w + PL.off_used) : nullptr;
+  P.usedcap = PL.off_used ? PL.nown + PL.nmid : 0;
+  P.vmap = PL.off_vmap ? (int32_t*)(w + PL.off_vmap) : nullptr;
+  P.vbsum = PL.off_vbsum ? (int64_t*)(w + PL.off_vbsum) : nullptr;
+  P.nused = PL.off_nused ? (int64_t*)(w + PL.off_nused) : nullptr;
   return P;
 }
 // Steps 1-3 (the grid, with its triangles when `triangles`), then the sizes
@@ -2715,17 +2722,19 @@ sbmt_status sbmt_preprocess_mesh(sbmt_handle h, const sbmt_image* img, double a,
   const Geo& g = PL.L.g[0];
   if (!pre_thresholds_ok(a, b, c, (double)g.h / g.U)) return SBMT_E_INVALID_ARG;
   if (!workspace || ws_bytes < PL.total) return SBMT_E_WORKSPACE;
-  // the grid vertices are written first and read back by the retriangulation
-  if (vert_cap < PL.nown + PL.nmid) return SBMT_E_CAPACITY;
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)workspace;
   const Shared sh = shared_of(PL.L, workspace, 1);
   OneSrc src;
   src.d = img_of(PL.L, 0, *img, workspace, nullptr);
   PreArgs P = pre_args(PL, w, a, b, c);
-  P.verts = verts;
+  // the grid goes to the workspace; the mesh keeps the grid vertices its
+  // triangles use, then the new ones
+  P.verts = (double*)(w + PL.off_gverts);
   P.on_polyline = (uint8_t*)(w + PL.off_onp);
-  P.vcap = vert_cap;
+  P.vcap = PL.nown + PL.nmid;
+  P.overts = verts;
+  P.ovcap = vert_cap;
   P.otris = tris;
   P.ocodes = codes;
   P.otcap = tri_cap;
@@ -2739,6 +2748,10 @@ sbmt_status sbmt_preprocess_mesh(sbmt_handle h, const sbmt_image* img, double a,
   hipLaunchKernelGGL(k_scan_reduce, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, sh);
   hipLaunchKernelGGL(k_scan_apply, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
+  if (PL.nvblk > 0x7fffffffLL) return SBMT_E_INVALID_ARG;
+  hipLaunchKernelGGL(k_pre_vscan_count, dim3((unsigned)PL.nvblk), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(k_pre_vscan_top, dim3(1), dim3(256), 0, s, P, PL.nvblk);
+  hipLaunchKernelGGL(k_pre_vscan_apply, dim3((unsigned)PL.nvblk), dim3(256), 0, s, P);
   hipLaunchKernelGGL(k_pre_mesh_vertices, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
   hipLaunchKernelGGL(k_pre_mesh_triangles, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
   hipLaunchKernelGGL(k_pre_mesh_sizes, dim3(1), dim3(1), 0, s, P, sh, out2);

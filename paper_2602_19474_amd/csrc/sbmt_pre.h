@@ -43,7 +43,17 @@ struct PreArgs {
   int32_t* otris;        // [otcap][3]
   uint8_t* ocodes;       // [otcap]
   int64_t otcap;
+  // compaction of the mesh's vertices: the grid vertices some output triangle
+  // uses (marked in the count pass) keep their order and come first
+  double* overts;        // [ovcap][2]: the mesh's vertices
+  int64_t ovcap;
+  uint8_t* used;         // [usedcap]: grid vertex used by an output triangle
+  int64_t usedcap;
+  int32_t* vmap;         // [usedcap]: its id in the mesh
+  int64_t* vbsum;        // per block of kPreVScan grid vertices: used count, then base
+  int64_t* nused;        // [1]: grid vertices in the mesh
 };
+constexpr int kPreVScan = 4096;  // grid vertices per block of the compaction scan
 constexpr uint8_t kPreMoved = 8;
 constexpr int kPreTally = 8;
 constexpr int kPreCounts = kPreTally + 512;
@@ -615,6 +625,12 @@ __global__ void k_pre_clear(PreArgs P, int64_t nmid) {
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < (nmid + 3) / 4; q += (int64_t)gridDim.x * blockDim.x)
     m4[q] = 0u;
   for (int q = threadIdx.x; blockIdx.x == 0 && q < kPreCounts; q += blockDim.x) P.counts[q] = 0;
+  if (P.used) {
+    uint32_t* u4 = reinterpret_cast<uint32_t*>(P.used);  // padded to 256 bytes
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < (P.usedcap + 3) / 4;
+         q += (int64_t)gridDim.x * blockDim.x)
+      u4[q] = 0u;
+  }
 }
 
 __global__ void k_pre_sizes(OneSrc src, PreArgs P, Shared sh, int64_t* out) {
@@ -1335,10 +1351,11 @@ __device__ __forceinline__ bool pre_owner_tri(const PreArgs& P, const Geo& g, in
   return true;
 }
 
-// The new vertices of a touched owner, from index NV + pos.
+// The new vertices of a touched owner, from mesh index NV + pos (NV: the
+// grid vertices kept).
 __device__ void pre_owner_vertices(const Img& d, const Geo& g, const PreArgs& P, int k, int i, uint32_t rc,
                                    int64_t pos, int64_t NV) {
-  double2* Vout = reinterpret_cast<double2*>(P.verts);
+  double2* Vout = reinterpret_cast<double2*>(P.overts);
   const PreSlots S = pre_owner_slots(P, g, k, i);
   PreBits Bits;
   pre_owner_bits(d, g, P, k, i, Bits);
@@ -1369,7 +1386,7 @@ __device__ void pre_owner_vertices(const Img& d, const Geo& g, const PreArgs& P,
     }, &Bits);
     for (int z = 0; z < cq && z < m; ++z) {
       const int64_t id = NV + pos + w + z;
-      if (id < P.vcap) Vout[id] = make_double2(xs[z], ys[z]);
+      if (id < P.ovcap) Vout[id] = make_double2(xs[z], ys[z]);
     }
     w += cq;
   }
@@ -1381,7 +1398,7 @@ __device__ void pre_owner_vertices(const Img& d, const Geo& g, const PreArgs& P,
       PrePt in;
       if (pre_tri_mesh(d, g, P, T[z], [](const PrePt&, const PrePt&, const PrePt&, int) {}, &in, nullptr, &Bits)) {
         const int64_t id = NV + pos + nc + nin;
-        if (id < P.vcap) Vout[id] = make_double2(in.x, in.y);
+        if (id < P.ovcap) Vout[id] = make_double2(in.x, in.y);
         ++nin;
       }
     }
@@ -1433,7 +1450,7 @@ __device__ void pre_owner_triangle(const Img& d, const Geo& g, const PreArgs& P,
     ecnt[e] = min(m, ecnt[e]);
   }
   auto id_of = [&](const PrePt& p) -> int64_t {
-    if (p.kind == 0) return p.a;
+    if (p.kind == 0) return P.vmap[p.a];
     if (p.kind == 2) return inner_id;
     for (int e = 0; e < 3; ++e) {
       const int64_t lo = TT.c[e].id < TT.c[(e + 1) % 3].id ? TT.c[e].id : TT.c[(e + 1) % 3].id;
@@ -1513,6 +1530,18 @@ __global__ void __launch_bounds__(256) k_pre_mesh_count(OneSrc src, PreArgs P, S
                              ? (int)pre_slot_ok(g, k, i, 0) + (int)pre_slot_ok(g, k, i, 1)
                              : 0;
           P.rcount[v] = (uint32_t)nt << 19;
+          if (nt) {  // the corners of its slots are in the mesh
+            const int o = k & 1;
+            P.used[v] = 1;
+            if (pre_slot_ok(g, k, i, 0)) {
+              P.used[(int64_t)(k + 1) * g.NI + (i + o)] = 1;
+              P.used[(int64_t)(k + 1) * g.NI + (i + o - 1)] = 1;
+            }
+            if (pre_slot_ok(g, k, i, 1)) {
+              P.used[v + 1] = 1;
+              P.used[(int64_t)(k + 1) * g.NI + (i + o)] = 1;
+            }
+          }
           ntri += nt;
         }
       }
@@ -1536,7 +1565,12 @@ __global__ void __launch_bounds__(256) k_pre_mesh_count(OneSrc src, PreArgs P, S
     int nt = 0;
     PrePt in;
     bool cut = false;
-    const int nin = pre_tri_mesh(d, g, P, T, [&](const PrePt&, const PrePt&, const PrePt&, int) { ++nt; }, &in, &cut,
+    const int nin = pre_tri_mesh(d, g, P, T, [&](const PrePt& a, const PrePt& b, const PrePt& c, int) {
+      ++nt;
+      if (a.kind == 0) P.used[a.a] = 1;
+      if (b.kind == 0) P.used[b.a] = 1;
+      if (c.kind == 0) P.used[c.a] = 1;
+    }, &in, &cut,
                                  &Bits);
     if (nt > 63) {
       pre_error(P);
@@ -1627,7 +1661,7 @@ __global__ void __launch_bounds__(256) k_pre_mesh_vertices(OneSrc src, PreArgs P
   __syncthreads();
   const int n = nlist;
   if (n == 0) return;
-  const int64_t NV = P.gsizes[0];
+  const int64_t NV = *P.nused;
   for (int q = (int)threadIdx.x; q < n; q += 256) {
     int kk, ii;
     pre_list_owner(g, list[q], kk, ii);
@@ -1670,9 +1704,9 @@ __global__ void __launch_bounds__(256) k_pre_mesh_triangles(OneSrc src, PreArgs 
           const int64_t c2 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o - 1) : (int64_t)(k + 1) * g.NI + (i + o);
           if (pos < P.otcap) {
             int32_t* out = P.otris + 3 * pos;
-            out[0] = (int32_t)v;
-            out[1] = (int32_t)c1;
-            out[2] = (int32_t)c2;
+            out[0] = P.vmap[v];
+            out[1] = P.vmap[c1];
+            out[2] = P.vmap[c2];
             P.ocodes[pos] = 0;
           }
           ++pos;
@@ -1685,7 +1719,7 @@ __global__ void __launch_bounds__(256) k_pre_mesh_triangles(OneSrc src, PreArgs 
   __syncthreads();
   const int n = nlist;
   if (n == 0) return;
-  const int64_t NV = P.gsizes[0];
+  const int64_t NV = *P.nused;
   for (int q = (int)threadIdx.x; q < 4 * n; q += 256) {  // one item per grid triangle
     const int ow = q >> 2, z = q & 3;
     int kk, ii;
@@ -1700,20 +1734,82 @@ __global__ void __launch_bounds__(256) k_pre_mesh_triangles(OneSrc src, PreArgs 
   }
 }
 
+// Compaction of the grid vertices: the used ones keep their order.  Per block
+// of kPreVScan grid vertices (of the NV the grid phase made): the used count;
+// one block scans the counts; then each block numbers its used vertices and
+// copies them into the mesh.
+__global__ void __launch_bounds__(256) k_pre_vscan_count(PreArgs P) {
+  __shared__ int part[4];
+  const int64_t NV = P.gsizes[0] < P.usedcap ? P.gsizes[0] : P.usedcap;
+  const int64_t b0 = (int64_t)blockIdx.x * kPreVScan;
+  int n = 0;
+  for (int q = threadIdx.x; q < kPreVScan; q += 256) n += (b0 + q < NV && P.used[b0 + q]) ? 1 : 0;
+  const int w = __builtin_amdgcn_readlane(wave_incl_scan_dpp(n), 63);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) P.vbsum[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+__global__ void __launch_bounds__(256) k_pre_vscan_top(PreArgs P, int64_t nblk) {
+  __shared__ int64_t part[4];
+  int64_t run = 0;
+  for (int64_t b = 0; b < nblk; b += 256) {
+    const int64_t j = b + threadIdx.x;
+    const int64_t x = j < nblk ? P.vbsum[j] : 0;
+    // block-wide exclusive scan of 256 int64 values (four waves of 64)
+    int64_t incl = x;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t y = __shfl_up(incl, off);
+      if ((int)(threadIdx.x & 63) >= off) incl += y;
+    }
+    if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    int64_t before = run;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) before += part[w];
+    if (j < nblk) P.vbsum[j] = before + incl - x;
+    run += part[0] + part[1] + part[2] + part[3];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *P.nused = run;
+}
+__global__ void __launch_bounds__(256) k_pre_vscan_apply(PreArgs P) {
+  __shared__ int part[4];
+  const int64_t NV = P.gsizes[0] < P.usedcap ? P.gsizes[0] : P.usedcap;
+  const int64_t b0 = (int64_t)blockIdx.x * kPreVScan;
+  if (b0 >= NV) return;
+  // each thread takes 16 consecutive vertices
+  const int64_t v0 = b0 + 16 * (int64_t)threadIdx.x;
+  uint32_t bits = 0;
+  for (int q = 0; q < 16; ++q) bits |= (v0 + q < NV && P.used[v0 + q]) ? (1u << q) : 0u;
+  const int n = __builtin_popcount(bits);
+  const int incl = wave_incl_scan_dpp(n);
+  if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = incl;
+  __syncthreads();
+  int64_t id = P.vbsum[blockIdx.x] + (incl - n);
+  for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) id += part[w];
+  const double2* G = reinterpret_cast<const double2*>(P.verts);
+  double2* O = reinterpret_cast<double2*>(P.overts);
+  for (int q = 0; q < 16; ++q) {
+    if (!((bits >> q) & 1u)) continue;
+    P.vmap[v0 + q] = (int32_t)id;
+    if (id < P.ovcap) O[id] = G[v0 + q];
+    ++id;
+  }
+}
+
 __global__ void k_pre_mesh_sizes(PreArgs P, Shared sh, int64_t* out) {
   const longlong4 tot = sh.seg_off[sh.nseg];
-  const int64_t NV = P.gsizes[0];
+  const int64_t NV = *P.nused;
   out[0] = NV + tot.x;        // vertices
   out[1] = tot.y;             // triangles
   out[2] = P.gsizes[2];       // snapped
   out[3] = P.gsizes[3];       // repelled
   out[4] = P.gsizes[4];       // inserted
-  out[6] = NV;                // grid vertices
+  out[6] = NV;                // grid vertices in the mesh
   out[7] = tot.z;             // cut grid triangles
   int64_t st = P.gsizes[5];
   if (st == SBMT_OK || st == SBMT_E_CAPACITY) {
     if (P.counts[2]) st = SBMT_E_PROTOCOL;
-    else if (out[0] > P.vcap || out[1] > P.otcap) st = SBMT_E_CAPACITY;
+    else if (out[0] > P.ovcap || out[1] > P.otcap) st = SBMT_E_CAPACITY;
     else st = SBMT_OK;
   }
   if (out[0] > 0x7fffffffLL) st = SBMT_E_INDEX_OVERFLOW;
@@ -1727,7 +1823,8 @@ struct PreLayout {
   CallLayout L;
   size_t off_mid, off_split, off_flags, off_ins, off_counts, off_out, off_snap, total;
   // the retriangulation (sbmt_preprocess_mesh): grid on-polyline bytes, per-owner counts and bases, sizes
-  size_t off_onp, off_rcount, off_rtri, off_rbase, off_out2;
+  size_t off_onp, off_rcount, off_rtri, off_rbase, off_out2, off_gverts, off_used, off_vmap, off_vbsum, off_nused;
+  int64_t nvblk;  // blocks of the vertex compaction scan
   int64_t nmid, nown;
 };
 static sbmt_status pre_layout(const sbmt_image* img, bool need_ptr, PreLayout* P, bool mesh = false) {
@@ -1753,6 +1850,8 @@ static sbmt_status pre_layout(const sbmt_image* img, bool need_ptr, PreLayout* P
   P->off_snap = off;
   off = align256(off + (size_t)P->nown * 4);
   P->off_onp = P->off_rcount = P->off_rtri = P->off_rbase = P->off_out2 = 0;
+  P->off_gverts = P->off_used = P->off_vmap = P->off_vbsum = P->off_nused = 0;
+  P->nvblk = 0;
   if (mesh) {
     P->off_onp = off;
     off = align256(off + (size_t)(P->nown + P->nmid));
@@ -1764,6 +1863,18 @@ static sbmt_status pre_layout(const sbmt_image* img, bool need_ptr, PreLayout* P
     off = align256(off + (size_t)P->nown * 8);
     P->off_out2 = off;
     off = align256(off + 8 * 8);
+    const int64_t ng = P->nown + P->nmid;  // bound on the grid vertices
+    P->nvblk = (ng + kPreVScan - 1) / kPreVScan;
+    P->off_gverts = off;
+    off = align256(off + (size_t)ng * 16);
+    P->off_used = off;
+    off = align256(off + (size_t)ng);
+    P->off_vmap = off;
+    off = align256(off + (size_t)ng * 4);
+    P->off_vbsum = off;
+    off = align256(off + (size_t)P->nvblk * 8);
+    P->off_nused = off;
+    off = align256(off + 8);
   }
   P->total = off;
   return SBMT_OK;

@@ -108,7 +108,7 @@ class Preprocessor:
 
 @dataclass
 class PreMesh:
-    verts: object     # float64 [V, 2]: the grid vertices (ids 0 .. n_grid_vertices-1), then the new ones
+    verts: object     # float64 [V, 2]: the grid vertices a triangle uses (ids 0 .. n_grid_vertices-1), then the new ones
     tris: object      # int32 [T, 3], positive signed area
     codes: object     # uint8 [T]: 0 grid triangle kept whole, 1 piece of a cut one
     n_grid_vertices: int
@@ -137,7 +137,7 @@ def preprocess_mesh(bitmap, grid_h: float, a: float | None = None, b: float | No
     dev = bitmap.device
     ws = torch.empty(int(ws_bytes.value), dtype=torch.uint8, device=dev)
     counts = (ctypes.c_int64 * 8)()
-    nv, nt = int(gbound.value), 0
+    nv, nt = 0, 0
     for attempt in range(2):
         verts = torch.empty((max(nv, 1), 2), dtype=torch.float64, device=dev)
         tris = torch.empty((max(nt, 1), 3), dtype=torch.int32, device=dev)
@@ -175,7 +175,7 @@ class MeshPreprocessor:
         self.counts = (ctypes.c_int64 * 8)()
         m = preprocess_mesh(bitmap, grid_h, *self.th, ctx=self.ctx)
         dev = bitmap.device
-        self.verts = torch.empty((max(m.verts.shape[0], int(gbound.value)), 2), dtype=torch.float64, device=dev)
+        self.verts = torch.empty((max(m.verts.shape[0], 1), 2), dtype=torch.float64, device=dev)
         self.tris = torch.empty((max(m.tris.shape[0], 1), 3), dtype=torch.int32, device=dev)
         self.codes = torch.empty((max(m.tris.shape[0], 1),), dtype=torch.uint8, device=dev)
         del m

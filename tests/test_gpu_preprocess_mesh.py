@@ -48,6 +48,10 @@ def _compare(name, bm, h, th=None):
                                                                   ref.n_cut)
     assert t.shape == ref.tris.shape, (t.shape, ref.tris.shape)
     assert np.unique(t).size == ref.verts.shape[0]
+    # only vertices some triangle uses are output: grid vertices first, then the new ones
+    assert v.shape[0] == ref.verts.shape[0], (v.shape, ref.verts.shape)
+    if t.shape[0]:
+        assert np.unique(t).size == v.shape[0] and t.min() == 0 and t.max() == v.shape[0] - 1
     A, B = _canon(v, t, c), _canon(ref.verts, ref.tris, ref.codes)
     assert np.array_equal(A[:, 6], B[:, 6]), "codes differ"
     assert np.abs(A[:, :6] - B[:, :6]).max(initial=0.0) <= 1e-9, "triangles differ"

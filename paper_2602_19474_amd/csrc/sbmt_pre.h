@@ -37,7 +37,7 @@ struct PreArgs {
   int32_t* snap_mid;     // [NK NI]: the polyline vertex a lattice vertex snapped to (written where snapped)
   // retriangulation of the grid (sbmt_preprocess_mesh)
   uint32_t* rcount;      // [NK NI]: per-owner counts (pre_rc_*)
-  uint32_t* rtri;        // [NK NI]: per grid triangle of the owner (4): output triangles (6 bits each), inner-vertex bits 24..27
+  uint32_t* rtri;        // [NK NI]: per grid triangle of the owner (4): output triangles (6 bits each), inner-vertex bits 24..27, cut bits 28..31
   int64_t* rbase;        // [NK NI]: first new vertex of the owner (written where it has one)
   const int64_t* gsizes; // the grid phase's sizes record (grid vertices first)
   int32_t* otris;        // [otcap][3]
@@ -943,10 +943,12 @@ struct PreSub {
 // Cuts grid triangle T by the polyline and triangulates its foreground faces,
 // calling out(p0, p1, p2, code) per output triangle (code 0: the grid
 // triangle kept whole, 1: a piece of a cut one).  Returns the number of
-// polyline vertices strictly inside T (0 or 1) and sets *inner to it.
+// polyline vertices strictly inside T (0 or 1) and sets *inner to it.  With
+// `defer`, a cut triangle only sets *cut and returns -1 once its pieces are
+// known (callers gather those and come back to them on full waves).
 template <class Out>
 __device__ int pre_tri_mesh(const Img& d, const Geo& g, const PreArgs& P, const PreGT& T, Out out, PrePt* inner,
-                            bool* cut = nullptr, const PreBits* Bits = nullptr) {
+                            bool* cut = nullptr, const PreBits* Bits = nullptr, bool defer = false) {
   const int64_t NLAT = (int64_t)g.NK * g.NI;
   double minx = T.c[0].x, maxx = T.c[0].x, miny = T.c[0].y, maxy = T.c[0].y;
   for (int j = 1; j < 3; ++j) {
@@ -1034,6 +1036,7 @@ __device__ int pre_tri_mesh(const Img& d, const Geo& g, const PreArgs& P, const 
     return 0;
   }
   if (cut) *cut = true;
+  if (defer) return -1;
   if (nsub > 2) {  // more than two segments in one triangle
     pre_error(P);
     return 0;
@@ -1503,7 +1506,8 @@ __device__ __forceinline__ void pre_list_owner(const Geo& g, int entry, int& k, 
 __global__ void __launch_bounds__(256) k_pre_mesh_count(OneSrc src, PreArgs P, Shared sh) {
   __shared__ int list[4 * kCB];
   __shared__ uint32_t ocross[4 * kCB], otri[4 * kCB], ocut[4 * kCB];
-  __shared__ int nlist;
+  __shared__ uint16_t heavy[4 * 4 * kCB];  // items of cut grid triangles
+  __shared__ int nlist, nheavy;
   __shared__ int sums[4][3];
   const Img& d = src.d;
   const Geo g = d.g;
@@ -1511,7 +1515,7 @@ __global__ void __launch_bounds__(256) k_pre_mesh_count(OneSrc src, PreArgs P, S
   int k, i0;
   const bool on = pre_segment(g, sh, seg, k, i0);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (threadIdx.x == 0) nlist = 0;
+  if (threadIdx.x == 0) nlist = nheavy = 0;
   if (threadIdx.x < 12) sums[threadIdx.x / 3][threadIdx.x % 3] = 0;
   for (int q = threadIdx.x; q < 4 * kCB; q += 256) ocross[q] = otri[q] = ocut[q] = 0u;
   __syncthreads();
@@ -1552,14 +1556,15 @@ __global__ void __launch_bounds__(256) k_pre_mesh_count(OneSrc src, PreArgs P, S
   if (lane == 0 && tot) atomicAdd(&sums[wv][1], tot);
   __syncthreads();
   const int n = nlist;
-  // the grid triangles of the touched owners, one item each
-  for (int q = (int)threadIdx.x; q < 4 * n; q += 256) {
+  // the grid triangles of the touched owners, one item each: the uncut ones
+  // here, the cut ones gathered and retriangulated on full waves below
+  auto tri_item = [&](int q, bool defer) {
     const int ow = q >> 2, z = q & 3;
     int kk, ii;
     pre_list_owner(g, list[ow], kk, ii);
     const PreSlots S = pre_owner_slots(P, g, kk, ii);
     PreGT T;
-    if (!pre_owner_tri(P, g, kk, ii, S, z, T)) continue;
+    if (!pre_owner_tri(P, g, kk, ii, S, z, T)) return;
     PreBits Bits;
     pre_owner_bits(d, g, P, kk, ii, Bits);
     int nt = 0;
@@ -1570,15 +1575,23 @@ __global__ void __launch_bounds__(256) k_pre_mesh_count(OneSrc src, PreArgs P, S
       if (a.kind == 0) P.used[a.a] = 1;
       if (b.kind == 0) P.used[b.a] = 1;
       if (c.kind == 0) P.used[c.a] = 1;
-    }, &in, &cut,
-                                 &Bits);
+    }, &in, &cut, &Bits, defer);
+    if (nin < 0) {
+      heavy[atomicAdd(&nheavy, 1)] = (uint16_t)q;
+      return;
+    }
     if (nt > 63) {
       pre_error(P);
       nt = 63;
     }
-    atomicOr(&otri[ow], ((uint32_t)nt << (6 * z)) | ((uint32_t)(nin ? 1 : 0) << (24 + z)));
+    atomicOr(&otri[ow], ((uint32_t)nt << (6 * z)) | ((uint32_t)(nin ? 1 : 0) << (24 + z)) |
+                            ((uint32_t)(cut ? 1 : 0) << (28 + z)));
     if (cut) atomicAdd(&ocut[ow], 1u);
-  }
+  };
+  for (int q = (int)threadIdx.x; q < 4 * n; q += 256) tri_item(q, true);
+  __syncthreads();
+  const int nh = nheavy;
+  for (int h = (int)threadIdx.x; h < nh; h += 256) tri_item(heavy[h], false);
   // the crossings of the touched owners' edges, one item per owner
   for (int ow = (int)threadIdx.x; ow < n; ow += 256) {
     int kk, ii;
@@ -1676,14 +1689,15 @@ __global__ void __launch_bounds__(256) k_pre_mesh_vertices(OneSrc src, PreArgs P
 __global__ void __launch_bounds__(256) k_pre_mesh_triangles(OneSrc src, PreArgs P, Shared sh) {
   __shared__ int list[4 * kCB];
   __shared__ int rel[4 * kCB];
-  __shared__ int nlist;
+  __shared__ uint16_t heavy[4 * 4 * kCB];  // items of cut grid triangles
+  __shared__ int nlist, nheavy;
   const Img& d = src.d;
   const Geo g = d.g;
   int64_t seg;
   int k, i0;
   const bool on = pre_segment(g, sh, seg, k, i0);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (threadIdx.x == 0) nlist = 0;
+  if (threadIdx.x == 0) nlist = nheavy = 0;
   __syncthreads();
   if (on) {
     const int64_t t0 = sh.seg_off[seg].y;
@@ -1720,18 +1734,43 @@ __global__ void __launch_bounds__(256) k_pre_mesh_triangles(OneSrc src, PreArgs 
   const int n = nlist;
   if (n == 0) return;
   const int64_t NV = *P.nused;
-  for (int q = (int)threadIdx.x; q < 4 * n; q += 256) {  // one item per grid triangle
+  // one item per grid triangle: an uncut one is written here, the cut ones
+  // are gathered and retriangulated on full waves
+  auto tri_item = [&](int q, bool whole) {
     const int ow = q >> 2, z = q & 3;
     int kk, ii;
     pre_list_owner(g, list[ow], kk, ii);
     const int64_t v = (int64_t)kk * g.NI + ii;
     const uint32_t rt = P.rtri[v];
-    if (!((rt >> (6 * z)) & 63u)) continue;
+    if (!((rt >> (6 * z)) & 63u)) return;
+    if (whole && ((rt >> (28 + z)) & 1u)) {
+      heavy[atomicAdd(&nheavy, 1)] = (uint16_t)q;
+      return;
+    }
     const int64_t sg = (int64_t)blockIdx.x * 4 + (list[ow] >> 10);
     int before = 0;
     for (int z2 = 0; z2 < z; ++z2) before += (int)((rt >> (6 * z2)) & 63u);
-    pre_owner_triangle(d, g, P, kk, ii, z, P.rcount[v], rt, sh.seg_off[sg].y + rel[ow] + before, NV);
-  }
+    const int64_t pos = sh.seg_off[sg].y + rel[ow] + before;
+    if (!whole) {
+      pre_owner_triangle(d, g, P, kk, ii, z, P.rcount[v], rt, pos, NV);
+      return;
+    }
+    // uncut and in the foreground: the grid triangle itself (code 0)
+    const PreSlots S = pre_owner_slots(P, g, kk, ii);
+    PreGT T;
+    if (!pre_owner_tri(P, g, kk, ii, S, z, T)) return;
+    if (pos < P.otcap) {
+      int32_t* o = P.otris + 3 * pos;
+      o[0] = P.vmap[T.c[0].id];
+      o[1] = P.vmap[T.c[1].id];
+      o[2] = P.vmap[T.c[2].id];
+      P.ocodes[pos] = 0;
+    }
+  };
+  for (int q = (int)threadIdx.x; q < 4 * n; q += 256) tri_item(q, true);
+  __syncthreads();
+  const int nh = nheavy;
+  for (int h = (int)threadIdx.x; h < nh; h += 256) tri_item(heavy[h], false);
 }
 
 // Compaction of the grid vertices: the used ones keep their order.  Per block

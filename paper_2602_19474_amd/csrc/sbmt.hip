@@ -2636,6 +2636,8 @@ static PreArgs pre_args(const PreLayout& PL, char* w, double a, double b, double
   P.vmap = PL.off_vmap ? (int32_t*)(w + PL.off_vmap) : nullptr;
   P.vbsum = PL.off_vbsum ? (int64_t*)(w + PL.off_vbsum) : nullptr;
   P.nused = PL.off_nused ? (int64_t*)(w + PL.off_nused) : nullptr;
+  P.tlist = PL.off_tlist ? (int32_t*)(w + PL.off_tlist) : nullptr;
+  P.rtbase = PL.off_rtbase ? (int64_t*)(w + PL.off_rtbase) : nullptr;
   return P;
 }
 // Steps 1-3 (the grid, with its triangles when `triangles`), then the sizes
@@ -2722,6 +2724,7 @@ sbmt_status sbmt_preprocess_mesh(sbmt_handle h, const sbmt_image* img, double a,
   const Geo& g = PL.L.g[0];
   if (!pre_thresholds_ok(a, b, c, (double)g.h / g.U)) return SBMT_E_INVALID_ARG;
   if (!workspace || ws_bytes < PL.total) return SBMT_E_WORKSPACE;
+  if (PL.nown > 0x7fffffffLL) return SBMT_E_INDEX_OVERFLOW;  // owner indices in 32 bits
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)workspace;
   const Shared sh = shared_of(PL.L, workspace, 1);
@@ -2743,8 +2746,22 @@ sbmt_status sbmt_preprocess_mesh(sbmt_handle h, const sbmt_image* img, double a,
   int64_t* out2 = (int64_t*)(w + PL.off_out2);
   const Geo& gg = PL.L.g[0];
   const int64_t nwb = ((int64_t)(gg.CH + 1) * gg.wpr + 255) / 256;
+  // blocks of the grid-stride passes: as many per compute unit as their
+  // registers let run at once
+  const int ncu = std::max(h->cus, 1);
+  const dim3 glight((unsigned)(8 * ncu)), gheavy((unsigned)(2 * ncu));
   hipLaunchKernelGGL(k_pre_mesh_touch, dim3((unsigned)nwb), dim3(256), 0, s, src, P);
+  // the touched owners' list: counts per row segment, their offsets, the list
+  hipLaunchKernelGGL(k_pre_mesh_tcount, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, sh);
+  hipLaunchKernelGGL(k_scan_apply, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
   hipLaunchKernelGGL(k_pre_mesh_count, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_mesh_probe, glight, dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_mesh_edges, glight, dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_mesh_cut_count, gheavy, dim3(256), 0, s, src, P, sh);
+  // the output counts per row segment and their offsets
+  hipLaunchKernelGGL(k_pre_mesh_segsum, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
   hipLaunchKernelGGL(k_scan_reduce, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, sh);
   hipLaunchKernelGGL(k_scan_apply, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
@@ -2754,6 +2771,8 @@ sbmt_status sbmt_preprocess_mesh(sbmt_handle h, const sbmt_image* img, double a,
   hipLaunchKernelGGL(k_pre_vscan_apply, dim3((unsigned)PL.nvblk), dim3(256), 0, s, P);
   hipLaunchKernelGGL(k_pre_mesh_vertices, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
   hipLaunchKernelGGL(k_pre_mesh_triangles, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_mesh_whole_tris, glight, dim3(256), 0, s, src, P);
+  hipLaunchKernelGGL(k_pre_mesh_cut_tris, gheavy, dim3(256), 0, s, src, P);
   hipLaunchKernelGGL(k_pre_mesh_sizes, dim3(1), dim3(1), 0, s, P, sh, out2);
   if (hipGetLastError() != hipSuccess) return SBMT_E_DEVICE;
   if ((st = pre_read_sizes(h, out2, 8, counts, s)) != SBMT_OK) return st;

@@ -38,6 +38,7 @@ struct PreArgs {
   // retriangulation of the grid (sbmt_preprocess_mesh)
   uint32_t* rcount;      // [NK NI]: per-owner counts (pre_rc_*)
   uint32_t* rtri;        // [NK NI]: per grid triangle of the owner (4): output triangles (6 bits each), inner-vertex bits 24..27, cut bits 28..31
+  // (counts[3]: the number of touched owners)
   int64_t* rbase;        // [NK NI]: first new vertex of the owner (written where it has one)
   const int64_t* gsizes; // the grid phase's sizes record (grid vertices first)
   int32_t* otris;        // [otcap][3]
@@ -50,6 +51,8 @@ struct PreArgs {
   uint8_t* used;         // [usedcap]: grid vertex used by an output triangle
   int64_t usedcap;
   int32_t* vmap;         // [usedcap]: its id in the mesh
+  int32_t* tlist;        // [NK NI]: the touched owners, in owner order
+  int64_t* rtbase;       // [NK NI]: a touched owner's first output triangle
   int64_t* vbsum;        // per block of kPreVScan grid vertices: used count, then base
   int64_t* nused;        // [1]: grid vertices in the mesh
 };
@@ -706,9 +709,17 @@ __device__ __forceinline__ void pre_bits_load(const Img& d, const Geo& g, int R0
     B.rw[r] = w;
   }
 }
+// Row r of the block, selected rather than indexed (which would put rw in
+// scratch memory).
+__device__ __forceinline__ uint32_t pre_bits_row(const PreBits& B, int r) {
+  uint32_t w = B.rw[0];
+#pragma unroll
+  for (int q = 1; q < 6; ++q) w = r == q ? B.rw[q] : w;
+  return w;
+}
 __device__ __forceinline__ int pre_cell_case(const Img& d, const Geo& g, int R, int C, const PreBits* B = nullptr) {
   if (B && R >= B->R0 && R + 1 < B->R0 + B->nr && C >= B->C0 && C + 1 < B->C0 + 32) {
-    const uint32_t t = B->rw[R - B->R0] >> (C - B->C0), u = B->rw[R + 1 - B->R0] >> (C - B->C0);
+    const uint32_t t = pre_bits_row(*B, R - B->R0) >> (C - B->C0), u = pre_bits_row(*B, R + 1 - B->R0) >> (C - B->C0);
     return (int)((t & 1u) | ((t & 2u)) | ((u & 2u) << 1) | ((u & 1u) << 3));
   }
   return sample_at(d, g, R, C) | (sample_at(d, g, R, C + 1) << 1) | (sample_at(d, g, R + 1, C + 1) << 2) |
@@ -823,6 +834,12 @@ struct PreGT {
   int64_t eo[3];
   int es[3];
 };
+// x, y or z for j = 0, 1, 2: selects rather than an indexed local array,
+// which would live in scratch memory.
+template <class V>
+__device__ __forceinline__ V pre_sel3(const V& x, const V& y, const V& z, int j) {
+  return j == 0 ? x : (j == 1 ? y : z);
+}
 // Edge slot q of owner (k, i): its ends (false if the owner has no such edge).
 __device__ bool pre_edge_slot(const PreArgs& P, const Geo& g, int k, int i, const PreSlots& S, int q, PreGV& A,
                               PreGV& B) {
@@ -854,9 +871,8 @@ __device__ bool pre_edge_slot(const PreArgs& P, const Geo& g, int k, int i, cons
   const int64_t w = t == 0 ? (js == 1 ? C2 : v) : (js == 1 ? v + 1 : v);
   const int e = t == 0 ? (js == 0 ? 2 : (js == 1 ? 0 : 1)) : js;
   const uint32_t fw = t == 0 ? (js == 1 ? S.fdl : S.fv) : (js == 1 ? S.fr : S.fv);
-  const int64_t Cs[3] = {C0, C1, C2};
   A = pre_ins_gv(P, g, w, e, fw);
-  B = pre_lat_gv(P, Cs[(js + 2) % 3]);
+  B = pre_lat_gv(P, pre_sel3(C0, C1, C2, (js + 2) % 3));
   return true;
 }
 // The grid triangles of slot t of owner (k, i): one, or two fanned around the
@@ -868,51 +884,59 @@ __device__ int pre_slot_tris(const PreArgs& P, const Geo& g, int k, int i, const
   const int64_t C0 = v;
   const int64_t C1 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o) : v + 1;
   const int64_t C2 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o - 1) : (int64_t)(k + 1) * g.NI + (i + o);
-  const int64_t Cs[3] = {C0, C1, C2};
   // side j: owner, owned side, and whether corner j is that owner
-  int64_t so[3];
-  int se[3];
-  bool sa[3];
-  if (t == 0) {  // Tb = [v, vdr, vdl]: E2 of v, E0 of vdl, E1 of v
-    so[0] = v; se[0] = 2; sa[0] = true;
-    so[1] = C2; se[1] = 0; sa[1] = false;
-    so[2] = v; se[2] = 1; sa[2] = false;
-  } else {  // Ta = [v, vr, vdr]: E0 of v, E1 of vr, E2 of v
-    so[0] = v; se[0] = 0; sa[0] = true;
-    so[1] = v + 1; se[1] = 1; sa[1] = true;
-    so[2] = v; se[2] = 2; sa[2] = false;
-  }
-  PreGV G[3];
-  for (int j = 0; j < 3; ++j) G[j] = pre_lat_gv(P, Cs[j]);
+  // Tb = [v, vdr, vdl]: E2 of v, E0 of vdl, E1 of v; Ta = [v, vr, vdr]: E0 of v, E1 of vr, E2 of v
+  const int64_t so0 = v, so1 = t == 0 ? C2 : v + 1, so2 = v;
+  const int se0 = t == 0 ? 2 : 0, se1 = t == 0 ? 0 : 1, se2 = t == 0 ? 1 : 2;
+  const bool sa0 = true, sa1 = t != 0, sa2 = false;
+  const PreGV G0 = pre_lat_gv(P, C0), G1 = pre_lat_gv(P, C1), G2 = pre_lat_gv(P, C2);
   if (!S.sides[t]) {
-    for (int j = 0; j < 3; ++j) {
-      T[0].c[j] = G[j];
-      T[0].eo[j] = so[j];
-      T[0].es[j] = 2 * se[j];
-    }
+    T[0].c[0] = G0;
+    T[0].c[1] = G1;
+    T[0].c[2] = G2;
+    T[0].eo[0] = so0;
+    T[0].eo[1] = so1;
+    T[0].eo[2] = so2;
+    T[0].es[0] = 2 * se0;
+    T[0].es[1] = 2 * se1;
+    T[0].es[2] = 2 * se2;
     return 1;
   }
   const int js = __builtin_ctz(S.sides[t]);
   const uint32_t fw = t == 0 ? (js == 1 ? S.fdl : S.fv) : (js == 1 ? S.fr : S.fv);
-  const PreGV M = pre_ins_gv(P, g, so[js], se[js], fw);
   const int j1 = (js + 1) % 3, j2 = (js + 2) % 3;
-  const int h0 = 2 * se[js] + (sa[js] ? 0 : 1), h1 = 2 * se[js] + (sa[js] ? 1 : 0);
+  const int64_t soj = pre_sel3(so0, so1, so2, js);
+  const int sej = pre_sel3(se0, se1, se2, js);
+  const bool saj = pre_sel3(sa0, sa1, sa2, js);
+  const PreGV M = pre_ins_gv(P, g, soj, sej, fw);
+  const int h0 = 2 * sej + (saj ? 0 : 1), h1 = 2 * sej + (saj ? 1 : 0);
+  const PreGV Gs = pre_sel3(G0, G1, G2, js), G1s = pre_sel3(G0, G1, G2, j1), G2s = pre_sel3(G0, G1, G2, j2);
   // (a0, m, a2): a0 -> m (half of the split side), m -> a2 (fan edge), a2 -> a0
-  T[0].c[0] = G[js]; T[0].c[1] = M; T[0].c[2] = G[j2];
-  T[0].eo[0] = so[js]; T[0].es[0] = h0;
-  T[0].eo[1] = v; T[0].es[1] = 6 + t;
-  T[0].eo[2] = so[j2]; T[0].es[2] = 2 * se[j2];
+  T[0].c[0] = Gs;
+  T[0].c[1] = M;
+  T[0].c[2] = G2s;
+  T[0].eo[0] = soj;
+  T[0].es[0] = h0;
+  T[0].eo[1] = v;
+  T[0].es[1] = 6 + t;
+  T[0].eo[2] = pre_sel3(so0, so1, so2, j2);
+  T[0].es[2] = 2 * pre_sel3(se0, se1, se2, j2);
   // (m, a1, a2): m -> a1 (other half), a1 -> a2, a2 -> m (fan edge)
-  T[1].c[0] = M; T[1].c[1] = G[j1]; T[1].c[2] = G[j2];
-  T[1].eo[0] = so[js]; T[1].es[0] = h1;
-  T[1].eo[1] = so[j1]; T[1].es[1] = 2 * se[j1];
-  T[1].eo[2] = v; T[1].es[2] = 6 + t;
+  T[1].c[0] = M;
+  T[1].c[1] = G1s;
+  T[1].c[2] = G2s;
+  T[1].eo[0] = soj;
+  T[1].es[0] = h1;
+  T[1].eo[1] = pre_sel3(so0, so1, so2, j1);
+  T[1].es[1] = 2 * pre_sel3(se0, se1, se2, j1);
+  T[1].eo[2] = v;
+  T[1].es[2] = 6 + t;
   return 2;
 }
 
 // Per-owner counts of the retriangulation: crossings of edge slot q in bits
 // 2q .. 2q+1, polyline vertices inside its triangles in 16 .. 18, output
-// triangles in 19 .. 26.
+// triangles in 19 .. 26, cut grid triangles in 27 .. 29.
 __device__ __forceinline__ int pre_rc_cross(uint32_t rc, int q) { return (int)((rc >> (2 * q)) & 3u); }
 __device__ __forceinline__ int pre_rc_before(uint32_t rc, int q) {  // crossings of slots before q
   int n = 0;
@@ -921,6 +945,7 @@ __device__ __forceinline__ int pre_rc_before(uint32_t rc, int q) {  // crossings
 }
 __device__ __forceinline__ int pre_rc_inner(uint32_t rc) { return (int)((rc >> 16) & 7u); }
 __device__ __forceinline__ int pre_rc_tris(uint32_t rc) { return (int)((rc >> 19) & 255u); }
+__device__ __forceinline__ int pre_rc_cut(uint32_t rc) { return (int)((rc >> 27) & 7u); }
 
 // A point of a triangle's subdivision: kind 0 grid vertex a; 1 crossing of
 // grid edge (a, b), a < b, by segment s; 2 polyline vertex a strictly inside
@@ -944,11 +969,11 @@ struct PreSub {
 // calling out(p0, p1, p2, code) per output triangle (code 0: the grid
 // triangle kept whole, 1: a piece of a cut one).  Returns the number of
 // polyline vertices strictly inside T (0 or 1) and sets *inner to it.  With
-// `defer`, a cut triangle only sets *cut and returns -1 once its pieces are
+// kDefer, a cut triangle only sets *cut and returns -1 once its pieces are
 // known (callers gather those and come back to them on full waves).
-template <class Out>
+template <bool kDefer = false, class Out>
 __device__ int pre_tri_mesh(const Img& d, const Geo& g, const PreArgs& P, const PreGT& T, Out out, PrePt* inner,
-                            bool* cut = nullptr, const PreBits* Bits = nullptr, bool defer = false) {
+                            bool* cut = nullptr, const PreBits* Bits = nullptr) {
   const int64_t NLAT = (int64_t)g.NK * g.NI;
   double minx = T.c[0].x, maxx = T.c[0].x, miny = T.c[0].y, maxy = T.c[0].y;
   for (int j = 1; j < 3; ++j) {
@@ -1011,7 +1036,7 @@ __device__ int pre_tri_mesh(const Img& d, const Geo& g, const PreArgs& P, const 
       edge_side = ((S.qx - S.px) * (T3.y - S.py) - (S.qy - S.py) * (T3.x - S.px)) > 0 ? 1 : 0;
       return;
     }
-    if (nsub < 3) subs[nsub] = sb;
+    if (!kDefer && nsub < 3) subs[nsub] = sb;  // (a probe only needs to know that there is one)
     ++nsub;
   }, Bits);
   if (nsub == 0) {
@@ -1036,7 +1061,7 @@ __device__ int pre_tri_mesh(const Img& d, const Geo& g, const PreArgs& P, const 
     return 0;
   }
   if (cut) *cut = true;
-  if (defer) return -1;
+  if (kDefer) return -1;
   if (nsub > 2) {  // more than two segments in one triangle
     pre_error(P);
     return 0;
@@ -1350,7 +1375,10 @@ __device__ __forceinline__ bool pre_owner_tri(const PreArgs& P, const Geo& g, in
   PreGT TT[2];
   const int m = pre_slot_tris(P, g, k, i, S, z >> 1, TT);
   if ((z & 1) >= m) return false;
-  T = TT[z & 1];
+  if (z & 1)  // constant indices keep TT in registers
+    T = TT[1];
+  else
+    T = TT[0];
   return true;
 }
 
@@ -1500,146 +1528,206 @@ __device__ __forceinline__ void pre_list_owner(const Geo& g, int entry, int& k, 
   i = (int)(sg - kk * (uint32_t)g.NCB) * kCB + (entry & 1023);
 }
 
-// Counts: quiet owners in place; a touched owner gives work items to the
-// block (each of its up to four grid triangles, then its edge crossings),
-// combined per owner in LDS.
+// The touched owners of each row segment (their list offsets come from a scan).
+__global__ void __launch_bounds__(256) k_pre_mesh_tcount(OneSrc src, PreArgs P, Shared sh) {
+  const Geo g = src.d.g;
+  int64_t seg;
+  int k, i0;
+  if (!pre_segment(g, sh, seg, k, i0)) return;  // wave-uniform
+  const int lane = threadIdx.x & 63;
+  int n = 0;
+  for (int j = 0; j < 4; ++j) {
+    const int i = i0 + 64 * j + lane;
+    n += (int)__popcll(__ballot(i < g.NI && (P.flags[(int64_t)k * g.NI + i] & kPreTouched)));
+  }
+  if (lane == 0) {
+    sh.seg_cnt[seg] = make_int4(n, 0, 0, 0);
+    sh.seg_slow[seg] = 0ull;
+  }
+}
+
+// Quiet owners in place (their slots kept whole when the owner vertex is
+// inside); the touched ones go to the list at their segment's offset, their
+// counts cleared for the dense pass.
 __global__ void __launch_bounds__(256) k_pre_mesh_count(OneSrc src, PreArgs P, Shared sh) {
-  __shared__ int list[4 * kCB];
-  __shared__ uint32_t ocross[4 * kCB], otri[4 * kCB], ocut[4 * kCB];
-  __shared__ uint16_t heavy[4 * 4 * kCB];  // items of cut grid triangles
-  __shared__ int nlist, nheavy;
-  __shared__ int sums[4][3];
   const Img& d = src.d;
   const Geo g = d.g;
   int64_t seg;
   int k, i0;
-  const bool on = pre_segment(g, sh, seg, k, i0);
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (threadIdx.x == 0) nlist = nheavy = 0;
-  if (threadIdx.x < 12) sums[threadIdx.x / 3][threadIdx.x % 3] = 0;
-  for (int q = threadIdx.x; q < 4 * kCB; q += 256) ocross[q] = otri[q] = ocut[q] = 0u;
-  __syncthreads();
-  int ntri = 0;
-  if (on) {
-    const double y = lat_y(g, k);
-    for (int j = 0; j < 4; ++j) {
-      const int i = i0 + 64 * j + lane;
-      bool heavy = false;
-      if (i < g.NI) {
-        const int64_t v = (int64_t)k * g.NI + i;
-        if (P.flags[v] & kPreTouched) {
-          heavy = true;
-        } else {
-          const int nt = pre_inside_point(d, g, lat_x(g, pre_lat_X(g, k, i)), y)
-                             ? (int)pre_slot_ok(g, k, i, 0) + (int)pre_slot_ok(g, k, i, 1)
-                             : 0;
-          P.rcount[v] = (uint32_t)nt << 19;
-          if (nt) {  // the corners of its slots are in the mesh
-            const int o = k & 1;
-            P.used[v] = 1;
-            if (pre_slot_ok(g, k, i, 0)) {
-              P.used[(int64_t)(k + 1) * g.NI + (i + o)] = 1;
-              P.used[(int64_t)(k + 1) * g.NI + (i + o - 1)] = 1;
-            }
-            if (pre_slot_ok(g, k, i, 1)) {
-              P.used[v + 1] = 1;
-              P.used[(int64_t)(k + 1) * g.NI + (i + o)] = 1;
-            }
-          }
-          ntri += nt;
+  if (!pre_segment(g, sh, seg, k, i0)) return;  // wave-uniform
+  const int lane = threadIdx.x & 63;
+  const double y = lat_y(g, k);
+  int64_t at = sh.seg_off[seg].x;
+  for (int j = 0; j < 4; ++j) {
+    const int i = i0 + 64 * j + lane;
+    const int64_t v = (int64_t)k * g.NI + i;
+    const bool touched = i < g.NI && (P.flags[v] & kPreTouched);
+    const unsigned long long bal = __ballot(touched);
+    if (touched) {
+      P.tlist[at + lanes_below(bal)] = (int32_t)v;
+      P.rcount[v] = 0u;
+      P.rtri[v] = 0u;
+    } else if (i < g.NI) {
+      const int nt = pre_inside_point(d, g, lat_x(g, pre_lat_X(g, k, i)), y)
+                         ? (int)pre_slot_ok(g, k, i, 0) + (int)pre_slot_ok(g, k, i, 1)
+                         : 0;
+      P.rcount[v] = (uint32_t)nt << 19;
+      if (nt) {  // the corners of its slots are in the mesh
+        const int o = k & 1;
+        P.used[v] = 1;
+        if (pre_slot_ok(g, k, i, 0)) {
+          P.used[(int64_t)(k + 1) * g.NI + (i + o)] = 1;
+          P.used[(int64_t)(k + 1) * g.NI + (i + o - 1)] = 1;
+        }
+        if (pre_slot_ok(g, k, i, 1)) {
+          P.used[v + 1] = 1;
+          P.used[(int64_t)(k + 1) * g.NI + (i + o)] = 1;
         }
       }
-      pre_list_push(list, &nlist, heavy, (wv << 10) | (64 * j + lane), nullptr, 0);
     }
+    at += (int64_t)__popcll(bal);
   }
-  const int tot = __builtin_amdgcn_readlane(wave_incl_scan_dpp(ntri), 63);
-  if (lane == 0 && tot) atomicAdd(&sums[wv][1], tot);
-  __syncthreads();
-  const int n = nlist;
-  // the grid triangles of the touched owners, one item each: the uncut ones
-  // here, the cut ones gathered and retriangulated on full waves below
-  auto tri_item = [&](int q, bool defer) {
-    const int ow = q >> 2, z = q & 3;
+}
+
+// Work over n items in chunks of a block (a grid-stride loop): light(item)
+// runs each item and returns true to put it off; put-off items are gathered
+// in LDS and run by heavy(item) on full blocks, the rest at the end.  dl
+// holds 2 * 256 entries; *nd starts at 0.
+template <class Light, class Heavy>
+__device__ __forceinline__ void pre_dense(int64_t n, int64_t* dl, int* nd, Light light, Heavy heavy) {
+  for (int64_t base = (int64_t)blockIdx.x * 256;; base += (int64_t)gridDim.x * 256) {
+    const bool more = base < n;  // uniform
+    if (more) {
+      const int64_t it = base + threadIdx.x;
+      if (it < n && light(it)) dl[atomicAdd(nd, 1)] = it;
+    }
+    __syncthreads();
+    int m = *nd;
+    while (m >= 256 || (!more && m > 0)) {  // uniform
+      const int take = m >= 256 ? 256 : m;
+      if ((int)threadIdx.x < take) heavy(dl[m - take + threadIdx.x]);
+      m -= take;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) *nd = m;
+    __syncthreads();
+    if (!more) break;
+  }
+}
+__device__ __forceinline__ void pre_tl_owner(const Geo& g, const PreArgs& P, int64_t t, int& k, int& i) {
+  const uint32_t v = (uint32_t)P.tlist[t];
+  const uint32_t kk = v / (uint32_t)g.NI;
+  k = (int)kk;
+  i = (int)(v - kk * (uint32_t)g.NI);
+}
+
+// Counts of the touched owners' grid triangles: pre_mesh_tri_count<true>
+// counts an uncut one and marks a cut one (its cut bit), <false>
+// retriangulates a cut one; the results are added to the owner's words.
+template <bool kProbe>
+__device__ __forceinline__ void pre_mesh_tri_count(const Img& d, const Geo& g, const PreArgs& P, int64_t it) {
+  int kk, ii;
+  pre_tl_owner(g, P, it >> 2, kk, ii);
+  const int z = (int)(it & 3);
+  const PreSlots S = pre_owner_slots(P, g, kk, ii);
+  PreGT Tg;
+  if (!pre_owner_tri(P, g, kk, ii, S, z, Tg)) return;
+  PreBits Bits;
+  pre_owner_bits(d, g, P, kk, ii, Bits);
+  int nt = 0;
+  PrePt in;
+  bool cut = false;
+  const int nin = pre_tri_mesh<kProbe>(d, g, P, Tg, [&](const PrePt& a, const PrePt& b, const PrePt& c, int) {
+    ++nt;
+    if (a.kind == 0) P.used[a.a] = 1;
+    if (b.kind == 0) P.used[b.a] = 1;
+    if (c.kind == 0) P.used[c.a] = 1;
+  }, &in, &cut, &Bits);
+  const int64_t v = (int64_t)kk * g.NI + ii;
+  if (nin < 0) {  // cut: the second pass takes it
+    atomicOr(&P.rtri[v], 1u << (28 + z));
+    return;
+  }
+  if (nt > 63) {
+    pre_error(P);
+    nt = 63;
+  }
+  const uint32_t bits = ((uint32_t)nt << (6 * z)) | ((uint32_t)(nin ? 1 : 0) << (24 + z)) |
+                        ((uint32_t)(cut ? 1 : 0) << (28 + z));
+  if (bits) atomicOr(&P.rtri[v], bits);
+  const uint32_t add = ((uint32_t)(nin ? 1 : 0) << 16) | ((uint32_t)nt << 19) | ((uint32_t)(cut ? 1 : 0) << 27);
+  if (add) atomicAdd(&P.rcount[v], add);
+}
+// One item per grid triangle of the touched owners (4 per owner), over a
+// grid-stride loop; at most 128 VGPRs (four waves per SIMD).
+__global__ void __launch_bounds__(256, 4) k_pre_mesh_probe(OneSrc src, PreArgs P, Shared sh) {
+  const Img& d = src.d;
+  const Geo g = d.g;
+  const int64_t T = sh.seg_off[sh.nseg].x;  // touched owners
+  for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < 4 * T; it += (int64_t)gridDim.x * 256)
+    pre_mesh_tri_count<true>(d, g, P, it);
+}
+// Crossings of the touched owners' edge slots, one item per slot (8 per owner).
+__global__ void __launch_bounds__(256) k_pre_mesh_edges(OneSrc src, PreArgs P, Shared sh) {
+  const Img& d = src.d;
+  const Geo g = d.g;
+  const int64_t T = sh.seg_off[sh.nseg].x;  // touched owners
+  for (int64_t e8 = (int64_t)blockIdx.x * 256 + threadIdx.x; e8 < 8 * T; e8 += (int64_t)gridDim.x * 256) {
     int kk, ii;
-    pre_list_owner(g, list[ow], kk, ii);
+    pre_tl_owner(g, P, e8 >> 3, kk, ii);
+    const int e = (int)(e8 & 7);
     const PreSlots S = pre_owner_slots(P, g, kk, ii);
-    PreGT T;
-    if (!pre_owner_tri(P, g, kk, ii, S, z, T)) return;
+    PreGV A, B;
+    if (!pre_edge_slot(P, g, kk, ii, S, e, A, B)) continue;
     PreBits Bits;
     pre_owner_bits(d, g, P, kk, ii, Bits);
-    int nt = 0;
-    PrePt in;
-    bool cut = false;
-    const int nin = pre_tri_mesh(d, g, P, T, [&](const PrePt& a, const PrePt& b, const PrePt& c, int) {
-      ++nt;
-      if (a.kind == 0) P.used[a.a] = 1;
-      if (b.kind == 0) P.used[b.a] = 1;
-      if (c.kind == 0) P.used[c.a] = 1;
-    }, &in, &cut, &Bits, defer);
-    if (nin < 0) {
-      heavy[atomicAdd(&nheavy, 1)] = (uint16_t)q;
-      return;
-    }
-    if (nt > 63) {
+    int c = 0;
+    pre_edge_crossings(d, g, A, B, [&](const PreSeg&, double) { ++c; }, &Bits);
+    if (c > 3) {  // more crossings of one grid edge than the numbering holds
       pre_error(P);
-      nt = 63;
+      c = 3;
     }
-    atomicOr(&otri[ow], ((uint32_t)nt << (6 * z)) | ((uint32_t)(nin ? 1 : 0) << (24 + z)) |
-                            ((uint32_t)(cut ? 1 : 0) << (28 + z)));
-    if (cut) atomicAdd(&ocut[ow], 1u);
-  };
-  for (int q = (int)threadIdx.x; q < 4 * n; q += 256) tri_item(q, true);
-  __syncthreads();
-  const int nh = nheavy;
-  for (int h = (int)threadIdx.x; h < nh; h += 256) tri_item(heavy[h], false);
-  // the crossings of the touched owners' edges, one item per owner
-  for (int ow = (int)threadIdx.x; ow < n; ow += 256) {
-    int kk, ii;
-    pre_list_owner(g, list[ow], kk, ii);
-    const PreSlots S = pre_owner_slots(P, g, kk, ii);
-    PreBits Bits;
-    pre_owner_bits(d, g, P, kk, ii, Bits);
-    uint32_t rc = 0;
-    for (int e = 0; e < 8; ++e) {
-      PreGV A, B;
-      if (!pre_edge_slot(P, g, kk, ii, S, e, A, B)) continue;
-      int c = 0;
-      pre_edge_crossings(d, g, A, B, [&](const PreSeg&, double) { ++c; }, &Bits);
-      if (c > 3) {  // more crossings of one grid edge than the numbering holds
-        pre_error(P);
-        c = 3;
-      }
-      rc |= (uint32_t)c << (2 * e);
-    }
-    ocross[ow] = rc;
+    if (c) atomicOr(&P.rcount[(int64_t)kk * g.NI + ii], (uint32_t)c << (2 * e));
   }
+}
+// The cut grid triangles (cut bit set, no count yet), gathered per block and
+// retriangulated on full blocks.
+__global__ void __launch_bounds__(256) k_pre_mesh_cut_count(OneSrc src, PreArgs P, Shared sh) {
+  __shared__ int64_t dl[512];
+  __shared__ int nd;
+  const Img& d = src.d;
+  const Geo g = d.g;
+  if (threadIdx.x == 0) nd = 0;
   __syncthreads();
-  for (int ow = (int)threadIdx.x; ow < n; ow += 256) {
-    int kk, ii;
-    pre_list_owner(g, list[ow], kk, ii);
-    const uint32_t rt = otri[ow];
-    int nt = 0;
-    for (int z = 0; z < 4; ++z) nt += (int)((rt >> (6 * z)) & 63u);
-    const int nin = __builtin_popcount((rt >> 24) & 15u);
-    if (nt > 255) {
-      pre_error(P);
-      nt = 255;
-    }
-    const int64_t v = (int64_t)kk * g.NI + ii;
-    P.rcount[v] = ocross[ow] | ((uint32_t)nin << 16) | ((uint32_t)nt << 19);
-    P.rtri[v] = rt;
-    const int w = list[ow] >> 10;
-    atomicAdd(&sums[w][0], pre_rc_before(ocross[ow], 8) + nin);
-    atomicAdd(&sums[w][1], nt);
-    atomicAdd(&sums[w][2], (int)ocut[ow]);
+  const int64_t T = sh.seg_off[sh.nseg].x;
+  pre_dense(4 * T, dl, &nd, [&](int64_t it) -> bool {
+    return (P.rtri[P.tlist[it >> 2]] >> (28 + (it & 3))) & 1u;
+  }, [&](int64_t it) { pre_mesh_tri_count<false>(d, g, P, it); });
+}
+
+// Per row segment: new vertices, triangles and cut grid triangles of its
+// owners, the input of the scan; counts[3] keeps the number of touched owners.
+__global__ void __launch_bounds__(256) k_pre_mesh_segsum(OneSrc src, PreArgs P, Shared sh) {
+  const Geo g = src.d.g;
+  if (blockIdx.x == 0 && threadIdx.x == 0) P.counts[3] = sh.seg_off[sh.nseg].x;
+  int64_t seg;
+  int k, i0;
+  if (!pre_segment(g, sh, seg, k, i0)) return;  // wave-uniform
+  const int lane = threadIdx.x & 63;
+  int nv = 0, nt = 0, nc = 0;
+  for (int j = 0; j < 4; ++j) {
+    const int i = i0 + 64 * j + lane;
+    const uint32_t rc = i < g.NI ? P.rcount[(int64_t)k * g.NI + i] : 0u;
+    nv += pre_rc_before(rc, 8) + pre_rc_inner(rc);
+    nt += pre_rc_tris(rc);
+    nc += pre_rc_cut(rc);
   }
-  __syncthreads();
-  if (threadIdx.x < 4) {
-    const int64_t sg = (int64_t)blockIdx.x * 4 + threadIdx.x;
-    if (sg < sh.nseg) {
-      sh.seg_cnt[sg] = make_int4(sums[threadIdx.x][0], sums[threadIdx.x][1], sums[threadIdx.x][2], 0);
-      sh.seg_slow[sg] = 0ull;
-    }
+  nv = __builtin_amdgcn_readlane(wave_incl_scan_dpp(nv), 63);
+  nt = __builtin_amdgcn_readlane(wave_incl_scan_dpp(nt), 63);
+  nc = __builtin_amdgcn_readlane(wave_incl_scan_dpp(nc), 63);
+  if (lane == 0) {
+    sh.seg_cnt[seg] = make_int4(nv, nt, nc, 0);
+    sh.seg_slow[seg] = 0ull;
   }
 }
 
@@ -1685,92 +1773,96 @@ __global__ void __launch_bounds__(256) k_pre_mesh_vertices(OneSrc src, PreArgs P
 }
 
 // Output triangles at their offsets, with their codes: a quiet owner's slots
-// as they are (code 0), a touched owner's by the retriangulation.
+// as they are (code 0); a touched owner's first output triangle is recorded
+// for the dense pass.
 __global__ void __launch_bounds__(256) k_pre_mesh_triangles(OneSrc src, PreArgs P, Shared sh) {
-  __shared__ int list[4 * kCB];
-  __shared__ int rel[4 * kCB];
-  __shared__ uint16_t heavy[4 * 4 * kCB];  // items of cut grid triangles
-  __shared__ int nlist, nheavy;
-  const Img& d = src.d;
-  const Geo g = d.g;
+  const Geo g = src.d.g;
   int64_t seg;
   int k, i0;
-  const bool on = pre_segment(g, sh, seg, k, i0);
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (threadIdx.x == 0) nlist = nheavy = 0;
-  __syncthreads();
-  if (on) {
-    const int64_t t0 = sh.seg_off[seg].y;
-    const int o = k & 1;
-    int acc = 0;
-    for (int j = 0; j < 4; ++j) {
-      const int i = i0 + 64 * j + lane;
-      const int64_t v = (int64_t)k * g.NI + i;
-      const uint32_t rc = i < g.NI ? P.rcount[v] : 0u;
-      const int n = pre_rc_tris(rc);
-      const int incl = wave_incl_scan_dpp(n);
-      const bool heavy = n > 0 && (P.flags[v] & kPreTouched);
-      if (n > 0 && !heavy) {
-        int64_t pos = t0 + acc + (incl - n);
-        for (int t = 0; t < 2; ++t) {
-          if (!pre_slot_ok(g, k, i, t)) continue;
-          const int64_t c1 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o) : v + 1;
-          const int64_t c2 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o - 1) : (int64_t)(k + 1) * g.NI + (i + o);
-          if (pos < P.otcap) {
-            int32_t* out = P.otris + 3 * pos;
-            out[0] = P.vmap[v];
-            out[1] = P.vmap[c1];
-            out[2] = P.vmap[c2];
-            P.ocodes[pos] = 0;
-          }
-          ++pos;
+  if (!pre_segment(g, sh, seg, k, i0)) return;  // wave-uniform
+  const int lane = threadIdx.x & 63;
+  const int64_t t0 = sh.seg_off[seg].y;
+  const int o = k & 1;
+  int acc = 0;
+  for (int j = 0; j < 4; ++j) {
+    const int i = i0 + 64 * j + lane;
+    const int64_t v = (int64_t)k * g.NI + i;
+    const uint32_t rc = i < g.NI ? P.rcount[v] : 0u;
+    const int n = pre_rc_tris(rc);
+    const int incl = wave_incl_scan_dpp(n);
+    int64_t pos = t0 + acc + (incl - n);
+    if (n > 0 && (P.flags[v] & kPreTouched)) {
+      P.rtbase[v] = pos;
+    } else if (n > 0) {
+      for (int t = 0; t < 2; ++t) {
+        if (!pre_slot_ok(g, k, i, t)) continue;
+        const int64_t c1 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o) : v + 1;
+        const int64_t c2 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o - 1) : (int64_t)(k + 1) * g.NI + (i + o);
+        if (pos < P.otcap) {
+          int32_t* out = P.otris + 3 * pos;
+          out[0] = P.vmap[v];
+          out[1] = P.vmap[c1];
+          out[2] = P.vmap[c2];
+          P.ocodes[pos] = 0;
         }
+        ++pos;
       }
-      pre_list_push(list, &nlist, heavy, (wv << 10) | (64 * j + lane), rel, acc + (incl - n));
-      acc += __builtin_amdgcn_readlane(incl, 63);
     }
+    acc += __builtin_amdgcn_readlane(incl, 63);
   }
-  __syncthreads();
-  const int n = nlist;
-  if (n == 0) return;
-  const int64_t NV = *P.nused;
-  // one item per grid triangle: an uncut one is written here, the cut ones
-  // are gathered and retriangulated on full waves
-  auto tri_item = [&](int q, bool whole) {
-    const int ow = q >> 2, z = q & 3;
+}
+
+// Triangles of the touched owners, one item per grid triangle: an uncut one
+// (in the foreground) is written as it is; the cut ones are retriangulated by
+// k_pre_mesh_cut_tris.
+__global__ void __launch_bounds__(256) k_pre_mesh_whole_tris(OneSrc src, PreArgs P) {
+  const Geo g = src.d.g;
+  const int64_t T = P.counts[3];
+  for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < 4 * T; it += (int64_t)gridDim.x * 256) {
     int kk, ii;
-    pre_list_owner(g, list[ow], kk, ii);
+    pre_tl_owner(g, P, it >> 2, kk, ii);
+    const int z = (int)(it & 3);
     const int64_t v = (int64_t)kk * g.NI + ii;
     const uint32_t rt = P.rtri[v];
-    if (!((rt >> (6 * z)) & 63u)) return;
-    if (whole && ((rt >> (28 + z)) & 1u)) {
-      heavy[atomicAdd(&nheavy, 1)] = (uint16_t)q;
-      return;
-    }
-    const int64_t sg = (int64_t)blockIdx.x * 4 + (list[ow] >> 10);
+    if (!((rt >> (6 * z)) & 63u) || ((rt >> (28 + z)) & 1u)) continue;
     int before = 0;
     for (int z2 = 0; z2 < z; ++z2) before += (int)((rt >> (6 * z2)) & 63u);
-    const int64_t pos = sh.seg_off[sg].y + rel[ow] + before;
-    if (!whole) {
-      pre_owner_triangle(d, g, P, kk, ii, z, P.rcount[v], rt, pos, NV);
-      return;
-    }
-    // uncut and in the foreground: the grid triangle itself (code 0)
+    const int64_t pos = P.rtbase[v] + before;
     const PreSlots S = pre_owner_slots(P, g, kk, ii);
-    PreGT T;
-    if (!pre_owner_tri(P, g, kk, ii, S, z, T)) return;
+    PreGT Tg;
+    if (!pre_owner_tri(P, g, kk, ii, S, z, Tg)) continue;
     if (pos < P.otcap) {
       int32_t* o = P.otris + 3 * pos;
-      o[0] = P.vmap[T.c[0].id];
-      o[1] = P.vmap[T.c[1].id];
-      o[2] = P.vmap[T.c[2].id];
+      o[0] = P.vmap[Tg.c[0].id];
+      o[1] = P.vmap[Tg.c[1].id];
+      o[2] = P.vmap[Tg.c[2].id];
       P.ocodes[pos] = 0;
     }
-  };
-  for (int q = (int)threadIdx.x; q < 4 * n; q += 256) tri_item(q, true);
+  }
+}
+__global__ void __launch_bounds__(256) k_pre_mesh_cut_tris(OneSrc src, PreArgs P) {
+  __shared__ int64_t dl[512];
+  __shared__ int nd;
+  const Img& d = src.d;
+  const Geo g = d.g;
+  if (threadIdx.x == 0) nd = 0;
   __syncthreads();
-  const int nh = nheavy;
-  for (int h = (int)threadIdx.x; h < nh; h += 256) tri_item(heavy[h], false);
+  const int64_t T = P.counts[3];
+  const int64_t NV = *P.nused;
+  pre_dense(4 * T, dl, &nd, [&](int64_t it) -> bool {
+    const uint32_t rt = P.rtri[P.tlist[it >> 2]];
+    const int z = (int)(it & 3);
+    return ((rt >> (6 * z)) & 63u) && ((rt >> (28 + z)) & 1u);
+  }, [&](int64_t it) {
+    int kk, ii;
+    pre_tl_owner(g, P, it >> 2, kk, ii);
+    const int z = (int)(it & 3);
+    const int64_t v = (int64_t)kk * g.NI + ii;
+    const uint32_t rt = P.rtri[v];
+    int before = 0;
+    for (int z2 = 0; z2 < z; ++z2) before += (int)((rt >> (6 * z2)) & 63u);
+    pre_owner_triangle(d, g, P, kk, ii, z, P.rcount[v], rt, P.rtbase[v] + before, NV);
+  });
 }
 
 // Compaction of the grid vertices: the used ones keep their order.  Per block
@@ -1862,7 +1954,8 @@ struct PreLayout {
   CallLayout L;
   size_t off_mid, off_split, off_flags, off_ins, off_counts, off_out, off_snap, total;
   // the retriangulation (sbmt_preprocess_mesh): grid on-polyline bytes, per-owner counts and bases, sizes
-  size_t off_onp, off_rcount, off_rtri, off_rbase, off_out2, off_gverts, off_used, off_vmap, off_vbsum, off_nused;
+  size_t off_onp, off_rcount, off_rtri, off_rbase, off_out2, off_gverts, off_used, off_vmap, off_vbsum, off_nused,
+      off_tlist, off_rtbase;
   int64_t nvblk;  // blocks of the vertex compaction scan
   int64_t nmid, nown;
 };
@@ -1889,7 +1982,7 @@ static sbmt_status pre_layout(const sbmt_image* img, bool need_ptr, PreLayout* P
   P->off_snap = off;
   off = align256(off + (size_t)P->nown * 4);
   P->off_onp = P->off_rcount = P->off_rtri = P->off_rbase = P->off_out2 = 0;
-  P->off_gverts = P->off_used = P->off_vmap = P->off_vbsum = P->off_nused = 0;
+  P->off_gverts = P->off_used = P->off_vmap = P->off_vbsum = P->off_nused = P->off_tlist = P->off_rtbase = 0;
   P->nvblk = 0;
   if (mesh) {
     P->off_onp = off;
@@ -1914,6 +2007,10 @@ static sbmt_status pre_layout(const sbmt_image* img, bool need_ptr, PreLayout* P
     off = align256(off + (size_t)P->nvblk * 8);
     P->off_nused = off;
     off = align256(off + 8);
+    P->off_tlist = off;
+    off = align256(off + (size_t)P->nown * 4);
+    P->off_rtbase = off;
+    off = align256(off + (size_t)P->nown * 8);
   }
   P->total = off;
   return SBMT_OK;

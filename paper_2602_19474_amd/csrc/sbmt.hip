@@ -2746,10 +2746,15 @@ sbmt_status sbmt_preprocess_mesh(sbmt_handle h, const sbmt_image* img, double a,
   int64_t* out2 = (int64_t*)(w + PL.off_out2);
   const Geo& gg = PL.L.g[0];
   const int64_t nwb = ((int64_t)(gg.CH + 1) * gg.wpr + 255) / 256;
-  // blocks of the grid-stride passes: as many per compute unit as their
-  // registers let run at once
+  // grid-stride passes: as many blocks as run at once on the device
   const int ncu = std::max(h->cus, 1);
-  const dim3 glight((unsigned)(8 * ncu)), gheavy((unsigned)(2 * ncu));
+  auto resident = [ncu](auto* k) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k), 256, 0) != hipSuccess ||
+        nb < 1)
+      nb = 2;
+    return dim3((unsigned)(nb * ncu));
+  };
   hipLaunchKernelGGL(k_pre_mesh_touch, dim3((unsigned)nwb), dim3(256), 0, s, src, P);
   // the touched owners' list: counts per row segment, their offsets, the list
   hipLaunchKernelGGL(k_pre_mesh_tcount, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
@@ -2757,9 +2762,9 @@ sbmt_status sbmt_preprocess_mesh(sbmt_handle h, const sbmt_image* img, double a,
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, sh);
   hipLaunchKernelGGL(k_scan_apply, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
   hipLaunchKernelGGL(k_pre_mesh_count, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
-  hipLaunchKernelGGL(k_pre_mesh_probe, glight, dim3(256), 0, s, src, P, sh);
-  hipLaunchKernelGGL(k_pre_mesh_edges, glight, dim3(256), 0, s, src, P, sh);
-  hipLaunchKernelGGL(k_pre_mesh_cut_count, gheavy, dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_mesh_probe, resident(&k_pre_mesh_probe), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_mesh_edges, resident(&k_pre_mesh_edges), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_mesh_cut_count, resident(&k_pre_mesh_cut_count), dim3(256), 0, s, src, P, sh);
   // the output counts per row segment and their offsets
   hipLaunchKernelGGL(k_pre_mesh_segsum, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
   hipLaunchKernelGGL(k_scan_reduce, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
@@ -2769,10 +2774,12 @@ sbmt_status sbmt_preprocess_mesh(sbmt_handle h, const sbmt_image* img, double a,
   hipLaunchKernelGGL(k_pre_vscan_count, dim3((unsigned)PL.nvblk), dim3(256), 0, s, P);
   hipLaunchKernelGGL(k_pre_vscan_top, dim3(1), dim3(256), 0, s, P, PL.nvblk);
   hipLaunchKernelGGL(k_pre_vscan_apply, dim3((unsigned)PL.nvblk), dim3(256), 0, s, P);
-  hipLaunchKernelGGL(k_pre_mesh_vertices, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_mesh_vbase, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_mesh_edge_verts, resident(&k_pre_mesh_edge_verts), dim3(256), 0, s, src, P);
+  hipLaunchKernelGGL(k_pre_mesh_inner_verts, resident(&k_pre_mesh_inner_verts), dim3(256), 0, s, src, P);
   hipLaunchKernelGGL(k_pre_mesh_triangles, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
-  hipLaunchKernelGGL(k_pre_mesh_whole_tris, glight, dim3(256), 0, s, src, P);
-  hipLaunchKernelGGL(k_pre_mesh_cut_tris, gheavy, dim3(256), 0, s, src, P);
+  hipLaunchKernelGGL(k_pre_mesh_whole_tris, resident(&k_pre_mesh_whole_tris), dim3(256), 0, s, src, P);
+  hipLaunchKernelGGL(k_pre_mesh_cut_tris, resident(&k_pre_mesh_cut_tris), dim3(256), 0, s, src, P);
   hipLaunchKernelGGL(k_pre_mesh_sizes, dim3(1), dim3(1), 0, s, P, sh, out2);
   if (hipGetLastError() != hipSuccess) return SBMT_E_DEVICE;
   if ((st = pre_read_sizes(h, out2, 8, counts, s)) != SBMT_OK) return st;

@@ -56,7 +56,7 @@ struct PreArgs {
   int64_t* vbsum;        // per block of kPreVScan grid vertices: used count, then base
   int64_t* nused;        // [1]: grid vertices in the mesh
 };
-constexpr int kPreVScan = 4096;  // grid vertices per block of the compaction scan
+constexpr int kPreVScan = 16384;  // grid vertices per block of the compaction scan
 constexpr uint8_t kPreMoved = 8;
 constexpr int kPreTally = 8;
 constexpr int kPreCounts = kPreTally + 512;
@@ -1382,58 +1382,49 @@ __device__ __forceinline__ bool pre_owner_tri(const PreArgs& P, const Geo& g, in
   return true;
 }
 
-// The new vertices of a touched owner, from mesh index NV + pos (NV: the
-// grid vertices kept).
-__device__ void pre_owner_vertices(const Img& d, const Geo& g, const PreArgs& P, int k, int i, uint32_t rc,
-                                   int64_t pos, int64_t NV) {
+// The crossings of edge slot q of owner (k, i) (cq of them, by position
+// along the edge from its lower-numbered end), from mesh index `first`.
+__device__ void pre_slot_vertices(const Img& d, const Geo& g, const PreArgs& P, int k, int i, int q, int cq,
+                                  int64_t first) {
   double2* Vout = reinterpret_cast<double2*>(P.overts);
   const PreSlots S = pre_owner_slots(P, g, k, i);
   PreBits Bits;
   pre_owner_bits(d, g, P, k, i, Bits);
-  const int nc = pre_rc_before(rc, 8);
-  int w = 0;
-  for (int q = 0; q < 8; ++q) {
-    const int cq = pre_rc_cross(rc, q);
-    if (!cq) continue;
-    PreGV A, B;
-    pre_edge_slot(P, g, k, i, S, q, A, B);
-    const PreGV& L = A.id < B.id ? A : B;
-    const PreGV& H = A.id < B.id ? B : A;
-    double te[3], xs[3], ys[3];
-    int m = 0;
-    pre_edge_crossings(d, g, L, H, [&](const PreSeg& Sg, double t) {
-      if (m >= 3) return;
-      te[m] = t;
-      pre_crossing_xy(Sg, L, H, xs[m], ys[m]);
-      for (int z = m++; z > 0 && te[z - 1] > te[z]; --z) {  // by position along the edge
-        const double a = te[z], bx = xs[z], by = ys[z];
-        te[z] = te[z - 1];
-        xs[z] = xs[z - 1];
-        ys[z] = ys[z - 1];
-        te[z - 1] = a;
-        xs[z - 1] = bx;
-        ys[z - 1] = by;
-      }
-    }, &Bits);
-    for (int z = 0; z < cq && z < m; ++z) {
-      const int64_t id = NV + pos + w + z;
-      if (id < P.ovcap) Vout[id] = make_double2(xs[z], ys[z]);
+  PreGV A, B;
+  pre_edge_slot(P, g, k, i, S, q, A, B);
+  const PreGV& L = A.id < B.id ? A : B;
+  const PreGV& H = A.id < B.id ? B : A;
+  double te[3], xs[3], ys[3];
+  int m = 0;
+  pre_edge_crossings(d, g, L, H, [&](const PreSeg& Sg, double t) {
+    if (m >= 3) return;
+    te[m] = t;
+    pre_crossing_xy(Sg, L, H, xs[m], ys[m]);
+    for (int z = m++; z > 0 && te[z - 1] > te[z]; --z) {  // by position along the edge
+      const double a = te[z], bx = xs[z], by = ys[z];
+      te[z] = te[z - 1];
+      xs[z] = xs[z - 1];
+      ys[z] = ys[z - 1];
+      te[z - 1] = a;
+      xs[z - 1] = bx;
+      ys[z - 1] = by;
     }
-    w += cq;
-  }
-  int nin = 0;
-  for (int t = 0; t < 2 && nin < pre_rc_inner(rc); ++t) {
-    PreGT T[2];
-    const int m = pre_slot_tris(P, g, k, i, S, t, T);
-    for (int z = 0; z < m; ++z) {
-      PrePt in;
-      if (pre_tri_mesh(d, g, P, T[z], [](const PrePt&, const PrePt&, const PrePt&, int) {}, &in, nullptr, &Bits)) {
-        const int64_t id = NV + pos + nc + nin;
-        if (id < P.ovcap) Vout[id] = make_double2(in.x, in.y);
-        ++nin;
-      }
-    }
-  }
+  }, &Bits);
+  for (int z = 0; z < cq && z < m; ++z)
+    if (first + z < P.ovcap) Vout[first + z] = make_double2(xs[z], ys[z]);
+}
+// The polyline vertex strictly inside grid triangle z of owner (k, i), at
+// mesh index `at`.
+__device__ void pre_inner_vertex(const Img& d, const Geo& g, const PreArgs& P, int k, int i, int z, int64_t at) {
+  const PreSlots S = pre_owner_slots(P, g, k, i);
+  PreGT T;
+  if (!pre_owner_tri(P, g, k, i, S, z, T)) return;
+  PreBits Bits;
+  pre_owner_bits(d, g, P, k, i, Bits);
+  PrePt in;
+  if (pre_tri_mesh(d, g, P, T, [](const PrePt&, const PrePt&, const PrePt&, int) {}, &in, nullptr, &Bits) &&
+      at < P.ovcap)
+    reinterpret_cast<double2*>(P.overts)[at] = make_double2(in.x, in.y);
 }
 
 // Output triangles of grid triangle z of a touched owner, from position pos.
@@ -1506,27 +1497,6 @@ __device__ void pre_owner_triangle(const Img& d, const Geo& g, const PreArgs& P,
   }, &in, nullptr, &Bits);
 }
 
-// The mesh kernels run one wave per row segment (owners interleaved across
-// lanes); quiet owners are done in place, touched ones are gathered in LDS
-// and finished by the whole block, so that the boundary work runs on full
-// waves.  List entries: wave << 10 | owner offset in its segment.
-__device__ __forceinline__ void pre_list_push(int* list, int* nlist, bool act, int entry, int* rel, int relv) {
-  const unsigned long long bal = __ballot(act);
-  if (!bal) return;
-  int base = 0;
-  if ((threadIdx.x & 63) == 0) base = atomicAdd(nlist, (int)__popcll(bal));
-  base = __shfl(base, 0);
-  if (act) {
-    list[base + lanes_below(bal)] = entry;
-    if (rel) rel[base + lanes_below(bal)] = relv;
-  }
-}
-__device__ __forceinline__ void pre_list_owner(const Geo& g, int entry, int& k, int& i) {
-  const uint32_t sg = blockIdx.x * 4u + (uint32_t)(entry >> 10);
-  const uint32_t kk = sg / (uint32_t)g.NCB;
-  k = (int)kk;
-  i = (int)(sg - kk * (uint32_t)g.NCB) * kCB + (entry & 1023);
-}
 
 // The touched owners of each row segment (their list offsets come from a scan).
 __global__ void __launch_bounds__(256) k_pre_mesh_tcount(OneSrc src, PreArgs P, Shared sh) {
@@ -1625,10 +1595,9 @@ __device__ __forceinline__ void pre_tl_owner(const Geo& g, const PreArgs& P, int
 // counts an uncut one and marks a cut one (its cut bit), <false>
 // retriangulates a cut one; the results are added to the owner's words.
 template <bool kProbe>
-__device__ __forceinline__ void pre_mesh_tri_count(const Img& d, const Geo& g, const PreArgs& P, int64_t it) {
+__device__ __forceinline__ void pre_mesh_tri_count(const Img& d, const Geo& g, const PreArgs& P, int64_t t, int z) {
   int kk, ii;
-  pre_tl_owner(g, P, it >> 2, kk, ii);
-  const int z = (int)(it & 3);
+  pre_tl_owner(g, P, t, kk, ii);
   const PreSlots S = pre_owner_slots(P, g, kk, ii);
   PreGT Tg;
   if (!pre_owner_tri(P, g, kk, ii, S, z, Tg)) return;
@@ -1659,23 +1628,33 @@ __device__ __forceinline__ void pre_mesh_tri_count(const Img& d, const Geo& g, c
   if (add) atomicAdd(&P.rcount[v], add);
 }
 // One item per grid triangle of the touched owners (4 per owner), over a
-// grid-stride loop; at most 128 VGPRs (four waves per SIMD).
+// grid-stride loop; at most 128 VGPRs (four waves per SIMD).  The first
+// triangles of the two slots come first (items 0 .. 2n-1), then the second
+// ones, which only owners with a split side have: waves of absent triangles
+// end early.
 __global__ void __launch_bounds__(256, 4) k_pre_mesh_probe(OneSrc src, PreArgs P, Shared sh) {
   const Img& d = src.d;
   const Geo g = d.g;
   const int64_t T = sh.seg_off[sh.nseg].x;  // touched owners
   for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < 4 * T; it += (int64_t)gridDim.x * 256)
-    pre_mesh_tri_count<true>(d, g, P, it);
+    pre_mesh_tri_count<true>(d, g, P, (it >= 2 * T ? it - 2 * T : it) >> 1, 2 * (int)(it & 1) + (it >= 2 * T ? 1 : 0));
 }
-// Crossings of the touched owners' edge slots, one item per slot (8 per owner).
+// Crossings of the touched owners' edge slots, one item per slot (8 per
+// owner): the whole or first halves of the owned sides first (items
+// 0 .. 3n-1), then the second halves and the fan edges, which only owners
+// with a split side have.
 __global__ void __launch_bounds__(256) k_pre_mesh_edges(OneSrc src, PreArgs P, Shared sh) {
   const Img& d = src.d;
   const Geo g = d.g;
   const int64_t T = sh.seg_off[sh.nseg].x;  // touched owners
-  for (int64_t e8 = (int64_t)blockIdx.x * 256 + threadIdx.x; e8 < 8 * T; e8 += (int64_t)gridDim.x * 256) {
+  for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < 8 * T; it += (int64_t)gridDim.x * 256) {
+    const bool first = it < 3 * T;
+    const int64_t r = first ? it : it - 3 * T;
+    const int64_t t = first ? r / 3 : r / 5;
+    const int j = (int)(r - t * (first ? 3 : 5));
+    const int e = first ? 2 * j : (j < 3 ? 2 * j + 1 : j + 3);  // 0 2 4, then 1 3 5 6 7
     int kk, ii;
-    pre_tl_owner(g, P, e8 >> 3, kk, ii);
-    const int e = (int)(e8 & 7);
+    pre_tl_owner(g, P, t, kk, ii);
     const PreSlots S = pre_owner_slots(P, g, kk, ii);
     PreGV A, B;
     if (!pre_edge_slot(P, g, kk, ii, S, e, A, B)) continue;
@@ -1702,7 +1681,7 @@ __global__ void __launch_bounds__(256) k_pre_mesh_cut_count(OneSrc src, PreArgs 
   const int64_t T = sh.seg_off[sh.nseg].x;
   pre_dense(4 * T, dl, &nd, [&](int64_t it) -> bool {
     return (P.rtri[P.tlist[it >> 2]] >> (28 + (it & 3))) & 1u;
-  }, [&](int64_t it) { pre_mesh_tri_count<false>(d, g, P, it); });
+  }, [&](int64_t it) { pre_mesh_tri_count<false>(d, g, P, it >> 2, (int)(it & 3)); });
 }
 
 // Per row segment: new vertices, triangles and cut grid triangles of its
@@ -1731,45 +1710,71 @@ __global__ void __launch_bounds__(256) k_pre_mesh_segsum(OneSrc src, PreArgs P, 
   }
 }
 
-// New vertices at their offsets: the crossings of each owned edge slot in
-// order from its lower-numbered end, then the polyline vertices inside the
-// owner's triangles; each owner with new vertices records its first index.
-__global__ void __launch_bounds__(256) k_pre_mesh_vertices(OneSrc src, PreArgs P, Shared sh) {
-  __shared__ int list[4 * kCB];
-  __shared__ int rel[4 * kCB];
-  __shared__ int nlist;
-  const Img& d = src.d;
-  const Geo g = d.g;
+// New vertices: the crossings of each owned edge slot in order from its
+// lower-numbered end, then the polyline vertices inside the owner's
+// triangles; each owner with new vertices records its first index (rbase,
+// relative to the grid vertices kept).
+__global__ void __launch_bounds__(256) k_pre_mesh_vbase(OneSrc src, PreArgs P, Shared sh) {
+  const Geo g = src.d.g;
   int64_t seg;
   int k, i0;
-  const bool on = pre_segment(g, sh, seg, k, i0) && sh.seg_cnt[seg].x > 0;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (threadIdx.x == 0) nlist = 0;
-  __syncthreads();
-  if (on) {
-    int acc = 0;
-    for (int j = 0; j < 4; ++j) {
-      const int i = i0 + 64 * j + lane;
-      const int64_t v = (int64_t)k * g.NI + i;
-      const uint32_t rc = i < g.NI ? P.rcount[v] : 0u;
-      const int n = pre_rc_before(rc, 8) + pre_rc_inner(rc);
-      const int incl = wave_incl_scan_dpp(n);
-      if (n) P.rbase[v] = sh.seg_off[seg].x + acc + (incl - n);
-      pre_list_push(list, &nlist, n > 0, (wv << 10) | (64 * j + lane), rel, acc + (incl - n));
-      acc += __builtin_amdgcn_readlane(incl, 63);
-    }
+  if (!pre_segment(g, sh, seg, k, i0) || sh.seg_cnt[seg].x == 0) return;  // wave-uniform
+  const int lane = threadIdx.x & 63;
+  int64_t acc = sh.seg_off[seg].x;
+  for (int j = 0; j < 4; ++j) {
+    const int i = i0 + 64 * j + lane;
+    const int64_t v = (int64_t)k * g.NI + i;
+    const uint32_t rc = i < g.NI ? P.rcount[v] : 0u;
+    const int n = pre_rc_before(rc, 8) + pre_rc_inner(rc);
+    const int incl = wave_incl_scan_dpp(n);
+    if (n) P.rbase[v] = acc + (incl - n);
+    acc += __builtin_amdgcn_readlane(incl, 63);
   }
+}
+// The crossings, one item per edge slot of the touched owners; the slots with
+// crossings are gathered per block and done on full blocks.
+__global__ void __launch_bounds__(256) k_pre_mesh_edge_verts(OneSrc src, PreArgs P) {
+  __shared__ int64_t dl[512];
+  __shared__ int nd;
+  const Img& d = src.d;
+  const Geo g = d.g;
+  if (threadIdx.x == 0) nd = 0;
   __syncthreads();
-  const int n = nlist;
-  if (n == 0) return;
+  const int64_t T = P.counts[3];
   const int64_t NV = *P.nused;
-  for (int q = (int)threadIdx.x; q < n; q += 256) {
+  pre_dense(8 * T, dl, &nd, [&](int64_t e8) -> bool {
+    return pre_rc_cross(P.rcount[P.tlist[e8 >> 3]], (int)(e8 & 7)) != 0;
+  }, [&](int64_t e8) {
     int kk, ii;
-    pre_list_owner(g, list[q], kk, ii);
-    const int64_t sg = (int64_t)blockIdx.x * 4 + (list[q] >> 10);
-    const uint32_t rc = P.rcount[(int64_t)kk * g.NI + ii];
-    pre_owner_vertices(d, g, P, kk, ii, rc, sh.seg_off[sg].x + rel[q], NV);
-  }
+    pre_tl_owner(g, P, e8 >> 3, kk, ii);
+    const int q = (int)(e8 & 7);
+    const int64_t v = (int64_t)kk * g.NI + ii;
+    const uint32_t rc = P.rcount[v];
+    pre_slot_vertices(d, g, P, kk, ii, q, pre_rc_cross(rc, q), NV + P.rbase[v] + pre_rc_before(rc, q));
+  });
+}
+// The inner polyline vertices, one item per grid triangle of the touched
+// owners; those with one are gathered per block and found on full blocks.
+__global__ void __launch_bounds__(256) k_pre_mesh_inner_verts(OneSrc src, PreArgs P) {
+  __shared__ int64_t dl[512];
+  __shared__ int nd;
+  const Img& d = src.d;
+  const Geo g = d.g;
+  if (threadIdx.x == 0) nd = 0;
+  __syncthreads();
+  const int64_t T = P.counts[3];
+  const int64_t NV = *P.nused;
+  pre_dense(4 * T, dl, &nd, [&](int64_t it) -> bool {
+    return (P.rtri[P.tlist[it >> 2]] >> (24 + (it & 3))) & 1u;
+  }, [&](int64_t it) {
+    int kk, ii;
+    pre_tl_owner(g, P, it >> 2, kk, ii);
+    const int z = (int)(it & 3);
+    const int64_t v = (int64_t)kk * g.NI + ii;
+    const uint32_t rc = P.rcount[v], rt = P.rtri[v];
+    const int64_t at = NV + P.rbase[v] + pre_rc_before(rc, 8) + __builtin_popcount((rt >> 24) & ((1u << z) - 1u));
+    pre_inner_vertex(d, g, P, kk, ii, z, at);
+  });
 }
 
 // Output triangles at their offsets, with their codes: a quiet owner's slots
@@ -1873,8 +1878,16 @@ __global__ void __launch_bounds__(256) k_pre_vscan_count(PreArgs P) {
   __shared__ int part[4];
   const int64_t NV = P.gsizes[0] < P.usedcap ? P.gsizes[0] : P.usedcap;
   const int64_t b0 = (int64_t)blockIdx.x * kPreVScan;
+  // four flags (bytes 0 or 1) per word, sixteen words per thread
+  const uint32_t* u4 = reinterpret_cast<const uint32_t*>(P.used);
   int n = 0;
-  for (int q = threadIdx.x; q < kPreVScan; q += 256) n += (b0 + q < NV && P.used[b0 + q]) ? 1 : 0;
+  for (int q = 0; q < kPreVScan / 1024; ++q) {
+    const int64_t at = b0 + 4 * ((int64_t)q * 256 + threadIdx.x);
+    if (at >= NV) break;
+    uint32_t w = u4[at >> 2];
+    if (NV - at < 4) w &= (1u << (8 * (NV - at))) - 1u;
+    n += __builtin_popcount(w);
+  }
   const int w = __builtin_amdgcn_readlane(wave_incl_scan_dpp(n), 63);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = w;
   __syncthreads();
@@ -1903,27 +1916,43 @@ __global__ void __launch_bounds__(256) k_pre_vscan_top(PreArgs P, int64_t nblk) 
   if (threadIdx.x == 0) *P.nused = run;
 }
 __global__ void __launch_bounds__(256) k_pre_vscan_apply(PreArgs P) {
-  __shared__ int part[4];
+  __shared__ int part[16][4];
   const int64_t NV = P.gsizes[0] < P.usedcap ? P.gsizes[0] : P.usedcap;
   const int64_t b0 = (int64_t)blockIdx.x * kPreVScan;
   if (b0 >= NV) return;
-  // each thread takes 16 consecutive vertices
-  const int64_t v0 = b0 + 16 * (int64_t)threadIdx.x;
-  uint32_t bits = 0;
-  for (int q = 0; q < 16; ++q) bits |= (v0 + q < NV && P.used[v0 + q]) ? (1u << q) : 0u;
-  const int n = __builtin_popcount(bits);
-  const int incl = wave_incl_scan_dpp(n);
-  if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = incl;
-  __syncthreads();
-  int64_t id = P.vbsum[blockIdx.x] + (incl - n);
-  for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) id += part[w];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double2* G = reinterpret_cast<const double2*>(P.verts);
   double2* O = reinterpret_cast<double2*>(P.overts);
-  for (int q = 0; q < 16; ++q) {
-    if (!((bits >> q) & 1u)) continue;
-    P.vmap[v0 + q] = (int32_t)id;
-    if (id < P.ovcap) O[id] = G[v0 + q];
-    ++id;
+  int64_t run = P.vbsum[blockIdx.x];
+  // rounds of 256 consecutive vertices, sixteen rounds per chunk: the ballots
+  // of a chunk, the waves' counts in LDS, then the ids
+  for (int c = 0; c < kPreVScan / 4096; ++c) {
+    unsigned long long bal[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int64_t v = b0 + (int64_t)(16 * c + q) * 256 + threadIdx.x;
+      bal[q] = __ballot(v < NV && P.used[v]);
+      if (lane == 0) part[q][wv] = (int)__popcll(bal[q]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      int before = 0, tot = 0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int tw = part[q][w];
+        before += w < wv ? tw : 0;
+        tot += tw;
+      }
+      const int64_t v = b0 + (int64_t)(16 * c + q) * 256 + threadIdx.x;
+      if ((bal[q] >> lane) & 1ull) {
+        const int64_t id = run + before + lanes_below(bal[q]);
+        P.vmap[v] = (int32_t)id;
+        if (id < P.ovcap) O[id] = G[v];
+      }
+      run += tot;
+    }
+    __syncthreads();
   }
 }
 

@@ -1670,8 +1670,10 @@ __global__ void __launch_bounds__(256) k_pre_mesh_edges(OneSrc src, PreArgs P, S
   }
 }
 // The cut grid triangles (cut bit set, no count yet), gathered per block and
-// retriangulated on full blocks.
-__global__ void __launch_bounds__(256) k_pre_mesh_cut_count(OneSrc src, PreArgs P, Shared sh) {
+// retriangulated on full blocks.  The retriangulating kernels are held to
+// 128 VGPRs (four waves per SIMD): spilling more to scratch costs less than
+// the latency two waves per SIMD leave uncovered.
+__global__ void __launch_bounds__(256, 4) k_pre_mesh_cut_count(OneSrc src, PreArgs P, Shared sh) {
   __shared__ int64_t dl[512];
   __shared__ int nd;
   const Img& d = src.d;
@@ -1755,7 +1757,7 @@ __global__ void __launch_bounds__(256) k_pre_mesh_edge_verts(OneSrc src, PreArgs
 }
 // The inner polyline vertices, one item per grid triangle of the touched
 // owners; those with one are gathered per block and found on full blocks.
-__global__ void __launch_bounds__(256) k_pre_mesh_inner_verts(OneSrc src, PreArgs P) {
+__global__ void __launch_bounds__(256, 4) k_pre_mesh_inner_verts(OneSrc src, PreArgs P) {
   __shared__ int64_t dl[512];
   __shared__ int nd;
   const Img& d = src.d;
@@ -1845,7 +1847,7 @@ __global__ void __launch_bounds__(256) k_pre_mesh_whole_tris(OneSrc src, PreArgs
     }
   }
 }
-__global__ void __launch_bounds__(256) k_pre_mesh_cut_tris(OneSrc src, PreArgs P) {
+__global__ void __launch_bounds__(256, 4) k_pre_mesh_cut_tris(OneSrc src, PreArgs P) {
   __shared__ int64_t dl[512];
   __shared__ int nd;
   const Img& d = src.d;

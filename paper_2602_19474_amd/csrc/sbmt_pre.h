@@ -1781,13 +1781,17 @@ __global__ void __launch_bounds__(256, 4) k_pre_mesh_inner_verts(OneSrc src, Pre
 
 // Output triangles at their offsets, with their codes: a quiet owner's slots
 // as they are (code 0); a touched owner's first output triangle is recorded
-// for the dense pass.
+// for the dense pass.  The 64 owners of a wave step hold consecutive output
+// ranges: their triangles are staged in LDS by rank and lane j writes ranks j
+// and j + 64 (a touched owner's ranks are left to the dense pass).
 __global__ void __launch_bounds__(256) k_pre_mesh_triangles(OneSrc src, PreArgs P, Shared sh) {
+  __shared__ Tri3 stage[4][128];
+  __shared__ uint8_t full[4][128];
   const Geo g = src.d.g;
   int64_t seg;
   int k, i0;
   if (!pre_segment(g, sh, seg, k, i0)) return;  // wave-uniform
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t t0 = sh.seg_off[seg].y;
   const int o = k & 1;
   int acc = 0;
@@ -1797,25 +1801,48 @@ __global__ void __launch_bounds__(256) k_pre_mesh_triangles(OneSrc src, PreArgs 
     const uint32_t rc = i < g.NI ? P.rcount[v] : 0u;
     const int n = pre_rc_tris(rc);
     const int incl = wave_incl_scan_dpp(n);
-    int64_t pos = t0 + acc + (incl - n);
-    if (n > 0 && (P.flags[v] & kPreTouched)) {
-      P.rtbase[v] = pos;
-    } else if (n > 0) {
-      for (int t = 0; t < 2; ++t) {
-        if (!pre_slot_ok(g, k, i, t)) continue;
-        const int64_t c1 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o) : v + 1;
-        const int64_t c2 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o - 1) : (int64_t)(k + 1) * g.NI + (i + o);
-        if (pos < P.otcap) {
-          int32_t* out = P.otris + 3 * pos;
-          out[0] = P.vmap[v];
-          out[1] = P.vmap[c1];
-          out[2] = P.vmap[c2];
+    const int tot = __builtin_amdgcn_readlane(incl, 63);  // at most 4 * 64 (a touched owner: 4 * 63)
+    const bool touched = n > 0 && (P.flags[v] & kPreTouched);
+    if (touched) P.rtbase[v] = t0 + acc + (incl - n);
+    for (int b = 0; b < tot; b += 128) {  // uniform
+      full[wv][lane] = full[wv][lane + 64] = 0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (n > 0 && !touched) {
+        int r = incl - n - b;
+        for (int t = 0; t < 2; ++t) {
+          if (!pre_slot_ok(g, k, i, t)) continue;
+          if (r >= 0 && r < 128) {
+            const int64_t c1 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o) : v + 1;
+            const int64_t c2 = t == 0 ? (int64_t)(k + 1) * g.NI + (i + o - 1) : (int64_t)(k + 1) * g.NI + (i + o);
+            Tri3 t3;
+            t3.a = P.vmap[v];
+            t3.b = P.vmap[c1];
+            t3.c = P.vmap[c2];
+            stage[wv][r] = t3;
+            full[wv][r] = 1;
+          }
+          ++r;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int r = lane + 64 * h;
+        const int64_t pos = t0 + acc + b + r;
+        if (full[wv][r] && pos < P.otcap) {
+          *reinterpret_cast<Tri3*>(P.otris + 3 * pos) = stage[wv][r];
           P.ocodes[pos] = 0;
         }
-        ++pos;
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    acc += __builtin_amdgcn_readlane(incl, 63);
+    acc += tot;
   }
 }
 

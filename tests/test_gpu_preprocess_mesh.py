@@ -143,3 +143,57 @@ def test_full_size_noise8192_bounds_and_crops():
         assert Ra.shape == Ga.shape and Ra.shape[0] > 1000, (Ra.shape, Ga.shape)
         assert np.array_equal(Ra[:, 6], Ga[:, 6])
         assert np.abs(Ra[:, :6] - Ga[:, :6]).max() <= 1e-9
+
+
+def test_refusals_capacity_and_repeated_calls():
+    """sbmt_preprocess_mesh through the C ABI: inadmissible thresholds and a short
+    workspace are refused; too few rows give the capacity status with the counts
+    filled in and nothing written past the capacity; exact capacities give the
+    wrapper's mesh; calls on one workspace repeat exactly (every per-call state is
+    cleared)."""
+    import ctypes
+
+    import torch
+    from paper_2602_19474_amd import _lib, context, _image, _stream_ptr
+    from paper_2602_19474_amd.preprocess import paper_thresholds, preprocess_mesh
+    print("[gpu-pre-mesh] refusals, capacity, repeats", flush=True)
+    bm = torch.from_numpy(wl.ellipses(150, 130, g=wl.rng(91, 4))).to("cuda")
+    ref = preprocess_mesh(bm, 1)
+    nv, nt = ref.verts.shape[0], ref.tris.shape[0]
+    L = _lib.lib()
+    img = _image(bm, 1, 0)
+    ws_bytes, gbound = ctypes.c_size_t(), ctypes.c_int64()
+    assert L.sbmt_pre_mesh_query(ctypes.byref(img), ctypes.byref(ws_bytes), ctypes.byref(gbound)) == 0
+    ws = torch.empty(int(ws_bytes.value), dtype=torch.uint8, device="cuda")
+    h = context(0).handle
+    counts = (ctypes.c_int64 * 8)()
+    a, b, c = paper_thresholds(1)
+    # one spare row past each capacity, holding a sentinel
+    verts = torch.full((nv + 1, 2), -7.0, dtype=torch.float64, device="cuda")
+    tris = torch.full((nt + 1, 3), -7, dtype=torch.int32, device="cuda")
+    codes = torch.full((nt + 1,), 7, dtype=torch.uint8, device="cuda")
+
+    def call(th, wsb, vcap, tcap):
+        return L.sbmt_preprocess_mesh(h, ctypes.byref(img), *th, ws.data_ptr(), wsb, verts.data_ptr(), vcap,
+                                      tris.data_ptr(), codes.data_ptr(), tcap, counts, _stream_ptr(None))
+
+    for th in ((0.4, 0.2, 0.1), (0.4, 0.1, 0.29), (0.5, 0.1, 0.1), (-0.1, 0.0, 0.0)):
+        assert call(th, int(ws_bytes.value), nv, nt) == -1, th
+    assert call((a, b, c), int(ws_bytes.value) - 1, nv, nt) == -4
+    for vcap, tcap in ((0, 0), (nv - 1, nt), (nv, nt - 1)):
+        verts.fill_(-7.0)
+        tris.fill_(-7)
+        codes.fill_(7)
+        assert call((a, b, c), int(ws_bytes.value), vcap, tcap) == -7, (vcap, tcap)
+        assert (counts[0], counts[1], counts[5]) == (nv, nt, -7)
+        torch.cuda.synchronize()
+        assert bool((verts[vcap:] == -7.0).all()) and bool((tris[tcap:] == -7).all()) and bool((codes[tcap:] == 7).all())
+    for rep in range(3):
+        verts[:nv] = 0.0
+        tris[:nt] = 0
+        assert call((a, b, c), int(ws_bytes.value), nv, nt) == 0, rep
+        torch.cuda.synchronize()
+        assert (counts[0], counts[1], counts[5], counts[6], counts[7]) == (nv, nt, 0, ref.n_grid_vertices, ref.n_cut)
+        assert torch.equal(verts[:nv], ref.verts) and torch.equal(tris[:nt], ref.tris)
+        assert torch.equal(codes[:nt], ref.codes)
+        assert bool((verts[nv:] == -7.0).all()) and bool((tris[nt:] == -7).all())

@@ -545,6 +545,20 @@ __global__ void __launch_bounds__(256) k_pre_inserted(OneSrc src, PreArgs P, Sha
   }
 }
 
+// One wave copies n int32 values staged in LDS to dst (4-byte aligned):
+// 16-byte stores over the 16-byte-aligned body, single words at its ends.
+__device__ __forceinline__ void pre_wave_store(const int32_t* src, int32_t* dst, int n, int lane) {
+  const int h = min((int)((16u - ((uint32_t)(uintptr_t)dst & 15u)) & 15u) >> 2, max(n, 0));
+  if (lane < h) dst[lane] = src[lane];
+  const int body = (n - h) >> 2;
+  for (int q = lane; q < body; q += 64) {
+    const int e = h + 4 * q;
+    *reinterpret_cast<int4*>(dst + e) = make_int4(src[e], src[e + 1], src[e + 2], src[e + 3]);
+  }
+  const int t0 = h + 4 * max(body, 0);
+  if (t0 + lane < n) dst[t0 + lane] = src[t0 + lane];
+}
+
 // Triangles of each row segment at their offsets (row segment base from the
 // scan, owner offsets by wave scans).  Per 64 owners the wave stages its
 // triangles in LDS and writes them as one contiguous run.  A slot with a split
@@ -613,9 +627,7 @@ __global__ void __launch_bounds__(256) k_pre_triangles(OneSrc src, PreArgs P, Sh
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int64_t lim = 3 * (P.tcap - base);  // staged entries that fit the capacity
-    int32_t* out = P.tris + 3 * base;
-    for (int q = lane; q < 3 * tot; q += 64)
-      if (q < lim) out[q] = st[q];
+    pre_wave_store(st, P.tris + 3 * base, (int)min((int64_t)(3 * tot), max(lim, (int64_t)0)), lane);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

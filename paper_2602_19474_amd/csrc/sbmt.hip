@@ -631,10 +631,11 @@ __global__ void __launch_bounds__(kThreads, 8) k_count(Src src, const int64_t* _
 // whatever the spread of slow owners over tiles.  Each record carries the
 // owner's position and its row's cell row; the classification replaces it in
 // place (with the owner's place in its tile in the spare bits 48..63) and the
-// owner's code goes to the owner map.
+// owner's code goes to the owner map.  Held to 64 VGPRs (eight waves per
+// SIMD): faster than the 78 it takes unbounded (six waves).
 // ---------------------------------------------------------------------------
 template <class Src, int RB>
-__global__ void __launch_bounds__(kThreads) k_slow_dense(Src src, Shared sh) {
+__global__ void __launch_bounds__(kThreads, 8) k_slow_dense(Src src, Shared sh) {
   __shared__ int64_t pre[kDenseLists + 1];
   if (threadIdx.x == 0) {
     int64_t t = 0;

@@ -2763,8 +2763,7 @@ sbmt_status sbmt_preprocess_mesh(sbmt_handle h, const sbmt_image* img, double a,
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, sh);
   hipLaunchKernelGGL(k_scan_apply, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
   hipLaunchKernelGGL(k_pre_mesh_count, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
-  hipLaunchKernelGGL(k_pre_mesh_probe, resident(&k_pre_mesh_probe), dim3(256), 0, s, src, P, sh);
-  hipLaunchKernelGGL(k_pre_mesh_edges, resident(&k_pre_mesh_edges), dim3(256), 0, s, src, P, sh);
+  hipLaunchKernelGGL(k_pre_mesh_probe_owner, resident(&k_pre_mesh_probe_owner), dim3(256), 0, s, src, P, sh);
   hipLaunchKernelGGL(k_pre_mesh_cut_count, resident(&k_pre_mesh_cut_count), dim3(256), 0, s, src, P, sh);
   // the output counts per row segment and their offsets
   hipLaunchKernelGGL(k_pre_mesh_segsum, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);

@@ -1603,11 +1603,10 @@ __device__ __forceinline__ void pre_tl_owner(const Geo& g, const PreArgs& P, int
   i = (int)(v - kk * (uint32_t)g.NI);
 }
 
-// Counts of the touched owners' grid triangles: pre_mesh_tri_count<true>
-// counts an uncut one and marks a cut one (its cut bit), <false>
-// retriangulates a cut one; the results are added to the owner's words.
-template <bool kProbe>
-__device__ __forceinline__ void pre_mesh_tri_count(const Img& d, const Geo& g, const PreArgs& P, int64_t t, int z) {
+// Counts of a cut grid triangle of a touched owner (item t * 4 + z of the
+// list): subdivision and template; triangles, inner vertex and the cut are
+// added to the owner's words.
+__device__ __forceinline__ void pre_mesh_cut_tri_count(const Img& d, const Geo& g, const PreArgs& P, int64_t t, int z) {
   int kk, ii;
   pre_tl_owner(g, P, t, kk, ii);
   const PreSlots S = pre_owner_slots(P, g, kk, ii);
@@ -1618,69 +1617,77 @@ __device__ __forceinline__ void pre_mesh_tri_count(const Img& d, const Geo& g, c
   int nt = 0;
   PrePt in;
   bool cut = false;
-  const int nin = pre_tri_mesh<kProbe>(d, g, P, Tg, [&](const PrePt& a, const PrePt& b, const PrePt& c, int) {
+  const int nin = pre_tri_mesh(d, g, P, Tg, [&](const PrePt& a, const PrePt& b, const PrePt& c, int) {
     ++nt;
     if (a.kind == 0) P.used[a.a] = 1;
     if (b.kind == 0) P.used[b.a] = 1;
     if (c.kind == 0) P.used[c.a] = 1;
   }, &in, &cut, &Bits);
-  const int64_t v = (int64_t)kk * g.NI + ii;
-  if (nin < 0) {  // cut: the second pass takes it
-    atomicOr(&P.rtri[v], 1u << (28 + z));
-    return;
-  }
   if (nt > 63) {
     pre_error(P);
     nt = 63;
   }
+  const int64_t v = (int64_t)kk * g.NI + ii;
   const uint32_t bits = ((uint32_t)nt << (6 * z)) | ((uint32_t)(nin ? 1 : 0) << (24 + z)) |
                         ((uint32_t)(cut ? 1 : 0) << (28 + z));
   if (bits) atomicOr(&P.rtri[v], bits);
   const uint32_t add = ((uint32_t)(nin ? 1 : 0) << 16) | ((uint32_t)nt << 19) | ((uint32_t)(cut ? 1 : 0) << 27);
   if (add) atomicAdd(&P.rcount[v], add);
 }
-// One item per grid triangle of the touched owners (4 per owner), over a
-// grid-stride loop; at most 128 VGPRs (four waves per SIMD).  The first
-// triangles of the two slots come first (items 0 .. 2n-1), then the second
-// ones, which only owners with a split side have: waves of absent triangles
-// end early.
-__global__ void __launch_bounds__(256, 4) k_pre_mesh_probe(OneSrc src, PreArgs P, Shared sh) {
+
+// Counts of the touched owners, one lane per owner: its flags, slots and
+// raster words are loaded once for its four grid triangles (the candidate
+// segments clipped: an uncut triangle is counted, one triangle when in the
+// foreground; a cut one gets its cut bit and is counted by
+// k_pre_mesh_cut_count) and its eight edge slots (crossings); its words are
+// written without atomics.  At most 128 VGPRs (four waves per SIMD).
+__global__ void __launch_bounds__(256, 4) k_pre_mesh_probe_owner(OneSrc src, PreArgs P, Shared sh) {
   const Img& d = src.d;
   const Geo g = d.g;
   const int64_t T = sh.seg_off[sh.nseg].x;  // touched owners
-  for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < 4 * T; it += (int64_t)gridDim.x * 256)
-    pre_mesh_tri_count<true>(d, g, P, (it >= 2 * T ? it - 2 * T : it) >> 1, 2 * (int)(it & 1) + (it >= 2 * T ? 1 : 0));
-}
-// Crossings of the touched owners' edge slots, one item per slot (8 per
-// owner): the whole or first halves of the owned sides first (items
-// 0 .. 3n-1), then the second halves and the fan edges, which only owners
-// with a split side have.
-__global__ void __launch_bounds__(256) k_pre_mesh_edges(OneSrc src, PreArgs P, Shared sh) {
-  const Img& d = src.d;
-  const Geo g = d.g;
-  const int64_t T = sh.seg_off[sh.nseg].x;  // touched owners
-  for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < 8 * T; it += (int64_t)gridDim.x * 256) {
-    const bool first = it < 3 * T;
-    const int64_t r = first ? it : it - 3 * T;
-    const int64_t t = first ? r / 3 : r / 5;
-    const int j = (int)(r - t * (first ? 3 : 5));
-    const int e = first ? 2 * j : (j < 3 ? 2 * j + 1 : j + 3);  // 0 2 4, then 1 3 5 6 7
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < T; t += (int64_t)gridDim.x * 256) {
     int kk, ii;
     pre_tl_owner(g, P, t, kk, ii);
+    const int64_t v = (int64_t)kk * g.NI + ii;
     const PreSlots S = pre_owner_slots(P, g, kk, ii);
-    PreGV A, B;
-    if (!pre_edge_slot(P, g, kk, ii, S, e, A, B)) continue;
     PreBits Bits;
     pre_owner_bits(d, g, P, kk, ii, Bits);
-    int c = 0;
-    pre_edge_crossings(d, g, A, B, [&](const PreSeg&, double) { ++c; }, &Bits);
-    if (c > 3) {  // more crossings of one grid edge than the numbering holds
-      pre_error(P);
-      c = 3;
+    uint32_t rt = 0, rc = 0;
+    for (int z = 0; z < 4; ++z) {
+      PreGT Tg;
+      if (!pre_owner_tri(P, g, kk, ii, S, z, Tg)) continue;
+      int nt = 0;
+      PrePt in;
+      bool cut = false;
+      const int nin = pre_tri_mesh<true>(d, g, P, Tg, [&](const PrePt& a, const PrePt& b, const PrePt& c, int) {
+        ++nt;
+        if (a.kind == 0) P.used[a.a] = 1;
+        if (b.kind == 0) P.used[b.a] = 1;
+        if (c.kind == 0) P.used[c.a] = 1;
+      }, &in, &cut, &Bits);
+      if (nin < 0) {  // cut: k_pre_mesh_cut_count takes it
+        rt |= 1u << (28 + z);
+        continue;
+      }
+      rt |= (uint32_t)nt << (6 * z);  // uncut: at most one triangle, no inner vertex
+      rc += (uint32_t)nt << 19;
     }
-    if (c) atomicOr(&P.rcount[(int64_t)kk * g.NI + ii], (uint32_t)c << (2 * e));
+    for (int e = 0; e < 8; ++e) {
+      PreGV A, B;
+      if (!pre_edge_slot(P, g, kk, ii, S, e, A, B)) continue;
+      int c = 0;
+      pre_edge_crossings(d, g, A, B, [&](const PreSeg&, double) { ++c; }, &Bits);
+      if (c > 3) {  // more crossings of one grid edge than the numbering holds
+        pre_error(P);
+        c = 3;
+      }
+      rc |= (uint32_t)c << (2 * e);
+    }
+    P.rtri[v] = rt;
+    P.rcount[v] = rc;
   }
 }
+
 // The cut grid triangles (cut bit set, no count yet), gathered per block and
 // retriangulated on full blocks.  The retriangulating kernels are held to
 // 128 VGPRs (four waves per SIMD): spilling more to scratch costs less than
@@ -1695,7 +1702,7 @@ __global__ void __launch_bounds__(256, 4) k_pre_mesh_cut_count(OneSrc src, PreAr
   const int64_t T = sh.seg_off[sh.nseg].x;
   pre_dense(4 * T, dl, &nd, [&](int64_t it) -> bool {
     return (P.rtri[P.tlist[it >> 2]] >> (28 + (it & 3))) & 1u;
-  }, [&](int64_t it) { pre_mesh_tri_count<false>(d, g, P, it >> 2, (int)(it & 3)); });
+  }, [&](int64_t it) { pre_mesh_cut_tri_count(d, g, P, it >> 2, (int)(it & 3)); });
 }
 
 // Per row segment: new vertices, triangles and cut grid triangles of its

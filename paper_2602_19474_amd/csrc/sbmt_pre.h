@@ -1640,8 +1640,9 @@ __device__ __forceinline__ void pre_mesh_cut_tri_count(const Img& d, const Geo& 
 // segments clipped: an uncut triangle is counted, one triangle when in the
 // foreground; a cut one gets its cut bit and is counted by
 // k_pre_mesh_cut_count) and its eight edge slots (crossings); its words are
-// written without atomics.  At most 128 VGPRs (four waves per SIMD).
-__global__ void __launch_bounds__(256, 4) k_pre_mesh_probe_owner(OneSrc src, PreArgs P, Shared sh) {
+// written without atomics.  It takes 165 VGPRs (three waves per SIMD):
+// held to 128 it spills and runs 7 % slower.
+__global__ void __launch_bounds__(256) k_pre_mesh_probe_owner(OneSrc src, PreArgs P, Shared sh) {
   const Img& d = src.d;
   const Geo g = d.g;
   const int64_t T = sh.seg_off[sh.nseg].x;  // touched owners

@@ -2725,7 +2725,7 @@ sbmt_status sbmt_preprocess_mesh(sbmt_handle h, const sbmt_image* img, double a,
   const Geo& g = PL.L.g[0];
   if (!pre_thresholds_ok(a, b, c, (double)g.h / g.U)) return SBMT_E_INVALID_ARG;
   if (!workspace || ws_bytes < PL.total) return SBMT_E_WORKSPACE;
-  if (PL.nown > 0x7fffffffLL) return SBMT_E_INDEX_OVERFLOW;  // owner indices in 32 bits
+  if (PL.nown + PL.nmid > 0x7fffffffLL) return SBMT_E_INDEX_OVERFLOW;  // grid vertex indices in 32 bits
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)workspace;
   const Shared sh = shared_of(PL.L, workspace, 1);

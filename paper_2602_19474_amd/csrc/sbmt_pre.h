@@ -776,15 +776,16 @@ __device__ __forceinline__ int pre_inside_point(const Img& d, const Geo& g, doub
   }
   return 1;
 }
-// Grid vertex: id, position, the polyline vertex it sits on (or -1).
+// Grid vertex: id, position, the polyline vertex it sits on (or -1).  Grid
+// vertex and owner indices fit 32 bits (the entry points check it).
 struct PreGV {
-  int64_t id;
-  double x, y;
+  int32_t id;
   int32_t bnd;
+  double x, y;
 };
 __device__ __forceinline__ PreGV pre_lat_gv(const PreArgs& P, int64_t v) {
   PreGV r;
-  r.id = v;
+  r.id = (int32_t)v;
   const double2 p = reinterpret_cast<const double2*>(P.verts)[v];
   r.x = p.x;
   r.y = p.y;
@@ -794,7 +795,7 @@ __device__ __forceinline__ PreGV pre_lat_gv(const PreArgs& P, int64_t v) {
 // The vertex inserted on side e of owner w (flags fw).
 __device__ __forceinline__ PreGV pre_ins_gv(const PreArgs& P, const Geo& g, int64_t w, int e, uint32_t fw) {
   PreGV r;
-  r.id = (int64_t)g.NK * g.NI + P.ins_base[w] + __builtin_popcount(fw & ((1u << e) - 1u));
+  r.id = (int32_t)((int64_t)g.NK * g.NI + P.ins_base[w] + __builtin_popcount(fw & ((1u << e) - 1u)));
   const double2 p = reinterpret_cast<const double2*>(P.verts)[r.id];
   r.x = p.x;
   r.y = p.y;
@@ -843,7 +844,7 @@ __device__ __forceinline__ void pre_edge_crossings(const Img& d, const Geo& g, c
 // e+1) the owner and edge slot that number its crossings.
 struct PreGT {
   PreGV c[3];
-  int64_t eo[3];
+  int32_t eo[3];
   int es[3];
 };
 // x, y or z for j = 0, 1, 2: selects rather than an indexed local array,
@@ -963,8 +964,8 @@ __device__ __forceinline__ int pre_rc_cut(uint32_t rc) { return (int)((rc >> 27)
 // grid edge (a, b), a < b, by segment s; 2 polyline vertex a strictly inside
 // (s: the segment ending there).  ct: position along the chain.
 struct PrePt {
-  int kind;
-  int64_t a, b;
+  int32_t kind;
+  int32_t a, b;
   int32_t s;
   double x, y, ct;
 };

@@ -331,7 +331,8 @@ sbmt_status sbmt_preprocess(sbmt_handle h, const sbmt_image* img, double a, doub
  *             the polyline cuts)
  * Rows beyond a capacity are not written; SBMT_E_CAPACITY then comes with the
  * counts filled in (size the outputs from them and call again).  Errors as
- * for sbmt_preprocess. */
+ * for sbmt_preprocess, and SBMT_E_INDEX_OVERFLOW before any launch when the
+ * query's grid vertex bound exceeds 2^31 - 1. */
 sbmt_status sbmt_pre_mesh_query(const sbmt_image* img, size_t* workspace_bytes, int64_t* grid_vert_bound);
 sbmt_status sbmt_preprocess_mesh(sbmt_handle h, const sbmt_image* img, double a, double b, double c,
                                  void* workspace, size_t ws_bytes, double* verts, int64_t vert_cap, int32_t* tris,

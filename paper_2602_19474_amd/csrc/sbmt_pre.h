@@ -984,7 +984,11 @@ struct PreSub {
 // polyline vertices strictly inside T (0 or 1) and sets *inner to it.  With
 // kDefer, a cut triangle only sets *cut and returns -1 once its pieces are
 // known (callers gather those and come back to them on full waves).
-template <bool kDefer = false, class Out>
+// With kCount, a foreground face of m points is reported as m - 2 triangles
+// fanned from its first point: the same count and the same points as the
+// template's triangles, without the template rule and its checks (for
+// passes that only count; the pass that writes the triangles applies them).
+template <bool kDefer = false, bool kCount = false, class Out>
 __device__ int pre_tri_mesh(const Img& d, const Geo& g, const PreArgs& P, const PreGT& T, Out out, PrePt* inner,
                             bool* cut = nullptr, const PreBits* Bits = nullptr) {
   const int64_t NLAT = (int64_t)g.NK * g.NI;
@@ -1280,6 +1284,10 @@ __device__ int pre_tri_mesh(const Img& d, const Geo& g, const PreArgs& P, const 
       pre_error(P);
       return 0;
     }
+    if (kCount) {
+      for (int t = 1; t + 1 < m; ++t) out(pool[face[0]], pool[face[t]], pool[face[t + 1]], 1);
+      continue;
+    }
     // the template rule on this foreground face
     int apex = -1;
     for (int j = 0; j < m; ++j)
@@ -1435,7 +1443,8 @@ __device__ void pre_inner_vertex(const Img& d, const Geo& g, const PreArgs& P, i
   PreBits Bits;
   pre_owner_bits(d, g, P, k, i, Bits);
   PrePt in;
-  if (pre_tri_mesh(d, g, P, T, [](const PrePt&, const PrePt&, const PrePt&, int) {}, &in, nullptr, &Bits) &&
+  if (pre_tri_mesh<false, true>(d, g, P, T, [](const PrePt&, const PrePt&, const PrePt&, int) {}, &in, nullptr,
+                                &Bits) &&
       at < P.ovcap)
     reinterpret_cast<double2*>(P.overts)[at] = make_double2(in.x, in.y);
 }
@@ -1618,7 +1627,7 @@ __device__ __forceinline__ void pre_mesh_cut_tri_count(const Img& d, const Geo& 
   int nt = 0;
   PrePt in;
   bool cut = false;
-  const int nin = pre_tri_mesh(d, g, P, Tg, [&](const PrePt& a, const PrePt& b, const PrePt& c, int) {
+  const int nin = pre_tri_mesh<false, true>(d, g, P, Tg, [&](const PrePt& a, const PrePt& b, const PrePt& c, int) {
     ++nt;
     if (a.kind == 0) P.used[a.a] = 1;
     if (b.kind == 0) P.used[b.a] = 1;

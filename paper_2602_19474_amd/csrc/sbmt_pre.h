@@ -30,15 +30,14 @@ struct PreArgs {
   int32_t* tris;         // [triangles][3]
   int64_t vcap, tcap;
   uint8_t* mid;          // per midpoint: 1 if a lattice vertex snapped to it
-  uint8_t* flags;        // per lattice vertex: bits 0-2 owned side E0-E2 split, bit 3 moved
+  uint8_t* flags;        // per lattice vertex: bits 0-2 owned side E0-E2 split, 3 moved, 4 claimed, 5 snapped, 6 touched (mesh)
   int32_t* split;        // [NK NI][3]: midpoint splitting side E0, E1, E2 (written where split)
   int64_t* ins_base;     // [NK NI]: first inserted vertex of the owner (written where it has one)
-  int64_t* counts;       // [8 + 512]: [2] error; from kPreTally 256 counters of snapped, then of repelled vertices
+  int64_t* counts;       // [8 + 512]: [2] error, [3] touched owners (mesh); from kPreTally 256 counters of snapped, then of repelled vertices
   int32_t* snap_mid;     // [NK NI]: the polyline vertex a lattice vertex snapped to (written where snapped)
   // retriangulation of the grid (sbmt_preprocess_mesh)
   uint32_t* rcount;      // [NK NI]: per-owner counts (pre_rc_*)
   uint32_t* rtri;        // [NK NI]: per grid triangle of the owner (4): output triangles (6 bits each), inner-vertex bits 24..27, cut bits 28..31
-  // (counts[3]: the number of touched owners)
   int64_t* rbase;        // [NK NI]: first new vertex of the owner (written where it has one)
   const int64_t* gsizes; // the grid phase's sizes record (grid vertices first)
   int32_t* otris;        // [otcap][3]

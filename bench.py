@@ -151,6 +151,36 @@ def headline(bm: np.ndarray, steps: int, warmup: int):
     return {"bitmap": bm, "plain": p, "wall": wall, "plan_ms": plan_ms, "emit_ms": emit_ms, "sizes": sz}
 
 
+def async_section(plain, steps: int, warmup: int):
+    """The headline image through sbmt_mesh_async: planning and emission queued back
+    to back with no host round trip (outputs of the capacity an earlier plan gave,
+    sizes left on the device and checked after the timed steps)."""
+    import torch
+    from paper_2602_19474_amd import _lib
+    sd = torch.zeros(_lib.SIZE_WORDS, dtype=torch.int64, device=plain.t.device)
+
+    def f():
+        plain.sbmt.mesh_async(plain.t, plain.h, plain.ws, plain.verts, plain.tris, plain.codes, sd)
+    for _ in range(warmup):
+        f()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        f()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    st = sd.cpu().tolist()
+    if st[3] != 0 or st[1] != plain.sizes.n_triangles:
+        raise RuntimeError(f"sbmt_mesh_async sizes {st}")
+    ms = wall / steps * 1e3
+    return {"ms_per_step": ms, "event_ms_per_step": e0.elapsed_time(e1) / steps,
+            "triangles_per_s": plain.sizes.n_triangles / (ms * 1e-3),
+            "launch": "sbmt_mesh_async: plan and emission queued without a host round trip"}
+
+
 def _event_ms(fn, reps: int) -> float:
     import torch
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -602,6 +632,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_emit", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_source": traffic_src, "alg_bytes_per_launch": emit_bytes},
+        "async": async_section(H["plain"], args.steps, args.warmup),
     }
     if not args.no_preprocess:
         log("preprocess section")

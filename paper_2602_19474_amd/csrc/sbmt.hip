@@ -2639,6 +2639,10 @@ static PreArgs pre_args(const PreLayout& PL, char* w, double a, double b, double
   P.nused = PL.off_nused ? (int64_t*)(w + PL.off_nused) : nullptr;
   P.tlist = PL.off_tlist ? (int32_t*)(w + PL.off_tlist) : nullptr;
   P.rtbase = PL.off_rtbase ? (int64_t*)(w + PL.off_rtbase) : nullptr;
+  P.cbase = PL.off_cbase ? (int32_t*)(w + PL.off_cbase) : nullptr;
+  P.cblk = PL.off_cblk ? (int64_t*)(w + PL.off_cblk) : nullptr;
+  P.cstore = PL.off_cstore ? (uint32_t*)(w + PL.off_cstore) : nullptr;
+  P.ccap = PL.off_cstore ? PL.ccap : 0;
   return P;
 }
 // Steps 1-3 (the grid, with its triangles when `triangles`), then the sizes
@@ -2764,6 +2768,11 @@ sbmt_status sbmt_preprocess_mesh(sbmt_handle h, const sbmt_image* img, double a,
   hipLaunchKernelGGL(k_scan_apply, dim3(PL.L.nblk), dim3(kScanThreads), 0, s, sh);
   hipLaunchKernelGGL(k_pre_mesh_count, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);
   hipLaunchKernelGGL(k_pre_mesh_probe_owner, resident(&k_pre_mesh_probe_owner), dim3(256), 0, s, src, P, sh);
+  // slots of the cut triangles' kept outputs, then their counts
+  if (PL.ncblk > 0x7fffffffLL) return SBMT_E_INVALID_ARG;
+  hipLaunchKernelGGL(k_pre_cut_count, dim3((unsigned)PL.ncblk), dim3(256), 0, s, P, sh);
+  hipLaunchKernelGGL(k_pre_cut_top, dim3(1), dim3(256), 0, s, P, PL.ncblk);
+  hipLaunchKernelGGL(k_pre_cut_apply, dim3((unsigned)PL.ncblk), dim3(256), 0, s, P, sh);
   hipLaunchKernelGGL(k_pre_mesh_cut_count, resident(&k_pre_mesh_cut_count), dim3(256), 0, s, src, P, sh);
   // the output counts per row segment and their offsets
   hipLaunchKernelGGL(k_pre_mesh_segsum, dim3((unsigned)nqb), dim3(256), 0, s, src, P, sh);

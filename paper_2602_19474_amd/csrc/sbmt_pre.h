@@ -54,8 +54,15 @@ struct PreArgs {
   int64_t* rtbase;       // [NK NI]: a touched owner's first output triangle
   int64_t* vbsum;        // per block of kPreVScan grid vertices: used count, then base
   int64_t* nused;        // [1]: grid vertices in the mesh
+  // a cut grid triangle's output kept by the count pass for the triangle pass
+  int32_t* cbase;        // [NK NI]: cut grid triangles of the touched owners before list position t
+  int64_t* cblk;         // per block of kPreVScan list positions: cut count, then base
+  uint32_t* cstore;      // [ccap][1 + 3 kPreKeep]: number of triangles kept (or kPreNotKept), point refs
+  int64_t ccap;
 };
-constexpr int kPreVScan = 16384;  // grid vertices per block of the compaction scan
+constexpr int kPreVScan = 16384;  // grid vertices (list positions) per block of the compaction (cut) scan
+constexpr int kPreKeep = 4;       // output triangles a cut grid triangle keeps for the triangle pass
+constexpr uint32_t kPreNotKept = 0xffffffffu;
 constexpr uint8_t kPreMoved = 8;
 constexpr int kPreTally = 8;
 constexpr int kPreCounts = kPreTally + 512;
@@ -1448,9 +1455,39 @@ __device__ void pre_inner_vertex(const Img& d, const Geo& g, const PreArgs& P, i
     reinterpret_cast<double2*>(P.overts)[at] = make_double2(in.x, in.y);
 }
 
-// Output triangles of grid triangle z of a touched owner, from position pos.
+// A point of a cut triangle's output in 32 bits: bits 30..31 the kind; a
+// grid vertex's id (below 2^30), a crossing's triangle edge (bits 28..29) and
+// segment (below 2^28), nothing for the inner polyline vertex.  False if the
+// point does not fit.
+__device__ __forceinline__ bool pre_ref_pack(const PreGT& T, const PrePt& p, uint32_t& r) {
+  if (p.kind == 0) {
+    r = (uint32_t)p.a;
+    return (uint32_t)p.a < (1u << 30);
+  }
+  if (p.kind == 2) {
+    r = 2u << 30;
+    return true;
+  }
+  if ((uint32_t)p.s >= (1u << 28)) return false;
+  for (int e = 0; e < 3; ++e) {
+    const int32_t ia = pre_sel3(T.c[0].id, T.c[1].id, T.c[2].id, e);
+    const int32_t ib = pre_sel3(T.c[0].id, T.c[1].id, T.c[2].id, (e + 1) % 3);
+    if (min(ia, ib) == p.a && max(ia, ib) == p.b) {
+      r = (1u << 30) | ((uint32_t)e << 28) | (uint32_t)p.s;
+      return true;
+    }
+  }
+  return false;
+}
+// The slot of cut grid triangle z of list position t in the kept outputs.
+__device__ __forceinline__ int64_t pre_cut_slot(const PreArgs& P, int64_t t, int z, uint32_t rt) {
+  return (int64_t)P.cbase[t] + __builtin_popcount((rt >> 28) & ((1u << z) - 1u));
+}
+
+// Output triangles of grid triangle z of a touched owner, from position pos
+// (kept: the count pass's output of a cut triangle, kn triangles of point refs).
 __device__ void pre_owner_triangle(const Img& d, const Geo& g, const PreArgs& P, int k, int i, int z, uint32_t rc,
-                                   uint32_t rt, int64_t pos, int64_t NV) {
+                                   uint32_t rt, int64_t pos, int64_t NV, const uint32_t* kept = nullptr, int kn = 0) {
   const int64_t v = (int64_t)k * g.NI + i;
   const PreSlots S = pre_owner_slots(P, g, k, i);
   PreBits Bits;
@@ -1505,6 +1542,31 @@ __device__ void pre_owner_triangle(const Img& d, const Geo& g, const PreArgs& P,
     pre_error(P);
     return 0;
   };
+  if (kept) {  // the count pass's output: ids from the point refs
+    auto ref_id = [&](uint32_t r) -> int64_t {
+      const uint32_t kind = r >> 30;
+      if (kind == 0) return P.vmap[r & 0x3fffffffu];
+      if (kind == 2) return inner_id;
+      const int e = (int)((r >> 28) & 3u);
+      const int32_t sg = (int32_t)(r & 0x0fffffffu);
+      const int ne = pre_sel3(ecnt[0], ecnt[1], ecnt[2], e);
+      for (int q = 0; q < ne; ++q) {
+        const int32_t sq = e == 0 ? eseg[0][q] : (e == 1 ? eseg[1][q] : eseg[2][q]);
+        if (sq == sg) return pre_sel3(ebase[0], ebase[1], ebase[2], e) + q;
+      }
+      pre_error(P);
+      return 0;
+    };
+    for (int j = 0; j < kn; ++j, ++pos) {
+      if (pos >= P.otcap) continue;
+      int32_t* o = P.otris + 3 * pos;
+      o[0] = (int32_t)ref_id(kept[3 * j]);
+      o[1] = (int32_t)ref_id(kept[3 * j + 1]);
+      o[2] = (int32_t)ref_id(kept[3 * j + 2]);
+      P.ocodes[pos] = 1;
+    }
+    return;
+  }
   PrePt in;
   (void)pre_tri_mesh(d, g, P, TT, [&](const PrePt& a, const PrePt& b, const PrePt& c, int code) {
     if (pos < P.otcap) {
@@ -1614,7 +1676,8 @@ __device__ __forceinline__ void pre_tl_owner(const Geo& g, const PreArgs& P, int
 
 // Counts of a cut grid triangle of a touched owner (item t * 4 + z of the
 // list): subdivision and template; triangles, inner vertex and the cut are
-// added to the owner's words.
+// added to the owner's words, and up to kPreKeep output triangles are kept in
+// the triangle's slot for the triangle pass.
 __device__ __forceinline__ void pre_mesh_cut_tri_count(const Img& d, const Geo& g, const PreArgs& P, int64_t t, int z) {
   int kk, ii;
   pre_tl_owner(g, P, t, kk, ii);
@@ -1626,12 +1689,27 @@ __device__ __forceinline__ void pre_mesh_cut_tri_count(const Img& d, const Geo& 
   int nt = 0;
   PrePt in;
   bool cut = false;
-  const int nin = pre_tri_mesh<false, true>(d, g, P, Tg, [&](const PrePt& a, const PrePt& b, const PrePt& c, int) {
+  // the output is kept for the triangle pass when it fits its slot
+  const uint32_t rt0 = P.rtri[(int64_t)kk * g.NI + ii];
+  const int64_t slot = pre_cut_slot(P, t, z, rt0);
+  uint32_t* kept = slot < P.ccap ? P.cstore + slot * (1 + 3 * kPreKeep) : nullptr;
+  bool keep = kept != nullptr;
+  const int nin = pre_tri_mesh(d, g, P, Tg, [&](const PrePt& a, const PrePt& b, const PrePt& c, int) {
+    if (keep && nt < kPreKeep) {
+      uint32_t ra, rb, rc;
+      keep = pre_ref_pack(Tg, a, ra) && pre_ref_pack(Tg, b, rb) && pre_ref_pack(Tg, c, rc);
+      kept[1 + 3 * nt] = ra;
+      kept[2 + 3 * nt] = rb;
+      kept[3 + 3 * nt] = rc;
+    } else {
+      keep = false;
+    }
     ++nt;
     if (a.kind == 0) P.used[a.a] = 1;
     if (b.kind == 0) P.used[b.a] = 1;
     if (c.kind == 0) P.used[c.a] = 1;
   }, &in, &cut, &Bits);
+  if (kept) kept[0] = keep ? (uint32_t)nt : kPreNotKept;
   if (nt > 63) {
     pre_error(P);
     nt = 63;
@@ -1695,6 +1773,75 @@ __global__ void __launch_bounds__(256) k_pre_mesh_probe_owner(OneSrc src, PreArg
     }
     P.rtri[v] = rt;
     P.rcount[v] = rc;
+  }
+}
+
+// Exclusive scan in place of nblk block counts by one block; *total (if
+// given) receives their sum.
+__device__ __forceinline__ void pre_scan_blocks(int64_t* a, int64_t nblk, int64_t* total) {
+  __shared__ int64_t part[4];
+  int64_t run = 0;
+  for (int64_t b = 0; b < nblk; b += 256) {
+    const int64_t j = b + threadIdx.x;
+    const int64_t x = j < nblk ? a[j] : 0;
+    // block-wide exclusive scan of 256 int64 values (four waves of 64)
+    int64_t incl = x;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t y = __shfl_up(incl, off);
+      if ((int)(threadIdx.x & 63) >= off) incl += y;
+    }
+    if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    int64_t before = run;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) before += part[w];
+    if (j < nblk) a[j] = before + incl - x;
+    run += part[0] + part[1] + part[2] + part[3];
+    __syncthreads();
+  }
+  if (total && threadIdx.x == 0) *total = run;
+}
+// Slots of the cut grid triangles' kept outputs, in list order: per block of
+// kPreVScan list positions the number of cut triangles; one block scans the
+// counts; then each position's first slot (clamped to 32 bits: slots past the
+// capacity keep nothing).
+__device__ __forceinline__ int pre_cut_n(const PreArgs& P, int64_t t, int64_t T) {
+  return t < T ? __builtin_popcount(P.rtri[P.tlist[t]] >> 28) : 0;
+}
+__global__ void __launch_bounds__(256) k_pre_cut_count(PreArgs P, Shared sh) {
+  __shared__ int part[4];
+  const int64_t T = sh.seg_off[sh.nseg].x;
+  const int64_t b0 = (int64_t)blockIdx.x * kPreVScan;
+  int n = 0;
+  for (int q = threadIdx.x; q < kPreVScan && b0 < T; q += 256) n += pre_cut_n(P, b0 + q, T);
+  const int w = __builtin_amdgcn_readlane(wave_incl_scan_dpp(n), 63);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) P.cblk[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+__global__ void __launch_bounds__(256) k_pre_cut_top(PreArgs P, int64_t nblk) { pre_scan_blocks(P.cblk, nblk, nullptr); }
+__global__ void __launch_bounds__(256) k_pre_cut_apply(PreArgs P, Shared sh) {
+  __shared__ int part[4];
+  const int64_t T = sh.seg_off[sh.nseg].x;
+  const int64_t b0 = (int64_t)blockIdx.x * kPreVScan;
+  if (b0 >= T) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int64_t run = P.cblk[blockIdx.x];
+  for (int c = 0; c < kPreVScan / 256; ++c) {
+    const int64_t t = b0 + (int64_t)c * 256 + threadIdx.x;
+    const int n = pre_cut_n(P, t, T);
+    const int incl = wave_incl_scan_dpp(n);
+    if (lane == 63) part[wv] = incl;
+    __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int tw = part[w];
+      before += w < wv ? tw : 0;
+      tot += tw;
+    }
+    if (t < T) P.cbase[t] = (int32_t)min(run + before + incl - n, (int64_t)0x7fffffff);
+    run += tot;
+    __syncthreads();
   }
 }
 
@@ -1924,7 +2071,13 @@ __global__ void __launch_bounds__(256, 4) k_pre_mesh_cut_tris(OneSrc src, PreArg
     const uint32_t rt = P.rtri[v];
     int before = 0;
     for (int z2 = 0; z2 < z; ++z2) before += (int)((rt >> (6 * z2)) & 63u);
-    pre_owner_triangle(d, g, P, kk, ii, z, P.rcount[v], rt, P.rtbase[v] + before, NV);
+    const int64_t slot = pre_cut_slot(P, it >> 2, z, rt);
+    const uint32_t* kept = slot < P.ccap ? P.cstore + slot * (1 + 3 * kPreKeep) : nullptr;
+    const uint32_t kn = kept ? kept[0] : kPreNotKept;
+    if (kn != kPreNotKept && kn == ((rt >> (6 * z)) & 63u))
+      pre_owner_triangle(d, g, P, kk, ii, z, P.rcount[v], rt, P.rtbase[v] + before, NV, kept + 1, (int)kn);
+    else  // not kept: retriangulated again
+      pre_owner_triangle(d, g, P, kk, ii, z, P.rcount[v], rt, P.rtbase[v] + before, NV);
   });
 }
 
@@ -1951,28 +2104,7 @@ __global__ void __launch_bounds__(256) k_pre_vscan_count(PreArgs P) {
   __syncthreads();
   if (threadIdx.x == 0) P.vbsum[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
 }
-__global__ void __launch_bounds__(256) k_pre_vscan_top(PreArgs P, int64_t nblk) {
-  __shared__ int64_t part[4];
-  int64_t run = 0;
-  for (int64_t b = 0; b < nblk; b += 256) {
-    const int64_t j = b + threadIdx.x;
-    const int64_t x = j < nblk ? P.vbsum[j] : 0;
-    // block-wide exclusive scan of 256 int64 values (four waves of 64)
-    int64_t incl = x;
-    for (int off = 1; off < 64; off <<= 1) {
-      const int64_t y = __shfl_up(incl, off);
-      if ((int)(threadIdx.x & 63) >= off) incl += y;
-    }
-    if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = incl;
-    __syncthreads();
-    int64_t before = run;
-    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) before += part[w];
-    if (j < nblk) P.vbsum[j] = before + incl - x;
-    run += part[0] + part[1] + part[2] + part[3];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *P.nused = run;
-}
+__global__ void __launch_bounds__(256) k_pre_vscan_top(PreArgs P, int64_t nblk) { pre_scan_blocks(P.vbsum, nblk, P.nused); }
 __global__ void __launch_bounds__(256) k_pre_vscan_apply(PreArgs P) {
   __shared__ int part[16][4];
   const int64_t NV = P.gsizes[0] < P.usedcap ? P.gsizes[0] : P.usedcap;
@@ -2042,7 +2174,8 @@ struct PreLayout {
   size_t off_mid, off_split, off_flags, off_ins, off_counts, off_out, off_snap, total;
   // the retriangulation (sbmt_preprocess_mesh): grid on-polyline bytes, per-owner counts and bases, sizes
   size_t off_onp, off_rcount, off_rtri, off_rbase, off_out2, off_gverts, off_used, off_vmap, off_vbsum, off_nused,
-      off_tlist, off_rtbase;
+      off_tlist, off_rtbase, off_cbase, off_cblk, off_cstore;
+  int64_t ncblk, ccap;  // blocks of the cut scan; cut triangles whose output is kept
   int64_t nvblk;  // blocks of the vertex compaction scan
   int64_t nmid, nown;
 };
@@ -2070,6 +2203,8 @@ static sbmt_status pre_layout(const sbmt_image* img, bool need_ptr, PreLayout* P
   off = align256(off + (size_t)P->nown * 4);
   P->off_onp = P->off_rcount = P->off_rtri = P->off_rbase = P->off_out2 = 0;
   P->off_gverts = P->off_used = P->off_vmap = P->off_vbsum = P->off_nused = P->off_tlist = P->off_rtbase = 0;
+  P->off_cbase = P->off_cblk = P->off_cstore = 0;
+  P->ncblk = P->ccap = 0;
   P->nvblk = 0;
   if (mesh) {
     P->off_onp = off;
@@ -2098,6 +2233,15 @@ static sbmt_status pre_layout(const sbmt_image* img, bool need_ptr, PreLayout* P
     off = align256(off + (size_t)P->nown * 4);
     P->off_rtbase = off;
     off = align256(off + (size_t)P->nown * 8);
+    // kept outputs of the cut grid triangles: room for one in 16 owners
+    P->ncblk = (P->nown + kPreVScan - 1) / kPreVScan;
+    P->ccap = std::max<int64_t>(65536, P->nown / 16);
+    P->off_cbase = off;
+    off = align256(off + (size_t)P->nown * 4);
+    P->off_cblk = off;
+    off = align256(off + (size_t)P->ncblk * 8);
+    P->off_cstore = off;
+    off = align256(off + (size_t)P->ccap * (1 + 3 * kPreKeep) * 4);
   }
   P->total = off;
   return SBMT_OK;

@@ -81,6 +81,11 @@ def test_ellipses(h):
     _compare("ellipses260x230", wl.ellipses(260, 230, g=wl.rng(97, int(4 * h))), h)
 
 
+@pytest.mark.parametrize("h", [0.75, 1.5, 6])
+def test_ellipses_other_grid_edges(h):
+    _compare("ellipses220x200", wl.ellipses(220, 200, g=wl.rng(93, int(8 * h))), h)
+
+
 @pytest.mark.parametrize("h,sigma", [(1, 2.0), (1, 4.0), (2, 3.0), (0.5, 1.5)])
 def test_smoothed_noise(h, sigma):
     _compare(f"noise sigma={sigma}", wl.smoothed_noise(300, 280, sigma, 0.0, False, wl.rng(98, int(4 * h + sigma))), h)

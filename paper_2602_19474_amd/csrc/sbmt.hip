@@ -2209,7 +2209,7 @@ sbmt_status sbmt_create(int device, sbmt_handle* out) {
   // this device's block segment table (idempotent; finished before any use)
   hipLaunchKernelGGL(k_block_table, dim3(2), dim3(256), 0, 0);
   if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
-    hipHostFree(c->pinned);
+    (void)hipHostFree(c->pinned);
     delete c;
     return SBMT_E_DEVICE;
   }

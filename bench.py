@@ -298,6 +298,17 @@ def preprocess_cpu_baseline(bm: np.ndarray, rows: int = 2048):
             "sample": f"Steps 1-3 of Alg. 3 on rows 0-{rows - 1} of noise8192 ({crop.shape[1]} px wide)"}
 
 
+def preprocess_mesh_cpu_baseline(bm: np.ndarray, rows: int = 512):
+    """The oracle's mesh of Alg. 3 on the first `rows` rows of the headline image."""
+    import oracle
+    crop = np.ascontiguousarray(bm[:rows])
+    a = time.perf_counter()
+    m = oracle.mesh_preprocessed(crop, 1)
+    dt = time.perf_counter() - a
+    return {"value": m.tris.shape[0] / dt, "unit": "triangles/s", "cores": 1, "kind": "oracle",
+            "sample": f"mesh of Alg. 3 on rows 0-{rows - 1} of noise8192 ({crop.shape[1]} px wide, {dt:.1f} s)"}
+
+
 def post_cpu_baseline(plain, n_tri: int = 4_000_000):
     """The oracle's quality pass over the first n_tri triangles of the headline mesh."""
     import oracle
@@ -639,6 +650,7 @@ def main():
         res["preprocess"] = preprocess_section(noise)
         if not args.no_cpu_baseline:
             res["preprocess"]["cpu_baseline"] = preprocess_cpu_baseline(noise)
+            res["preprocess"]["mesh"]["cpu_baseline"] = preprocess_mesh_cpu_baseline(noise)
     if not args.no_post:
         log("post section")
         res["post"] = post_section(H["plain"])
